@@ -1,0 +1,592 @@
+/*
+ * oracle.c -- plain, slow, single-threaded CPU FP64 reference of
+ * block-ILU0-preconditioned BiCGStab on BCSR matrices with 3x3 blocks.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or constant with the HIP library: its own BCSR walk, its own
+ * 3x3 inverse, its own orderings.  Built with gcc -O2 -ffp-contract=off so
+ * every multiply and add rounds separately, in program order.
+ *
+ * What it follows (paper: Qiu et al., "An Evaluation and Comparison of GPU
+ * Hardware and Solver Libraries for Accelerating the OPM Flow Reservoir
+ * Simulator"):
+ *   - BCSR layout: values, row pointers and column indices; blocks stored
+ *     row-major, one after another (Section "OPM Flow"; Section "Sparse
+ *     Matrix-Vector multiplication", last paragraph).
+ *   - ILU0 decomposition: Algorithm 2 ("ILU0 decomposition"), restricted to
+ *     the sparsity pattern S, with block entries.  Reading for blocks: the
+ *     scalar "e = d * a_ir" with d = 1/a_rr becomes the block product
+ *     a_ir * inv(a_rr) (right multiplication), the only order for which
+ *     L*U reproduces A on S.
+ *   - ILU0 application: equations (3) and (4) of Section "ILU0": forward
+ *     substitution with the unit lower factor, then backward substitution
+ *     with the upper factor.  The body of Algorithm 1 is not printed; the
+ *     substitutions are reconstructed from the equations.
+ *   - Level scheduling and graph colouring: Section "ILU0" of the
+ *     implementation chapter.  LS levels respect direct and indirect lower
+ *     dependencies; GC is greedy first-fit in natural order on the
+ *     symmetrised graph (the paper does not name its colouring algorithm).
+ *     Rows are then sorted stably by (level or colour, original index) and a
+ *     reordered copy of the matrix and of b is made.
+ *   - BiCGStab: named in Section "Bicgstab solver" (spmv, axpy, norm, dot)
+ *     but not written out; the preconditioned form of van der Vorst (1992)
+ *     as given in Barrett et al., "Templates" (1994), with x0 = 0.
+ *   - Stopping rule: relative reduction 1e-2 of the residual 2-norm, at
+ *     most 200 iterations (Section "Bicgstab solver"), tested after both the
+ *     half step (on s) and the full step (on r).
+ *   - Zero-diagonal check (Section "Profiling", runtime breakdown table):
+ *     a missing diagonal block is a pattern error; a singular diagonal block
+ *     during the decomposition is a zero pivot.
+ *
+ * parity unpinned: the mixed-precision apply's FP32 summation order (its
+ * result is pinned only by error bounds, not bit for bit).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_NOT_CONVERGED 1
+#define ORC_BREAKDOWN 2
+#define ORC_INVALID -1
+#define ORC_BAD_PATTERN -3
+#define ORC_MISSING_DIAG -4
+#define ORC_ZERO_PIVOT -5
+#define ORC_NON_FINITE -6
+#define ORC_NO_MEMORY -7
+
+#define ORC_ORDER_NATURAL 0
+#define ORC_ORDER_LEVEL 1
+#define ORC_ORDER_COLOUR 2
+
+#define ORC_PREC_ILU_F64 0
+#define ORC_PREC_ILU_F32 1
+#define ORC_PREC_NONE 2
+
+typedef struct {
+    int status;
+    int half_steps;
+    double r0_norm;
+    double final_norm;
+    double true_rel_residual;
+} orc_info;
+
+/* ---------------------------------------------------------------- pattern */
+
+/* Sorted, unique, in-range columns; a diagonal block in every row.
+ * Returns 0, ORC_BAD_PATTERN or ORC_MISSING_DIAG; *bad_row names the row. */
+int orc_validate(int n, const int *rowptr, const int *colidx, int *bad_row)
+{
+    *bad_row = -1;
+    if (n < 0 || rowptr[0] != 0) return ORC_BAD_PATTERN;
+    for (int i = 0; i < n; ++i) {
+        int has_diag = 0;
+        if (rowptr[i + 1] < rowptr[i]) { *bad_row = i; return ORC_BAD_PATTERN; }
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            int j = colidx[p];
+            if (j < 0 || j >= n) { *bad_row = i; return ORC_BAD_PATTERN; }
+            if (p > rowptr[i] && colidx[p - 1] >= j) { *bad_row = i; return ORC_BAD_PATTERN; }
+            if (j == i) has_diag = 1;
+        }
+        if (!has_diag) { *bad_row = i; return ORC_MISSING_DIAG; }
+    }
+    return ORC_OK;
+}
+
+static int find_col(const int *rowptr, const int *colidx, int i, int j)
+{
+    for (int p = rowptr[i]; p < rowptr[i + 1]; ++p)
+        if (colidx[p] == j) return p;
+    return -1;
+}
+
+/* Stable sort of rows by key (counting sort): perm[new] = old. */
+static void sort_by_key(int n, const int *key, int nkeys, int *perm)
+{
+    int *count = calloc((size_t)nkeys + 1, sizeof(int));
+    for (int i = 0; i < n; ++i) count[key[i] + 1]++;
+    for (int c = 0; c < nkeys; ++c) count[c + 1] += count[c];
+    for (int i = 0; i < n; ++i) perm[count[key[i]]++] = i;
+    free(count);
+}
+
+/* Level scheduling on lower dependencies: level(i) = 1 + max level(j) over
+ * j < i with (i,j) in S, 0 when row i has no lower entry.  Rows sorted
+ * stably by level.  Returns the number of levels. */
+int orc_level_sets(int n, const int *rowptr, const int *colidx, int *level, int *perm)
+{
+    int nlev = 0;
+    for (int i = 0; i < n; ++i) {
+        int lv = 0;
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            int j = colidx[p];
+            if (j < i && level[j] + 1 > lv) lv = level[j] + 1;
+        }
+        level[i] = lv;
+        if (lv + 1 > nlev) nlev = lv + 1;
+    }
+    sort_by_key(n, level, nlev, perm);
+    return nlev;
+}
+
+/* Greedy first-fit colouring in natural order on the symmetrised graph
+ * (i ~ j when (i,j) or (j,i) is in S, i != j).  Rows sorted stably by colour.
+ * Returns the number of colours. */
+int orc_greedy_colour(int n, const int *rowptr, const int *colidx, int *colour, int *perm)
+{
+    int nnz = rowptr[n];
+    /* transpose pattern, to see (j,i) entries from row i */
+    int *tptr = calloc((size_t)n + 1, sizeof(int));
+    int *tcol = malloc(sizeof(int) * (size_t)(nnz > 0 ? nnz : 1));
+    int *fill = malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    int *mark = malloc(sizeof(int) * (size_t)(n + 2));
+    for (int p = 0; p < nnz; ++p) tptr[colidx[p] + 1]++;
+    for (int i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
+    memcpy(fill, tptr, sizeof(int) * (size_t)n);
+    for (int i = 0; i < n; ++i)
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) tcol[fill[colidx[p]]++] = i;
+    for (int c = 0; c < n + 2; ++c) mark[c] = -1;
+    int ncol = 0;
+    for (int i = 0; i < n; ++i) colour[i] = -1;
+    for (int i = 0; i < n; ++i) {
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            int j = colidx[p];
+            if (j != i && colour[j] >= 0) mark[colour[j]] = i;
+        }
+        for (int p = tptr[i]; p < tptr[i + 1]; ++p) {
+            int j = tcol[p];
+            if (j != i && colour[j] >= 0) mark[colour[j]] = i;
+        }
+        int c = 0;
+        while (mark[c] == i) ++c;
+        colour[i] = c;
+        if (c + 1 > ncol) ncol = c + 1;
+    }
+    sort_by_key(n, colour, ncol, perm);
+    free(tptr); free(tcol); free(fill); free(mark);
+    return ncol;
+}
+
+/* A' = P A P^T with perm[new] = old: row i of A' is row perm[i] of A, its
+ * columns renamed by the inverse permutation and re-sorted ascending.
+ * Output arrays are sized like the input. */
+void orc_permute(int n, const int *rowptr, const int *colidx, const double *vals, const int *perm,
+                 int *prow, int *pcol, double *pvals)
+{
+    int *iperm = malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    for (int i = 0; i < n; ++i) iperm[perm[i]] = i;
+    prow[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        int old = perm[i];
+        int len = rowptr[old + 1] - rowptr[old];
+        int base = prow[i];
+        prow[i + 1] = base + len;
+        /* insertion sort by new column index; rows are short */
+        for (int q = 0; q < len; ++q) {
+            int p = rowptr[old] + q;
+            int jn = iperm[colidx[p]];
+            int t = base + q;
+            while (t > base && pcol[t - 1] > jn) {
+                pcol[t] = pcol[t - 1];
+                memcpy(pvals + 9 * (size_t)t, pvals + 9 * (size_t)(t - 1), 9 * sizeof(double));
+                --t;
+            }
+            pcol[t] = jn;
+            memcpy(pvals + 9 * (size_t)t, vals + 9 * (size_t)p, 9 * sizeof(double));
+        }
+    }
+    free(iperm);
+}
+
+/* ------------------------------------------------------------ 3x3 algebra */
+
+/* Inverse by the adjugate: inv(A) = adj(A) / det(A).  Returns 0 when the
+ * determinant is zero or not finite. */
+static int inv3(const double *a, double *out)
+{
+    double c00 = a[4] * a[8] - a[5] * a[7];
+    double c01 = a[5] * a[6] - a[3] * a[8];
+    double c02 = a[3] * a[7] - a[4] * a[6];
+    double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+    if (det == 0.0 || !isfinite(det)) return 0;
+    out[0] = c00 / det;
+    out[1] = (a[2] * a[7] - a[1] * a[8]) / det;
+    out[2] = (a[1] * a[5] - a[2] * a[4]) / det;
+    out[3] = c01 / det;
+    out[4] = (a[0] * a[8] - a[2] * a[6]) / det;
+    out[5] = (a[2] * a[3] - a[0] * a[5]) / det;
+    out[6] = c02 / det;
+    out[7] = (a[1] * a[6] - a[0] * a[7]) / det;
+    out[8] = (a[0] * a[4] - a[1] * a[3]) / det;
+    return 1;
+}
+
+/* c = a * b, 3x3 row-major */
+static void mul3(const double *a, const double *b, double *c)
+{
+    for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) {
+            double s = 0.0;
+            for (int m = 0; m < 3; ++m) s += a[3 * r + m] * b[3 * m + k];
+            c[3 * r + k] = s;
+        }
+}
+
+int orc_inv3(const double *a, double *out) { return inv3(a, out); }
+
+/* -------------------------------------------------------------- ILU0 (Alg 2) */
+
+/* Block ILU0 in place, row by row (IKJ form of Algorithm 2): for each row i
+ * and each k < i in row i, ascending, L_ik = a_ik inv(U_kk), then
+ * a_ij -= L_ik U_kj for every j > k with (k,j) and (i,j) in S.  When row i
+ * is done its diagonal block is U_ii and dinv_i = inv(U_ii).
+ * On return vals holds L (strictly lower blocks; unit diagonal implied) and
+ * U (diagonal and upper blocks); dinv holds inv(U_ii).
+ * A singular or non-finite U_ii gives ORC_ZERO_PIVOT and *bad_row = i. */
+int orc_ilu0(int n, const int *rowptr, const int *colidx, double *vals, double *dinv, int *bad_row)
+{
+    double tmp[9];
+    *bad_row = -1;
+    for (int i = 0; i < n; ++i) {
+        int pdiag = -1;
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            int k = colidx[p];
+            if (k == i) pdiag = p;
+            if (k >= i) continue;
+            mul3(vals + 9 * (size_t)p, dinv + 9 * (size_t)k, tmp);
+            memcpy(vals + 9 * (size_t)p, tmp, sizeof tmp);
+            for (int q = rowptr[k]; q < rowptr[k + 1]; ++q) {
+                int j = colidx[q];
+                if (j <= k) continue;
+                int t = find_col(rowptr, colidx, i, j);
+                if (t < 0) continue; /* (i,j) not in S: fill is dropped */
+                double prod[9];
+                mul3(vals + 9 * (size_t)p, vals + 9 * (size_t)q, prod);
+                for (int e = 0; e < 9; ++e) vals[9 * (size_t)t + e] -= prod[e];
+            }
+        }
+        if (pdiag < 0) { *bad_row = i; return ORC_MISSING_DIAG; }
+        if (!inv3(vals + 9 * (size_t)pdiag, dinv + 9 * (size_t)i)) { *bad_row = i; return ORC_ZERO_PIVOT; }
+    }
+    return ORC_OK;
+}
+
+/* Algorithm 2 as printed (KIJ): for each pivot row r, d = inv(a_rr); for each
+ * later row i with (i,r) in S: e = a_ir d, a_ir = e, and a_ij -= e a_rj for
+ * j > r with (i,j), (r,j) in S.  Same result as orc_ilu0; kept to check that
+ * the row-by-row form performs the same updates in the same order. */
+int orc_ilu0_kij(int n, const int *rowptr, const int *colidx, double *vals, double *dinv, int *bad_row)
+{
+    double e[9], prod[9];
+    *bad_row = -1;
+    for (int r = 0; r < n; ++r) {
+        int prr = find_col(rowptr, colidx, r, r);
+        if (prr < 0) { *bad_row = r; return ORC_MISSING_DIAG; }
+        if (!inv3(vals + 9 * (size_t)prr, dinv + 9 * (size_t)r)) { *bad_row = r; return ORC_ZERO_PIVOT; }
+        for (int i = r + 1; i < n; ++i) {
+            int pir = find_col(rowptr, colidx, i, r);
+            if (pir < 0) continue;
+            mul3(vals + 9 * (size_t)pir, dinv + 9 * (size_t)r, e);
+            memcpy(vals + 9 * (size_t)pir, e, sizeof e);
+            for (int q = rowptr[r]; q < rowptr[r + 1]; ++q) {
+                int j = colidx[q];
+                if (j <= r) continue;
+                int t = find_col(rowptr, colidx, i, j);
+                if (t < 0) continue;
+                mul3(e, vals + 9 * (size_t)q, prod);
+                for (int m = 0; m < 9; ++m) vals[9 * (size_t)t + m] -= prod[m];
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------- apply (eqs 3, 4) */
+
+/* z = U^{-1} L^{-1} v: forward substitution y_i = v_i - sum_{j<i} L_ij y_j
+ * (i ascending), then backward z_i = dinv_i (y_i - sum_{j>i} U_ij z_j)
+ * (i descending); sums over a row in ascending column order. */
+void orc_apply(int n, const int *rowptr, const int *colidx, const double *lu, const double *dinv,
+               const double *v, double *z)
+{
+    double *y = malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    for (int i = 0; i < n; ++i) {
+        double acc[3] = {v[3 * i], v[3 * i + 1], v[3 * i + 2]};
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            int j = colidx[p];
+            if (j >= i) break;
+            const double *b = lu + 9 * (size_t)p;
+            for (int r = 0; r < 3; ++r)
+                acc[r] -= b[3 * r] * y[3 * j] + b[3 * r + 1] * y[3 * j + 1] + b[3 * r + 2] * y[3 * j + 2];
+        }
+        y[3 * i] = acc[0]; y[3 * i + 1] = acc[1]; y[3 * i + 2] = acc[2];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double acc[3] = {y[3 * i], y[3 * i + 1], y[3 * i + 2]};
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            int j = colidx[p];
+            if (j <= i) continue;
+            const double *b = lu + 9 * (size_t)p;
+            for (int r = 0; r < 3; ++r)
+                acc[r] -= b[3 * r] * z[3 * j] + b[3 * r + 1] * z[3 * j + 1] + b[3 * r + 2] * z[3 * j + 2];
+        }
+        const double *d = dinv + 9 * (size_t)i;
+        for (int r = 0; r < 3; ++r)
+            z[3 * i + r] = d[3 * r] * acc[0] + d[3 * r + 1] * acc[1] + d[3 * r + 2] * acc[2];
+    }
+    free(y);
+}
+
+/* The same substitutions with factors and the input vector rounded to FP32
+ * (round to nearest even) and every operation of the sweeps in FP32; the
+ * result is widened back to FP64.  lu32/dinv32 hold the rounded factors. */
+void orc_apply_f32(int n, const int *rowptr, const int *colidx, const float *lu32, const float *dinv32,
+                   const double *v, double *z)
+{
+    float *y = malloc(sizeof(float) * 3 * (size_t)(n > 0 ? n : 1));
+    float *zz = malloc(sizeof(float) * 3 * (size_t)(n > 0 ? n : 1));
+    for (int i = 0; i < n; ++i) {
+        float acc[3] = {(float)v[3 * i], (float)v[3 * i + 1], (float)v[3 * i + 2]};
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            int j = colidx[p];
+            if (j >= i) break;
+            const float *b = lu32 + 9 * (size_t)p;
+            for (int r = 0; r < 3; ++r)
+                acc[r] -= b[3 * r] * y[3 * j] + b[3 * r + 1] * y[3 * j + 1] + b[3 * r + 2] * y[3 * j + 2];
+        }
+        y[3 * i] = acc[0]; y[3 * i + 1] = acc[1]; y[3 * i + 2] = acc[2];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        float acc[3] = {y[3 * i], y[3 * i + 1], y[3 * i + 2]};
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            int j = colidx[p];
+            if (j <= i) continue;
+            const float *b = lu32 + 9 * (size_t)p;
+            for (int r = 0; r < 3; ++r)
+                acc[r] -= b[3 * r] * zz[3 * j] + b[3 * r + 1] * zz[3 * j + 1] + b[3 * r + 2] * zz[3 * j + 2];
+        }
+        const float *d = dinv32 + 9 * (size_t)i;
+        for (int r = 0; r < 3; ++r)
+            zz[3 * i + r] = d[3 * r] * acc[0] + d[3 * r + 1] * acc[1] + d[3 * r + 2] * acc[2];
+    }
+    for (int i = 0; i < 3 * n; ++i) z[i] = (double)zz[i];
+    free(y);
+    free(zz);
+}
+
+/* --------------------------------------------------------- SpMV, vectors */
+
+/* y = A x, blocks row-major, ascending column order within a row. */
+void orc_spmv(int n, const int *rowptr, const int *colidx, const double *vals, const double *x, double *y)
+{
+    for (int i = 0; i < n; ++i) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            const double *b = vals + 9 * (size_t)p;
+            const double *xj = x + 3 * (size_t)colidx[p];
+            for (int r = 0; r < 3; ++r) acc[r] += b[3 * r] * xj[0] + b[3 * r + 1] * xj[1] + b[3 * r + 2] * xj[2];
+        }
+        y[3 * i] = acc[0]; y[3 * i + 1] = acc[1]; y[3 * i + 2] = acc[2];
+    }
+}
+
+static double dot(int m, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* --------------------------------------------------------------- BiCGStab */
+
+typedef struct {
+    int kind;                  /* ORC_PREC_* */
+    int n;
+    const int *rowptr, *colidx;
+    const double *lu, *dinv;   /* FP64 factors */
+    const float *lu32, *dinv32;
+} precond;
+
+static void prec_apply(const precond *m, const double *v, double *z)
+{
+    if (m->kind == ORC_PREC_ILU_F64) orc_apply(m->n, m->rowptr, m->colidx, m->lu, m->dinv, v, z);
+    else if (m->kind == ORC_PREC_ILU_F32) orc_apply_f32(m->n, m->rowptr, m->colidx, m->lu32, m->dinv32, v, z);
+    else memcpy(z, v, sizeof(double) * 3 * (size_t)m->n);
+}
+
+/* Preconditioned BiCGStab on one system (already in the order the factors
+ * were computed in).  x0 = 0, r0 = b, rhat = r0, rho_old = alpha = omega = 1,
+ * v = p = 0.  Each iteration i:
+ *   rho = (rhat, r); beta = (rho / rho_old)(alpha / omega);
+ *   p = r + beta (p - omega v); phat = M^{-1} p; v = A phat;
+ *   alpha = rho / (rhat, v); s = r - alpha v;
+ *   ||s|| <= tol: x += alpha phat, stop after 2i-1 half steps;
+ *   shat = M^{-1} s; t = A shat; omega = (t, s) / (t, t);
+ *   x += alpha phat + omega shat; r = s - omega t;
+ *   ||r|| <= tol: stop after 2i half steps;  rho_old = rho.
+ * tol = reduction * ||r0||.  Breakdown when rho, (rhat, v), (t, t) or omega
+ * is zero; non-finite scalars give ORC_NON_FINITE.  On an omega breakdown
+ * x keeps the half-step update.  max_iter full iterations without meeting
+ * the test give ORC_NOT_CONVERGED with the last iterate in x.
+ * trace (optional, 8 doubles per iteration): rho, (rhat,v), alpha, ||s||,
+ * (t,s), (t,t), omega, ||r||. */
+static int bicgstab(int n, const int *rowptr, const int *colidx, const double *vals, const precond *m,
+                    const double *b, double reduction, int max_iter, double *x, orc_info *info, double *trace)
+{
+    size_t m3 = 3 * (size_t)n;
+    size_t bytes = sizeof(double) * (m3 > 0 ? m3 : 1);
+    double *r = malloc(bytes), *rhat = malloc(bytes), *p = malloc(bytes), *v = malloc(bytes);
+    double *phat = malloc(bytes), *s = malloc(bytes), *shat = malloc(bytes), *t = malloc(bytes);
+    int status = ORC_NOT_CONVERGED, half = 0;
+    for (size_t i = 0; i < m3; ++i) { x[i] = 0.0; r[i] = b[i]; rhat[i] = b[i]; p[i] = 0.0; v[i] = 0.0; }
+    double r0 = sqrt(dot((int)m3, r, r));
+    double tol = reduction * r0;
+    double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    double rho = dot((int)m3, rhat, r);
+    double last = r0;
+    info->r0_norm = r0;
+    if (!isfinite(r0)) { status = ORC_NON_FINITE; goto done; }
+    if (r0 == 0.0) { status = ORC_OK; goto done; }
+    for (int it = 1; it <= max_iter; ++it) {
+        double *tr = trace ? trace + 8 * (size_t)(it - 1) : NULL;
+        if (rho == 0.0) { status = ORC_BREAKDOWN; goto done; }
+        double beta = (rho / rho_old) * (alpha / omega);
+        for (size_t i = 0; i < m3; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        prec_apply(m, p, phat);
+        orc_spmv(n, rowptr, colidx, vals, phat, v);
+        double rv = dot((int)m3, rhat, v);
+        if (tr) { tr[0] = rho; tr[1] = rv; }
+        if (!isfinite(rv)) { status = ORC_NON_FINITE; goto done; }
+        if (rv == 0.0) { status = ORC_BREAKDOWN; goto done; }
+        alpha = rho / rv;
+        for (size_t i = 0; i < m3; ++i) s[i] = r[i] - alpha * v[i];
+        double snorm = sqrt(dot((int)m3, s, s));
+        if (tr) { tr[2] = alpha; tr[3] = snorm; }
+        if (!isfinite(snorm)) { status = ORC_NON_FINITE; goto done; }
+        half = 2 * it - 1;
+        last = snorm;
+        if (snorm <= tol) {
+            for (size_t i = 0; i < m3; ++i) x[i] += alpha * phat[i];
+            status = ORC_OK;
+            goto done;
+        }
+        prec_apply(m, s, shat);
+        orc_spmv(n, rowptr, colidx, vals, shat, t);
+        double ts = dot((int)m3, t, s), tt = dot((int)m3, t, t);
+        if (tr) { tr[4] = ts; tr[5] = tt; }
+        if (!isfinite(ts) || !isfinite(tt)) { status = ORC_NON_FINITE; goto done; }
+        if (tt == 0.0) { status = ORC_BREAKDOWN; goto done; }
+        omega = ts / tt;
+        if (tr) tr[6] = omega;
+        if (omega == 0.0) {
+            for (size_t i = 0; i < m3; ++i) x[i] += alpha * phat[i];
+            status = ORC_BREAKDOWN;
+            goto done;
+        }
+        for (size_t i = 0; i < m3; ++i) {
+            x[i] += alpha * phat[i] + omega * shat[i];
+            r[i] = s[i] - omega * t[i];
+        }
+        double rnorm = sqrt(dot((int)m3, r, r));
+        if (tr) tr[7] = rnorm;
+        if (!isfinite(rnorm)) { status = ORC_NON_FINITE; goto done; }
+        half = 2 * it;
+        last = rnorm;
+        if (rnorm <= tol) { status = ORC_OK; goto done; }
+        rho_old = rho;
+        rho = dot((int)m3, rhat, r);
+    }
+    status = ORC_NOT_CONVERGED;
+done:
+    info->status = status;
+    info->half_steps = half;
+    info->final_norm = last;
+    free(r); free(rhat); free(p); free(v); free(phat); free(s); free(shat); free(t);
+    return status;
+}
+
+/* BiCGStab on an already ordered system with given factors (lu, dinv: FP64
+ * factors from orc_ilu0 on the same pattern).  precond_kind picks the FP64
+ * factors, their FP32 roundings, or no preconditioner. */
+int orc_bicgstab(int n, const int *rowptr, const int *colidx, const double *vals, const double *lu,
+                 const double *dinv, int precond_kind, const double *b, double reduction, int max_iter,
+                 double *x, orc_info *info, double *trace)
+{
+    precond m = {precond_kind, n, rowptr, colidx, lu, dinv, NULL, NULL};
+    float *lu32 = NULL, *dinv32 = NULL;
+    if (precond_kind == ORC_PREC_ILU_F32) {
+        size_t nnz = (size_t)rowptr[n];
+        lu32 = malloc(sizeof(float) * 9 * (nnz > 0 ? nnz : 1));
+        dinv32 = malloc(sizeof(float) * 9 * (size_t)(n > 0 ? n : 1));
+        for (size_t e = 0; e < 9 * nnz; ++e) lu32[e] = (float)lu[e];
+        for (size_t e = 0; e < 9 * (size_t)n; ++e) dinv32[e] = (float)dinv[e];
+        m.lu32 = lu32;
+        m.dinv32 = dinv32;
+    }
+    int st = bicgstab(n, rowptr, colidx, vals, &m, b, reduction, max_iter, x, info, trace);
+    free(lu32);
+    free(dinv32);
+    return st;
+}
+
+/* The whole path on one system in its original order:
+ * validate -> ordering (natural, LS or GC) -> reordered copy of A and b ->
+ * ILU0 -> BiCGStab -> x back to the original order -> true residual
+ * ||b - A x|| / ||b|| with the original A.  perm_out (n ints, may be NULL)
+ * receives perm[new] = old; *n_sets the number of levels or colours
+ * (n for the natural order). */
+int orc_solve(int n, const int *rowptr, const int *colidx, const double *vals, const double *b,
+              int ordering, int precond_kind, double reduction, int max_iter, double *x,
+              orc_info *info, int *perm_out, int *n_sets, int *bad_row)
+{
+    int st = orc_validate(n, rowptr, colidx, bad_row);
+    memset(info, 0, sizeof *info);
+    info->status = st;
+    if (st != ORC_OK) return st;
+    size_t nnz = (size_t)rowptr[n];
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int *key = malloc(sizeof(int) * nn), *perm = malloc(sizeof(int) * nn);
+    int *prow = malloc(sizeof(int) * (nn + 1)), *pcol = malloc(sizeof(int) * (nnz > 0 ? nnz : 1));
+    double *pvals = malloc(sizeof(double) * 9 * (nnz > 0 ? nnz : 1));
+    double *lu = malloc(sizeof(double) * 9 * (nnz > 0 ? nnz : 1));
+    double *dinv = malloc(sizeof(double) * 9 * nn);
+    double *pb = malloc(sizeof(double) * 3 * nn), *px = malloc(sizeof(double) * 3 * nn);
+    double *ax = malloc(sizeof(double) * 3 * nn);
+    int sets = n;
+    if (ordering == ORC_ORDER_LEVEL) sets = orc_level_sets(n, rowptr, colidx, key, perm);
+    else if (ordering == ORC_ORDER_COLOUR) sets = orc_greedy_colour(n, rowptr, colidx, key, perm);
+    else for (int i = 0; i < n; ++i) perm[i] = i;
+    if (n_sets) *n_sets = sets;
+    if (perm_out) memcpy(perm_out, perm, sizeof(int) * (size_t)n);
+    orc_permute(n, rowptr, colidx, vals, perm, prow, pcol, pvals);
+    memcpy(lu, pvals, sizeof(double) * 9 * nnz);
+    if (precond_kind != ORC_PREC_NONE) {
+        int brow;
+        st = orc_ilu0(n, prow, pcol, lu, dinv, &brow);
+        if (st != ORC_OK) {
+            *bad_row = brow >= 0 ? perm[brow] : -1;
+            info->status = st;
+            goto out;
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c) pb[3 * i + c] = b[3 * (size_t)perm[i] + c];
+    st = orc_bicgstab(n, prow, pcol, pvals, lu, dinv, precond_kind, pb, reduction, max_iter, px, info, NULL);
+    for (int i = 0; i < n; ++i)
+        for (int c = 0; c < 3; ++c) x[3 * (size_t)perm[i] + c] = px[3 * i + c];
+    orc_spmv(n, rowptr, colidx, vals, x, ax);
+    {
+        double rr = 0.0, bb = 0.0;
+        for (size_t i = 0; i < 3 * (size_t)n; ++i) {
+            double d = b[i] - ax[i];
+            rr += d * d;
+            bb += b[i] * b[i];
+        }
+        info->true_rel_residual = bb > 0.0 ? sqrt(rr) / sqrt(bb) : 0.0;
+    }
+out:
+    free(key); free(perm); free(prow); free(pcol); free(pvals); free(lu); free(dinv);
+    free(pb); free(px); free(ax);
+    return st;
+}

@@ -1,0 +1,380 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test fixes one part of the oracle with an independent truth: a
+hand-derived fixture, exact LU where ILU0 drops no fill, dense triangular
+solves, closed-form level/colour counts, Krylov finite-termination, the
+minimisation property of the BiCGStab omega step, and the agreement of the
+recursive and true residuals.
+"""
+
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+from synth import config_system, make_grid_system
+from tests.helpers import (chain_pattern, dense_pattern, pattern_from_pairs, pattern_set, random_values,
+                           read_golden, split_lu, to_dense)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------- fixture
+
+def test_golden_two_block_ilu0():
+    g = read_golden(os.path.join(GOLDEN, "ilu0_two_block.txt"))
+    rowptr, colidx = dense_pattern(2)
+    vals = np.stack([g["A00"], g["A01"], g["A10"], g["A11"]])
+    st, bad, lu, dinv = oracle.ilu0(rowptr, colidx, vals)
+    assert st == oracle.OK and bad == -1
+    np.testing.assert_allclose(lu[0], g["A00"], rtol=0, atol=1e-15)   # U00 = A00
+    np.testing.assert_allclose(lu[1], g["A01"], rtol=0, atol=1e-15)   # U01 = A01
+    np.testing.assert_allclose(lu[2], g["L10"], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(lu[3], g["U11"], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(dinv[0], g["DINV0"], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(dinv[1], g["DINV1"], rtol=0, atol=1e-15)
+    x, info = oracle.bicgstab(rowptr, colidx, vals, lu, dinv, g["B"], reduction=1e-12)
+    assert info["status"] == oracle.OK and info["half_steps"] == 1
+    np.testing.assert_allclose(x.ravel(), g["X"], rtol=0, atol=1e-14)
+
+
+# --------------------------------------------------------------- validation
+
+def test_validate_errors():
+    rowptr, colidx = chain_pattern(4)
+    assert oracle.validate(rowptr, colidx) == (oracle.OK, -1)
+    c = colidx.copy()
+    c[3], c[4] = c[4], c[3]                       # unsorted row 1
+    assert oracle.validate(rowptr, c) == (oracle.BAD_PATTERN, 1)
+    c = colidx.copy()
+    c[4] = c[3]                                   # duplicate in row 1
+    assert oracle.validate(rowptr, c)[0] == oracle.BAD_PATTERN
+    c = colidx.copy()
+    c[-1] = 7                                     # out of range
+    assert oracle.validate(rowptr, c) == (oracle.BAD_PATTERN, 3)
+    rp, ci = pattern_from_pairs(3, [(0, 1), (1, 2)])
+    keep = [p for p in range(len(ci)) if not (ci[p] == 2 and p >= rp[2])]  # drop (2,2)
+    rows = np.repeat(np.arange(3), np.diff(rp))[keep]
+    rp2 = np.zeros(4, np.int32)
+    np.cumsum(np.bincount(rows, minlength=3), out=rp2[1:])
+    assert oracle.validate(rp2, ci[keep]) == (oracle.MISSING_DIAG, 2)
+
+
+# -------------------------------------------------------------- orderings
+
+@pytest.mark.parametrize("shape", [(20, 20, 10), (40, 40, 30), (7, 3, 5), (1, 1, 9)])
+def test_level_count_closed_form(shape):
+    s = make_grid_system(*shape, seed=1)
+    nl, level, perm = oracle.level_sets(s.rowptr, s.colidx)
+    assert nl == sum(shape) - 2
+    # level of cell (i,j,k) is its Manhattan distance from the origin
+    nx, ny, nz = shape
+    c = np.arange(nx * ny * nz)
+    assert np.array_equal(level, c % nx + (c // nx) % ny + c // (nx * ny))
+    assert np.array_equal(np.sort(perm), np.arange(s.n))
+
+
+def test_level_sets_respect_dependencies():
+    s = make_grid_system(12, 10, 6, active_frac=0.8, nnc_frac=0.05, seed=3)
+    nl, level, perm = oracle.level_sets(s.rowptr, s.colidx)
+    for i in range(s.n):
+        for p in range(s.rowptr[i], s.rowptr[i + 1]):
+            j = s.colidx[p]
+            if j < i:
+                assert level[j] < level[i]
+    # each row sits one level above its deepest lower dependency
+    for i in range(s.n):
+        deps = [level[j] for j in s.colidx[s.rowptr[i]:s.rowptr[i + 1]] if j < i]
+        assert level[i] == (max(deps) + 1 if deps else 0)
+    # stable order inside a level
+    assert np.all(np.diff(level[perm]) >= 0)
+    for lv in range(nl):
+        rows = perm[level[perm] == lv]
+        assert np.all(np.diff(rows) > 0)
+
+
+@pytest.mark.parametrize("shape", [(20, 20, 10), (5, 6, 7)])
+def test_greedy_colour_full_grid_is_red_black(shape):
+    s = make_grid_system(*shape, seed=2)
+    nc, col, perm = oracle.greedy_colour(s.rowptr, s.colidx)
+    assert nc == 2
+    nx, ny, _ = shape
+    c = np.arange(s.n)
+    assert np.array_equal(col, (c % nx + (c // nx) % ny + c // (nx * ny)) % 2)
+
+
+def test_greedy_colour_is_proper_on_nnc_pattern():
+    s = make_grid_system(14, 12, 8, active_frac=0.85, nnc_frac=0.02, seed=5)
+    nc, col, perm = oracle.greedy_colour(s.rowptr, s.colidx)
+    for i in range(s.n):
+        for j in s.colidx[s.rowptr[i]:s.rowptr[i + 1]]:
+            if j != i:
+                assert col[i] != col[j]
+    # first fit: every row with colour c > 0 touches colours 0..c-1
+    for i in range(s.n):
+        nb = {col[j] for j in s.colidx[s.rowptr[i]:s.rowptr[i + 1]] if j != i}
+        assert set(range(col[i])) <= nb
+
+
+def test_permute_is_similarity():
+    s = make_grid_system(6, 5, 4, active_frac=0.9, nnc_frac=0.05, seed=7)
+    vals = s.vals[0]
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(s.n).astype(np.int32)
+    prow, pcol, pv = oracle.permute(s.rowptr, s.colidx, vals, perm)
+    assert oracle.validate(prow, pcol)[0] == oracle.OK
+    P = np.zeros((3 * s.n, 3 * s.n))
+    for new, old in enumerate(perm):
+        P[3 * new:3 * new + 3, 3 * old:3 * old + 3] = np.eye(3)
+    A = to_dense(s.rowptr, s.colidx, vals)
+    assert np.array_equal(to_dense(prow, pcol, pv), P @ A @ P.T)
+
+
+# --------------------------------------------------------------------- ILU0
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8])
+def test_ilu0_dense_pattern_is_exact_lu(n):
+    rowptr, colidx = dense_pattern(n)
+    vals = random_values(rowptr, colidx, seed=n)
+    st, _, lu, dinv = oracle.ilu0(rowptr, colidx, vals)
+    assert st == oracle.OK
+    L, U = split_lu(rowptr, colidx, lu)
+    A = to_dense(rowptr, colidx, vals)
+    assert np.linalg.norm(L @ U - A) / np.linalg.norm(A) < 1e-14
+    for i in range(n):
+        d = i * n + i
+        np.testing.assert_allclose(dinv[i] @ lu[d], np.eye(3), atol=1e-13)
+
+
+def test_ilu0_chain_is_exact_lu():
+    rowptr, colidx = chain_pattern(30)
+    vals = random_values(rowptr, colidx, seed=11, diag_boost=1.0)
+    st, _, lu, _ = oracle.ilu0(rowptr, colidx, vals)
+    assert st == oracle.OK
+    L, U = split_lu(rowptr, colidx, lu)
+    A = to_dense(rowptr, colidx, vals)
+    assert np.linalg.norm(L @ U - A) / np.linalg.norm(A) < 1e-14
+
+
+@pytest.mark.parametrize("case", ["c1", "nnc"])
+def test_ilu0_reproduces_a_on_pattern(case):
+    if case == "c1":
+        s = config_system("c1")
+    else:
+        s = make_grid_system(10, 9, 6, active_frac=0.85, nnc_frac=0.05, seed=4)
+    vals = s.vals[0]
+    st, _, lu, _ = oracle.ilu0(s.rowptr, s.colidx, vals)
+    assert st == oracle.OK
+    L, U = split_lu(s.rowptr, s.colidx, lu)
+    LU = L @ U
+    A = to_dense(s.rowptr, s.colidx, vals)
+    mask = np.zeros_like(A, dtype=bool)
+    for (i, j) in pattern_set(s.rowptr, s.colidx):
+        mask[3 * i:3 * i + 3, 3 * j:3 * j + 3] = True
+    err = np.abs(LU - A)[mask].max() / np.abs(A).max()
+    assert err < 1e-14
+    # and the factorisation is incomplete: fill outside S is dropped
+    if case == "nnc":
+        assert np.abs(LU - A)[~mask].max() > 1e-6
+
+
+def test_ilu0_kij_equals_ikj_bitwise():
+    s = make_grid_system(9, 8, 5, active_frac=0.85, nnc_frac=0.08, seed=9)
+    st1, _, lu1, d1 = oracle.ilu0(s.rowptr, s.colidx, s.vals[0])
+    st2, _, lu2, d2 = oracle.ilu0(s.rowptr, s.colidx, s.vals[0], kij=True)
+    assert st1 == st2 == oracle.OK
+    assert np.array_equal(lu1, lu2) and np.array_equal(d1, d2)
+
+
+def test_ilu0_level_order_invariance():
+    s = config_system("c1")
+    vals = s.vals[0]
+    _, _, perm = oracle.level_sets(s.rowptr, s.colidx)
+    prow, pcol, pv = oracle.permute(s.rowptr, s.colidx, vals, perm)
+    _, _, lu, dinv = oracle.ilu0(s.rowptr, s.colidx, vals)
+    _, _, plu, pdinv = oracle.ilu0(prow, pcol, pv)
+    q_lu = oracle.permute(s.rowptr, s.colidx, lu, perm)[2]
+    assert np.abs(q_lu - plu).max() <= 1e-14 * np.abs(lu).max()
+    assert np.abs(dinv[perm] - pdinv).max() <= 1e-14 * np.abs(dinv).max()
+
+
+def test_ilu0_zero_pivot_reports_row():
+    rowptr, colidx = chain_pattern(5)
+    vals = random_values(rowptr, colidx, seed=1)
+    vals[rowptr[3] + 1] = 0.0           # diagonal block of row 3 (row 3 has cols 2,3,4)
+    vals[rowptr[3]] = 0.0               # and no incoming update
+    st, bad, _, _ = oracle.ilu0(rowptr, colidx, vals)
+    assert (st, bad) == (oracle.ZERO_PIVOT, 3)
+
+
+def test_inv3_matches_linalg():
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        a = rng.standard_normal((3, 3))
+        ok, inv = oracle.inv3(a)
+        assert ok
+        np.testing.assert_allclose(inv, np.linalg.inv(a), rtol=1e-12, atol=1e-12)
+    assert oracle.inv3(np.ones((3, 3)))[0] == 0
+
+
+# -------------------------------------------------------------------- apply
+
+def test_apply_equals_dense_triangular_solves():
+    s = make_grid_system(6, 5, 4, active_frac=0.85, nnc_frac=0.05, seed=12)
+    vals = s.vals[0]
+    _, _, lu, dinv = oracle.ilu0(s.rowptr, s.colidx, vals)
+    L, U = split_lu(s.rowptr, s.colidx, lu)
+    v = np.random.default_rng(1).standard_normal((s.n, 3))
+    z = oracle.apply(s.rowptr, s.colidx, lu, dinv, v)
+    # L is unit lower triangular also entrywise; U is only block upper
+    # triangular (full 3x3 diagonal blocks), so it takes a general solve
+    y = sla.solve_triangular(L, v.ravel(), lower=True, unit_diagonal=True)
+    zr = np.linalg.solve(U, y)
+    assert np.linalg.norm(z.ravel() - zr) / np.linalg.norm(zr) < 1e-13
+
+
+def test_apply_on_chain_is_exact_inverse():
+    rowptr, colidx = chain_pattern(25)
+    vals = random_values(rowptr, colidx, seed=4, diag_boost=1.0)
+    _, _, lu, dinv = oracle.ilu0(rowptr, colidx, vals)
+    v = np.random.default_rng(2).standard_normal((25, 3))
+    z = oracle.apply(rowptr, colidx, lu, dinv, v)
+    A = to_dense(rowptr, colidx, vals)
+    assert np.linalg.norm(A @ z.ravel() - v.ravel()) / np.linalg.norm(v) < 1e-13
+
+
+def test_apply_f32_close_to_f64():
+    s = config_system("c1")
+    _, _, lu, dinv = oracle.ilu0(s.rowptr, s.colidx, s.vals[0])
+    v = np.random.default_rng(5).standard_normal((s.n, 3))
+    z64 = oracle.apply(s.rowptr, s.colidx, lu, dinv, v)
+    z32 = oracle.apply_f32(s.rowptr, s.colidx, lu, dinv, v)
+    rel = np.linalg.norm(z32 - z64) / np.linalg.norm(z64)
+    assert 0 < rel < 1e-5
+
+
+def test_spmv_matches_dense():
+    s = make_grid_system(5, 4, 3, active_frac=0.9, nnc_frac=0.1, seed=8)
+    x = np.random.default_rng(0).standard_normal((s.n, 3))
+    y = oracle.spmv(s.rowptr, s.colidx, s.vals[0], x)
+    yr = to_dense(s.rowptr, s.colidx, s.vals[0]) @ x.ravel()
+    np.testing.assert_allclose(y.ravel(), yr, rtol=1e-13, atol=1e-13)
+
+
+# ----------------------------------------------------------------- BiCGStab
+
+def _dense_with_spectrum(eigs, seed):
+    """A dense 3n x 3n matrix (as a full block pattern) with the given eigenvalues."""
+    n3 = len(eigs)
+    rng = np.random.default_rng(seed)
+    S = rng.standard_normal((n3, n3)) + 3 * np.eye(n3)
+    A = S @ np.diag(eigs) @ np.linalg.inv(S)
+    n = n3 // 3
+    rowptr, colidx = dense_pattern(n)
+    vals = np.stack([A[3 * i:3 * i + 3, 3 * j:3 * j + 3] for i in range(n) for j in range(n)])
+    return rowptr, colidx, vals, A
+
+
+@pytest.mark.parametrize("k,half", [(1, 1), (2, 3), (3, 5)])
+def test_bicgstab_finite_termination(k, half):
+    """Unpreconditioned BiCGStab on a matrix with k distinct eigenvalues: the
+    BiCG polynomial of degree k annihilates r0, so s vanishes at the half step
+    of iteration k (2k-1 half steps) with the exact solution."""
+    eigs = np.repeat([1.0, 2.5, -1.7][:k], [4, 3, 2][:k] if k > 1 else [9])
+    eigs = np.resize(eigs, 9)
+    rowptr, colidx, vals, A = _dense_with_spectrum(eigs, seed=k)
+    b = np.random.default_rng(10 + k).standard_normal(9)
+    x, info = oracle.bicgstab(rowptr, colidx, vals, None, None, b, precond=oracle.PREC_NONE,
+                              reduction=1e-9, max_iter=20)
+    assert info["status"] == oracle.OK
+    assert info["half_steps"] == half
+    np.testing.assert_allclose(x.ravel(), np.linalg.solve(A, b), rtol=1e-8, atol=1e-8)
+
+
+def test_bicgstab_exact_preconditioner_half_step():
+    rowptr, colidx = chain_pattern(40)
+    vals = random_values(rowptr, colidx, seed=6, diag_boost=1.0)
+    _, _, lu, dinv = oracle.ilu0(rowptr, colidx, vals)
+    b = np.random.default_rng(7).standard_normal((40, 3))
+    x, info = oracle.bicgstab(rowptr, colidx, vals, lu, dinv, b, reduction=1e-10)
+    assert info["status"] == oracle.OK and info["half_steps"] == 1
+    A = to_dense(rowptr, colidx, vals)
+    np.testing.assert_allclose(x.ravel(), np.linalg.solve(A, b.ravel()), rtol=1e-12, atol=1e-12)
+
+
+def test_bicgstab_omega_minimises_and_residuals_agree():
+    s = make_grid_system(8, 7, 5, sigma=2.0, active_frac=0.9, nnc_frac=0.03, seed=13)
+    vals = s.vals[0]
+    _, _, lu, dinv = oracle.ilu0(s.rowptr, s.colidx, vals)
+    b = s.b[0, 0]
+    kmax = 6
+    _, _, tr = oracle.bicgstab(s.rowptr, s.colidx, vals, lu, dinv, b, reduction=1e-30, max_iter=kmax,
+                               trace=True)
+    A = to_dense(s.rowptr, s.colidx, vals)
+    for it in range(kmax):
+        rho, rv, alpha, snorm, ts, tt, omega, rnorm = tr[it]
+        # omega = argmin ||s - w t||: the minimum is ||s||^2 - (t,s)^2/(t,t)
+        assert abs(rnorm ** 2 - (snorm ** 2 - ts ** 2 / tt)) <= 1e-9 * snorm ** 2
+        assert rnorm <= snorm * (1 + 1e-12)
+        # the recursively updated residual is the true residual of the iterate
+        xk, info = oracle.bicgstab(s.rowptr, s.colidx, vals, lu, dinv, b, reduction=1e-30, max_iter=it + 1)
+        assert info["status"] == oracle.NOT_CONVERGED and info["half_steps"] == 2 * (it + 1)
+        true = np.linalg.norm(b.ravel() - A @ xk.ravel())
+        assert abs(true - rnorm) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_bicgstab_dense_solve_tight():
+    s = make_grid_system(10, 10, 5, seed=21)
+    A = to_dense(s.rowptr, s.colidx, s.vals[0])
+    b = s.b[0, 0]
+    xr = np.linalg.solve(A, b.ravel())
+    for ordering in (oracle.ORDER_NATURAL, oracle.ORDER_LEVEL, oracle.ORDER_COLOUR):
+        x, info = oracle.solve(s.rowptr, s.colidx, s.vals[0], b, ordering=ordering, reduction=1e-12)
+        assert info["status"] == oracle.OK
+        assert info["true_rel_residual"] <= 1e-11
+        assert np.linalg.norm(x.ravel() - xr) / np.linalg.norm(xr) < 1e-9
+
+
+@pytest.mark.parametrize("precond", [oracle.PREC_ILU_F64, oracle.PREC_ILU_F32])
+@pytest.mark.parametrize("red", [1e-2, 1e-6])
+def test_solve_meets_reduction(precond, red):
+    s = config_system("c1")
+    x, info = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=oracle.ORDER_LEVEL,
+                           precond=precond, reduction=red)
+    assert info["status"] == oracle.OK
+    assert info["final_norm"] <= red * info["r0_norm"]
+    assert info["true_rel_residual"] <= red * (1 + 1e-6)
+
+
+def test_mixed_and_fp64_iteration_counts_close():
+    s = config_system("c1")
+    h = []
+    for precond in (oracle.PREC_ILU_F64, oracle.PREC_ILU_F32):
+        _, info = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=oracle.ORDER_LEVEL,
+                               precond=precond, reduction=1e-6)
+        h.append(info["half_steps"])
+    assert abs(h[0] - h[1]) <= 2
+
+
+def test_stopping_and_fault_statuses():
+    s = config_system("c1")
+    vals, b = s.vals[0], s.b[0, 0]
+    _, info = oracle.solve(s.rowptr, s.colidx, vals, b, reduction=1e-12, max_iter=1)
+    assert info["status"] == oracle.NOT_CONVERGED and info["half_steps"] == 2
+    x, info = oracle.solve(s.rowptr, s.colidx, vals, np.zeros_like(b))
+    assert info["status"] == oracle.OK and info["half_steps"] == 0 and not x.any()
+    bn = b.copy()
+    bn[5, 1] = np.nan
+    _, info = oracle.solve(s.rowptr, s.colidx, vals, bn)
+    assert info["status"] == oracle.NON_FINITE
+    vz = vals.copy()
+    row = 17
+    for p in range(s.rowptr[row], s.rowptr[row + 1]):
+        if s.colidx[p] == row:
+            vz[p] = 0.0
+        elif s.colidx[p] < row:
+            vz[p] = 0.0   # no update reaches the zeroed diagonal
+    _, info = oracle.solve(s.rowptr, s.colidx, vz, b)
+    assert info["status"] == oracle.ZERO_PIVOT and info["bad_row"] == row
