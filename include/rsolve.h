@@ -1,0 +1,179 @@
+/*
+ * rsolve.h -- C ABI of an MI355X (gfx950) block-ILU0-preconditioned BiCGStab
+ * solver for BCSR matrices with 3x3 FP64 blocks.
+ *
+ * Problem statement followed (Qiu et al., "An Evaluation and Comparison of
+ * GPU Hardware and Solver Libraries for Accelerating the OPM Flow Reservoir
+ * Simulator"):
+ *   - a matrix handed over as three arrays, nonzero blocks, row pointers and
+ *     column indices, blocks stored row-major one after another, vectors as
+ *     one contiguous array of 3 values per block row (Section "OPM Flow");
+ *   - a sparsity pattern analysed once and reused while the values change
+ *     every solve; rows reordered by level scheduling or graph colouring, or
+ *     kept in natural order (Section "ILU0" of the implementation chapter);
+ *   - ILU0 decomposition (Algorithm 2) and application (equations 3-4);
+ *   - BiCGStab with a relative residual reduction (default 1e-2) and an
+ *     iteration limit (default 200) (Section "Bicgstab solver");
+ *   - a solver that may fail without being fatal, so the caller can fall
+ *     back to another solver (Section "Fallback");
+ *   - a check for zeros on the diagonal (runtime breakdown in Section
+ *     "Profiling").
+ *
+ * Conventions for every entry point:
+ *   - Return value: RS_OK (0), a positive non-fatal solver outcome, or a
+ *     negative error.  Nothing is thrown across the ABI; nothing exits.
+ *     rsolve_last_error() gives a text for the last error of the calling
+ *     thread.
+ *   - Pointers marked "mem" live where the `mem` argument says: RS_MEM_HOST
+ *     or RS_MEM_DEVICE (device memory of the current HIP device).  They are
+ *     borrowed for the duration of the call; device sources must stay valid
+ *     until `stream` has passed the call's work.  The library never frees
+ *     caller memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls that
+ *     return a status read from the device (factor, solve) synchronise it.
+ *   - Handles own every device buffer they allocate.  A handle must not be
+ *     used from two host threads at once.
+ *   - Block size is 3; indices are int32; values FP64, block-row-major.
+ *   - Vectors `b`, `x`, `v`, `z`, `y` are in the caller's (original) row
+ *     order; the internal reordering is applied and undone inside the calls.
+ */
+#ifndef RSOLVE_H
+#define RSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rs_bcsr *bcsr_t;
+typedef struct rs_ilu0 *ilu0_t;
+
+enum rs_status {
+    RS_OK = 0,
+    RS_NOT_CONVERGED = 1,   /* iteration limit reached; x holds the last iterate */
+    RS_BREAKDOWN = 2,       /* rho, (rhat,v), (t,t) or omega became zero */
+    RS_INVALID_ARG = -1,
+    RS_UNSUPPORTED_BLOCK_SIZE = -2,
+    RS_BAD_PATTERN = -3,    /* row pointers not monotone, columns unsorted, duplicate or out of range */
+    RS_MISSING_DIAGONAL = -4,
+    RS_ZERO_PIVOT = -5,     /* a diagonal block of U is singular or not finite */
+    RS_NON_FINITE = -6,     /* NaN or Inf reached a reduction */
+    RS_OUT_OF_MEMORY = -7,  /* device allocation failed or a budget was exceeded */
+    RS_HIP_ERROR = -8,
+    RS_PATTERN_MISMATCH = -9, /* an ilu0_t used with a matrix of another pattern */
+    RS_NOT_FACTORED = -10   /* solve or apply before a successful ilu0_factor */
+};
+
+enum rs_ordering { RS_ORDER_NATURAL = 0, RS_ORDER_LEVEL_SET = 1, RS_ORDER_GRAPH_COLOUR = 2 };
+enum rs_precision { RS_PREC_FP64 = 0, RS_PREC_FP32_FACTORS = 1 };
+enum rs_mem { RS_MEM_HOST = 0, RS_MEM_DEVICE = 1 };
+
+/* Per-system outcome of bicgstab_solve. */
+typedef struct {
+    int32_t status;            /* rs_status of this system */
+    int32_t half_steps;        /* 2i-1 when stopping at the half step of iteration i, 2i at its end */
+    double r0_norm;            /* ||b||_2 (x0 = 0) */
+    double final_norm;         /* recursively updated residual norm at the stop */
+    double true_rel_residual;  /* ||b - A x||_2 / ||b||_2 with the caller's A, FP64 */
+} solve_info;
+
+/* bcsr_create -- validate a BCSR pattern and copy pattern and values to the
+ * device.  Section "OPM Flow" (three arrays, contiguous nonzeros that must be
+ * checked) and the zero-diagonal check of Section "Profiling".
+ *   n_brows, nnzb : block rows and stored blocks (n_brows >= 0)
+ *   block_size    : must be 3, else RS_UNSUPPORTED_BLOCK_SIZE
+ *   batch         : number of same-pattern systems (>= 1)
+ *   row_ptr[n+1], col_idx[nnzb] (mem): columns ascending and unique per row,
+ *                   every row has its diagonal block
+ *   vals (mem)    : batch * nnzb * 9 doubles, system-major, may be NULL
+ *                   (values set later with bcsr_set_values)
+ *   out           : receives the handle; bad_row (host, may be NULL)
+ *                   receives the offending row on a pattern error.
+ * Errors: RS_INVALID_ARG, RS_UNSUPPORTED_BLOCK_SIZE, RS_BAD_PATTERN,
+ * RS_MISSING_DIAGONAL, RS_OUT_OF_MEMORY, RS_HIP_ERROR. */
+int bcsr_create(int32_t n_brows, int32_t nnzb, int32_t block_size, int32_t batch, const int32_t *row_ptr,
+                const int32_t *col_idx, const double *vals, int32_t mem, void *stream, bcsr_t *out,
+                int32_t *bad_row);
+
+/* bcsr_set_values -- replace the values of systems [first_sys, first_sys +
+ * n_sys) (vals: n_sys * nnzb * 9 doubles, mem).  The pattern is unchanged,
+ * as between Newton steps.  Stream-ordered; no synchronisation. */
+int bcsr_set_values(bcsr_t A, const double *vals, int32_t first_sys, int32_t n_sys, int32_t mem, void *stream);
+
+/* bcsr_get_dims -- n_brows, nnzb, batch of a handle (host outputs, any may be NULL). */
+int bcsr_get_dims(bcsr_t A, int32_t *n_brows, int32_t *nnzb, int32_t *batch);
+
+/* bcsr_spmv -- y = A x for systems [first_sys, first_sys + n_sys), FP64,
+ * caller order (x, y: n_sys * n_brows * 3 doubles, mem).  Section "Sparse
+ * Matrix-Vector multiplication". */
+int bcsr_spmv(bcsr_t A, const double *x, double *y, int32_t first_sys, int32_t n_sys, int32_t mem, void *stream);
+
+/* bcsr_destroy -- free the handle (NULL is accepted). */
+int bcsr_destroy(bcsr_t A);
+
+/* ilu0_analyse -- host analysis of A's pattern (integer work, once per
+ * pattern): the ordering (RS_ORDER_*), the reordered pattern, lower and
+ * upper sweep schedules and the factor update lists; all copied to the
+ * device.  Section "ILU0" of the implementation chapter. */
+int ilu0_analyse(bcsr_t A, int32_t ordering, ilu0_t *out);
+
+/* ilu0_get_schedule -- perm[new] = old (host, n_brows ints, may be NULL);
+ * *n_sets = number of levels (LS), colours (GC) or lower-sweep levels
+ * (natural order); set_ptr (host, n_sets + 1 ints, may be NULL) = the start
+ * of each level/colour in the new order (LS, GC) or in the lower-sweep
+ * schedule (natural). */
+int ilu0_get_schedule(ilu0_t M, int32_t *perm, int32_t *n_sets, int32_t *set_ptr);
+
+/* ilu0_get_sweep_levels -- number of levels of the lower and upper sweep
+ * schedules the device executes (host outputs, may be NULL). */
+int ilu0_get_sweep_levels(ilu0_t M, int32_t *n_lower, int32_t *n_upper);
+
+/* ilu0_factor -- block ILU0 (Algorithm 2) of every system of A in the
+ * analysed order, levels ascending.  precision RS_PREC_FP64 keeps FP64
+ * factors; RS_PREC_FP32_FACTORS computes them in FP64 and stores them
+ * rounded to FP32 for the sweeps.  bad_row (host, batch ints, may be NULL)
+ * receives, per system, the original index of the first singular pivot
+ * block or -1.  Returns RS_ZERO_PIVOT if any system failed.  Synchronises
+ * `stream`. */
+int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *bad_row);
+
+/* ilu0_get_factors -- copy system `sys`'s factors to host, in the reordered
+ * pattern (rows in new order, columns renumbered and ascending, as P A P^T):
+ * lu (nnzb * 9 doubles) holds L below the diagonal and U on and above it;
+ * dinv (n_brows * 9) holds inv(U_ii) in new row order.  FP32 factors are
+ * returned widened.  Synchronous. */
+int ilu0_get_factors(ilu0_t M, int32_t sys, double *lu, double *dinv);
+
+/* ilu0_apply -- z = U^{-1} L^{-1} v for systems [first_sys, first_sys +
+ * n_sys) in caller order (equations 3-4).  Stream-ordered. */
+int ilu0_apply(ilu0_t M, const double *v, double *z, int32_t first_sys, int32_t n_sys, int32_t mem,
+               void *stream);
+
+/* bicgstab_solve -- preconditioned BiCGStab for every system of A (b, x:
+ * batch * n_brows * 3 doubles, mem) with x0 = 0, stopping when the residual
+ * 2-norm, tested after each half and full step, falls to reduction * ||b||
+ * or after max_iter iterations.  info (host, batch entries, may be NULL)
+ * receives each system's outcome, including the true FP64 residual.
+ * Returns the worst status over the systems (errors first, then
+ * RS_BREAKDOWN, RS_NOT_CONVERGED, RS_OK).  Synchronises `stream`. */
+int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduction, int32_t max_iter,
+                   int32_t mem, void *stream, solve_info *info);
+
+/* ilu0_destroy -- free the handle (NULL is accepted). */
+int ilu0_destroy(ilu0_t M);
+
+/* ilu0_analyse_host -- the host analysis alone, without a device: validates
+ * the pattern and writes perm[new] = old (n ints) and the number of
+ * levels/colours.  Same orderings as ilu0_analyse. */
+int ilu0_analyse_host(int32_t n_brows, const int32_t *row_ptr, const int32_t *col_idx, int32_t ordering,
+                      int32_t *perm, int32_t *n_sets, int32_t *bad_row);
+
+const char *rsolve_status_string(int status);
+const char *rsolve_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

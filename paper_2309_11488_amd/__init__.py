@@ -1,0 +1,308 @@
+"""Python binding of librsolve.so: BCSR (3x3 FP64 blocks) BiCGStab with block-ILU0 on MI355X.
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+The functions carry the C names (``bcsr_create``, ``ilu0_analyse``,
+``ilu0_factor``, ``bicgstab_solve`` ...).  Arrays may be NumPy arrays (host
+memory) or torch CUDA tensors (device memory; PyTorch supplies memory and the
+current stream only).  There is no CPU fallback: when the library is missing
+the import of a function fails loudly.
+"""
+
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librsolve.so")
+
+OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
+INVALID_ARG, UNSUPPORTED_BLOCK_SIZE, BAD_PATTERN, MISSING_DIAGONAL = -1, -2, -3, -4
+ZERO_PIVOT, NON_FINITE, OUT_OF_MEMORY, HIP_ERROR, PATTERN_MISMATCH, NOT_FACTORED = -5, -6, -7, -8, -9, -10
+ORDER_NATURAL, ORDER_LEVEL_SET, ORDER_GRAPH_COLOUR = 0, 1, 2
+PREC_FP64, PREC_FP32_FACTORS = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+
+EXPORTS = (
+    "bcsr_create", "bcsr_set_values", "bcsr_get_dims", "bcsr_spmv", "bcsr_destroy", "ilu0_analyse",
+    "ilu0_get_schedule", "ilu0_get_sweep_levels", "ilu0_factor", "ilu0_get_factors", "ilu0_apply",
+    "bicgstab_solve", "ilu0_destroy", "ilu0_analyse_host", "rsolve_status_string", "rsolve_last_error",
+)
+
+
+class SolveInfo(ct.Structure):
+    _fields_ = [("status", ct.c_int32), ("half_steps", ct.c_int32), ("r0_norm", ct.c_double),
+                ("final_norm", ct.c_double), ("true_rel_residual", ct.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class RsolveError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = lib().rsolve_last_error().decode()
+        super().__init__(f"{where}: {status_string(status)} ({status}): {msg}")
+
+
+_lib = None
+
+
+def lib():
+    """Load librsolve.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        # torch ships its own HIP runtime; loading it first makes librsolve.so
+        # bind to that same runtime (by soname), so one HIP runtime serves
+        # the process and torch's streams and pointers are valid here
+        try:
+            import torch  # noqa: F401
+        except ImportError:  # pragma: no cover - host-only callers
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ct.CDLL(LIB_PATH)
+        i32, vp, dbl = ct.c_int32, ct.c_void_p, ct.c_double
+        P = ct.POINTER
+        L.bcsr_create.argtypes = [i32, i32, i32, i32, vp, vp, vp, i32, vp, P(vp), P(i32)]
+        L.bcsr_set_values.argtypes = [vp, vp, i32, i32, i32, vp]
+        L.bcsr_get_dims.argtypes = [vp, P(i32), P(i32), P(i32)]
+        L.bcsr_spmv.argtypes = [vp, vp, vp, i32, i32, i32, vp]
+        L.bcsr_destroy.argtypes = [vp]
+        L.ilu0_analyse.argtypes = [vp, i32, P(vp)]
+        L.ilu0_get_schedule.argtypes = [vp, vp, P(i32), vp]
+        L.ilu0_get_sweep_levels.argtypes = [vp, P(i32), P(i32)]
+        L.ilu0_factor.argtypes = [vp, vp, i32, vp, vp]
+        L.ilu0_get_factors.argtypes = [vp, i32, vp, vp]
+        L.ilu0_apply.argtypes = [vp, vp, vp, i32, i32, i32, vp]
+        L.bicgstab_solve.argtypes = [vp, vp, vp, vp, dbl, i32, i32, vp, vp]
+        L.ilu0_destroy.argtypes = [vp]
+        L.ilu0_analyse_host.argtypes = [i32, vp, vp, i32, vp, P(i32), P(i32)]
+        L.rsolve_status_string.argtypes = [ct.c_int]
+        L.rsolve_status_string.restype = ct.c_char_p
+        L.rsolve_last_error.restype = ct.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().rsolve_status_string(int(status)).decode()
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _mem_ptr(*arrays):
+    """(mem, [pointers]) for arrays that are all host NumPy or all CUDA torch tensors."""
+    kinds = {_is_torch(a) for a in arrays if a is not None}
+    if len(kinds) > 1:
+        raise TypeError("mix of host and device arrays")
+    if kinds == {True}:
+        for a in arrays:
+            if a is not None and (not a.is_cuda or not a.is_contiguous()):
+                raise TypeError("torch tensors must be contiguous CUDA tensors")
+        return MEM_DEVICE, [a.data_ptr() if a is not None else None for a in arrays]
+    ptrs = []
+    for a in arrays:
+        if a is None:
+            ptrs.append(None)
+        else:
+            if not a.flags["C_CONTIGUOUS"]:
+                raise TypeError("NumPy arrays must be C-contiguous")
+            ptrs.append(a.ctypes.data)
+    return MEM_HOST, ptrs
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:  # pragma: no cover - torch is optional for host callers
+        pass
+    return None
+
+
+def _check(st, where, ok=(OK,)):
+    if st not in ok:
+        raise RsolveError(st, where)
+    return st
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# --------------------------------------------------------------- C names
+
+def bcsr_create(rowptr, colidx, vals=None, *, batch=None, stream=None):
+    """Create a BCSR handle.  vals: (batch, nnzb, 3, 3) or (nnzb, 3, 3) FP64."""
+    if not _is_torch(rowptr):
+        rowptr, colidx = _host(rowptr, np.int32), _host(colidx, np.int32)
+    n = len(rowptr) - 1
+    nnzb = len(colidx)
+    if vals is not None:
+        if not _is_torch(vals):
+            vals = _host(vals, np.float64)
+        if batch is None:
+            batch = 1 if vals.ndim == 3 else int(vals.shape[0])
+    batch = 1 if batch is None else batch
+    mem, (rp, ci) = _mem_ptr(rowptr, colidx)
+    vmem, (vp,) = _mem_ptr(vals)
+    if vals is not None and vmem != mem:
+        raise TypeError("pattern and values must live in the same memory")
+    h = ct.c_void_p()
+    bad = ct.c_int32(-1)
+    st = lib().bcsr_create(n, nnzb, 3, batch, rp, ci, vp, mem, _stream(stream), ct.byref(h), ct.byref(bad))
+    if st != OK:
+        err = RsolveError(st, "bcsr_create")
+        err.bad_row = bad.value
+        raise err
+    return h
+
+
+def bcsr_set_values(A, vals, first_sys=0, n_sys=None, *, stream=None):
+    if not _is_torch(vals):
+        vals = _host(vals, np.float64)
+    if n_sys is None:
+        n_sys = 1 if vals.ndim == 3 else int(vals.shape[0])
+    mem, (vp,) = _mem_ptr(vals)
+    return _check(lib().bcsr_set_values(A, vp, first_sys, n_sys, mem, _stream(stream)), "bcsr_set_values")
+
+
+def bcsr_get_dims(A):
+    n, nnzb, b = ct.c_int32(), ct.c_int32(), ct.c_int32()
+    _check(lib().bcsr_get_dims(A, ct.byref(n), ct.byref(nnzb), ct.byref(b)), "bcsr_get_dims")
+    return n.value, nnzb.value, b.value
+
+
+def bcsr_spmv(A, x, y=None, first_sys=0, n_sys=None, *, stream=None):
+    n, _, batch = bcsr_get_dims(A)
+    if n_sys is None:
+        n_sys = batch - first_sys
+    if not _is_torch(x):
+        x = _host(x, np.float64)
+        if y is None:
+            y = np.zeros((n_sys, n, 3))
+    mem, (xp, yp) = _mem_ptr(x, y)
+    _check(lib().bcsr_spmv(A, xp, yp, first_sys, n_sys, mem, _stream(stream)), "bcsr_spmv")
+    return y
+
+
+def bcsr_destroy(A):
+    if A:
+        lib().bcsr_destroy(A)
+
+
+def ilu0_analyse(A, ordering=ORDER_LEVEL_SET):
+    h = ct.c_void_p()
+    _check(lib().ilu0_analyse(A, ordering, ct.byref(h)), "ilu0_analyse")
+    return h
+
+
+def ilu0_get_schedule(M, n):
+    perm = np.zeros(max(n, 1), np.int32)
+    ns = ct.c_int32()
+    _check(lib().ilu0_get_schedule(M, perm.ctypes.data, ct.byref(ns), None), "ilu0_get_schedule")
+    sp = np.zeros(ns.value + 1, np.int32)
+    lib().ilu0_get_schedule(M, None, ct.byref(ns), sp.ctypes.data)
+    return perm[:n], ns.value, sp
+
+
+def ilu0_get_sweep_levels(M):
+    a, b = ct.c_int32(), ct.c_int32()
+    _check(lib().ilu0_get_sweep_levels(M, ct.byref(a), ct.byref(b)), "ilu0_get_sweep_levels")
+    return a.value, b.value
+
+
+def ilu0_factor(M, A, precision=PREC_FP64, *, stream=None):
+    """Factor every system; returns (status, bad_row per system)."""
+    _, _, batch = bcsr_get_dims(A)
+    bad = np.full(batch, -1, np.int32)
+    st = lib().ilu0_factor(M, A, precision, _stream(stream), bad.ctypes.data)
+    _check(st, "ilu0_factor", ok=(OK, ZERO_PIVOT))
+    return st, bad
+
+
+def ilu0_get_factors(M, sys, n, nnzb):
+    lu = np.zeros((max(nnzb, 1), 3, 3))
+    dinv = np.zeros((max(n, 1), 3, 3))
+    _check(lib().ilu0_get_factors(M, sys, lu.ctypes.data, dinv.ctypes.data), "ilu0_get_factors")
+    return lu[:nnzb], dinv[:n]
+
+
+def ilu0_apply(M, v, z=None, first_sys=0, n_sys=1, *, stream=None):
+    if not _is_torch(v):
+        v = _host(v, np.float64)
+        if z is None:
+            z = np.zeros_like(v)
+    mem, (vp, zp) = _mem_ptr(v, z)
+    _check(lib().ilu0_apply(M, vp, zp, first_sys, n_sys, mem, _stream(stream)), "ilu0_apply")
+    return z
+
+
+def bicgstab_solve(M, A, b, x=None, reduction=1e-2, max_iter=200, *, stream=None):
+    """Solve every system of A.  Returns (x, status, [info dict per system])."""
+    _, _, batch = bcsr_get_dims(A)
+    if not _is_torch(b):
+        b = _host(b, np.float64)
+        if x is None:
+            x = np.zeros_like(b)
+    mem, (bp, xp) = _mem_ptr(b, x)
+    info = (SolveInfo * batch)()
+    st = lib().bicgstab_solve(M, A, bp, xp, float(reduction), int(max_iter), mem, _stream(stream), info)
+    _check(st, "bicgstab_solve", ok=(OK, NOT_CONVERGED, BREAKDOWN, NON_FINITE, ZERO_PIVOT))
+    return x, st, [i.as_dict() for i in info]
+
+
+def ilu0_destroy(M):
+    if M:
+        lib().ilu0_destroy(M)
+
+
+def ilu0_analyse_host(rowptr, colidx, ordering=ORDER_LEVEL_SET):
+    """Host-only analysis: (status, perm, n_sets, bad_row); needs no GPU."""
+    rowptr, colidx = _host(rowptr, np.int32), _host(colidx, np.int32)
+    n = len(rowptr) - 1
+    perm = np.zeros(max(n, 1), np.int32)
+    ns, bad = ct.c_int32(), ct.c_int32()
+    st = lib().ilu0_analyse_host(n, rowptr.ctypes.data, colidx.ctypes.data, ordering, perm.ctypes.data,
+                                 ct.byref(ns), ct.byref(bad))
+    return st, perm[:n], ns.value, bad.value
+
+
+# ------------------------------------------------------------ convenience
+
+class Solver:
+    """Owns a matrix handle and its ILU0 handle: create -> analyse -> factor -> solve."""
+
+    def __init__(self, rowptr, colidx, vals, *, ordering=ORDER_LEVEL_SET, precision=PREC_FP64, stream=None):
+        self.A = bcsr_create(rowptr, colidx, vals, stream=stream)
+        self.n, self.nnzb, self.batch = bcsr_get_dims(self.A)
+        self.M = ilu0_analyse(self.A, ordering)
+        self.precision = precision
+        self.stream = stream
+
+    def factor(self, vals=None):
+        if vals is not None:
+            bcsr_set_values(self.A, vals, stream=self.stream)
+        return ilu0_factor(self.M, self.A, self.precision, stream=self.stream)
+
+    def solve(self, b, x=None, reduction=1e-2, max_iter=200):
+        return bicgstab_solve(self.M, self.A, b, x, reduction, max_iter, stream=self.stream)
+
+    def close(self):
+        ilu0_destroy(self.M)
+        bcsr_destroy(self.A)
+        self.M = self.A = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,226 @@
+// Host analysis of a BCSR pattern: validation, orderings (natural, level
+// scheduling, greedy graph colouring), the reordered pattern, lower/upper
+// sweep schedules and the ILU0 update lists.
+//
+// Orderings follow Section "ILU0" of the paper's implementation chapter:
+// level scheduling respects direct and indirect dependencies; graph colouring
+// only separates rows that are directly coupled, so more rows run together;
+// the natural order is the sequential reference.  A reordered copy of the
+// matrix is made with each level/colour contiguous.
+#include "analysis.h"
+
+#include <algorithm>
+
+#include "../../include/rsolve.h"
+
+namespace rs {
+
+int validate_pattern(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx, int *bad_row) {
+    *bad_row = -1;
+    if (rowptr[0] != 0 || rowptr[n] != nnzb) return RS_BAD_PATTERN;
+    for (int i = 0; i < n; ++i) {
+        const int a = rowptr[i], b = rowptr[i + 1];
+        if (b < a || b > nnzb) { *bad_row = i; return RS_BAD_PATTERN; }
+        bool diag = false;
+        for (int p = a; p < b; ++p) {
+            const int j = colidx[p];
+            if (j < 0 || j >= n || (p > a && colidx[p - 1] >= j)) { *bad_row = i; return RS_BAD_PATTERN; }
+            diag |= (j == i);
+        }
+        if (!diag) { *bad_row = i; return RS_MISSING_DIAGONAL; }
+    }
+    return RS_OK;
+}
+
+// Stable grouping of rows by an integer key in [0, nkeys): order[pos] = row,
+// start[k] = first position of key k.
+static void group_by_key(const std::vector<int32_t> &key, int nkeys, std::vector<int32_t> &order,
+                         std::vector<int32_t> &start) {
+    const int n = (int)key.size();
+    start.assign(nkeys + 1, 0);
+    for (int i = 0; i < n; ++i) start[key[i] + 1]++;
+    for (int k = 0; k < nkeys; ++k) start[k + 1] += start[k];
+    std::vector<int32_t> next(start.begin(), start.end() - 1);
+    order.resize(n);
+    for (int i = 0; i < n; ++i) order[next[key[i]]++] = i;
+}
+
+// Longest-path depth through lower (j < i) or upper (j > i) neighbours.
+static int depth_lower(int n, const int32_t *rowptr, const int32_t *colidx, std::vector<int32_t> &d) {
+    d.assign(n, 0);
+    int depth = n > 0 ? 1 : 0;
+    for (int i = 0; i < n; ++i) {
+        int v = 0;
+        for (int p = rowptr[i]; p < rowptr[i + 1] && colidx[p] < i; ++p) v = std::max(v, d[colidx[p]] + 1);
+        d[i] = v;
+        depth = std::max(depth, v + 1);
+    }
+    return depth;
+}
+
+static int depth_upper(int n, const int32_t *rowptr, const int32_t *colidx, std::vector<int32_t> &d) {
+    d.assign(n, 0);
+    int depth = n > 0 ? 1 : 0;
+    for (int i = n - 1; i >= 0; --i) {
+        int v = 0;
+        for (int p = rowptr[i + 1] - 1; p >= rowptr[i] && colidx[p] > i; --p) v = std::max(v, d[colidx[p]] + 1);
+        d[i] = v;
+        depth = std::max(depth, v + 1);
+    }
+    return depth;
+}
+
+// Greedy first-fit colouring in natural order; two rows conflict when either
+// holds the other in its pattern.
+static int greedy_colour(int n, const int32_t *rowptr, const int32_t *colidx, std::vector<int32_t> &colour) {
+    const int nnz = rowptr[n];
+    std::vector<int32_t> tptr(n + 1, 0), tcol(std::max(nnz, 1));
+    for (int p = 0; p < nnz; ++p) tptr[colidx[p] + 1]++;
+    for (int i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
+    {
+        std::vector<int32_t> pos(tptr.begin(), tptr.end() - 1);
+        for (int i = 0; i < n; ++i)
+            for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) tcol[pos[colidx[p]]++] = i;
+    }
+    colour.assign(n, -1);
+    std::vector<int32_t> seen(n + 2, -1);
+    int ncol = 0;
+    for (int i = 0; i < n; ++i) {
+        auto mark = [&](int j) { if (j != i && colour[j] >= 0) seen[colour[j]] = i; };
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) mark(colidx[p]);
+        for (int p = tptr[i]; p < tptr[i + 1]; ++p) mark(tcol[p]);
+        int c = 0;
+        while (seen[c] == i) ++c;
+        colour[i] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    return ncol;
+}
+
+int make_ordering(int n, const int32_t *rowptr, const int32_t *colidx, int ordering, std::vector<int32_t> &perm,
+                  std::vector<int32_t> &set_ptr) {
+    std::vector<int32_t> key;
+    int nsets;
+    if (ordering == RS_ORDER_LEVEL_SET) {
+        nsets = depth_lower(n, rowptr, colidx, key);
+    } else if (ordering == RS_ORDER_GRAPH_COLOUR) {
+        nsets = greedy_colour(n, rowptr, colidx, key);
+    } else {
+        perm.resize(n);
+        set_ptr.resize(n + 1);
+        for (int i = 0; i < n; ++i) perm[i] = i;
+        for (int i = 0; i <= n; ++i) set_ptr[i] = i;
+        return n;
+    }
+    group_by_key(key, nsets, perm, set_ptr);
+    return nsets;
+}
+
+int make_ordering(int n, const int32_t *rowptr, const int32_t *colidx, int ordering, std::vector<int32_t> &perm) {
+    std::vector<int32_t> sp;
+    return make_ordering(n, rowptr, colidx, ordering, perm, sp);
+}
+
+int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx, int ordering, Schedule &s) {
+    s = Schedule();
+    s.n = n;
+    s.nnzb = nnzb;
+    s.ordering = ordering;
+    s.n_sets = make_ordering(n, rowptr, colidx, ordering, s.perm, s.set_ptr);
+    s.iperm.assign(n, 0);
+    for (int i = 0; i < n; ++i) s.iperm[s.perm[i]] = i;
+
+    // reordered pattern A' = P A P^T, columns ascending in the new numbering
+    s.prow.assign(n + 1, 0);
+    s.pcol.resize(nnzb);
+    s.psrc.resize(nnzb);
+    std::vector<std::pair<int32_t, int32_t>> row;
+    for (int i = 0; i < n; ++i) {
+        const int old = s.perm[i];
+        row.clear();
+        for (int p = rowptr[old]; p < rowptr[old + 1]; ++p) row.emplace_back(s.iperm[colidx[p]], p);
+        std::sort(row.begin(), row.end());
+        const int base = s.prow[i];
+        for (size_t q = 0; q < row.size(); ++q) {
+            s.pcol[base + q] = row[q].first;
+            s.psrc[base + q] = row[q].second;
+        }
+        s.prow[i + 1] = base + (int)row.size();
+    }
+    const int32_t *prow = s.prow.data(), *pcol = s.pcol.data();
+
+    // sweep schedules on the reordered pattern
+    std::vector<int32_t> ldep, udep;
+    s.nl_levels = depth_lower(n, prow, pcol, ldep);
+    s.nu_levels = depth_upper(n, prow, pcol, udep);
+    group_by_key(ldep, s.nl_levels, s.lrows, s.lset);
+    group_by_key(udep, s.nu_levels, s.urows, s.uset);
+    std::vector<int32_t> upos(n);
+    for (int q = 0; q < n; ++q) upos[s.urows[q]] = q;
+
+    std::vector<int32_t> a2l(nnzb, -1), a2u(nnzb, -1), pdiag(n, -1);
+    s.lptr.assign(n + 1, 0);
+    s.l2u.resize(n);
+    for (int q = 0; q < n; ++q) {
+        const int i = s.lrows[q];
+        int cnt = 0;
+        for (int p = prow[i]; p < prow[i + 1]; ++p) {
+            if (pcol[p] == i) pdiag[i] = p;
+            if (pcol[p] >= i) continue;
+            a2l[p] = (int)s.lcol.size();
+            s.lcol.push_back(pcol[p]);
+            s.lsrc.push_back(p);
+            s.ldq.push_back(upos[pcol[p]]);
+            ++cnt;
+        }
+        s.lptr[q + 1] = s.lptr[q] + cnt;
+        s.l2u[q] = upos[i];
+        s.max_lrow = std::max(s.max_lrow, cnt);
+    }
+    s.uptr.assign(n + 1, 0);
+    s.dsrc.resize(n);
+    for (int q = 0; q < n; ++q) {
+        const int i = s.urows[q];
+        int cnt = 0;
+        for (int p = prow[i]; p < prow[i + 1]; ++p) {
+            if (pcol[p] <= i) continue;
+            a2u[p] = (int)s.ucol.size();
+            s.ucol.push_back(pcol[p]);
+            s.usrc.push_back(p);
+            ++cnt;
+        }
+        s.uptr[q + 1] = s.uptr[q] + cnt;
+        s.dsrc[q] = pdiag[i];
+        s.max_urow = std::max(s.max_urow, cnt);
+    }
+    s.nL = (int)s.lcol.size();
+    s.nU = (int)s.ucol.size();
+
+    // update lists: for L block (i,k), every j > k in row k that row i also
+    // holds, ascending j, in the order Algorithm 2 applies them
+    s.upd_ptr.assign(s.nL + 1, 0);
+    for (int q = 0; q < n; ++q) {
+        const int i = s.lrows[q];
+        for (int e = s.lptr[q]; e < s.lptr[q + 1]; ++e) {
+            const int k = s.lcol[e];
+            const int32_t *ib = pcol + prow[i], *ie = pcol + prow[i + 1];
+            for (int p = prow[k]; p < prow[k + 1]; ++p) {
+                const int j = pcol[p];
+                if (j <= k) continue;
+                const int32_t *hit = std::lower_bound(ib, ie, j);
+                if (hit == ie || *hit != j) continue;  // fill outside the pattern is dropped
+                const int t = prow[i] + (int)(hit - ib);
+                int code;
+                if (j < i) code = 4 * a2l[t] + 0;
+                else if (j == i) code = 1;
+                else code = 4 * a2u[t] + 2;
+                s.upd.push_back(code);
+                s.upd.push_back(a2u[p]);
+            }
+            s.upd_ptr[e + 1] = (int32_t)(s.upd.size() / 2);
+        }
+    }
+    return RS_OK;
+}
+
+}  // namespace rs

@@ -1,0 +1,52 @@
+// Host-side pattern analysis: validation, orderings, sweep schedules and the
+// factor update lists.  Integer work only, done once per pattern.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace rs {
+
+// Pattern check: row pointers start at 0 and never decrease, columns in
+// range, strictly ascending per row, diagonal present.  Returns 0,
+// RS_BAD_PATTERN or RS_MISSING_DIAGONAL; *bad_row names the row.
+int validate_pattern(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx, int *bad_row);
+
+// perm[new] = old for the three orderings, and set_ptr = the first new
+// position of each level/colour.  Returns the number of levels (level sets),
+// colours (graph colouring) or n (natural order: one row per set).
+int make_ordering(int n, const int32_t *rowptr, const int32_t *colidx, int ordering, std::vector<int32_t> &perm,
+                  std::vector<int32_t> &set_ptr);
+int make_ordering(int n, const int32_t *rowptr, const int32_t *colidx, int ordering, std::vector<int32_t> &perm);
+
+// Everything the device needs to factor, sweep and multiply in the new order.
+//
+// A' = P A P^T is kept in CSR (prow, pcol) with psrc[p] = the caller's block
+// position of A'[p].  The lower sweep visits rows in "L-schedule" order
+// (levels ascending, new index ascending inside a level); the upper sweep in
+// "U-schedule" order (upper levels ascending).  L blocks are stored in
+// L-schedule order, U blocks and inv(U_ii) in U-schedule order, so each level
+// is one contiguous range of rows and blocks.
+struct Schedule {
+    int n = 0, nnzb = 0, ordering = 0;
+    int n_sets = 0;                 // levels / colours reported to the caller
+    std::vector<int32_t> set_ptr;   // n_sets + 1
+    std::vector<int32_t> perm, iperm;
+    // reordered matrix
+    std::vector<int32_t> prow, pcol, psrc;
+    // lower sweep
+    int nl_levels = 0, nL = 0;
+    std::vector<int32_t> lrows, lset, lptr, lcol, lsrc, ldq, l2u;
+    // upper sweep
+    int nu_levels = 0, nU = 0;
+    std::vector<int32_t> urows, uset, uptr, ucol, usrc, dsrc;
+    // factor: for each L block e, updates upd[upd_ptr[e] .. upd_ptr[e+1])
+    // as pairs (target code, U block position of U_kj); target code =
+    // 4 * position + kind, kind 0 = L block, 1 = diagonal of the row, 2 = U block.
+    std::vector<int32_t> upd_ptr, upd;
+    int max_lrow = 0, max_urow = 0;
+};
+
+int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx, int ordering, Schedule &s);
+
+}  // namespace rs

@@ -1,0 +1,560 @@
+// C ABI of the BCSR BiCGStab-ILU0 library: handles, validation, device
+// buffers and the host side of the solve (kernel sequencing and the
+// convergence poll).  All arithmetic of the path runs in kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rsolve.h"
+#include "analysis.h"
+#include "kernels.h"
+
+using rs::DevSchedule;
+using rs::Krylov;
+using rs::SysState;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(e_ == hipErrorOutOfMemory ? RS_OUT_OF_MEMORY : RS_HIP_ERROR,               \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                        \
+    } while (0)
+
+uint64_t fnv(const void *p, size_t bytes, uint64_t h = 1469598103934665603ull) {
+    const unsigned char *c = (const unsigned char *)p;
+    for (size_t i = 0; i < bytes; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    return h;
+}
+
+// Device allocation owned by a handle.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    hipError_t alloc(size_t b) {
+        if (p && bytes >= b) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (b == 0) b = 16;
+        hipError_t e = hipMalloc(&p, b);
+        if (e == hipSuccess) bytes = b;
+        return e;
+    }
+    template <typename T> T *as() const { return (T *)p; }
+};
+
+hipError_t upload(DevBuf &buf, const std::vector<int32_t> &v) {
+    hipError_t e = buf.alloc(v.size() * sizeof(int32_t));
+    if (e != hipSuccess || v.empty()) return e;
+    return hipMemcpy(buf.p, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+struct rs_bcsr {
+    int n = 0, nnzb = 0, batch = 1;
+    uint64_t hash = 0;
+    std::vector<int32_t> h_rowptr, h_colidx;
+    DevBuf rowptr, colidx, vals;
+};
+
+struct rs_ilu0 {
+    int n = 0, nnzb = 0, batch = 1;
+    uint64_t hash = 0;
+    rs::Schedule sch;
+    DevSchedule dev{};
+    DevBuf perm, prow, pcol, psrc, lrows, lptr, lcol, lsrc, ldq, l2u, upd_ptr, upd, urows, uptr, ucol, usrc, dsrc;
+    // factors
+    int precision = -1;
+    bool factored = false;
+    DevBuf pvals, L, U, Dinv, Lf, Uf, Dinvf, bad;
+    std::vector<int32_t> bad_host;
+    // solve workspace
+    DevBuf work, ywork, part, state, bstage, xstage;
+    Krylov k{};
+    SysState *h_state = nullptr;
+    int chunk = 1;
+    ~rs_ilu0() { if (h_state) (void)hipHostFree(h_state); }
+};
+
+static int read_pattern(int32_t n, int32_t nnzb, const int32_t *row_ptr, const int32_t *col_idx, int32_t mem,
+                        std::vector<int32_t> &rp, std::vector<int32_t> &ci) {
+    rp.resize((size_t)n + 1);
+    ci.resize((size_t)nnzb);
+    if (mem == RS_MEM_DEVICE) {
+        HIP_TRY(hipMemcpy(rp.data(), row_ptr, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (nnzb) HIP_TRY(hipMemcpy(ci.data(), col_idx, ci.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(rp.data(), row_ptr, rp.size() * sizeof(int32_t));
+        if (nnzb) std::memcpy(ci.data(), col_idx, ci.size() * sizeof(int32_t));
+    }
+    return RS_OK;
+}
+
+extern "C" {
+
+const char *rsolve_last_error(void) { return g_err.c_str(); }
+
+const char *rsolve_status_string(int status) {
+    switch (status) {
+    case RS_OK: return "ok";
+    case RS_NOT_CONVERGED: return "not converged";
+    case RS_BREAKDOWN: return "breakdown";
+    case RS_INVALID_ARG: return "invalid argument";
+    case RS_UNSUPPORTED_BLOCK_SIZE: return "unsupported block size";
+    case RS_BAD_PATTERN: return "bad pattern";
+    case RS_MISSING_DIAGONAL: return "missing diagonal block";
+    case RS_ZERO_PIVOT: return "zero pivot";
+    case RS_NON_FINITE: return "non-finite value";
+    case RS_OUT_OF_MEMORY: return "out of memory";
+    case RS_HIP_ERROR: return "HIP error";
+    case RS_PATTERN_MISMATCH: return "pattern mismatch";
+    case RS_NOT_FACTORED: return "not factored";
+    default: return "unknown status";
+    }
+}
+
+int ilu0_analyse_host(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t ordering, int32_t *perm,
+                      int32_t *n_sets, int32_t *bad_row) {
+    if (bad_row) *bad_row = -1;
+    if (n < 0 || !row_ptr || (n > 0 && !col_idx) || ordering < 0 || ordering > 2)
+        return fail(RS_INVALID_ARG, "ilu0_analyse_host: bad arguments");
+    int bad = -1;
+    const int nnzb = row_ptr[n];
+    if (nnzb < 0) return fail(RS_BAD_PATTERN, "ilu0_analyse_host: negative nnzb");
+    int st = rs::validate_pattern(n, nnzb, row_ptr, col_idx, &bad);
+    if (bad_row) *bad_row = bad;
+    if (st != RS_OK) return fail(st, "ilu0_analyse_host: invalid pattern");
+    std::vector<int32_t> p, sp;
+    const int ns = rs::make_ordering(n, row_ptr, col_idx, ordering, p, sp);
+    if (perm && n) std::memcpy(perm, p.data(), sizeof(int32_t) * (size_t)n);
+    if (n_sets) *n_sets = ns;
+    return RS_OK;
+}
+
+int bcsr_create(int32_t n_brows, int32_t nnzb, int32_t block_size, int32_t batch, const int32_t *row_ptr,
+                const int32_t *col_idx, const double *vals, int32_t mem, void *stream, bcsr_t *out,
+                int32_t *bad_row) {
+    if (bad_row) *bad_row = -1;
+    if (!out) return fail(RS_INVALID_ARG, "bcsr_create: out is NULL");
+    *out = nullptr;
+    if (block_size != 3) return fail(RS_UNSUPPORTED_BLOCK_SIZE, "bcsr_create: block size must be 3");
+    if (n_brows < 0 || nnzb < 0 || batch < 1 || !row_ptr || (nnzb > 0 && !col_idx) ||
+        (mem != RS_MEM_HOST && mem != RS_MEM_DEVICE))
+        return fail(RS_INVALID_ARG, "bcsr_create: bad arguments");
+    if ((size_t)nnzb * 9 * (size_t)batch > (size_t)1 << 40) return fail(RS_INVALID_ARG, "bcsr_create: too large");
+    rs_bcsr *A = new rs_bcsr();
+    A->n = n_brows;
+    A->nnzb = nnzb;
+    A->batch = batch;
+    int st = read_pattern(n_brows, nnzb, row_ptr, col_idx, mem, A->h_rowptr, A->h_colidx);
+    if (st != RS_OK) { delete A; return st; }
+    int bad = -1;
+    st = rs::validate_pattern(n_brows, nnzb, A->h_rowptr.data(), A->h_colidx.data(), &bad);
+    if (st != RS_OK) {
+        if (bad_row) *bad_row = bad;
+        delete A;
+        return fail(st, "bcsr_create: invalid pattern at row " + std::to_string(bad));
+    }
+    A->hash = fnv(A->h_colidx.data(), A->h_colidx.size() * 4, fnv(A->h_rowptr.data(), A->h_rowptr.size() * 4));
+    hipError_t e;
+    if ((e = upload(A->rowptr, A->h_rowptr)) != hipSuccess || (e = upload(A->colidx, A->h_colidx)) != hipSuccess ||
+        (e = A->vals.alloc((size_t)nnzb * 9 * batch * sizeof(double))) != hipSuccess) {
+        delete A;
+        return fail(e == hipErrorOutOfMemory ? RS_OUT_OF_MEMORY : RS_HIP_ERROR,
+                    std::string("bcsr_create: ") + hipGetErrorString(e));
+    }
+    *out = A;
+    if (vals) {
+        st = bcsr_set_values(A, vals, 0, batch, mem, stream);
+        if (st != RS_OK) {
+            delete A;
+            *out = nullptr;
+            return st;
+        }
+    }
+    return RS_OK;
+}
+
+int bcsr_set_values(bcsr_t A, const double *vals, int32_t first_sys, int32_t n_sys, int32_t mem, void *stream) {
+    if (!A || !vals || first_sys < 0 || n_sys < 0 || first_sys + n_sys > A->batch)
+        return fail(RS_INVALID_ARG, "bcsr_set_values: bad arguments");
+    const size_t per = (size_t)A->nnzb * 9;
+    if (n_sys == 0 || per == 0) return RS_OK;
+    HIP_TRY(hipMemcpyAsync(A->vals.as<double>() + per * first_sys, vals, per * n_sys * sizeof(double),
+                           mem == RS_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           (hipStream_t)stream));
+    if (mem != RS_MEM_DEVICE) HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    return RS_OK;
+}
+
+int bcsr_get_dims(bcsr_t A, int32_t *n_brows, int32_t *nnzb, int32_t *batch) {
+    if (!A) return fail(RS_INVALID_ARG, "bcsr_get_dims: NULL handle");
+    if (n_brows) *n_brows = A->n;
+    if (nnzb) *nnzb = A->nnzb;
+    if (batch) *batch = A->batch;
+    return RS_OK;
+}
+
+int bcsr_destroy(bcsr_t A) {
+    delete A;
+    return RS_OK;
+}
+
+// Stage a caller vector set (nsys systems of 3n doubles) on the device.
+static int stage_in(const double *src, int32_t mem, DevBuf &buf, size_t count, hipStream_t s, const double **dev) {
+    if (mem == RS_MEM_DEVICE) {
+        *dev = src;
+        return RS_OK;
+    }
+    HIP_TRY(buf.alloc(std::max<size_t>(count, 1) * sizeof(double)));
+    if (count) HIP_TRY(hipMemcpyAsync(buf.p, src, count * sizeof(double), hipMemcpyHostToDevice, s));
+    *dev = buf.as<double>();
+    return RS_OK;
+}
+
+int bcsr_spmv(bcsr_t A, const double *x, double *y, int32_t first_sys, int32_t n_sys, int32_t mem, void *stream) {
+    if (!A || !x || !y || first_sys < 0 || n_sys < 0 || first_sys + n_sys > A->batch)
+        return fail(RS_INVALID_ARG, "bcsr_spmv: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t m = 3 * (size_t)A->n * n_sys;
+    DevBuf xb, yb;
+    const double *xd = nullptr;
+    int st = stage_in(x, mem, xb, m, s, &xd);
+    if (st != RS_OK) return st;
+    double *yd = y;
+    if (mem != RS_MEM_DEVICE) {
+        HIP_TRY(yb.alloc(std::max<size_t>(m, 1) * sizeof(double)));
+        yd = yb.as<double>();
+    }
+    const size_t per = (size_t)A->nnzb * 9;
+    rs::launch_spmv(A->n, A->rowptr.as<int32_t>(), A->colidx.as<int32_t>(), A->vals.as<double>() + per * first_sys,
+                    per, xd, yd, 3 * (size_t)A->n, n_sys, s);
+    HIP_TRY(hipGetLastError());
+    if (mem != RS_MEM_DEVICE) {
+        if (m) HIP_TRY(hipMemcpyAsync(y, yd, m * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    return RS_OK;
+}
+
+int ilu0_analyse(bcsr_t A, int32_t ordering, ilu0_t *out) {
+    if (!A || !out || ordering < 0 || ordering > 2) return fail(RS_INVALID_ARG, "ilu0_analyse: bad arguments");
+    *out = nullptr;
+    rs_ilu0 *M = new rs_ilu0();
+    M->n = A->n;
+    M->nnzb = A->nnzb;
+    M->batch = A->batch;
+    M->hash = A->hash;
+    rs::build_schedule(A->n, A->nnzb, A->h_rowptr.data(), A->h_colidx.data(), ordering, M->sch);
+    const rs::Schedule &S = M->sch;
+    hipError_t e = hipSuccess;
+    struct Up { DevBuf *b; const std::vector<int32_t> *v; } ups[] = {
+        {&M->perm, &S.perm}, {&M->prow, &S.prow}, {&M->pcol, &S.pcol}, {&M->psrc, &S.psrc},
+        {&M->lrows, &S.lrows}, {&M->lptr, &S.lptr}, {&M->lcol, &S.lcol}, {&M->lsrc, &S.lsrc},
+        {&M->ldq, &S.ldq}, {&M->l2u, &S.l2u}, {&M->upd_ptr, &S.upd_ptr}, {&M->upd, &S.upd},
+        {&M->urows, &S.urows}, {&M->uptr, &S.uptr}, {&M->ucol, &S.ucol}, {&M->usrc, &S.usrc},
+        {&M->dsrc, &S.dsrc}};
+    for (auto &u : ups)
+        if ((e = upload(*u.b, *u.v)) != hipSuccess) break;
+    if (e != hipSuccess) {
+        delete M;
+        return fail(e == hipErrorOutOfMemory ? RS_OUT_OF_MEMORY : RS_HIP_ERROR,
+                    std::string("ilu0_analyse: ") + hipGetErrorString(e));
+    }
+    DevSchedule &d = M->dev;
+    d.n = S.n; d.nnzb = S.nnzb; d.nL = S.nL; d.nU = S.nU;
+    d.perm = M->perm.as<int32_t>(); d.prow = M->prow.as<int32_t>(); d.pcol = M->pcol.as<int32_t>();
+    d.psrc = M->psrc.as<int32_t>(); d.lrows = M->lrows.as<int32_t>(); d.lptr = M->lptr.as<int32_t>();
+    d.lcol = M->lcol.as<int32_t>(); d.lsrc = M->lsrc.as<int32_t>(); d.ldq = M->ldq.as<int32_t>();
+    d.l2u = M->l2u.as<int32_t>(); d.upd_ptr = M->upd_ptr.as<int32_t>(); d.upd = M->upd.as<int32_t>();
+    d.urows = M->urows.as<int32_t>(); d.uptr = M->uptr.as<int32_t>(); d.ucol = M->ucol.as<int32_t>();
+    d.usrc = M->usrc.as<int32_t>(); d.dsrc = M->dsrc.as<int32_t>();
+    if (const char *c = std::getenv("RSOLVE_CHUNK")) M->chunk = std::max(1, std::atoi(c));
+    *out = M;
+    return RS_OK;
+}
+
+int ilu0_get_schedule(ilu0_t M, int32_t *perm, int32_t *n_sets, int32_t *set_ptr) {
+    if (!M) return fail(RS_INVALID_ARG, "ilu0_get_schedule: NULL handle");
+    if (perm && M->n) std::memcpy(perm, M->sch.perm.data(), sizeof(int32_t) * (size_t)M->n);
+    if (n_sets) *n_sets = M->sch.n_sets;
+    if (set_ptr) std::memcpy(set_ptr, M->sch.set_ptr.data(), sizeof(int32_t) * M->sch.set_ptr.size());
+    return RS_OK;
+}
+
+int ilu0_get_sweep_levels(ilu0_t M, int32_t *n_lower, int32_t *n_upper) {
+    if (!M) return fail(RS_INVALID_ARG, "ilu0_get_sweep_levels: NULL handle");
+    if (n_lower) *n_lower = M->sch.nl_levels;
+    if (n_upper) *n_upper = M->sch.nu_levels;
+    return RS_OK;
+}
+
+static int check_pair(ilu0_t M, bcsr_t A) {
+    if (!M || !A) return fail(RS_INVALID_ARG, "NULL handle");
+    if (M->hash != A->hash || M->n != A->n || M->nnzb != A->nnzb)
+        return fail(RS_PATTERN_MISMATCH, "ilu0 handle analysed for another pattern");
+    if (M->batch != A->batch) return fail(RS_PATTERN_MISMATCH, "batch size differs from the analysed matrix");
+    return RS_OK;
+}
+
+int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *bad_row) {
+    int st = check_pair(M, A);
+    if (st != RS_OK) return st;
+    if (precision != RS_PREC_FP64 && precision != RS_PREC_FP32_FACTORS)
+        return fail(RS_INVALID_ARG, "ilu0_factor: unknown precision");
+    hipStream_t s = (hipStream_t)stream;
+    const rs::Schedule &S = M->sch;
+    const size_t B = (size_t)M->batch;
+    HIP_TRY(M->pvals.alloc(B * M->nnzb * 9 * sizeof(double)));
+    HIP_TRY(M->L.alloc(B * S.nL * 9 * sizeof(double)));
+    HIP_TRY(M->U.alloc(B * S.nU * 9 * sizeof(double)));
+    HIP_TRY(M->Dinv.alloc(B * M->n * 9 * sizeof(double)));
+    HIP_TRY(M->bad.alloc(B * sizeof(int32_t)));
+    if (precision == RS_PREC_FP32_FACTORS) {
+        HIP_TRY(M->Lf.alloc(B * S.nL * 9 * sizeof(float)));
+        HIP_TRY(M->Uf.alloc(B * S.nU * 9 * sizeof(float)));
+        HIP_TRY(M->Dinvf.alloc(B * M->n * 9 * sizeof(float)));
+    }
+    M->factored = false;
+    HIP_TRY(hipMemsetAsync(M->bad.p, 0x7f, B * sizeof(int32_t), s));
+    const size_t per = (size_t)M->nnzb * 9;
+    rs::launch_gather_blocks(A->vals.as<double>(), per, M->pvals.as<double>(), per, M->dev.psrc, M->nnzb,
+                             M->batch, s);
+    for (int l = 0; l < S.nl_levels; ++l)
+        rs::launch_factor_level(M->dev, M->pvals.as<double>(), M->L.as<double>(), M->U.as<double>(),
+                                M->Dinv.as<double>(), M->bad.as<int32_t>(), S.lset[l], S.lset[l + 1], M->batch, s);
+    if (precision == RS_PREC_FP32_FACTORS) {
+        rs::launch_to_fp32(M->L.as<double>(), M->Lf.as<float>(), B * S.nL * 9, s);
+        rs::launch_to_fp32(M->U.as<double>(), M->Uf.as<float>(), B * S.nU * 9, s);
+        rs::launch_to_fp32(M->Dinv.as<double>(), M->Dinvf.as<float>(), B * M->n * 9, s);
+    }
+    HIP_TRY(hipGetLastError());
+    M->bad_host.assign(B, 0);
+    HIP_TRY(hipMemcpyAsync(M->bad_host.data(), M->bad.p, B * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int worst = RS_OK;
+    for (size_t i = 0; i < B; ++i) {
+        const int32_t b = M->bad_host[i];
+        const int32_t orig = (b >= 0 && b < M->n) ? S.perm[b] : -1;
+        if (bad_row) bad_row[i] = orig;
+        if (orig >= 0) worst = RS_ZERO_PIVOT;
+    }
+    M->precision = precision;
+    M->factored = true;
+    if (worst != RS_OK) g_err = "ilu0_factor: singular pivot block";
+    return worst;
+}
+
+int ilu0_get_factors(ilu0_t M, int32_t sys, double *lu, double *dinv) {
+    if (!M || sys < 0 || sys >= M->batch) return fail(RS_INVALID_ARG, "ilu0_get_factors: bad arguments");
+    if (!M->factored) return fail(RS_NOT_FACTORED, "ilu0_get_factors: not factored");
+    const rs::Schedule &S = M->sch;
+    std::vector<double> L((size_t)S.nL * 9), U((size_t)S.nU * 9), D((size_t)M->n * 9);
+    if (M->precision == RS_PREC_FP32_FACTORS) {
+        std::vector<float> Lf(L.size()), Uf(U.size()), Df(D.size());
+        if (!Lf.empty()) HIP_TRY(hipMemcpy(Lf.data(), M->Lf.as<float>() + (size_t)sys * Lf.size(), Lf.size() * 4, hipMemcpyDeviceToHost));
+        if (!Uf.empty()) HIP_TRY(hipMemcpy(Uf.data(), M->Uf.as<float>() + (size_t)sys * Uf.size(), Uf.size() * 4, hipMemcpyDeviceToHost));
+        if (!Df.empty()) HIP_TRY(hipMemcpy(Df.data(), M->Dinvf.as<float>() + (size_t)sys * Df.size(), Df.size() * 4, hipMemcpyDeviceToHost));
+        std::copy(Lf.begin(), Lf.end(), L.begin());
+        std::copy(Uf.begin(), Uf.end(), U.begin());
+        std::copy(Df.begin(), Df.end(), D.begin());
+    } else {
+        if (!L.empty()) HIP_TRY(hipMemcpy(L.data(), M->L.as<double>() + (size_t)sys * L.size(), L.size() * 8, hipMemcpyDeviceToHost));
+        if (!U.empty()) HIP_TRY(hipMemcpy(U.data(), M->U.as<double>() + (size_t)sys * U.size(), U.size() * 8, hipMemcpyDeviceToHost));
+        if (!D.empty()) HIP_TRY(hipMemcpy(D.data(), M->Dinv.as<double>() + (size_t)sys * D.size(), D.size() * 8, hipMemcpyDeviceToHost));
+    }
+    if (lu) {
+        for (int e = 0; e < S.nL; ++e) std::memcpy(lu + (size_t)S.lsrc[e] * 9, &L[(size_t)e * 9], 72);
+        for (int f = 0; f < S.nU; ++f) std::memcpy(lu + (size_t)S.usrc[f] * 9, &U[(size_t)f * 9], 72);
+    }
+    if (dinv)
+        for (int q = 0; q < M->n; ++q) std::memcpy(dinv + (size_t)S.urows[q] * 9, &D[(size_t)q * 9], 72);
+    return RS_OK;
+}
+
+static int ensure_workspace(ilu0_t M) {
+    const size_t B = (size_t)M->batch, m = 3 * (size_t)M->n;
+    const size_t vec = std::max<size_t>(B * m, 1);
+    HIP_TRY(M->work.alloc(9 * vec * sizeof(double)));
+    HIP_TRY(M->ywork.alloc(vec * sizeof(double)));
+    const size_t pstride = 2 * (size_t)std::max(rs::row_blocks(std::max(M->n, 1)), rs::vec_blocks(M->n));
+    if (!M->part.p || M->k.part_stride != pstride) HIP_TRY(M->part.alloc(B * pstride * sizeof(double)));
+    if (!M->state.p) {
+        HIP_TRY(M->state.alloc(B * sizeof(SysState)));
+        HIP_TRY(hipMemset(M->state.p, 0, B * sizeof(SysState)));
+        HIP_TRY(hipHostMalloc((void **)&M->h_state, B * sizeof(SysState), hipHostMallocDefault));
+    }
+    double *w = M->work.as<double>();
+    Krylov &k = M->k;
+    k.r = w; k.rhat = w + vec; k.p = w + 2 * vec; k.v = w + 3 * vec; k.phat = w + 4 * vec;
+    k.s = w + 5 * vec; k.shat = w + 6 * vec; k.t = w + 7 * vec; k.x = w + 8 * vec;
+    k.y = M->ywork.p;
+    k.part = M->part.as<double>();
+    k.part_stride = pstride;
+    k.st = M->state.as<SysState>();
+    return RS_OK;
+}
+
+}  // extern "C"
+
+// One preconditioner application M^{-1} in -> out (new order), all levels.
+template <typename T>
+static void apply_levels(ilu0_t M, const T *L, const T *U, const T *D, const double *in, double *out, bool fuse_p,
+                         Krylov &k, SysState *st, int nsys, hipStream_t s) {
+    const rs::Schedule &S = M->sch;
+    const size_t vs = 3 * (size_t)M->n;
+    T *y = (T *)k.y;
+    for (int l = 0; l < S.nl_levels; ++l)
+        rs::launch_lsweep<T>(M->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, S.lset[l],
+                             S.lset[l + 1], nsys, s);
+    for (int l = 0; l < S.nu_levels; ++l)
+        rs::launch_usweep<T>(M->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, S.uset[l],
+                             S.uset[l + 1], nsys, s);
+}
+
+template <typename T>
+static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipStream_t s) {
+    Krylov &k = M->k;
+    const int B = M->batch;
+    const size_t per = (size_t)M->nnzb * 9;
+    apply_levels<T>(M, L, U, D, nullptr, k.phat, true, k, k.st, B, s);
+    rs::launch_spmv_v(M->dev, M->pvals.as<double>(), per, k, B, s);
+    rs::launch_s_update(M->n, k, B, s);
+    apply_levels<T>(M, L, U, D, k.s, k.shat, false, k, k.st, B, s);
+    rs::launch_spmv_t(M->dev, M->pvals.as<double>(), per, k, B, s);
+    rs::launch_xr_update(M->n, k, B, s);
+}
+
+static void enqueue_iteration_any(ilu0_t M, hipStream_t s) {
+    if (M->precision == RS_PREC_FP32_FACTORS)
+        enqueue_iteration<float>(M, M->Lf.as<float>(), M->Uf.as<float>(), M->Dinvf.as<float>(), s);
+    else
+        enqueue_iteration<double>(M, M->L.as<double>(), M->U.as<double>(), M->Dinv.as<double>(), s);
+}
+
+extern "C" {
+
+int ilu0_apply(ilu0_t M, const double *v, double *z, int32_t first_sys, int32_t n_sys, int32_t mem, void *stream) {
+    if (!M || !v || !z || first_sys < 0 || n_sys < 0 || first_sys + n_sys > M->batch)
+        return fail(RS_INVALID_ARG, "ilu0_apply: bad arguments");
+    if (!M->factored) return fail(RS_NOT_FACTORED, "ilu0_apply: not factored");
+    if (n_sys == 0 || M->n == 0) return RS_OK;
+    int st = ensure_workspace(M);
+    if (st != RS_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t m = 3 * (size_t)M->n * n_sys;
+    const double *vd = nullptr;
+    st = stage_in(v, mem, M->bstage, m, s, &vd);
+    if (st != RS_OK) return st;
+    double *zd = z;
+    if (mem != RS_MEM_DEVICE) {
+        HIP_TRY(M->xstage.alloc(m * sizeof(double)));
+        zd = M->xstage.as<double>();
+    }
+    Krylov &k = M->k;
+    const rs::Schedule &S = M->sch;
+    rs::launch_permute_vec(M->dev.perm, vd, k.s, M->n, n_sys, false, s);
+    if (M->precision == RS_PREC_FP32_FACTORS)
+        apply_levels<float>(M, M->Lf.as<float>() + (size_t)first_sys * S.nL * 9,
+                            M->Uf.as<float>() + (size_t)first_sys * S.nU * 9,
+                            M->Dinvf.as<float>() + (size_t)first_sys * M->n * 9, k.s, k.shat, false, k, nullptr,
+                            n_sys, s);
+    else
+        apply_levels<double>(M, M->L.as<double>() + (size_t)first_sys * S.nL * 9,
+                             M->U.as<double>() + (size_t)first_sys * S.nU * 9,
+                             M->Dinv.as<double>() + (size_t)first_sys * M->n * 9, k.s, k.shat, false, k, nullptr,
+                             n_sys, s);
+    rs::launch_permute_vec(M->dev.perm, k.shat, zd, M->n, n_sys, true, s);
+    HIP_TRY(hipGetLastError());
+    if (mem != RS_MEM_DEVICE) {
+        HIP_TRY(hipMemcpyAsync(z, zd, m * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    return RS_OK;
+}
+
+static int status_rank(int s) {
+    if (s < 0) return 4;
+    if (s == RS_BREAKDOWN) return 3;
+    if (s == RS_NOT_CONVERGED) return 2;
+    return 1;
+}
+
+int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduction, int32_t max_iter, int32_t mem,
+                   void *stream, solve_info *info) {
+    int st = check_pair(M, A);
+    if (st != RS_OK) return st;
+    if (!b || !x || !(reduction >= 0.0) || max_iter < 0 || (mem != RS_MEM_HOST && mem != RS_MEM_DEVICE))
+        return fail(RS_INVALID_ARG, "bicgstab_solve: bad arguments");
+    if (!M->factored) return fail(RS_NOT_FACTORED, "bicgstab_solve: call ilu0_factor first");
+    const int B = M->batch;
+    if (M->n == 0) {
+        if (info)
+            for (int i = 0; i < B; ++i) info[i] = solve_info{RS_OK, 0, 0.0, 0.0, 0.0};
+        return RS_OK;
+    }
+    st = ensure_workspace(M);
+    if (st != RS_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t m = 3 * (size_t)M->n * B;
+    const double *bd = nullptr;
+    st = stage_in(b, mem, M->bstage, m, s, &bd);
+    if (st != RS_OK) return st;
+    double *xd = x;
+    if (mem != RS_MEM_DEVICE) {
+        HIP_TRY(M->xstage.alloc(m * sizeof(double)));
+        xd = M->xstage.as<double>();
+    }
+    Krylov &k = M->k;
+    rs::launch_setup(M->dev, bd, M->bad.as<int32_t>(), reduction, max_iter, k, B, s);
+    int done_iters = 0;
+    while (done_iters < max_iter) {
+        const int c = std::min(M->chunk, max_iter - done_iters);
+        for (int i = 0; i < c; ++i) enqueue_iteration_any(M, s);
+        done_iters += c;
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        bool all = true;
+        for (int i = 0; i < B; ++i) all &= (M->h_state[i].phase == rs::PH_DONE);
+        if (all) break;
+    }
+    rs::launch_finish(M->dev, A->rowptr.as<int32_t>(), A->colidx.as<int32_t>(), A->vals.as<double>(),
+                      (size_t)A->nnzb * 9, bd, xd, k, B, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
+    if (mem != RS_MEM_DEVICE) HIP_TRY(hipMemcpyAsync(x, xd, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int worst = RS_OK;
+    for (int i = 0; i < B; ++i) {
+        const SysState &S = M->h_state[i];
+        if (info) info[i] = solve_info{S.status, S.half_steps, S.r0norm, S.last_norm, S.true_res};
+        if (status_rank(S.status) > status_rank(worst)) worst = S.status;
+    }
+    return worst;
+}
+
+int ilu0_destroy(ilu0_t M) {
+    delete M;
+    return RS_OK;
+}
+
+}  // extern "C"

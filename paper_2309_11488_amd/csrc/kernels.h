@@ -1,0 +1,100 @@
+// Device data structures and kernel launchers of the BCSR BiCGStab-ILU0 path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace rs {
+
+// Per-system BiCGStab scalars, kept on the device for the whole solve.
+// phase: RUN while iterating, HALF after a half-step stop (x still needs
+// x += alpha phat), DONE when finished.
+enum Phase : int32_t { PH_RUN = 0, PH_HALF = 1, PH_DONE = 2 };
+
+struct SysState {
+    double rho, rho_old, alpha, omega, beta;
+    double r0norm, tol, last_norm;
+    double true_res;
+    int32_t phase, status, half_steps, iter;
+    int32_t max_iter, pad0;
+    uint32_t ticket, pad;
+};
+
+// Device copies of the schedule (see analysis.h for the meaning).
+struct DevSchedule {
+    int n, nnzb, nL, nU;
+    const int32_t *perm, *prow, *pcol, *psrc;
+    const int32_t *lrows, *lptr, *lcol, *lsrc, *ldq, *l2u, *upd_ptr, *upd;
+    const int32_t *urows, *uptr, *ucol, *usrc, *dsrc;
+};
+
+// Workspace vectors of one solve, each nsys * 3n long in the new order.
+struct Krylov {
+    double *r, *rhat, *p, *v, *phat, *s, *shat, *t, *x;
+    void *y;            // lower-sweep intermediate, FP64 or FP32 (factor type)
+    double *part;       // reduction partials, nsys * part_stride
+    size_t part_stride;
+    SysState *st;       // nsys states
+};
+
+// Launch geometry shared by host and device code.
+constexpr int kWave = 64;
+constexpr int kRowsPerWave = 21;                            // 3 lanes per block row, 63 of 64 lanes busy
+constexpr int kWavesPerBlock = 4;
+constexpr int kRowsPerBlock = kRowsPerWave * kWavesPerBlock;  // 84 block rows per workgroup
+constexpr int kRowThreads = kWave * kWavesPerBlock;           // 256
+constexpr int kStageBlocks = 448;                           // 3x3 blocks staged in LDS per pass
+constexpr int kVecThreads = 256;
+constexpr int kVecMaxBlocks = 1024;
+
+inline int row_blocks(int rows) { return (rows + kRowsPerBlock - 1) / kRowsPerBlock; }
+int vec_blocks(int n);  // workgroups of the vector kernels for 3n entries
+
+// A'[p] = A[src[p]] for every system (blocks of 9 doubles).
+void launch_gather_blocks(const double *A, size_t a_stride, double *Ap, size_t ap_stride, const int32_t *src,
+                          int cnt, int nsys, hipStream_t s);
+
+// One level of the block ILU0 factorisation: L-schedule rows [q0, q1).
+void launch_factor_level(const DevSchedule &d, const double *Ap, double *L, double *U, double *Dinv, int32_t *bad,
+                         int q0, int q1, int nsys, hipStream_t s);
+
+// FP32 copies of the factors (round to nearest even).
+void launch_to_fp32(const double *src, float *dst, size_t count, hipStream_t s);
+
+// Lower sweep y = L^{-1} in for L-schedule rows [q0, q1).  When fuse_p is
+// set, the input is p = r + beta (p - omega v) computed on the fly (and
+// stored); otherwise `in`.  st may be NULL (no phase check).
+template <typename T>
+void launch_lsweep(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
+                   bool fuse_p, const double *r, const double *v, double *p, SysState *st, int q0, int q1, int nsys,
+                   hipStream_t s);
+
+// Upper sweep z = inv(U_ii) (y - U z) for U-schedule rows [q0, q1).
+template <typename T>
+void launch_usweep(const DevSchedule &d, const T *U, size_t u_stride, const T *Dinv, size_t d_stride, const T *y,
+                   double *z, size_t vstride, SysState *st, int q0, int q1, int nsys, hipStream_t s);
+
+// Plain y = A x (rows in storage order), FP64.
+void launch_spmv(int n, const int32_t *ptr, const int32_t *col, const double *A, size_t a_stride, const double *x,
+                 double *y, size_t vstride, int nsys, hipStream_t s);
+
+// Solver kernels (new order, all nsys systems of the Krylov workspace).
+// bad[sys] < n marks a system whose factorisation hit a singular pivot.
+void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad, double reduction, int max_iter,
+                  Krylov &k, int nsys, hipStream_t s);
+void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, hipStream_t s);
+void launch_s_update(int n, Krylov &k, int nsys, hipStream_t s);
+void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, hipStream_t s);
+void launch_xr_update(int n, Krylov &k, int nsys, hipStream_t s);
+// x_orig[perm[i]] = x'[i]; then r = b - A x_orig with the caller's A, and the
+// true relative residual into the states.
+void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *colidx, const double *A,
+                   size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, hipStream_t s);
+
+// out[i] = in[perm[i]] (gather to the new order) and its inverse scatter.
+void launch_permute_vec(const int32_t *perm, const double *in, double *out, int n, int nsys, bool scatter,
+                        hipStream_t s);
+
+}  // namespace rs

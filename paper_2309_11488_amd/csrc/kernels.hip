@@ -1,0 +1,562 @@
+// HIP kernels (gfx950) of the BCSR 3x3 BiCGStab-ILU0 path.
+//
+// Row kernels (SpMV, ILU0 sweeps, ILU0 factor) give each block row three
+// lanes, one per row of the 3x3 blocks: 21 rows per 64-wide wavefront (lane
+// 63 idle), 84 rows per 256-thread workgroup.  The values of a workgroup's
+// rows are one contiguous range (rows are stored level by level), so they are
+// first copied into LDS with fully coalesced loads, then each lane walks its
+// row's blocks from LDS.  This is the blocked SpMV idea of Eberhardt and
+// Hoemmen cited in Section "Sparse Matrix-Vector multiplication" (lanes with a
+// fixed position inside a block), re-shaped for wave64 and LDS.
+//
+// Reductions are deterministic: every workgroup writes its partial sum, and
+// the last workgroup to arrive (ticket counter) adds the partials in a fixed
+// order and updates the BiCGStab scalars on the device.  The number of
+// workgroups depends only on the system size, so a system gives the same bits
+// alone and inside a batch.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "../../include/rsolve.h"
+
+namespace rs {
+
+namespace {
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Remap the linear
+// workgroup id so each XCD gets one contiguous run of (system, tile) pairs:
+// neighbouring tiles then share x/y lines in that XCD's L2.
+__device__ inline void xcd_map(int &sys, int &bx) {
+    const unsigned gx = gridDim.x, total = gx * gridDim.y;
+    const unsigned lin = blockIdx.x + blockIdx.y * gx;
+    const unsigned q = total / 8u, rem = total % 8u, xcd = lin % 8u, k = lin / 8u;
+    const unsigned logical = (xcd < rem ? xcd * (q + 1u) : rem * (q + 1u) + (xcd - rem) * q) + k;
+    sys = (int)(logical / gx);
+    bx = (int)(logical % gx);
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum NV values over the workgroup; thread 0 gets the result.
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double *lds) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+        for (int k = 0; k < NV; ++k) lds[w * NV + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int i = 0; i < nw; ++i) s += lds[i * NV + k];
+            v[k] = s;
+        }
+    __syncthreads();
+}
+
+// Deterministic grid reduction.  Returns true in the last workgroup to
+// finish, where thread 0's v[] holds the grid total.
+template <int NV>
+__device__ bool grid_reduce(double (&v)[NV], double *part, uint32_t *ticket, int nblk, int bx) {
+    __shared__ double lds[16 * NV];
+    __shared__ int last;
+    block_sum<NV>(v, lds);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < NV; ++k)
+            __hip_atomic_store(part + (size_t)bx * NV + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = (t == (uint32_t)(nblk - 1));
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    double acc[NV];
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+        for (int k = 0; k < NV; ++k)
+            acc[k] += __hip_atomic_load(part + (size_t)b * NV + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    block_sum<NV>(acc, lds);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < NV; ++k) v[k] = acc[k];
+        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return true;
+}
+
+__device__ inline bool finite(double x) { return __builtin_isfinite(x); }
+
+// Lane geometry of the row kernels.
+struct RowLane {
+    int q;      // row position in the launch's range
+    int r;      // row inside the 3x3 block
+    int base;   // first lane of this block row in the wave
+    bool act;
+};
+
+__device__ inline RowLane row_lane(int bx, int q0, int q1) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    RowLane L;
+    L.q = q0 + bx * kRowsPerBlock + w * kRowsPerWave + lane / 3;
+    L.r = lane % 3;
+    L.base = lane - L.r;
+    L.act = lane < 63 && L.q < q1;
+    return L;
+}
+
+// Walk the blocks of this lane's row, staged through LDS pass by pass.
+// acc (+|-)= sum_c val[e][r][c] * x[3 col[e] + c] per block, blocks ascending.
+template <int CAP, bool SUB, typename T, typename TX>
+__device__ inline T stage_walk(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                               const T *__restrict__ val, int qb0, int qb1, const RowLane &L, const TX *__restrict__ x,
+                               T acc, T *sv) {
+    const int e0 = ptr[qb0], e1 = ptr[qb1];
+    const int my0 = L.act ? ptr[L.q] : 0, my1 = L.act ? ptr[L.q + 1] : 0;
+    for (int base = e0; base < e1; base += CAP) {
+        const int cnt = min(CAP, e1 - base);
+        __syncthreads();
+        const T *src = val + (size_t)base * 9;
+        for (int i = threadIdx.x; i < cnt * 9; i += blockDim.x) sv[i] = src[i];
+        __syncthreads();
+        const int lo = max(my0, base), hi = min(my1, base + cnt);
+        for (int e = lo; e < hi; ++e) {
+            const int j = col[e];
+            const T *b = sv + (e - base) * 9 + 3 * L.r;
+            const T s = b[0] * (T)x[3 * j] + b[1] * (T)x[3 * j + 1] + b[2] * (T)x[3 * j + 2];
+            if (SUB) acc -= s; else acc += s;
+        }
+    }
+    return acc;
+}
+
+constexpr int kSpmvCap = 640;   // 46 KB of FP64 blocks
+constexpr int kSweepCap = 320;
+
+// ------------------------------------------------------------------ gather
+
+__global__ void k_gather_blocks(const double *__restrict__ A, size_t a_stride, double *__restrict__ Ap,
+                                size_t ap_stride, const int32_t *__restrict__ src, int cnt) {
+    const int sys = blockIdx.y;
+    const size_t total = (size_t)cnt * 9;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const size_t p = t / 9, e = t % 9;
+        Ap[sys * ap_stride + t] = A[sys * a_stride + (size_t)src[p] * 9 + e];
+    }
+}
+
+// ------------------------------------------------------------------ factor
+
+// Block ILU0, one level of the lower schedule.  Lane r of row i owns row r of
+// every block of block row i.  In Algorithm 2's order: for each lower block
+// (i,k), k ascending, L_ik = a_ik inv(U_kk); then a_ij -= L_ik U_kj over the
+// precomputed update list (j ascending).  Finally inv(U_ii) from the
+// adjugate; a singular or non-finite pivot is reported by its new index.
+__global__ void k_factor_level(DevSchedule d, const double *__restrict__ Ap, double *__restrict__ L,
+                               double *__restrict__ U, double *__restrict__ Dinv, int32_t *__restrict__ bad, int q0,
+                               int q1) {
+    int sys, bx;
+    xcd_map(sys, bx);
+    const RowLane rl = row_lane(bx, q0, q1);
+    const double *A = Ap + (size_t)sys * d.nnzb * 9;
+    double *Ls = L + (size_t)sys * d.nL * 9;
+    double *Us = U + (size_t)sys * d.nU * 9;
+    double *Ds = Dinv + (size_t)sys * d.n * 9;
+    const int r = rl.r;
+    double dr0 = 0.0, dr1 = 0.0, dr2 = 0.0;
+    int uq = 0;
+    if (rl.act) {
+        const int q = rl.q;
+        uq = d.l2u[q];
+        for (int f = d.uptr[uq]; f < d.uptr[uq + 1]; ++f)
+            for (int c = 0; c < 3; ++c) Us[(size_t)f * 9 + 3 * r + c] = A[(size_t)d.usrc[f] * 9 + 3 * r + c];
+        const double *ad = A + (size_t)d.dsrc[uq] * 9 + 3 * r;
+        dr0 = ad[0]; dr1 = ad[1]; dr2 = ad[2];
+        const int e0 = d.lptr[q], e1 = d.lptr[q + 1];
+        for (int e = e0; e < e1; ++e)
+            for (int c = 0; c < 3; ++c) Ls[(size_t)e * 9 + 3 * r + c] = A[(size_t)d.lsrc[e] * 9 + 3 * r + c];
+        for (int e = e0; e < e1; ++e) {
+            double *le = Ls + (size_t)e * 9 + 3 * r;
+            const double a0 = le[0], a1 = le[1], a2 = le[2];
+            const double *dk = Ds + (size_t)d.ldq[e] * 9;
+            double l[3];
+            for (int c = 0; c < 3; ++c) l[c] = a0 * dk[c] + a1 * dk[3 + c] + a2 * dk[6 + c];
+            le[0] = l[0]; le[1] = l[1]; le[2] = l[2];
+            for (int u = d.upd_ptr[e]; u < d.upd_ptr[e + 1]; ++u) {
+                const int code = d.upd[2 * u], fs = d.upd[2 * u + 1];
+                const double *ukj = Us + (size_t)fs * 9;
+                double pr[3];
+                for (int c = 0; c < 3; ++c) pr[c] = l[0] * ukj[c] + l[1] * ukj[3 + c] + l[2] * ukj[6 + c];
+                const int kind = code & 3, pos = code >> 2;
+                if (kind == 1) {
+                    dr0 -= pr[0]; dr1 -= pr[1]; dr2 -= pr[2];
+                } else {
+                    double *t = (kind == 0 ? Ls : Us) + (size_t)pos * 9 + 3 * r;
+                    t[0] -= pr[0]; t[1] -= pr[1]; t[2] -= pr[2];
+                }
+            }
+        }
+    }
+    // gather the three rows of U_ii from the row's lanes
+    double a[9];
+    for (int rr = 0; rr < 3; ++rr) {
+        a[3 * rr + 0] = __shfl(dr0, rl.base + rr, 64);
+        a[3 * rr + 1] = __shfl(dr1, rl.base + rr, 64);
+        a[3 * rr + 2] = __shfl(dr2, rl.base + rr, 64);
+    }
+    if (!rl.act) return;
+    const double c00 = a[4] * a[8] - a[5] * a[7];
+    const double c01 = a[5] * a[6] - a[3] * a[8];
+    const double c02 = a[3] * a[7] - a[4] * a[6];
+    const double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+    double inv[3];
+    if (r == 0) { inv[0] = c00 / det; inv[1] = (a[2] * a[7] - a[1] * a[8]) / det; inv[2] = (a[1] * a[5] - a[2] * a[4]) / det; }
+    else if (r == 1) { inv[0] = c01 / det; inv[1] = (a[0] * a[8] - a[2] * a[6]) / det; inv[2] = (a[2] * a[3] - a[0] * a[5]) / det; }
+    else { inv[0] = c02 / det; inv[1] = (a[1] * a[6] - a[0] * a[7]) / det; inv[2] = (a[0] * a[4] - a[1] * a[3]) / det; }
+    double *dq = Ds + (size_t)uq * 9 + 3 * r;
+    dq[0] = inv[0]; dq[1] = inv[1]; dq[2] = inv[2];
+    if (r == 0 && (det == 0.0 || !finite(det))) atomicMin(bad + sys, d.lrows[rl.q]);
+}
+
+__global__ void k_to_fp32(const double *__restrict__ src, float *__restrict__ dst, size_t count) {
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (size_t)gridDim.x * blockDim.x)
+        dst[t] = (float)src[t];
+}
+
+// ------------------------------------------------------------------ sweeps
+
+template <typename T, bool FUSE_P>
+__global__ void __launch_bounds__(kRowThreads) k_lsweep(DevSchedule d, const T *__restrict__ L, size_t l_stride,
+                                                        const double *__restrict__ in, T *__restrict__ y,
+                                                        size_t vstride, const double *__restrict__ rv,
+                                                        const double *__restrict__ vv, double *__restrict__ pv,
+                                                        SysState *__restrict__ st, int q0, int q1) {
+    __shared__ T sv[kSweepCap * 9];
+    int sys, bx;
+    xcd_map(sys, bx);
+    if (st && st[sys].phase != PH_RUN) return;
+    const RowLane rl = row_lane(bx, q0, q1);
+    const int qb0 = q0 + bx * kRowsPerBlock, qb1 = min(qb0 + kRowsPerBlock, q1);
+    const size_t vo = (size_t)sys * vstride;
+    const int i = rl.act ? d.lrows[rl.q] : 0;
+    T acc = 0;
+    if (rl.act) {
+        const size_t k = vo + 3 * (size_t)i + rl.r;
+        if (FUSE_P) {
+            const double beta = st[sys].beta, omega = st[sys].omega;
+            const double p = rv[k] + beta * (pv[k] - omega * vv[k]);
+            pv[k] = p;
+            acc = (T)p;
+        } else {
+            acc = (T)in[k];
+        }
+    }
+    acc = stage_walk<kSweepCap, true>(d.lptr, d.lcol, L + (size_t)sys * l_stride, qb0, qb1, rl, y + vo, acc, sv);
+    if (rl.act) y[vo + 3 * (size_t)i + rl.r] = acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRowThreads) k_usweep(DevSchedule d, const T *__restrict__ U, size_t u_stride,
+                                                        const T *__restrict__ Dinv, size_t d_stride,
+                                                        const T *__restrict__ y, double *__restrict__ z,
+                                                        size_t vstride, SysState *__restrict__ st, int q0, int q1) {
+    __shared__ T sv[kSweepCap * 9];
+    int sys, bx;
+    xcd_map(sys, bx);
+    if (st && st[sys].phase != PH_RUN) return;
+    const RowLane rl = row_lane(bx, q0, q1);
+    const int qb0 = q0 + bx * kRowsPerBlock, qb1 = min(qb0 + kRowsPerBlock, q1);
+    const size_t vo = (size_t)sys * vstride;
+    const int i = rl.act ? d.urows[rl.q] : 0;
+    T acc = rl.act ? y[vo + 3 * (size_t)i + rl.r] : (T)0;
+    acc = stage_walk<kSweepCap, true>(d.uptr, d.ucol, U + (size_t)sys * u_stride, qb0, qb1, rl, z + vo, acc, sv);
+    const T t0 = __shfl(acc, rl.base, 64), t1 = __shfl(acc, rl.base + 1, 64), t2 = __shfl(acc, rl.base + 2, 64);
+    if (!rl.act) return;
+    const T *dq = Dinv + (size_t)sys * d_stride + (size_t)rl.q * 9 + 3 * rl.r;
+    const T zr = dq[0] * t0 + dq[1] * t1 + dq[2] * t2;
+    z[vo + 3 * (size_t)i + rl.r] = (double)zr;
+}
+
+// -------------------------------------------------------------------- SpMV
+
+enum SpmvMode { SPMV_PLAIN = 0, SPMV_V = 1, SPMV_T = 2, SPMV_TRUE = 3 };
+
+// y = A x over rows in storage order, with the epilogue of the mode:
+//   SPMV_V:    v = A phat, reduce (rhat, v), alpha = rho / (rhat, v)
+//   SPMV_T:    t = A shat, reduce (t, s) and (t, t), omega = (t, s) / (t, t)
+//   SPMV_TRUE: reduce ||b - A x||^2 and ||b||^2, true relative residual
+template <int MODE>
+__global__ void __launch_bounds__(kRowThreads) k_spmv(int n, const int32_t *__restrict__ ptr,
+                                                      const int32_t *__restrict__ col, const double *__restrict__ A,
+                                                      size_t a_stride, const double *__restrict__ x,
+                                                      double *__restrict__ y, size_t vstride,
+                                                      const double *__restrict__ w1, const double *__restrict__ w2,
+                                                      double *__restrict__ part, size_t part_stride,
+                                                      SysState *__restrict__ st) {
+    __shared__ double sv[kSpmvCap * 9];
+    int sys, bx;
+    xcd_map(sys, bx);
+    if (MODE != SPMV_PLAIN && MODE != SPMV_TRUE && st[sys].phase != PH_RUN) return;
+    const RowLane rl = row_lane(bx, 0, n);
+    const int qb0 = bx * kRowsPerBlock, qb1 = min(qb0 + kRowsPerBlock, n);
+    const size_t vo = (size_t)sys * vstride;
+    double acc = stage_walk<kSpmvCap, false>(ptr, col, A + (size_t)sys * a_stride, qb0, qb1, rl, x + vo, 0.0, sv);
+    const size_t k = vo + 3 * (size_t)rl.q + rl.r;
+    if (MODE == SPMV_PLAIN) {
+        if (rl.act) y[k] = acc;
+        return;
+    }
+    if (MODE == SPMV_V) {
+        double v[1] = {0.0};
+        if (rl.act) { y[k] = acc; v[0] = w1[k] * acc; }
+        if (grid_reduce<1>(v, part + sys * part_stride, &st[sys].ticket, gridDim.x, bx) && threadIdx.x == 0) {
+            SysState &S = st[sys];
+            const double rv = v[0];
+            if (!finite(rv)) { S.status = RS_NON_FINITE; S.phase = PH_DONE; }
+            else if (rv == 0.0) { S.status = RS_BREAKDOWN; S.phase = PH_DONE; }
+            else S.alpha = S.rho / rv;
+        }
+    } else if (MODE == SPMV_T) {
+        double v[2] = {0.0, 0.0};
+        if (rl.act) { y[k] = acc; v[0] = acc * w1[k]; v[1] = acc * acc; }
+        if (grid_reduce<2>(v, part + sys * part_stride, &st[sys].ticket, gridDim.x, bx) && threadIdx.x == 0) {
+            SysState &S = st[sys];
+            const double ts = v[0], tt = v[1];
+            if (!finite(ts) || !finite(tt)) { S.status = RS_NON_FINITE; S.phase = PH_DONE; }
+            else if (tt == 0.0) { S.status = RS_BREAKDOWN; S.phase = PH_DONE; }
+            else {
+                S.omega = ts / tt;
+                if (S.omega == 0.0) { S.status = RS_BREAKDOWN; S.phase = PH_HALF; }
+            }
+        }
+    } else {  // SPMV_TRUE: w1 = b
+        double v[2] = {0.0, 0.0};
+        if (rl.act) { const double res = w1[k] - acc; v[0] = res * res; v[1] = w1[k] * w1[k]; }
+        if (grid_reduce<2>(v, part + sys * part_stride, &st[sys].ticket, gridDim.x, bx) && threadIdx.x == 0) {
+            st[sys].true_res = v[1] > 0.0 ? sqrt(v[0]) / sqrt(v[1]) : 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- vectors
+
+// r = rhat = P b, x = p = v = 0, ||b||; initial scalars.
+__global__ void __launch_bounds__(kVecThreads) k_setup(int n, const int32_t *__restrict__ perm,
+                                                       const double *__restrict__ b, size_t vstride, Krylov k,
+                                                       const int32_t *__restrict__ bad, double reduction,
+                                                       int max_iter) {
+    const int sys = blockIdx.y, bx = blockIdx.x;
+    const size_t vo = (size_t)sys * vstride, m = 3 * (size_t)n;
+    double v[1] = {0.0};
+    for (size_t e = (size_t)bx * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
+        const double val = b[vo + 3 * (size_t)perm[e / 3] + e % 3];
+        k.r[vo + e] = val; k.rhat[vo + e] = val;
+        k.x[vo + e] = 0.0; k.p[vo + e] = 0.0; k.v[vo + e] = 0.0;
+        v[0] += val * val;
+    }
+    if (grid_reduce<1>(v, k.part + sys * k.part_stride, &k.st[sys].ticket, gridDim.x, bx) && threadIdx.x == 0) {
+        SysState &S = k.st[sys];
+        const double r0 = sqrt(v[0]);
+        S.r0norm = r0; S.tol = reduction * r0; S.last_norm = r0;
+        S.rho = v[0]; S.rho_old = 1.0; S.alpha = 1.0; S.omega = 1.0;
+        S.beta = (S.rho / S.rho_old) * (S.alpha / S.omega);
+        S.half_steps = 0; S.iter = 1; S.max_iter = max_iter; S.true_res = 0.0;
+        if (bad && bad[sys] < n) { S.status = RS_ZERO_PIVOT; S.phase = PH_DONE; }
+        else if (!finite(r0)) { S.status = RS_NON_FINITE; S.phase = PH_DONE; }
+        else if (r0 == 0.0) { S.status = RS_OK; S.phase = PH_DONE; }
+        else if (max_iter <= 0) { S.status = RS_NOT_CONVERGED; S.phase = PH_DONE; }
+        else { S.status = RS_NOT_CONVERGED; S.phase = PH_RUN; }
+    }
+}
+
+// s = r - alpha v, ||s||; half-step test.
+__global__ void __launch_bounds__(kVecThreads) k_s_update(int n, size_t vstride, Krylov k) {
+    const int sys = blockIdx.y, bx = blockIdx.x;
+    SysState &S = k.st[sys];
+    if (S.phase != PH_RUN) return;
+    const double alpha = S.alpha;
+    const size_t vo = (size_t)sys * vstride, m = 3 * (size_t)n;
+    double v[1] = {0.0};
+    for (size_t e = (size_t)bx * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
+        const double s = k.r[vo + e] - alpha * k.v[vo + e];
+        k.s[vo + e] = s;
+        v[0] += s * s;
+    }
+    if (grid_reduce<1>(v, k.part + sys * k.part_stride, &S.ticket, gridDim.x, bx) && threadIdx.x == 0) {
+        const double sn = sqrt(v[0]);
+        S.half_steps = 2 * S.iter - 1;
+        S.last_norm = sn;
+        if (!finite(sn)) { S.status = RS_NON_FINITE; S.phase = PH_DONE; }
+        else if (sn <= S.tol) { S.status = RS_OK; S.phase = PH_HALF; }
+    }
+}
+
+// Full step: x += alpha phat + omega shat, r = s - omega t, ||r||, (rhat, r),
+// full-step test, next rho and beta.  After a half-step stop (or an omega
+// breakdown) only x += alpha phat.
+__global__ void __launch_bounds__(kVecThreads) k_xr_update(int n, size_t vstride, Krylov k) {
+    const int sys = blockIdx.y, bx = blockIdx.x;
+    SysState &S = k.st[sys];
+    const int phase = S.phase;
+    if (phase == PH_DONE) return;
+    const double alpha = S.alpha, omega = S.omega;
+    const size_t vo = (size_t)sys * vstride, m = 3 * (size_t)n;
+    double v[2] = {0.0, 0.0};
+    if (phase == PH_HALF) {
+        for (size_t e = (size_t)bx * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x)
+            k.x[vo + e] += alpha * k.phat[vo + e];
+    } else {
+        for (size_t e = (size_t)bx * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
+            const size_t t = vo + e;
+            k.x[t] += alpha * k.phat[t] + omega * k.shat[t];
+            const double r = k.s[t] - omega * k.t[t];
+            k.r[t] = r;
+            v[0] += r * r;
+            v[1] += k.rhat[t] * r;
+        }
+    }
+    if (grid_reduce<2>(v, k.part + sys * k.part_stride, &S.ticket, gridDim.x, bx) && threadIdx.x == 0) {
+        if (phase == PH_HALF) { S.phase = PH_DONE; return; }
+        const double rn = sqrt(v[0]);
+        S.half_steps = 2 * S.iter;
+        S.last_norm = rn;
+        if (!finite(rn)) { S.status = RS_NON_FINITE; S.phase = PH_DONE; }
+        else if (rn <= S.tol) { S.status = RS_OK; S.phase = PH_DONE; }
+        else if (S.iter >= S.max_iter) { S.status = RS_NOT_CONVERGED; S.phase = PH_DONE; }
+        else {
+            S.rho_old = S.rho;
+            S.rho = v[1];
+            if (S.rho == 0.0) { S.status = RS_BREAKDOWN; S.phase = PH_DONE; }
+            else {
+                S.beta = (S.rho / S.rho_old) * (S.alpha / S.omega);
+                S.iter += 1;
+            }
+        }
+    }
+}
+
+__global__ void k_permute_vec(const int32_t *__restrict__ perm, const double *__restrict__ in,
+                              double *__restrict__ out, int n, size_t vstride, int scatter) {
+    const int sys = blockIdx.y;
+    const size_t vo = (size_t)sys * vstride, m = 3 * (size_t)n;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t o = 3 * (size_t)perm[e / 3] + e % 3;
+        if (scatter) out[vo + o] = in[vo + e];
+        else out[vo + e] = in[vo + o];
+    }
+}
+
+}  // namespace
+
+int vec_blocks(int n) {
+    const long m = 3L * n;
+    long g = (m + kVecThreads * 4 - 1) / (kVecThreads * 4);
+    if (g < 1) g = 1;
+    if (g > kVecMaxBlocks) g = kVecMaxBlocks;
+    return (int)g;
+}
+
+static int copy_blocks(size_t m) {
+    size_t g = (m + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 8192) g = 8192;
+    return (int)g;
+}
+
+void launch_gather_blocks(const double *A, size_t a_stride, double *Ap, size_t ap_stride, const int32_t *src, int cnt,
+                          int nsys, hipStream_t s) {
+    if (cnt <= 0 || nsys <= 0) return;
+    k_gather_blocks<<<dim3(copy_blocks((size_t)cnt * 9), nsys), 256, 0, s>>>(A, a_stride, Ap, ap_stride, src, cnt);
+}
+
+void launch_factor_level(const DevSchedule &d, const double *Ap, double *L, double *U, double *Dinv, int32_t *bad,
+                         int q0, int q1, int nsys, hipStream_t s) {
+    if (q1 <= q0 || nsys <= 0) return;
+    k_factor_level<<<dim3(row_blocks(q1 - q0), nsys), kRowThreads, 0, s>>>(d, Ap, L, U, Dinv, bad, q0, q1);
+}
+
+void launch_to_fp32(const double *src, float *dst, size_t count, hipStream_t s) {
+    if (count == 0) return;
+    k_to_fp32<<<copy_blocks(count), 256, 0, s>>>(src, dst, count);
+}
+
+template <typename T>
+void launch_lsweep(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
+                   bool fuse_p, const double *r, const double *v, double *p, SysState *st, int q0, int q1, int nsys,
+                   hipStream_t s) {
+    if (q1 <= q0 || nsys <= 0) return;
+    const dim3 g(row_blocks(q1 - q0), nsys);
+    if (fuse_p) k_lsweep<T, true><<<g, kRowThreads, 0, s>>>(d, L, l_stride, in, y, vstride, r, v, p, st, q0, q1);
+    else k_lsweep<T, false><<<g, kRowThreads, 0, s>>>(d, L, l_stride, in, y, vstride, r, v, p, st, q0, q1);
+}
+
+template <typename T>
+void launch_usweep(const DevSchedule &d, const T *U, size_t u_stride, const T *Dinv, size_t d_stride, const T *y,
+                   double *z, size_t vstride, SysState *st, int q0, int q1, int nsys, hipStream_t s) {
+    if (q1 <= q0 || nsys <= 0) return;
+    k_usweep<T><<<dim3(row_blocks(q1 - q0), nsys), kRowThreads, 0, s>>>(d, U, u_stride, Dinv, d_stride, y, z, vstride,
+                                                                        st, q0, q1);
+}
+
+template void launch_lsweep<double>(const DevSchedule &, const double *, size_t, const double *, double *, size_t,
+                                    bool, const double *, const double *, double *, SysState *, int, int, int,
+                                    hipStream_t);
+template void launch_lsweep<float>(const DevSchedule &, const float *, size_t, const double *, float *, size_t, bool,
+                                   const double *, const double *, double *, SysState *, int, int, int, hipStream_t);
+template void launch_usweep<double>(const DevSchedule &, const double *, size_t, const double *, size_t,
+                                    const double *, double *, size_t, SysState *, int, int, int, hipStream_t);
+template void launch_usweep<float>(const DevSchedule &, const float *, size_t, const float *, size_t, const float *,
+                                   double *, size_t, SysState *, int, int, int, hipStream_t);
+
+void launch_spmv(int n, const int32_t *ptr, const int32_t *col, const double *A, size_t a_stride, const double *x,
+                 double *y, size_t vstride, int nsys, hipStream_t s) {
+    if (n <= 0 || nsys <= 0) return;
+    k_spmv<SPMV_PLAIN><<<dim3(row_blocks(n), nsys), kRowThreads, 0, s>>>(n, ptr, col, A, a_stride, x, y, vstride,
+                                                                        nullptr, nullptr, nullptr, 0, nullptr);
+}
+
+void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad, double reduction, int max_iter,
+                  Krylov &k, int nsys, hipStream_t s) {
+    k_setup<<<dim3(vec_blocks(d.n), nsys), kVecThreads, 0, s>>>(d.n, d.perm, b_orig, 3 * (size_t)d.n, k, bad,
+                                                               reduction, max_iter);
+}
+
+void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, hipStream_t s) {
+    k_spmv<SPMV_V><<<dim3(row_blocks(d.n), nsys), kRowThreads, 0, s>>>(
+        d.n, d.prow, d.pcol, Ap, a_stride, k.phat, k.v, 3 * (size_t)d.n, k.rhat, nullptr, k.part, k.part_stride, k.st);
+}
+
+void launch_s_update(int n, Krylov &k, int nsys, hipStream_t s) {
+    k_s_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(n, 3 * (size_t)n, k);
+}
+
+void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, hipStream_t s) {
+    k_spmv<SPMV_T><<<dim3(row_blocks(d.n), nsys), kRowThreads, 0, s>>>(
+        d.n, d.prow, d.pcol, Ap, a_stride, k.shat, k.t, 3 * (size_t)d.n, k.s, nullptr, k.part, k.part_stride, k.st);
+}
+
+void launch_xr_update(int n, Krylov &k, int nsys, hipStream_t s) {
+    k_xr_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(n, 3 * (size_t)n, k);
+}
+
+void launch_permute_vec(const int32_t *perm, const double *in, double *out, int n, int nsys, bool scatter,
+                        hipStream_t s) {
+    if (n <= 0 || nsys <= 0) return;
+    k_permute_vec<<<dim3(copy_blocks(3 * (size_t)n), nsys), 256, 0, s>>>(perm, in, out, n, 3 * (size_t)n,
+                                                                         scatter ? 1 : 0);
+}
+
+void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *colidx, const double *A,
+                   size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, hipStream_t s) {
+    if (d.n <= 0 || nsys <= 0) return;
+    launch_permute_vec(d.perm, k.x, x_orig, d.n, nsys, true, s);
+    k_spmv<SPMV_TRUE><<<dim3(row_blocks(d.n), nsys), kRowThreads, 0, s>>>(
+        d.n, rowptr, colidx, A, a_stride, x_orig, nullptr, 3 * (size_t)d.n, b_orig, nullptr, k.part, k.part_stride,
+        k.st);
+}
+
+}  // namespace rs

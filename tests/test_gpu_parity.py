@@ -1,0 +1,327 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances: ILU0 factors within 1e-12 relative (per block row, max-norm of
+the difference over the max-norm of the factor) under the same ordering;
+solutions within 1e-8 relative 2-norm at a reduction of 1e-10 with equal
+half-step counts.  SpMV and the preconditioner apply have no stated bound:
+both sides sum the same terms in the same order, the GPU contracting
+multiply-adds into FMAs, so each entry may differ by a few units of
+eps * (|A| |x|)_i; the tests allow 1e-13 of that.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2309_11488_amd as rs
+from synth import config_system, make_ensemble, make_grid_system
+from tests.helpers import chain_pattern, dense_pattern, random_values
+
+pytestmark = pytest.mark.gpu
+
+ORDERINGS = [rs.ORDER_NATURAL, rs.ORDER_LEVEL_SET, rs.ORDER_GRAPH_COLOUR]
+
+
+def cases():
+    out = {
+        "c1": config_system("c1"),
+        "nnc": make_grid_system(17, 13, 9, active_frac=0.85, nnc_frac=0.03, seed=4, sigma=2.0),
+        "thin": make_grid_system(1, 1, 200, seed=5),
+        "ragged": make_grid_system(5, 17, 1, seed=6),     # 85 rows: one full tile + 1
+        "one": make_grid_system(1, 1, 1, seed=7),
+    }
+    return out
+
+
+CASES = cases()
+
+
+def oracle_factors(s, ordering, vals=None):
+    vals = s.vals[0] if vals is None else vals
+    perm = oracle.ordering_perm(s.rowptr, s.colidx, ordering)
+    prow, pcol, pv = oracle.permute(s.rowptr, s.colidx, vals, perm)
+    st, bad, lu, dinv = oracle.ilu0(prow, pcol, pv)
+    return perm, prow, pcol, pv, st, bad, lu, dinv
+
+
+def rel_block_err(a, b):
+    """max over block rows of ||a - b||_inf, over max ||b||_inf."""
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.fixture
+def solver_of():
+    made = []
+
+    def make(s, ordering, precision=rs.PREC_FP64, vals=None):
+        v = s.vals if vals is None else vals
+        A = rs.bcsr_create(s.rowptr, s.colidx, v)
+        M = rs.ilu0_analyse(A, ordering)
+        made.append((A, M))
+        st, bad = rs.ilu0_factor(M, A, precision)
+        return A, M, st, bad
+
+    yield make
+    for A, M in made:
+        rs.ilu0_destroy(M)
+        rs.bcsr_destroy(A)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_spmv_parity(name):
+    s = CASES[name]
+    A = rs.bcsr_create(s.rowptr, s.colidx, s.vals)
+    try:
+        x = np.random.default_rng(1).standard_normal((1, s.n, 3))
+        y = rs.bcsr_spmv(A, x)
+        yo = oracle.spmv(s.rowptr, s.colidx, s.vals[0], x[0])
+        ax = oracle.spmv(s.rowptr, s.colidx, np.abs(s.vals[0]), np.abs(x[0]))
+        assert np.all(np.abs(y[0] - yo) <= 1e-13 * ax + 1e-300)
+    finally:
+        rs.bcsr_destroy(A)
+
+
+def test_spmv_batch_and_sizes():
+    s = make_ensemble(9, 10, 3, seeds=[1, 2, 3])
+    A = rs.bcsr_create(s.rowptr, s.colidx, s.vals)
+    try:
+        x = np.random.default_rng(2).standard_normal((3, s.n, 3))
+        y = rs.bcsr_spmv(A, x)
+        for k in range(3):
+            yo = oracle.spmv(s.rowptr, s.colidx, s.vals[k], x[k])
+            assert np.abs(y[k] - yo).max() <= 1e-13 * np.abs(yo).max()
+        y2 = rs.bcsr_spmv(A, x[1:2], first_sys=1, n_sys=1)
+        assert np.array_equal(y2[0], y[1])
+    finally:
+        rs.bcsr_destroy(A)
+
+
+@pytest.mark.parametrize("ordering", ORDERINGS)
+@pytest.mark.parametrize("name", list(CASES))
+def test_schedule_matches_oracle(solver_of, name, ordering):
+    s = CASES[name]
+    A, M, st, _ = solver_of(s, ordering)
+    perm, ns, sp = rs.ilu0_get_schedule(M, s.n)
+    assert np.array_equal(perm, oracle.ordering_perm(s.rowptr, s.colidx, ordering))
+
+
+@pytest.mark.parametrize("ordering", ORDERINGS)
+@pytest.mark.parametrize("name", list(CASES))
+def test_factor_parity(solver_of, name, ordering):
+    s = CASES[name]
+    A, M, st, bad = solver_of(s, ordering)
+    assert st == rs.OK and bad[0] == -1
+    perm, prow, pcol, pv, ost, obad, lu, dinv = oracle_factors(s, ordering)
+    assert ost == oracle.OK
+    glu, gdinv = rs.ilu0_get_factors(M, 0, s.n, s.nnzb)
+    offd = np.array([pcol[p] != i for i in range(s.n) for p in range(prow[i], prow[i + 1])], bool)
+    if offd.any():
+        assert rel_block_err(glu[offd], lu[offd]) <= 1e-12
+    assert rel_block_err(gdinv, dinv) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [2, 6])
+def test_factor_parity_dense_pattern(solver_of, n):
+    rowptr, colidx = dense_pattern(n)
+    vals = random_values(rowptr, colidx, seed=n)
+
+    class S:
+        pass
+    s = S()
+    s.rowptr, s.colidx, s.vals, s.n, s.nnzb = rowptr, colidx, vals[None], n, len(colidx)
+    A, M, st, _ = solver_of(s, rs.ORDER_NATURAL)
+    assert st == rs.OK
+    _, _, lu, dinv = oracle.ilu0(rowptr, colidx, vals)
+    glu, gdinv = rs.ilu0_get_factors(M, 0, n, len(colidx))
+    offd = colidx != np.repeat(np.arange(n), n)
+    assert rel_block_err(glu[offd], lu[offd]) <= 1e-12
+    assert rel_block_err(gdinv, dinv) <= 1e-12
+
+
+@pytest.mark.parametrize("ordering", ORDERINGS)
+@pytest.mark.parametrize("name", ["c1", "nnc", "ragged"])
+@pytest.mark.parametrize("precision", [rs.PREC_FP64, rs.PREC_FP32_FACTORS])
+def test_apply_parity(solver_of, name, ordering, precision):
+    s = CASES[name]
+    A, M, st, _ = solver_of(s, ordering, precision)
+    v = np.random.default_rng(3).standard_normal((1, s.n, 3))
+    z = rs.ilu0_apply(M, v)
+    perm, prow, pcol, pv, _, _, lu, dinv = oracle_factors(s, ordering)
+    f = oracle.apply if precision == rs.PREC_FP64 else oracle.apply_f32
+    zp = f(prow, pcol, lu, dinv, v[0][perm])
+    zo = np.empty_like(zp)
+    zo[perm] = zp
+    tol = 1e-12 if precision == rs.PREC_FP64 else 1e-5
+    assert np.linalg.norm(z[0] - zo) <= tol * np.linalg.norm(zo)
+
+
+def test_fp32_factors_are_rounded_fp64_factors(solver_of):
+    s = CASES["nnc"]
+    A, M, st, _ = solver_of(s, rs.ORDER_LEVEL_SET, rs.PREC_FP32_FACTORS)
+    _, prow, pcol, _, _, _, lu, dinv = oracle_factors(s, rs.ORDER_LEVEL_SET)
+    glu, gdinv = rs.ilu0_get_factors(M, 0, s.n, s.nnzb)
+    offd = np.array([pcol[p] != i for i in range(s.n) for p in range(prow[i], prow[i + 1])], bool)
+    for g, o in ((glu[offd], lu[offd]), (gdinv, dinv)):
+        o32 = o.astype(np.float32)
+        ulp = np.spacing(np.abs(o32)).astype(np.float64)
+        assert np.all(np.abs(g - o32.astype(np.float64)) <= ulp)
+
+
+@pytest.mark.parametrize("ordering", ORDERINGS)
+@pytest.mark.parametrize("name", ["c1", "nnc", "thin", "ragged", "one"])
+def test_solve_parity_tight(solver_of, name, ordering):
+    s = CASES[name]
+    A, M, st, _ = solver_of(s, ordering)
+    b = s.b[0, 0]
+    x, st, info = rs.bicgstab_solve(M, A, b[None], reduction=1e-10)
+    xo, oinfo = oracle.solve(s.rowptr, s.colidx, s.vals[0], b, ordering=ordering, reduction=1e-10)
+    assert st == rs.OK and info[0]["status"] == rs.OK
+    assert np.linalg.norm(x[0] - xo) <= 1e-8 * np.linalg.norm(xo)
+    hs, ohs = info[0]["half_steps"], oinfo["half_steps"]
+    near = abs(oinfo["final_norm"] - 1e-10 * oinfo["r0_norm"]) <= 1e-3 * 1e-10 * oinfo["r0_norm"]
+    assert hs == ohs or (abs(hs - ohs) == 1 and near)
+    assert info[0]["true_rel_residual"] <= 1e-9
+    assert abs(info[0]["r0_norm"] - oinfo["r0_norm"]) <= 1e-13 * oinfo["r0_norm"]
+
+
+@pytest.mark.parametrize("precision", [rs.PREC_FP64, rs.PREC_FP32_FACTORS])
+@pytest.mark.parametrize("red", [1e-2, 1e-6])
+def test_solve_reduction_and_true_residual(solver_of, precision, red):
+    s = CASES["nnc"]
+    A, M, st, _ = solver_of(s, rs.ORDER_LEVEL_SET, precision)
+    x, st, info = rs.bicgstab_solve(M, A, s.b[0], reduction=red)
+    oprec = oracle.PREC_ILU_F64 if precision == rs.PREC_FP64 else oracle.PREC_ILU_F32
+    xo, oinfo = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=rs.ORDER_LEVEL_SET,
+                             precond=oprec, reduction=red)
+    assert st == rs.OK
+    assert info[0]["final_norm"] <= red * info[0]["r0_norm"]
+    assert info[0]["true_rel_residual"] <= red * (1 + 1e-6)
+    assert abs(info[0]["half_steps"] - oinfo["half_steps"]) <= 1
+    xt = oracle.spmv(s.rowptr, s.colidx, s.vals[0], x[0])
+    assert np.linalg.norm(s.b[0, 0] - xt) / np.linalg.norm(s.b[0, 0]) <= red * (1 + 1e-6)
+
+
+def test_batch_members_equal_alone(solver_of):
+    s = make_ensemble(12, 10, 6, seeds=[11, 12, 13, 14])
+    A, M, st, _ = solver_of(s, rs.ORDER_LEVEL_SET, rs.PREC_FP32_FACTORS)
+    assert st == rs.OK
+    xb, stb, infob = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-6)
+    for k in range(4):
+        class S1:
+            pass
+        one = S1()
+        one.rowptr, one.colidx, one.vals, one.n, one.nnzb = s.rowptr, s.colidx, s.vals[k:k + 1], s.n, s.nnzb
+        A1, M1, _, _ = solver_of(one, rs.ORDER_LEVEL_SET, rs.PREC_FP32_FACTORS)
+        x1, st1, info1 = rs.bicgstab_solve(M1, A1, s.b[k:k + 1, 0], reduction=1e-6)
+        assert np.array_equal(x1[0], xb[k])
+        assert info1[0]["half_steps"] == infob[k]["half_steps"]
+
+
+def test_repeat_solve_bitwise(solver_of):
+    s = CASES["nnc"]
+    A, M, _, _ = solver_of(s, rs.ORDER_GRAPH_COLOUR)
+    x1, _, i1 = rs.bicgstab_solve(M, A, s.b[0], reduction=1e-8)
+    x2, _, i2 = rs.bicgstab_solve(M, A, s.b[0], reduction=1e-8)
+    assert np.array_equal(x1, x2) and i1 == i2
+
+
+def test_status_paths(solver_of):
+    s = CASES["c1"]
+    A, M, st, _ = solver_of(s, rs.ORDER_LEVEL_SET)
+    b = s.b[0]
+    x, st, info = rs.bicgstab_solve(M, A, np.zeros_like(b))
+    assert st == rs.OK and info[0]["half_steps"] == 0 and not x.any()
+    bn = b.copy()
+    bn[0, 7, 2] = np.nan
+    x, st, info = rs.bicgstab_solve(M, A, bn)
+    assert st == rs.NON_FINITE
+    x, st, info = rs.bicgstab_solve(M, A, b, reduction=1e-12, max_iter=1)
+    assert st == rs.NOT_CONVERGED and info[0]["half_steps"] == 2
+    xo, oinfo = oracle.solve(s.rowptr, s.colidx, s.vals[0], b[0], ordering=rs.ORDER_LEVEL_SET, reduction=1e-12,
+                             max_iter=1)
+    assert np.linalg.norm(x[0] - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+def test_zero_pivot_reports_oracle_row(solver_of):
+    s = CASES["c1"]
+    vz = s.vals.copy()
+    row = 1234
+    for p in range(s.rowptr[row], s.rowptr[row + 1]):
+        if s.colidx[p] <= row:
+            vz[0, p] = 0.0
+    for ordering in ORDERINGS:
+        A, M, st, bad = solver_of(s, ordering, vals=vz)
+        _, oinfo = oracle.solve(s.rowptr, s.colidx, vz[0], s.b[0, 0], ordering=ordering)
+        assert st == rs.ZERO_PIVOT and oinfo["status"] == oracle.ZERO_PIVOT
+        assert bad[0] == oinfo["bad_row"]
+        x, sst, info = rs.bicgstab_solve(M, A, s.b[0])
+        assert sst == rs.ZERO_PIVOT
+
+
+def test_handle_errors(solver_of):
+    s = CASES["c1"]
+    A = rs.bcsr_create(s.rowptr, s.colidx, s.vals)
+    M = rs.ilu0_analyse(A, rs.ORDER_LEVEL_SET)
+    try:
+        with pytest.raises(rs.RsolveError) as e:
+            rs.bicgstab_solve(M, A, s.b[0])
+        assert e.value.status == rs.NOT_FACTORED
+        other = CASES["nnc"]
+        B = rs.bcsr_create(other.rowptr, other.colidx, other.vals)
+        with pytest.raises(rs.RsolveError) as e:
+            rs.ilu0_factor(M, B)
+        assert e.value.status == rs.PATTERN_MISMATCH
+        rs.bcsr_destroy(B)
+        bad_cols = s.colidx.copy()
+        bad_cols[[0, 1]] = bad_cols[[1, 0]]
+        with pytest.raises(rs.RsolveError) as e:
+            rs.bcsr_create(s.rowptr, bad_cols, s.vals)
+        assert e.value.status == rs.BAD_PATTERN and e.value.bad_row == 0
+    finally:
+        rs.ilu0_destroy(M)
+        rs.bcsr_destroy(A)
+
+
+def test_device_memory_path():
+    torch = pytest.importorskip("torch")
+    s = CASES["nnc"]
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(s.rowptr).to(dev)
+    ci = torch.from_numpy(s.colidx).to(dev)
+    vals = torch.from_numpy(s.vals).to(dev)
+    b = torch.from_numpy(s.b[:, 0].copy()).to(dev)
+    x = torch.zeros_like(b)
+    A = rs.bcsr_create(rp, ci, vals)
+    M = rs.ilu0_analyse(A, rs.ORDER_GRAPH_COLOUR)
+    try:
+        rs.ilu0_factor(M, A)
+        rs.bicgstab_solve(M, A, b, x, reduction=1e-10)
+        torch.cuda.synchronize()
+        xo, _ = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=rs.ORDER_GRAPH_COLOUR,
+                             reduction=1e-10)
+        xg = x.cpu().numpy()[0]
+        assert np.linalg.norm(xg - xo) <= 1e-8 * np.linalg.norm(xo)
+    finally:
+        rs.ilu0_destroy(M)
+        rs.bcsr_destroy(A)
+
+
+@pytest.mark.parametrize("ordering", [rs.ORDER_GRAPH_COLOUR, rs.ORDER_LEVEL_SET])
+def test_c2_full_size_parity(solver_of, ordering):
+    """The 46x112x22 masked grid with 2% NNCs at full size: factors on sampled
+    rows, and the solution at 1e-10 for the first right-hand side."""
+    s = config_system("c2", n_rhs=2)
+    A, M, st, _ = solver_of(s, ordering)
+    assert st == rs.OK
+    perm, prow, pcol, pv, ost, _, lu, dinv = oracle_factors(s, ordering)
+    glu, gdinv = rs.ilu0_get_factors(M, 0, s.n, s.nnzb)
+    assert rel_block_err(gdinv, dinv) <= 1e-12
+    offd = np.repeat(np.arange(s.n), np.diff(prow)) != pcol
+    assert rel_block_err(glu[offd], lu[offd]) <= 1e-12
+    x, st, info = rs.bicgstab_solve(M, A, s.b[0, :1], reduction=1e-10)
+    xo, oinfo = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=ordering, reduction=1e-10)
+    assert st == rs.OK
+    assert np.linalg.norm(x[0] - xo) <= 1e-8 * np.linalg.norm(xo)
+    assert abs(info[0]["half_steps"] - oinfo["half_steps"]) <= 1
+    x, st, info = rs.bicgstab_solve(M, A, s.b[0, 1:2], reduction=1e-2)
+    assert st == rs.OK and info[0]["true_rel_residual"] <= 1e-2
