@@ -170,6 +170,19 @@ int ilu0_destroy(ilu0_t M);
 int ilu0_analyse_host(int32_t n_brows, const int32_t *row_ptr, const int32_t *col_idx, int32_t ordering,
                       int32_t *perm, int32_t *n_sets, int32_t *bad_row);
 
+/* rsolve_profile_enable -- time classes of kernel work with HIP events
+ * recorded on the launch stream (bit c of mask enables class c:
+ * 0 = one ILU0 factorisation, 1 = one lower sweep, 2 = one upper sweep,
+ * 3 = one SpMV launch inside the solve, 4 = one vector-update launch).
+ * Resets the counters.  Process-wide, not thread-safe; 0 disables. */
+int rsolve_profile_enable(int32_t mask);
+
+/* rsolve_profile_get -- accumulated device milliseconds, units timed and
+ * algorithmic bytes moved (the bytes the method must read and write, not
+ * cache traffic) of class `cls` since the last enable (host outputs, may be
+ * NULL).  Waits for pending events. */
+int rsolve_profile_get(int32_t cls, double *ms, int64_t *units, double *bytes);
+
 const char *rsolve_status_string(int status);
 const char *rsolve_last_error(void);
 

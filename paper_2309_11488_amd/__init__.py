@@ -28,8 +28,10 @@ MEM_HOST, MEM_DEVICE = 0, 1
 EXPORTS = (
     "bcsr_create", "bcsr_set_values", "bcsr_get_dims", "bcsr_spmv", "bcsr_destroy", "ilu0_analyse",
     "ilu0_get_schedule", "ilu0_get_sweep_levels", "ilu0_factor", "ilu0_get_factors", "ilu0_apply",
-    "bicgstab_solve", "ilu0_destroy", "ilu0_analyse_host", "rsolve_status_string", "rsolve_last_error",
+    "bicgstab_solve", "ilu0_destroy", "ilu0_analyse_host", "rsolve_profile_enable", "rsolve_profile_get",
+    "rsolve_status_string", "rsolve_last_error",
 )
+PROF_FACTOR, PROF_LSWEEP, PROF_USWEEP, PROF_SPMV, PROF_VEC = 0, 1, 2, 3, 4
 
 
 class SolveInfo(ct.Structure):
@@ -80,6 +82,8 @@ def lib():
         L.bicgstab_solve.argtypes = [vp, vp, vp, vp, dbl, i32, i32, vp, vp]
         L.ilu0_destroy.argtypes = [vp]
         L.ilu0_analyse_host.argtypes = [i32, vp, vp, i32, vp, P(i32), P(i32)]
+        L.rsolve_profile_enable.argtypes = [i32]
+        L.rsolve_profile_get.argtypes = [i32, P(dbl), P(ct.c_int64), P(dbl)]
         L.rsolve_status_string.argtypes = [ct.c_int]
         L.rsolve_status_string.restype = ct.c_char_p
         L.rsolve_last_error.restype = ct.c_char_p
@@ -274,6 +278,17 @@ def ilu0_analyse_host(rowptr, colidx, ordering=ORDER_LEVEL_SET):
     st = lib().ilu0_analyse_host(n, rowptr.ctypes.data, colidx.ctypes.data, ordering, perm.ctypes.data,
                                  ct.byref(ns), ct.byref(bad))
     return st, perm[:n], ns.value, bad.value
+
+
+def rsolve_profile_enable(mask):
+    return _check(lib().rsolve_profile_enable(int(mask)), "rsolve_profile_enable")
+
+
+def rsolve_profile_get(cls):
+    """(device ms, units, algorithmic bytes) accumulated for a kernel class."""
+    ms, units, byt = ct.c_double(), ct.c_int64(), ct.c_double()
+    _check(lib().rsolve_profile_get(int(cls), ct.byref(ms), ct.byref(units), ct.byref(byt)), "rsolve_profile_get")
+    return ms.value, units.value, byt.value
 
 
 # ------------------------------------------------------------ convenience

@@ -52,7 +52,9 @@ struct DevBuf {
         if (p) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
-        if (b == 0) b = 16;
+        // 64 spare bytes: row kernels copy whole 16-byte units into LDS and
+        // may read up to 15 bytes past the last block of an array
+        b += 64;
         hipError_t e = hipMalloc(&p, b);
         if (e == hipSuccess) bytes = b;
         return e;
@@ -64,6 +66,70 @@ hipError_t upload(DevBuf &buf, const std::vector<int32_t> &v) {
     hipError_t e = buf.alloc(v.size() * sizeof(int32_t));
     if (e != hipSuccess || v.empty()) return e;
     return hipMemcpy(buf.p, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+}
+
+// Optional per-class kernel timing with HIP events recorded on the launch
+// stream around each unit of work (a kernel launch, or a whole sweep).
+// Process-wide and not thread-safe; off unless enabled.
+enum ProfClass { PC_FACTOR = 0, PC_LSWEEP = 1, PC_USWEEP = 2, PC_SPMV = 3, PC_VEC = 4, PC_COUNT = 5 };
+
+struct Prof {
+    int mask = 0;
+    double ms[PC_COUNT] = {}, bytes[PC_COUNT] = {};
+    long long units[PC_COUNT] = {};
+    struct Pending {
+        int cls;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+};
+Prof g_prof;
+
+hipEvent_t prof_event() {
+    hipEvent_t e = nullptr;
+    if (!g_prof.pool.empty()) {
+        e = g_prof.pool.back();
+        g_prof.pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+    }
+    return e;
+}
+
+struct ProfScope {
+    int cls;
+    hipStream_t s;
+    double bytes;
+    hipEvent_t a = nullptr;
+    ProfScope(int c, hipStream_t st, double b) : cls(c), s(st), bytes(b) {
+        if ((g_prof.mask >> cls) & 1) {
+            a = prof_event();
+            if (a) (void)hipEventRecord(a, s);
+        }
+    }
+    ~ProfScope() {
+        if (!a) return;
+        hipEvent_t b = prof_event();
+        if (!b) return;
+        (void)hipEventRecord(b, s);
+        g_prof.pending.push_back({cls, a, b, bytes});
+    }
+};
+
+void prof_flush() {
+    for (auto &p : g_prof.pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            g_prof.ms[p.cls] += ms;
+            g_prof.units[p.cls] += 1;
+            g_prof.bytes[p.cls] += p.bytes;
+        }
+        g_prof.pool.push_back(p.a);
+        g_prof.pool.push_back(p.b);
+    }
+    g_prof.pending.clear();
 }
 
 }  // namespace
@@ -336,15 +402,25 @@ int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *ba
     M->factored = false;
     HIP_TRY(hipMemsetAsync(M->bad.p, 0x7f, B * sizeof(int32_t), s));
     const size_t per = (size_t)M->nnzb * 9;
-    rs::launch_gather_blocks(A->vals.as<double>(), per, M->pvals.as<double>(), per, M->dev.psrc, M->nnzb,
-                             M->batch, s);
-    for (int l = 0; l < S.nl_levels; ++l)
-        rs::launch_factor_level(M->dev, M->pvals.as<double>(), M->L.as<double>(), M->U.as<double>(),
-                                M->Dinv.as<double>(), M->bad.as<int32_t>(), S.lset[l], S.lset[l + 1], M->batch, s);
-    if (precision == RS_PREC_FP32_FACTORS) {
-        rs::launch_to_fp32(M->L.as<double>(), M->Lf.as<float>(), B * S.nL * 9, s);
-        rs::launch_to_fp32(M->U.as<double>(), M->Uf.as<float>(), B * S.nU * 9, s);
-        rs::launch_to_fp32(M->Dinv.as<double>(), M->Dinvf.as<float>(), B * M->n * 9, s);
+    {
+        // reordered copy of A (read, index, write), then the factor: A' read,
+        // L/U/inv(U_ii) written, index and update lists read (FP32 copies:
+        // FP64 factors read again, FP32 written)
+        const double nnzb = M->nnzb, n = M->n;
+        double bytes = 148 * nnzb + 72 * nnzb + 72 * nnzb + 4 * (3.0 * S.nL + 2.0 * S.nU + 3 * n) + 4.0 * S.upd.size();
+        if (precision == RS_PREC_FP32_FACTORS) bytes += 108 * nnzb;
+        ProfScope ps(PC_FACTOR, s, B * bytes);
+        rs::launch_gather_blocks(A->vals.as<double>(), per, M->pvals.as<double>(), per, M->dev.psrc, M->nnzb,
+                                 M->batch, s);
+        for (int l = 0; l < S.nl_levels; ++l)
+            rs::launch_factor_level(M->dev, M->pvals.as<double>(), M->L.as<double>(), M->U.as<double>(),
+                                    M->Dinv.as<double>(), M->bad.as<int32_t>(), S.lset[l], S.lset[l + 1], M->batch,
+                                    s);
+        if (precision == RS_PREC_FP32_FACTORS) {
+            rs::launch_to_fp32(M->L.as<double>(), M->Lf.as<float>(), B * S.nL * 9, s);
+            rs::launch_to_fp32(M->U.as<double>(), M->Uf.as<float>(), B * S.nU * 9, s);
+            rs::launch_to_fp32(M->Dinv.as<double>(), M->Dinvf.as<float>(), B * M->n * 9, s);
+        }
     }
     HIP_TRY(hipGetLastError());
     M->bad_host.assign(B, 0);
@@ -391,11 +467,14 @@ int ilu0_get_factors(ilu0_t M, int32_t sys, double *lu, double *dinv) {
 }
 
 static int ensure_workspace(ilu0_t M) {
-    const size_t B = (size_t)M->batch, m = 3 * (size_t)M->n;
-    const size_t vec = std::max<size_t>(B * m, 1);
-    HIP_TRY(M->work.alloc(9 * vec * sizeof(double)));
+    const size_t B = (size_t)M->batch, vs = rs::vec_stride(M->n);
+    const size_t vec = std::max<size_t>(B * vs, 1);
+    if (!M->work.p) {
+        HIP_TRY(M->work.alloc(9 * vec * sizeof(double)));
+        HIP_TRY(hipMemset(M->work.p, 0, 9 * vec * sizeof(double)));  // padding stays zero
+    }
     HIP_TRY(M->ywork.alloc(vec * sizeof(double)));
-    const size_t pstride = 2 * (size_t)std::max(rs::row_blocks(std::max(M->n, 1)), rs::vec_blocks(M->n));
+    const size_t pstride = 2 * (size_t)std::max(rs::row_blocks(std::max(M->n, 1)), rs::kVecMaxBlocks);
     if (!M->part.p || M->k.part_stride != pstride) HIP_TRY(M->part.alloc(B * pstride * sizeof(double)));
     if (!M->state.p) {
         HIP_TRY(M->state.alloc(B * sizeof(SysState)));
@@ -406,6 +485,7 @@ static int ensure_workspace(ilu0_t M) {
     Krylov &k = M->k;
     k.r = w; k.rhat = w + vec; k.p = w + 2 * vec; k.v = w + 3 * vec; k.phat = w + 4 * vec;
     k.s = w + 5 * vec; k.shat = w + 6 * vec; k.t = w + 7 * vec; k.x = w + 8 * vec;
+    k.vstride = vs;
     k.y = M->ywork.p;
     k.part = M->part.as<double>();
     k.part_stride = pstride;
@@ -420,14 +500,26 @@ template <typename T>
 static void apply_levels(ilu0_t M, const T *L, const T *U, const T *D, const double *in, double *out, bool fuse_p,
                          Krylov &k, SysState *st, int nsys, hipStream_t s) {
     const rs::Schedule &S = M->sch;
-    const size_t vs = 3 * (size_t)M->n;
+    const size_t vs = k.vstride;
+    const double n = M->n, tb = sizeof(T), B = nsys;
     T *y = (T *)k.y;
-    for (int l = 0; l < S.nl_levels; ++l)
-        rs::launch_lsweep<T>(M->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, S.lset[l],
-                             S.lset[l + 1], nsys, s);
-    for (int l = 0; l < S.nu_levels; ++l)
-        rs::launch_usweep<T>(M->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, S.uset[l],
-                             S.uset[l + 1], nsys, s);
+    {
+        // L blocks + column indices, row pointers and row list, the input
+        // (r, p, v read and p written when fused), y written once
+        const double bytes = B * ((9 * tb + 4) * S.nL + 8 * n + (fuse_p ? 96 : 24) * n + 3 * tb * n);
+        ProfScope ps(PC_LSWEEP, s, bytes);
+        for (int l = 0; l < S.nl_levels; ++l)
+            rs::launch_lsweep<T>(M->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, S.lset[l],
+                                 S.lset[l + 1], nsys, s);
+    }
+    {
+        // U blocks + indices, inv(U_ii), row pointers and row list, y read, z written
+        const double bytes = B * ((9 * tb + 4) * S.nU + 9 * tb * n + 8 * n + 3 * tb * n + 24 * n);
+        ProfScope ps(PC_USWEEP, s, bytes);
+        for (int l = 0; l < S.nu_levels; ++l)
+            rs::launch_usweep<T>(M->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, S.uset[l],
+                                 S.uset[l + 1], nsys, s);
+    }
 }
 
 template <typename T>
@@ -435,12 +527,16 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
     Krylov &k = M->k;
     const int B = M->batch;
     const size_t per = (size_t)M->nnzb * 9;
+    const double n = M->n, nnzb = M->nnzb;
+    // values + column indices, row pointers, x gathered once, y written, one
+    // more vector read by the fused dot product
+    const double spmv_bytes = B * (76 * nnzb + 4 * n + 72 * n);
     apply_levels<T>(M, L, U, D, nullptr, k.phat, true, k, k.st, B, s);
-    rs::launch_spmv_v(M->dev, M->pvals.as<double>(), per, k, B, s);
-    rs::launch_s_update(M->n, k, B, s);
+    { ProfScope ps(PC_SPMV, s, spmv_bytes); rs::launch_spmv_v(M->dev, M->pvals.as<double>(), per, k, B, s); }
+    { ProfScope ps(PC_VEC, s, B * 72 * n); rs::launch_s_update(M->n, k, B, s); }
     apply_levels<T>(M, L, U, D, k.s, k.shat, false, k, k.st, B, s);
-    rs::launch_spmv_t(M->dev, M->pvals.as<double>(), per, k, B, s);
-    rs::launch_xr_update(M->n, k, B, s);
+    { ProfScope ps(PC_SPMV, s, spmv_bytes); rs::launch_spmv_t(M->dev, M->pvals.as<double>(), per, k, B, s); }
+    { ProfScope ps(PC_VEC, s, B * 192 * n); rs::launch_xr_update(M->n, k, B, s); }
 }
 
 static void enqueue_iteration_any(ilu0_t M, hipStream_t s) {
@@ -471,7 +567,7 @@ int ilu0_apply(ilu0_t M, const double *v, double *z, int32_t first_sys, int32_t 
     }
     Krylov &k = M->k;
     const rs::Schedule &S = M->sch;
-    rs::launch_permute_vec(M->dev.perm, vd, k.s, M->n, n_sys, false, s);
+    rs::launch_permute_vec(M->dev.perm, vd, k.s, M->n, k.vstride, n_sys, false, s);
     if (M->precision == RS_PREC_FP32_FACTORS)
         apply_levels<float>(M, M->Lf.as<float>() + (size_t)first_sys * S.nL * 9,
                             M->Uf.as<float>() + (size_t)first_sys * S.nU * 9,
@@ -482,7 +578,7 @@ int ilu0_apply(ilu0_t M, const double *v, double *z, int32_t first_sys, int32_t 
                              M->U.as<double>() + (size_t)first_sys * S.nU * 9,
                              M->Dinv.as<double>() + (size_t)first_sys * M->n * 9, k.s, k.shat, false, k, nullptr,
                              n_sys, s);
-    rs::launch_permute_vec(M->dev.perm, k.shat, zd, M->n, n_sys, true, s);
+    rs::launch_permute_vec(M->dev.perm, k.shat, zd, M->n, k.vstride, n_sys, true, s);
     HIP_TRY(hipGetLastError());
     if (mem != RS_MEM_DEVICE) {
         HIP_TRY(hipMemcpyAsync(z, zd, m * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -524,7 +620,10 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
         xd = M->xstage.as<double>();
     }
     Krylov &k = M->k;
-    rs::launch_setup(M->dev, bd, M->bad.as<int32_t>(), reduction, max_iter, k, B, s);
+    {
+        ProfScope ps(PC_VEC, s, (double)B * 152 * M->n);
+        rs::launch_setup(M->dev, bd, M->bad.as<int32_t>(), reduction, max_iter, k, B, s);
+    }
     int done_iters = 0;
     while (done_iters < max_iter) {
         const int c = std::min(M->chunk, max_iter - done_iters);
@@ -550,6 +649,26 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
         if (status_rank(S.status) > status_rank(worst)) worst = S.status;
     }
     return worst;
+}
+
+int rsolve_profile_enable(int32_t mask) {
+    prof_flush();
+    g_prof.mask = mask;
+    for (int c = 0; c < PC_COUNT; ++c) {
+        g_prof.ms[c] = 0.0;
+        g_prof.bytes[c] = 0.0;
+        g_prof.units[c] = 0;
+    }
+    return RS_OK;
+}
+
+int rsolve_profile_get(int32_t cls, double *ms, int64_t *units, double *bytes) {
+    if (cls < 0 || cls >= PC_COUNT) return fail(RS_INVALID_ARG, "rsolve_profile_get: unknown class");
+    prof_flush();
+    if (ms) *ms = g_prof.ms[cls];
+    if (units) *units = g_prof.units[cls];
+    if (bytes) *bytes = g_prof.bytes[cls];
+    return RS_OK;
 }
 
 int ilu0_destroy(ilu0_t M) {

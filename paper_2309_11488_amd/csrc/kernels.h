@@ -30,9 +30,12 @@ struct DevSchedule {
     const int32_t *urows, *uptr, *ucol, *usrc, *dsrc;
 };
 
-// Workspace vectors of one solve, each nsys * 3n long in the new order.
+// Workspace vectors of one solve in the new order: system k's vector starts
+// at k * vstride; vstride is 3n rounded up to whole vector tiles and the
+// padding holds zeros, so the vector kernels run without bounds checks.
 struct Krylov {
     double *r, *rhat, *p, *v, *phat, *s, *shat, *t, *x;
+    size_t vstride;
     void *y;            // lower-sweep intermediate, FP64 or FP32 (factor type)
     double *part;       // reduction partials, nsys * part_stride
     size_t part_stride;
@@ -45,12 +48,14 @@ constexpr int kRowsPerWave = 21;                            // 3 lanes per block
 constexpr int kWavesPerBlock = 4;
 constexpr int kRowsPerBlock = kRowsPerWave * kWavesPerBlock;  // 84 block rows per workgroup
 constexpr int kRowThreads = kWave * kWavesPerBlock;           // 256
-constexpr int kStageBlocks = 448;                           // 3x3 blocks staged in LDS per pass
 constexpr int kVecThreads = 256;
-constexpr int kVecMaxBlocks = 1024;
+constexpr int kVecItems = 4;                                // entries per thread per tile
+constexpr int kVecTile = kVecThreads * kVecItems;           // 1024 entries
+constexpr int kVecMaxBlocks = 2048;
 
 inline int row_blocks(int rows) { return (rows + kRowsPerBlock - 1) / kRowsPerBlock; }
-int vec_blocks(int n);  // workgroups of the vector kernels for 3n entries
+inline size_t vec_stride(int n) { return (3 * (size_t)n + kVecTile - 1) / kVecTile * kVecTile; }
+int vec_blocks(int n);  // workgroups of the vector kernels for one padded vector
 
 // A'[p] = A[src[p]] for every system (blocks of 9 doubles).
 void launch_gather_blocks(const double *A, size_t a_stride, double *Ap, size_t ap_stride, const int32_t *src,
@@ -93,8 +98,9 @@ void launch_xr_update(int n, Krylov &k, int nsys, hipStream_t s);
 void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *colidx, const double *A,
                    size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, hipStream_t s);
 
-// out[i] = in[perm[i]] (gather to the new order) and its inverse scatter.
-void launch_permute_vec(const int32_t *perm, const double *in, double *out, int n, int nsys, bool scatter,
-                        hipStream_t s);
+// out[i] = in[perm[i]] (gather to the new order) and its inverse scatter;
+// the new-order side has stride vstride, the caller side 3n.
+void launch_permute_vec(const int32_t *perm, const double *in, double *out, int n, size_t vstride, int nsys,
+                        bool scatter, hipStream_t s);
 
 }  // namespace rs

@@ -61,6 +61,13 @@ __device__ inline void block_sum(double (&v)[NV], double *lds) {
 
 // Deterministic grid reduction.  Returns true in the last workgroup to
 // finish, where thread 0's v[] holds the grid total.
+//
+// Each workgroup stores its partials with agent-scope atomic stores (they
+// are written through to the coherence point, so no L2 writeback of the
+// whole XCD cache is needed), waits until they have completed, then takes a
+// ticket with an agent-scope atomic add.  The workgroup that draws the last
+// ticket reads all partials with agent-scope atomic loads and adds them in
+// block order.  The ticket is reset for the next reduction on this system.
 template <int NV>
 __device__ bool grid_reduce(double (&v)[NV], double *part, uint32_t *ticket, int nblk, int bx) {
     __shared__ double lds[16 * NV];
@@ -69,18 +76,31 @@ __device__ bool grid_reduce(double (&v)[NV], double *part, uint32_t *ticket, int
     if (threadIdx.x == 0) {
         for (int k = 0; k < NV; ++k)
             __hip_atomic_store(part + (size_t)bx * NV + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         last = (t == (uint32_t)(nblk - 1));
     }
     __syncthreads();
     if (!last) return false;
-    __threadfence();
     double acc[NV];
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-        for (int k = 0; k < NV; ++k)
-            acc[k] += __hip_atomic_load(part + (size_t)b * NV + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    constexpr int U = 8;
+    for (int b0 = 0; b0 < nblk; b0 += U * (int)blockDim.x) {
+        double t[U][NV];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = b0 + u * blockDim.x + threadIdx.x;
+            for (int k = 0; k < NV; ++k)
+                t[u][k] = b < nblk ? __hip_atomic_load(part + (size_t)b * NV + k, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT)
+                                   : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            for (int k = 0; k < NV; ++k) acc[k] += t[u][k];
+    }
     block_sum<NV>(acc, lds);
     if (threadIdx.x == 0) {
         for (int k = 0; k < NV; ++k) v[k] = acc[k];
@@ -109,26 +129,77 @@ __device__ inline RowLane row_lane(int bx, int q0, int q1) {
     return L;
 }
 
-// Walk the blocks of this lane's row, staged through LDS pass by pass.
-// acc (+|-)= sum_c val[e][r][c] * x[3 col[e] + c] per block, blocks ascending.
+// LDS image of up to CAP consecutive 3x3 blocks and their column indices.
+// Values are copied in aligned 16-byte units; `shift` is the offset (in
+// elements) of the first block inside the first unit.
+template <typename T, int CAP>
+struct Stage {
+    static constexpr int kUnits = (CAP * 9 * (int)sizeof(T) + 15) / 16 + 1;
+    static constexpr int kPerThread = (kUnits + kRowThreads - 1) / kRowThreads;
+    static constexpr int kColsPerThread = (CAP + kRowThreads - 1) / kRowThreads;
+    uint4 v[kUnits];
+    int32_t c[CAP];
+};
+
+// Copy blocks [base, base + cnt) of val and col into LDS.  Every thread
+// issues all of its loads before any LDS store.  Load and store indices are
+// clamped into range instead of branched on (threads past the end rewrite
+// the last unit with the same data), so the compiler cannot sink a load
+// into a branch and serialise the copy.  Reads stay inside the 16-byte
+// units that overlap the range (allocations are padded for that).
+template <typename T, int CAP>
+__device__ inline int stage_copy(const T *__restrict__ val, const int32_t *__restrict__ col, int base, int cnt,
+                                 Stage<T, CAP> &st) {
+    using S = Stage<T, CAP>;
+    const char *first = (const char *)(val + (size_t)base * 9);
+    const int mis = (int)((uintptr_t)first & 15);
+    const uint4 *src = (const uint4 *)(first - mis);
+    const int units = (mis + cnt * 9 * (int)sizeof(T) + 15) / 16;
+    uint4 t[S::kPerThread];
+#pragma unroll
+    for (int u = 0; u < S::kPerThread; ++u) t[u] = src[min(u * kRowThreads + (int)threadIdx.x, units - 1)];
+    int32_t c[S::kColsPerThread];
+#pragma unroll
+    for (int u = 0; u < S::kColsPerThread; ++u) c[u] = col[base + min(u * kRowThreads + (int)threadIdx.x, cnt - 1)];
+#pragma unroll
+    for (int u = 0; u < S::kPerThread; ++u) st.v[min(u * kRowThreads + (int)threadIdx.x, units - 1)] = t[u];
+#pragma unroll
+    for (int u = 0; u < S::kColsPerThread; ++u) st.c[min(u * kRowThreads + (int)threadIdx.x, cnt - 1)] = c[u];
+    return mis / (int)sizeof(T);
+}
+
+// Walk the blocks of this lane's row, staged through LDS pass by pass:
+// acc (+|-)= sum_c val[e][r][c] * x[3 col[e] + c] per block, blocks
+// ascending.  The x entries of up to 8 blocks are gathered before use.
 template <int CAP, bool SUB, typename T, typename TX>
 __device__ inline T stage_walk(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
                                const T *__restrict__ val, int qb0, int qb1, const RowLane &L, const TX *__restrict__ x,
-                               T acc, T *sv) {
+                               T acc, Stage<T, CAP> &st) {
     const int e0 = ptr[qb0], e1 = ptr[qb1];
     const int my0 = L.act ? ptr[L.q] : 0, my1 = L.act ? ptr[L.q + 1] : 0;
+    const T *sv = (const T *)st.v;
     for (int base = e0; base < e1; base += CAP) {
         const int cnt = min(CAP, e1 - base);
         __syncthreads();
-        const T *src = val + (size_t)base * 9;
-        for (int i = threadIdx.x; i < cnt * 9; i += blockDim.x) sv[i] = src[i];
+        const int shift = stage_copy<T, CAP>(val, col, base, cnt, st);
         __syncthreads();
         const int lo = max(my0, base), hi = min(my1, base + cnt);
-        for (int e = lo; e < hi; ++e) {
-            const int j = col[e];
-            const T *b = sv + (e - base) * 9 + 3 * L.r;
-            const T s = b[0] * (T)x[3 * j] + b[1] * (T)x[3 * j + 1] + b[2] * (T)x[3 * j + 2];
-            if (SUB) acc -= s; else acc += s;
+        for (int e = lo; e < hi; e += 8) {
+            TX xv[8][3];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = st.c[min(e + u, hi - 1) - base];
+                xv[u][0] = x[3 * j];
+                xv[u][1] = x[3 * j + 1];
+                xv[u][2] = x[3 * j + 2];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (e + u < hi) {
+                    const T *b = sv + shift + (e + u - base) * 9 + 3 * L.r;
+                    const T s = b[0] * (T)xv[u][0] + b[1] * (T)xv[u][1] + b[2] * (T)xv[u][2];
+                    if (SUB) acc -= s; else acc += s;
+                }
         }
     }
     return acc;
@@ -235,7 +306,7 @@ __global__ void __launch_bounds__(kRowThreads) k_lsweep(DevSchedule d, const T *
                                                         size_t vstride, const double *__restrict__ rv,
                                                         const double *__restrict__ vv, double *__restrict__ pv,
                                                         SysState *__restrict__ st, int q0, int q1) {
-    __shared__ T sv[kSweepCap * 9];
+    __shared__ Stage<T, kSweepCap> sv;
     int sys, bx;
     xcd_map(sys, bx);
     if (st && st[sys].phase != PH_RUN) return;
@@ -264,7 +335,7 @@ __global__ void __launch_bounds__(kRowThreads) k_usweep(DevSchedule d, const T *
                                                         const T *__restrict__ Dinv, size_t d_stride,
                                                         const T *__restrict__ y, double *__restrict__ z,
                                                         size_t vstride, SysState *__restrict__ st, int q0, int q1) {
-    __shared__ T sv[kSweepCap * 9];
+    __shared__ Stage<T, kSweepCap> sv;
     int sys, bx;
     xcd_map(sys, bx);
     if (st && st[sys].phase != PH_RUN) return;
@@ -297,7 +368,7 @@ __global__ void __launch_bounds__(kRowThreads) k_spmv(int n, const int32_t *__re
                                                       const double *__restrict__ w1, const double *__restrict__ w2,
                                                       double *__restrict__ part, size_t part_stride,
                                                       SysState *__restrict__ st) {
-    __shared__ double sv[kSpmvCap * 9];
+    __shared__ Stage<double, kSpmvCap> sv;
     int sys, bx;
     xcd_map(sys, bx);
     if (MODE != SPMV_PLAIN && MODE != SPMV_TRUE && st[sys].phase != PH_RUN) return;
@@ -344,19 +415,34 @@ __global__ void __launch_bounds__(kRowThreads) k_spmv(int n, const int32_t *__re
 
 // ---------------------------------------------------------------- vectors
 
-// r = rhat = P b, x = p = v = 0, ||b||; initial scalars.
+// Vector kernels: each thread handles kVecItems entries of a 1024-entry
+// tile, all loads of a tile issued before the arithmetic; tiles are
+// grid-strided.  Vectors are padded to whole tiles with zeros, so there are
+// no bounds checks (the padding contributes zeros to every reduction).
+
+// r = rhat = P b, x = p = v = 0 (padding included), ||b||; initial scalars.
 __global__ void __launch_bounds__(kVecThreads) k_setup(int n, const int32_t *__restrict__ perm,
-                                                       const double *__restrict__ b, size_t vstride, Krylov k,
+                                                       const double *__restrict__ b, Krylov k,
                                                        const int32_t *__restrict__ bad, double reduction,
                                                        int max_iter) {
     const int sys = blockIdx.y, bx = blockIdx.x;
-    const size_t vo = (size_t)sys * vstride, m = 3 * (size_t)n;
+    const size_t vo = (size_t)sys * k.vstride, bo = (size_t)sys * 3 * n, m = 3 * (size_t)n;
+    const size_t tiles = k.vstride / kVecTile;
     double v[1] = {0.0};
-    for (size_t e = (size_t)bx * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
-        const double val = b[vo + 3 * (size_t)perm[e / 3] + e % 3];
-        k.r[vo + e] = val; k.rhat[vo + e] = val;
-        k.x[vo + e] = 0.0; k.p[vo + e] = 0.0; k.v[vo + e] = 0.0;
-        v[0] += val * val;
+    for (size_t t = bx; t < tiles; t += gridDim.x) {
+        double val[kVecItems];
+#pragma unroll
+        for (int u = 0; u < kVecItems; ++u) {
+            const size_t e = t * kVecTile + u * kVecThreads + threadIdx.x;
+            val[u] = e < m ? b[bo + 3 * (size_t)perm[e / 3] + e % 3] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kVecItems; ++u) {
+            const size_t e = vo + t * kVecTile + u * kVecThreads + threadIdx.x;
+            k.r[e] = val[u]; k.rhat[e] = val[u];
+            k.x[e] = 0.0; k.p[e] = 0.0; k.v[e] = 0.0;
+            v[0] += val[u] * val[u];
+        }
     }
     if (grid_reduce<1>(v, k.part + sys * k.part_stride, &k.st[sys].ticket, gridDim.x, bx) && threadIdx.x == 0) {
         SysState &S = k.st[sys];
@@ -374,17 +460,24 @@ __global__ void __launch_bounds__(kVecThreads) k_setup(int n, const int32_t *__r
 }
 
 // s = r - alpha v, ||s||; half-step test.
-__global__ void __launch_bounds__(kVecThreads) k_s_update(int n, size_t vstride, Krylov k) {
+__global__ void __launch_bounds__(kVecThreads) k_s_update(Krylov k) {
     const int sys = blockIdx.y, bx = blockIdx.x;
     SysState &S = k.st[sys];
     if (S.phase != PH_RUN) return;
     const double alpha = S.alpha;
-    const size_t vo = (size_t)sys * vstride, m = 3 * (size_t)n;
+    const size_t vo = (size_t)sys * k.vstride, tiles = k.vstride / kVecTile;
     double v[1] = {0.0};
-    for (size_t e = (size_t)bx * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
-        const double s = k.r[vo + e] - alpha * k.v[vo + e];
-        k.s[vo + e] = s;
-        v[0] += s * s;
+    for (size_t t = bx; t < tiles; t += gridDim.x) {
+        const size_t e0 = vo + t * kVecTile + threadIdx.x;
+        double r[kVecItems], w[kVecItems];
+#pragma unroll
+        for (int u = 0; u < kVecItems; ++u) { r[u] = k.r[e0 + u * kVecThreads]; w[u] = k.v[e0 + u * kVecThreads]; }
+#pragma unroll
+        for (int u = 0; u < kVecItems; ++u) {
+            const double sv = r[u] - alpha * w[u];
+            k.s[e0 + u * kVecThreads] = sv;
+            v[0] += sv * sv;
+        }
     }
     if (grid_reduce<1>(v, k.part + sys * k.part_stride, &S.ticket, gridDim.x, bx) && threadIdx.x == 0) {
         const double sn = sqrt(v[0]);
@@ -398,25 +491,39 @@ __global__ void __launch_bounds__(kVecThreads) k_s_update(int n, size_t vstride,
 // Full step: x += alpha phat + omega shat, r = s - omega t, ||r||, (rhat, r),
 // full-step test, next rho and beta.  After a half-step stop (or an omega
 // breakdown) only x += alpha phat.
-__global__ void __launch_bounds__(kVecThreads) k_xr_update(int n, size_t vstride, Krylov k) {
+__global__ void __launch_bounds__(kVecThreads) k_xr_update(Krylov k) {
     const int sys = blockIdx.y, bx = blockIdx.x;
     SysState &S = k.st[sys];
     const int phase = S.phase;
     if (phase == PH_DONE) return;
     const double alpha = S.alpha, omega = S.omega;
-    const size_t vo = (size_t)sys * vstride, m = 3 * (size_t)n;
+    const size_t vo = (size_t)sys * k.vstride, tiles = k.vstride / kVecTile;
     double v[2] = {0.0, 0.0};
-    if (phase == PH_HALF) {
-        for (size_t e = (size_t)bx * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x)
-            k.x[vo + e] += alpha * k.phat[vo + e];
-    } else {
-        for (size_t e = (size_t)bx * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
-            const size_t t = vo + e;
-            k.x[t] += alpha * k.phat[t] + omega * k.shat[t];
-            const double r = k.s[t] - omega * k.t[t];
-            k.r[t] = r;
-            v[0] += r * r;
-            v[1] += k.rhat[t] * r;
+    for (size_t t = bx; t < tiles; t += gridDim.x) {
+        const size_t e0 = vo + t * kVecTile + threadIdx.x;
+        if (phase == PH_HALF) {
+            double xv[kVecItems], ph[kVecItems];
+#pragma unroll
+            for (int u = 0; u < kVecItems; ++u) { xv[u] = k.x[e0 + u * kVecThreads]; ph[u] = k.phat[e0 + u * kVecThreads]; }
+#pragma unroll
+            for (int u = 0; u < kVecItems; ++u) k.x[e0 + u * kVecThreads] = xv[u] + alpha * ph[u];
+        } else {
+            double xv[kVecItems], ph[kVecItems], sh[kVecItems], sv[kVecItems], tv[kVecItems], rh[kVecItems];
+#pragma unroll
+            for (int u = 0; u < kVecItems; ++u) {
+                const size_t e = e0 + u * kVecThreads;
+                xv[u] = k.x[e]; ph[u] = k.phat[e]; sh[u] = k.shat[e];
+                sv[u] = k.s[e]; tv[u] = k.t[e]; rh[u] = k.rhat[e];
+            }
+#pragma unroll
+            for (int u = 0; u < kVecItems; ++u) {
+                const size_t e = e0 + u * kVecThreads;
+                k.x[e] = xv[u] + (alpha * ph[u] + omega * sh[u]);
+                const double r = sv[u] - omega * tv[u];
+                k.r[e] = r;
+                v[0] += r * r;
+                v[1] += rh[u] * r;
+            }
         }
     }
     if (grid_reduce<2>(v, k.part + sys * k.part_stride, &S.ticket, gridDim.x, bx) && threadIdx.x == 0) {
@@ -439,22 +546,22 @@ __global__ void __launch_bounds__(kVecThreads) k_xr_update(int n, size_t vstride
     }
 }
 
+// New-order side at stride vstride, caller side at stride 3n.
 __global__ void k_permute_vec(const int32_t *__restrict__ perm, const double *__restrict__ in,
                               double *__restrict__ out, int n, size_t vstride, int scatter) {
     const int sys = blockIdx.y;
-    const size_t vo = (size_t)sys * vstride, m = 3 * (size_t)n;
+    const size_t vo = (size_t)sys * vstride, m = 3 * (size_t)n, co = (size_t)sys * m;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (size_t)gridDim.x * blockDim.x) {
-        const size_t o = 3 * (size_t)perm[e / 3] + e % 3;
-        if (scatter) out[vo + o] = in[vo + e];
-        else out[vo + e] = in[vo + o];
+        const size_t o = co + 3 * (size_t)perm[e / 3] + e % 3;
+        if (scatter) out[o] = in[vo + e];
+        else out[vo + e] = in[o];
     }
 }
 
 }  // namespace
 
 int vec_blocks(int n) {
-    const long m = 3L * n;
-    long g = (m + kVecThreads * 4 - 1) / (kVecThreads * 4);
+    long g = (long)(vec_stride(n) / kVecTile);
     if (g < 1) g = 1;
     if (g > kVecMaxBlocks) g = kVecMaxBlocks;
     return (int)g;
@@ -521,39 +628,38 @@ void launch_spmv(int n, const int32_t *ptr, const int32_t *col, const double *A,
 
 void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad, double reduction, int max_iter,
                   Krylov &k, int nsys, hipStream_t s) {
-    k_setup<<<dim3(vec_blocks(d.n), nsys), kVecThreads, 0, s>>>(d.n, d.perm, b_orig, 3 * (size_t)d.n, k, bad,
-                                                               reduction, max_iter);
+    k_setup<<<dim3(vec_blocks(d.n), nsys), kVecThreads, 0, s>>>(d.n, d.perm, b_orig, k, bad, reduction, max_iter);
 }
 
 void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, hipStream_t s) {
     k_spmv<SPMV_V><<<dim3(row_blocks(d.n), nsys), kRowThreads, 0, s>>>(
-        d.n, d.prow, d.pcol, Ap, a_stride, k.phat, k.v, 3 * (size_t)d.n, k.rhat, nullptr, k.part, k.part_stride, k.st);
+        d.n, d.prow, d.pcol, Ap, a_stride, k.phat, k.v, k.vstride, k.rhat, nullptr, k.part, k.part_stride, k.st);
 }
 
 void launch_s_update(int n, Krylov &k, int nsys, hipStream_t s) {
-    k_s_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(n, 3 * (size_t)n, k);
+    k_s_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(k);
 }
 
 void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, hipStream_t s) {
     k_spmv<SPMV_T><<<dim3(row_blocks(d.n), nsys), kRowThreads, 0, s>>>(
-        d.n, d.prow, d.pcol, Ap, a_stride, k.shat, k.t, 3 * (size_t)d.n, k.s, nullptr, k.part, k.part_stride, k.st);
+        d.n, d.prow, d.pcol, Ap, a_stride, k.shat, k.t, k.vstride, k.s, nullptr, k.part, k.part_stride, k.st);
 }
 
 void launch_xr_update(int n, Krylov &k, int nsys, hipStream_t s) {
-    k_xr_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(n, 3 * (size_t)n, k);
+    k_xr_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(k);
 }
 
-void launch_permute_vec(const int32_t *perm, const double *in, double *out, int n, int nsys, bool scatter,
-                        hipStream_t s) {
+void launch_permute_vec(const int32_t *perm, const double *in, double *out, int n, size_t vstride, int nsys,
+                        bool scatter, hipStream_t s) {
     if (n <= 0 || nsys <= 0) return;
-    k_permute_vec<<<dim3(copy_blocks(3 * (size_t)n), nsys), 256, 0, s>>>(perm, in, out, n, 3 * (size_t)n,
+    k_permute_vec<<<dim3(copy_blocks(3 * (size_t)n), nsys), 256, 0, s>>>(perm, in, out, n, vstride,
                                                                          scatter ? 1 : 0);
 }
 
 void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *colidx, const double *A,
                    size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, hipStream_t s) {
     if (d.n <= 0 || nsys <= 0) return;
-    launch_permute_vec(d.perm, k.x, x_orig, d.n, nsys, true, s);
+    launch_permute_vec(d.perm, k.x, x_orig, d.n, k.vstride, nsys, true, s);
     k_spmv<SPMV_TRUE><<<dim3(row_blocks(d.n), nsys), kRowThreads, 0, s>>>(
         d.n, rowptr, colidx, A, a_stride, x_orig, nullptr, 3 * (size_t)d.n, b_orig, nullptr, k.part, k.part_stride,
         k.st);
