@@ -42,7 +42,7 @@ WORKLOADS = {
 }
 ORDER = {"natural": 0, "level": 1, "colour": 2}
 PREC = {"fp64": 0, "fp32": 1}
-CLASS = {"factor": 0, "lsweep": 1, "usweep": 2, "spmv": 3, "vec": 4}
+CLASS = {"factor": 0, "lsweep": 1, "usweep": 2, "spmv": 3, "vec": 4, "spmv_t": 5}
 
 
 def log(*a):
@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--roofline", default="spmv", choices=sorted(CLASS))
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the run, copy a MIB-sized buffer with torch (a kernel of known traffic, "
+                         "used to scale rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -165,6 +168,9 @@ def main():
                     true_res.append(i["true_rel_residual"])
                     statuses.append(i["status"])
 
+    # the profiled configuration is captured into the iteration graph during
+    # warm-up; enabling again with the same mask only clears the counters
+    rs.rsolve_profile_enable(1 << CLASS[args.roofline])
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -204,6 +210,13 @@ def main():
 
     rs.ilu0_destroy(M)
     rs.bcsr_destroy(A)
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibrate_copy} MiB read + {args.calibrate_copy} MiB written, 3 times")
     out = {
         "metric": "BiCGStab-ILU0 solves/sec at 1e-2 reduction (HBM GB/s vs roofline of the dominant kernel)",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -70,6 +70,17 @@ enum rs_ordering { RS_ORDER_NATURAL = 0, RS_ORDER_LEVEL_SET = 1, RS_ORDER_GRAPH_
 enum rs_precision { RS_PREC_FP64 = 0, RS_PREC_FP32_FACTORS = 1 };
 enum rs_mem { RS_MEM_HOST = 0, RS_MEM_DEVICE = 1 };
 
+/* Execution options of an ilu0_t (ilu0_set_option).  They change how the
+ * work is launched, never the arithmetic or its order. */
+enum rs_option {
+    RS_OPT_SWEEP_TILES = 0,  /* 1: one launch per triangular sweep, row tiles wait only on the
+                                tiles they depend on; 0: one launch per level.  Default: 0 for
+                                graph colouring (few wide levels), 1 otherwise */
+    RS_OPT_SWEEP_GRID = 1,   /* workgroups of a single-launch sweep (default 1024) */
+    RS_OPT_POLL_CHUNK = 2,   /* BiCGStab iterations queued between host polls of convergence (default 1) */
+    RS_OPT_USE_GRAPH = 3     /* 1 (default): an iteration is captured once as a HIP graph and replayed */
+};
+
 /* Per-system outcome of bicgstab_solve. */
 typedef struct {
     int32_t status;            /* rs_status of this system */
@@ -130,6 +141,11 @@ int ilu0_get_schedule(ilu0_t M, int32_t *perm, int32_t *n_sets, int32_t *set_ptr
  * schedules the device executes (host outputs, may be NULL). */
 int ilu0_get_sweep_levels(ilu0_t M, int32_t *n_lower, int32_t *n_upper);
 
+/* ilu0_set_option / ilu0_get_option -- read or change an rs_option of the
+ * handle.  RS_INVALID_ARG for an unknown option or a value out of range. */
+int ilu0_set_option(ilu0_t M, int32_t option, int32_t value);
+int ilu0_get_option(ilu0_t M, int32_t option, int32_t *value);
+
 /* ilu0_factor -- block ILU0 (Algorithm 2) of every system of A in the
  * analysed order, levels ascending.  precision RS_PREC_FP64 keeps FP64
  * factors; RS_PREC_FP32_FACTORS computes them in FP64 and stores them
@@ -173,7 +189,8 @@ int ilu0_analyse_host(int32_t n_brows, const int32_t *row_ptr, const int32_t *co
 /* rsolve_profile_enable -- time classes of kernel work with HIP events
  * recorded on the launch stream (bit c of mask enables class c:
  * 0 = one ILU0 factorisation, 1 = one lower sweep, 2 = one upper sweep,
- * 3 = one SpMV launch inside the solve, 4 = one vector-update launch).
+ * 3 = one v = A phat launch, 4 = one vector-update launch, 5 = one
+ * t = A shat launch).
  * Resets the counters.  Process-wide, not thread-safe; 0 disables. */
 int rsolve_profile_enable(int32_t mask);
 

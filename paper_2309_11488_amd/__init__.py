@@ -24,14 +24,15 @@ ZERO_PIVOT, NON_FINITE, OUT_OF_MEMORY, HIP_ERROR, PATTERN_MISMATCH, NOT_FACTORED
 ORDER_NATURAL, ORDER_LEVEL_SET, ORDER_GRAPH_COLOUR = 0, 1, 2
 PREC_FP64, PREC_FP32_FACTORS = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
+OPT_SWEEP_TILES, OPT_SWEEP_GRID, OPT_POLL_CHUNK, OPT_USE_GRAPH = 0, 1, 2, 3
 
 EXPORTS = (
     "bcsr_create", "bcsr_set_values", "bcsr_get_dims", "bcsr_spmv", "bcsr_destroy", "ilu0_analyse",
-    "ilu0_get_schedule", "ilu0_get_sweep_levels", "ilu0_factor", "ilu0_get_factors", "ilu0_apply",
+    "ilu0_get_schedule", "ilu0_get_sweep_levels", "ilu0_set_option", "ilu0_get_option", "ilu0_factor", "ilu0_get_factors", "ilu0_apply",
     "bicgstab_solve", "ilu0_destroy", "ilu0_analyse_host", "rsolve_profile_enable", "rsolve_profile_get",
     "rsolve_status_string", "rsolve_last_error",
 )
-PROF_FACTOR, PROF_LSWEEP, PROF_USWEEP, PROF_SPMV, PROF_VEC = 0, 1, 2, 3, 4
+PROF_FACTOR, PROF_LSWEEP, PROF_USWEEP, PROF_SPMV_V, PROF_VEC, PROF_SPMV_T = 0, 1, 2, 3, 4, 5
 
 
 class SolveInfo(ct.Structure):
@@ -76,6 +77,8 @@ def lib():
         L.ilu0_analyse.argtypes = [vp, i32, P(vp)]
         L.ilu0_get_schedule.argtypes = [vp, vp, P(i32), vp]
         L.ilu0_get_sweep_levels.argtypes = [vp, P(i32), P(i32)]
+        L.ilu0_set_option.argtypes = [vp, i32, i32]
+        L.ilu0_get_option.argtypes = [vp, i32, P(i32)]
         L.ilu0_factor.argtypes = [vp, vp, i32, vp, vp]
         L.ilu0_get_factors.argtypes = [vp, i32, vp, vp]
         L.ilu0_apply.argtypes = [vp, vp, vp, i32, i32, i32, vp]
@@ -222,6 +225,16 @@ def ilu0_get_sweep_levels(M):
     a, b = ct.c_int32(), ct.c_int32()
     _check(lib().ilu0_get_sweep_levels(M, ct.byref(a), ct.byref(b)), "ilu0_get_sweep_levels")
     return a.value, b.value
+
+
+def ilu0_set_option(M, option, value):
+    return _check(lib().ilu0_set_option(M, int(option), int(value)), "ilu0_set_option")
+
+
+def ilu0_get_option(M, option):
+    v = ct.c_int32()
+    _check(lib().ilu0_get_option(M, int(option), ct.byref(v)), "ilu0_get_option")
+    return v.value
 
 
 def ilu0_factor(M, A, precision=PREC_FP64, *, stream=None):

@@ -121,7 +121,33 @@ int make_ordering(int n, const int32_t *rowptr, const int32_t *colidx, int order
     return make_ordering(n, rowptr, colidx, ordering, perm, sp);
 }
 
-int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx, int ordering, Schedule &s) {
+// Split every level into tiles of at most R rows and collect each tile's
+// dependencies (the tiles owning the rows its blocks reference).
+static void make_tiles(int n, int nlev, const std::vector<int32_t> &lev_ptr, int R, const std::vector<int32_t> &ptr,
+                       const std::vector<int32_t> &col, const std::vector<int32_t> &pos_of_row, Schedule::Tiles &t) {
+    t.start.clear();
+    for (int l = 0; l < nlev; ++l)
+        for (int q = lev_ptr[l]; q < lev_ptr[l + 1]; q += R) t.start.push_back(q);
+    t.n = (int)t.start.size();
+    t.start.push_back(n);
+    std::vector<int32_t> tile_of(n);
+    for (int k = 0; k < t.n; ++k)
+        for (int q = t.start[k]; q < t.start[k + 1]; ++q) tile_of[q] = k;
+    t.dep_ptr.assign(t.n + 1, 0);
+    t.dep.clear();
+    std::vector<int32_t> d;
+    for (int k = 0; k < t.n; ++k) {
+        d.clear();
+        for (int e = ptr[t.start[k]]; e < ptr[t.start[k + 1]]; ++e) d.push_back(tile_of[pos_of_row[col[e]]]);
+        std::sort(d.begin(), d.end());
+        d.erase(std::unique(d.begin(), d.end()), d.end());
+        t.dep.insert(t.dep.end(), d.begin(), d.end());
+        t.dep_ptr[k + 1] = (int32_t)t.dep.size();
+    }
+}
+
+int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx, int ordering, Schedule &s,
+                   int tile_rows) {
     s = Schedule();
     s.n = n;
     s.nnzb = nnzb;
@@ -220,6 +246,11 @@ int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx
             s.upd_ptr[e + 1] = (int32_t)(s.upd.size() / 2);
         }
     }
+
+    std::vector<int32_t> lpos(n);
+    for (int q = 0; q < n; ++q) lpos[s.lrows[q]] = q;
+    make_tiles(n, s.nl_levels, s.lset, tile_rows, s.lptr, s.lcol, lpos, s.ltiles);
+    make_tiles(n, s.nu_levels, s.uset, tile_rows, s.uptr, s.ucol, upos, s.utiles);
     return RS_OK;
 }
 

@@ -45,8 +45,18 @@ struct Schedule {
     // 4 * position + kind, kind 0 = L block, 1 = diagonal of the row, 2 = U block.
     std::vector<int32_t> upd_ptr, upd;
     int max_lrow = 0, max_urow = 0;
+    // row tiles of the single-launch sweeps: tile t covers schedule
+    // positions [start[t], start[t+1]) inside one level, and must wait for
+    // the tiles dep[dep_ptr[t] .. dep_ptr[t+1]) (earlier tiles holding rows
+    // that its rows read)
+    struct Tiles {
+        int n = 0;
+        std::vector<int32_t> start, dep_ptr, dep;
+    } ltiles, utiles;
 };
 
-int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx, int ordering, Schedule &s);
+// tile_rows: rows per sweep tile (a multiple of the rows one workgroup covers).
+int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx, int ordering, Schedule &s,
+                   int tile_rows);
 
 }  // namespace rs

@@ -68,10 +68,15 @@ hipError_t upload(DevBuf &buf, const std::vector<int32_t> &v) {
     return hipMemcpy(buf.p, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice);
 }
 
-// Optional per-class kernel timing with HIP events recorded on the launch
-// stream around each unit of work (a kernel launch, or a whole sweep).
 // Process-wide and not thread-safe; off unless enabled.
-enum ProfClass { PC_FACTOR = 0, PC_LSWEEP = 1, PC_USWEEP = 2, PC_SPMV = 3, PC_VEC = 4, PC_COUNT = 5 };
+// Optional per-class kernel timing with HIP events recorded on the launch
+// stream around each unit of work (a kernel launch, or a whole sweep).  The
+// SpMV classes are split so that v = A phat, which runs in every launched
+// iteration, can be timed apart from t = A shat, which exits early in an
+// iteration that stopped at its half step.
+enum ProfClass {
+    PC_FACTOR = 0, PC_LSWEEP = 1, PC_USWEEP = 2, PC_SPMV_V = 3, PC_VEC = 4, PC_SPMV_T = 5, PC_COUNT = 6
+};
 
 struct Prof {
     int mask = 0;
@@ -147,17 +152,43 @@ struct rs_ilu0 {
     rs::Schedule sch;
     DevSchedule dev{};
     DevBuf perm, prow, pcol, psrc, lrows, lptr, lcol, lsrc, ldq, l2u, upd_ptr, upd, urows, uptr, ucol, usrc, dsrc;
+    DevBuf lt_start, lt_dptr, lt_dep, ut_start, ut_dptr, ut_dep;
     // factors
     int precision = -1;
     bool factored = false;
     DevBuf pvals, L, U, Dinv, Lf, Uf, Dinvf, bad;
     std::vector<int32_t> bad_host;
     // solve workspace
-    DevBuf work, ywork, part, state, bstage, xstage;
+    DevBuf work, ywork, part, state, bstage, xstage, flags, ctrs;
     Krylov k{};
     SysState *h_state = nullptr;
+    rs::SweepCtr *h_ctr = nullptr;
     int chunk = 1;
-    ~rs_ilu0() { if (h_state) (void)hipHostFree(h_state); }
+    bool tile_sweeps = true;   // single-launch sweeps (else one launch per level)
+    int sweep_grid = 1024;     // workgroups of a single-launch sweep
+    // a BiCGStab iteration captured as HIP graphs, replayed on the caller's
+    // stream: segment 0 = the whole iteration; 1 and 2 = the parts before and
+    // after v = A phat, used while that kernel is being timed with events
+    bool use_graph = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph[3] = {};
+    hipGraphExec_t gexec[3] = {};
+    long long graph_key[3] = {-1, -1, -1};
+    void drop_graph() {
+        for (int i = 0; i < 3; ++i) {
+            if (gexec[i]) (void)hipGraphExecDestroy(gexec[i]);
+            if (graph[i]) (void)hipGraphDestroy(graph[i]);
+            gexec[i] = nullptr;
+            graph[i] = nullptr;
+            graph_key[i] = -1;
+        }
+    }
+    ~rs_ilu0() {
+        drop_graph();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (h_state) (void)hipHostFree(h_state);
+        if (h_ctr) (void)hipHostFree(h_ctr);
+    }
 };
 
 static int read_pattern(int32_t n, int32_t nnzb, const int32_t *row_ptr, const int32_t *col_idx, int32_t mem,
@@ -329,7 +360,7 @@ int ilu0_analyse(bcsr_t A, int32_t ordering, ilu0_t *out) {
     M->nnzb = A->nnzb;
     M->batch = A->batch;
     M->hash = A->hash;
-    rs::build_schedule(A->n, A->nnzb, A->h_rowptr.data(), A->h_colidx.data(), ordering, M->sch);
+    rs::build_schedule(A->n, A->nnzb, A->h_rowptr.data(), A->h_colidx.data(), ordering, M->sch, rs::kRowsPerBlock);
     const rs::Schedule &S = M->sch;
     hipError_t e = hipSuccess;
     struct Up { DevBuf *b; const std::vector<int32_t> *v; } ups[] = {
@@ -337,7 +368,9 @@ int ilu0_analyse(bcsr_t A, int32_t ordering, ilu0_t *out) {
         {&M->lrows, &S.lrows}, {&M->lptr, &S.lptr}, {&M->lcol, &S.lcol}, {&M->lsrc, &S.lsrc},
         {&M->ldq, &S.ldq}, {&M->l2u, &S.l2u}, {&M->upd_ptr, &S.upd_ptr}, {&M->upd, &S.upd},
         {&M->urows, &S.urows}, {&M->uptr, &S.uptr}, {&M->ucol, &S.ucol}, {&M->usrc, &S.usrc},
-        {&M->dsrc, &S.dsrc}};
+        {&M->dsrc, &S.dsrc}, {&M->lt_start, &S.ltiles.start}, {&M->lt_dptr, &S.ltiles.dep_ptr},
+        {&M->lt_dep, &S.ltiles.dep}, {&M->ut_start, &S.utiles.start}, {&M->ut_dptr, &S.utiles.dep_ptr},
+        {&M->ut_dep, &S.utiles.dep}};
     for (auto &u : ups)
         if ((e = upload(*u.b, *u.v)) != hipSuccess) break;
     if (e != hipSuccess) {
@@ -353,7 +386,11 @@ int ilu0_analyse(bcsr_t A, int32_t ordering, ilu0_t *out) {
     d.l2u = M->l2u.as<int32_t>(); d.upd_ptr = M->upd_ptr.as<int32_t>(); d.upd = M->upd.as<int32_t>();
     d.urows = M->urows.as<int32_t>(); d.uptr = M->uptr.as<int32_t>(); d.ucol = M->ucol.as<int32_t>();
     d.usrc = M->usrc.as<int32_t>(); d.dsrc = M->dsrc.as<int32_t>();
-    if (const char *c = std::getenv("RSOLVE_CHUNK")) M->chunk = std::max(1, std::atoi(c));
+    d.nlt = S.ltiles.n; d.nut = S.utiles.n;
+    // few, wide colours: one launch per colour; many thin levels: one launch per sweep
+    M->tile_sweeps = ordering != RS_ORDER_GRAPH_COLOUR;
+    d.lt_start = M->lt_start.as<int32_t>(); d.lt_dptr = M->lt_dptr.as<int32_t>(); d.lt_dep = M->lt_dep.as<int32_t>();
+    d.ut_start = M->ut_start.as<int32_t>(); d.ut_dptr = M->ut_dptr.as<int32_t>(); d.ut_dep = M->ut_dep.as<int32_t>();
     *out = M;
     return RS_OK;
 }
@@ -371,6 +408,42 @@ int ilu0_get_sweep_levels(ilu0_t M, int32_t *n_lower, int32_t *n_upper) {
     if (n_lower) *n_lower = M->sch.nl_levels;
     if (n_upper) *n_upper = M->sch.nu_levels;
     return RS_OK;
+}
+
+int ilu0_set_option(ilu0_t M, int32_t option, int32_t value) {
+    if (!M) return fail(RS_INVALID_ARG, "ilu0_set_option: NULL handle");
+    switch (option) {
+    case RS_OPT_SWEEP_TILES:
+        if (value != 0 && value != 1) break;
+        M->tile_sweeps = value != 0;
+        return RS_OK;
+    case RS_OPT_SWEEP_GRID:
+        if (value < 1) break;
+        M->sweep_grid = value;
+        return RS_OK;
+    case RS_OPT_POLL_CHUNK:
+        if (value < 1) break;
+        M->chunk = value;
+        return RS_OK;
+    case RS_OPT_USE_GRAPH:
+        if (value != 0 && value != 1) break;
+        M->use_graph = value != 0;
+        return RS_OK;
+    default:
+        break;
+    }
+    return fail(RS_INVALID_ARG, "ilu0_set_option: unknown option or bad value");
+}
+
+int ilu0_get_option(ilu0_t M, int32_t option, int32_t *value) {
+    if (!M || !value) return fail(RS_INVALID_ARG, "ilu0_get_option: bad arguments");
+    switch (option) {
+    case RS_OPT_SWEEP_TILES: *value = M->tile_sweeps ? 1 : 0; return RS_OK;
+    case RS_OPT_SWEEP_GRID: *value = M->sweep_grid; return RS_OK;
+    case RS_OPT_POLL_CHUNK: *value = M->chunk; return RS_OK;
+    case RS_OPT_USE_GRAPH: *value = M->use_graph ? 1 : 0; return RS_OK;
+    default: return fail(RS_INVALID_ARG, "ilu0_get_option: unknown option");
+    }
 }
 
 static int check_pair(ilu0_t M, bcsr_t A) {
@@ -480,6 +553,12 @@ static int ensure_workspace(ilu0_t M) {
         HIP_TRY(M->state.alloc(B * sizeof(SysState)));
         HIP_TRY(hipMemset(M->state.p, 0, B * sizeof(SysState)));
         HIP_TRY(hipHostMalloc((void **)&M->h_state, B * sizeof(SysState), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void **)&M->h_ctr, 2 * sizeof(rs::SweepCtr), hipHostMallocDefault));
+        const size_t nf = B * ((size_t)M->sch.ltiles.n + M->sch.utiles.n);
+        HIP_TRY(M->flags.alloc(nf * sizeof(int32_t)));
+        HIP_TRY(hipMemset(M->flags.p, 0, nf * sizeof(int32_t)));
+        HIP_TRY(M->ctrs.alloc(2 * sizeof(rs::SweepCtr)));
+        HIP_TRY(hipMemset(M->ctrs.p, 0, 2 * sizeof(rs::SweepCtr)));
     }
     double *w = M->work.as<double>();
     Krylov &k = M->k;
@@ -490,6 +569,23 @@ static int ensure_workspace(ilu0_t M) {
     k.part = M->part.as<double>();
     k.part_stride = pstride;
     k.st = M->state.as<SysState>();
+    k.lflags = M->flags.as<int32_t>();
+    k.uflags = k.lflags + B * (size_t)M->sch.ltiles.n;
+    k.lctr = M->ctrs.as<rs::SweepCtr>();
+    k.uctr = k.lctr + 1;
+    return RS_OK;
+}
+
+// Non-zero when a single-launch sweep reported a dependency wait that ran
+// past its spin limit (clears the flag).
+static int sweep_error(ilu0_t M, hipStream_t s) {
+    rs::SweepCtr c[2];
+    HIP_TRY(hipMemcpyAsync(c, M->ctrs.p, sizeof c, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c[0].error || c[1].error) {
+        HIP_TRY(hipMemset(M->ctrs.p, 0, sizeof c));
+        return fail(RS_HIP_ERROR, "sweep dependency wait exceeded its limit");
+    }
     return RS_OK;
 }
 
@@ -508,22 +604,34 @@ static void apply_levels(ilu0_t M, const T *L, const T *U, const T *D, const dou
         // (r, p, v read and p written when fused), y written once
         const double bytes = B * ((9 * tb + 4) * S.nL + 8 * n + (fuse_p ? 96 : 24) * n + 3 * tb * n);
         ProfScope ps(PC_LSWEEP, s, bytes);
-        for (int l = 0; l < S.nl_levels; ++l)
-            rs::launch_lsweep<T>(M->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, S.lset[l],
-                                 S.lset[l + 1], nsys, s);
+        if (M->tile_sweeps)
+            rs::launch_lsweep_tiles<T>(M->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, k.lflags,
+                                       k.lctr, nsys, M->sweep_grid, s);
+        else
+            for (int l = 0; l < S.nl_levels; ++l)
+                rs::launch_lsweep<T>(M->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, S.lset[l],
+                                     S.lset[l + 1], nsys, s);
     }
     {
         // U blocks + indices, inv(U_ii), row pointers and row list, y read, z written
         const double bytes = B * ((9 * tb + 4) * S.nU + 9 * tb * n + 8 * n + 3 * tb * n + 24 * n);
         ProfScope ps(PC_USWEEP, s, bytes);
-        for (int l = 0; l < S.nu_levels; ++l)
-            rs::launch_usweep<T>(M->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, S.uset[l],
-                                 S.uset[l + 1], nsys, s);
+        if (M->tile_sweeps)
+            rs::launch_usweep_tiles<T>(M->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, k.uflags,
+                                       k.uctr, nsys, M->sweep_grid, s);
+        else
+            for (int l = 0; l < S.nu_levels; ++l)
+                rs::launch_usweep<T>(M->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, S.uset[l],
+                                     S.uset[l + 1], nsys, s);
     }
 }
 
+// Parts of an iteration: 1 = first preconditioner apply, 2 = v = A phat,
+// 4 = the rest (half-step update, second apply, t = A shat, full step).
+enum { IT_APPLY1 = 1, IT_SPMV_V = 2, IT_REST = 4, IT_ALL = 7 };
+
 template <typename T>
-static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipStream_t s) {
+static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipStream_t s, int parts) {
     Krylov &k = M->k;
     const int B = M->batch;
     const size_t per = (size_t)M->nnzb * 9;
@@ -531,19 +639,68 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
     // values + column indices, row pointers, x gathered once, y written, one
     // more vector read by the fused dot product
     const double spmv_bytes = B * (76 * nnzb + 4 * n + 72 * n);
-    apply_levels<T>(M, L, U, D, nullptr, k.phat, true, k, k.st, B, s);
-    { ProfScope ps(PC_SPMV, s, spmv_bytes); rs::launch_spmv_v(M->dev, M->pvals.as<double>(), per, k, B, s); }
+    if (parts & IT_APPLY1) apply_levels<T>(M, L, U, D, nullptr, k.phat, true, k, k.st, B, s);
+    if (parts & IT_SPMV_V) {
+        ProfScope ps(PC_SPMV_V, s, spmv_bytes);
+        rs::launch_spmv_v(M->dev, M->pvals.as<double>(), per, k, B, s);
+    }
+    if (!(parts & IT_REST)) return;
     { ProfScope ps(PC_VEC, s, B * 72 * n); rs::launch_s_update(M->n, k, B, s); }
     apply_levels<T>(M, L, U, D, k.s, k.shat, false, k, k.st, B, s);
-    { ProfScope ps(PC_SPMV, s, spmv_bytes); rs::launch_spmv_t(M->dev, M->pvals.as<double>(), per, k, B, s); }
+    { ProfScope ps(PC_SPMV_T, s, spmv_bytes); rs::launch_spmv_t(M->dev, M->pvals.as<double>(), per, k, B, s); }
     { ProfScope ps(PC_VEC, s, B * 192 * n); rs::launch_xr_update(M->n, k, B, s); }
 }
 
-static void enqueue_iteration_any(ilu0_t M, hipStream_t s) {
+static void enqueue_iteration_any(ilu0_t M, hipStream_t s, int parts) {
     if (M->precision == RS_PREC_FP32_FACTORS)
-        enqueue_iteration<float>(M, M->Lf.as<float>(), M->Uf.as<float>(), M->Dinvf.as<float>(), s);
+        enqueue_iteration<float>(M, M->Lf.as<float>(), M->Uf.as<float>(), M->Dinvf.as<float>(), s, parts);
     else
-        enqueue_iteration<double>(M, M->L.as<double>(), M->U.as<double>(), M->Dinv.as<double>(), s);
+        enqueue_iteration<double>(M, M->L.as<double>(), M->U.as<double>(), M->Dinv.as<double>(), s, parts);
+}
+
+// Replay graph segment `seg` holding `parts` (captured on a private stream
+// the first time this configuration is seen).  Nothing is timed inside a
+// graph: profiling is off while segments are captured.
+static int replay_segment(ilu0_t M, int seg, int parts, hipStream_t s) {
+    const long long key = (long long)M->precision | (long long)M->tile_sweeps << 2 | (long long)M->sweep_grid << 3;
+    if (!M->gexec[seg] || M->graph_key[seg] != key) {
+        if (M->gexec[seg]) (void)hipGraphExecDestroy(M->gexec[seg]);
+        if (M->graph[seg]) (void)hipGraphDestroy(M->graph[seg]);
+        M->gexec[seg] = nullptr;
+        M->graph[seg] = nullptr;
+        if (!M->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&M->cap_stream, hipStreamNonBlocking));
+        const int mask = g_prof.mask;
+        g_prof.mask = 0;
+        hipError_t e = hipStreamBeginCapture(M->cap_stream, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+            enqueue_iteration_any(M, M->cap_stream, parts);
+            e = hipStreamEndCapture(M->cap_stream, &M->graph[seg]);
+        }
+        g_prof.mask = mask;
+        HIP_TRY(e);
+        HIP_TRY(hipGraphInstantiate(&M->gexec[seg], M->graph[seg], nullptr, nullptr, 0));
+        M->graph_key[seg] = key;
+    }
+    HIP_TRY(hipGraphLaunch(M->gexec[seg], s));
+    return RS_OK;
+}
+
+// Queue one BiCGStab iteration on `s`.  With graphs on, the iteration is
+// one replay; while v = A phat is timed, it runs as a direct launch between
+// two replays; when any other kernel class is timed, all launches are direct.
+static int run_iteration(ilu0_t M, hipStream_t s) {
+    const int mask = g_prof.mask;
+    if (!M->use_graph || (mask & ~(1 << PC_SPMV_V))) {
+        enqueue_iteration_any(M, s, IT_ALL);
+        HIP_TRY(hipGetLastError());
+        return RS_OK;
+    }
+    if (!mask) return replay_segment(M, 0, IT_ALL, s);
+    int st = replay_segment(M, 1, IT_APPLY1, s);
+    if (st != RS_OK) return st;
+    enqueue_iteration_any(M, s, IT_SPMV_V);
+    HIP_TRY(hipGetLastError());
+    return replay_segment(M, 2, IT_REST, s);
 }
 
 extern "C" {
@@ -580,11 +737,8 @@ int ilu0_apply(ilu0_t M, const double *v, double *z, int32_t first_sys, int32_t 
                              n_sys, s);
     rs::launch_permute_vec(M->dev.perm, k.shat, zd, M->n, k.vstride, n_sys, true, s);
     HIP_TRY(hipGetLastError());
-    if (mem != RS_MEM_DEVICE) {
-        HIP_TRY(hipMemcpyAsync(z, zd, m * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-    }
-    return RS_OK;
+    if (mem != RS_MEM_DEVICE) HIP_TRY(hipMemcpyAsync(z, zd, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    return sweep_error(M, s);
 }
 
 static int status_rank(int s) {
@@ -627,9 +781,11 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
     int done_iters = 0;
     while (done_iters < max_iter) {
         const int c = std::min(M->chunk, max_iter - done_iters);
-        for (int i = 0; i < c; ++i) enqueue_iteration_any(M, s);
+        for (int i = 0; i < c; ++i) {
+            st = run_iteration(M, s);
+            if (st != RS_OK) return st;
+        }
         done_iters += c;
-        HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         bool all = true;
@@ -640,8 +796,13 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
                       (size_t)A->nnzb * 9, bd, xd, k, B, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(M->h_ctr, k.lctr, 2 * sizeof(rs::SweepCtr), hipMemcpyDeviceToHost, s));
     if (mem != RS_MEM_DEVICE) HIP_TRY(hipMemcpyAsync(x, xd, m * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (M->h_ctr[0].error || M->h_ctr[1].error) {
+        HIP_TRY(hipMemset(M->ctrs.p, 0, 2 * sizeof(rs::SweepCtr)));
+        return fail(RS_HIP_ERROR, "sweep dependency wait exceeded its limit");
+    }
     int worst = RS_OK;
     for (int i = 0; i < B; ++i) {
         const SysState &S = M->h_state[i];

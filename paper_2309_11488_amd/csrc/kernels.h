@@ -28,6 +28,17 @@ struct DevSchedule {
     const int32_t *perm, *prow, *pcol, *psrc;
     const int32_t *lrows, *lptr, *lcol, *lsrc, *ldq, *l2u, *upd_ptr, *upd;
     const int32_t *urows, *uptr, *ucol, *usrc, *dsrc;
+    // sweep tiles (see Schedule::Tiles)
+    int nlt, nut;
+    const int32_t *lt_start, *lt_dptr, *lt_dep, *ut_start, *ut_dptr, *ut_dep;
+};
+
+// Work counter of one single-launch sweep kernel: tickets hand out (tile,
+// system) items in dependency order; the last workgroup to leave resets the
+// tickets and publishes the epoch that marks a tile as done in this sweep.
+// error != 0 records a dependency wait that exceeded its spin limit.
+struct SweepCtr {
+    uint32_t ticket, exit, epoch, error;
 };
 
 // Workspace vectors of one solve in the new order: system k's vector starts
@@ -40,6 +51,8 @@ struct Krylov {
     double *part;       // reduction partials, nsys * part_stride
     size_t part_stride;
     SysState *st;       // nsys states
+    int32_t *lflags, *uflags;  // per (system, tile): epoch of the sweep that finished it
+    SweepCtr *lctr, *uctr;
 };
 
 // Launch geometry shared by host and device code.
@@ -80,6 +93,17 @@ void launch_lsweep(const DevSchedule &d, const T *L, size_t l_stride, const doub
 template <typename T>
 void launch_usweep(const DevSchedule &d, const T *U, size_t u_stride, const T *Dinv, size_t d_stride, const T *y,
                    double *z, size_t vstride, SysState *st, int q0, int q1, int nsys, hipStream_t s);
+
+// Single-launch sweeps over all tiles of all nsys systems (L: lower
+// schedule, U: upper schedule).  grid = number of workgroups.
+template <typename T>
+void launch_lsweep_tiles(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
+                         bool fuse_p, const double *r, const double *v, double *p, SysState *st, int32_t *flags,
+                         SweepCtr *ctr, int nsys, int grid, hipStream_t s);
+template <typename T>
+void launch_usweep_tiles(const DevSchedule &d, const T *U, size_t u_stride, const T *Dinv, size_t d_stride,
+                         const T *y, double *z, size_t vstride, SysState *st, int32_t *flags, SweepCtr *ctr, int nsys,
+                         int grid, hipStream_t s);
 
 // Plain y = A x (rows in storage order), FP64.
 void launch_spmv(int n, const int32_t *ptr, const int32_t *col, const double *A, size_t a_stride, const double *x,

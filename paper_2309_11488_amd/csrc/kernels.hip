@@ -16,6 +16,8 @@
 // alone and inside a batch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 #include "../../include/rsolve.h"
 
@@ -168,39 +170,48 @@ __device__ inline int stage_copy(const T *__restrict__ val, const int32_t *__res
     return mis / (int)sizeof(T);
 }
 
-// Walk the blocks of this lane's row, staged through LDS pass by pass:
-// acc (+|-)= sum_c val[e][r][c] * x[3 col[e] + c] per block, blocks
-// ascending.  The x entries of up to 8 blocks are gathered before use.
+// acc (+|-)= sum_c val[e][r][c] * x[3 col[e] + c] over this lane's blocks
+// e in [lo, hi), all staged in LDS from `base`; blocks ascending.  The x
+// entries of up to 8 blocks are gathered before use; COH gathers them with
+// agent-coherent loads (x written by other workgroups of the same launch).
+template <bool SUB, bool COH, typename T, typename TX>
+__device__ inline T walk_pass(const T *sv, const int32_t *sc, int shift, int base, int lo, int hi, int r,
+                              const TX *__restrict__ x, T acc) {
+    for (int e = lo; e < hi; e += 8) {
+        TX xv[8][3];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = sc[min(e + u, hi - 1) - base];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                xv[u][c] = COH ? __hip_atomic_load(x + 3 * j + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                               : x[3 * j + c];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (e + u < hi) {
+                const T *b = sv + shift + (e + u - base) * 9 + 3 * r;
+                const T s = b[0] * (T)xv[u][0] + b[1] * (T)xv[u][1] + b[2] * (T)xv[u][2];
+                if (SUB) acc -= s; else acc += s;
+            }
+    }
+    return acc;
+}
+
+// Walk the blocks of this lane's row, staged through LDS pass by pass.
 template <int CAP, bool SUB, typename T, typename TX>
 __device__ inline T stage_walk(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
                                const T *__restrict__ val, int qb0, int qb1, const RowLane &L, const TX *__restrict__ x,
                                T acc, Stage<T, CAP> &st) {
     const int e0 = ptr[qb0], e1 = ptr[qb1];
     const int my0 = L.act ? ptr[L.q] : 0, my1 = L.act ? ptr[L.q + 1] : 0;
-    const T *sv = (const T *)st.v;
     for (int base = e0; base < e1; base += CAP) {
         const int cnt = min(CAP, e1 - base);
         __syncthreads();
         const int shift = stage_copy<T, CAP>(val, col, base, cnt, st);
         __syncthreads();
-        const int lo = max(my0, base), hi = min(my1, base + cnt);
-        for (int e = lo; e < hi; e += 8) {
-            TX xv[8][3];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int j = st.c[min(e + u, hi - 1) - base];
-                xv[u][0] = x[3 * j];
-                xv[u][1] = x[3 * j + 1];
-                xv[u][2] = x[3 * j + 2];
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (e + u < hi) {
-                    const T *b = sv + shift + (e + u - base) * 9 + 3 * L.r;
-                    const T s = b[0] * (T)xv[u][0] + b[1] * (T)xv[u][1] + b[2] * (T)xv[u][2];
-                    if (SUB) acc -= s; else acc += s;
-                }
-        }
+        acc = walk_pass<SUB, false>((const T *)st.v, st.c, shift, base, max(my0, base), min(my1, base + cnt), L.r,
+                                    x, acc);
     }
     return acc;
 }
@@ -350,6 +361,173 @@ __global__ void __launch_bounds__(kRowThreads) k_usweep(DevSchedule d, const T *
     const T *dq = Dinv + (size_t)sys * d_stride + (size_t)rl.q * 9 + 3 * rl.r;
     const T zr = dq[0] * t0 + dq[1] * t1 + dq[2] * t2;
     z[vo + 3 * (size_t)i + rl.r] = (double)zr;
+}
+
+// ------------------------------------------------ single-launch sweeps
+
+// Tiles are handed out by an atomic ticket in schedule order (tile-major,
+// system-minor), so a workgroup only ever waits for items with smaller
+// tickets, which are held by running workgroups: the launch cannot
+// deadlock, whatever the number of resident workgroups.  A tile first copies
+// its factor blocks into LDS (independent of the solution), then waits until
+// every tile it depends on carries this sweep's epoch, computes, writes its
+// rows with agent-coherent stores, waits for those stores to complete and
+// publishes its own flag.  Waits are bounded: past kSpinLimit polls the
+// counter's error word is set and the tile proceeds (no hang).
+constexpr int kSpinLimit = 1 << 22;
+
+struct TileWalk {
+    int item, tile, sys;
+};
+
+// Draw the next item for the workgroup; false when none is left.
+__device__ inline bool next_item(SweepCtr *ctr, int total, int nsys, TileWalk &w) {
+    __shared__ int s_item;
+    if (threadIdx.x == 0)
+        s_item = (int)__hip_atomic_fetch_add(&ctr->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    w.item = s_item;
+    __syncthreads();
+    if (w.item >= total) return false;
+    w.tile = w.item / nsys;
+    w.sys = w.item % nsys;
+    return true;
+}
+
+__device__ inline void leave_sweep(SweepCtr *ctr, uint32_t epoch) {
+    if (threadIdx.x == 0) {
+        const uint32_t e = __hip_atomic_fetch_add(&ctr->exit, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (e == gridDim.x - 1) {
+            __hip_atomic_store(&ctr->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctr->exit, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctr->epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+__device__ inline void wait_tiles(const int32_t *__restrict__ dptr, const int32_t *__restrict__ dep,
+                                  const int32_t *flags, int tile, uint32_t epoch, SweepCtr *ctr) {
+    for (int i = dptr[tile] + threadIdx.x; i < dptr[tile + 1]; i += blockDim.x) {
+        const int32_t *f = flags + dep[i];
+        int spins = 0;
+        while ((uint32_t)__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kSpinLimit) {
+                __hip_atomic_fetch_or(&ctr->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+}
+
+// Every wave waits for its own stores, then one thread marks the tile done.
+__device__ inline void publish_tile(int32_t *flags, int tile, uint32_t epoch) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flags + tile, (int32_t)epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T, bool FUSE_P>
+__global__ void __launch_bounds__(kRowThreads) k_lsweep_tiles(DevSchedule d, const T *__restrict__ L,
+                                                              size_t l_stride, const double *__restrict__ in,
+                                                              T *__restrict__ y, size_t vstride,
+                                                              const double *__restrict__ rv,
+                                                              const double *__restrict__ vv, double *__restrict__ pv,
+                                                              SysState *__restrict__ st, int32_t *__restrict__ flags,
+                                                              SweepCtr *__restrict__ ctr, int nsys) {
+    __shared__ Stage<T, kSweepCap> sv;
+    const uint32_t epoch = __hip_atomic_load(&ctr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    const int total = d.nlt * nsys;
+    TileWalk w;
+    while (next_item(ctr, total, nsys, w)) {
+        if (st && st[w.sys].phase != PH_RUN) continue;
+        const int q0 = d.lt_start[w.tile], q1 = d.lt_start[w.tile + 1];
+        const RowLane rl = row_lane(0, q0, q1);
+        const size_t vo = (size_t)w.sys * vstride;
+        const T *Ls = L + (size_t)w.sys * l_stride;
+        const int e0 = d.lptr[q0], e1 = d.lptr[q1];
+        const int my0 = rl.act ? d.lptr[rl.q] : 0, my1 = rl.act ? d.lptr[rl.q + 1] : 0;
+        int cnt = min(kSweepCap, e1 - e0), shift = 0;
+        if (cnt > 0) shift = stage_copy<T, kSweepCap>(Ls, d.lcol, e0, cnt, sv);
+        const int i = rl.act ? d.lrows[rl.q] : 0;
+        T acc = 0;
+        if (rl.act) {
+            const size_t k = vo + 3 * (size_t)i + rl.r;
+            if (FUSE_P) {
+                const double beta = st[w.sys].beta, omega = st[w.sys].omega;
+                const double p = rv[k] + beta * (pv[k] - omega * vv[k]);
+                pv[k] = p;
+                acc = (T)p;
+            } else {
+                acc = (T)in[k];
+            }
+        }
+        wait_tiles(d.lt_dptr, d.lt_dep, flags + (size_t)w.sys * d.nlt, w.tile, epoch, ctr);
+        __syncthreads();
+        for (int base = e0; base < e1; base += kSweepCap) {
+            if (base != e0) {
+                cnt = min(kSweepCap, e1 - base);
+                __syncthreads();
+                shift = stage_copy<T, kSweepCap>(Ls, d.lcol, base, cnt, sv);
+                __syncthreads();
+            }
+            acc = walk_pass<true, true>((const T *)sv.v, sv.c, shift, base, max(my0, base), min(my1, base + cnt),
+                                        rl.r, y + vo, acc);
+        }
+        if (rl.act) __hip_atomic_store(y + vo + 3 * (size_t)i + rl.r, acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        publish_tile(flags + (size_t)w.sys * d.nlt, w.tile, epoch);
+    }
+    leave_sweep(ctr, epoch);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRowThreads) k_usweep_tiles(DevSchedule d, const T *__restrict__ U,
+                                                              size_t u_stride, const T *__restrict__ Dinv,
+                                                              size_t d_stride, const T *__restrict__ y,
+                                                              double *__restrict__ z, size_t vstride,
+                                                              SysState *__restrict__ st, int32_t *__restrict__ flags,
+                                                              SweepCtr *__restrict__ ctr, int nsys) {
+    __shared__ Stage<T, kSweepCap> sv;
+    const uint32_t epoch = __hip_atomic_load(&ctr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    const int total = d.nut * nsys;
+    TileWalk w;
+    while (next_item(ctr, total, nsys, w)) {
+        if (st && st[w.sys].phase != PH_RUN) continue;
+        const int q0 = d.ut_start[w.tile], q1 = d.ut_start[w.tile + 1];
+        const RowLane rl = row_lane(0, q0, q1);
+        const size_t vo = (size_t)w.sys * vstride;
+        const T *Us = U + (size_t)w.sys * u_stride;
+        const int e0 = d.uptr[q0], e1 = d.uptr[q1];
+        const int my0 = rl.act ? d.uptr[rl.q] : 0, my1 = rl.act ? d.uptr[rl.q + 1] : 0;
+        int cnt = min(kSweepCap, e1 - e0), shift = 0;
+        if (cnt > 0) shift = stage_copy<T, kSweepCap>(Us, d.ucol, e0, cnt, sv);
+        const int i = rl.act ? d.urows[rl.q] : 0;
+        T acc = rl.act ? y[vo + 3 * (size_t)i + rl.r] : (T)0;
+        T dq[3] = {0, 0, 0};
+        if (rl.act) {
+            const T *dp = Dinv + (size_t)w.sys * d_stride + (size_t)rl.q * 9 + 3 * rl.r;
+            dq[0] = dp[0]; dq[1] = dp[1]; dq[2] = dp[2];
+        }
+        wait_tiles(d.ut_dptr, d.ut_dep, flags + (size_t)w.sys * d.nut, w.tile, epoch, ctr);
+        __syncthreads();
+        for (int base = e0; base < e1; base += kSweepCap) {
+            if (base != e0) {
+                cnt = min(kSweepCap, e1 - base);
+                __syncthreads();
+                shift = stage_copy<T, kSweepCap>(Us, d.ucol, base, cnt, sv);
+                __syncthreads();
+            }
+            acc = walk_pass<true, true>((const T *)sv.v, sv.c, shift, base, max(my0, base), min(my1, base + cnt),
+                                        rl.r, z + vo, acc);
+        }
+        const T t0 = __shfl(acc, rl.base, 64), t1 = __shfl(acc, rl.base + 1, 64), t2 = __shfl(acc, rl.base + 2, 64);
+        if (rl.act) {
+            const T zr = dq[0] * t0 + dq[1] * t1 + dq[2] * t2;
+            __hip_atomic_store(z + vo + 3 * (size_t)i + rl.r, (double)zr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        publish_tile(flags + (size_t)w.sys * d.nut, w.tile, epoch);
+    }
+    leave_sweep(ctr, epoch);
 }
 
 // -------------------------------------------------------------------- SpMV
@@ -618,6 +796,43 @@ template void launch_usweep<double>(const DevSchedule &, const double *, size_t,
                                     const double *, double *, size_t, SysState *, int, int, int, hipStream_t);
 template void launch_usweep<float>(const DevSchedule &, const float *, size_t, const float *, size_t, const float *,
                                    double *, size_t, SysState *, int, int, int, hipStream_t);
+
+template <typename T>
+void launch_lsweep_tiles(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
+                         bool fuse_p, const double *r, const double *v, double *p, SysState *st, int32_t *flags,
+                         SweepCtr *ctr, int nsys, int grid, hipStream_t s) {
+    if (d.nlt <= 0 || nsys <= 0) return;
+    grid = std::max(1, std::min(grid, d.nlt * nsys));
+    if (fuse_p)
+        k_lsweep_tiles<T, true><<<grid, kRowThreads, 0, s>>>(d, L, l_stride, in, y, vstride, r, v, p, st, flags, ctr,
+                                                             nsys);
+    else
+        k_lsweep_tiles<T, false><<<grid, kRowThreads, 0, s>>>(d, L, l_stride, in, y, vstride, r, v, p, st, flags,
+                                                              ctr, nsys);
+}
+
+template <typename T>
+void launch_usweep_tiles(const DevSchedule &d, const T *U, size_t u_stride, const T *Dinv, size_t d_stride,
+                         const T *y, double *z, size_t vstride, SysState *st, int32_t *flags, SweepCtr *ctr, int nsys,
+                         int grid, hipStream_t s) {
+    if (d.nut <= 0 || nsys <= 0) return;
+    grid = std::max(1, std::min(grid, d.nut * nsys));
+    k_usweep_tiles<T><<<grid, kRowThreads, 0, s>>>(d, U, u_stride, Dinv, d_stride, y, z, vstride, st, flags, ctr,
+                                                   nsys);
+}
+
+template void launch_lsweep_tiles<double>(const DevSchedule &, const double *, size_t, const double *, double *,
+                                          size_t, bool, const double *, const double *, double *, SysState *,
+                                          int32_t *, SweepCtr *, int, int, hipStream_t);
+template void launch_lsweep_tiles<float>(const DevSchedule &, const float *, size_t, const double *, float *,
+                                         size_t, bool, const double *, const double *, double *, SysState *,
+                                         int32_t *, SweepCtr *, int, int, hipStream_t);
+template void launch_usweep_tiles<double>(const DevSchedule &, const double *, size_t, const double *, size_t,
+                                          const double *, double *, size_t, SysState *, int32_t *, SweepCtr *, int,
+                                          int, hipStream_t);
+template void launch_usweep_tiles<float>(const DevSchedule &, const float *, size_t, const float *, size_t,
+                                         const float *, double *, size_t, SysState *, int32_t *, SweepCtr *, int,
+                                         int, hipStream_t);
 
 void launch_spmv(int n, const int32_t *ptr, const int32_t *col, const double *A, size_t a_stride, const double *x,
                  double *y, size_t vstride, int nsys, hipStream_t s) {

@@ -184,6 +184,66 @@ def test_solve_parity_tight(solver_of, name, ordering):
     assert abs(info[0]["r0_norm"] - oinfo["r0_norm"]) <= 1e-13 * oinfo["r0_norm"]
 
 
+@pytest.mark.parametrize("tiles", [0, 1])
+@pytest.mark.parametrize("ordering", ORDERINGS)
+@pytest.mark.parametrize("name", ["c1", "nnc"])
+def test_sweep_modes_agree(solver_of, name, ordering, tiles):
+    """One launch per level and single-launch tiled sweeps give the same bits
+    (same arithmetic per row, only the launch structure differs)."""
+    s = CASES[name]
+    A, M, _, _ = solver_of(s, ordering)
+    rs.ilu0_set_option(M, rs.OPT_SWEEP_TILES, tiles)
+    assert rs.ilu0_get_option(M, rs.OPT_SWEEP_TILES) == tiles
+    v = np.random.default_rng(9).standard_normal((1, s.n, 3))
+    z = rs.ilu0_apply(M, v)
+    x, st, info = rs.bicgstab_solve(M, A, s.b[0], reduction=1e-8)
+    rs.ilu0_set_option(M, rs.OPT_SWEEP_TILES, 1 - tiles)
+    z2 = rs.ilu0_apply(M, v)
+    x2, st2, info2 = rs.bicgstab_solve(M, A, s.b[0], reduction=1e-8)
+    assert np.array_equal(z, z2) and np.array_equal(x, x2) and info == info2
+
+
+@pytest.mark.parametrize("precision", [rs.PREC_FP64, rs.PREC_FP32_FACTORS])
+@pytest.mark.parametrize("ordering", [rs.ORDER_LEVEL_SET, rs.ORDER_GRAPH_COLOUR])
+def test_graph_replays_equal_eager(solver_of, ordering, precision):
+    """An iteration replayed from a captured graph gives the eager result,
+    replay after replay, with eager work and synchronisations in between."""
+    s = make_ensemble(11, 9, 7, seeds=[3, 4])
+    A, M, _, _ = solver_of(s, ordering, precision)
+    rs.ilu0_set_option(M, rs.OPT_USE_GRAPH, 0)
+    ref = [rs.bicgstab_solve(M, A, s.b[:, 0] * (k + 1), reduction=1e-9) for k in range(3)]
+    rs.ilu0_set_option(M, rs.OPT_USE_GRAPH, 1)
+    for rep in range(2):
+        for k in range(3):
+            x, st, info = rs.bicgstab_solve(M, A, s.b[:, 0] * (k + 1), reduction=1e-9)
+            rs.ilu0_apply(M, s.b[0, 0][None])           # eager work between replays
+            assert np.array_equal(x, ref[k][0]) and info == ref[k][2]
+    rs.ilu0_set_option(M, rs.OPT_SWEEP_TILES, 1 - rs.ilu0_get_option(M, rs.OPT_SWEEP_TILES))
+    x, st, info = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-9)   # recaptured
+    assert np.array_equal(x, ref[0][0])
+    # timing v = A phat: two graph segments with a direct launch between them
+    rs.rsolve_profile_enable(1 << rs.PROF_SPMV_V)
+    try:
+        for k in range(3):
+            x, st, info = rs.bicgstab_solve(M, A, s.b[:, 0] * (k + 1), reduction=1e-9)
+            assert np.array_equal(x, ref[k][0]) and info == ref[k][2]
+        ms, units, byts = rs.rsolve_profile_get(rs.PROF_SPMV_V)
+        assert units > 0 and ms > 0 and byts > 0
+    finally:
+        rs.rsolve_profile_enable(0)
+
+
+@pytest.mark.parametrize("grid", [1, 3, 64])
+def test_tiled_sweep_small_grids(solver_of, grid):
+    """Fewer workgroups than tiles: each workgroup walks many tiles in ticket order."""
+    s = CASES["nnc"]
+    A, M, _, _ = solver_of(s, rs.ORDER_LEVEL_SET)
+    rs.ilu0_set_option(M, rs.OPT_SWEEP_GRID, grid)
+    x, st, info = rs.bicgstab_solve(M, A, s.b[0], reduction=1e-10)
+    xo, _ = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=rs.ORDER_LEVEL_SET, reduction=1e-10)
+    assert st == rs.OK and np.linalg.norm(x[0] - xo) <= 1e-8 * np.linalg.norm(xo)
+
+
 @pytest.mark.parametrize("precision", [rs.PREC_FP64, rs.PREC_FP32_FACTORS])
 @pytest.mark.parametrize("red", [1e-2, 1e-6])
 def test_solve_reduction_and_true_residual(solver_of, precision, red):
