@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--roofline", default="spmv", choices=sorted(CLASS))
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-configuration autotuner")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-sized buffer with torch (a kernel of known traffic, "
                          "used to scale rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -156,6 +157,12 @@ def main():
     log(f"ordering {args.ordering}: {n_sets} sets, sweep levels lower {nl} upper {nu}")
     prec = PREC[precision]
     half_steps, true_res, statuses = [], [], []
+    tune = None
+    if not args.no_tune:
+        st, _ = rs.ilu0_factor(M, A, prec)
+        t = time.perf_counter()
+        tune = rs.ilu0_autotune(M, A, b[0], reduction, reps=3)
+        log(f"autotune: {tune} in {time.perf_counter() - t:.2f}s")
 
     def step(record=False):
         st, bad = rs.ilu0_factor(M, A, prec)
@@ -225,7 +232,8 @@ def main():
         "config": {"workload": f"{args.workload}: {wl['desc']}", "ordering": args.ordering, "precision": precision,
                    "reduction": reduction, "max_iter": 200, "n_brows": s.n, "nnzb": s.nnzb, "batch": s.batch,
                    "rhs_per_step": rhs, "sets": n_sets, "sweep_levels": [nl, nu],
-                   "mean_half_steps": float(np.mean(half_steps)), "max_true_rel_residual": float(max(true_res))},
+                   "mean_half_steps": float(np.mean(half_steps)), "max_true_rel_residual": float(max(true_res)),
+                   "launch_config": tune},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -54,6 +54,7 @@ enum rs_status {
     RS_OK = 0,
     RS_NOT_CONVERGED = 1,   /* iteration limit reached; x holds the last iterate */
     RS_BREAKDOWN = 2,       /* rho, (rhat,v), (t,t) or omega became zero */
+    RS_PENDING = 3,         /* server_poll: the request has not finished yet */
     RS_INVALID_ARG = -1,
     RS_UNSUPPORTED_BLOCK_SIZE = -2,
     RS_BAD_PATTERN = -3,    /* row pointers not monotone, columns unsorted, duplicate or out of range */
@@ -78,7 +79,16 @@ enum rs_option {
                                 graph colouring (few wide levels), 1 otherwise */
     RS_OPT_SWEEP_GRID = 1,   /* workgroups of a single-launch sweep (default 1024) */
     RS_OPT_POLL_CHUNK = 2,   /* BiCGStab iterations queued between host polls of convergence (default 1) */
-    RS_OPT_USE_GRAPH = 3     /* 1 (default): an iteration is captured once as a HIP graph and replayed */
+    RS_OPT_USE_GRAPH = 3,    /* 1 (default): an iteration is captured once as a HIP graph and replayed.
+                                A capture is invalidated by device-synchronising calls (hipFree,
+                                synchronous copies) made meanwhile by other threads: set 0 when
+                                solving from several threads */
+    RS_OPT_PREDICT_POLL = 4, /* 1 (default): the first poll comes after as many iterations as the
+                                previous solve on this handle needed (iterations queued past
+                                convergence return at once) */
+    RS_OPT_SPMV_VARIANT = 5, /* launch shape of the SpMVs: 0..5 = {4, 2, 1} waves per workgroup
+                                with blocks staged in LDS, then the same three reading directly */
+    RS_OPT_SWEEP_VARIANT = 6 /* launch shape of the one-launch-per-level sweeps (same encoding) */
 };
 
 /* Per-system outcome of bicgstab_solve. */
@@ -121,6 +131,10 @@ int bcsr_get_dims(bcsr_t A, int32_t *n_brows, int32_t *nnzb, int32_t *batch);
  * Matrix-Vector multiplication". */
 int bcsr_spmv(bcsr_t A, const double *x, double *y, int32_t first_sys, int32_t n_sys, int32_t mem, void *stream);
 
+/* bcsr_set_option -- RS_OPT_SPMV_VARIANT of bcsr_spmv (other options are
+ * RS_INVALID_ARG). */
+int bcsr_set_option(bcsr_t A, int32_t option, int32_t value);
+
 /* bcsr_destroy -- free the handle (NULL is accepted). */
 int bcsr_destroy(bcsr_t A);
 
@@ -145,6 +159,29 @@ int ilu0_get_sweep_levels(ilu0_t M, int32_t *n_lower, int32_t *n_upper);
  * handle.  RS_INVALID_ARG for an unknown option or a value out of range. */
 int ilu0_set_option(ilu0_t M, int32_t option, int32_t value);
 int ilu0_get_option(ilu0_t M, int32_t option, int32_t *value);
+
+/* Outcome of ilu0_autotune. */
+typedef struct {
+    int32_t spmv_variant, sweep_variant, sweep_tiles, sweep_grid; /* chosen rs_option values */
+    double us_per_solve;   /* mean time of one bicgstab_solve call with them (0 when cached) */
+    int32_t candidates;    /* configurations timed (0 when taken from the cache) */
+    int32_t from_cache;    /* 1 when read from the cache file */
+} rs_tune_result;
+
+/* ilu0_autotune -- pick the launch configuration of a factored handle by
+ * timing it: every one-launch-per-level sweep shape, the single-launch sweep
+ * with several grid sizes, then every SpMV shape with the best sweep, each
+ * over `reps` (>= 1) bicgstab_solve calls on right-hand sides b (batch *
+ * n_brows * 3 doubles, mem) at `reduction`.  The fastest is applied with
+ * ilu0_set_option.  When the environment variable RSOLVE_TUNE_CACHE names a
+ * file, results are looked up there first and appended after a search,
+ * keyed by the problem shape (n, nnzb, batch, ordering, precision, sweep
+ * levels) and the device.  Configurations change launch shapes only; a
+ * different SpMV shape reorders the partial sums of the fused dot products
+ * (results agree to rounding; each configuration is deterministic).
+ * Synchronises `stream`. */
+int ilu0_autotune(ilu0_t M, bcsr_t A, const double *b, int32_t mem, double reduction, int32_t reps, void *stream,
+                  rs_tune_result *out);
 
 /* ilu0_factor -- block ILU0 (Algorithm 2) of every system of A in the
  * analysed order, levels ascending.  precision RS_PREC_FP64 keeps FP64
@@ -199,6 +236,72 @@ int rsolve_profile_enable(int32_t mask);
  * cache traffic) of class `cls` since the last enable (host outputs, may be
  * NULL).  Waits for pending events. */
 int rsolve_profile_get(int32_t cls, double *ms, int64_t *units, double *bytes);
+
+/* ------------------------------------------------------------- serving
+ * A request server for streams of solves of mixed sizes (one system each):
+ * requests wait in arrival order and are admitted as soon as a worker slot
+ * is free and their device footprint fits in the memory budget; each slot
+ * runs on its own HIP stream, so admitted requests overlap on the device.
+ * A slot keeps its matrix / preconditioner handles, so a later request with
+ * the same pattern skips the analysis and reuses buffers and graphs.  Idle
+ * slots give their handles back when the head of the queue needs the room.
+ * Each request is analysed (first time), factored (`precision`), optionally
+ * autotuned (first time per slot and pattern) and solved exactly as the
+ * calls above would; results do not depend on what else is running. */
+typedef struct rs_server *server_t;
+
+typedef struct {
+    size_t hbm_budget_bytes;  /* device bytes all resident requests may hold together */
+    int32_t max_slots;        /* requests processed at once (1..64) */
+    int32_t ordering;         /* RS_ORDER_* for every request */
+    int32_t precision;        /* RS_PREC_* for every request */
+    int32_t autotune;         /* 1: ilu0_autotune on a slot's first solve of a pattern */
+} server_config;
+
+typedef struct {
+    double queue_ms;    /* submission to admission */
+    double analyse_ms;  /* handle creation and pattern analysis (0 when reused) */
+    double factor_ms;   /* value upload and ILU0 factorisation */
+    double tune_ms;     /* autotuning (first solve of a pattern on a slot) */
+    double solve_ms;    /* BiCGStab, true residual, result copy */
+    double total_ms;    /* submission to completion */
+    int32_t slot;
+} server_timing;
+
+typedef struct {
+    int64_t queued, running, completed;
+    size_t reserved_bytes, peak_reserved_bytes;
+} server_stats;
+
+/* server_create -- start max_slots worker threads on the current device.
+ * Errors: RS_INVALID_ARG, RS_HIP_ERROR. */
+int server_create(const server_config *cfg, server_t *out);
+
+/* server_request_bytes -- the device footprint a request of this shape
+ * reserves against the budget. */
+int server_request_bytes(int32_t n_brows, int32_t nnzb, int32_t precision, size_t *bytes);
+
+/* server_submit -- queue one solve (batch 1).  row_ptr/col_idx: host memory;
+ * vals (nnzb*9), b (n*3) and x (n*3, the result) in `mem`.  All are
+ * borrowed until server_poll/server_wait reports completion.  Returns a
+ * ticket; RS_OUT_OF_MEMORY when the request alone exceeds the budget. */
+int server_submit(server_t S, int32_t n_brows, int32_t nnzb, const int32_t *row_ptr, const int32_t *col_idx,
+                  const double *vals, const double *b, double *x, double reduction, int32_t max_iter, int32_t mem,
+                  int64_t *ticket);
+
+/* server_poll -- RS_PENDING while the request runs or waits; otherwise its
+ * status (as bicgstab_solve would return), with info and timing (may be
+ * NULL); the ticket is then released. */
+int server_poll(server_t S, int64_t ticket, solve_info *info, server_timing *timing);
+
+/* server_wait -- as server_poll, blocking until the request completes. */
+int server_wait(server_t S, int64_t ticket, solve_info *info, server_timing *timing);
+
+int server_get_stats(server_t S, server_stats *out);
+
+/* server_destroy -- finish queued and running requests, stop the slots,
+ * free every handle (NULL accepted). */
+int server_destroy(server_t S);
 
 const char *rsolve_status_string(int status);
 const char *rsolve_last_error(void);

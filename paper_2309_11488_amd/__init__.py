@@ -18,19 +18,23 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librsolve.so")
 
-OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
+OK, NOT_CONVERGED, BREAKDOWN, PENDING = 0, 1, 2, 3
 INVALID_ARG, UNSUPPORTED_BLOCK_SIZE, BAD_PATTERN, MISSING_DIAGONAL = -1, -2, -3, -4
 ZERO_PIVOT, NON_FINITE, OUT_OF_MEMORY, HIP_ERROR, PATTERN_MISMATCH, NOT_FACTORED = -5, -6, -7, -8, -9, -10
 ORDER_NATURAL, ORDER_LEVEL_SET, ORDER_GRAPH_COLOUR = 0, 1, 2
 PREC_FP64, PREC_FP32_FACTORS = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
-OPT_SWEEP_TILES, OPT_SWEEP_GRID, OPT_POLL_CHUNK, OPT_USE_GRAPH = 0, 1, 2, 3
+OPT_SWEEP_TILES, OPT_SWEEP_GRID, OPT_POLL_CHUNK, OPT_USE_GRAPH, OPT_PREDICT_POLL = 0, 1, 2, 3, 4
+OPT_SPMV_VARIANT, OPT_SWEEP_VARIANT = 5, 6
+N_ROW_VARIANTS = 6
 
 EXPORTS = (
-    "bcsr_create", "bcsr_set_values", "bcsr_get_dims", "bcsr_spmv", "bcsr_destroy", "ilu0_analyse",
-    "ilu0_get_schedule", "ilu0_get_sweep_levels", "ilu0_set_option", "ilu0_get_option", "ilu0_factor", "ilu0_get_factors", "ilu0_apply",
+    "bcsr_create", "bcsr_set_values", "bcsr_get_dims", "bcsr_spmv", "bcsr_set_option", "bcsr_destroy", "ilu0_analyse",
+    "ilu0_get_schedule", "ilu0_get_sweep_levels", "ilu0_set_option", "ilu0_get_option", "ilu0_autotune",
+    "ilu0_factor", "ilu0_get_factors", "ilu0_apply",
     "bicgstab_solve", "ilu0_destroy", "ilu0_analyse_host", "rsolve_profile_enable", "rsolve_profile_get",
-    "rsolve_status_string", "rsolve_last_error",
+    "server_create", "server_request_bytes", "server_submit", "server_poll", "server_wait", "server_get_stats",
+    "server_destroy", "rsolve_status_string", "rsolve_last_error",
 )
 PROF_FACTOR, PROF_LSWEEP, PROF_USWEEP, PROF_SPMV_V, PROF_VEC, PROF_SPMV_T = 0, 1, 2, 3, 4, 5
 
@@ -38,6 +42,37 @@ PROF_FACTOR, PROF_LSWEEP, PROF_USWEEP, PROF_SPMV_V, PROF_VEC, PROF_SPMV_T = 0, 1
 class SolveInfo(ct.Structure):
     _fields_ = [("status", ct.c_int32), ("half_steps", ct.c_int32), ("r0_norm", ct.c_double),
                 ("final_norm", ct.c_double), ("true_rel_residual", ct.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TuneResult(ct.Structure):
+    _fields_ = [("spmv_variant", ct.c_int32), ("sweep_variant", ct.c_int32), ("sweep_tiles", ct.c_int32),
+                ("sweep_grid", ct.c_int32), ("us_per_solve", ct.c_double), ("candidates", ct.c_int32),
+                ("from_cache", ct.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerConfig(ct.Structure):
+    _fields_ = [("hbm_budget_bytes", ct.c_size_t), ("max_slots", ct.c_int32), ("ordering", ct.c_int32),
+                ("precision", ct.c_int32), ("autotune", ct.c_int32)]
+
+
+class ServerTiming(ct.Structure):
+    _fields_ = [("queue_ms", ct.c_double), ("analyse_ms", ct.c_double), ("factor_ms", ct.c_double),
+                ("tune_ms", ct.c_double), ("solve_ms", ct.c_double), ("total_ms", ct.c_double),
+                ("slot", ct.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(ct.Structure):
+    _fields_ = [("queued", ct.c_int64), ("running", ct.c_int64), ("completed", ct.c_int64),
+                ("reserved_bytes", ct.c_size_t), ("peak_reserved_bytes", ct.c_size_t)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -74,12 +109,14 @@ def lib():
         L.bcsr_get_dims.argtypes = [vp, P(i32), P(i32), P(i32)]
         L.bcsr_spmv.argtypes = [vp, vp, vp, i32, i32, i32, vp]
         L.bcsr_destroy.argtypes = [vp]
+        L.bcsr_set_option.argtypes = [vp, i32, i32]
         L.ilu0_analyse.argtypes = [vp, i32, P(vp)]
         L.ilu0_get_schedule.argtypes = [vp, vp, P(i32), vp]
         L.ilu0_get_sweep_levels.argtypes = [vp, P(i32), P(i32)]
         L.ilu0_set_option.argtypes = [vp, i32, i32]
         L.ilu0_get_option.argtypes = [vp, i32, P(i32)]
         L.ilu0_factor.argtypes = [vp, vp, i32, vp, vp]
+        L.ilu0_autotune.argtypes = [vp, vp, vp, i32, dbl, i32, vp, ct.POINTER(TuneResult)]
         L.ilu0_get_factors.argtypes = [vp, i32, vp, vp]
         L.ilu0_apply.argtypes = [vp, vp, vp, i32, i32, i32, vp]
         L.bicgstab_solve.argtypes = [vp, vp, vp, vp, dbl, i32, i32, vp, vp]
@@ -87,6 +124,13 @@ def lib():
         L.ilu0_analyse_host.argtypes = [i32, vp, vp, i32, vp, P(i32), P(i32)]
         L.rsolve_profile_enable.argtypes = [i32]
         L.rsolve_profile_get.argtypes = [i32, P(dbl), P(ct.c_int64), P(dbl)]
+        L.server_create.argtypes = [P(ServerConfig), P(vp)]
+        L.server_request_bytes.argtypes = [i32, i32, i32, P(ct.c_size_t)]
+        L.server_submit.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, dbl, i32, i32, P(ct.c_int64)]
+        L.server_poll.argtypes = [vp, ct.c_int64, P(SolveInfo), P(ServerTiming)]
+        L.server_wait.argtypes = [vp, ct.c_int64, P(SolveInfo), P(ServerTiming)]
+        L.server_get_stats.argtypes = [vp, P(ServerStats)]
+        L.server_destroy.argtypes = [vp]
         L.rsolve_status_string.argtypes = [ct.c_int]
         L.rsolve_status_string.restype = ct.c_char_p
         L.rsolve_last_error.restype = ct.c_char_p
@@ -201,6 +245,10 @@ def bcsr_spmv(A, x, y=None, first_sys=0, n_sys=None, *, stream=None):
     return y
 
 
+def bcsr_set_option(A, option, value):
+    return _check(lib().bcsr_set_option(A, int(option), int(value)), "bcsr_set_option")
+
+
 def bcsr_destroy(A):
     if A:
         lib().bcsr_destroy(A)
@@ -235,6 +283,17 @@ def ilu0_get_option(M, option):
     v = ct.c_int32()
     _check(lib().ilu0_get_option(M, int(option), ct.byref(v)), "ilu0_get_option")
     return v.value
+
+
+def ilu0_autotune(M, A, b, reduction=1e-2, reps=3, *, stream=None):
+    """Time launch configurations on solves of b and apply the fastest (see rsolve.h)."""
+    if not _is_torch(b):
+        b = _host(b, np.float64)
+    mem, (bp,) = _mem_ptr(b)
+    r = TuneResult()
+    _check(lib().ilu0_autotune(M, A, bp, mem, float(reduction), int(reps), _stream(stream), ct.byref(r)),
+           "ilu0_autotune")
+    return r.as_dict()
 
 
 def ilu0_factor(M, A, precision=PREC_FP64, *, stream=None):
@@ -328,6 +387,76 @@ class Solver:
         ilu0_destroy(self.M)
         bcsr_destroy(self.A)
         self.M = self.A = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Server:
+    """A request server (see ``server_create`` in rsolve.h).
+
+    ``submit`` borrows its arrays until the request is collected with
+    ``poll``/``wait``; the binding keeps references to them until then.
+    """
+
+    def __init__(self, hbm_budget_bytes=200 << 30, max_slots=4, ordering=ORDER_GRAPH_COLOUR,
+                 precision=PREC_FP32_FACTORS, autotune=False):
+        cfg = ServerConfig(int(hbm_budget_bytes), int(max_slots), int(ordering), int(precision), int(autotune))
+        h = ct.c_void_p()
+        _check(lib().server_create(ct.byref(cfg), ct.byref(h)), "server_create")
+        self.h = h
+        self.precision = precision
+        self._held = {}
+
+    def submit(self, rowptr, colidx, vals, b, x=None, reduction=1e-2, max_iter=200):
+        rowptr, colidx = _host(rowptr, np.int32), _host(colidx, np.int32)
+        if not _is_torch(vals):
+            vals, b = _host(vals, np.float64), _host(b, np.float64)
+            if x is None:
+                x = np.zeros_like(b)
+        mem, (vp, bp, xp) = _mem_ptr(vals, b, x)
+        t = ct.c_int64()
+        _check(lib().server_submit(self.h, len(rowptr) - 1, len(colidx), rowptr.ctypes.data, colidx.ctypes.data,
+                                   vp, bp, xp, float(reduction), int(max_iter), mem, ct.byref(t)), "server_submit")
+        self._held[t.value] = (rowptr, colidx, vals, b, x)
+        return t.value
+
+    def _finish(self, fn, ticket):
+        info, tm = SolveInfo(), ServerTiming()
+        if ticket not in self._held:
+            raise RsolveError(INVALID_ARG, "server: unknown or already collected ticket")
+        st = fn(self.h, int(ticket), ct.byref(info), ct.byref(tm))
+        if st == PENDING:
+            return None
+        x = self._held.pop(ticket)[4]
+        return x, st, info.as_dict(), tm.as_dict()
+
+    def poll(self, ticket):
+        """None while pending, else (x, status, info, timing)."""
+        return self._finish(lib().server_poll, ticket)
+
+    def wait(self, ticket):
+        return self._finish(lib().server_wait, ticket)
+
+    def stats(self):
+        st = ServerStats()
+        _check(lib().server_get_stats(self.h, ct.byref(st)), "server_get_stats")
+        return st.as_dict()
+
+    @staticmethod
+    def request_bytes(n, nnzb, precision=PREC_FP32_FACTORS):
+        v = ct.c_size_t()
+        _check(lib().server_request_bytes(int(n), int(nnzb), int(precision), ct.byref(v)), "server_request_bytes")
+        return v.value
+
+    def close(self):
+        if self.h:
+            lib().server_destroy(self.h)
+            self.h = None
+            self._held.clear()
 
     def __enter__(self):
         return self

@@ -9,14 +9,14 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librsolve.so")
-SOURCES = ["csrc/analysis.cpp", "csrc/kernels.hip", "csrc/capi.hip"]
+SOURCES = ["csrc/analysis.cpp", "csrc/kernels.hip", "csrc/capi.hip", "csrc/server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions anywhere
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument", "-pthread",
 ]
 
 

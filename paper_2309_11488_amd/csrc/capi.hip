@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
+#include <fstream>
+#include <sstream>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -141,6 +144,7 @@ void prof_flush() {
 
 struct rs_bcsr {
     int n = 0, nnzb = 0, batch = 1;
+    int spmv_variant = rs::RV_W4_LDS;
     uint64_t hash = 0;
     std::vector<int32_t> h_rowptr, h_colidx;
     DevBuf rowptr, colidx, vals;
@@ -159,13 +163,17 @@ struct rs_ilu0 {
     DevBuf pvals, L, U, Dinv, Lf, Uf, Dinvf, bad;
     std::vector<int32_t> bad_host;
     // solve workspace
-    DevBuf work, ywork, part, state, bstage, xstage, flags, ctrs;
+    DevBuf work, ywork, part, spart, tickets, state, bstage, xstage, flags, ctrs;
     Krylov k{};
     SysState *h_state = nullptr;
     rs::SweepCtr *h_ctr = nullptr;
     int chunk = 1;
+    bool predict = true;       // first poll after as many iterations as the previous solve needed
+    int last_iters = 1;
     bool tile_sweeps = true;   // single-launch sweeps (else one launch per level)
     int sweep_grid = 1024;     // workgroups of a single-launch sweep
+    int spmv_variant = rs::RV_W4_LDS;   // launch shape of the SpMVs
+    int sweep_variant = rs::RV_W4_LDS;  // launch shape of the per-level sweeps
     // a BiCGStab iteration captured as HIP graphs, replayed on the caller's
     // stream: segment 0 = the whole iteration; 1 and 2 = the parts before and
     // after v = A phat, used while that kernel is being timed with events
@@ -214,6 +222,7 @@ const char *rsolve_status_string(int status) {
     case RS_OK: return "ok";
     case RS_NOT_CONVERGED: return "not converged";
     case RS_BREAKDOWN: return "breakdown";
+    case RS_PENDING: return "pending";
     case RS_INVALID_ARG: return "invalid argument";
     case RS_UNSUPPORTED_BLOCK_SIZE: return "unsupported block size";
     case RS_BAD_PATTERN: return "bad pattern";
@@ -310,6 +319,15 @@ int bcsr_get_dims(bcsr_t A, int32_t *n_brows, int32_t *nnzb, int32_t *batch) {
     return RS_OK;
 }
 
+int bcsr_set_option(bcsr_t A, int32_t option, int32_t value) {
+    if (!A) return fail(RS_INVALID_ARG, "bcsr_set_option: NULL handle");
+    if (option == RS_OPT_SPMV_VARIANT && value >= 0 && value < rs::RV_COUNT) {
+        A->spmv_variant = value;
+        return RS_OK;
+    }
+    return fail(RS_INVALID_ARG, "bcsr_set_option: unknown option or bad value");
+}
+
 int bcsr_destroy(bcsr_t A) {
     delete A;
     return RS_OK;
@@ -343,7 +361,7 @@ int bcsr_spmv(bcsr_t A, const double *x, double *y, int32_t first_sys, int32_t n
     }
     const size_t per = (size_t)A->nnzb * 9;
     rs::launch_spmv(A->n, A->rowptr.as<int32_t>(), A->colidx.as<int32_t>(), A->vals.as<double>() + per * first_sys,
-                    per, xd, yd, 3 * (size_t)A->n, n_sys, s);
+                    per, xd, yd, 3 * (size_t)A->n, n_sys, A->spmv_variant, s);
     HIP_TRY(hipGetLastError());
     if (mem != RS_MEM_DEVICE) {
         if (m) HIP_TRY(hipMemcpyAsync(y, yd, m * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -429,6 +447,18 @@ int ilu0_set_option(ilu0_t M, int32_t option, int32_t value) {
         if (value != 0 && value != 1) break;
         M->use_graph = value != 0;
         return RS_OK;
+    case RS_OPT_PREDICT_POLL:
+        if (value != 0 && value != 1) break;
+        M->predict = value != 0;
+        return RS_OK;
+    case RS_OPT_SPMV_VARIANT:
+        if (value < 0 || value >= rs::RV_COUNT) break;
+        M->spmv_variant = value;
+        return RS_OK;
+    case RS_OPT_SWEEP_VARIANT:
+        if (value < 0 || value >= rs::RV_COUNT) break;
+        M->sweep_variant = value;
+        return RS_OK;
     default:
         break;
     }
@@ -442,6 +472,9 @@ int ilu0_get_option(ilu0_t M, int32_t option, int32_t *value) {
     case RS_OPT_SWEEP_GRID: *value = M->sweep_grid; return RS_OK;
     case RS_OPT_POLL_CHUNK: *value = M->chunk; return RS_OK;
     case RS_OPT_USE_GRAPH: *value = M->use_graph ? 1 : 0; return RS_OK;
+    case RS_OPT_PREDICT_POLL: *value = M->predict ? 1 : 0; return RS_OK;
+    case RS_OPT_SPMV_VARIANT: *value = M->spmv_variant; return RS_OK;
+    case RS_OPT_SWEEP_VARIANT: *value = M->sweep_variant; return RS_OK;
     default: return fail(RS_INVALID_ARG, "ilu0_get_option: unknown option");
     }
 }
@@ -547,8 +580,15 @@ static int ensure_workspace(ilu0_t M) {
         HIP_TRY(hipMemset(M->work.p, 0, 9 * vec * sizeof(double)));  // padding stays zero
     }
     HIP_TRY(M->ywork.alloc(vec * sizeof(double)));
-    const size_t pstride = 2 * (size_t)std::max(rs::row_blocks(std::max(M->n, 1)), rs::kVecMaxBlocks);
+    const int max_blocks = std::max(rs::row_blocks(std::max(M->n, 1), 1), rs::kVecMaxBlocks);
+    const size_t pstride = rs::part_stride_for(max_blocks), tstride = rs::ticket_stride_for(max_blocks);
     if (!M->part.p || M->k.part_stride != pstride) HIP_TRY(M->part.alloc(B * pstride * sizeof(double)));
+    const size_t sstride = rs::part_stride_for(rs::row_blocks(std::max(M->n, 1), 1));
+    if (!M->spart.p) HIP_TRY(M->spart.alloc(B * sstride * sizeof(double)));
+    if (!M->tickets.p) {
+        HIP_TRY(M->tickets.alloc(B * tstride * sizeof(uint32_t)));
+        HIP_TRY(hipMemset(M->tickets.p, 0, B * tstride * sizeof(uint32_t)));
+    }
     if (!M->state.p) {
         HIP_TRY(M->state.alloc(B * sizeof(SysState)));
         HIP_TRY(hipMemset(M->state.p, 0, B * sizeof(SysState)));
@@ -568,6 +608,10 @@ static int ensure_workspace(ilu0_t M) {
     k.y = M->ywork.p;
     k.part = M->part.as<double>();
     k.part_stride = pstride;
+    k.tickets = M->tickets.as<uint32_t>();
+    k.ticket_stride = tstride;
+    k.spart = M->spart.as<double>();
+    k.spart_stride = sstride;
     k.st = M->state.as<SysState>();
     k.lflags = M->flags.as<int32_t>();
     k.uflags = k.lflags + B * (size_t)M->sch.ltiles.n;
@@ -610,7 +654,7 @@ static void apply_levels(ilu0_t M, const T *L, const T *U, const T *D, const dou
         else
             for (int l = 0; l < S.nl_levels; ++l)
                 rs::launch_lsweep<T>(M->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, S.lset[l],
-                                     S.lset[l + 1], nsys, s);
+                                     S.lset[l + 1], nsys, M->sweep_variant, s);
     }
     {
         // U blocks + indices, inv(U_ii), row pointers and row list, y read, z written
@@ -622,7 +666,7 @@ static void apply_levels(ilu0_t M, const T *L, const T *U, const T *D, const dou
         else
             for (int l = 0; l < S.nu_levels; ++l)
                 rs::launch_usweep<T>(M->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, S.uset[l],
-                                     S.uset[l + 1], nsys, s);
+                                     S.uset[l + 1], nsys, M->sweep_variant, s);
     }
 }
 
@@ -642,13 +686,13 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
     if (parts & IT_APPLY1) apply_levels<T>(M, L, U, D, nullptr, k.phat, true, k, k.st, B, s);
     if (parts & IT_SPMV_V) {
         ProfScope ps(PC_SPMV_V, s, spmv_bytes);
-        rs::launch_spmv_v(M->dev, M->pvals.as<double>(), per, k, B, s);
+        rs::launch_spmv_v(M->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, s);
     }
     if (!(parts & IT_REST)) return;
-    { ProfScope ps(PC_VEC, s, B * 72 * n); rs::launch_s_update(M->n, k, B, s); }
+    { ProfScope ps(PC_VEC, s, B * 72 * n); rs::launch_s_update(M->n, k, B, M->spmv_variant, s); }
     apply_levels<T>(M, L, U, D, k.s, k.shat, false, k, k.st, B, s);
-    { ProfScope ps(PC_SPMV_T, s, spmv_bytes); rs::launch_spmv_t(M->dev, M->pvals.as<double>(), per, k, B, s); }
-    { ProfScope ps(PC_VEC, s, B * 192 * n); rs::launch_xr_update(M->n, k, B, s); }
+    { ProfScope ps(PC_SPMV_T, s, spmv_bytes); rs::launch_spmv_t(M->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, s); }
+    { ProfScope ps(PC_VEC, s, B * 192 * n); rs::launch_xr_update(M->n, k, B, M->spmv_variant, s); }
 }
 
 static void enqueue_iteration_any(ilu0_t M, hipStream_t s, int parts) {
@@ -662,7 +706,8 @@ static void enqueue_iteration_any(ilu0_t M, hipStream_t s, int parts) {
 // the first time this configuration is seen).  Nothing is timed inside a
 // graph: profiling is off while segments are captured.
 static int replay_segment(ilu0_t M, int seg, int parts, hipStream_t s) {
-    const long long key = (long long)M->precision | (long long)M->tile_sweeps << 2 | (long long)M->sweep_grid << 3;
+    const long long key = (long long)M->precision | (long long)M->tile_sweeps << 2 | (long long)M->spmv_variant << 3 |
+                          (long long)M->sweep_variant << 6 | (long long)M->sweep_grid << 10;
     if (!M->gexec[seg] || M->graph_key[seg] != key) {
         if (M->gexec[seg]) (void)hipGraphExecDestroy(M->gexec[seg]);
         if (M->graph[seg]) (void)hipGraphDestroy(M->graph[seg]);
@@ -779,8 +824,11 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
         rs::launch_setup(M->dev, bd, M->bad.as<int32_t>(), reduction, max_iter, k, B, s);
     }
     int done_iters = 0;
+    bool first = true;
     while (done_iters < max_iter) {
-        const int c = std::min(M->chunk, max_iter - done_iters);
+        int c = first && M->predict ? std::max(M->chunk, M->last_iters) : M->chunk;
+        c = std::min(c, max_iter - done_iters);
+        first = false;
         for (int i = 0; i < c; ++i) {
             st = run_iteration(M, s);
             if (st != RS_OK) return st;
@@ -793,7 +841,7 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
         if (all) break;
     }
     rs::launch_finish(M->dev, A->rowptr.as<int32_t>(), A->colidx.as<int32_t>(), A->vals.as<double>(),
-                      (size_t)A->nnzb * 9, bd, xd, k, B, s);
+                      (size_t)A->nnzb * 9, bd, xd, k, B, M->spmv_variant, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(M->h_ctr, k.lctr, 2 * sizeof(rs::SweepCtr), hipMemcpyDeviceToHost, s));
@@ -803,12 +851,14 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
         HIP_TRY(hipMemset(M->ctrs.p, 0, 2 * sizeof(rs::SweepCtr)));
         return fail(RS_HIP_ERROR, "sweep dependency wait exceeded its limit");
     }
-    int worst = RS_OK;
+    int worst = RS_OK, needed = 1;
     for (int i = 0; i < B; ++i) {
         const SysState &S = M->h_state[i];
         if (info) info[i] = solve_info{S.status, S.half_steps, S.r0norm, S.last_norm, S.true_res};
         if (status_rank(S.status) > status_rank(worst)) worst = S.status;
+        needed = std::max(needed, (S.half_steps + 1) / 2);
     }
+    M->last_iters = needed;
     return worst;
 }
 
@@ -829,6 +879,117 @@ int rsolve_profile_get(int32_t cls, double *ms, int64_t *units, double *bytes) {
     if (ms) *ms = g_prof.ms[cls];
     if (units) *units = g_prof.units[cls];
     if (bytes) *bytes = g_prof.bytes[cls];
+    return RS_OK;
+}
+
+static std::string tune_key(ilu0_t M) {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) prop.multiProcessorCount = 0;
+    std::ostringstream k;
+    k << "n=" << M->n << ",nnzb=" << M->nnzb << ",batch=" << M->batch << ",ord=" << M->sch.ordering
+      << ",prec=" << M->precision << ",nl=" << M->sch.nl_levels << ",nu=" << M->sch.nu_levels
+      << ",arch=" << prop.gcnArchName << ",cu=" << prop.multiProcessorCount;
+    std::string r = k.str();
+    for (char &c : r)
+        if (c == ' ') c = '_';
+    return r;
+}
+
+int ilu0_autotune(ilu0_t M, bcsr_t A, const double *b, int32_t mem, double reduction, int32_t reps, void *stream,
+                  rs_tune_result *out) {
+    int st = check_pair(M, A);
+    if (st != RS_OK) return st;
+    if (!b || reps < 1 || !(reduction >= 0.0) || (mem != RS_MEM_HOST && mem != RS_MEM_DEVICE))
+        return fail(RS_INVALID_ARG, "ilu0_autotune: bad arguments");
+    if (!M->factored) return fail(RS_NOT_FACTORED, "ilu0_autotune: call ilu0_factor first");
+    hipStream_t s = (hipStream_t)stream;
+    rs_tune_result res{M->spmv_variant, M->sweep_variant, M->tile_sweeps ? 1 : 0, M->sweep_grid, 0.0, 0, 0};
+    const std::string key = tune_key(M);
+    const char *cache = std::getenv("RSOLVE_TUNE_CACHE");
+    if (cache && *cache) {
+        std::ifstream in(cache);
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream ls(line);
+            std::string k;
+            rs_tune_result r{};
+            if (ls >> k >> r.spmv_variant >> r.sweep_variant >> r.sweep_tiles >> r.sweep_grid && k == key &&
+                r.spmv_variant >= 0 && r.spmv_variant < rs::RV_COUNT && r.sweep_variant >= 0 &&
+                r.sweep_variant < rs::RV_COUNT && r.sweep_grid >= 1) {
+                res = r;
+                res.from_cache = 1;
+            }
+        }
+        if (res.from_cache) {
+            M->spmv_variant = res.spmv_variant;
+            M->sweep_variant = res.sweep_variant;
+            M->tile_sweeps = res.sweep_tiles != 0;
+            M->sweep_grid = res.sweep_grid;
+            if (out) *out = res;
+            return RS_OK;
+        }
+    }
+    const size_t m = 3 * (size_t)M->n * M->batch;
+    DevBuf bb, xb;
+    HIP_TRY(bb.alloc(std::max<size_t>(m, 1) * sizeof(double)));
+    HIP_TRY(xb.alloc(std::max<size_t>(m, 1) * sizeof(double)));
+    if (m)
+        HIP_TRY(hipMemcpyAsync(bb.p, b, m * sizeof(double),
+                               mem == RS_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    struct Cfg {
+        int spmv, sweep, tiles, grid;
+    };
+    auto apply = [&](const Cfg &c) {
+        M->spmv_variant = c.spmv;
+        M->sweep_variant = c.sweep;
+        M->tile_sweeps = c.tiles != 0;
+        M->sweep_grid = c.grid;
+    };
+    double best = 1e300;
+    Cfg bestc{M->spmv_variant, M->sweep_variant, M->tile_sweeps ? 1 : 0, M->sweep_grid};
+    int ncand = 0;
+    auto time_cfg = [&](const Cfg &c) -> int {
+        apply(c);
+        int r = bicgstab_solve(M, A, bb.as<double>(), xb.as<double>(), reduction, 200, RS_MEM_DEVICE, stream, nullptr);
+        if (r < 0) return r;
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int i = 0; i < reps; ++i) {
+            r = bicgstab_solve(M, A, bb.as<double>(), xb.as<double>(), reduction, 200, RS_MEM_DEVICE, stream, nullptr);
+            if (r < 0) return r;
+        }
+        const double us =
+            std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() / reps;
+        ++ncand;
+        if (us < best) {
+            best = us;
+            bestc = c;
+        }
+        return RS_OK;
+    };
+    const int sp0 = M->spmv_variant;
+    for (int v = 0; v < rs::RV_COUNT; ++v) {
+        st = time_cfg({sp0, v, 0, M->sweep_grid});
+        if (st != RS_OK) return st;
+    }
+    for (int g : {256, 512, 1024, 2048}) {
+        st = time_cfg({sp0, bestc.sweep, 1, g});
+        if (st != RS_OK) return st;
+    }
+    const Cfg sweep_best = bestc;
+    for (int v = 0; v < rs::RV_COUNT; ++v) {
+        if (v == sp0) continue;
+        st = time_cfg({v, sweep_best.sweep, sweep_best.tiles, sweep_best.grid});
+        if (st != RS_OK) return st;
+    }
+    apply(bestc);
+    res = rs_tune_result{bestc.spmv, bestc.sweep, bestc.tiles, bestc.grid, best, ncand, 0};
+    if (cache && *cache) {
+        std::ofstream o(cache, std::ios::app);
+        o << key << " " << res.spmv_variant << " " << res.sweep_variant << " " << res.sweep_tiles << " "
+          << res.sweep_grid << " " << res.us_per_solve << "\n";
+    }
+    if (out) *out = res;
     return RS_OK;
 }
 

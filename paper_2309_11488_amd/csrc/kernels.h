@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
 
@@ -19,7 +20,6 @@ struct SysState {
     double true_res;
     int32_t phase, status, half_steps, iter;
     int32_t max_iter, pad0;
-    uint32_t ticket, pad;
 };
 
 // Device copies of the schedule (see analysis.h for the meaning).
@@ -50,6 +50,10 @@ struct Krylov {
     void *y;            // lower-sweep intermediate, FP64 or FP32 (factor type)
     double *part;       // reduction partials, nsys * part_stride
     size_t part_stride;
+    uint32_t *tickets;  // reduction ticket counters, nsys * ticket_stride
+    size_t ticket_stride;
+    double *spart;      // per-workgroup partials of the two SpMVs, nsys * spart_stride
+    size_t spart_stride;
     SysState *st;       // nsys states
     int32_t *lflags, *uflags;  // per (system, tile): epoch of the sweep that finished it
     SweepCtr *lctr, *uctr;
@@ -66,7 +70,21 @@ constexpr int kVecItems = 4;                                // entries per threa
 constexpr int kVecTile = kVecThreads * kVecItems;           // 1024 entries
 constexpr int kVecMaxBlocks = 2048;
 
-inline int row_blocks(int rows) { return (rows + kRowsPerBlock - 1) / kRowsPerBlock; }
+inline int row_blocks(int rows, int waves = kWavesPerBlock) {
+    return (rows + waves * kRowsPerWave - 1) / (waves * kRowsPerWave);
+}
+
+// Launch shapes of the row kernels (SpMV, per-level sweeps): 4, 2 or 1
+// waves per workgroup, blocks staged through LDS or read directly.  The
+// arithmetic and its order are the same in every shape.
+enum RowVariant { RV_W4_LDS = 0, RV_W2_LDS = 1, RV_W1_LDS = 2, RV_W4_DIRECT = 3, RV_W2_DIRECT = 4, RV_W1_DIRECT = 5,
+                  RV_COUNT = 6 };
+inline int variant_waves(int v) { return v % 3 == 0 ? 4 : (v % 3 == 1 ? 2 : 1); }
+// SpMV workgroups: one row tile each.
+inline int spmv_grid(int n, int waves) { return std::max(1, row_blocks(n, waves)); }
+// Reduction scratch of a system whose largest launch has `blocks` workgroups.
+inline size_t part_stride_for(int blocks) { return 2 * (size_t)blocks + 2 * ((size_t)blocks / 32 + 1) + 16; }
+inline size_t ticket_stride_for(int blocks) { return 2 + (size_t)blocks / 32 + 1; }
 inline size_t vec_stride(int n) { return (3 * (size_t)n + kVecTile - 1) / kVecTile * kVecTile; }
 int vec_blocks(int n);  // workgroups of the vector kernels for one padded vector
 
@@ -87,12 +105,12 @@ void launch_to_fp32(const double *src, float *dst, size_t count, hipStream_t s);
 template <typename T>
 void launch_lsweep(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
                    bool fuse_p, const double *r, const double *v, double *p, SysState *st, int q0, int q1, int nsys,
-                   hipStream_t s);
+                   int variant, hipStream_t s);
 
 // Upper sweep z = inv(U_ii) (y - U z) for U-schedule rows [q0, q1).
 template <typename T>
 void launch_usweep(const DevSchedule &d, const T *U, size_t u_stride, const T *Dinv, size_t d_stride, const T *y,
-                   double *z, size_t vstride, SysState *st, int q0, int q1, int nsys, hipStream_t s);
+                   double *z, size_t vstride, SysState *st, int q0, int q1, int nsys, int variant, hipStream_t s);
 
 // Single-launch sweeps over all tiles of all nsys systems (L: lower
 // schedule, U: upper schedule).  grid = number of workgroups.
@@ -107,20 +125,25 @@ void launch_usweep_tiles(const DevSchedule &d, const T *U, size_t u_stride, cons
 
 // Plain y = A x (rows in storage order), FP64.
 void launch_spmv(int n, const int32_t *ptr, const int32_t *col, const double *A, size_t a_stride, const double *x,
-                 double *y, size_t vstride, int nsys, hipStream_t s);
+                 double *y, size_t vstride, int nsys, int variant, hipStream_t s);
 
 // Solver kernels (new order, all nsys systems of the Krylov workspace).
+// The two SpMVs store per-workgroup partial sums; the s- and x/r-updates
+// that follow add them (their launch shape fixes the partials' count).
 // bad[sys] < n marks a system whose factorisation hit a singular pivot.
 void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad, double reduction, int max_iter,
                   Krylov &k, int nsys, hipStream_t s);
-void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, hipStream_t s);
-void launch_s_update(int n, Krylov &k, int nsys, hipStream_t s);
-void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, hipStream_t s);
-void launch_xr_update(int n, Krylov &k, int nsys, hipStream_t s);
+void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
+                   hipStream_t s);
+void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, hipStream_t s);
+void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
+                   hipStream_t s);
+void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, hipStream_t s);
 // x_orig[perm[i]] = x'[i]; then r = b - A x_orig with the caller's A, and the
 // true relative residual into the states.
 void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *colidx, const double *A,
-                   size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, hipStream_t s);
+                   size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, int variant,
+                   hipStream_t s);
 
 // out[i] = in[perm[i]] (gather to the new order) and its inverse scatter;
 // the new-order side has stride vstride, the caller side 3n.

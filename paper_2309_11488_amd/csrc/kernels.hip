@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.h"
 #include "../../include/rsolve.h"
@@ -64,54 +65,135 @@ __device__ inline void block_sum(double (&v)[NV], double *lds) {
 // Deterministic grid reduction.  Returns true in the last workgroup to
 // finish, where thread 0's v[] holds the grid total.
 //
-// Each workgroup stores its partials with agent-scope atomic stores (they
-// are written through to the coherence point, so no L2 writeback of the
-// whole XCD cache is needed), waits until they have completed, then takes a
-// ticket with an agent-scope atomic add.  The workgroup that draws the last
-// ticket reads all partials with agent-scope atomic loads and adds them in
-// block order.  The ticket is reset for the next reduction on this system.
+// Two-level ticket tree, so no counter takes more than a few hundred
+// atomics: workgroups form groups of kGroup consecutive (logical) ids.  Each
+// workgroup stores its partials with agent-scope atomic stores (written
+// through to the coherence point, so no writeback of the whole XCD L2 is
+// needed), waits until they have completed, then takes a ticket on its
+// group's counter.  The last workgroup of a group adds the group's partials
+// in id order, stores the group partial the same way and takes a ticket on
+// the top counter; the last group's workgroup adds the group partials in
+// group order.  Counters are reset by their last taker.  The tree depends
+// only on the number of workgroups, so results are reproducible bit for bit.
+// Layout: part[0 .. nblk*NV) block partials, then group partials;
+// tickets[0] = top counter, tickets[1 + g] = counter of group g.
+constexpr int kGroup = 32;
+
 template <int NV>
-__device__ bool grid_reduce(double (&v)[NV], double *part, uint32_t *ticket, int nblk, int bx) {
+__device__ bool grid_reduce(double (&v)[NV], double *part, uint32_t *tickets, int nblk, int bx) {
     __shared__ double lds[16 * NV];
-    __shared__ int last;
+    __shared__ int glast, last;
     block_sum<NV>(v, lds);
+    const int ng = (nblk + kGroup - 1) / kGroup, g = bx / kGroup;
+    const int gsize = min(kGroup, nblk - g * kGroup);
+    double *gpart = part + (size_t)nblk * NV;
     if (threadIdx.x == 0) {
         for (int k = 0; k < NV; ++k)
             __hip_atomic_store(part + (size_t)bx * NV + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_s_waitcnt(0);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        const uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        last = (t == (uint32_t)(nblk - 1));
+        const uint32_t t = __hip_atomic_fetch_add(tickets + 1 + g, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        glast = t == (uint32_t)(gsize - 1);
+        last = 0;
     }
     __syncthreads();
+    if (glast) {
+        // group reduction by wave 0: one partial per lane, butterfly sum
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            double gs[NV];
+            for (int k = 0; k < NV; ++k) {
+                const double p = lane < gsize ? __hip_atomic_load(part + (size_t)(g * kGroup + lane) * NV + k,
+                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                              : 0.0;
+                gs[k] = wave_sum(p);
+            }
+            if (lane == 0) {
+                __hip_atomic_store(tickets + 1 + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int k = 0; k < NV; ++k)
+                    __hip_atomic_store(gpart + (size_t)g * NV + k, gs[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                __builtin_amdgcn_s_waitcnt(0);
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                const uint32_t t2 = __hip_atomic_fetch_add(tickets, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (t2 == (uint32_t)(ng - 1)) {
+                    __hip_atomic_store(tickets, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    last = 1;
+                }
+            }
+        }
+        __syncthreads();
+    }
     if (!last) return false;
     double acc[NV];
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    constexpr int U = 8;
-    for (int b0 = 0; b0 < nblk; b0 += U * (int)blockDim.x) {
+    constexpr int U = 4;
+    for (int b0 = 0; b0 < ng; b0 += U * (int)blockDim.x) {
         double t[U][NV];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int b = b0 + u * blockDim.x + threadIdx.x;
             for (int k = 0; k < NV; ++k)
-                t[u][k] = b < nblk ? __hip_atomic_load(part + (size_t)b * NV + k, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT)
-                                   : 0.0;
+                t[u][k] = b < ng ? __hip_atomic_load(gpart + (size_t)b * NV + k, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)
+                                 : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
             for (int k = 0; k < NV; ++k) acc[k] += t[u][k];
     }
     block_sum<NV>(acc, lds);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0)
         for (int k = 0; k < NV; ++k) v[k] = acc[k];
-        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
     return true;
 }
 
+// First level of grid_reduce only: the last workgroup of each group of
+// kGroup stores the group's sum at part[nblk*NV + g*NV].  A later kernel adds
+// the ceil(nblk / kGroup) group sums (no top-level counter, no serial tail).
+template <int NV>
+__device__ void group_reduce(double (&v)[NV], double *part, uint32_t *tickets, int nblk, int bx) {
+    __shared__ double lds[16 * NV];
+    __shared__ int glast;
+    block_sum<NV>(v, lds);
+    const int g = bx / kGroup, gsize = min(kGroup, nblk - g * kGroup);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < NV; ++k)
+            __hip_atomic_store(part + (size_t)bx * NV + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const uint32_t t = __hip_atomic_fetch_add(tickets + 1 + g, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        glast = t == (uint32_t)(gsize - 1);
+    }
+    __syncthreads();
+    if (glast && threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        double gs[NV];
+        for (int k = 0; k < NV; ++k) {
+            const double p = lane < gsize ? __hip_atomic_load(part + (size_t)(g * kGroup + lane) * NV + k,
+                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                          : 0.0;
+            gs[k] = wave_sum(p);
+        }
+        if (lane == 0) {
+            __hip_atomic_store(tickets + 1 + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int k = 0; k < NV; ++k) part[(size_t)nblk * NV + (size_t)g * NV + k] = gs[k];
+        }
+    }
+}
+
 __device__ inline bool finite(double x) { return __builtin_isfinite(x); }
+
+// One block-row times a 3-vector, b0 x0 + b1 x1 + b2 x2, with the fused
+// multiply-adds written out so every code path rounds the same way.
+__device__ inline double dot3(double b0, double b1, double b2, double x0, double x1, double x2) {
+    return __builtin_fma(b2, x2, __builtin_fma(b1, x1, b0 * x0));
+}
+__device__ inline float dot3(float b0, float b1, float b2, float x0, float x1, float x2) {
+    return __builtin_fmaf(b2, x2, __builtin_fmaf(b1, x1, b0 * x0));
+}
 
 // Lane geometry of the row kernels.
 struct RowLane {
@@ -121,10 +203,11 @@ struct RowLane {
     bool act;
 };
 
+template <int W>
 __device__ inline RowLane row_lane(int bx, int q0, int q1) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     RowLane L;
-    L.q = q0 + bx * kRowsPerBlock + w * kRowsPerWave + lane / 3;
+    L.q = q0 + bx * (W * kRowsPerWave) + w * kRowsPerWave + lane / 3;
     L.r = lane % 3;
     L.base = lane - L.r;
     L.act = lane < 63 && L.q < q1;
@@ -134,11 +217,12 @@ __device__ inline RowLane row_lane(int bx, int q0, int q1) {
 // LDS image of up to CAP consecutive 3x3 blocks and their column indices.
 // Values are copied in aligned 16-byte units; `shift` is the offset (in
 // elements) of the first block inside the first unit.
-template <typename T, int CAP>
+template <typename T, int CAP, int NT = kRowThreads>
 struct Stage {
+    static constexpr int kThreads = NT;
     static constexpr int kUnits = (CAP * 9 * (int)sizeof(T) + 15) / 16 + 1;
-    static constexpr int kPerThread = (kUnits + kRowThreads - 1) / kRowThreads;
-    static constexpr int kColsPerThread = (CAP + kRowThreads - 1) / kRowThreads;
+    static constexpr int kPerThread = (kUnits + NT - 1) / NT;
+    static constexpr int kColsPerThread = (CAP + NT - 1) / NT;
     uint4 v[kUnits];
     int32_t c[CAP];
 };
@@ -149,24 +233,24 @@ struct Stage {
 // the last unit with the same data), so the compiler cannot sink a load
 // into a branch and serialise the copy.  Reads stay inside the 16-byte
 // units that overlap the range (allocations are padded for that).
-template <typename T, int CAP>
+template <typename T, int CAP, int NT>
 __device__ inline int stage_copy(const T *__restrict__ val, const int32_t *__restrict__ col, int base, int cnt,
-                                 Stage<T, CAP> &st) {
-    using S = Stage<T, CAP>;
+                                 Stage<T, CAP, NT> &st) {
+    using S = Stage<T, CAP, NT>;
     const char *first = (const char *)(val + (size_t)base * 9);
     const int mis = (int)((uintptr_t)first & 15);
     const uint4 *src = (const uint4 *)(first - mis);
     const int units = (mis + cnt * 9 * (int)sizeof(T) + 15) / 16;
     uint4 t[S::kPerThread];
 #pragma unroll
-    for (int u = 0; u < S::kPerThread; ++u) t[u] = src[min(u * kRowThreads + (int)threadIdx.x, units - 1)];
+    for (int u = 0; u < S::kPerThread; ++u) t[u] = src[min(u * NT + (int)threadIdx.x, units - 1)];
     int32_t c[S::kColsPerThread];
 #pragma unroll
-    for (int u = 0; u < S::kColsPerThread; ++u) c[u] = col[base + min(u * kRowThreads + (int)threadIdx.x, cnt - 1)];
+    for (int u = 0; u < S::kColsPerThread; ++u) c[u] = col[base + min(u * NT + (int)threadIdx.x, cnt - 1)];
 #pragma unroll
-    for (int u = 0; u < S::kPerThread; ++u) st.v[min(u * kRowThreads + (int)threadIdx.x, units - 1)] = t[u];
+    for (int u = 0; u < S::kPerThread; ++u) st.v[min(u * NT + (int)threadIdx.x, units - 1)] = t[u];
 #pragma unroll
-    for (int u = 0; u < S::kColsPerThread; ++u) st.c[min(u * kRowThreads + (int)threadIdx.x, cnt - 1)] = c[u];
+    for (int u = 0; u < S::kColsPerThread; ++u) st.c[min(u * NT + (int)threadIdx.x, cnt - 1)] = c[u];
     return mis / (int)sizeof(T);
 }
 
@@ -191,7 +275,39 @@ __device__ inline T walk_pass(const T *sv, const int32_t *sc, int shift, int bas
         for (int u = 0; u < 8; ++u)
             if (e + u < hi) {
                 const T *b = sv + shift + (e + u - base) * 9 + 3 * r;
-                const T s = b[0] * (T)xv[u][0] + b[1] * (T)xv[u][1] + b[2] * (T)xv[u][2];
+                const T s = dot3(b[0], b[1], b[2], (T)xv[u][0], (T)xv[u][1], (T)xv[u][2]);
+                if (SUB) acc -= s; else acc += s;
+            }
+    }
+    return acc;
+}
+
+// The same sum with blocks and column indices read straight from global
+// memory (no LDS): each lane loads its 24-byte row slice of 8 blocks, their
+// columns, then the x entries, before any arithmetic.
+template <bool SUB, typename T, typename TX>
+__device__ inline T direct_walk(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                const T *__restrict__ val, const RowLane &L, const TX *__restrict__ x, T acc) {
+    if (!L.act) return acc;
+    const int my0 = ptr[L.q], my1 = ptr[L.q + 1];
+    for (int e = my0; e < my1; e += 8) {
+        int j[8];
+        T b[8][3];
+        TX xv[8][3];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int ee = min(e + u, my1 - 1);
+            j[u] = col[ee];
+            const T *bp = val + (size_t)ee * 9 + 3 * L.r;
+            b[u][0] = bp[0]; b[u][1] = bp[1]; b[u][2] = bp[2];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            for (int c = 0; c < 3; ++c) xv[u][c] = x[3 * j[u] + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (e + u < my1) {
+                const T s = dot3(b[u][0], b[u][1], b[u][2], (T)xv[u][0], (T)xv[u][1], (T)xv[u][2]);
                 if (SUB) acc -= s; else acc += s;
             }
     }
@@ -199,16 +315,16 @@ __device__ inline T walk_pass(const T *sv, const int32_t *sc, int shift, int bas
 }
 
 // Walk the blocks of this lane's row, staged through LDS pass by pass.
-template <int CAP, bool SUB, typename T, typename TX>
+template <int CAP, bool SUB, typename T, typename TX, int NT>
 __device__ inline T stage_walk(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
                                const T *__restrict__ val, int qb0, int qb1, const RowLane &L, const TX *__restrict__ x,
-                               T acc, Stage<T, CAP> &st) {
+                               T acc, Stage<T, CAP, NT> &st) {
     const int e0 = ptr[qb0], e1 = ptr[qb1];
     const int my0 = L.act ? ptr[L.q] : 0, my1 = L.act ? ptr[L.q + 1] : 0;
     for (int base = e0; base < e1; base += CAP) {
         const int cnt = min(CAP, e1 - base);
         __syncthreads();
-        const int shift = stage_copy<T, CAP>(val, col, base, cnt, st);
+        const int shift = stage_copy<T, CAP, NT>(val, col, base, cnt, st);
         __syncthreads();
         acc = walk_pass<SUB, false>((const T *)st.v, st.c, shift, base, max(my0, base), min(my1, base + cnt), L.r,
                                     x, acc);
@@ -216,8 +332,23 @@ __device__ inline T stage_walk(const int32_t *__restrict__ ptr, const int32_t *_
     return acc;
 }
 
-constexpr int kSpmvCap = 640;   // 46 KB of FP64 blocks
-constexpr int kSweepCap = 320;
+// LDS capacity (blocks) per pass: 160 (SpMV) or 80 (sweeps) per wave.
+constexpr int kSpmvCapPerWave = 160;
+constexpr int kSweepCapPerWave = 80;
+constexpr int kSweepCap = 4 * kSweepCapPerWave;   // single-launch sweeps: 4-wave workgroups
+
+// Row walk of a workgroup of W waves: staged through LDS or direct.
+template <int W, bool STAGE, int CAPW, bool SUB, typename T, typename TX>
+__device__ inline T row_walk(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                             const T *__restrict__ val, int qb0, int qb1, const RowLane &L, const TX *__restrict__ x,
+                             T acc) {
+    if constexpr (STAGE) {
+        __shared__ Stage<T, CAPW * W, 64 * W> sv;
+        return stage_walk<CAPW * W, SUB>(ptr, col, val, qb0, qb1, L, x, acc, sv);
+    } else {
+        return direct_walk<SUB>(ptr, col, val, L, x, acc);
+    }
+}
 
 // ------------------------------------------------------------------ gather
 
@@ -243,7 +374,7 @@ __global__ void k_factor_level(DevSchedule d, const double *__restrict__ Ap, dou
                                int q1) {
     int sys, bx;
     xcd_map(sys, bx);
-    const RowLane rl = row_lane(bx, q0, q1);
+    const RowLane rl = row_lane<kWavesPerBlock>(bx, q0, q1);
     const double *A = Ap + (size_t)sys * d.nnzb * 9;
     double *Ls = L + (size_t)sys * d.nL * 9;
     double *Us = U + (size_t)sys * d.nU * 9;
@@ -311,18 +442,17 @@ __global__ void k_to_fp32(const double *__restrict__ src, float *__restrict__ ds
 
 // ------------------------------------------------------------------ sweeps
 
-template <typename T, bool FUSE_P>
-__global__ void __launch_bounds__(kRowThreads) k_lsweep(DevSchedule d, const T *__restrict__ L, size_t l_stride,
+template <typename T, bool FUSE_P, int W, bool STAGE>
+__global__ void __launch_bounds__(64 * W) k_lsweep(DevSchedule d, const T *__restrict__ L, size_t l_stride,
                                                         const double *__restrict__ in, T *__restrict__ y,
                                                         size_t vstride, const double *__restrict__ rv,
                                                         const double *__restrict__ vv, double *__restrict__ pv,
                                                         SysState *__restrict__ st, int q0, int q1) {
-    __shared__ Stage<T, kSweepCap> sv;
     int sys, bx;
     xcd_map(sys, bx);
     if (st && st[sys].phase != PH_RUN) return;
-    const RowLane rl = row_lane(bx, q0, q1);
-    const int qb0 = q0 + bx * kRowsPerBlock, qb1 = min(qb0 + kRowsPerBlock, q1);
+    const RowLane rl = row_lane<W>(bx, q0, q1);
+    const int qb0 = q0 + bx * W * kRowsPerWave, qb1 = min(qb0 + W * kRowsPerWave, q1);
     const size_t vo = (size_t)sys * vstride;
     const int i = rl.act ? d.lrows[rl.q] : 0;
     T acc = 0;
@@ -337,25 +467,26 @@ __global__ void __launch_bounds__(kRowThreads) k_lsweep(DevSchedule d, const T *
             acc = (T)in[k];
         }
     }
-    acc = stage_walk<kSweepCap, true>(d.lptr, d.lcol, L + (size_t)sys * l_stride, qb0, qb1, rl, y + vo, acc, sv);
+    acc = row_walk<W, STAGE, kSweepCapPerWave, true>(d.lptr, d.lcol, L + (size_t)sys * l_stride, qb0, qb1, rl, y + vo,
+                                                     acc);
     if (rl.act) y[vo + 3 * (size_t)i + rl.r] = acc;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kRowThreads) k_usweep(DevSchedule d, const T *__restrict__ U, size_t u_stride,
+template <typename T, int W, bool STAGE>
+__global__ void __launch_bounds__(64 * W) k_usweep(DevSchedule d, const T *__restrict__ U, size_t u_stride,
                                                         const T *__restrict__ Dinv, size_t d_stride,
                                                         const T *__restrict__ y, double *__restrict__ z,
                                                         size_t vstride, SysState *__restrict__ st, int q0, int q1) {
-    __shared__ Stage<T, kSweepCap> sv;
     int sys, bx;
     xcd_map(sys, bx);
     if (st && st[sys].phase != PH_RUN) return;
-    const RowLane rl = row_lane(bx, q0, q1);
-    const int qb0 = q0 + bx * kRowsPerBlock, qb1 = min(qb0 + kRowsPerBlock, q1);
+    const RowLane rl = row_lane<W>(bx, q0, q1);
+    const int qb0 = q0 + bx * W * kRowsPerWave, qb1 = min(qb0 + W * kRowsPerWave, q1);
     const size_t vo = (size_t)sys * vstride;
     const int i = rl.act ? d.urows[rl.q] : 0;
     T acc = rl.act ? y[vo + 3 * (size_t)i + rl.r] : (T)0;
-    acc = stage_walk<kSweepCap, true>(d.uptr, d.ucol, U + (size_t)sys * u_stride, qb0, qb1, rl, z + vo, acc, sv);
+    acc = row_walk<W, STAGE, kSweepCapPerWave, true>(d.uptr, d.ucol, U + (size_t)sys * u_stride, qb0, qb1, rl, z + vo,
+                                                     acc);
     const T t0 = __shfl(acc, rl.base, 64), t1 = __shfl(acc, rl.base + 1, 64), t2 = __shfl(acc, rl.base + 2, 64);
     if (!rl.act) return;
     const T *dq = Dinv + (size_t)sys * d_stride + (size_t)rl.q * 9 + 3 * rl.r;
@@ -442,13 +573,13 @@ __global__ void __launch_bounds__(kRowThreads) k_lsweep_tiles(DevSchedule d, con
     while (next_item(ctr, total, nsys, w)) {
         if (st && st[w.sys].phase != PH_RUN) continue;
         const int q0 = d.lt_start[w.tile], q1 = d.lt_start[w.tile + 1];
-        const RowLane rl = row_lane(0, q0, q1);
+        const RowLane rl = row_lane<kWavesPerBlock>(0, q0, q1);
         const size_t vo = (size_t)w.sys * vstride;
         const T *Ls = L + (size_t)w.sys * l_stride;
         const int e0 = d.lptr[q0], e1 = d.lptr[q1];
         const int my0 = rl.act ? d.lptr[rl.q] : 0, my1 = rl.act ? d.lptr[rl.q + 1] : 0;
         int cnt = min(kSweepCap, e1 - e0), shift = 0;
-        if (cnt > 0) shift = stage_copy<T, kSweepCap>(Ls, d.lcol, e0, cnt, sv);
+        if (cnt > 0) shift = stage_copy<T, kSweepCap, kRowThreads>(Ls, d.lcol, e0, cnt, sv);
         const int i = rl.act ? d.lrows[rl.q] : 0;
         T acc = 0;
         if (rl.act) {
@@ -468,7 +599,7 @@ __global__ void __launch_bounds__(kRowThreads) k_lsweep_tiles(DevSchedule d, con
             if (base != e0) {
                 cnt = min(kSweepCap, e1 - base);
                 __syncthreads();
-                shift = stage_copy<T, kSweepCap>(Ls, d.lcol, base, cnt, sv);
+                shift = stage_copy<T, kSweepCap, kRowThreads>(Ls, d.lcol, base, cnt, sv);
                 __syncthreads();
             }
             acc = walk_pass<true, true>((const T *)sv.v, sv.c, shift, base, max(my0, base), min(my1, base + cnt),
@@ -494,13 +625,13 @@ __global__ void __launch_bounds__(kRowThreads) k_usweep_tiles(DevSchedule d, con
     while (next_item(ctr, total, nsys, w)) {
         if (st && st[w.sys].phase != PH_RUN) continue;
         const int q0 = d.ut_start[w.tile], q1 = d.ut_start[w.tile + 1];
-        const RowLane rl = row_lane(0, q0, q1);
+        const RowLane rl = row_lane<kWavesPerBlock>(0, q0, q1);
         const size_t vo = (size_t)w.sys * vstride;
         const T *Us = U + (size_t)w.sys * u_stride;
         const int e0 = d.uptr[q0], e1 = d.uptr[q1];
         const int my0 = rl.act ? d.uptr[rl.q] : 0, my1 = rl.act ? d.uptr[rl.q + 1] : 0;
         int cnt = min(kSweepCap, e1 - e0), shift = 0;
-        if (cnt > 0) shift = stage_copy<T, kSweepCap>(Us, d.ucol, e0, cnt, sv);
+        if (cnt > 0) shift = stage_copy<T, kSweepCap, kRowThreads>(Us, d.ucol, e0, cnt, sv);
         const int i = rl.act ? d.urows[rl.q] : 0;
         T acc = rl.act ? y[vo + 3 * (size_t)i + rl.r] : (T)0;
         T dq[3] = {0, 0, 0};
@@ -514,7 +645,7 @@ __global__ void __launch_bounds__(kRowThreads) k_usweep_tiles(DevSchedule d, con
             if (base != e0) {
                 cnt = min(kSweepCap, e1 - base);
                 __syncthreads();
-                shift = stage_copy<T, kSweepCap>(Us, d.ucol, base, cnt, sv);
+                shift = stage_copy<T, kSweepCap, kRowThreads>(Us, d.ucol, base, cnt, sv);
                 __syncthreads();
             }
             acc = walk_pass<true, true>((const T *)sv.v, sv.c, shift, base, max(my0, base), min(my1, base + cnt),
@@ -538,60 +669,86 @@ enum SpmvMode { SPMV_PLAIN = 0, SPMV_V = 1, SPMV_T = 2, SPMV_TRUE = 3 };
 //   SPMV_V:    v = A phat, reduce (rhat, v), alpha = rho / (rhat, v)
 //   SPMV_T:    t = A shat, reduce (t, s) and (t, t), omega = (t, s) / (t, t)
 //   SPMV_TRUE: reduce ||b - A x||^2 and ||b||^2, true relative residual
-template <int MODE>
-__global__ void __launch_bounds__(kRowThreads) k_spmv(int n, const int32_t *__restrict__ ptr,
+template <int MODE, int W, bool STAGE>
+__global__ void __launch_bounds__(64 * W) k_spmv(int n, const int32_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ col, const double *__restrict__ A,
                                                       size_t a_stride, const double *__restrict__ x,
                                                       double *__restrict__ y, size_t vstride,
                                                       const double *__restrict__ w1, const double *__restrict__ w2,
                                                       double *__restrict__ part, size_t part_stride,
+                                                      uint32_t *__restrict__ tk, size_t tk_stride,
                                                       SysState *__restrict__ st) {
-    __shared__ Stage<double, kSpmvCap> sv;
     int sys, bx;
     xcd_map(sys, bx);
     if (MODE != SPMV_PLAIN && MODE != SPMV_TRUE && st[sys].phase != PH_RUN) return;
-    const RowLane rl = row_lane(bx, 0, n);
-    const int qb0 = bx * kRowsPerBlock, qb1 = min(qb0 + kRowsPerBlock, n);
+    // workgroup bx walks row tiles [bx * per, (bx + 1) * per); per = 1 with
+    // one workgroup per tile
+    constexpr int R = W * kRowsPerWave;
+    const int ntiles = (n + R - 1) / R;
+    const int per = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int t0 = bx * per, t1 = min(t0 + per, ntiles);
     const size_t vo = (size_t)sys * vstride;
-    double acc = stage_walk<kSpmvCap, false>(ptr, col, A + (size_t)sys * a_stride, qb0, qb1, rl, x + vo, 0.0, sv);
-    const size_t k = vo + 3 * (size_t)rl.q + rl.r;
-    if (MODE == SPMV_PLAIN) {
-        if (rl.act) y[k] = acc;
-        return;
+    const double *As = A + (size_t)sys * a_stride;
+    double v[2] = {0.0, 0.0};
+    for (int t = t0; t < t1; ++t) {
+        const RowLane rl = row_lane<W>(t, 0, n);
+        const int qb0 = t * R, qb1 = min(qb0 + R, n);
+        const double acc = row_walk<W, STAGE, kSpmvCapPerWave, false>(ptr, col, As, qb0, qb1, rl, x + vo, 0.0);
+        const size_t k = vo + 3 * (size_t)rl.q + rl.r;
+        if (!rl.act) continue;
+        if (MODE == SPMV_PLAIN) {
+            y[k] = acc;
+        } else if (MODE == SPMV_V || MODE == SPMV_T) {
+            y[k] = acc;
+            v[0] += w1[k] * acc;
+            v[1] += acc * acc;
+        } else {  // SPMV_TRUE: w1 = b
+            const double res = w1[k] - acc;
+            v[0] += res * res;
+            v[1] += w1[k] * w1[k];
+        }
     }
-    if (MODE == SPMV_V) {
-        double v[1] = {0.0};
-        if (rl.act) { y[k] = acc; v[0] = w1[k] * acc; }
-        if (grid_reduce<1>(v, part + sys * part_stride, &st[sys].ticket, gridDim.x, bx) && threadIdx.x == 0) {
-            SysState &S = st[sys];
-            const double rv = v[0];
-            if (!finite(rv)) { S.status = RS_NON_FINITE; S.phase = PH_DONE; }
-            else if (rv == 0.0) { S.status = RS_BREAKDOWN; S.phase = PH_DONE; }
-            else S.alpha = S.rho / rv;
-        }
-    } else if (MODE == SPMV_T) {
-        double v[2] = {0.0, 0.0};
-        if (rl.act) { y[k] = acc; v[0] = acc * w1[k]; v[1] = acc * acc; }
-        if (grid_reduce<2>(v, part + sys * part_stride, &st[sys].ticket, gridDim.x, bx) && threadIdx.x == 0) {
-            SysState &S = st[sys];
-            const double ts = v[0], tt = v[1];
-            if (!finite(ts) || !finite(tt)) { S.status = RS_NON_FINITE; S.phase = PH_DONE; }
-            else if (tt == 0.0) { S.status = RS_BREAKDOWN; S.phase = PH_DONE; }
-            else {
-                S.omega = ts / tt;
-                if (S.omega == 0.0) { S.status = RS_BREAKDOWN; S.phase = PH_HALF; }
-            }
-        }
-    } else {  // SPMV_TRUE: w1 = b
-        double v[2] = {0.0, 0.0};
-        if (rl.act) { const double res = w1[k] - acc; v[0] = res * res; v[1] = w1[k] * w1[k]; }
-        if (grid_reduce<2>(v, part + sys * part_stride, &st[sys].ticket, gridDim.x, bx) && threadIdx.x == 0) {
-            st[sys].true_res = v[1] > 0.0 ? sqrt(v[0]) / sqrt(v[1]) : 0.0;
-        }
+    if (MODE == SPMV_PLAIN) return;
+    if (MODE == SPMV_V || MODE == SPMV_T) {
+        // group sums of (rhat, v) or of (t, s) and (t, t); the next kernel
+        // adds the group sums (kernel boundary: no serial tail here)
+        group_reduce<2>(v, part + sys * part_stride, tk + sys * tk_stride, gridDim.x, bx);
+    } else if (grid_reduce<2>(v, part + sys * part_stride, tk + sys * tk_stride, gridDim.x, bx) &&
+               threadIdx.x == 0) {
+        st[sys].true_res = v[1] > 0.0 ? sqrt(v[0]) / sqrt(v[1]) : 0.0;
     }
 }
 
 // ---------------------------------------------------------------- vectors
+
+// Sum the NV-wide partials of nblk workgroups of the previous kernel, the
+// same way in every workgroup (thread-strided sums, then the block tree), and
+// hand the totals to every thread.
+template <int NV>
+__device__ inline void sum_partials(const double *__restrict__ p, int nblk, double (&out)[NV]) {
+    __shared__ double lds[16 * NV];
+    __shared__ double tot[NV];
+    double acc[NV];
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    constexpr int U = 4;
+    for (int b0 = 0; b0 < nblk; b0 += U * (int)blockDim.x) {
+        double t[U][NV];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = min(b0 + u * (int)blockDim.x + (int)threadIdx.x, nblk - 1);
+            for (int k = 0; k < NV; ++k) t[u][k] = p[(size_t)b * NV + k];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (b0 + u * (int)blockDim.x + (int)threadIdx.x < nblk)
+                for (int k = 0; k < NV; ++k) acc[k] += t[u][k];
+    }
+    block_sum<NV>(acc, lds);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NV; ++k) tot[k] = acc[k];
+    __syncthreads();
+    for (int k = 0; k < NV; ++k) out[k] = tot[k];
+}
 
 // Vector kernels: each thread handles kVecItems entries of a 1024-entry
 // tile, all loads of a tile issued before the arithmetic; tiles are
@@ -622,7 +779,7 @@ __global__ void __launch_bounds__(kVecThreads) k_setup(int n, const int32_t *__r
             v[0] += val[u] * val[u];
         }
     }
-    if (grid_reduce<1>(v, k.part + sys * k.part_stride, &k.st[sys].ticket, gridDim.x, bx) && threadIdx.x == 0) {
+    if (grid_reduce<1>(v, k.part + sys * k.part_stride, k.tickets + sys * k.ticket_stride, gridDim.x, bx) && threadIdx.x == 0) {
         SysState &S = k.st[sys];
         const double r0 = sqrt(v[0]);
         S.r0norm = r0; S.tol = reduction * r0; S.last_norm = r0;
@@ -637,12 +794,25 @@ __global__ void __launch_bounds__(kVecThreads) k_setup(int n, const int32_t *__r
     }
 }
 
-// s = r - alpha v, ||s||; half-step test.
-__global__ void __launch_bounds__(kVecThreads) k_s_update(Krylov k) {
+// alpha = rho / (rhat, v) from the partials of v = A phat; s = r - alpha v,
+// ||s||; half-step test.
+__global__ void __launch_bounds__(kVecThreads) k_s_update(Krylov k, int spmv_blocks) {
     const int sys = blockIdx.y, bx = blockIdx.x;
     SysState &S = k.st[sys];
     if (S.phase != PH_RUN) return;
-    const double alpha = S.alpha;
+    double rvv[2];
+    sum_partials<2>(k.spart + sys * k.spart_stride + 2 * (size_t)spmv_blocks, (spmv_blocks + kGroup - 1) / kGroup,
+                    rvv);
+    const double rv = rvv[0];
+    if (!finite(rv) || rv == 0.0) {
+        if (bx == 0 && threadIdx.x == 0) {
+            S.status = finite(rv) ? RS_BREAKDOWN : RS_NON_FINITE;
+            S.phase = PH_DONE;
+        }
+        return;
+    }
+    const double alpha = S.rho / rv;
+    if (bx == 0 && threadIdx.x == 0) S.alpha = alpha;
     const size_t vo = (size_t)sys * k.vstride, tiles = k.vstride / kVecTile;
     double v[1] = {0.0};
     for (size_t t = bx; t < tiles; t += gridDim.x) {
@@ -657,7 +827,7 @@ __global__ void __launch_bounds__(kVecThreads) k_s_update(Krylov k) {
             v[0] += sv * sv;
         }
     }
-    if (grid_reduce<1>(v, k.part + sys * k.part_stride, &S.ticket, gridDim.x, bx) && threadIdx.x == 0) {
+    if (grid_reduce<1>(v, k.part + sys * k.part_stride, k.tickets + sys * k.ticket_stride, gridDim.x, bx) && threadIdx.x == 0) {
         const double sn = sqrt(v[0]);
         S.half_steps = 2 * S.iter - 1;
         S.last_norm = sn;
@@ -669,12 +839,35 @@ __global__ void __launch_bounds__(kVecThreads) k_s_update(Krylov k) {
 // Full step: x += alpha phat + omega shat, r = s - omega t, ||r||, (rhat, r),
 // full-step test, next rho and beta.  After a half-step stop (or an omega
 // breakdown) only x += alpha phat.
-__global__ void __launch_bounds__(kVecThreads) k_xr_update(Krylov k) {
+__global__ void __launch_bounds__(kVecThreads) k_xr_update(Krylov k, int spmv_blocks) {
     const int sys = blockIdx.y, bx = blockIdx.x;
     SysState &S = k.st[sys];
-    const int phase = S.phase;
+    int phase = S.phase;
     if (phase == PH_DONE) return;
-    const double alpha = S.alpha, omega = S.omega;
+    const double alpha = S.alpha;
+    double omega = S.omega;
+    bool omega_zero = false;
+    if (phase == PH_RUN) {
+        // omega = (t, s) / (t, t) from the partials of t = A shat
+        double tv[2];
+        sum_partials<2>(k.spart + sys * k.spart_stride + 2 * (size_t)spmv_blocks,
+                        (spmv_blocks + kGroup - 1) / kGroup, tv);
+        const double ts = tv[0], tt = tv[1];
+        if (!finite(ts) || !finite(tt) || tt == 0.0) {
+            if (bx == 0 && threadIdx.x == 0) {
+                S.status = (finite(ts) && finite(tt)) ? RS_BREAKDOWN : RS_NON_FINITE;
+                S.phase = PH_DONE;
+            }
+            return;
+        }
+        omega = ts / tt;
+        if (omega == 0.0) {
+            // breakdown after the half step: keep x + alpha phat
+            phase = PH_HALF;
+            omega_zero = true;
+        }
+        if (bx == 0 && threadIdx.x == 0) S.omega = omega;
+    }
     const size_t vo = (size_t)sys * k.vstride, tiles = k.vstride / kVecTile;
     double v[2] = {0.0, 0.0};
     for (size_t t = bx; t < tiles; t += gridDim.x) {
@@ -704,8 +897,13 @@ __global__ void __launch_bounds__(kVecThreads) k_xr_update(Krylov k) {
             }
         }
     }
-    if (grid_reduce<2>(v, k.part + sys * k.part_stride, &S.ticket, gridDim.x, bx) && threadIdx.x == 0) {
-        if (phase == PH_HALF) { S.phase = PH_DONE; return; }
+    if (grid_reduce<2>(v, k.part + sys * k.part_stride, k.tickets + sys * k.ticket_stride, gridDim.x, bx) && threadIdx.x == 0) {
+        // every workgroup computed the same omega: use this one's copy
+        if (phase == PH_HALF) {
+            if (omega_zero) S.status = RS_BREAKDOWN;
+            S.phase = PH_DONE;
+            return;
+        }
         const double rn = sqrt(v[0]);
         S.half_steps = 2 * S.iter;
         S.last_norm = rn;
@@ -717,7 +915,7 @@ __global__ void __launch_bounds__(kVecThreads) k_xr_update(Krylov k) {
             S.rho = v[1];
             if (S.rho == 0.0) { S.status = RS_BREAKDOWN; S.phase = PH_DONE; }
             else {
-                S.beta = (S.rho / S.rho_old) * (S.alpha / S.omega);
+                S.beta = (S.rho / S.rho_old) * (alpha / omega);
                 S.iter += 1;
             }
         }
@@ -737,6 +935,22 @@ __global__ void k_permute_vec(const int32_t *__restrict__ perm, const double *__
 }
 
 }  // namespace
+
+// Call f(waves, staged) with compile-time constants for a RowVariant.
+template <typename F>
+static void with_variant(int v, F &&f) {
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I4 = std::integral_constant<int, 4>;
+    switch (v) {
+    case RV_W2_LDS: f(I2{}, std::true_type{}); break;
+    case RV_W1_LDS: f(I1{}, std::true_type{}); break;
+    case RV_W4_DIRECT: f(I4{}, std::false_type{}); break;
+    case RV_W2_DIRECT: f(I2{}, std::false_type{}); break;
+    case RV_W1_DIRECT: f(I1{}, std::false_type{}); break;
+    default: f(I4{}, std::true_type{}); break;
+    }
+}
 
 int vec_blocks(int n) {
     long g = (long)(vec_stride(n) / kVecTile);
@@ -772,30 +986,41 @@ void launch_to_fp32(const double *src, float *dst, size_t count, hipStream_t s) 
 template <typename T>
 void launch_lsweep(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
                    bool fuse_p, const double *r, const double *v, double *p, SysState *st, int q0, int q1, int nsys,
-                   hipStream_t s) {
+                   int variant, hipStream_t s) {
     if (q1 <= q0 || nsys <= 0) return;
-    const dim3 g(row_blocks(q1 - q0), nsys);
-    if (fuse_p) k_lsweep<T, true><<<g, kRowThreads, 0, s>>>(d, L, l_stride, in, y, vstride, r, v, p, st, q0, q1);
-    else k_lsweep<T, false><<<g, kRowThreads, 0, s>>>(d, L, l_stride, in, y, vstride, r, v, p, st, q0, q1);
+    with_variant(variant, [&](auto W, auto ST) {
+        constexpr int w = decltype(W)::value;
+        constexpr bool staged = decltype(ST)::value;
+        const dim3 g(row_blocks(q1 - q0, w), nsys);
+        if (fuse_p)
+            k_lsweep<T, true, w, staged><<<g, 64 * w, 0, s>>>(d, L, l_stride, in, y, vstride, r, v, p, st, q0, q1);
+        else
+            k_lsweep<T, false, w, staged><<<g, 64 * w, 0, s>>>(d, L, l_stride, in, y, vstride, r, v, p, st, q0, q1);
+    });
 }
 
 template <typename T>
 void launch_usweep(const DevSchedule &d, const T *U, size_t u_stride, const T *Dinv, size_t d_stride, const T *y,
-                   double *z, size_t vstride, SysState *st, int q0, int q1, int nsys, hipStream_t s) {
+                   double *z, size_t vstride, SysState *st, int q0, int q1, int nsys, int variant, hipStream_t s) {
     if (q1 <= q0 || nsys <= 0) return;
-    k_usweep<T><<<dim3(row_blocks(q1 - q0), nsys), kRowThreads, 0, s>>>(d, U, u_stride, Dinv, d_stride, y, z, vstride,
-                                                                        st, q0, q1);
+    with_variant(variant, [&](auto W, auto ST) {
+        constexpr int w = decltype(W)::value;
+        constexpr bool staged = decltype(ST)::value;
+        k_usweep<T, w, staged><<<dim3(row_blocks(q1 - q0, w), nsys), 64 * w, 0, s>>>(d, U, u_stride, Dinv, d_stride, y,
+                                                                                   z, vstride, st, q0, q1);
+    });
 }
 
 template void launch_lsweep<double>(const DevSchedule &, const double *, size_t, const double *, double *, size_t,
-                                    bool, const double *, const double *, double *, SysState *, int, int, int,
+                                    bool, const double *, const double *, double *, SysState *, int, int, int, int,
                                     hipStream_t);
 template void launch_lsweep<float>(const DevSchedule &, const float *, size_t, const double *, float *, size_t, bool,
-                                   const double *, const double *, double *, SysState *, int, int, int, hipStream_t);
+                                   const double *, const double *, double *, SysState *, int, int, int, int,
+                                   hipStream_t);
 template void launch_usweep<double>(const DevSchedule &, const double *, size_t, const double *, size_t,
-                                    const double *, double *, size_t, SysState *, int, int, int, hipStream_t);
+                                    const double *, double *, size_t, SysState *, int, int, int, int, hipStream_t);
 template void launch_usweep<float>(const DevSchedule &, const float *, size_t, const float *, size_t, const float *,
-                                   double *, size_t, SysState *, int, int, int, hipStream_t);
+                                   double *, size_t, SysState *, int, int, int, int, hipStream_t);
 
 template <typename T>
 void launch_lsweep_tiles(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
@@ -834,11 +1059,23 @@ template void launch_usweep_tiles<float>(const DevSchedule &, const float *, siz
                                          const float *, double *, size_t, SysState *, int32_t *, SweepCtr *, int,
                                          int, hipStream_t);
 
+template <int MODE>
+static void spmv_any(int variant, int n, const int32_t *ptr, const int32_t *col, const double *A, size_t a_stride,
+                     const double *x, double *y, size_t vstride, const double *w1, double *part, size_t part_stride,
+                     uint32_t *tk, size_t tk_stride, SysState *st, int nsys, hipStream_t s) {
+    with_variant(variant, [&](auto W, auto ST) {
+        constexpr int w = decltype(W)::value;
+        constexpr bool staged = decltype(ST)::value;
+        k_spmv<MODE, w, staged><<<dim3(spmv_grid(n, w), nsys), 64 * w, 0, s>>>(
+            n, ptr, col, A, a_stride, x, y, vstride, w1, nullptr, part, part_stride, tk, tk_stride, st);
+    });
+}
+
 void launch_spmv(int n, const int32_t *ptr, const int32_t *col, const double *A, size_t a_stride, const double *x,
-                 double *y, size_t vstride, int nsys, hipStream_t s) {
+                 double *y, size_t vstride, int nsys, int variant, hipStream_t s) {
     if (n <= 0 || nsys <= 0) return;
-    k_spmv<SPMV_PLAIN><<<dim3(row_blocks(n), nsys), kRowThreads, 0, s>>>(n, ptr, col, A, a_stride, x, y, vstride,
-                                                                        nullptr, nullptr, nullptr, 0, nullptr);
+    spmv_any<SPMV_PLAIN>(variant, n, ptr, col, A, a_stride, x, y, vstride, nullptr, nullptr, 0, nullptr, 0, nullptr,
+                         nsys, s);
 }
 
 void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad, double reduction, int max_iter,
@@ -846,22 +1083,24 @@ void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad
     k_setup<<<dim3(vec_blocks(d.n), nsys), kVecThreads, 0, s>>>(d.n, d.perm, b_orig, k, bad, reduction, max_iter);
 }
 
-void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, hipStream_t s) {
-    k_spmv<SPMV_V><<<dim3(row_blocks(d.n), nsys), kRowThreads, 0, s>>>(
-        d.n, d.prow, d.pcol, Ap, a_stride, k.phat, k.v, k.vstride, k.rhat, nullptr, k.part, k.part_stride, k.st);
+void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
+                   hipStream_t s) {
+    spmv_any<SPMV_V>(variant, d.n, d.prow, d.pcol, Ap, a_stride, k.phat, k.v, k.vstride, k.rhat, k.spart,
+                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, s);
 }
 
-void launch_s_update(int n, Krylov &k, int nsys, hipStream_t s) {
-    k_s_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(k);
+void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, hipStream_t s) {
+    k_s_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(k, spmv_grid(n, variant_waves(spmv_variant)));
 }
 
-void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, hipStream_t s) {
-    k_spmv<SPMV_T><<<dim3(row_blocks(d.n), nsys), kRowThreads, 0, s>>>(
-        d.n, d.prow, d.pcol, Ap, a_stride, k.shat, k.t, k.vstride, k.s, nullptr, k.part, k.part_stride, k.st);
+void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
+                   hipStream_t s) {
+    spmv_any<SPMV_T>(variant, d.n, d.prow, d.pcol, Ap, a_stride, k.shat, k.t, k.vstride, k.s, k.spart,
+                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, s);
 }
 
-void launch_xr_update(int n, Krylov &k, int nsys, hipStream_t s) {
-    k_xr_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(k);
+void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, hipStream_t s) {
+    k_xr_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(k, spmv_grid(n, variant_waves(spmv_variant)));
 }
 
 void launch_permute_vec(const int32_t *perm, const double *in, double *out, int n, size_t vstride, int nsys,
@@ -872,12 +1111,12 @@ void launch_permute_vec(const int32_t *perm, const double *in, double *out, int 
 }
 
 void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *colidx, const double *A,
-                   size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, hipStream_t s) {
+                   size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, int variant,
+                   hipStream_t s) {
     if (d.n <= 0 || nsys <= 0) return;
     launch_permute_vec(d.perm, k.x, x_orig, d.n, k.vstride, nsys, true, s);
-    k_spmv<SPMV_TRUE><<<dim3(row_blocks(d.n), nsys), kRowThreads, 0, s>>>(
-        d.n, rowptr, colidx, A, a_stride, x_orig, nullptr, 3 * (size_t)d.n, b_orig, nullptr, k.part, k.part_stride,
-        k.st);
+    spmv_any<SPMV_TRUE>(variant, d.n, rowptr, colidx, A, a_stride, x_orig, nullptr, 3 * (size_t)d.n, b_orig, k.part,
+                        k.part_stride, k.tickets, k.ticket_stride, k.st, nsys, s);
 }
 
 }  // namespace rs

@@ -233,6 +233,60 @@ def test_graph_replays_equal_eager(solver_of, ordering, precision):
         rs.rsolve_profile_enable(0)
 
 
+def test_row_variants(solver_of):
+    """Every launch shape (waves per workgroup, LDS staging or direct loads)
+    of the SpMV and of the per-level sweeps does the same arithmetic: plain
+    SpMV and sweeps are bit-identical across shapes.  The SpMV shape also
+    sets the number of partial sums of the fused dot products, so solves
+    under different SpMV shapes agree to rounding (each one deterministic)."""
+    s = CASES["nnc"]
+    A, M, _, _ = solver_of(s, rs.ORDER_GRAPH_COLOUR)
+    x = np.random.default_rng(4).standard_normal((1, s.n, 3))
+    ref_y = None
+    for v in range(rs.N_ROW_VARIANTS):
+        rs.bcsr_set_option(A, rs.OPT_SPMV_VARIANT, v)
+        y = rs.bcsr_spmv(A, x)
+        ref_y = y if ref_y is None else ref_y
+        assert np.array_equal(y, ref_y), v
+    ref = None
+    for v in range(rs.N_ROW_VARIANTS):
+        rs.ilu0_set_option(M, rs.OPT_SWEEP_VARIANT, v)
+        z = rs.ilu0_apply(M, x)
+        xs, st, info = rs.bicgstab_solve(M, A, s.b[0], reduction=1e-9)
+        ref = (z, xs, info) if ref is None else ref
+        assert np.array_equal(z, ref[0]) and np.array_equal(xs, ref[1]) and info == ref[2], v
+    for v in range(rs.N_ROW_VARIANTS):
+        rs.ilu0_set_option(M, rs.OPT_SPMV_VARIANT, v)
+        xs, st, info = rs.bicgstab_solve(M, A, s.b[0], reduction=1e-9)
+        xs2, _, info2 = rs.bicgstab_solve(M, A, s.b[0], reduction=1e-9)
+        assert np.array_equal(xs, xs2) and info == info2, v
+        assert np.linalg.norm(xs - ref[1]) <= 1e-10 * np.linalg.norm(ref[1]), v
+        assert abs(info[0]["half_steps"] - ref[2][0]["half_steps"]) <= 1, v
+    with pytest.raises(rs.RsolveError):
+        rs.ilu0_set_option(M, rs.OPT_SPMV_VARIANT, rs.N_ROW_VARIANTS)
+
+
+def test_autotune_picks_valid_config_and_caches(solver_of, tmp_path, monkeypatch):
+    s = make_ensemble(13, 11, 9, seeds=[5, 6, 7])
+    A, M, _, _ = solver_of(s, rs.ORDER_GRAPH_COLOUR, rs.PREC_FP32_FACTORS)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("RSOLVE_TUNE_CACHE", str(cache))
+    r = rs.ilu0_autotune(M, A, s.b[:, 0], reduction=1e-2, reps=1)
+    assert r["from_cache"] == 0 and r["candidates"] >= 10 and r["us_per_solve"] > 0
+    assert rs.ilu0_get_option(M, rs.OPT_SPMV_VARIANT) == r["spmv_variant"]
+    assert rs.ilu0_get_option(M, rs.OPT_SWEEP_TILES) == r["sweep_tiles"]
+    x, st, info = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-8)
+    for k in range(3):
+        xo, _ = oracle.solve(s.rowptr, s.colidx, s.vals[k], s.b[k, 0], ordering=rs.ORDER_GRAPH_COLOUR,
+                             precond=oracle.PREC_ILU_F32, reduction=1e-8)
+        assert np.linalg.norm(x[k] - xo) <= 1e-6 * np.linalg.norm(xo)
+    assert cache.exists() and cache.read_text().count("\n") == 1
+    rs.ilu0_set_option(M, rs.OPT_SPMV_VARIANT, (r["spmv_variant"] + 1) % rs.N_ROW_VARIANTS)
+    r2 = rs.ilu0_autotune(M, A, s.b[:, 0], reduction=1e-2, reps=1)
+    assert r2["from_cache"] == 1 and r2["spmv_variant"] == r["spmv_variant"]
+    assert rs.ilu0_get_option(M, rs.OPT_SPMV_VARIANT) == r["spmv_variant"]
+
+
 @pytest.mark.parametrize("grid", [1, 3, 64])
 def test_tiled_sweep_small_grids(solver_of, grid):
     """Fewer workgroups than tiles: each workgroup walks many tiles in ticket order."""
