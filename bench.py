@@ -39,6 +39,11 @@ WORKLOADS = {
     "c4": dict(desc="64 same-pattern realisations of a 40x40x30 grid (48000 cells each), lognormal sigma=1; "
                     "1 batched ILU0 factorisation + 1 batched solve of all 64 per step", rhs=1, precision="fp32",
                reduction=1e-2),
+    "c5": dict(desc="request stream: Poisson arrivals of single solves, sizes uniform over 10k (25x20x20), "
+                    "50k (50x50x20), 200k (100x100x20) and 1M (100x100x100) cells, lognormal sigma=1, 5% of "
+                    "requests also carry 2% non-neighbour connections; each request = upload values + ILU0 "
+                    "factorisation + 1 solve; FP32 factors in FP64 BiCGStab; HBM budget 200 GB",
+               rhs=1, precision="fp32", reduction=1e-2),
 }
 ORDER = {"natural": 0, "level": 1, "colour": 2}
 PREC = {"fp64": 0, "fp32": 1}
@@ -62,6 +67,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-configuration autotuner")
+    ap.add_argument("--slots", type=int, default=8, help="request stream: concurrent worker slots")
+    ap.add_argument("--requests", type=int, default=2000, help="request stream: requests per arrival rate")
+    ap.add_argument("--loads", default="0.5,0.8,1.0",
+                    help="request stream: arrival rates as fractions of the measured saturated rate")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-sized buffer with torch (a kernel of known traffic, "
                          "used to scale rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -126,6 +135,10 @@ def main():
         print(json.dumps({"error": "this build measures one GPU only: the solver runs on a single MI355X; "
                                    "run bench.py with --gpus 1"}), flush=True)
         sys.exit(2)
+
+    if args.workload == "c5":
+        serve(args)
+        return
 
     import numpy as np
     import torch
@@ -235,6 +248,204 @@ def main():
                    "mean_half_steps": float(np.mean(half_steps)), "max_true_rel_residual": float(max(true_res)),
                    "launch_config": tune},
         "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+# ----------------------------------------------------------------- serving
+
+def solve_bytes(n, nnzb, half_steps, precision):
+    """Algorithmic HBM bytes of one request: value upload (device copy), ILU0
+    factorisation, BiCGStab half-steps and the true-residual SpMV."""
+    per_iter = (304 if precision == "fp64" else 232) * nnzb + 712 * n
+    factor = 148 * nnzb + (108 * nnzb if precision == "fp32" else 0)
+    upload = 144 * nnzb
+    spmv = 76 * nnzb + 52 * n
+    return upload + factor + half_steps * per_iter / 2 + spmv
+
+
+def serve(args):
+    """Request stream: saturated burst, then Poisson arrivals at fractions of
+    the saturated rate; p50 / p99 latency from arrival to result."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_2309_11488_amd as rs
+    from synth import make_grid_system, serving_classes
+
+    wl = WORKLOADS["c5"]
+    precision = args.precision or wl["precision"]
+    reduction = args.reduction if args.reduction is not None else wl["reduction"]
+    ordering = ORDER[args.ordering]
+    dev = torch.device("cuda:0")
+    classes = serving_classes()
+    # per class: plain realisations (one pattern per class) and one with NNCs
+    plain_seeds = {10_000: 4, 50_000: 4, 200_000: 3, 1_000_000: 2}
+    pool = {}
+    t = time.perf_counter()
+    for cells, shape in classes.items():
+        sysl = []
+        for k in range(plain_seeds[cells]):
+            sysl.append(make_grid_system(*shape, seed=1000 + 10 * k, n_rhs=2))
+        nnc = make_grid_system(*shape, nnc_frac=0.02, seed=7777, n_rhs=2)
+        pool[cells] = (sysl, nnc)
+        log(f"class {cells}: n={sysl[0].n} nnzb={sysl[0].nnzb} (+NNC nnzb={nnc.nnzb}); "
+            f"{time.perf_counter() - t:.1f}s")
+
+    def on_device(s):
+        return (torch.from_numpy(s.vals[0]).to(dev), torch.from_numpy(np.ascontiguousarray(s.b[0])).to(dev))
+
+    budget = 200 * 10**9
+    srv = rs.Server(hbm_budget_bytes=budget, max_slots=args.slots, ordering=ordering, precision=PREC[precision],
+                    autotune=not args.no_tune)
+    entries = {}      # cells -> ([(pattern, s, vals_d, b_d)], nnc entry)
+    for cells, (sysl, nnc) in pool.items():
+        p = srv.add_pattern(sysl[0].rowptr, sysl[0].colidx)
+        plain = [(p, s) + on_device(s) for s in sysl]
+        q = srv.add_pattern(nnc.rowptr, nnc.colidx)
+        entries[cells] = (plain, (q, nnc) + on_device(nnc))
+    torch.cuda.synchronize()
+    sizes = sorted(entries)
+
+    def draw(rng, count):
+        out = []
+        for _ in range(count):
+            cells = sizes[int(rng.integers(0, len(sizes)))]
+            plain, nnc = entries[cells]
+            e = nnc if rng.random() < 0.05 else plain[int(rng.integers(0, len(plain)))]
+            out.append((cells, e, int(rng.integers(0, 2))))
+        return out
+
+    def run_stream(reqs, rate):
+        """Submit at Poisson times (rate None: all at once); returns per-request records and the makespan."""
+        rng = np.random.default_rng(12345)
+        gaps = rng.exponential(1.0 / rate, len(reqs)) if rate else np.zeros(len(reqs))
+        arrivals = np.cumsum(gaps) - gaps[0]
+        done = []
+        tickets = []
+        lock = threading.Condition()
+
+        def collector():
+            k = 0
+            while True:
+                with lock:
+                    while k >= len(tickets):
+                        lock.wait()
+                    item = tickets[k]
+                    tickets[k] = 0           # drop the result buffer once collected
+                if item is None:
+                    return
+                ticket, t_arr, t_sub, cells, e, _ = item
+                _, st, info, tm = srv.wait(ticket)
+                # latency from the scheduled arrival: submission lag + submission to completion
+                t_end = t_sub + tm["total_ms"] / 1e3
+                done.append(dict(cells=cells, n=e[1].n, nnzb=e[1].nnzb, status=st, half=info["half_steps"],
+                                 res=info["true_rel_residual"], lat_ms=(t_end - t_arr) * 1e3, t_end=t_end,
+                                 resident=tm["resident"], queue_ms=tm["queue_ms"], solve_ms=tm["solve_ms"],
+                                 factor_ms=tm["factor_ms"]))
+                k += 1
+
+        th = threading.Thread(target=collector)
+        th.start()
+        t0 = time.perf_counter()
+        for (cells, e, j), a in zip(reqs, arrivals):
+            now = time.perf_counter() - t0
+            if a > now:
+                time.sleep(a - now)
+            pid, s, vals_d, b_d = e
+            x = torch.empty_like(b_d[j])
+            t_sub = time.perf_counter()
+            ticket = srv.submit(pid, vals_d, b_d[j], x, reduction=reduction)
+            with lock:
+                tickets.append((ticket, t0 + a, t_sub, cells, e, x))
+                lock.notify()
+        with lock:
+            tickets.append(None)
+            lock.notify()
+        th.join()
+        makespan = max(d["t_end"] for d in done) - t0
+        return done, makespan
+
+    def summarise(done, makespan, offered=None):
+        lat = np.array([d["lat_ms"] for d in done])
+        byts = sum(solve_bytes(d["n"], d["nnzb"], d["half"], precision) for d in done)
+        per_class = {}
+        for c in sizes:
+            lc = np.array([d["lat_ms"] for d in done if d["cells"] == c])
+            if len(lc):
+                per_class[str(c)] = {"count": int(len(lc)), "p50_ms": float(np.percentile(lc, 50)),
+                                     "p99_ms": float(np.percentile(lc, 99))}
+        return {"offered_per_s": offered, "solves_per_s": len(done) / makespan, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "makespan_s": makespan, "requests": len(done),
+                "hbm_gbs": byts / makespan / 1e9, "statuses": sorted({d["status"] for d in done}),
+                "max_true_rel_residual": max(d["res"] for d in done),
+                "mean_half_steps": float(np.mean([d["half"] for d in done])), "per_class": per_class}
+
+    rng = np.random.default_rng(2024)
+    t = time.perf_counter()
+    warm, wspan = run_stream(draw(rng, max(4 * args.slots * len(sizes), 100)), None)
+    W = summarise(warm, wspan)
+    log(f"warm-up: {len(warm)} requests in {time.perf_counter() - t:.1f}s, statuses {W['statuses']}, max true "
+        f"residual {W['max_true_rel_residual']:.3e}; stats {srv.stats()}")
+    burst, span = run_stream(draw(rng, max(args.requests // 4, 50)), None)
+    sat = summarise(burst, span)
+    log(f"saturated burst: {sat['requests']} requests, {sat['solves_per_s']:.1f} solves/s, "
+        f"{sat['hbm_gbs']:.0f} GB/s algorithmic, statuses {sat['statuses']}, max true residual "
+        f"{sat['max_true_rel_residual']:.3e}")
+    loads = {}
+    for f in [float(v) for v in args.loads.split(",") if v]:
+        rate = f * sat["solves_per_s"]
+        recs, span = run_stream(draw(rng, args.requests), rate)
+        loads[f"{f:g}"] = summarise(recs, span, offered=rate)
+        L = loads[f"{f:g}"]
+        log(f"load {f:g} ({rate:.1f}/s offered): {L['solves_per_s']:.1f} solves/s, p50 {L['p50_ms']:.2f} ms, "
+            f"p99 {L['p99_ms']:.2f} ms, statuses {L['statuses']}, max true residual "
+            f"{L['max_true_rel_residual']:.3e}")
+    stats = srv.stats()
+    srv.close()
+    log(f"server stats {stats}")
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        prec = oracle.PREC_ILU_F64 if precision == "fp64" else oracle.PREC_ILU_F32
+        sample = draw(np.random.default_rng(99), 64)
+        t0 = time.perf_counter()
+        nsol = 0
+        for cells, e, j in sample:
+            s = e[1]
+            x, info = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, j], ordering=ordering, reduction=reduction,
+                                   precond=prec)
+            nsol += 1
+            if time.perf_counter() - t0 > args.cpu_seconds:
+                break
+        dt = time.perf_counter() - t0
+        cpu = {"value": nsol / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"the first {nsol} requests of a seeded draw from the same mix, one after another "
+                         f"(ordering, ILU0, BiCGStab, true residual), in {dt:.1f}s, single-threaded C oracle"}
+        log(f"cpu oracle: {nsol / dt:.3f} solves/s ({nsol} requests in {dt:.1f}s)")
+
+    top = loads.get("1", sat)
+    out = {
+        "metric": "BiCGStab-ILU0 solves/sec with p50/p99 latency at 1e-2 reduction (request stream)",
+        "value": sat["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": sat["requests"], "warmup": len(warm),
+        "ms_per_step": 1e3 / sat["solves_per_s"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32-factors" if precision == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": f"c5: {wl['desc']}", "ordering": args.ordering, "precision": precision,
+                   "reduction": reduction, "slots": args.slots, "hbm_budget_bytes": budget,
+                   "requests_per_load": args.requests, "pool": {str(c): {"n": entries[c][0][0][1].n,
+                                                                         "nnzb": entries[c][0][0][1].nnzb,
+                                                                         "realisations": len(entries[c][0])}
+                                                                for c in sizes},
+                   "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"], "saturated": sat, "loads": loads,
+                   "server_stats": stats},
+        "roofline": {"bound": "hbm", "achieved": sat["hbm_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": sat["hbm_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "whole request stream: algorithmic bytes of upload, factorisation, BiCGStab "
+                               "half-steps and true residual per request over the burst makespan"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

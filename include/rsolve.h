@@ -112,6 +112,8 @@ typedef struct {
  *                   (values set later with bcsr_set_values)
  *   out           : receives the handle; bad_row (host, may be NULL)
  *                   receives the offending row on a pattern error.
+ * The pattern is copied on `stream`, which is synchronised before return
+ * (values, when given, stay stream-ordered as in bcsr_set_values).
  * Errors: RS_INVALID_ARG, RS_UNSUPPORTED_BLOCK_SIZE, RS_BAD_PATTERN,
  * RS_MISSING_DIAGONAL, RS_OUT_OF_MEMORY, RS_HIP_ERROR. */
 int bcsr_create(int32_t n_brows, int32_t nnzb, int32_t block_size, int32_t batch, const int32_t *row_ptr,
@@ -141,8 +143,17 @@ int bcsr_destroy(bcsr_t A);
 /* ilu0_analyse -- host analysis of A's pattern (integer work, once per
  * pattern): the ordering (RS_ORDER_*), the reordered pattern, lower and
  * upper sweep schedules and the factor update lists; all copied to the
- * device.  Section "ILU0" of the implementation chapter. */
+ * device (complete on return, usable from any stream).  Section "ILU0" of
+ * the implementation chapter. */
 int ilu0_analyse(bcsr_t A, int32_t ordering, ilu0_t *out);
+
+/* ilu0_analyse_shared -- a further preconditioner handle for A, whose
+ * pattern must equal the one `like` was analysed for (RS_PATTERN_MISMATCH
+ * otherwise): it shares like's analysis (ordering, schedules, their device
+ * copy; reference-counted, so `like` may be destroyed first) and has its own
+ * factors, workspace and default options.  No host analysis runs.  Reads
+ * only immutable parts of `like`, so `like` may be in use on another thread. */
+int ilu0_analyse_shared(bcsr_t A, ilu0_t like, ilu0_t *out);
 
 /* ilu0_get_schedule -- perm[new] = old (host, n_brows ints, may be NULL);
  * *n_sets = number of levels (LS), colours (GC) or lower-sweep levels
@@ -196,7 +207,7 @@ int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *ba
  * pattern (rows in new order, columns renumbered and ascending, as P A P^T):
  * lu (nnzb * 9 doubles) holds L below the diagonal and U on and above it;
  * dinv (n_brows * 9) holds inv(U_ii) in new row order.  FP32 factors are
- * returned widened.  Synchronous. */
+ * returned widened.  Synchronous (waits for the whole device). */
 int ilu0_get_factors(ilu0_t M, int32_t sys, double *lu, double *dinv);
 
 /* ilu0_apply -- z = U^{-1} L^{-1} v for systems [first_sys, first_sys +
@@ -238,38 +249,45 @@ int rsolve_profile_enable(int32_t mask);
 int rsolve_profile_get(int32_t cls, double *ms, int64_t *units, double *bytes);
 
 /* ------------------------------------------------------------- serving
- * A request server for streams of solves of mixed sizes (one system each):
- * requests wait in arrival order and are admitted as soon as a worker slot
- * is free and their device footprint fits in the memory budget; each slot
- * runs on its own HIP stream, so admitted requests overlap on the device.
- * A slot keeps its matrix / preconditioner handles, so a later request with
- * the same pattern skips the analysis and reuses buffers and graphs.  Idle
- * slots give their handles back when the head of the queue needs the room.
- * Each request is analysed (first time), factored (`precision`), optionally
- * autotuned (first time per slot and pattern) and solved exactly as the
- * calls above would; results do not depend on what else is running. */
+ * A request server for streams of solves of mixed sizes (one system each).
+ * Requests name a registered pattern; they wait in arrival order and are
+ * admitted as soon as a worker slot is free and a resident instance of the
+ * pattern is idle, or the device footprint of a new instance fits in the
+ * memory budget.  Each slot runs on its own HIP stream, so admitted requests
+ * overlap on the device.  An instance (matrix + preconditioner handles,
+ * factors, Krylov workspace) stays resident after its request, so a later
+ * request of the same pattern only uploads values, factors and solves; all
+ * instances of a pattern share one analysis (ilu0_analyse_shared).  When the
+ * head of the queue does not fit, idle instances are freed, least recently
+ * used first.  Each request is factored (`precision`) and solved exactly as
+ * ilu0_factor / bicgstab_solve would, so results do not depend on the mix;
+ * with `autotune`, the first instance of a pattern runs ilu0_autotune and
+ * later instances take its launch configuration. */
 typedef struct rs_server *server_t;
 
 typedef struct {
-    size_t hbm_budget_bytes;  /* device bytes all resident requests may hold together */
+    size_t hbm_budget_bytes;  /* device bytes all resident instances may hold together */
     int32_t max_slots;        /* requests processed at once (1..64) */
-    int32_t ordering;         /* RS_ORDER_* for every request */
+    int32_t ordering;         /* RS_ORDER_* for every pattern */
     int32_t precision;        /* RS_PREC_* for every request */
-    int32_t autotune;         /* 1: ilu0_autotune on a slot's first solve of a pattern */
+    int32_t autotune;         /* 1: ilu0_autotune once per pattern */
 } server_config;
 
 typedef struct {
     double queue_ms;    /* submission to admission */
-    double analyse_ms;  /* handle creation and pattern analysis (0 when reused) */
+    double analyse_ms;  /* instance creation: handles, analysis or its reuse, allocation (0 when resident) */
     double factor_ms;   /* value upload and ILU0 factorisation */
-    double tune_ms;     /* autotuning (first solve of a pattern on a slot) */
+    double tune_ms;     /* autotuning (first instance of a pattern) */
     double solve_ms;    /* BiCGStab, true residual, result copy */
     double total_ms;    /* submission to completion */
     int32_t slot;
+    int32_t resident;   /* 1: ran on an instance that was already resident */
 } server_timing;
 
 typedef struct {
     int64_t queued, running, completed;
+    int64_t instances;      /* resident instances now */
+    int64_t created, evicted, analyses;
     size_t reserved_bytes, peak_reserved_bytes;
 } server_stats;
 
@@ -277,17 +295,25 @@ typedef struct {
  * Errors: RS_INVALID_ARG, RS_HIP_ERROR. */
 int server_create(const server_config *cfg, server_t *out);
 
-/* server_request_bytes -- the device footprint a request of this shape
- * reserves against the budget. */
+/* server_request_bytes -- the device footprint an instance of this shape
+ * reserves against the budget (the shared analysis is counted once per
+ * pattern, in addition, as server_analysis_bytes). */
 int server_request_bytes(int32_t n_brows, int32_t nnzb, int32_t precision, size_t *bytes);
+int server_analysis_bytes(int32_t n_brows, int32_t nnzb, size_t *bytes);
 
-/* server_submit -- queue one solve (batch 1).  row_ptr/col_idx: host memory;
- * vals (nnzb*9), b (n*3) and x (n*3, the result) in `mem`.  All are
- * borrowed until server_poll/server_wait reports completion.  Returns a
- * ticket; RS_OUT_OF_MEMORY when the request alone exceeds the budget. */
-int server_submit(server_t S, int32_t n_brows, int32_t nnzb, const int32_t *row_ptr, const int32_t *col_idx,
-                  const double *vals, const double *b, double *x, double reduction, int32_t max_iter, int32_t mem,
-                  int64_t *ticket);
+/* server_add_pattern -- register a pattern (host row_ptr / col_idx, copied
+ * and validated as bcsr_create does) and return its id; an identical
+ * pattern registered again gets the same id.  Errors: RS_INVALID_ARG,
+ * RS_BAD_PATTERN, RS_MISSING_DIAGONAL (bad_row set when not NULL),
+ * RS_OUT_OF_MEMORY when one instance of it exceeds the budget. */
+int server_add_pattern(server_t S, int32_t n_brows, int32_t nnzb, const int32_t *row_ptr, const int32_t *col_idx,
+                       int32_t *pattern, int32_t *bad_row);
+
+/* server_submit -- queue one solve (batch 1) of a registered pattern:
+ * vals (nnzb*9), b (n*3) and x (n*3, the result) in `mem`, borrowed until
+ * server_poll/server_wait reports completion.  Returns a ticket. */
+int server_submit(server_t S, int32_t pattern, const double *vals, const double *b, double *x, double reduction,
+                  int32_t max_iter, int32_t mem, int64_t *ticket);
 
 /* server_poll -- RS_PENDING while the request runs or waits; otherwise its
  * status (as bicgstab_solve would return), with info and timing (may be
@@ -300,7 +326,7 @@ int server_wait(server_t S, int64_t ticket, solve_info *info, server_timing *tim
 int server_get_stats(server_t S, server_stats *out);
 
 /* server_destroy -- finish queued and running requests, stop the slots,
- * free every handle (NULL accepted). */
+ * free every instance and pattern (NULL accepted). */
 int server_destroy(server_t S);
 
 const char *rsolve_status_string(int status);

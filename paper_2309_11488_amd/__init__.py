@@ -33,7 +33,8 @@ EXPORTS = (
     "ilu0_get_schedule", "ilu0_get_sweep_levels", "ilu0_set_option", "ilu0_get_option", "ilu0_autotune",
     "ilu0_factor", "ilu0_get_factors", "ilu0_apply",
     "bicgstab_solve", "ilu0_destroy", "ilu0_analyse_host", "rsolve_profile_enable", "rsolve_profile_get",
-    "server_create", "server_request_bytes", "server_submit", "server_poll", "server_wait", "server_get_stats",
+    "ilu0_analyse_shared", "server_create", "server_request_bytes", "server_analysis_bytes", "server_add_pattern",
+    "server_submit", "server_poll", "server_wait", "server_get_stats",
     "server_destroy", "rsolve_status_string", "rsolve_last_error",
 )
 PROF_FACTOR, PROF_LSWEEP, PROF_USWEEP, PROF_SPMV_V, PROF_VEC, PROF_SPMV_T = 0, 1, 2, 3, 4, 5
@@ -64,7 +65,7 @@ class ServerConfig(ct.Structure):
 class ServerTiming(ct.Structure):
     _fields_ = [("queue_ms", ct.c_double), ("analyse_ms", ct.c_double), ("factor_ms", ct.c_double),
                 ("tune_ms", ct.c_double), ("solve_ms", ct.c_double), ("total_ms", ct.c_double),
-                ("slot", ct.c_int32)]
+                ("slot", ct.c_int32), ("resident", ct.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -72,7 +73,8 @@ class ServerTiming(ct.Structure):
 
 class ServerStats(ct.Structure):
     _fields_ = [("queued", ct.c_int64), ("running", ct.c_int64), ("completed", ct.c_int64),
-                ("reserved_bytes", ct.c_size_t), ("peak_reserved_bytes", ct.c_size_t)]
+                ("instances", ct.c_int64), ("created", ct.c_int64), ("evicted", ct.c_int64),
+                ("analyses", ct.c_int64), ("reserved_bytes", ct.c_size_t), ("peak_reserved_bytes", ct.c_size_t)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -111,6 +113,7 @@ def lib():
         L.bcsr_destroy.argtypes = [vp]
         L.bcsr_set_option.argtypes = [vp, i32, i32]
         L.ilu0_analyse.argtypes = [vp, i32, P(vp)]
+        L.ilu0_analyse_shared.argtypes = [vp, vp, P(vp)]
         L.ilu0_get_schedule.argtypes = [vp, vp, P(i32), vp]
         L.ilu0_get_sweep_levels.argtypes = [vp, P(i32), P(i32)]
         L.ilu0_set_option.argtypes = [vp, i32, i32]
@@ -126,7 +129,9 @@ def lib():
         L.rsolve_profile_get.argtypes = [i32, P(dbl), P(ct.c_int64), P(dbl)]
         L.server_create.argtypes = [P(ServerConfig), P(vp)]
         L.server_request_bytes.argtypes = [i32, i32, i32, P(ct.c_size_t)]
-        L.server_submit.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, dbl, i32, i32, P(ct.c_int64)]
+        L.server_analysis_bytes.argtypes = [i32, i32, P(ct.c_size_t)]
+        L.server_add_pattern.argtypes = [vp, i32, i32, vp, vp, P(i32), P(i32)]
+        L.server_submit.argtypes = [vp, i32, vp, vp, vp, dbl, i32, i32, P(ct.c_int64)]
         L.server_poll.argtypes = [vp, ct.c_int64, P(SolveInfo), P(ServerTiming)]
         L.server_wait.argtypes = [vp, ct.c_int64, P(SolveInfo), P(ServerTiming)]
         L.server_get_stats.argtypes = [vp, P(ServerStats)]
@@ -257,6 +262,13 @@ def bcsr_destroy(A):
 def ilu0_analyse(A, ordering=ORDER_LEVEL_SET):
     h = ct.c_void_p()
     _check(lib().ilu0_analyse(A, ordering, ct.byref(h)), "ilu0_analyse")
+    return h
+
+
+def ilu0_analyse_shared(A, like):
+    """A further preconditioner for A sharing the analysis of ``like`` (same pattern)."""
+    h = ct.c_void_p()
+    _check(lib().ilu0_analyse_shared(A, like, ct.byref(h)), "ilu0_analyse_shared")
     return h
 
 
@@ -411,17 +423,29 @@ class Server:
         self.precision = precision
         self._held = {}
 
-    def submit(self, rowptr, colidx, vals, b, x=None, reduction=1e-2, max_iter=200):
+    def add_pattern(self, rowptr, colidx):
+        """Register a pattern (copied by the server); returns its id."""
         rowptr, colidx = _host(rowptr, np.int32), _host(colidx, np.int32)
+        pid, bad = ct.c_int32(), ct.c_int32(-1)
+        st = lib().server_add_pattern(self.h, len(rowptr) - 1, len(colidx), rowptr.ctypes.data, colidx.ctypes.data,
+                                      ct.byref(pid), ct.byref(bad))
+        if st != OK:
+            err = RsolveError(st, "server_add_pattern")
+            err.bad_row = bad.value
+            raise err
+        return pid.value
+
+    def submit(self, pattern, vals, b, x=None, reduction=1e-2, max_iter=200):
+        """Queue a solve of a registered pattern; returns a ticket."""
         if not _is_torch(vals):
             vals, b = _host(vals, np.float64), _host(b, np.float64)
             if x is None:
                 x = np.zeros_like(b)
         mem, (vp, bp, xp) = _mem_ptr(vals, b, x)
         t = ct.c_int64()
-        _check(lib().server_submit(self.h, len(rowptr) - 1, len(colidx), rowptr.ctypes.data, colidx.ctypes.data,
-                                   vp, bp, xp, float(reduction), int(max_iter), mem, ct.byref(t)), "server_submit")
-        self._held[t.value] = (rowptr, colidx, vals, b, x)
+        _check(lib().server_submit(self.h, int(pattern), vp, bp, xp, float(reduction), int(max_iter), mem,
+                                   ct.byref(t)), "server_submit")
+        self._held[t.value] = (vals, b, x)
         return t.value
 
     def _finish(self, fn, ticket):
@@ -431,7 +455,7 @@ class Server:
         st = fn(self.h, int(ticket), ct.byref(info), ct.byref(tm))
         if st == PENDING:
             return None
-        x = self._held.pop(ticket)[4]
+        x = self._held.pop(ticket)[2]
         return x, st, info.as_dict(), tm.as_dict()
 
     def poll(self, ticket):
@@ -450,6 +474,12 @@ class Server:
     def request_bytes(n, nnzb, precision=PREC_FP32_FACTORS):
         v = ct.c_size_t()
         _check(lib().server_request_bytes(int(n), int(nnzb), int(precision), ct.byref(v)), "server_request_bytes")
+        return v.value
+
+    @staticmethod
+    def analysis_bytes(n, nnzb):
+        v = ct.c_size_t()
+        _check(lib().server_analysis_bytes(int(n), int(nnzb), ct.byref(v)), "server_analysis_bytes")
         return v.value
 
     def close(self):

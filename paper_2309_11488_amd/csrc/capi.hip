@@ -7,6 +7,7 @@
 #include <chrono>
 #include <climits>
 #include <fstream>
+#include <memory>
 #include <sstream>
 #include <cstdio>
 #include <cstdlib>
@@ -39,10 +40,23 @@ int fail(int code, const std::string &msg) {
                         std::string(#expr) + ": " + hipGetErrorString(e_));                        \
     } while (0)
 
-uint64_t fnv(const void *p, size_t bytes, uint64_t h = 1469598103934665603ull) {
-    const unsigned char *c = (const unsigned char *)p;
-    for (size_t i = 0; i < bytes; ++i) h = (h ^ c[i]) * 1099511628211ull;
-    return h;
+// Pattern fingerprint: FNV-1a style over 32-bit words in four independent
+// lanes (a pattern of a million rows hashes in a few milliseconds).
+uint64_t pattern_fingerprint(const std::vector<int32_t> &rp, const std::vector<int32_t> &ci) {
+    const uint64_t prime = 1099511628211ull;
+    uint64_t h[4] = {1469598103934665603ull, 0x9e3779b97f4a7c15ull, 0xc2b2ae3d27d4eb4full, 0x165667b19e3779f9ull};
+    auto mix = [&](const std::vector<int32_t> &v) {
+        const size_t n = v.size(), n4 = n & ~(size_t)3;
+        for (size_t i = 0; i < n4; i += 4)
+            for (int l = 0; l < 4; ++l) h[l] = (h[l] ^ (uint32_t)v[i + l]) * prime;
+        for (size_t i = n4; i < n; ++i) h[0] = (h[0] ^ (uint32_t)v[i]) * prime;
+        h[1] = (h[1] ^ n) * prime;
+    };
+    mix(rp);
+    mix(ci);
+    uint64_t r = h[0];
+    for (int l = 1; l < 4; ++l) r = (r ^ h[l]) * prime;
+    return r;
 }
 
 // Device allocation owned by a handle.
@@ -65,10 +79,12 @@ struct DevBuf {
     template <typename T> T *as() const { return (T *)p; }
 };
 
-hipError_t upload(DevBuf &buf, const std::vector<int32_t> &v) {
+// Stream-ordered upload of a host array the handle owns (the caller
+// synchronises `s` before the data is used on another stream).
+hipError_t upload(DevBuf &buf, const std::vector<int32_t> &v, hipStream_t s) {
     hipError_t e = buf.alloc(v.size() * sizeof(int32_t));
     if (e != hipSuccess || v.empty()) return e;
-    return hipMemcpy(buf.p, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    return hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
 }
 
 // Process-wide and not thread-safe; off unless enabled.
@@ -150,13 +166,21 @@ struct rs_bcsr {
     DevBuf rowptr, colidx, vals;
 };
 
-struct rs_ilu0 {
-    int n = 0, nnzb = 0, batch = 1;
+// The analysis of one pattern: the host schedule and its device copy.
+// Immutable once built; every preconditioner handle of the pattern holds a
+// reference, and the last one to go frees it.
+struct Analysis {
     uint64_t hash = 0;
     rs::Schedule sch;
     DevSchedule dev{};
     DevBuf perm, prow, pcol, psrc, lrows, lptr, lcol, lsrc, ldq, l2u, upd_ptr, upd, urows, uptr, ucol, usrc, dsrc;
     DevBuf lt_start, lt_dptr, lt_dep, ut_start, ut_dptr, ut_dep;
+};
+
+struct rs_ilu0 {
+    int n = 0, nnzb = 0, batch = 1;
+    uint64_t hash = 0;
+    std::shared_ptr<const Analysis> an;
     // factors
     int precision = -1;
     bool factored = false;
@@ -200,12 +224,13 @@ struct rs_ilu0 {
 };
 
 static int read_pattern(int32_t n, int32_t nnzb, const int32_t *row_ptr, const int32_t *col_idx, int32_t mem,
-                        std::vector<int32_t> &rp, std::vector<int32_t> &ci) {
+                        hipStream_t s, std::vector<int32_t> &rp, std::vector<int32_t> &ci) {
     rp.resize((size_t)n + 1);
     ci.resize((size_t)nnzb);
     if (mem == RS_MEM_DEVICE) {
-        HIP_TRY(hipMemcpy(rp.data(), row_ptr, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-        if (nnzb) HIP_TRY(hipMemcpy(ci.data(), col_idx, ci.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpyAsync(rp.data(), row_ptr, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        if (nnzb) HIP_TRY(hipMemcpyAsync(ci.data(), col_idx, ci.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
     } else {
         std::memcpy(rp.data(), row_ptr, rp.size() * sizeof(int32_t));
         if (nnzb) std::memcpy(ci.data(), col_idx, ci.size() * sizeof(int32_t));
@@ -270,7 +295,7 @@ int bcsr_create(int32_t n_brows, int32_t nnzb, int32_t block_size, int32_t batch
     A->n = n_brows;
     A->nnzb = nnzb;
     A->batch = batch;
-    int st = read_pattern(n_brows, nnzb, row_ptr, col_idx, mem, A->h_rowptr, A->h_colidx);
+    int st = read_pattern(n_brows, nnzb, row_ptr, col_idx, mem, (hipStream_t)stream, A->h_rowptr, A->h_colidx);
     if (st != RS_OK) { delete A; return st; }
     int bad = -1;
     st = rs::validate_pattern(n_brows, nnzb, A->h_rowptr.data(), A->h_colidx.data(), &bad);
@@ -279,10 +304,12 @@ int bcsr_create(int32_t n_brows, int32_t nnzb, int32_t block_size, int32_t batch
         delete A;
         return fail(st, "bcsr_create: invalid pattern at row " + std::to_string(bad));
     }
-    A->hash = fnv(A->h_colidx.data(), A->h_colidx.size() * 4, fnv(A->h_rowptr.data(), A->h_rowptr.size() * 4));
+    A->hash = pattern_fingerprint(A->h_rowptr, A->h_colidx);
     hipError_t e;
-    if ((e = upload(A->rowptr, A->h_rowptr)) != hipSuccess || (e = upload(A->colidx, A->h_colidx)) != hipSuccess ||
-        (e = A->vals.alloc((size_t)nnzb * 9 * batch * sizeof(double))) != hipSuccess) {
+    if ((e = upload(A->rowptr, A->h_rowptr, (hipStream_t)stream)) != hipSuccess ||
+        (e = upload(A->colidx, A->h_colidx, (hipStream_t)stream)) != hipSuccess ||
+        (e = A->vals.alloc((size_t)nnzb * 9 * batch * sizeof(double))) != hipSuccess ||
+        (e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess) {
         delete A;
         return fail(e == hipErrorOutOfMemory ? RS_OUT_OF_MEMORY : RS_HIP_ERROR,
                     std::string("bcsr_create: ") + hipGetErrorString(e));
@@ -370,61 +397,92 @@ int bcsr_spmv(bcsr_t A, const double *x, double *y, int32_t first_sys, int32_t n
     return RS_OK;
 }
 
-int ilu0_analyse(bcsr_t A, int32_t ordering, ilu0_t *out) {
-    if (!A || !out || ordering < 0 || ordering > 2) return fail(RS_INVALID_ARG, "ilu0_analyse: bad arguments");
-    *out = nullptr;
+static int build_analysis(const rs_bcsr *A, int32_t ordering, std::shared_ptr<Analysis> &out) {
+    auto an = std::make_shared<Analysis>();
+    an->hash = A->hash;
+    rs::build_schedule(A->n, A->nnzb, A->h_rowptr.data(), A->h_colidx.data(), ordering, an->sch, rs::kRowsPerBlock);
+    const rs::Schedule &S = an->sch;
+    hipError_t e = hipSuccess;
+    struct Up { DevBuf *b; const std::vector<int32_t> *v; } ups[] = {
+        {&an->perm, &S.perm}, {&an->prow, &S.prow}, {&an->pcol, &S.pcol}, {&an->psrc, &S.psrc},
+        {&an->lrows, &S.lrows}, {&an->lptr, &S.lptr}, {&an->lcol, &S.lcol}, {&an->lsrc, &S.lsrc},
+        {&an->ldq, &S.ldq}, {&an->l2u, &S.l2u}, {&an->upd_ptr, &S.upd_ptr}, {&an->upd, &S.upd},
+        {&an->urows, &S.urows}, {&an->uptr, &S.uptr}, {&an->ucol, &S.ucol}, {&an->usrc, &S.usrc},
+        {&an->dsrc, &S.dsrc}, {&an->lt_start, &S.ltiles.start}, {&an->lt_dptr, &S.ltiles.dep_ptr},
+        {&an->lt_dep, &S.ltiles.dep}, {&an->ut_start, &S.utiles.start}, {&an->ut_dptr, &S.utiles.dep_ptr},
+        {&an->ut_dep, &S.utiles.dep}};
+    // uploads on a private stream, complete before the handle is returned,
+    // so that any stream may use the analysis
+    hipStream_t us = nullptr;
+    e = hipStreamCreateWithFlags(&us, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+        for (auto &u : ups)
+            if ((e = upload(*u.b, *u.v, us)) != hipSuccess) break;
+        const hipError_t e2 = hipStreamSynchronize(us);
+        if (e == hipSuccess) e = e2;
+        (void)hipStreamDestroy(us);
+    }
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? RS_OUT_OF_MEMORY : RS_HIP_ERROR,
+                    std::string("ilu0_analyse: ") + hipGetErrorString(e));
+    DevSchedule &d = an->dev;
+    d.n = S.n; d.nnzb = S.nnzb; d.nL = S.nL; d.nU = S.nU;
+    d.perm = an->perm.as<int32_t>(); d.prow = an->prow.as<int32_t>(); d.pcol = an->pcol.as<int32_t>();
+    d.psrc = an->psrc.as<int32_t>(); d.lrows = an->lrows.as<int32_t>(); d.lptr = an->lptr.as<int32_t>();
+    d.lcol = an->lcol.as<int32_t>(); d.lsrc = an->lsrc.as<int32_t>(); d.ldq = an->ldq.as<int32_t>();
+    d.l2u = an->l2u.as<int32_t>(); d.upd_ptr = an->upd_ptr.as<int32_t>(); d.upd = an->upd.as<int32_t>();
+    d.urows = an->urows.as<int32_t>(); d.uptr = an->uptr.as<int32_t>(); d.ucol = an->ucol.as<int32_t>();
+    d.usrc = an->usrc.as<int32_t>(); d.dsrc = an->dsrc.as<int32_t>();
+    d.nlt = S.ltiles.n; d.nut = S.utiles.n;
+    d.lt_start = an->lt_start.as<int32_t>(); d.lt_dptr = an->lt_dptr.as<int32_t>(); d.lt_dep = an->lt_dep.as<int32_t>();
+    d.ut_start = an->ut_start.as<int32_t>(); d.ut_dptr = an->ut_dptr.as<int32_t>(); d.ut_dep = an->ut_dep.as<int32_t>();
+    out = std::move(an);
+    return RS_OK;
+}
+
+static rs_ilu0 *new_ilu0(const rs_bcsr *A, std::shared_ptr<const Analysis> an) {
     rs_ilu0 *M = new rs_ilu0();
     M->n = A->n;
     M->nnzb = A->nnzb;
     M->batch = A->batch;
     M->hash = A->hash;
-    rs::build_schedule(A->n, A->nnzb, A->h_rowptr.data(), A->h_colidx.data(), ordering, M->sch, rs::kRowsPerBlock);
-    const rs::Schedule &S = M->sch;
-    hipError_t e = hipSuccess;
-    struct Up { DevBuf *b; const std::vector<int32_t> *v; } ups[] = {
-        {&M->perm, &S.perm}, {&M->prow, &S.prow}, {&M->pcol, &S.pcol}, {&M->psrc, &S.psrc},
-        {&M->lrows, &S.lrows}, {&M->lptr, &S.lptr}, {&M->lcol, &S.lcol}, {&M->lsrc, &S.lsrc},
-        {&M->ldq, &S.ldq}, {&M->l2u, &S.l2u}, {&M->upd_ptr, &S.upd_ptr}, {&M->upd, &S.upd},
-        {&M->urows, &S.urows}, {&M->uptr, &S.uptr}, {&M->ucol, &S.ucol}, {&M->usrc, &S.usrc},
-        {&M->dsrc, &S.dsrc}, {&M->lt_start, &S.ltiles.start}, {&M->lt_dptr, &S.ltiles.dep_ptr},
-        {&M->lt_dep, &S.ltiles.dep}, {&M->ut_start, &S.utiles.start}, {&M->ut_dptr, &S.utiles.dep_ptr},
-        {&M->ut_dep, &S.utiles.dep}};
-    for (auto &u : ups)
-        if ((e = upload(*u.b, *u.v)) != hipSuccess) break;
-    if (e != hipSuccess) {
-        delete M;
-        return fail(e == hipErrorOutOfMemory ? RS_OUT_OF_MEMORY : RS_HIP_ERROR,
-                    std::string("ilu0_analyse: ") + hipGetErrorString(e));
-    }
-    DevSchedule &d = M->dev;
-    d.n = S.n; d.nnzb = S.nnzb; d.nL = S.nL; d.nU = S.nU;
-    d.perm = M->perm.as<int32_t>(); d.prow = M->prow.as<int32_t>(); d.pcol = M->pcol.as<int32_t>();
-    d.psrc = M->psrc.as<int32_t>(); d.lrows = M->lrows.as<int32_t>(); d.lptr = M->lptr.as<int32_t>();
-    d.lcol = M->lcol.as<int32_t>(); d.lsrc = M->lsrc.as<int32_t>(); d.ldq = M->ldq.as<int32_t>();
-    d.l2u = M->l2u.as<int32_t>(); d.upd_ptr = M->upd_ptr.as<int32_t>(); d.upd = M->upd.as<int32_t>();
-    d.urows = M->urows.as<int32_t>(); d.uptr = M->uptr.as<int32_t>(); d.ucol = M->ucol.as<int32_t>();
-    d.usrc = M->usrc.as<int32_t>(); d.dsrc = M->dsrc.as<int32_t>();
-    d.nlt = S.ltiles.n; d.nut = S.utiles.n;
     // few, wide colours: one launch per colour; many thin levels: one launch per sweep
-    M->tile_sweeps = ordering != RS_ORDER_GRAPH_COLOUR;
-    d.lt_start = M->lt_start.as<int32_t>(); d.lt_dptr = M->lt_dptr.as<int32_t>(); d.lt_dep = M->lt_dep.as<int32_t>();
-    d.ut_start = M->ut_start.as<int32_t>(); d.ut_dptr = M->ut_dptr.as<int32_t>(); d.ut_dep = M->ut_dep.as<int32_t>();
-    *out = M;
+    M->tile_sweeps = an->sch.ordering != RS_ORDER_GRAPH_COLOUR;
+    M->an = std::move(an);
+    return M;
+}
+
+int ilu0_analyse(bcsr_t A, int32_t ordering, ilu0_t *out) {
+    if (!A || !out || ordering < 0 || ordering > 2) return fail(RS_INVALID_ARG, "ilu0_analyse: bad arguments");
+    *out = nullptr;
+    std::shared_ptr<Analysis> an;
+    const int st = build_analysis(A, ordering, an);
+    if (st != RS_OK) return st;
+    *out = new_ilu0(A, std::move(an));
+    return RS_OK;
+}
+
+int ilu0_analyse_shared(bcsr_t A, ilu0_t like, ilu0_t *out) {
+    if (!A || !like || !out) return fail(RS_INVALID_ARG, "ilu0_analyse_shared: bad arguments");
+    *out = nullptr;
+    if (A->n != like->n || A->nnzb != like->nnzb || A->hash != like->an->hash)
+        return fail(RS_PATTERN_MISMATCH, "ilu0_analyse_shared: A's pattern differs from the analysed one");
+    *out = new_ilu0(A, like->an);
     return RS_OK;
 }
 
 int ilu0_get_schedule(ilu0_t M, int32_t *perm, int32_t *n_sets, int32_t *set_ptr) {
     if (!M) return fail(RS_INVALID_ARG, "ilu0_get_schedule: NULL handle");
-    if (perm && M->n) std::memcpy(perm, M->sch.perm.data(), sizeof(int32_t) * (size_t)M->n);
-    if (n_sets) *n_sets = M->sch.n_sets;
-    if (set_ptr) std::memcpy(set_ptr, M->sch.set_ptr.data(), sizeof(int32_t) * M->sch.set_ptr.size());
+    if (perm && M->n) std::memcpy(perm, M->an->sch.perm.data(), sizeof(int32_t) * (size_t)M->n);
+    if (n_sets) *n_sets = M->an->sch.n_sets;
+    if (set_ptr) std::memcpy(set_ptr, M->an->sch.set_ptr.data(), sizeof(int32_t) * M->an->sch.set_ptr.size());
     return RS_OK;
 }
 
 int ilu0_get_sweep_levels(ilu0_t M, int32_t *n_lower, int32_t *n_upper) {
     if (!M) return fail(RS_INVALID_ARG, "ilu0_get_sweep_levels: NULL handle");
-    if (n_lower) *n_lower = M->sch.nl_levels;
-    if (n_upper) *n_upper = M->sch.nu_levels;
+    if (n_lower) *n_lower = M->an->sch.nl_levels;
+    if (n_upper) *n_upper = M->an->sch.nu_levels;
     return RS_OK;
 }
 
@@ -493,7 +551,7 @@ int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *ba
     if (precision != RS_PREC_FP64 && precision != RS_PREC_FP32_FACTORS)
         return fail(RS_INVALID_ARG, "ilu0_factor: unknown precision");
     hipStream_t s = (hipStream_t)stream;
-    const rs::Schedule &S = M->sch;
+    const rs::Schedule &S = M->an->sch;
     const size_t B = (size_t)M->batch;
     HIP_TRY(M->pvals.alloc(B * M->nnzb * 9 * sizeof(double)));
     HIP_TRY(M->L.alloc(B * S.nL * 9 * sizeof(double)));
@@ -516,10 +574,10 @@ int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *ba
         double bytes = 148 * nnzb + 72 * nnzb + 72 * nnzb + 4 * (3.0 * S.nL + 2.0 * S.nU + 3 * n) + 4.0 * S.upd.size();
         if (precision == RS_PREC_FP32_FACTORS) bytes += 108 * nnzb;
         ProfScope ps(PC_FACTOR, s, B * bytes);
-        rs::launch_gather_blocks(A->vals.as<double>(), per, M->pvals.as<double>(), per, M->dev.psrc, M->nnzb,
+        rs::launch_gather_blocks(A->vals.as<double>(), per, M->pvals.as<double>(), per, M->an->dev.psrc, M->nnzb,
                                  M->batch, s);
         for (int l = 0; l < S.nl_levels; ++l)
-            rs::launch_factor_level(M->dev, M->pvals.as<double>(), M->L.as<double>(), M->U.as<double>(),
+            rs::launch_factor_level(M->an->dev, M->pvals.as<double>(), M->L.as<double>(), M->U.as<double>(),
                                     M->Dinv.as<double>(), M->bad.as<int32_t>(), S.lset[l], S.lset[l + 1], M->batch,
                                     s);
         if (precision == RS_PREC_FP32_FACTORS) {
@@ -548,7 +606,8 @@ int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *ba
 int ilu0_get_factors(ilu0_t M, int32_t sys, double *lu, double *dinv) {
     if (!M || sys < 0 || sys >= M->batch) return fail(RS_INVALID_ARG, "ilu0_get_factors: bad arguments");
     if (!M->factored) return fail(RS_NOT_FACTORED, "ilu0_get_factors: not factored");
-    const rs::Schedule &S = M->sch;
+    HIP_TRY(hipDeviceSynchronize());   // the factorisation may still run on any stream
+    const rs::Schedule &S = M->an->sch;
     std::vector<double> L((size_t)S.nL * 9), U((size_t)S.nU * 9), D((size_t)M->n * 9);
     if (M->precision == RS_PREC_FP32_FACTORS) {
         std::vector<float> Lf(L.size()), Uf(U.size()), Df(D.size());
@@ -572,12 +631,14 @@ int ilu0_get_factors(ilu0_t M, int32_t sys, double *lu, double *dinv) {
     return RS_OK;
 }
 
-static int ensure_workspace(ilu0_t M) {
+// Allocate (first call) and bind the solve workspace; initialisation is
+// ordered on the caller's stream `s`.
+static int ensure_workspace(ilu0_t M, hipStream_t s) {
     const size_t B = (size_t)M->batch, vs = rs::vec_stride(M->n);
     const size_t vec = std::max<size_t>(B * vs, 1);
     if (!M->work.p) {
         HIP_TRY(M->work.alloc(9 * vec * sizeof(double)));
-        HIP_TRY(hipMemset(M->work.p, 0, 9 * vec * sizeof(double)));  // padding stays zero
+        HIP_TRY(hipMemsetAsync(M->work.p, 0, 9 * vec * sizeof(double), s));  // padding stays zero
     }
     HIP_TRY(M->ywork.alloc(vec * sizeof(double)));
     const int max_blocks = std::max(rs::row_blocks(std::max(M->n, 1), 1), rs::kVecMaxBlocks);
@@ -587,18 +648,18 @@ static int ensure_workspace(ilu0_t M) {
     if (!M->spart.p) HIP_TRY(M->spart.alloc(B * sstride * sizeof(double)));
     if (!M->tickets.p) {
         HIP_TRY(M->tickets.alloc(B * tstride * sizeof(uint32_t)));
-        HIP_TRY(hipMemset(M->tickets.p, 0, B * tstride * sizeof(uint32_t)));
+        HIP_TRY(hipMemsetAsync(M->tickets.p, 0, B * tstride * sizeof(uint32_t), s));
     }
     if (!M->state.p) {
         HIP_TRY(M->state.alloc(B * sizeof(SysState)));
-        HIP_TRY(hipMemset(M->state.p, 0, B * sizeof(SysState)));
+        HIP_TRY(hipMemsetAsync(M->state.p, 0, B * sizeof(SysState), s));
         HIP_TRY(hipHostMalloc((void **)&M->h_state, B * sizeof(SysState), hipHostMallocDefault));
         HIP_TRY(hipHostMalloc((void **)&M->h_ctr, 2 * sizeof(rs::SweepCtr), hipHostMallocDefault));
-        const size_t nf = B * ((size_t)M->sch.ltiles.n + M->sch.utiles.n);
+        const size_t nf = B * ((size_t)M->an->sch.ltiles.n + M->an->sch.utiles.n);
         HIP_TRY(M->flags.alloc(nf * sizeof(int32_t)));
-        HIP_TRY(hipMemset(M->flags.p, 0, nf * sizeof(int32_t)));
+        HIP_TRY(hipMemsetAsync(M->flags.p, 0, nf * sizeof(int32_t), s));
         HIP_TRY(M->ctrs.alloc(2 * sizeof(rs::SweepCtr)));
-        HIP_TRY(hipMemset(M->ctrs.p, 0, 2 * sizeof(rs::SweepCtr)));
+        HIP_TRY(hipMemsetAsync(M->ctrs.p, 0, 2 * sizeof(rs::SweepCtr), s));
     }
     double *w = M->work.as<double>();
     Krylov &k = M->k;
@@ -614,7 +675,7 @@ static int ensure_workspace(ilu0_t M) {
     k.spart_stride = sstride;
     k.st = M->state.as<SysState>();
     k.lflags = M->flags.as<int32_t>();
-    k.uflags = k.lflags + B * (size_t)M->sch.ltiles.n;
+    k.uflags = k.lflags + B * (size_t)M->an->sch.ltiles.n;
     k.lctr = M->ctrs.as<rs::SweepCtr>();
     k.uctr = k.lctr + 1;
     return RS_OK;
@@ -627,7 +688,8 @@ static int sweep_error(ilu0_t M, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(c, M->ctrs.p, sizeof c, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (c[0].error || c[1].error) {
-        HIP_TRY(hipMemset(M->ctrs.p, 0, sizeof c));
+        HIP_TRY(hipMemsetAsync(M->ctrs.p, 0, sizeof c, s));
+        HIP_TRY(hipStreamSynchronize(s));
         return fail(RS_HIP_ERROR, "sweep dependency wait exceeded its limit");
     }
     return RS_OK;
@@ -639,7 +701,7 @@ static int sweep_error(ilu0_t M, hipStream_t s) {
 template <typename T>
 static void apply_levels(ilu0_t M, const T *L, const T *U, const T *D, const double *in, double *out, bool fuse_p,
                          Krylov &k, SysState *st, int nsys, hipStream_t s) {
-    const rs::Schedule &S = M->sch;
+    const rs::Schedule &S = M->an->sch;
     const size_t vs = k.vstride;
     const double n = M->n, tb = sizeof(T), B = nsys;
     T *y = (T *)k.y;
@@ -649,11 +711,11 @@ static void apply_levels(ilu0_t M, const T *L, const T *U, const T *D, const dou
         const double bytes = B * ((9 * tb + 4) * S.nL + 8 * n + (fuse_p ? 96 : 24) * n + 3 * tb * n);
         ProfScope ps(PC_LSWEEP, s, bytes);
         if (M->tile_sweeps)
-            rs::launch_lsweep_tiles<T>(M->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, k.lflags,
+            rs::launch_lsweep_tiles<T>(M->an->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, k.lflags,
                                        k.lctr, nsys, M->sweep_grid, s);
         else
             for (int l = 0; l < S.nl_levels; ++l)
-                rs::launch_lsweep<T>(M->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, S.lset[l],
+                rs::launch_lsweep<T>(M->an->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, S.lset[l],
                                      S.lset[l + 1], nsys, M->sweep_variant, s);
     }
     {
@@ -661,11 +723,11 @@ static void apply_levels(ilu0_t M, const T *L, const T *U, const T *D, const dou
         const double bytes = B * ((9 * tb + 4) * S.nU + 9 * tb * n + 8 * n + 3 * tb * n + 24 * n);
         ProfScope ps(PC_USWEEP, s, bytes);
         if (M->tile_sweeps)
-            rs::launch_usweep_tiles<T>(M->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, k.uflags,
+            rs::launch_usweep_tiles<T>(M->an->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, k.uflags,
                                        k.uctr, nsys, M->sweep_grid, s);
         else
             for (int l = 0; l < S.nu_levels; ++l)
-                rs::launch_usweep<T>(M->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, S.uset[l],
+                rs::launch_usweep<T>(M->an->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, S.uset[l],
                                      S.uset[l + 1], nsys, M->sweep_variant, s);
     }
 }
@@ -686,12 +748,12 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
     if (parts & IT_APPLY1) apply_levels<T>(M, L, U, D, nullptr, k.phat, true, k, k.st, B, s);
     if (parts & IT_SPMV_V) {
         ProfScope ps(PC_SPMV_V, s, spmv_bytes);
-        rs::launch_spmv_v(M->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, s);
+        rs::launch_spmv_v(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, s);
     }
     if (!(parts & IT_REST)) return;
     { ProfScope ps(PC_VEC, s, B * 72 * n); rs::launch_s_update(M->n, k, B, M->spmv_variant, s); }
     apply_levels<T>(M, L, U, D, k.s, k.shat, false, k, k.st, B, s);
-    { ProfScope ps(PC_SPMV_T, s, spmv_bytes); rs::launch_spmv_t(M->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, s); }
+    { ProfScope ps(PC_SPMV_T, s, spmv_bytes); rs::launch_spmv_t(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, s); }
     { ProfScope ps(PC_VEC, s, B * 192 * n); rs::launch_xr_update(M->n, k, B, M->spmv_variant, s); }
 }
 
@@ -755,9 +817,9 @@ int ilu0_apply(ilu0_t M, const double *v, double *z, int32_t first_sys, int32_t 
         return fail(RS_INVALID_ARG, "ilu0_apply: bad arguments");
     if (!M->factored) return fail(RS_NOT_FACTORED, "ilu0_apply: not factored");
     if (n_sys == 0 || M->n == 0) return RS_OK;
-    int st = ensure_workspace(M);
-    if (st != RS_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    int st = ensure_workspace(M, s);
+    if (st != RS_OK) return st;
     const size_t m = 3 * (size_t)M->n * n_sys;
     const double *vd = nullptr;
     st = stage_in(v, mem, M->bstage, m, s, &vd);
@@ -768,8 +830,8 @@ int ilu0_apply(ilu0_t M, const double *v, double *z, int32_t first_sys, int32_t 
         zd = M->xstage.as<double>();
     }
     Krylov &k = M->k;
-    const rs::Schedule &S = M->sch;
-    rs::launch_permute_vec(M->dev.perm, vd, k.s, M->n, k.vstride, n_sys, false, s);
+    const rs::Schedule &S = M->an->sch;
+    rs::launch_permute_vec(M->an->dev.perm, vd, k.s, M->n, k.vstride, n_sys, false, s);
     if (M->precision == RS_PREC_FP32_FACTORS)
         apply_levels<float>(M, M->Lf.as<float>() + (size_t)first_sys * S.nL * 9,
                             M->Uf.as<float>() + (size_t)first_sys * S.nU * 9,
@@ -780,7 +842,7 @@ int ilu0_apply(ilu0_t M, const double *v, double *z, int32_t first_sys, int32_t 
                              M->U.as<double>() + (size_t)first_sys * S.nU * 9,
                              M->Dinv.as<double>() + (size_t)first_sys * M->n * 9, k.s, k.shat, false, k, nullptr,
                              n_sys, s);
-    rs::launch_permute_vec(M->dev.perm, k.shat, zd, M->n, k.vstride, n_sys, true, s);
+    rs::launch_permute_vec(M->an->dev.perm, k.shat, zd, M->n, k.vstride, n_sys, true, s);
     HIP_TRY(hipGetLastError());
     if (mem != RS_MEM_DEVICE) HIP_TRY(hipMemcpyAsync(z, zd, m * sizeof(double), hipMemcpyDeviceToHost, s));
     return sweep_error(M, s);
@@ -806,9 +868,9 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
             for (int i = 0; i < B; ++i) info[i] = solve_info{RS_OK, 0, 0.0, 0.0, 0.0};
         return RS_OK;
     }
-    st = ensure_workspace(M);
-    if (st != RS_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    st = ensure_workspace(M, s);
+    if (st != RS_OK) return st;
     const size_t m = 3 * (size_t)M->n * B;
     const double *bd = nullptr;
     st = stage_in(b, mem, M->bstage, m, s, &bd);
@@ -821,7 +883,7 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
     Krylov &k = M->k;
     {
         ProfScope ps(PC_VEC, s, (double)B * 152 * M->n);
-        rs::launch_setup(M->dev, bd, M->bad.as<int32_t>(), reduction, max_iter, k, B, s);
+        rs::launch_setup(M->an->dev, bd, M->bad.as<int32_t>(), reduction, max_iter, k, B, s);
     }
     int done_iters = 0;
     bool first = true;
@@ -840,7 +902,7 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
         for (int i = 0; i < B; ++i) all &= (M->h_state[i].phase == rs::PH_DONE);
         if (all) break;
     }
-    rs::launch_finish(M->dev, A->rowptr.as<int32_t>(), A->colidx.as<int32_t>(), A->vals.as<double>(),
+    rs::launch_finish(M->an->dev, A->rowptr.as<int32_t>(), A->colidx.as<int32_t>(), A->vals.as<double>(),
                       (size_t)A->nnzb * 9, bd, xd, k, B, M->spmv_variant, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
@@ -848,7 +910,8 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
     if (mem != RS_MEM_DEVICE) HIP_TRY(hipMemcpyAsync(x, xd, m * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (M->h_ctr[0].error || M->h_ctr[1].error) {
-        HIP_TRY(hipMemset(M->ctrs.p, 0, 2 * sizeof(rs::SweepCtr)));
+        HIP_TRY(hipMemsetAsync(M->ctrs.p, 0, 2 * sizeof(rs::SweepCtr), s));
+        HIP_TRY(hipStreamSynchronize(s));
         return fail(RS_HIP_ERROR, "sweep dependency wait exceeded its limit");
     }
     int worst = RS_OK, needed = 1;
@@ -887,8 +950,8 @@ static std::string tune_key(ilu0_t M) {
     hipDeviceProp_t prop{};
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) prop.multiProcessorCount = 0;
     std::ostringstream k;
-    k << "n=" << M->n << ",nnzb=" << M->nnzb << ",batch=" << M->batch << ",ord=" << M->sch.ordering
-      << ",prec=" << M->precision << ",nl=" << M->sch.nl_levels << ",nu=" << M->sch.nu_levels
+    k << "n=" << M->n << ",nnzb=" << M->nnzb << ",batch=" << M->batch << ",ord=" << M->an->sch.ordering
+      << ",prec=" << M->precision << ",nl=" << M->an->sch.nl_levels << ",nu=" << M->an->sch.nu_levels
       << ",arch=" << prop.gcnArchName << ",cu=" << prop.multiProcessorCount;
     std::string r = k.str();
     for (char &c : r)

@@ -1,23 +1,26 @@
 // Request server: continuous admission of BiCGStab-ILU0 solves of mixed
 // sizes under a device-memory budget.
 //
+// Patterns are registered once (a reservoir model keeps its sparsity
+// pattern across Newton steps); requests name one and bring values, b and x.
 // Requests are queued in arrival order.  Each of `max_slots` worker threads
-// owns a HIP stream and a cached (matrix, preconditioner) handle pair; it
-// takes the request at the head of the queue as soon as that request's
-// device footprint fits in the budget, so requests that arrive while others
-// run are admitted as slots and memory free up, and the work of different
-// slots overlaps on the device.  A slot keeps its handles after a request:
-// the next request with the same pattern reuses the analysis, schedule,
-// buffers and captured graphs and only uploads values, factors and solves.
-// When the head of the queue does not fit, idle slots drop their cached
-// handles until it does (a request larger than the whole budget is refused
-// at submission), so admission cannot deadlock.
+// owns a HIP stream; it takes the request at the head of the queue as soon
+// as either an idle resident instance of the request's pattern exists, or a
+// new instance fits in the budget.  An instance is a (matrix,
+// preconditioner) handle pair with its factors and Krylov workspace; it
+// stays resident after its request, so the steady state allocates nothing
+// and runs no analysis.  All instances of one pattern share one analysis
+// (ilu0_analyse_shared), which is reserved once per pattern.  When the head
+// of the queue does not fit, idle instances are freed, least recently used
+// first; a pattern whose single instance exceeds the budget is refused at
+// registration, so admission cannot deadlock.  The budget is an account of
+// the footprints: an evicted instance's memory is released right after the
+// admission that evicted it.
 //
-// Inputs are borrowed: pattern arrays must be host memory; values, b and x
-// live where `mem` says, and must stay valid until the request completes.
-// Slots launch their kernels directly (no graph capture): a capture on one
-// slot's stream would be invalidated by another slot's device-synchronising
-// calls (frees, synchronous copies).
+// Inputs are borrowed: values, b and x live where `mem` says and must stay
+// valid until the request completes.  Slots launch their kernels directly
+// (no graph capture): a capture on one slot's stream would be invalidated
+// by another slot's device-synchronising calls (frees, synchronous copies).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,6 +34,7 @@
 #include <vector>
 
 #include "../../include/rsolve.h"
+#include "analysis.h"
 
 namespace {
 
@@ -40,28 +44,46 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
     return std::chrono::duration<double, std::milli>(b - a).count();
 }
 
-uint64_t pattern_hash(int32_t n, int32_t nnzb, const int32_t *rowptr, const int32_t *colidx) {
+uint64_t words_hash(const std::vector<int32_t> &a, const std::vector<int32_t> &b) {
     uint64_t h = 1469598103934665603ull;
-    auto mix = [&](const void *p, size_t bytes) {
-        const unsigned char *c = (const unsigned char *)p;
-        for (size_t i = 0; i < bytes; ++i) h = (h ^ c[i]) * 1099511628211ull;
-    };
-    mix(&n, sizeof n);
-    mix(&nnzb, sizeof nnzb);
-    mix(rowptr, sizeof(int32_t) * ((size_t)n + 1));
-    mix(colidx, sizeof(int32_t) * (size_t)nnzb);
+    for (const auto *v : {&a, &b})
+        for (int32_t w : *v) h = (h ^ (uint32_t)w) * 1099511628211ull;
     return h;
 }
 
+struct Instance;
+
+struct Pattern {
+    int32_t id = 0, n = 0, nnzb = 0;
+    std::vector<int32_t> rowptr, colidx;
+    uint64_t hash = 0;
+    size_t inst_bytes = 0, an_bytes = 0;
+    std::vector<Instance *> inst;   // resident instances and those being created
+    bool tuned = false;             // a tuner ran or runs; `opts` valid once opts_version > 0
+    int opts_version = 0;
+    int32_t opts[4] = {};           // spmv variant, sweep variant, sweep tiles, sweep grid
+};
+
+struct Instance {
+    Pattern *pat = nullptr;
+    bcsr_t A = nullptr;
+    ilu0_t M = nullptr;
+    bool ready = false;   // handles created
+    bool busy = false;    // a request runs on it, or it is being created
+    int pins = 0;         // creators reading its analysis
+    uint64_t seq = 0;     // creation order
+    int opts_version = 0;
+    size_t bytes = 0;
+    uint64_t last_use = 0;
+};
+
 struct Request {
     int64_t id = 0;
-    int32_t n = 0, nnzb = 0, mem = RS_MEM_HOST, max_iter = 200;
-    const int32_t *rowptr = nullptr, *colidx = nullptr;
+    Pattern *pat = nullptr;
+    int32_t mem = RS_MEM_HOST, max_iter = 200;
     const double *vals = nullptr, *b = nullptr;
     double *x = nullptr;
     double reduction = 1e-2;
-    uint64_t hash = 0;
-    size_t bytes = 0;
     Clock::time_point t_submit;
     bool done = false;
     int32_t status = RS_OK;
@@ -72,23 +94,28 @@ struct Request {
 struct Slot {
     int id = 0;
     hipStream_t stream = nullptr;
-    bcsr_t A = nullptr;
-    ilu0_t M = nullptr;
-    uint64_t hash = 0;
-    int32_t n = -1, nnzb = -1;
-    size_t held = 0;   // bytes of the budget this slot holds (server lock)
-    bool tuned = false;
     std::thread th;
-    void drop() {      // destroy the cached handles (budget accounting is the caller's)
-        ilu0_destroy(M);
-        bcsr_destroy(A);
-        M = nullptr;
-        A = nullptr;
-        hash = 0;
-        n = nnzb = -1;
-        tuned = false;
-    }
 };
+
+void destroy_instance(Instance *I) {
+    ilu0_destroy(I->M);
+    bcsr_destroy(I->A);
+    delete I;
+}
+
+// An instance of P created before `self` is still being created (only the
+// earliest creator analyses; later ones wait for it and share).
+bool earlier_creating(const Pattern *P, const Instance *self) {
+    for (const Instance *J : P->inst)
+        if (J->seq < self->seq && !J->ready) return true;
+    return false;
+}
+
+Instance *ready_instance(const Pattern *P) {
+    for (Instance *J : P->inst)
+        if (J->ready) return J;
+    return nullptr;
+}
 
 }  // namespace
 
@@ -96,27 +123,28 @@ struct rs_server {
     server_config cfg{};
     int device = 0;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_done, cv_ready;
     std::deque<Request *> queue;
     std::unordered_map<int64_t, Request *> live;
+    std::vector<Pattern *> patterns;
     std::vector<Slot *> slots;
     size_t reserved = 0, peak = 0;
     int64_t next_id = 1;
-    int64_t completed = 0, running = 0;
+    int64_t completed = 0, running = 0, instances = 0, created = 0, evicted = 0, analyses = 0;
+    uint64_t clock = 0;
     bool stopping = false;
 };
 
-// Device bytes a request keeps while it is resident: the caller's matrix,
-// its reordered copy and factors, the schedule, the Krylov workspace and
-// staging, as allocated by bcsr_create / ilu0_analyse / ilu0_factor /
-// bicgstab_solve.
-static size_t footprint(int32_t n, int32_t nnzb, int32_t precision) {
+// Device bytes of one instance while it is resident, as allocated by
+// bcsr_create / ilu0_factor / bicgstab_solve: the caller-order matrix, its
+// reordered copy and FP64 factors (plus FP32 copies), the Krylov vectors,
+// sweep intermediate, staging and reduction partials.
+static size_t instance_bytes(int32_t n, int32_t nnzb, int32_t precision) {
     const double N = n, Z = nnzb;
     const double vec = 3.0 * N + 1024.0;
     double b = 72 * Z + 4 * (N + Z)                  // caller's matrix
                + 72 * Z                              // reordered copy
                + 72 * Z                              // FP64 factors (L, U, inv(U_ii))
-               + 4 * (8 * Z + 14 * N)                // schedule and update lists
                + 8 * (10 * vec + 2 * 3 * N)          // Krylov vectors, sweep intermediate, staging
                + 8 * (2 * N / 21 + 8192)             // reduction partials
                + (1 << 20);                          // small buffers
@@ -124,102 +152,211 @@ static size_t footprint(int32_t n, int32_t nnzb, int32_t precision) {
     return (size_t)b;
 }
 
+// Device bytes of a pattern's shared analysis: permutation, reordered
+// pattern, sweep schedules and factor update lists (a bound for 7-point
+// patterns with non-neighbour connections).
+static size_t analysis_bytes(int32_t n, int32_t nnzb) {
+    return (size_t)(4 * (8.0 * nnzb + 14.0 * n)) + (1 << 16);
+}
+
 static bool hard_error(int st) { return st < 0 && st != RS_ZERO_PIVOT && st != RS_NON_FINITE; }
+
+// Under the lock: take the head request if it can run now, on an idle
+// resident instance of its pattern or on a new one (returned not ready).
+// Idle instances freed to make room are appended to `victims`; the caller
+// destroys them after unlocking.
+static Request *admit(rs_server *S, Instance **out, std::vector<Instance *> &victims) {
+    Request *h = S->queue.front();
+    Pattern *P = h->pat;
+    Instance *idle = nullptr;
+    for (Instance *I : P->inst)
+        if (I->ready && !I->busy && (!idle || I->last_use > idle->last_use)) idle = I;
+    if (idle) {
+        idle->busy = true;
+        S->queue.pop_front();
+        *out = idle;
+        return h;
+    }
+    for (;;) {
+        const size_t need = P->inst_bytes + (P->inst.empty() ? P->an_bytes : 0);
+        if (S->reserved + need <= S->cfg.hbm_budget_bytes) break;
+        // free the least recently used idle instance of any pattern
+        Instance *v = nullptr;
+        for (Pattern *Q : S->patterns)
+            for (Instance *I : Q->inst)
+                if (I->ready && !I->busy && I->pins == 0 && (!v || I->last_use < v->last_use)) v = I;
+        if (!v) return nullptr;
+        Pattern *Q = v->pat;
+        Q->inst.erase(std::find(Q->inst.begin(), Q->inst.end(), v));
+        S->reserved -= v->bytes + (Q->inst.empty() ? Q->an_bytes : 0);
+        --S->instances;
+        ++S->evicted;
+        victims.push_back(v);
+    }
+    const size_t need = P->inst_bytes + (P->inst.empty() ? P->an_bytes : 0);
+    Instance *I = new Instance();
+    I->pat = P;
+    I->busy = true;
+    I->bytes = P->inst_bytes;
+    I->seq = ++S->clock;
+    P->inst.push_back(I);
+    S->reserved += need;
+    S->peak = std::max(S->peak, S->reserved);
+    ++S->instances;
+    ++S->created;
+    S->queue.pop_front();
+    *out = I;
+    return h;
+}
+
+// Create the handles of a new instance: share the analysis of a ready
+// instance of the pattern, waiting for one that is being created, else
+// analyse.
+static int create_instance(rs_server *S, Slot *sl, Instance *I) {
+    Pattern *P = I->pat;
+    int32_t bad = -1;
+    int st = bcsr_create(P->n, P->nnzb, 3, 1, P->rowptr.data(), P->colidx.data(), nullptr, RS_MEM_HOST, sl->stream,
+                         &I->A, &bad);
+    if (st != RS_OK) return st;
+    Instance *like = nullptr;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv_ready.wait(lk, [&] { return ready_instance(P) || !earlier_creating(P, I); });
+        like = ready_instance(P);
+        if (like) ++like->pins;
+    }
+    if (like) {
+        st = ilu0_analyse_shared(I->A, like->M, &I->M);
+    } else {
+        st = ilu0_analyse(I->A, S->cfg.ordering, &I->M);
+    }
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (like) --like->pins;
+        else if (st == RS_OK) ++S->analyses;
+    }
+    if (st == RS_OK) st = ilu0_set_option(I->M, RS_OPT_USE_GRAPH, 0);
+    return st;
+}
+
+static void apply_opts(Instance *I, const int32_t (&o)[4]) {
+    (void)bcsr_set_option(I->A, RS_OPT_SPMV_VARIANT, o[0]);
+    (void)ilu0_set_option(I->M, RS_OPT_SPMV_VARIANT, o[0]);
+    (void)ilu0_set_option(I->M, RS_OPT_SWEEP_VARIANT, o[1]);
+    (void)ilu0_set_option(I->M, RS_OPT_SWEEP_TILES, o[2]);
+    (void)ilu0_set_option(I->M, RS_OPT_SWEEP_GRID, o[3]);
+}
 
 static void slot_main(rs_server *S, Slot *sl) {
     (void)hipSetDevice(S->device);
     for (;;) {
         Request *r = nullptr;
-        bool reuse = false;
+        Instance *I = nullptr;
+        std::vector<Instance *> victims;
+        bool stop = false;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             for (;;) {
-                if (!S->queue.empty()) {
-                    Request *h = S->queue.front();
-                    reuse = sl->M && sl->hash == h->hash && sl->n == h->n && sl->nnzb == h->nnzb;
-                    const size_t after = reuse ? S->reserved : S->reserved - sl->held + h->bytes;
-                    if (after <= S->cfg.hbm_budget_bytes) {
-                        S->queue.pop_front();
-                        r = h;
-                        if (!reuse) sl->held = h->bytes;
-                        S->reserved = after;
-                        S->peak = std::max(S->peak, S->reserved);
-                        ++S->running;
-                        break;
-                    }
-                    if (sl->M) {
-                        // the head does not fit: give back this idle slot's handles
-                        const size_t freed = sl->held;
-                        sl->held = 0;
-                        lk.unlock();
-                        sl->drop();
-                        lk.lock();
-                        S->reserved -= freed;
-                        S->cv_work.notify_all();
-                        continue;
-                    }
-                } else if (S->stopping) {
-                    S->reserved -= sl->held;
-                    sl->held = 0;
-                    lk.unlock();
-                    sl->drop();
-                    return;
+                if (!S->queue.empty() && (r = admit(S, &I, victims))) break;
+                if (S->queue.empty() && S->stopping) {
+                    stop = true;
+                    break;
                 }
+                if (!victims.empty()) break;     // free them, then look again
                 S->cv_work.wait(lk);
             }
+            if (r) ++S->running;
         }
+        for (Instance *v : victims) destroy_instance(v);
+        if (stop) return;
+        if (!r) continue;
         const Clock::time_point t0 = Clock::now();
         r->timing.queue_ms = ms_between(r->t_submit, t0);
         r->timing.slot = sl->id;
+        r->timing.resident = I->ready ? 1 : 0;
+        Pattern *P = I->pat;
         int st = RS_OK;
-        if (!reuse) {
-            sl->drop();
-            int32_t bad = -1;
-            st = bcsr_create(r->n, r->nnzb, 3, 1, r->rowptr, r->colidx, nullptr, RS_MEM_HOST, sl->stream, &sl->A, &bad);
-            if (st == RS_OK) st = ilu0_analyse(sl->A, S->cfg.ordering, &sl->M);
-            // other slots allocate, free and copy synchronously at any time,
-            // which would invalidate a stream capture: launch directly
-            if (st == RS_OK) st = ilu0_set_option(sl->M, RS_OPT_USE_GRAPH, 0);
-            if (st == RS_OK) {
-                sl->hash = r->hash;
-                sl->n = r->n;
-                sl->nnzb = r->nnzb;
+        if (!I->ready) {
+            st = create_instance(S, sl, I);
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                I->ready = st == RS_OK;
             }
+            S->cv_ready.notify_all();
+        }
+        int32_t opts[4];
+        int version = 0;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (P->opts_version > I->opts_version) {
+                std::memcpy(opts, P->opts, sizeof opts);
+                version = P->opts_version;
+            }
+        }
+        if (st == RS_OK && version) {
+            apply_opts(I, opts);
+            I->opts_version = version;
         }
         const Clock::time_point t1 = Clock::now();
         r->timing.analyse_ms = ms_between(t0, t1);
-        if (st == RS_OK) st = bcsr_set_values(sl->A, r->vals, 0, 1, r->mem, sl->stream);
+        if (st == RS_OK) st = bcsr_set_values(I->A, r->vals, 0, 1, r->mem, sl->stream);
         if (st == RS_OK) {
             int32_t bad = -1;
-            st = ilu0_factor(sl->M, sl->A, S->cfg.precision, sl->stream, &bad);
+            st = ilu0_factor(I->M, I->A, S->cfg.precision, sl->stream, &bad);
         }
         const Clock::time_point t2 = Clock::now();
         r->timing.factor_ms = ms_between(t1, t2);
-        if (st == RS_OK && S->cfg.autotune && !sl->tuned) {
+        bool tune = false;
+        if (st == RS_OK && S->cfg.autotune) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (!P->tuned) {
+                P->tuned = true;          // one tuner per pattern; other instances keep defaults until it ends
+                tune = true;
+            }
+        }
+        if (tune) {
             rs_tune_result tr{};
-            st = ilu0_autotune(sl->M, sl->A, r->b, r->mem, r->reduction, 1, sl->stream, &tr);
-            sl->tuned = true;
+            const int ts = ilu0_autotune(I->M, I->A, r->b, r->mem, r->reduction, 1, sl->stream, &tr);
+            if (ts == RS_OK) {
+                std::lock_guard<std::mutex> lk(S->mu);
+                P->opts[0] = tr.spmv_variant;
+                P->opts[1] = tr.sweep_variant;
+                P->opts[2] = tr.sweep_tiles;
+                P->opts[3] = tr.sweep_grid;
+                I->opts_version = ++P->opts_version;
+            } else if (hard_error(ts)) {
+                st = ts;
+            }
         }
         const Clock::time_point t3 = Clock::now();
         r->timing.tune_ms = ms_between(t2, t3);
         if (st == RS_OK)
-            st = bicgstab_solve(sl->M, sl->A, r->b, r->x, r->reduction, r->max_iter, r->mem, sl->stream, &r->info);
+            st = bicgstab_solve(I->M, I->A, r->b, r->x, r->reduction, r->max_iter, r->mem, sl->stream, &r->info);
         else
             r->info.status = st;
         const Clock::time_point t4 = Clock::now();
         r->timing.solve_ms = ms_between(t3, t4);
         r->timing.total_ms = ms_between(r->t_submit, t4);
-        if (hard_error(st)) sl->drop();   // the handles may be unusable
+        Instance *dead = nullptr;
         {
             std::lock_guard<std::mutex> lk(S->mu);
-            if (hard_error(st)) {
-                S->reserved -= sl->held;
-                sl->held = 0;
+            I->busy = false;
+            I->last_use = ++S->clock;
+            if ((hard_error(st) || !I->ready) && I->pins == 0) {
+                // the handles may be unusable: give the instance back
+                P->inst.erase(std::find(P->inst.begin(), P->inst.end(), I));
+                S->reserved -= I->bytes + (P->inst.empty() ? P->an_bytes : 0);
+                --S->instances;
+                dead = I;
             }
             r->status = st;
             r->done = true;
             --S->running;
             ++S->completed;
+        }
+        if (dead) {
+            destroy_instance(dead);
+            S->cv_ready.notify_all();
         }
         S->cv_done.notify_all();
         S->cv_work.notify_all();
@@ -256,40 +393,73 @@ int server_create(const server_config *cfg, server_t *out) {
 
 int server_request_bytes(int32_t n_brows, int32_t nnzb, int32_t precision, size_t *bytes) {
     if (n_brows < 0 || nnzb < 0 || !bytes) return RS_INVALID_ARG;
-    *bytes = footprint(n_brows, nnzb, precision);
+    *bytes = instance_bytes(n_brows, nnzb, precision);
     return RS_OK;
 }
 
-int server_submit(server_t S, int32_t n_brows, int32_t nnzb, const int32_t *row_ptr, const int32_t *col_idx,
-                  const double *vals, const double *b, double *x, double reduction, int32_t max_iter, int32_t mem,
-                  int64_t *ticket) {
-    if (!S || !ticket || n_brows < 0 || nnzb < 0 || !row_ptr || (nnzb > 0 && !col_idx) || !vals || !b || !x ||
-        !(reduction >= 0.0) || max_iter < 0 || (mem != RS_MEM_HOST && mem != RS_MEM_DEVICE))
+int server_analysis_bytes(int32_t n_brows, int32_t nnzb, size_t *bytes) {
+    if (n_brows < 0 || nnzb < 0 || !bytes) return RS_INVALID_ARG;
+    *bytes = analysis_bytes(n_brows, nnzb);
+    return RS_OK;
+}
+
+int server_add_pattern(server_t S, int32_t n_brows, int32_t nnzb, const int32_t *row_ptr, const int32_t *col_idx,
+                       int32_t *pattern, int32_t *bad_row) {
+    if (bad_row) *bad_row = -1;
+    if (!S || !pattern || n_brows < 0 || nnzb < 0 || !row_ptr || (nnzb > 0 && !col_idx)) return RS_INVALID_ARG;
+    Pattern *P = new Pattern();
+    P->n = n_brows;
+    P->nnzb = nnzb;
+    P->rowptr.assign(row_ptr, row_ptr + (size_t)n_brows + 1);
+    P->colidx.assign(col_idx, col_idx + nnzb);
+    int bad = -1;
+    const int st = rs::validate_pattern(n_brows, nnzb, P->rowptr.data(), P->colidx.data(), &bad);
+    if (st != RS_OK) {
+        if (bad_row) *bad_row = bad;
+        delete P;
+        return st;
+    }
+    P->hash = words_hash(P->rowptr, P->colidx);
+    P->inst_bytes = instance_bytes(n_brows, nnzb, S->cfg.precision);
+    P->an_bytes = analysis_bytes(n_brows, nnzb);
+    if (P->inst_bytes + P->an_bytes > S->cfg.hbm_budget_bytes) {
+        delete P;
+        return RS_OUT_OF_MEMORY;
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (Pattern *Q : S->patterns)
+        if (Q->hash == P->hash && Q->n == P->n && Q->nnzb == P->nnzb && Q->rowptr == P->rowptr &&
+            Q->colidx == P->colidx) {
+            *pattern = Q->id;
+            delete P;
+            return RS_OK;
+        }
+    P->id = (int32_t)S->patterns.size();
+    S->patterns.push_back(P);
+    *pattern = P->id;
+    return RS_OK;
+}
+
+int server_submit(server_t S, int32_t pattern, const double *vals, const double *b, double *x, double reduction,
+                  int32_t max_iter, int32_t mem, int64_t *ticket) {
+    if (!S || !ticket || !vals || !b || !x || !(reduction >= 0.0) || max_iter < 0 ||
+        (mem != RS_MEM_HOST && mem != RS_MEM_DEVICE))
         return RS_INVALID_ARG;
     Request *r = new Request();
-    r->n = n_brows;
-    r->nnzb = nnzb;
-    r->rowptr = row_ptr;
-    r->colidx = col_idx;
     r->vals = vals;
     r->b = b;
     r->x = x;
     r->mem = mem;
     r->reduction = reduction;
     r->max_iter = max_iter;
-    r->hash = pattern_hash(n_brows, nnzb, row_ptr, col_idx);
-    r->bytes = footprint(n_brows, nnzb, S->cfg.precision);
-    if (r->bytes > S->cfg.hbm_budget_bytes) {
-        delete r;
-        return RS_OUT_OF_MEMORY;
-    }
     r->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(S->mu);
-        if (S->stopping) {
+        if (S->stopping || pattern < 0 || pattern >= (int32_t)S->patterns.size()) {
             delete r;
             return RS_INVALID_ARG;
         }
+        r->pat = S->patterns[pattern];
         r->id = S->next_id++;
         S->live[r->id] = r;
         S->queue.push_back(r);
@@ -333,6 +503,10 @@ int server_get_stats(server_t S, server_stats *out) {
     out->queued = (int64_t)S->queue.size();
     out->running = S->running;
     out->completed = S->completed;
+    out->instances = S->instances;
+    out->created = S->created;
+    out->evicted = S->evicted;
+    out->analyses = S->analyses;
     out->reserved_bytes = S->reserved;
     out->peak_reserved_bytes = S->peak;
     return RS_OK;
@@ -347,8 +521,11 @@ int server_destroy(server_t S) {
     S->cv_work.notify_all();
     for (Slot *sl : S->slots)
         if (sl->th.joinable()) sl->th.join();
+    for (Pattern *P : S->patterns) {
+        for (Instance *I : P->inst) destroy_instance(I);
+        delete P;
+    }
     for (Slot *sl : S->slots) {
-        sl->drop();
         if (sl->stream) (void)hipStreamDestroy(sl->stream);
         delete sl;
     }

@@ -109,26 +109,33 @@ def _pattern(nx, ny, nz, rng, active_frac, nnc_frac):
 
 
 def _assemble(n, u, v, k, a, cmat, dpert):
-    """Blocks from the drawn fields; returns rowptr, colidx, vals, trans."""
+    """Blocks from the drawn fields; returns rowptr, colidx, vals, trans.
+
+    Every block is written straight to its sorted position (row, then
+    column), so no unsorted copy of the values is ever materialised.
+    """
     trans_u = 2.0 * k[u] * k[v] / (k[u] + k[v])
     du = np.concatenate([u, v])
     dv = np.concatenate([v, u])
     dt = np.concatenate([trans_u, trans_u])
-    off = -dt[:, None, None] * cmat
-    tc = dt[:, None, None] * cmat
+    m = du.shape[0]
+    rows = np.concatenate([du, np.arange(n, dtype=np.int64)])
+    cols = np.concatenate([dv, np.arange(n, dtype=np.int64)])
+    order = np.argsort(rows * max(n, 1) + cols, kind="stable")
+    pos = np.empty_like(order)
+    pos[order] = np.arange(order.shape[0], dtype=order.dtype)
+    vals = np.empty((m + n, 3, 3))
     diag = a[:, None, None] * (np.eye(3)[None, :, :] + dpert)
     for r in range(3):
         for c in range(3):
-            diag[:, r, c] += np.bincount(du, weights=tc[:, r, c], minlength=n)
-    rows = np.concatenate([du, np.arange(n, dtype=np.int64)])
-    cols = np.concatenate([dv, np.arange(n, dtype=np.int64)])
-    blocks = np.concatenate([off, diag], axis=0)
-    trans = np.concatenate([dt, np.zeros(n)])
-    order = np.lexsort((cols, rows))
+            diag[:, r, c] += np.bincount(du, weights=dt * cmat[:, r, c], minlength=n)
+    cmat *= -dt[:, None, None]          # the couplings become the off-diagonal blocks
+    vals[pos[:m]] = cmat
+    vals[pos[m:]] = diag
+    trans = np.concatenate([dt, np.zeros(n)])[order]
     rowptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(np.bincount(rows, minlength=n), out=rowptr[1:])
-    return (rowptr.astype(np.int32), cols[order].astype(np.int32),
-            np.ascontiguousarray(blocks[order]), trans[order])
+    return rowptr.astype(np.int32), cols[order].astype(np.int32), vals, trans
 
 
 def _one(nx, ny, nz, sigma, active_frac, nnc_frac, seed, n_rhs):

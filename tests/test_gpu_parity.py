@@ -396,6 +396,73 @@ def test_handle_errors(solver_of):
         rs.bcsr_destroy(A)
 
 
+def test_shared_analysis_gives_identical_factors_and_solutions():
+    s = CASES["nnc"]
+    for ordering in ORDERINGS:
+        A = rs.bcsr_create(s.rowptr, s.colidx, s.vals)
+        M = rs.ilu0_analyse(A, ordering)
+        A2 = rs.bcsr_create(s.rowptr, s.colidx, s.vals)
+        M2 = rs.ilu0_analyse_shared(A2, M)
+        try:
+            rs.ilu0_factor(M, A)
+            x1, st1, i1 = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-10)
+            lu1, d1 = rs.ilu0_get_factors(M, 0, s.n, s.nnzb)
+            rs.ilu0_destroy(M)                    # the shared analysis outlives the handle it came from
+            M = None
+            rs.ilu0_factor(M2, A2)
+            x2, st2, i2 = rs.bicgstab_solve(M2, A2, s.b[:, 0], reduction=1e-10)
+            lu2, d2 = rs.ilu0_get_factors(M2, 0, s.n, s.nnzb)
+            assert st1 == st2 == rs.OK and i1[0]["half_steps"] == i2[0]["half_steps"]
+            assert np.array_equal(lu1, lu2) and np.array_equal(d1, d2) and np.array_equal(x1, x2)
+            assert rs.ilu0_get_schedule(M2, s.n)[0].tolist() == oracle.ordering_perm(
+                s.rowptr, s.colidx, ordering).tolist()
+            other = CASES["c1"]
+            B = rs.bcsr_create(other.rowptr, other.colidx, other.vals)
+            with pytest.raises(rs.RsolveError) as e:
+                rs.ilu0_analyse_shared(B, M2)
+            assert e.value.status == rs.PATTERN_MISMATCH
+            rs.bcsr_destroy(B)
+        finally:
+            rs.ilu0_destroy(M)
+            rs.ilu0_destroy(M2)
+            rs.bcsr_destroy(A)
+            rs.bcsr_destroy(A2)
+
+
+def test_fresh_handles_on_a_non_blocking_stream():
+    """Every device initialisation (pattern and schedule uploads, workspace
+    clearing) must be ordered before work that the caller queues on its own
+    stream, which need not synchronise with the null stream."""
+    torch = pytest.importorskip("torch")
+    s = CASES["nnc"]
+    ref = {}
+    for ordering in ORDERINGS:
+        with rs.Solver(s.rowptr, s.colidx, s.vals, ordering=ordering) as sol:
+            sol.factor()
+            ref[ordering] = sol.solve(s.b[:, 0], reduction=1e-10)
+    side = torch.cuda.Stream()
+    dev = torch.device("cuda:0")
+    vals = torch.from_numpy(s.vals).to(dev)
+    b = torch.from_numpy(np.ascontiguousarray(s.b[:, 0])).to(dev)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for ordering in ORDERINGS:
+            x = torch.empty_like(b)
+            A = rs.bcsr_create(s.rowptr, s.colidx, stream=side.cuda_stream)
+            M = rs.ilu0_analyse(A, ordering)
+            try:
+                rs.bcsr_set_values(A, vals, stream=side.cuda_stream)
+                rs.ilu0_factor(M, A, stream=side.cuda_stream)
+                _, st, info = rs.bicgstab_solve(M, A, b, x, reduction=1e-10, stream=side.cuda_stream)
+                side.synchronize()
+                xr, str_, ir = ref[ordering]
+                assert st == str_ == rs.OK and info[0]["half_steps"] == ir[0]["half_steps"]
+                assert np.array_equal(x.cpu().numpy(), xr)
+            finally:
+                rs.ilu0_destroy(M)
+                rs.bcsr_destroy(A)
+
+
 def test_device_memory_path():
     torch = pytest.importorskip("torch")
     s = CASES["nnc"]

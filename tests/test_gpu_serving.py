@@ -26,18 +26,27 @@ def requests(n):
     return [SYS[int(k)] for k in rng.integers(0, len(SYS), n)]
 
 
+def register(srv, systems):
+    return {id(s): srv.add_pattern(s.rowptr, s.colidx) for s in systems}
+
+
 def test_results_same_alone_and_in_the_mix():
     reqs = requests(24)
     with rs.Server(max_slots=1, ordering=rs.ORDER_GRAPH_COLOUR) as alone:
+        pid = register(alone, SYS)
         ref = []
         for s in reqs:
-            t = alone.submit(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], reduction=1e-8)
+            t = alone.submit(pid[id(s)], s.vals[0], s.b[0, 0], reduction=1e-8)
             ref.append(alone.wait(t))
     with rs.Server(max_slots=4, ordering=rs.ORDER_GRAPH_COLOUR) as mix:
-        tickets = [mix.submit(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], reduction=1e-8) for s in reqs]
+        pid = register(mix, SYS)
+        tickets = [mix.submit(pid[id(s)], s.vals[0], s.b[0, 0], reduction=1e-8) for s in reqs]
         got = [mix.wait(t) for t in tickets]
         slots = {g[3]["slot"] for g in got}
+        stats = mix.stats()
     assert len(slots) > 1
+    # one analysis per pattern (SYS[0] and SYS[1] share theirs), shared by every instance of it
+    assert stats["analyses"] == 4 and stats["evicted"] == 0
     for (x1, st1, i1, _), (x2, st2, i2, _) in zip(ref, got):
         assert st1 == st2 == rs.OK
         assert np.array_equal(x1, x2) and i1 == i2
@@ -45,7 +54,8 @@ def test_results_same_alone_and_in_the_mix():
 
 def test_results_match_oracle():
     with rs.Server(max_slots=3, ordering=rs.ORDER_LEVEL_SET, precision=rs.PREC_FP64) as srv:
-        tickets = [(s, srv.submit(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], reduction=1e-10)) for s in SYS]
+        pid = register(srv, SYS)
+        tickets = [(s, srv.submit(pid[id(s)], s.vals[0], s.b[0, 0], reduction=1e-10)) for s in SYS]
         for s, t in tickets:
             x, st, info, tm = srv.wait(t)
             xo, _ = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=rs.ORDER_LEVEL_SET,
@@ -57,26 +67,29 @@ def test_results_match_oracle():
 
 def test_budget_is_never_exceeded_and_oversize_is_refused():
     big = SYS[4]
-    need = rs.Server.request_bytes(big.n, big.nnzb)
-    budget = int(need * 1.5)          # room for one resident request of this size
+    need = rs.Server.request_bytes(big.n, big.nnzb) + rs.Server.analysis_bytes(big.n, big.nnzb)
+    budget = int(need * 1.5)          # room for one resident instance of this size
     reqs = requests(12)
     with rs.Server(hbm_budget_bytes=budget, max_slots=4) as srv:
-        tickets = [(s, srv.submit(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], reduction=1e-6)) for s in reqs]
+        pid = register(srv, SYS)
+        tickets = [(s, srv.submit(pid[id(s)], s.vals[0], s.b[0, 0], reduction=1e-6)) for s in reqs]
         for s, t in tickets:
             x, st, info, _ = srv.wait(t)
             assert st == rs.OK and info["true_rel_residual"] <= 1e-6 * (1 + 1e-6)
         stats = srv.stats()
         assert stats["completed"] == len(reqs) and stats["peak_reserved_bytes"] <= budget
+        assert stats["evicted"] > 0 and stats["reserved_bytes"] <= budget
     with rs.Server(hbm_budget_bytes=need - 1, max_slots=2) as srv:
         with pytest.raises(rs.RsolveError) as e:
-            srv.submit(big.rowptr, big.colidx, big.vals[0], big.b[0, 0])
+            srv.add_pattern(big.rowptr, big.colidx)
         assert e.value.status == rs.OUT_OF_MEMORY
 
 
 def test_poll_then_wait_and_ticket_release():
     s = SYS[4]
     with rs.Server(max_slots=1) as srv:
-        ts = [srv.submit(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], reduction=1e-10) for _ in range(4)]
+        p = srv.add_pattern(s.rowptr, s.colidx)
+        ts = [srv.submit(p, s.vals[0], s.b[0, 0], reduction=1e-10) for _ in range(4)]
         early = srv.poll(ts[-1])                # one slot, four requests: usually still queued
         results = [early] if early is not None else []
         for t in (ts[:-1] if early is not None else ts):
@@ -84,3 +97,46 @@ def test_poll_then_wait_and_ticket_release():
         assert all(r[1] == rs.OK for r in results)
         with pytest.raises(rs.RsolveError):     # a collected ticket is released
             srv.wait(ts[0])
+
+
+def test_instances_share_one_analysis_and_match_a_standalone_solver():
+    s = SYS[2]
+    with rs.Solver(s.rowptr, s.colidx, s.vals, ordering=rs.ORDER_GRAPH_COLOUR, precision=rs.PREC_FP32_FACTORS) as ref:
+        ref.factor()
+        xr, str_, ir = ref.solve(s.b[:, 0], reduction=1e-8)
+    with rs.Server(max_slots=4, ordering=rs.ORDER_GRAPH_COLOUR) as srv:
+        p = srv.add_pattern(s.rowptr, s.colidx)
+        assert srv.add_pattern(s.rowptr.copy(), s.colidx.copy()) == p      # same pattern, same id
+        ts = [srv.submit(p, s.vals[0], s.b[0, 0], reduction=1e-8) for _ in range(16)]
+        got = [srv.wait(t) for t in ts]
+        stats = srv.stats()
+    assert stats["analyses"] == 1 and 1 <= stats["created"] <= 4 and stats["evicted"] == 0
+    assert any(g[3]["resident"] for g in got)
+    for x, st, info, _ in got:
+        assert st == str_ == rs.OK
+        assert np.array_equal(x, xr[0]) and info["half_steps"] == ir[0]["half_steps"]
+
+
+def test_autotuned_server_matches_oracle():
+    with rs.Server(max_slots=2, ordering=rs.ORDER_LEVEL_SET, precision=rs.PREC_FP64, autotune=True) as srv:
+        pid = register(srv, SYS)
+        tickets = [(s, srv.submit(pid[id(s)], s.vals[0], s.b[0, 0], reduction=1e-10)) for s in SYS + SYS]
+        for s, t in tickets:
+            x, st, info, tm = srv.wait(t)
+            xo, _ = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=rs.ORDER_LEVEL_SET,
+                                 reduction=1e-10)
+            assert st == rs.OK and np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+
+
+def test_bad_pattern_and_unknown_pattern_are_rejected():
+    s = SYS[0]
+    with rs.Server(max_slots=1) as srv:
+        c = s.colidx.copy()
+        r0, r1 = s.rowptr[0], s.rowptr[1]
+        c[r0:r1] = c[r0:r1][::-1]                       # unsorted first row
+        with pytest.raises(rs.RsolveError) as e:
+            srv.add_pattern(s.rowptr, c)
+        assert e.value.status == rs.BAD_PATTERN and e.value.bad_row == 0
+        with pytest.raises(rs.RsolveError) as e:
+            srv.submit(7, s.vals[0], s.b[0, 0])
+        assert e.value.status == rs.INVALID_ARG
