@@ -75,8 +75,13 @@ def lib():
         L.orc_inv3.argtypes = [_F64P, _F64P]
         L.orc_bicgstab.argtypes = [ci, _I32P, _I32P, _F64P, _F64P, _F64P, ci, _F64P, cd, ci, _F64P,
                                    ct.POINTER(Info), vp]
+        L.orc_bicgstab_split.argtypes = [ci, _I32P, _I32P, _F64P, _I32P, _I32P, _F64P, _F64P, ci, _F64P, cd, ci,
+                                         _F64P, ct.POINTER(Info), vp]
         L.orc_solve.argtypes = [ci, _I32P, _I32P, _F64P, _F64P, ci, ci, cd, ci, _F64P, ct.POINTER(Info),
                                 _I32P, ct.POINTER(ci), ct.POINTER(ci)]
+        L.orc_solve_jacobi.argtypes = [ci, _I32P, _I32P, _F64P, vp, _F64P, ci, ci, cd, ci, _F64P,
+                                       ct.POINTER(Info), _I32P, ct.POINTER(ci), ct.POINTER(ci)]
+        L.orc_jacobi_matrix.argtypes = [ci, _I32P, _I32P, _F64P, _I32P, _I32P, _I32P, _F64P]
         _lib = L
     return _lib
 
@@ -174,27 +179,44 @@ def inv3(a):
     return ok, out
 
 
+def jacobi_matrix(rowptr, colidx, vals, part):
+    """(rowptr', colidx', vals') of the Jacobi matrix: blocks within one partition."""
+    n = len(rowptr) - 1
+    nnz = len(colidx)
+    rrow = np.zeros(n + 1, np.int32)
+    rcol = np.zeros(max(nnz, 1), np.int32)
+    rv = np.zeros((max(nnz, 1), 3, 3), np.float64)
+    k = lib().orc_jacobi_matrix(n, _i32(rowptr), _i32(colidx), _f64(vals), _i32(part), rrow, rcol, rv)
+    return rrow, rcol[:k], rv[:k]
+
+
 def bicgstab(rowptr, colidx, vals, lu, dinv, b, *, precond=PREC_ILU_F64, reduction=1e-2, max_iter=200,
-             trace=False):
-    """BiCGStab on an already ordered system.  Returns (x, info dict[, trace (k, 8)])."""
+             trace=False, mrow=None, mcol=None):
+    """BiCGStab on an already ordered system.  Returns (x, info dict[, trace (k, 8)]).
+
+    The factors lu / dinv live on (mrow, mcol) when given (a Jacobi matrix's
+    pattern), else on the matrix's own pattern."""
     n = len(rowptr) - 1
     x = np.zeros((n, 3), np.float64)
     info = Info()
     tr = np.zeros((max(max_iter, 1), 8), np.float64) if trace else None
-    lu = _f64(lu) if lu is not None else np.zeros((max(len(colidx), 1), 3, 3))
+    mrow = _i32(rowptr if mrow is None else mrow)
+    mcol = _i32(colidx if mcol is None else mcol)
+    lu = _f64(lu) if lu is not None else np.zeros((max(len(mcol), 1), 3, 3))
     dinv = _f64(dinv) if dinv is not None else np.zeros((max(n, 1), 3, 3))
-    lib().orc_bicgstab(n, _i32(rowptr), _i32(colidx), _f64(vals), lu, dinv, precond,
-                       _f64(b).reshape(n, 3), reduction, max_iter, x, ct.byref(info),
-                       tr.ctypes.data if tr is not None else None)
+    lib().orc_bicgstab_split(n, _i32(rowptr), _i32(colidx), _f64(vals), mrow, mcol, lu, dinv, precond,
+                             _f64(b).reshape(n, 3), reduction, max_iter, x, ct.byref(info),
+                             tr.ctypes.data if tr is not None else None)
     if trace:
         return x, info.as_dict(), tr
     return x, info.as_dict()
 
 
 def solve(rowptr, colidx, vals, b, *, ordering=ORDER_NATURAL, precond=PREC_ILU_F64, reduction=1e-2,
-          max_iter=200):
+          max_iter=200, part=None):
     """The whole path on one system in original order.
 
+    ``part`` (n partition ids) selects the Block-Jacobi-ILU0 preconditioner.
     Returns (x[n,3], info dict with status, half_steps, r0_norm, final_norm,
     true_rel_residual, n_sets, bad_row, perm).
     """
@@ -204,8 +226,10 @@ def solve(rowptr, colidx, vals, b, *, ordering=ORDER_NATURAL, precond=PREC_ILU_F
     perm = np.zeros(max(n, 1), np.int32)
     nsets = ct.c_int(0)
     bad = ct.c_int(-1)
-    lib().orc_solve(n, _i32(rowptr), _i32(colidx), _f64(vals), _f64(b).reshape(n, 3), ordering, precond,
-                    reduction, max_iter, x, ct.byref(info), perm, ct.byref(nsets), ct.byref(bad))
+    part = None if part is None else _i32(part)
+    lib().orc_solve_jacobi(n, _i32(rowptr), _i32(colidx), _f64(vals), None if part is None else part.ctypes.data,
+                           _f64(b).reshape(n, 3), ordering, precond, reduction, max_iter, x, ct.byref(info), perm,
+                           ct.byref(nsets), ct.byref(bad))
     d = info.as_dict()
     d.update(n_sets=nsets.value, bad_row=bad.value, perm=perm[:n])
     return x, d

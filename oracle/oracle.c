@@ -35,6 +35,10 @@
  *   - Stopping rule: relative reduction 1e-2 of the residual 2-norm, at
  *     most 200 iterations (Section "Bicgstab solver"), tested after both the
  *     half step (on s) and the full step (on r).
+ *   - Block-Jacobi-ILU0 (Section "Block-Jacobi-ILU0"): the preconditioner is
+ *     built from a "Jacobi matrix" that keeps only the blocks coupling rows
+ *     of the same partition; the full matrix stays in the SpMV.  The ordering
+ *     is computed on the Jacobi matrix's pattern.  The partition is an input.
  *   - Zero-diagonal check (Section "Profiling", runtime breakdown table):
  *     a missing diagonal block is a pattern error; a singular diagonal block
  *     during the decomposition is a zero pivot.
@@ -71,6 +75,13 @@ typedef struct {
     double final_norm;
     double true_rel_residual;
 } orc_info;
+
+int orc_bicgstab_split(int n, const int *rowptr, const int *colidx, const double *vals, const int *mrow,
+                       const int *mcol, const double *lu, const double *dinv, int precond_kind, const double *b,
+                       double reduction, int max_iter, double *x, orc_info *info, double *trace);
+int orc_solve_jacobi(int n, const int *rowptr, const int *colidx, const double *vals, const int *part,
+                     const double *b, int ordering, int precond_kind, double reduction, int max_iter, double *x,
+                     orc_info *info, int *perm_out, int *n_sets, int *bad_row);
 
 /* ---------------------------------------------------------------- pattern */
 
@@ -391,6 +402,29 @@ void orc_spmv(int n, const int *rowptr, const int *colidx, const double *vals, c
     }
 }
 
+/* ----------------------------------------------------------- Block-Jacobi */
+
+/* The Jacobi matrix of Section "Block-Jacobi-ILU0": the blocks (i, j) of A
+ * with part[i] == part[j] (diagonal blocks always qualify), in A's order.
+ * rrow (n + 1), rcol and rvals (room for rowptr[n] blocks).  Returns the
+ * number of blocks kept. */
+int orc_jacobi_matrix(int n, const int *rowptr, const int *colidx, const double *vals, const int *part,
+                      int *rrow, int *rcol, double *rvals)
+{
+    int k = 0;
+    rrow[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            if (part[colidx[p]] != part[i]) continue;
+            rcol[k] = colidx[p];
+            memcpy(rvals + 9 * (size_t)k, vals + 9 * (size_t)p, 9 * sizeof(double));
+            ++k;
+        }
+        rrow[i + 1] = k;
+    }
+    return k;
+}
+
 static double dot(int m, const double *a, const double *b)
 {
     double s = 0.0;
@@ -513,10 +547,20 @@ int orc_bicgstab(int n, const int *rowptr, const int *colidx, const double *vals
                  const double *dinv, int precond_kind, const double *b, double reduction, int max_iter,
                  double *x, orc_info *info, double *trace)
 {
-    precond m = {precond_kind, n, rowptr, colidx, lu, dinv, NULL, NULL};
+    return orc_bicgstab_split(n, rowptr, colidx, vals, rowptr, colidx, lu, dinv, precond_kind, b, reduction,
+                              max_iter, x, info, trace);
+}
+
+/* As orc_bicgstab, with factors on their own pattern (mrow, mcol): the
+ * preconditioner of a Jacobi matrix while the SpMV uses the full matrix. */
+int orc_bicgstab_split(int n, const int *rowptr, const int *colidx, const double *vals, const int *mrow,
+                       const int *mcol, const double *lu, const double *dinv, int precond_kind, const double *b,
+                       double reduction, int max_iter, double *x, orc_info *info, double *trace)
+{
+    precond m = {precond_kind, n, mrow, mcol, lu, dinv, NULL, NULL};
     float *lu32 = NULL, *dinv32 = NULL;
     if (precond_kind == ORC_PREC_ILU_F32) {
-        size_t nnz = (size_t)rowptr[n];
+        size_t nnz = (size_t)mrow[n];
         lu32 = malloc(sizeof(float) * 9 * (nnz > 0 ? nnz : 1));
         dinv32 = malloc(sizeof(float) * 9 * (size_t)(n > 0 ? n : 1));
         for (size_t e = 0; e < 9 * nnz; ++e) lu32[e] = (float)lu[e];
@@ -540,6 +584,17 @@ int orc_solve(int n, const int *rowptr, const int *colidx, const double *vals, c
               int ordering, int precond_kind, double reduction, int max_iter, double *x,
               orc_info *info, int *perm_out, int *n_sets, int *bad_row)
 {
+    return orc_solve_jacobi(n, rowptr, colidx, vals, NULL, b, ordering, precond_kind, reduction, max_iter, x,
+                            info, perm_out, n_sets, bad_row);
+}
+
+/* As orc_solve, with the Block-Jacobi-ILU0 preconditioner when part (n
+ * partition ids) is given: ordering and ILU0 on the Jacobi matrix, SpMV and
+ * true residual with the full matrix.  part == NULL is plain ILU0. */
+int orc_solve_jacobi(int n, const int *rowptr, const int *colidx, const double *vals, const int *part,
+                     const double *b, int ordering, int precond_kind, double reduction, int max_iter, double *x,
+                     orc_info *info, int *perm_out, int *n_sets, int *bad_row)
+{
     int st = orc_validate(n, rowptr, colidx, bad_row);
     memset(info, 0, sizeof *info);
     info->status = st;
@@ -553,17 +608,28 @@ int orc_solve(int n, const int *rowptr, const int *colidx, const double *vals, c
     double *dinv = malloc(sizeof(double) * 9 * nn);
     double *pb = malloc(sizeof(double) * 3 * nn), *px = malloc(sizeof(double) * 3 * nn);
     double *ax = malloc(sizeof(double) * 3 * nn);
+    /* the preconditioner's matrix: A itself, or its Jacobi matrix */
+    int *jrow = malloc(sizeof(int) * (nn + 1)), *jcol = malloc(sizeof(int) * (nnz > 0 ? nnz : 1));
+    double *jvals = malloc(sizeof(double) * 9 * (nnz > 0 ? nnz : 1));
+    int *mrow = malloc(sizeof(int) * (nn + 1)), *mcol = malloc(sizeof(int) * (nnz > 0 ? nnz : 1));
+    if (part) {
+        orc_jacobi_matrix(n, rowptr, colidx, vals, part, jrow, jcol, jvals);
+    } else {
+        memcpy(jrow, rowptr, sizeof(int) * (nn + 1));
+        memcpy(jcol, colidx, sizeof(int) * nnz);
+        memcpy(jvals, vals, sizeof(double) * 9 * nnz);
+    }
     int sets = n;
-    if (ordering == ORC_ORDER_LEVEL) sets = orc_level_sets(n, rowptr, colidx, key, perm);
-    else if (ordering == ORC_ORDER_COLOUR) sets = orc_greedy_colour(n, rowptr, colidx, key, perm);
+    if (ordering == ORC_ORDER_LEVEL) sets = orc_level_sets(n, jrow, jcol, key, perm);
+    else if (ordering == ORC_ORDER_COLOUR) sets = orc_greedy_colour(n, jrow, jcol, key, perm);
     else for (int i = 0; i < n; ++i) perm[i] = i;
     if (n_sets) *n_sets = sets;
     if (perm_out) memcpy(perm_out, perm, sizeof(int) * (size_t)n);
     orc_permute(n, rowptr, colidx, vals, perm, prow, pcol, pvals);
-    memcpy(lu, pvals, sizeof(double) * 9 * nnz);
+    orc_permute(n, jrow, jcol, jvals, perm, mrow, mcol, lu);
     if (precond_kind != ORC_PREC_NONE) {
         int brow;
-        st = orc_ilu0(n, prow, pcol, lu, dinv, &brow);
+        st = orc_ilu0(n, mrow, mcol, lu, dinv, &brow);
         if (st != ORC_OK) {
             *bad_row = brow >= 0 ? perm[brow] : -1;
             info->status = st;
@@ -572,7 +638,8 @@ int orc_solve(int n, const int *rowptr, const int *colidx, const double *vals, c
     }
     for (int i = 0; i < n; ++i)
         for (int c = 0; c < 3; ++c) pb[3 * i + c] = b[3 * (size_t)perm[i] + c];
-    st = orc_bicgstab(n, prow, pcol, pvals, lu, dinv, precond_kind, pb, reduction, max_iter, px, info, NULL);
+    st = orc_bicgstab_split(n, prow, pcol, pvals, mrow, mcol, lu, dinv, precond_kind, pb, reduction, max_iter, px,
+                            info, NULL);
     for (int i = 0; i < n; ++i)
         for (int c = 0; c < 3; ++c) x[3 * (size_t)perm[i] + c] = px[3 * i + c];
     orc_spmv(n, rowptr, colidx, vals, x, ax);
@@ -587,6 +654,6 @@ int orc_solve(int n, const int *rowptr, const int *colidx, const double *vals, c
     }
 out:
     free(key); free(perm); free(prow); free(pcol); free(pvals); free(lu); free(dinv);
-    free(pb); free(px); free(ax);
+    free(pb); free(px); free(ax); free(jrow); free(jcol); free(jvals); free(mrow); free(mcol);
     return st;
 }

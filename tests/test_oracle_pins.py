@@ -378,3 +378,107 @@ def test_stopping_and_fault_statuses():
             vz[p] = 0.0   # no update reaches the zeroed diagonal
     _, info = oracle.solve(s.rowptr, s.colidx, vz, b)
     assert info["status"] == oracle.ZERO_PIVOT and info["bad_row"] == row
+
+
+# ------------------------------------------------------------ Block-Jacobi
+
+def slab_partition(n, parts):
+    """Contiguous row ranges of near-equal size (z-slabs of a grid numbered i, j, k)."""
+    return (np.arange(n, dtype=np.int64) * parts // max(n, 1)).astype(np.int32)
+
+
+def test_jacobi_matrix_keeps_exactly_the_blocks_inside_partitions():
+    s = make_grid_system(6, 5, 4, nnc_frac=0.05, seed=31)
+    part = np.random.default_rng(3).integers(0, 3, s.n).astype(np.int32)
+    rrow, rcol, rv = oracle.jacobi_matrix(s.rowptr, s.colidx, s.vals[0], part)
+    kept = []
+    for i in range(s.n):                      # brute force over every stored block
+        for p in range(s.rowptr[i], s.rowptr[i + 1]):
+            if part[i] == part[s.colidx[p]]:
+                kept.append((i, s.colidx[p], p))
+    got = [(i, rcol[q]) for i in range(s.n) for q in range(rrow[i], rrow[i + 1])]
+    assert got == [(i, j) for i, j, _ in kept]
+    assert np.array_equal(rv, s.vals[0][[p for _, _, p in kept]])
+
+
+def test_jacobi_with_one_partition_is_plain_ilu0():
+    s = make_grid_system(8, 6, 5, nnc_frac=0.03, seed=32)
+    for ordering in (oracle.ORDER_NATURAL, oracle.ORDER_LEVEL, oracle.ORDER_COLOUR):
+        x1, i1 = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=ordering, reduction=1e-10)
+        x2, i2 = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=ordering, reduction=1e-10,
+                              part=np.zeros(s.n, np.int32))
+        assert np.array_equal(x1, x2) and i1["half_steps"] == i2["half_steps"]
+
+
+def test_jacobi_on_uncoupled_partitions_is_plain_ilu0():
+    """A matrix with no blocks between partitions loses nothing to the Jacobi matrix."""
+    a = make_grid_system(6, 5, 4, seed=33)
+    b = make_grid_system(5, 4, 3, nnc_frac=0.05, seed=34)
+    rowptr = np.concatenate([a.rowptr, b.rowptr[1:] + a.rowptr[-1]]).astype(np.int32)
+    colidx = np.concatenate([a.colidx, b.colidx + a.n]).astype(np.int32)
+    vals = np.concatenate([a.vals[0], b.vals[0]])
+    rhs = np.concatenate([a.b[0, 0], b.b[0, 0]])
+    part = np.concatenate([np.zeros(a.n), np.ones(b.n)]).astype(np.int32)
+    for ordering in (oracle.ORDER_LEVEL, oracle.ORDER_COLOUR):
+        x1, i1 = oracle.solve(rowptr, colidx, vals, rhs, ordering=ordering, reduction=1e-10)
+        x2, i2 = oracle.solve(rowptr, colidx, vals, rhs, ordering=ordering, reduction=1e-10, part=part)
+        assert np.array_equal(x1, x2) and i1["half_steps"] == i2["half_steps"]
+
+
+def test_jacobi_factors_split_into_independent_partitions():
+    """ILU0 of the Jacobi matrix restricted to one partition equals ILU0 of
+    that partition's diagonal sub-matrix factored on its own."""
+    s = make_grid_system(7, 6, 5, nnc_frac=0.04, seed=35)
+    part = slab_partition(s.n, 3)
+    rrow, rcol, rv = oracle.jacobi_matrix(s.rowptr, s.colidx, s.vals[0], part)
+    st, _, lu, dinv = oracle.ilu0(rrow, rcol, rv)
+    assert st == oracle.OK
+    for q in range(3):
+        rows = np.flatnonzero(part == q)
+        local = {int(r): k for k, r in enumerate(rows)}
+        sp, sc, sv, pos = [0], [], [], []
+        for r in rows:                               # the sub-matrix A[P, P], built here from A
+            for p in range(s.rowptr[r], s.rowptr[r + 1]):
+                if int(s.colidx[p]) in local:
+                    sc.append(local[int(s.colidx[p])])
+                    sv.append(s.vals[0][p])
+            sp.append(len(sc))
+        for r in rows:                               # the same blocks' positions in the Jacobi matrix
+            pos.extend(range(rrow[r], rrow[r + 1]))
+        st2, _, lu2, dinv2 = oracle.ilu0(np.asarray(sp, np.int32), np.asarray(sc, np.int32), np.asarray(sv))
+        assert st2 == oracle.OK
+        assert np.array_equal(lu[pos], lu2) and np.array_equal(dinv[rows], dinv2)
+
+
+def test_jacobi_one_row_per_partition_is_block_diagonal():
+    s = make_grid_system(6, 5, 4, seed=36)
+    part = np.arange(s.n, dtype=np.int32)
+    rrow, rcol, rv = oracle.jacobi_matrix(s.rowptr, s.colidx, s.vals[0], part)
+    assert np.array_equal(rcol, np.arange(s.n)) and np.array_equal(rrow, np.arange(s.n + 1))
+    st, _, lu, dinv = oracle.ilu0(rrow, rcol, rv)
+    diag = np.array([s.vals[0][p] for i in range(s.n) for p in range(s.rowptr[i], s.rowptr[i + 1])
+                     if s.colidx[p] == i])
+    assert np.allclose(dinv, np.linalg.inv(diag), rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("parts", [2, 5, 17])
+def test_jacobi_solve_converges_to_the_full_system(parts):
+    """The SpMV keeps the full matrix: the solution is that of A, not of the Jacobi matrix."""
+    s = make_grid_system(10, 8, 6, nnc_frac=0.03, seed=37)
+    A = to_dense(s.rowptr, s.colidx, s.vals[0])
+    b = s.b[0, 0]
+    xr = np.linalg.solve(A, b.ravel())
+    part = slab_partition(s.n, parts)
+    for ordering in (oracle.ORDER_LEVEL, oracle.ORDER_COLOUR):
+        x, info = oracle.solve(s.rowptr, s.colidx, s.vals[0], b, ordering=ordering, reduction=1e-12, part=part)
+        assert info["status"] == oracle.OK and info["true_rel_residual"] <= 1e-11
+        assert np.linalg.norm(x.ravel() - xr) / np.linalg.norm(xr) < 1e-9
+
+
+def test_jacobi_levels_shrink_with_slabs():
+    """Cutting a grid into z-slabs leaves the level count of the thickest slab."""
+    nx, ny, nz = 7, 6, 12
+    s = make_grid_system(nx, ny, nz, seed=38)
+    part = (np.arange(s.n) // (nx * ny * 3)).astype(np.int32)       # 4 slabs of 3 layers
+    _, info = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=oracle.ORDER_LEVEL, part=part)
+    assert info["n_sets"] == nx + ny + 3 - 2
