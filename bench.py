@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--precision", default=None, choices=sorted(PREC))
     ap.add_argument("--reduction", type=float, default=None)
     ap.add_argument("--roofline", default="spmv", choices=sorted(CLASS))
+    ap.add_argument("--jacobi", type=int, default=0, metavar="P",
+                    help="Block-Jacobi-ILU0 with P transmissibility-weighted partitions (0: plain ILU0)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-configuration autotuner")
@@ -100,7 +102,7 @@ def measured_traffic(workload, cls):
     return ent.get("bytes_per_unit")
 
 
-def cpu_baseline(s, rhs, ordering, precision, reduction, budget_s):
+def cpu_baseline(s, rhs, ordering, precision, reduction, budget_s, part=None):
     """The oracle as it stands, single-threaded, on whole steps of the same workload."""
     import numpy as np
 
@@ -110,12 +112,19 @@ def cpu_baseline(s, rhs, ordering, precision, reduction, budget_s):
     steps = solves = 0
     while True:
         for sysk in range(s.batch):
-            perm = oracle.ordering_perm(s.rowptr, s.colidx, ordering)
-            prow, pcol, pv = oracle.permute(s.rowptr, s.colidx, s.vals[sysk], perm)
-            st, _, lu, dinv = oracle.ilu0(prow, pcol, pv)
+            if part is None:
+                perm = oracle.ordering_perm(s.rowptr, s.colidx, ordering)
+                prow, pcol, pv = oracle.permute(s.rowptr, s.colidx, s.vals[sysk], perm)
+                mrow, mcol, mv = prow, pcol, pv
+            else:        # Block-Jacobi: ordering and ILU0 on the Jacobi matrix
+                jrow, jcol, jv = oracle.jacobi_matrix(s.rowptr, s.colidx, s.vals[sysk], part)
+                perm = oracle.ordering_perm(jrow, jcol, ordering)
+                prow, pcol, pv = oracle.permute(s.rowptr, s.colidx, s.vals[sysk], perm)
+                mrow, mcol, mv = oracle.permute(jrow, jcol, jv, perm)
+            st, _, lu, dinv = oracle.ilu0(mrow, mcol, mv)
             for j in range(rhs):
                 x, info = oracle.bicgstab(prow, pcol, pv, lu, dinv, s.b[sysk, j][perm], precond=prec,
-                                          reduction=reduction)
+                                          reduction=reduction, mrow=mrow, mcol=mcol)
                 xo = np.empty_like(x)
                 xo[perm] = x
                 solves += 1
@@ -164,7 +173,12 @@ def main():
     b = torch.from_numpy(np.ascontiguousarray(s.b.transpose(1, 0, 2, 3))).to(dev)  # (rhs, batch, n, 3)
     x = torch.zeros_like(b)
     A = rs.bcsr_create(rowptr, colidx, vals)
-    M = rs.ilu0_analyse(A, ordering)
+    part = None
+    if args.jacobi > 0:
+        part = rs.bcsr_partition(s.rowptr, s.colidx, args.jacobi, weights=s.trans)
+        M = rs.ilu0_analyse_jacobi(A, ordering, part)
+    else:
+        M = rs.ilu0_analyse(A, ordering)
     nl, nu = rs.ilu0_get_sweep_levels(M)
     _, n_sets, _ = rs.ilu0_get_schedule(M, s.n)
     log(f"ordering {args.ordering}: {n_sets} sets, sweep levels lower {nl} upper {nu}")
@@ -222,7 +236,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        v, nsol, dt = cpu_baseline(s, rhs, ordering, precision, reduction, args.cpu_seconds)
+        v, nsol, dt = cpu_baseline(s, rhs, ordering, precision, reduction, args.cpu_seconds, part)
         cpu = {"value": v, "unit": "solves/s", "cores": 1, "kind": "oracle",
                "sample": f"{nsol} solves of the same workload (ordering, reordered copy, ILU0 per step, "
                          f"then BiCGStab per right-hand side) in {dt:.1f}s, single-threaded C oracle"}
@@ -245,6 +259,7 @@ def main():
         "config": {"workload": f"{args.workload}: {wl['desc']}", "ordering": args.ordering, "precision": precision,
                    "reduction": reduction, "max_iter": 200, "n_brows": s.n, "nnzb": s.nnzb, "batch": s.batch,
                    "rhs_per_step": rhs, "sets": n_sets, "sweep_levels": [nl, nu],
+                   "jacobi_partitions": args.jacobi or None,
                    "mean_half_steps": float(np.mean(half_steps)), "max_true_rel_residual": float(max(true_res)),
                    "launch_config": tune},
         "roofline": roofline,

@@ -147,6 +147,28 @@ int bcsr_destroy(bcsr_t A);
  * the implementation chapter. */
 int ilu0_analyse(bcsr_t A, int32_t ordering, ilu0_t *out);
 
+/* ilu0_analyse_jacobi -- as ilu0_analyse for the Block-Jacobi-ILU0
+ * preconditioner of Section "Block-Jacobi-ILU0": part (host, n_brows ints)
+ * assigns every row a partition id; the ordering, sweep schedules and ILU0
+ * use only the blocks joining rows of one partition (the Jacobi matrix),
+ * while the SpMV and the true residual keep all of A.  The Jacobi matrix's
+ * blocks are gathered from A at every ilu0_factor (the paper's copy
+ * indexes), so values change freely between factorisations.
+ * Errors: RS_INVALID_ARG (part NULL), RS_OUT_OF_MEMORY, RS_HIP_ERROR. */
+int ilu0_analyse_jacobi(bcsr_t A, int32_t ordering, const int32_t *part, ilu0_t *out);
+
+/* bcsr_partition -- host-only partitioner for ilu0_analyse_jacobi: n_parts
+ * partitions of near-equal size (sizes differ by at most one), each grown
+ * from the first unassigned row in natural order by repeatedly taking the
+ * unassigned row most strongly coupled to it.  Coupling = sum of |weights|
+ * (host, one per stored block, e.g. transmissibilities; NULL: all 1) of the
+ * blocks joining the row to the partition, so strongly coupled cells stay
+ * together (the paper partitions by transmissibility).  part: host output,
+ * n_brows ints in [0, n_parts).  Errors: RS_INVALID_ARG, RS_BAD_PATTERN,
+ * RS_MISSING_DIAGONAL. */
+int bcsr_partition(int32_t n_brows, int32_t nnzb, const int32_t *row_ptr, const int32_t *col_idx,
+                   const double *weights, int32_t n_parts, int32_t *part);
+
 /* ilu0_analyse_shared -- a further preconditioner handle for A, whose
  * pattern must equal the one `like` was analysed for (RS_PATTERN_MISMATCH
  * otherwise): it shares like's analysis (ordering, schedules, their device
@@ -205,9 +227,10 @@ int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *ba
 
 /* ilu0_get_factors -- copy system `sys`'s factors to host, in the reordered
  * pattern (rows in new order, columns renumbered and ascending, as P A P^T):
- * lu (nnzb * 9 doubles) holds L below the diagonal and U on and above it;
- * dinv (n_brows * 9) holds inv(U_ii) in new row order.  FP32 factors are
- * returned widened.  Synchronous (waits for the whole device). */
+ * lu (nnzb * 9 doubles) holds L below the diagonal and U above it, zero
+ * elsewhere (the diagonal, and blocks outside a Jacobi matrix); dinv
+ * (n_brows * 9) holds inv(U_ii) in new row order.  FP32 factors are returned
+ * widened.  Synchronous (waits for the whole device). */
 int ilu0_get_factors(ilu0_t M, int32_t sys, double *lu, double *dinv);
 
 /* ilu0_apply -- z = U^{-1} L^{-1} v for systems [first_sys, first_sys +

@@ -33,7 +33,7 @@ EXPORTS = (
     "ilu0_get_schedule", "ilu0_get_sweep_levels", "ilu0_set_option", "ilu0_get_option", "ilu0_autotune",
     "ilu0_factor", "ilu0_get_factors", "ilu0_apply",
     "bicgstab_solve", "ilu0_destroy", "ilu0_analyse_host", "rsolve_profile_enable", "rsolve_profile_get",
-    "ilu0_analyse_shared", "server_create", "server_request_bytes", "server_analysis_bytes", "server_add_pattern",
+    "ilu0_analyse_shared", "ilu0_analyse_jacobi", "bcsr_partition", "server_create", "server_request_bytes", "server_analysis_bytes", "server_add_pattern",
     "server_submit", "server_poll", "server_wait", "server_get_stats",
     "server_destroy", "rsolve_status_string", "rsolve_last_error",
 )
@@ -114,6 +114,8 @@ def lib():
         L.bcsr_set_option.argtypes = [vp, i32, i32]
         L.ilu0_analyse.argtypes = [vp, i32, P(vp)]
         L.ilu0_analyse_shared.argtypes = [vp, vp, P(vp)]
+        L.ilu0_analyse_jacobi.argtypes = [vp, i32, vp, P(vp)]
+        L.bcsr_partition.argtypes = [i32, i32, vp, vp, vp, i32, vp]
         L.ilu0_get_schedule.argtypes = [vp, vp, P(i32), vp]
         L.ilu0_get_sweep_levels.argtypes = [vp, P(i32), P(i32)]
         L.ilu0_set_option.argtypes = [vp, i32, i32]
@@ -265,6 +267,31 @@ def ilu0_analyse(A, ordering=ORDER_LEVEL_SET):
     return h
 
 
+def ilu0_analyse_jacobi(A, ordering, part):
+    """Block-Jacobi-ILU0 analysis: ``part`` gives every row a partition id."""
+    n, _, _ = bcsr_get_dims(A)
+    part = _host(part, np.int32)
+    if part.shape != (n,):
+        raise ValueError("part must hold one partition id per block row")
+    h = ct.c_void_p()
+    _check(lib().ilu0_analyse_jacobi(A, ordering, part.ctypes.data, ct.byref(h)), "ilu0_analyse_jacobi")
+    return h
+
+
+def bcsr_partition(rowptr, colidx, n_parts, weights=None):
+    """Coupling-weighted partition of the rows into n_parts near-equal parts (host only)."""
+    rowptr, colidx = _host(rowptr, np.int32), _host(colidx, np.int32)
+    n = len(rowptr) - 1
+    part = np.zeros(max(n, 1), np.int32)
+    w = None if weights is None else _host(weights, np.float64)
+    if w is not None and w.shape != (len(colidx),):
+        raise ValueError("weights must hold one value per stored block")
+    _check(lib().bcsr_partition(n, len(colidx), rowptr.ctypes.data, colidx.ctypes.data,
+                                None if w is None else w.ctypes.data, int(n_parts), part.ctypes.data),
+           "bcsr_partition")
+    return part[:n]
+
+
 def ilu0_analyse_shared(A, like):
     """A further preconditioner for A sharing the analysis of ``like`` (same pattern)."""
     h = ct.c_void_p()
@@ -380,10 +407,11 @@ def rsolve_profile_get(cls):
 class Solver:
     """Owns a matrix handle and its ILU0 handle: create -> analyse -> factor -> solve."""
 
-    def __init__(self, rowptr, colidx, vals, *, ordering=ORDER_LEVEL_SET, precision=PREC_FP64, stream=None):
+    def __init__(self, rowptr, colidx, vals, *, ordering=ORDER_LEVEL_SET, precision=PREC_FP64, stream=None,
+                 part=None):
         self.A = bcsr_create(rowptr, colidx, vals, stream=stream)
         self.n, self.nnzb, self.batch = bcsr_get_dims(self.A)
-        self.M = ilu0_analyse(self.A, ordering)
+        self.M = ilu0_analyse(self.A, ordering) if part is None else ilu0_analyse_jacobi(self.A, ordering, part)
         self.precision = precision
         self.stream = stream
 

@@ -10,6 +10,9 @@
 #include "analysis.h"
 
 #include <algorithm>
+#include <cmath>
+#include <queue>
+#include <utility>
 
 #include "../../include/rsolve.h"
 
@@ -147,12 +150,25 @@ static void make_tiles(int n, int nlev, const std::vector<int32_t> &lev_ptr, int
 }
 
 int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx, int ordering, Schedule &s,
-                   int tile_rows) {
+                   int tile_rows, const int32_t *part) {
     s = Schedule();
     s.n = n;
     s.nnzb = nnzb;
     s.ordering = ordering;
-    s.n_sets = make_ordering(n, rowptr, colidx, ordering, s.perm, s.set_ptr);
+    s.jacobi = part != nullptr;
+    // the preconditioner's matrix: A, or its Jacobi matrix
+    std::vector<int32_t> jrow, jcol;
+    if (part) {
+        jrow.assign(n + 1, 0);
+        for (int i = 0; i < n; ++i) {
+            for (int p = rowptr[i]; p < rowptr[i + 1]; ++p)
+                if (part[colidx[p]] == part[i]) jcol.push_back(colidx[p]);
+            jrow[i + 1] = (int32_t)jcol.size();
+        }
+        s.n_sets = make_ordering(n, jrow.data(), jcol.data(), ordering, s.perm, s.set_ptr);
+    } else {
+        s.n_sets = make_ordering(n, rowptr, colidx, ordering, s.perm, s.set_ptr);
+    }
     s.iperm.assign(n, 0);
     for (int i = 0; i < n; ++i) s.iperm[s.perm[i]] = i;
 
@@ -173,30 +189,50 @@ int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx
         }
         s.prow[i + 1] = base + (int)row.size();
     }
-    const int32_t *prow = s.prow.data(), *pcol = s.pcol.data();
 
-    // sweep schedules on the reordered pattern
+    // the preconditioner's reordered pattern (mrow, mcol) with mmap[q] = its
+    // position in A'
+    std::vector<int32_t> mrow_v, mcol_v, mmap_v;
+    const int32_t *mrow = s.prow.data(), *mcol = s.pcol.data();
+    if (part) {
+        mrow_v.assign(n + 1, 0);
+        for (int i = 0; i < n; ++i) {
+            for (int p = s.prow[i]; p < s.prow[i + 1]; ++p)
+                if (part[s.perm[s.pcol[p]]] == part[s.perm[i]]) {
+                    mcol_v.push_back(s.pcol[p]);
+                    mmap_v.push_back(p);
+                }
+            mrow_v[i + 1] = (int32_t)mcol_v.size();
+        }
+        mrow = mrow_v.data();
+        mcol = mcol_v.data();
+    }
+    const int nnz_m = mrow[n];
+    s.nnz_m = nnz_m;
+    auto apos = [&](int q) { return part ? mmap_v[q] : q; };
+
+    // sweep schedules on the preconditioner's pattern
     std::vector<int32_t> ldep, udep;
-    s.nl_levels = depth_lower(n, prow, pcol, ldep);
-    s.nu_levels = depth_upper(n, prow, pcol, udep);
+    s.nl_levels = depth_lower(n, mrow, mcol, ldep);
+    s.nu_levels = depth_upper(n, mrow, mcol, udep);
     group_by_key(ldep, s.nl_levels, s.lrows, s.lset);
     group_by_key(udep, s.nu_levels, s.urows, s.uset);
     std::vector<int32_t> upos(n);
     for (int q = 0; q < n; ++q) upos[s.urows[q]] = q;
 
-    std::vector<int32_t> a2l(nnzb, -1), a2u(nnzb, -1), pdiag(n, -1);
+    std::vector<int32_t> a2l(std::max(nnz_m, 1), -1), a2u(std::max(nnz_m, 1), -1), pdiag(n, -1);
     s.lptr.assign(n + 1, 0);
     s.l2u.resize(n);
     for (int q = 0; q < n; ++q) {
         const int i = s.lrows[q];
         int cnt = 0;
-        for (int p = prow[i]; p < prow[i + 1]; ++p) {
-            if (pcol[p] == i) pdiag[i] = p;
-            if (pcol[p] >= i) continue;
+        for (int p = mrow[i]; p < mrow[i + 1]; ++p) {
+            if (mcol[p] == i) pdiag[i] = apos(p);
+            if (mcol[p] >= i) continue;
             a2l[p] = (int)s.lcol.size();
-            s.lcol.push_back(pcol[p]);
-            s.lsrc.push_back(p);
-            s.ldq.push_back(upos[pcol[p]]);
+            s.lcol.push_back(mcol[p]);
+            s.lsrc.push_back(apos(p));
+            s.ldq.push_back(upos[mcol[p]]);
             ++cnt;
         }
         s.lptr[q + 1] = s.lptr[q] + cnt;
@@ -208,11 +244,11 @@ int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx
     for (int q = 0; q < n; ++q) {
         const int i = s.urows[q];
         int cnt = 0;
-        for (int p = prow[i]; p < prow[i + 1]; ++p) {
-            if (pcol[p] <= i) continue;
+        for (int p = mrow[i]; p < mrow[i + 1]; ++p) {
+            if (mcol[p] <= i) continue;
             a2u[p] = (int)s.ucol.size();
-            s.ucol.push_back(pcol[p]);
-            s.usrc.push_back(p);
+            s.ucol.push_back(mcol[p]);
+            s.usrc.push_back(apos(p));
             ++cnt;
         }
         s.uptr[q + 1] = s.uptr[q] + cnt;
@@ -229,13 +265,13 @@ int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx
         const int i = s.lrows[q];
         for (int e = s.lptr[q]; e < s.lptr[q + 1]; ++e) {
             const int k = s.lcol[e];
-            const int32_t *ib = pcol + prow[i], *ie = pcol + prow[i + 1];
-            for (int p = prow[k]; p < prow[k + 1]; ++p) {
-                const int j = pcol[p];
+            const int32_t *ib = mcol + mrow[i], *ie = mcol + mrow[i + 1];
+            for (int p = mrow[k]; p < mrow[k + 1]; ++p) {
+                const int j = mcol[p];
                 if (j <= k) continue;
                 const int32_t *hit = std::lower_bound(ib, ie, j);
                 if (hit == ie || *hit != j) continue;  // fill outside the pattern is dropped
-                const int t = prow[i] + (int)(hit - ib);
+                const int t = mrow[i] + (int)(hit - ib);
                 int code;
                 if (j < i) code = 4 * a2l[t] + 0;
                 else if (j == i) code = 1;
@@ -252,6 +288,50 @@ int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx
     make_tiles(n, s.nl_levels, s.lset, tile_rows, s.lptr, s.lcol, lpos, s.ltiles);
     make_tiles(n, s.nu_levels, s.uset, tile_rows, s.uptr, s.ucol, upos, s.utiles);
     return RS_OK;
+}
+
+void partition_rows(int n, const int32_t *rowptr, const int32_t *colidx, const double *weights, int n_parts,
+                    int32_t *part) {
+    if (n <= 0) return;
+    n_parts = std::max(1, std::min(n_parts, n));
+    std::fill(part, part + n, -1);
+    std::vector<double> gain(n, 0.0);       // coupling of an unassigned row to the growing partition
+    std::vector<int32_t> touched;
+    std::priority_queue<std::pair<double, int32_t>> heap;   // (coupling, -row): strongest, then lowest row
+    int cursor = 0;
+    for (int q = 0; q < n_parts; ++q) {
+        const int target = (int)((int64_t)n * (q + 1) / n_parts - (int64_t)n * q / n_parts);
+        heap = {};
+        for (int j : touched) gain[j] = 0.0;
+        touched.clear();
+        int size = 0;
+        auto take = [&](int r) {
+            part[r] = q;
+            ++size;
+            for (int p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+                const int j = colidx[p];
+                if (part[j] >= 0) continue;
+                if (gain[j] == 0.0) touched.push_back(j);
+                gain[j] += weights ? std::fabs(weights[p]) + 1e-300 : 1.0;
+                heap.emplace(gain[j], -j);
+            }
+        };
+        while (size < target) {
+            if (heap.empty()) {              // no unassigned neighbour: jump to the next free row
+                while (cursor < n && part[cursor] >= 0) ++cursor;
+                if (cursor >= n) break;
+                take(cursor);
+                continue;
+            }
+            const auto top = heap.top();
+            heap.pop();
+            const int r = -top.second;
+            if (part[r] >= 0 || top.first != gain[r]) continue;   // taken, or a stale entry
+            take(r);
+        }
+    }
+    for (int j = 0; j < n; ++j)
+        if (part[j] < 0) part[j] = n_parts - 1;
 }
 
 }  // namespace rs

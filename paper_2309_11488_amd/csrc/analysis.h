@@ -27,8 +27,15 @@ int make_ordering(int n, const int32_t *rowptr, const int32_t *colidx, int order
 // "U-schedule" order (upper levels ascending).  L blocks are stored in
 // L-schedule order, U blocks and inv(U_ii) in U-schedule order, so each level
 // is one contiguous range of rows and blocks.
+//
+// With a partition (Block-Jacobi-ILU0) the orderings, sweep schedules and
+// update lists are those of the Jacobi matrix (blocks whose two rows share a
+// partition); A' stays the full matrix, and lsrc / usrc / dsrc still point
+// into it.
 struct Schedule {
     int n = 0, nnzb = 0, ordering = 0;
+    bool jacobi = false;
+    int nnz_m = 0;                  // blocks of the preconditioner's matrix
     int n_sets = 0;                 // levels / colours reported to the caller
     std::vector<int32_t> set_ptr;   // n_sets + 1
     std::vector<int32_t> perm, iperm;
@@ -56,7 +63,16 @@ struct Schedule {
 };
 
 // tile_rows: rows per sweep tile (a multiple of the rows one workgroup covers).
+// part: optional partition id per row (Block-Jacobi-ILU0), else plain ILU0.
 int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx, int ordering, Schedule &s,
-                   int tile_rows);
+                   int tile_rows, const int32_t *part = nullptr);
+
+// Grow n_parts partitions of near-equal size (sizes differ by at most one):
+// each starts from the first unassigned row in natural order and repeatedly
+// takes the unassigned row most strongly coupled to it (sum of `weights` of
+// the stored blocks joining them; all weights 1 when NULL), jumping to the
+// next unassigned row when it has no unassigned neighbour left.
+void partition_rows(int n, const int32_t *rowptr, const int32_t *colidx, const double *weights, int n_parts,
+                    int32_t *part);
 
 }  // namespace rs

@@ -397,10 +397,11 @@ int bcsr_spmv(bcsr_t A, const double *x, double *y, int32_t first_sys, int32_t n
     return RS_OK;
 }
 
-static int build_analysis(const rs_bcsr *A, int32_t ordering, std::shared_ptr<Analysis> &out) {
+static int build_analysis(const rs_bcsr *A, int32_t ordering, const int32_t *part, std::shared_ptr<Analysis> &out) {
     auto an = std::make_shared<Analysis>();
     an->hash = A->hash;
-    rs::build_schedule(A->n, A->nnzb, A->h_rowptr.data(), A->h_colidx.data(), ordering, an->sch, rs::kRowsPerBlock);
+    rs::build_schedule(A->n, A->nnzb, A->h_rowptr.data(), A->h_colidx.data(), ordering, an->sch, rs::kRowsPerBlock,
+                       part);
     const rs::Schedule &S = an->sch;
     hipError_t e = hipSuccess;
     struct Up { DevBuf *b; const std::vector<int32_t> *v; } ups[] = {
@@ -456,9 +457,31 @@ int ilu0_analyse(bcsr_t A, int32_t ordering, ilu0_t *out) {
     if (!A || !out || ordering < 0 || ordering > 2) return fail(RS_INVALID_ARG, "ilu0_analyse: bad arguments");
     *out = nullptr;
     std::shared_ptr<Analysis> an;
-    const int st = build_analysis(A, ordering, an);
+    const int st = build_analysis(A, ordering, nullptr, an);
     if (st != RS_OK) return st;
     *out = new_ilu0(A, std::move(an));
+    return RS_OK;
+}
+
+int ilu0_analyse_jacobi(bcsr_t A, int32_t ordering, const int32_t *part, ilu0_t *out) {
+    if (!A || !out || !part || ordering < 0 || ordering > 2)
+        return fail(RS_INVALID_ARG, "ilu0_analyse_jacobi: bad arguments");
+    *out = nullptr;
+    std::shared_ptr<Analysis> an;
+    const int st = build_analysis(A, ordering, part, an);
+    if (st != RS_OK) return st;
+    *out = new_ilu0(A, std::move(an));
+    return RS_OK;
+}
+
+int bcsr_partition(int32_t n_brows, int32_t nnzb, const int32_t *row_ptr, const int32_t *col_idx,
+                   const double *weights, int32_t n_parts, int32_t *part) {
+    if (n_brows < 0 || nnzb < 0 || !row_ptr || (nnzb > 0 && !col_idx) || n_parts < 1 || (n_brows > 0 && !part))
+        return fail(RS_INVALID_ARG, "bcsr_partition: bad arguments");
+    int bad = -1;
+    const int st = rs::validate_pattern(n_brows, nnzb, row_ptr, col_idx, &bad);
+    if (st != RS_OK) return fail(st, "bcsr_partition: invalid pattern at row " + std::to_string(bad));
+    rs::partition_rows(n_brows, row_ptr, col_idx, weights, n_parts, part);
     return RS_OK;
 }
 
@@ -608,6 +631,7 @@ int ilu0_get_factors(ilu0_t M, int32_t sys, double *lu, double *dinv) {
     if (!M->factored) return fail(RS_NOT_FACTORED, "ilu0_get_factors: not factored");
     HIP_TRY(hipDeviceSynchronize());   // the factorisation may still run on any stream
     const rs::Schedule &S = M->an->sch;
+    if (lu) std::memset(lu, 0, sizeof(double) * 9 * (size_t)M->nnzb);   // diagonal, blocks outside a Jacobi matrix
     std::vector<double> L((size_t)S.nL * 9), U((size_t)S.nU * 9), D((size_t)M->n * 9);
     if (M->precision == RS_PREC_FP32_FACTORS) {
         std::vector<float> Lf(L.size()), Uf(U.size()), Df(D.size());
@@ -952,6 +976,7 @@ static std::string tune_key(ilu0_t M) {
     std::ostringstream k;
     k << "n=" << M->n << ",nnzb=" << M->nnzb << ",batch=" << M->batch << ",ord=" << M->an->sch.ordering
       << ",prec=" << M->precision << ",nl=" << M->an->sch.nl_levels << ",nu=" << M->an->sch.nu_levels
+      << ",m=" << M->an->sch.nnz_m
       << ",arch=" << prop.gcnArchName << ",cu=" << prop.multiProcessorCount;
     std::string r = k.str();
     for (char &c : r)

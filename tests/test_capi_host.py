@@ -89,3 +89,40 @@ def test_host_analysis_nonsymmetric_pattern():
         assert sorted(perm.tolist()) == [0, 1, 2]
         operm = oracle.ordering_perm(rowptr, colidx, ordering)
         assert np.array_equal(perm, operm)
+
+
+@pytest.mark.parametrize("parts", [1, 3, 8, 50])
+def test_partition_is_balanced_and_deterministic(parts):
+    s = make_grid_system(9, 7, 6, active_frac=0.9, nnc_frac=0.03, seed=12)
+    part = rs.bcsr_partition(s.rowptr, s.colidx, parts, weights=s.trans)
+    assert part.shape == (s.n,) and part.min() == 0 and part.max() == parts - 1
+    sizes = np.bincount(part, minlength=parts)
+    assert sizes.max() - sizes.min() <= 1
+    assert np.array_equal(part, rs.bcsr_partition(s.rowptr, s.colidx, parts, weights=s.trans))
+
+
+def test_partition_keeps_strong_couplings_inside():
+    """Two tightly coupled chains joined by weak links split along the weak links."""
+    n = 40
+    pairs = [(i, i + 1) for i in range(19)] + [(i, i + 1) for i in range(20, 39)] + [(i, i + 20) for i in range(20)]
+    rowptr, colidx = pattern_from_pairs(n, pairs)
+    w = np.zeros(len(colidx))
+    for i in range(n):
+        for p in range(rowptr[i], rowptr[i + 1]):
+            j = colidx[p]
+            w[p] = 100.0 if abs(i - j) == 1 and (i < 20) == (j < 20) else 1e-3
+    part = rs.bcsr_partition(rowptr, colidx, 2, weights=w)
+    assert (part[:20] == part[0]).all() and (part[20:] == part[20]).all() and part[0] != part[20]
+    cut_weak = rs.bcsr_partition(rowptr, colidx, 2)                 # unweighted: grown breadth-first
+    assert np.bincount(cut_weak).tolist() == [20, 20]
+
+
+def test_partition_rejects_bad_input():
+    s = make_grid_system(4, 3, 2, seed=1)
+    with pytest.raises(rs.RsolveError):
+        rs.bcsr_partition(s.rowptr, s.colidx, 0)
+    bad = s.colidx.copy()
+    bad[[0, 1]] = bad[[1, 0]]
+    with pytest.raises(rs.RsolveError) as e:
+        rs.bcsr_partition(s.rowptr, bad, 2)
+    assert e.value.status == rs.BAD_PATTERN

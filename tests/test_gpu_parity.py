@@ -463,6 +463,84 @@ def test_fresh_handles_on_a_non_blocking_stream():
                 rs.bcsr_destroy(A)
 
 
+def jacobi_case(parts):
+    s = CASES["nnc"]
+    return s, rs.bcsr_partition(s.rowptr, s.colidx, parts, weights=s.trans)
+
+
+def jacobi_handles(s, ordering, part, precision=rs.PREC_FP64):
+    A = rs.bcsr_create(s.rowptr, s.colidx, s.vals)
+    M = rs.ilu0_analyse_jacobi(A, ordering, part)
+    st, bad = rs.ilu0_factor(M, A, precision)
+    return A, M, st
+
+
+@pytest.mark.parametrize("ordering", ORDERINGS)
+@pytest.mark.parametrize("parts", [3, 40])
+def test_jacobi_factor_and_solve_parity(ordering, parts):
+    s, part = jacobi_case(parts)
+    A, M, st = jacobi_handles(s, ordering, part)
+    try:
+        assert st == rs.OK
+        # oracle: ILU0 of the Jacobi matrix in its own ordering
+        rrow, rcol, rv = oracle.jacobi_matrix(s.rowptr, s.colidx, s.vals[0], part)
+        perm = oracle.ordering_perm(rrow, rcol, ordering)
+        gperm, nsets, _ = rs.ilu0_get_schedule(M, s.n)
+        assert np.array_equal(gperm, perm)
+        mrow, mcol, mv = oracle.permute(rrow, rcol, rv, perm)
+        ost, _, lu, dinv = oracle.ilu0(mrow, mcol, mv)
+        assert ost == oracle.OK
+        prow, pcol, _ = oracle.permute(s.rowptr, s.colidx, s.vals[0], perm)
+        glu, gdinv = rs.ilu0_get_factors(M, 0, s.n, s.nnzb)
+        keep = np.array([part[perm[i]] == part[perm[pcol[p]]] for i in range(s.n)
+                         for p in range(prow[i], prow[i + 1])], bool)
+        offd = np.array([mcol[p] != i for i in range(s.n) for p in range(mrow[i], mrow[i + 1])], bool)
+        assert not glu[~keep].any()                               # dropped blocks stay empty
+        assert rel_block_err(glu[keep][offd], lu[offd]) <= 1e-12
+        assert rel_block_err(gdinv, dinv) <= 1e-12
+        x, sst, info = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-10)
+        xo, oinfo = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=ordering, reduction=1e-10,
+                                 part=part)
+        assert sst == oinfo["status"] == rs.OK
+        assert np.linalg.norm(x[0] - xo) <= 1e-8 * np.linalg.norm(xo)
+        assert info[0]["half_steps"] == oinfo["half_steps"]
+        assert info[0]["true_rel_residual"] <= 1e-9
+    finally:
+        rs.ilu0_destroy(M)
+        rs.bcsr_destroy(A)
+
+
+def test_jacobi_single_partition_is_plain_ilu0(solver_of):
+    s = CASES["nnc"]
+    for ordering in ORDERINGS:
+        A, M, st = jacobi_handles(s, ordering, np.zeros(s.n, np.int32))
+        try:
+            A2, M2, st2, _ = solver_of(s, ordering)
+            x1, st1, i1 = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-10)
+            x2, st2, i2 = rs.bicgstab_solve(M2, A2, s.b[:, 0], reduction=1e-10)
+            assert np.array_equal(x1, x2) and i1[0]["half_steps"] == i2[0]["half_steps"]
+        finally:
+            rs.ilu0_destroy(M)
+            rs.bcsr_destroy(A)
+
+
+def test_jacobi_mixed_precision_and_fewer_levels():
+    s = make_grid_system(20, 18, 24, seed=9)
+    part = (np.arange(s.n) // (20 * 18 * 6)).astype(np.int32)          # 4 z-slabs of 6 layers
+    A, M, st = jacobi_handles(s, rs.ORDER_LEVEL_SET, part, rs.PREC_FP32_FACTORS)
+    try:
+        assert st == rs.OK
+        assert rs.ilu0_get_sweep_levels(M) == (20 + 18 + 6 - 2, 20 + 18 + 6 - 2)
+        x, sst, info = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-6)
+        xo, oinfo = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=rs.ORDER_LEVEL_SET,
+                                 precond=oracle.PREC_ILU_F32, reduction=1e-6, part=part)
+        assert sst == rs.OK and info[0]["true_rel_residual"] <= 1e-6 * (1 + 1e-6)
+        assert abs(info[0]["half_steps"] - oinfo["half_steps"]) <= 2
+    finally:
+        rs.ilu0_destroy(M)
+        rs.bcsr_destroy(A)
+
+
 def test_device_memory_path():
     torch = pytest.importorskip("torch")
     s = CASES["nnc"]
