@@ -72,7 +72,9 @@ enum rs_precision { RS_PREC_FP64 = 0, RS_PREC_FP32_FACTORS = 1 };
 enum rs_mem { RS_MEM_HOST = 0, RS_MEM_DEVICE = 1 };
 
 /* Execution options of an ilu0_t (ilu0_set_option).  They change how the
- * work is launched, never the arithmetic or its order. */
+ * work is launched.  The factor's and the sweeps' arithmetic never changes;
+ * SpMV shapes and reduction modes change only the summation order of the
+ * dot products fused into the SpMVs (the last bits of alpha and omega). */
 enum rs_option {
     RS_OPT_SWEEP_TILES = 0,  /* 1: one launch per triangular sweep, row tiles wait only on the
                                 tiles they depend on; 0: one launch per level.  Default: 0 for
@@ -88,7 +90,10 @@ enum rs_option {
                                 convergence return at once) */
     RS_OPT_SPMV_VARIANT = 5, /* launch shape of the SpMVs: 0..5 = {4, 2, 1} waves per workgroup
                                 with blocks staged in LDS, then the same three reading directly */
-    RS_OPT_SWEEP_VARIANT = 6 /* launch shape of the one-launch-per-level sweeps (same encoding) */
+    RS_OPT_SWEEP_VARIANT = 6, /* launch shape of the one-launch-per-level sweeps (same encoding) */
+    RS_OPT_REDUCE_SPLIT = 7  /* dot products fused into the SpMVs: 0 (default) = each workgroup
+                                joins a ticket tree inside the SpMV; 1 = each wave only stores
+                                its partial and a one-workgroup kernel adds them */
 };
 
 /* Per-system outcome of bicgstab_solve. */
@@ -199,11 +204,13 @@ typedef struct {
     double us_per_solve;   /* mean time of one bicgstab_solve call with them (0 when cached) */
     int32_t candidates;    /* configurations timed (0 when taken from the cache) */
     int32_t from_cache;    /* 1 when read from the cache file */
+    int32_t reduce_split;  /* chosen RS_OPT_REDUCE_SPLIT */
 } rs_tune_result;
 
 /* ilu0_autotune -- pick the launch configuration of a factored handle by
  * timing it: every one-launch-per-level sweep shape, the single-launch sweep
- * with several grid sizes, then every SpMV shape with the best sweep, each
+ * with several grid sizes, then every SpMV shape with the best sweep, then
+ * the split reduction with the best of those, each
  * over `reps` (>= 1) bicgstab_solve calls on right-hand sides b (batch *
  * n_brows * 3 doubles, mem) at `reduction`.  The fastest is applied with
  * ilu0_set_option.  When the environment variable RSOLVE_TUNE_CACHE names a

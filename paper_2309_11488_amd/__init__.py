@@ -25,7 +25,7 @@ ORDER_NATURAL, ORDER_LEVEL_SET, ORDER_GRAPH_COLOUR = 0, 1, 2
 PREC_FP64, PREC_FP32_FACTORS = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 OPT_SWEEP_TILES, OPT_SWEEP_GRID, OPT_POLL_CHUNK, OPT_USE_GRAPH, OPT_PREDICT_POLL = 0, 1, 2, 3, 4
-OPT_SPMV_VARIANT, OPT_SWEEP_VARIANT = 5, 6
+OPT_SPMV_VARIANT, OPT_SWEEP_VARIANT, OPT_REDUCE_SPLIT = 5, 6, 7
 N_ROW_VARIANTS = 6
 
 EXPORTS = (
@@ -51,7 +51,7 @@ class SolveInfo(ct.Structure):
 class TuneResult(ct.Structure):
     _fields_ = [("spmv_variant", ct.c_int32), ("sweep_variant", ct.c_int32), ("sweep_tiles", ct.c_int32),
                 ("sweep_grid", ct.c_int32), ("us_per_solve", ct.c_double), ("candidates", ct.c_int32),
-                ("from_cache", ct.c_int32)]
+                ("from_cache", ct.c_int32), ("reduce_split", ct.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

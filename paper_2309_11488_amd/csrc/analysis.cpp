@@ -257,6 +257,23 @@ int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx
     }
     s.nL = (int)s.lcol.size();
     s.nU = (int)s.ucol.size();
+    s.lsrc_a.resize(s.nL);
+    s.usrc_a.resize(s.nU);
+    s.dsrc_a.resize(n);
+    for (int e = 0; e < s.nL; ++e) s.lsrc_a[e] = s.psrc[s.lsrc[e]];
+    for (int f = 0; f < s.nU; ++f) s.usrc_a[f] = s.psrc[s.usrc[f]];
+    for (int q = 0; q < n; ++q) s.dsrc_a[q] = s.psrc[s.dsrc[q]];
+    if (part) {
+        std::vector<char> used(nnzb, 0);
+        for (int32_t p : s.lsrc) used[p] = 1;
+        for (int32_t p : s.usrc) used[p] = 1;
+        for (int32_t p : s.dsrc) used[p] = 1;
+        for (int p = 0; p < nnzb; ++p)
+            if (!used[p]) {
+                s.rest_dst.push_back(p);
+                s.rest_src.push_back(s.psrc[p]);
+            }
+    }
 
     // update lists: for L block (i,k), every j > k in row k that row i also
     // holds, ascending j, in the order Algorithm 2 applies them

@@ -41,6 +41,10 @@ struct Schedule {
     std::vector<int32_t> perm, iperm;
     // reordered matrix
     std::vector<int32_t> prow, pcol, psrc;
+    // caller-order block positions of the factor's inputs (psrc composed
+    // with lsrc / usrc / dsrc), and the A' blocks the factor does not read
+    // (Block-Jacobi: blocks outside the Jacobi matrix) with their sources
+    std::vector<int32_t> lsrc_a, usrc_a, dsrc_a, rest_dst, rest_src;
     // lower sweep
     int nl_levels = 0, nL = 0;
     std::vector<int32_t> lrows, lset, lptr, lcol, lsrc, ldq, l2u;

@@ -174,6 +174,7 @@ struct Analysis {
     rs::Schedule sch;
     DevSchedule dev{};
     DevBuf perm, prow, pcol, psrc, lrows, lptr, lcol, lsrc, ldq, l2u, upd_ptr, upd, urows, uptr, ucol, usrc, dsrc;
+    DevBuf lsrc_a, usrc_a, dsrc_a, rest_dst, rest_src;
     DevBuf lt_start, lt_dptr, lt_dep, ut_start, ut_dptr, ut_dep;
 };
 
@@ -198,6 +199,8 @@ struct rs_ilu0 {
     int sweep_grid = 1024;     // workgroups of a single-launch sweep
     int spmv_variant = rs::RV_W4_LDS;   // launch shape of the SpMVs
     int sweep_variant = rs::RV_W4_LDS;  // launch shape of the per-level sweeps
+    int reduce_split = 0;               // RS_OPT_REDUCE_SPLIT
+    bool split() const { return reduce_split != 0; }
     // a BiCGStab iteration captured as HIP graphs, replayed on the caller's
     // stream: segment 0 = the whole iteration; 1 and 2 = the parts before and
     // after v = A phat, used while that kernel is being timed with events
@@ -409,7 +412,8 @@ static int build_analysis(const rs_bcsr *A, int32_t ordering, const int32_t *par
         {&an->lrows, &S.lrows}, {&an->lptr, &S.lptr}, {&an->lcol, &S.lcol}, {&an->lsrc, &S.lsrc},
         {&an->ldq, &S.ldq}, {&an->l2u, &S.l2u}, {&an->upd_ptr, &S.upd_ptr}, {&an->upd, &S.upd},
         {&an->urows, &S.urows}, {&an->uptr, &S.uptr}, {&an->ucol, &S.ucol}, {&an->usrc, &S.usrc},
-        {&an->dsrc, &S.dsrc}, {&an->lt_start, &S.ltiles.start}, {&an->lt_dptr, &S.ltiles.dep_ptr},
+        {&an->dsrc, &S.dsrc}, {&an->lsrc_a, &S.lsrc_a}, {&an->usrc_a, &S.usrc_a}, {&an->dsrc_a, &S.dsrc_a},
+        {&an->rest_dst, &S.rest_dst}, {&an->rest_src, &S.rest_src}, {&an->lt_start, &S.ltiles.start}, {&an->lt_dptr, &S.ltiles.dep_ptr},
         {&an->lt_dep, &S.ltiles.dep}, {&an->ut_start, &S.utiles.start}, {&an->ut_dptr, &S.utiles.dep_ptr},
         {&an->ut_dep, &S.utiles.dep}};
     // uploads on a private stream, complete before the handle is returned,
@@ -434,6 +438,9 @@ static int build_analysis(const rs_bcsr *A, int32_t ordering, const int32_t *par
     d.l2u = an->l2u.as<int32_t>(); d.upd_ptr = an->upd_ptr.as<int32_t>(); d.upd = an->upd.as<int32_t>();
     d.urows = an->urows.as<int32_t>(); d.uptr = an->uptr.as<int32_t>(); d.ucol = an->ucol.as<int32_t>();
     d.usrc = an->usrc.as<int32_t>(); d.dsrc = an->dsrc.as<int32_t>();
+    d.lsrc_a = an->lsrc_a.as<int32_t>(); d.usrc_a = an->usrc_a.as<int32_t>(); d.dsrc_a = an->dsrc_a.as<int32_t>();
+    d.nrest = (int)S.rest_dst.size();
+    d.rest_dst = an->rest_dst.as<int32_t>(); d.rest_src = an->rest_src.as<int32_t>();
     d.nlt = S.ltiles.n; d.nut = S.utiles.n;
     d.lt_start = an->lt_start.as<int32_t>(); d.lt_dptr = an->lt_dptr.as<int32_t>(); d.lt_dep = an->lt_dep.as<int32_t>();
     d.ut_start = an->ut_start.as<int32_t>(); d.ut_dptr = an->ut_dptr.as<int32_t>(); d.ut_dep = an->ut_dep.as<int32_t>();
@@ -536,6 +543,10 @@ int ilu0_set_option(ilu0_t M, int32_t option, int32_t value) {
         if (value < 0 || value >= rs::RV_COUNT) break;
         M->spmv_variant = value;
         return RS_OK;
+    case RS_OPT_REDUCE_SPLIT:
+        if (value < 0 || value > 1) break;
+        M->reduce_split = value;
+        return RS_OK;
     case RS_OPT_SWEEP_VARIANT:
         if (value < 0 || value >= rs::RV_COUNT) break;
         M->sweep_variant = value;
@@ -556,6 +567,7 @@ int ilu0_get_option(ilu0_t M, int32_t option, int32_t *value) {
     case RS_OPT_PREDICT_POLL: *value = M->predict ? 1 : 0; return RS_OK;
     case RS_OPT_SPMV_VARIANT: *value = M->spmv_variant; return RS_OK;
     case RS_OPT_SWEEP_VARIANT: *value = M->sweep_variant; return RS_OK;
+    case RS_OPT_REDUCE_SPLIT: *value = M->reduce_split; return RS_OK;
     default: return fail(RS_INVALID_ARG, "ilu0_get_option: unknown option");
     }
 }
@@ -590,24 +602,25 @@ int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *ba
     HIP_TRY(hipMemsetAsync(M->bad.p, 0x7f, B * sizeof(int32_t), s));
     const size_t per = (size_t)M->nnzb * 9;
     {
-        // reordered copy of A (read, index, write), then the factor: A' read,
-        // L/U/inv(U_ii) written, index and update lists read (FP32 copies:
-        // FP64 factors read again, FP32 written)
-        const double nnzb = M->nnzb, n = M->n;
-        double bytes = 148 * nnzb + 72 * nnzb + 72 * nnzb + 4 * (3.0 * S.nL + 2.0 * S.nU + 3 * n) + 4.0 * S.upd.size();
-        if (precision == RS_PREC_FP32_FACTORS) bytes += 108 * nnzb;
+        // the factor reads A once (blocks and caller positions), writes the
+        // reordered copy A' (the SpMV operand) and L / U / inv(U_ii), reads
+        // inv(U_kk) once per lower block and U_kj once per update, plus the
+        // schedule's index lists; FP32 copies written alongside
+        const double nnzb = M->nnzb, n = M->n, nupd = (double)S.upd.size() / 2;
+        double bytes = 72 * nnzb + 72 * nnzb + 72 * nnzb + 72 * (double)S.nL + 72 * nupd +
+                       4 * (4.0 * S.nL + 3.0 * S.nU + 5 * n) + 8 * nupd;
+        if (precision == RS_PREC_FP32_FACTORS) bytes += 36 * nnzb;
+        if (S.jacobi) bytes += 152 * (double)S.rest_dst.size();
         ProfScope ps(PC_FACTOR, s, B * bytes);
-        rs::launch_gather_blocks(A->vals.as<double>(), per, M->pvals.as<double>(), per, M->an->dev.psrc, M->nnzb,
-                                 M->batch, s);
+        const DevSchedule &d = M->an->dev;
+        rs::launch_gather_pairs(A->vals.as<double>(), per, M->pvals.as<double>(), per, d.rest_dst, d.rest_src,
+                                d.nrest, M->batch, s);
+        const bool f32 = precision == RS_PREC_FP32_FACTORS;
         for (int l = 0; l < S.nl_levels; ++l)
-            rs::launch_factor_level(M->an->dev, M->pvals.as<double>(), M->L.as<double>(), M->U.as<double>(),
-                                    M->Dinv.as<double>(), M->bad.as<int32_t>(), S.lset[l], S.lset[l + 1], M->batch,
-                                    s);
-        if (precision == RS_PREC_FP32_FACTORS) {
-            rs::launch_to_fp32(M->L.as<double>(), M->Lf.as<float>(), B * S.nL * 9, s);
-            rs::launch_to_fp32(M->U.as<double>(), M->Uf.as<float>(), B * S.nU * 9, s);
-            rs::launch_to_fp32(M->Dinv.as<double>(), M->Dinvf.as<float>(), B * M->n * 9, s);
-        }
+            rs::launch_factor_level(d, A->vals.as<double>(), per, M->pvals.as<double>(), M->L.as<double>(),
+                                    M->U.as<double>(), M->Dinv.as<double>(), f32 ? M->Lf.as<float>() : nullptr,
+                                    f32 ? M->Uf.as<float>() : nullptr, f32 ? M->Dinvf.as<float>() : nullptr,
+                                    M->bad.as<int32_t>(), S.lset[l], S.lset[l + 1], M->batch, s);
     }
     HIP_TRY(hipGetLastError());
     M->bad_host.assign(B, 0);
@@ -772,13 +785,13 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
     if (parts & IT_APPLY1) apply_levels<T>(M, L, U, D, nullptr, k.phat, true, k, k.st, B, s);
     if (parts & IT_SPMV_V) {
         ProfScope ps(PC_SPMV_V, s, spmv_bytes);
-        rs::launch_spmv_v(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, s);
+        rs::launch_spmv_v(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), s);
     }
     if (!(parts & IT_REST)) return;
-    { ProfScope ps(PC_VEC, s, B * 72 * n); rs::launch_s_update(M->n, k, B, M->spmv_variant, s); }
+    { ProfScope ps(PC_VEC, s, B * 72 * n); rs::launch_s_update(M->n, k, B, M->spmv_variant, M->split(), s); }
     apply_levels<T>(M, L, U, D, k.s, k.shat, false, k, k.st, B, s);
-    { ProfScope ps(PC_SPMV_T, s, spmv_bytes); rs::launch_spmv_t(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, s); }
-    { ProfScope ps(PC_VEC, s, B * 192 * n); rs::launch_xr_update(M->n, k, B, M->spmv_variant, s); }
+    { ProfScope ps(PC_SPMV_T, s, spmv_bytes); rs::launch_spmv_t(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), s); }
+    { ProfScope ps(PC_VEC, s, B * 192 * n); rs::launch_xr_update(M->n, k, B, M->spmv_variant, M->split(), s); }
 }
 
 static void enqueue_iteration_any(ilu0_t M, hipStream_t s, int parts) {
@@ -793,7 +806,8 @@ static void enqueue_iteration_any(ilu0_t M, hipStream_t s, int parts) {
 // graph: profiling is off while segments are captured.
 static int replay_segment(ilu0_t M, int seg, int parts, hipStream_t s) {
     const long long key = (long long)M->precision | (long long)M->tile_sweeps << 2 | (long long)M->spmv_variant << 3 |
-                          (long long)M->sweep_variant << 6 | (long long)M->sweep_grid << 10;
+                          (long long)M->sweep_variant << 6 | (long long)(M->split() ? 1 : 0) << 9 |
+                          (long long)M->sweep_grid << 10;
     if (!M->gexec[seg] || M->graph_key[seg] != key) {
         if (M->gexec[seg]) (void)hipGraphExecDestroy(M->gexec[seg]);
         if (M->graph[seg]) (void)hipGraphDestroy(M->graph[seg]);
@@ -927,7 +941,7 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
         if (all) break;
     }
     rs::launch_finish(M->an->dev, A->rowptr.as<int32_t>(), A->colidx.as<int32_t>(), A->vals.as<double>(),
-                      (size_t)A->nnzb * 9, bd, xd, k, B, M->spmv_variant, s);
+                      (size_t)A->nnzb * 9, bd, xd, k, B, M->spmv_variant, M->split(), s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(M->h_ctr, k.lctr, 2 * sizeof(rs::SweepCtr), hipMemcpyDeviceToHost, s));
@@ -976,7 +990,7 @@ static std::string tune_key(ilu0_t M) {
     std::ostringstream k;
     k << "n=" << M->n << ",nnzb=" << M->nnzb << ",batch=" << M->batch << ",ord=" << M->an->sch.ordering
       << ",prec=" << M->precision << ",nl=" << M->an->sch.nl_levels << ",nu=" << M->an->sch.nu_levels
-      << ",m=" << M->an->sch.nnz_m
+      << ",m=" << M->an->sch.nnz_m << ",fmt=2"
       << ",arch=" << prop.gcnArchName << ",cu=" << prop.multiProcessorCount;
     std::string r = k.str();
     for (char &c : r)
@@ -992,7 +1006,8 @@ int ilu0_autotune(ilu0_t M, bcsr_t A, const double *b, int32_t mem, double reduc
         return fail(RS_INVALID_ARG, "ilu0_autotune: bad arguments");
     if (!M->factored) return fail(RS_NOT_FACTORED, "ilu0_autotune: call ilu0_factor first");
     hipStream_t s = (hipStream_t)stream;
-    rs_tune_result res{M->spmv_variant, M->sweep_variant, M->tile_sweeps ? 1 : 0, M->sweep_grid, 0.0, 0, 0};
+    rs_tune_result res{M->spmv_variant, M->sweep_variant, M->tile_sweeps ? 1 : 0, M->sweep_grid, 0.0, 0, 0,
+                       M->reduce_split};
     const std::string key = tune_key(M);
     const char *cache = std::getenv("RSOLVE_TUNE_CACHE");
     if (cache && *cache) {
@@ -1002,9 +1017,9 @@ int ilu0_autotune(ilu0_t M, bcsr_t A, const double *b, int32_t mem, double reduc
             std::istringstream ls(line);
             std::string k;
             rs_tune_result r{};
-            if (ls >> k >> r.spmv_variant >> r.sweep_variant >> r.sweep_tiles >> r.sweep_grid && k == key &&
-                r.spmv_variant >= 0 && r.spmv_variant < rs::RV_COUNT && r.sweep_variant >= 0 &&
-                r.sweep_variant < rs::RV_COUNT && r.sweep_grid >= 1) {
+            if (ls >> k >> r.spmv_variant >> r.sweep_variant >> r.sweep_tiles >> r.sweep_grid >> r.reduce_split &&
+                k == key && r.spmv_variant >= 0 && r.spmv_variant < rs::RV_COUNT && r.sweep_variant >= 0 &&
+                r.sweep_variant < rs::RV_COUNT && r.sweep_grid >= 1 && (r.reduce_split == 0 || r.reduce_split == 1)) {
                 res = r;
                 res.from_cache = 1;
             }
@@ -1014,6 +1029,7 @@ int ilu0_autotune(ilu0_t M, bcsr_t A, const double *b, int32_t mem, double reduc
             M->sweep_variant = res.sweep_variant;
             M->tile_sweeps = res.sweep_tiles != 0;
             M->sweep_grid = res.sweep_grid;
+            M->reduce_split = res.reduce_split;
             if (out) *out = res;
             return RS_OK;
         }
@@ -1026,16 +1042,17 @@ int ilu0_autotune(ilu0_t M, bcsr_t A, const double *b, int32_t mem, double reduc
         HIP_TRY(hipMemcpyAsync(bb.p, b, m * sizeof(double),
                                mem == RS_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
     struct Cfg {
-        int spmv, sweep, tiles, grid;
+        int spmv, sweep, tiles, grid, split;
     };
     auto apply = [&](const Cfg &c) {
         M->spmv_variant = c.spmv;
         M->sweep_variant = c.sweep;
         M->tile_sweeps = c.tiles != 0;
         M->sweep_grid = c.grid;
+        M->reduce_split = c.split;
     };
     double best = 1e300;
-    Cfg bestc{M->spmv_variant, M->sweep_variant, M->tile_sweeps ? 1 : 0, M->sweep_grid};
+    Cfg bestc{M->spmv_variant, M->sweep_variant, M->tile_sweeps ? 1 : 0, M->sweep_grid, 0};
     int ncand = 0;
     auto time_cfg = [&](const Cfg &c) -> int {
         apply(c);
@@ -1057,25 +1074,30 @@ int ilu0_autotune(ilu0_t M, bcsr_t A, const double *b, int32_t mem, double reduc
     };
     const int sp0 = M->spmv_variant;
     for (int v = 0; v < rs::RV_COUNT; ++v) {
-        st = time_cfg({sp0, v, 0, M->sweep_grid});
+        st = time_cfg({sp0, v, 0, M->sweep_grid, 0});
         if (st != RS_OK) return st;
     }
     for (int g : {256, 512, 1024, 2048}) {
-        st = time_cfg({sp0, bestc.sweep, 1, g});
+        st = time_cfg({sp0, bestc.sweep, 1, g, 0});
         if (st != RS_OK) return st;
     }
     const Cfg sweep_best = bestc;
     for (int v = 0; v < rs::RV_COUNT; ++v) {
         if (v == sp0) continue;
-        st = time_cfg({v, sweep_best.sweep, sweep_best.tiles, sweep_best.grid});
+        st = time_cfg({v, sweep_best.sweep, sweep_best.tiles, sweep_best.grid, 0});
+        if (st != RS_OK) return st;
+    }
+    {
+        const Cfg c = bestc;
+        st = time_cfg({c.spmv, c.sweep, c.tiles, c.grid, 1});
         if (st != RS_OK) return st;
     }
     apply(bestc);
-    res = rs_tune_result{bestc.spmv, bestc.sweep, bestc.tiles, bestc.grid, best, ncand, 0};
+    res = rs_tune_result{bestc.spmv, bestc.sweep, bestc.tiles, bestc.grid, best, ncand, 0, bestc.split};
     if (cache && *cache) {
         std::ofstream o(cache, std::ios::app);
         o << key << " " << res.spmv_variant << " " << res.sweep_variant << " " << res.sweep_tiles << " "
-          << res.sweep_grid << " " << res.us_per_solve << "\n";
+          << res.sweep_grid << " " << res.reduce_split << " " << res.us_per_solve << "\n";
     }
     if (out) *out = res;
     return RS_OK;

@@ -28,6 +28,9 @@ struct DevSchedule {
     const int32_t *perm, *prow, *pcol, *psrc;
     const int32_t *lrows, *lptr, *lcol, *lsrc, *ldq, *l2u, *upd_ptr, *upd;
     const int32_t *urows, *uptr, *ucol, *usrc, *dsrc;
+    const int32_t *lsrc_a, *usrc_a, *dsrc_a;   // caller-order sources of the factor's blocks
+    int nrest;                                 // A' blocks the factor does not read (Block-Jacobi)
+    const int32_t *rest_dst, *rest_src;
     // sweep tiles (see Schedule::Tiles)
     int nlt, nut;
     const int32_t *lt_start, *lt_dptr, *lt_dep, *ut_start, *ut_dptr, *ut_dep;
@@ -82,22 +85,41 @@ enum RowVariant { RV_W4_LDS = 0, RV_W2_LDS = 1, RV_W1_LDS = 2, RV_W4_DIRECT = 3,
 inline int variant_waves(int v) { return v % 3 == 0 ? 4 : (v % 3 == 1 ? 2 : 1); }
 // SpMV workgroups: one row tile each.
 inline int spmv_grid(int n, int waves) { return std::max(1, row_blocks(n, waves)); }
+
+// Split reduction of the dot products fused into an SpMV (RS_OPT_REDUCE_SPLIT):
+// waves store partials and a one-workgroup kernel adds them.
+constexpr int kTotalThreads = 1024;   // threads of the one-workgroup summing kernel
+// Where the consumers of an SpMV's dot products find the sums they add (in
+// doubles from the start of the system's partials) and how many pairs:
+// the group sums of the ticket tree, or the one total of k_spmv_total
+// stored after the wave partials.
+struct SpmvSums {
+    int offset, count;
+};
+inline SpmvSums spmv_sums(int n, int waves, bool split) {
+    const int g = spmv_grid(n, waves);
+    return split ? SpmvSums{2 * g * waves, 1} : SpmvSums{2 * g, (g + 31) / 32};
+}
 // Reduction scratch of a system whose largest launch has `blocks` workgroups.
 inline size_t part_stride_for(int blocks) { return 2 * (size_t)blocks + 2 * ((size_t)blocks / 32 + 1) + 16; }
-inline size_t ticket_stride_for(int blocks) { return 2 + (size_t)blocks / 32 + 1; }
+// Reduction counters sit on their own 128-byte lines (kTicketPad uint32
+// apart): counter 0 is the top of the tree, counter 1 + g that of group g.
+constexpr int kTicketPad = 32;
+inline size_t ticket_stride_for(int blocks) { return (size_t)kTicketPad * (2 + (size_t)blocks / 32 + 1); }
 inline size_t vec_stride(int n) { return (3 * (size_t)n + kVecTile - 1) / kVecTile * kVecTile; }
 int vec_blocks(int n);  // workgroups of the vector kernels for one padded vector
 
-// A'[p] = A[src[p]] for every system (blocks of 9 doubles).
-void launch_gather_blocks(const double *A, size_t a_stride, double *Ap, size_t ap_stride, const int32_t *src,
-                          int cnt, int nsys, hipStream_t s);
+// Ap[dst[i]] = A[src[i]] for every system (blocks of 9 doubles).
+void launch_gather_pairs(const double *A, size_t a_stride, double *Ap, size_t ap_stride, const int32_t *dst,
+                         const int32_t *src, int cnt, int nsys, hipStream_t s);
 
 // One level of the block ILU0 factorisation: L-schedule rows [q0, q1).
-void launch_factor_level(const DevSchedule &d, const double *Ap, double *L, double *U, double *Dinv, int32_t *bad,
-                         int q0, int q1, int nsys, hipStream_t s);
-
-// FP32 copies of the factors (round to nearest even).
-void launch_to_fp32(const double *src, float *dst, size_t count, hipStream_t s);
+// Reads the caller's blocks A, writes the reordered copy Ap of every block
+// it reads (the SpMV operand), the FP64 factors and, when Lf is not null,
+// their FP32 roundings.
+void launch_factor_level(const DevSchedule &d, const double *A, size_t a_stride, double *Ap, double *L, double *U,
+                         double *Dinv, float *Lf, float *Uf, float *Df, int32_t *bad, int q0, int q1, int nsys,
+                         hipStream_t s);
 
 // Lower sweep y = L^{-1} in for L-schedule rows [q0, q1).  When fuse_p is
 // set, the input is p = r + beta (p - omega v) computed on the fly (and
@@ -133,17 +155,14 @@ void launch_spmv(int n, const int32_t *ptr, const int32_t *col, const double *A,
 // bad[sys] < n marks a system whose factorisation hit a singular pivot.
 void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad, double reduction, int max_iter,
                   Krylov &k, int nsys, hipStream_t s);
-void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
-                   hipStream_t s);
-void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, hipStream_t s);
-void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
-                   hipStream_t s);
-void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, hipStream_t s);
+void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, bool split, hipStream_t s);
+void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, bool split, hipStream_t s);
+void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, bool split, hipStream_t s);
+void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, bool split, hipStream_t s);
 // x_orig[perm[i]] = x'[i]; then r = b - A x_orig with the caller's A, and the
 // true relative residual into the states.
 void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *colidx, const double *A,
-                   size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, int variant,
-                   hipStream_t s);
+                   size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, int variant, bool split, hipStream_t s);
 
 // out[i] = in[perm[i]] (gather to the new order) and its inverse scatter;
 // the new-order side has stride vstride, the caller side 3n.

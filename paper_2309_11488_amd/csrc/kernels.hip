@@ -76,7 +76,8 @@ __device__ inline void block_sum(double (&v)[NV], double *lds) {
 // group order.  Counters are reset by their last taker.  The tree depends
 // only on the number of workgroups, so results are reproducible bit for bit.
 // Layout: part[0 .. nblk*NV) block partials, then group partials;
-// tickets[0] = top counter, tickets[1 + g] = counter of group g.
+// tickets[0] = top counter, tickets[kTicketPad * (1 + g)] = counter of
+// group g (one 128-byte line per counter, so groups do not contend).
 constexpr int kGroup = 32;
 
 template <int NV>
@@ -93,7 +94,7 @@ __device__ bool grid_reduce(double (&v)[NV], double *part, uint32_t *tickets, in
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_s_waitcnt(0);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        const uint32_t t = __hip_atomic_fetch_add(tickets + 1 + g, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t t = __hip_atomic_fetch_add(tickets + (size_t)kTicketPad * (1 + g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         glast = t == (uint32_t)(gsize - 1);
         last = 0;
     }
@@ -110,7 +111,7 @@ __device__ bool grid_reduce(double (&v)[NV], double *part, uint32_t *tickets, in
                 gs[k] = wave_sum(p);
             }
             if (lane == 0) {
-                __hip_atomic_store(tickets + 1 + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(tickets + (size_t)kTicketPad * (1 + g), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 for (int k = 0; k < NV; ++k)
                     __hip_atomic_store(gpart + (size_t)g * NV + k, gs[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -164,7 +165,7 @@ __device__ void group_reduce(double (&v)[NV], double *part, uint32_t *tickets, i
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_s_waitcnt(0);
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        const uint32_t t = __hip_atomic_fetch_add(tickets + 1 + g, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t t = __hip_atomic_fetch_add(tickets + (size_t)kTicketPad * (1 + g), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         glast = t == (uint32_t)(gsize - 1);
     }
     __syncthreads();
@@ -178,7 +179,7 @@ __device__ void group_reduce(double (&v)[NV], double *part, uint32_t *tickets, i
             gs[k] = wave_sum(p);
         }
         if (lane == 0) {
-            __hip_atomic_store(tickets + 1 + g, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(tickets + (size_t)kTicketPad * (1 + g), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             for (int k = 0; k < NV; ++k) part[(size_t)nblk * NV + (size_t)g * NV + k] = gs[k];
         }
     }
@@ -352,64 +353,164 @@ __device__ inline T row_walk(const int32_t *__restrict__ ptr, const int32_t *__r
 
 // ------------------------------------------------------------------ gather
 
-__global__ void k_gather_blocks(const double *__restrict__ A, size_t a_stride, double *__restrict__ Ap,
-                                size_t ap_stride, const int32_t *__restrict__ src, int cnt) {
+__global__ void k_gather_pairs(const double *__restrict__ A, size_t a_stride, double *__restrict__ Ap,
+                               size_t ap_stride, const int32_t *__restrict__ dst, const int32_t *__restrict__ src,
+                               int cnt) {
     const int sys = blockIdx.y;
     const size_t total = (size_t)cnt * 9;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
         const size_t p = t / 9, e = t % 9;
-        Ap[sys * ap_stride + t] = A[sys * a_stride + (size_t)src[p] * 9 + e];
+        Ap[sys * ap_stride + (size_t)dst[p] * 9 + e] = A[sys * a_stride + (size_t)src[p] * 9 + e];
     }
 }
 
 // ------------------------------------------------------------------ factor
+
+// Rows with at most kFactorMax lower and kFactorMax upper blocks keep their
+// slices in registers; longer rows work through global memory.
+constexpr int kFactorMax = 8;
+
+__device__ inline void row3_load(const double *p, double (&v)[3]) { v[0] = p[0]; v[1] = p[1]; v[2] = p[2]; }
+__device__ inline void row3_store(double *p, const double (&v)[3]) { p[0] = v[0]; p[1] = v[1]; p[2] = v[2]; }
+__device__ inline void row3_store(float *p, const double (&v)[3]) {
+    p[0] = (float)v[0]; p[1] = (float)v[1]; p[2] = (float)v[2];
+}
+// out = row (a0 a1 a2) times the 3x3 block m
+__device__ inline void row3_mul(const double (&a)[3], const double *__restrict__ m, double (&out)[3]) {
+    for (int c = 0; c < 3; ++c) out[c] = a[0] * m[c] + a[1] * m[3 + c] + a[2] * m[6 + c];
+}
 
 // Block ILU0, one level of the lower schedule.  Lane r of row i owns row r of
 // every block of block row i.  In Algorithm 2's order: for each lower block
 // (i,k), k ascending, L_ik = a_ik inv(U_kk); then a_ij -= L_ik U_kj over the
 // precomputed update list (j ascending).  Finally inv(U_ii) from the
 // adjugate; a singular or non-finite pivot is reported by its new index.
-__global__ void k_factor_level(DevSchedule d, const double *__restrict__ Ap, double *__restrict__ L,
-                               double *__restrict__ U, double *__restrict__ Dinv, int32_t *__restrict__ bad, int q0,
-                               int q1) {
+// The row's blocks come straight from the caller's matrix and are also
+// written to the reordered copy used by the SpMV, so no separate gather
+// pass reads A.
+template <bool F32>
+__global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, const double *__restrict__ A,
+                                                              size_t a_stride, double *__restrict__ Ap,
+                                                              double *__restrict__ L, double *__restrict__ U,
+                                                              double *__restrict__ Dinv, float *__restrict__ Lf,
+                                                              float *__restrict__ Uf, float *__restrict__ Df,
+                                                              int32_t *__restrict__ bad, int q0, int q1) {
     int sys, bx;
     xcd_map(sys, bx);
     const RowLane rl = row_lane<kWavesPerBlock>(bx, q0, q1);
-    const double *A = Ap + (size_t)sys * d.nnzb * 9;
+    const double *As = A + (size_t)sys * a_stride;
+    double *Aps = Ap + (size_t)sys * d.nnzb * 9;
     double *Ls = L + (size_t)sys * d.nL * 9;
     double *Us = U + (size_t)sys * d.nU * 9;
     double *Ds = Dinv + (size_t)sys * d.n * 9;
     const int r = rl.r;
-    double dr0 = 0.0, dr1 = 0.0, dr2 = 0.0;
+    double dr[3] = {0.0, 0.0, 0.0};
     int uq = 0;
     if (rl.act) {
         const int q = rl.q;
         uq = d.l2u[q];
-        for (int f = d.uptr[uq]; f < d.uptr[uq + 1]; ++f)
-            for (int c = 0; c < 3; ++c) Us[(size_t)f * 9 + 3 * r + c] = A[(size_t)d.usrc[f] * 9 + 3 * r + c];
-        const double *ad = A + (size_t)d.dsrc[uq] * 9 + 3 * r;
-        dr0 = ad[0]; dr1 = ad[1]; dr2 = ad[2];
-        const int e0 = d.lptr[q], e1 = d.lptr[q + 1];
-        for (int e = e0; e < e1; ++e)
-            for (int c = 0; c < 3; ++c) Ls[(size_t)e * 9 + 3 * r + c] = A[(size_t)d.lsrc[e] * 9 + 3 * r + c];
-        for (int e = e0; e < e1; ++e) {
-            double *le = Ls + (size_t)e * 9 + 3 * r;
-            const double a0 = le[0], a1 = le[1], a2 = le[2];
-            const double *dk = Ds + (size_t)d.ldq[e] * 9;
-            double l[3];
-            for (int c = 0; c < 3; ++c) l[c] = a0 * dk[c] + a1 * dk[3 + c] + a2 * dk[6 + c];
-            le[0] = l[0]; le[1] = l[1]; le[2] = l[2];
-            for (int u = d.upd_ptr[e]; u < d.upd_ptr[e + 1]; ++u) {
-                const int code = d.upd[2 * u], fs = d.upd[2 * u + 1];
-                const double *ukj = Us + (size_t)fs * 9;
-                double pr[3];
-                for (int c = 0; c < 3; ++c) pr[c] = l[0] * ukj[c] + l[1] * ukj[3 + c] + l[2] * ukj[6 + c];
-                const int kind = code & 3, pos = code >> 2;
-                if (kind == 1) {
-                    dr0 -= pr[0]; dr1 -= pr[1]; dr2 -= pr[2];
-                } else {
-                    double *t = (kind == 0 ? Ls : Us) + (size_t)pos * 9 + 3 * r;
-                    t[0] -= pr[0]; t[1] -= pr[1]; t[2] -= pr[2];
+        const int e0 = d.lptr[q], e1 = d.lptr[q + 1], f0 = d.uptr[uq], f1 = d.uptr[uq + 1];
+        row3_load(As + (size_t)d.dsrc_a[uq] * 9 + 3 * r, dr);
+        row3_store(Aps + (size_t)d.dsrc[uq] * 9 + 3 * r, dr);
+        if (e1 - e0 <= kFactorMax && f1 - f0 <= kFactorMax) {
+            double lv[kFactorMax][3], uv[kFactorMax][3];
+            int dq[kFactorMax];
+#pragma unroll
+            for (int t = 0; t < kFactorMax; ++t)
+                if (e0 + t < e1) {
+                    row3_load(As + (size_t)d.lsrc_a[e0 + t] * 9 + 3 * r, lv[t]);
+                    dq[t] = d.ldq[e0 + t];
+                }
+#pragma unroll
+            for (int t = 0; t < kFactorMax; ++t)
+                if (f0 + t < f1) row3_load(As + (size_t)d.usrc_a[f0 + t] * 9 + 3 * r, uv[t]);
+#pragma unroll
+            for (int t = 0; t < kFactorMax; ++t)
+                if (e0 + t < e1) row3_store(Aps + (size_t)d.lsrc[e0 + t] * 9 + 3 * r, lv[t]);
+#pragma unroll
+            for (int t = 0; t < kFactorMax; ++t)
+                if (f0 + t < f1) row3_store(Aps + (size_t)d.usrc[f0 + t] * 9 + 3 * r, uv[t]);
+#pragma unroll
+            for (int t = 0; t < kFactorMax; ++t) {
+                if (e0 + t >= e1) continue;
+                double l[3];
+                row3_mul(lv[t], Ds + (size_t)dq[t] * 9, l);
+                lv[t][0] = l[0]; lv[t][1] = l[1]; lv[t][2] = l[2];
+                const int u1 = d.upd_ptr[e0 + t + 1];
+                for (int u = d.upd_ptr[e0 + t]; u < u1; ++u) {
+                    const int code = d.upd[2 * u], fs = d.upd[2 * u + 1];
+                    double pr[3];
+                    row3_mul(l, Us + (size_t)fs * 9, pr);
+                    const int kind = code & 3, pos = code >> 2;
+                    if (kind == 1) {
+                        dr[0] -= pr[0]; dr[1] -= pr[1]; dr[2] -= pr[2];
+                    } else if (kind == 0) {
+#pragma unroll
+                        for (int j = 0; j < kFactorMax; ++j)
+                            if (j == pos - e0) { lv[j][0] -= pr[0]; lv[j][1] -= pr[1]; lv[j][2] -= pr[2]; }
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < kFactorMax; ++j)
+                            if (j == pos - f0) { uv[j][0] -= pr[0]; uv[j][1] -= pr[1]; uv[j][2] -= pr[2]; }
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < kFactorMax; ++t)
+                if (e0 + t < e1) {
+                    // later levels never read L: with FP32 factors only the FP32 copy is kept
+                    if (F32) row3_store(Lf + ((size_t)sys * d.nL + e0 + t) * 9 + 3 * r, lv[t]);
+                    else row3_store(Ls + (size_t)(e0 + t) * 9 + 3 * r, lv[t]);
+                }
+#pragma unroll
+            for (int t = 0; t < kFactorMax; ++t)
+                if (f0 + t < f1) {
+                    row3_store(Us + (size_t)(f0 + t) * 9 + 3 * r, uv[t]);
+                    if (F32) row3_store(Uf + ((size_t)sys * d.nU + f0 + t) * 9 + 3 * r, uv[t]);
+                }
+        } else {
+            // long rows: the same steps on the row's blocks in global memory
+            for (int f = f0; f < f1; ++f) {
+                double a[3];
+                row3_load(As + (size_t)d.usrc_a[f] * 9 + 3 * r, a);
+                row3_store(Aps + (size_t)d.usrc[f] * 9 + 3 * r, a);
+                row3_store(Us + (size_t)f * 9 + 3 * r, a);
+            }
+            for (int e = e0; e < e1; ++e) {
+                double a[3];
+                row3_load(As + (size_t)d.lsrc_a[e] * 9 + 3 * r, a);
+                row3_store(Aps + (size_t)d.lsrc[e] * 9 + 3 * r, a);
+                row3_store(Ls + (size_t)e * 9 + 3 * r, a);
+            }
+            for (int e = e0; e < e1; ++e) {
+                double *le = Ls + (size_t)e * 9 + 3 * r;
+                double a[3], l[3];
+                row3_load(le, a);
+                row3_mul(a, Ds + (size_t)d.ldq[e] * 9, l);
+                row3_store(le, l);
+                for (int u = d.upd_ptr[e]; u < d.upd_ptr[e + 1]; ++u) {
+                    const int code = d.upd[2 * u], fs = d.upd[2 * u + 1];
+                    double pr[3];
+                    row3_mul(l, Us + (size_t)fs * 9, pr);
+                    const int kind = code & 3, pos = code >> 2;
+                    if (kind == 1) {
+                        dr[0] -= pr[0]; dr[1] -= pr[1]; dr[2] -= pr[2];
+                    } else {
+                        double *t = (kind == 0 ? Ls : Us) + (size_t)pos * 9 + 3 * r;
+                        t[0] -= pr[0]; t[1] -= pr[1]; t[2] -= pr[2];
+                    }
+                }
+            }
+            if (F32) {
+                for (int e = e0; e < e1; ++e) {
+                    double a[3];
+                    row3_load(Ls + (size_t)e * 9 + 3 * r, a);
+                    row3_store(Lf + ((size_t)sys * d.nL + e) * 9 + 3 * r, a);
+                }
+                for (int f = f0; f < f1; ++f) {
+                    double a[3];
+                    row3_load(Us + (size_t)f * 9 + 3 * r, a);
+                    row3_store(Uf + ((size_t)sys * d.nU + f) * 9 + 3 * r, a);
                 }
             }
         }
@@ -417,9 +518,9 @@ __global__ void k_factor_level(DevSchedule d, const double *__restrict__ Ap, dou
     // gather the three rows of U_ii from the row's lanes
     double a[9];
     for (int rr = 0; rr < 3; ++rr) {
-        a[3 * rr + 0] = __shfl(dr0, rl.base + rr, 64);
-        a[3 * rr + 1] = __shfl(dr1, rl.base + rr, 64);
-        a[3 * rr + 2] = __shfl(dr2, rl.base + rr, 64);
+        a[3 * rr + 0] = __shfl(dr[0], rl.base + rr, 64);
+        a[3 * rr + 1] = __shfl(dr[1], rl.base + rr, 64);
+        a[3 * rr + 2] = __shfl(dr[2], rl.base + rr, 64);
     }
     if (!rl.act) return;
     const double c00 = a[4] * a[8] - a[5] * a[7];
@@ -430,14 +531,9 @@ __global__ void k_factor_level(DevSchedule d, const double *__restrict__ Ap, dou
     if (r == 0) { inv[0] = c00 / det; inv[1] = (a[2] * a[7] - a[1] * a[8]) / det; inv[2] = (a[1] * a[5] - a[2] * a[4]) / det; }
     else if (r == 1) { inv[0] = c01 / det; inv[1] = (a[0] * a[8] - a[2] * a[6]) / det; inv[2] = (a[2] * a[3] - a[0] * a[5]) / det; }
     else { inv[0] = c02 / det; inv[1] = (a[1] * a[6] - a[0] * a[7]) / det; inv[2] = (a[0] * a[4] - a[1] * a[3]) / det; }
-    double *dq = Ds + (size_t)uq * 9 + 3 * r;
-    dq[0] = inv[0]; dq[1] = inv[1]; dq[2] = inv[2];
+    row3_store(Ds + (size_t)uq * 9 + 3 * r, inv);
+    if (F32) row3_store(Df + ((size_t)sys * d.n + uq) * 9 + 3 * r, inv);
     if (r == 0 && (det == 0.0 || !finite(det))) atomicMin(bad + sys, d.lrows[rl.q]);
-}
-
-__global__ void k_to_fp32(const double *__restrict__ src, float *__restrict__ dst, size_t count) {
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (size_t)gridDim.x * blockDim.x)
-        dst[t] = (float)src[t];
 }
 
 // ------------------------------------------------------------------ sweeps
@@ -677,7 +773,7 @@ __global__ void __launch_bounds__(64 * W) k_spmv(int n, const int32_t *__restric
                                                       const double *__restrict__ w1, const double *__restrict__ w2,
                                                       double *__restrict__ part, size_t part_stride,
                                                       uint32_t *__restrict__ tk, size_t tk_stride,
-                                                      SysState *__restrict__ st) {
+                                                      SysState *__restrict__ st, int split) {
     int sys, bx;
     xcd_map(sys, bx);
     if (MODE != SPMV_PLAIN && MODE != SPMV_TRUE && st[sys].phase != PH_RUN) return;
@@ -693,22 +789,36 @@ __global__ void __launch_bounds__(64 * W) k_spmv(int n, const int32_t *__restric
     for (int t = t0; t < t1; ++t) {
         const RowLane rl = row_lane<W>(t, 0, n);
         const int qb0 = t * R, qb1 = min(qb0 + R, n);
-        const double acc = row_walk<W, STAGE, kSpmvCapPerWave, false>(ptr, col, As, qb0, qb1, rl, x + vo, 0.0);
         const size_t k = vo + 3 * (size_t)rl.q + rl.r;
+        // the dot-product operand is loaded before the row walk, so its
+        // latency overlaps the walk's
+        const double w = (MODE != SPMV_PLAIN && rl.act) ? w1[k] : 0.0;
+        const double acc = row_walk<W, STAGE, kSpmvCapPerWave, false>(ptr, col, As, qb0, qb1, rl, x + vo, 0.0);
         if (!rl.act) continue;
         if (MODE == SPMV_PLAIN) {
             y[k] = acc;
         } else if (MODE == SPMV_V || MODE == SPMV_T) {
             y[k] = acc;
-            v[0] += w1[k] * acc;
+            v[0] += w * acc;
             v[1] += acc * acc;
         } else {  // SPMV_TRUE: w1 = b
-            const double res = w1[k] - acc;
+            const double res = w - acc;
             v[0] += res * res;
-            v[1] += w1[k] * w1[k];
+            v[1] += w * w;
         }
     }
     if (MODE == SPMV_PLAIN) return;
+    if (split) {
+        // one partial per wave (no workgroup barrier); k_spmv_total adds
+        // them after the kernel boundary
+        const double a = wave_sum(v[0]), b = wave_sum(v[1]);
+        if ((threadIdx.x & 63) == 0) {
+            double *pp = part + sys * part_stride + ((size_t)bx * W + (threadIdx.x >> 6)) * 2;
+            pp[0] = a;
+            pp[1] = b;
+        }
+        return;
+    }
     if (MODE == SPMV_V || MODE == SPMV_T) {
         // group sums of (rhat, v) or of (t, s) and (t, t); the next kernel
         // adds the group sums (kernel boundary: no serial tail here)
@@ -748,6 +858,26 @@ __device__ inline void sum_partials(const double *__restrict__ p, int nblk, doub
         for (int k = 0; k < NV; ++k) tot[k] = acc[k];
     __syncthreads();
     for (int k = 0; k < NV; ++k) out[k] = tot[k];
+}
+
+// The SpMV's dot products in split mode: one workgroup per system adds the
+// nblk wave partials (fixed order) and stores the totals right after them,
+// where the consumers read them, or the true residual.
+template <int MODE>
+__global__ void __launch_bounds__(kTotalThreads) k_spmv_total(double *__restrict__ part, size_t part_stride, int nblk,
+                                                              SysState *__restrict__ st) {
+    const int sys = blockIdx.y;
+    if (MODE != SPMV_TRUE && st[sys].phase != PH_RUN) return;
+    double *p = part + sys * part_stride;
+    double tot[2];
+    sum_partials<2>(p, nblk, tot);
+    if (threadIdx.x != 0) return;
+    if (MODE == SPMV_TRUE) {
+        st[sys].true_res = tot[1] > 0.0 ? sqrt(tot[0]) / sqrt(tot[1]) : 0.0;
+    } else {
+        p[2 * (size_t)nblk] = tot[0];
+        p[2 * (size_t)nblk + 1] = tot[1];
+    }
 }
 
 // Vector kernels: each thread handles kVecItems entries of a 1024-entry
@@ -796,13 +926,12 @@ __global__ void __launch_bounds__(kVecThreads) k_setup(int n, const int32_t *__r
 
 // alpha = rho / (rhat, v) from the partials of v = A phat; s = r - alpha v,
 // ||s||; half-step test.
-__global__ void __launch_bounds__(kVecThreads) k_s_update(Krylov k, int spmv_blocks) {
+__global__ void __launch_bounds__(kVecThreads) k_s_update(Krylov k, int sums_at, int sums) {
     const int sys = blockIdx.y, bx = blockIdx.x;
     SysState &S = k.st[sys];
     if (S.phase != PH_RUN) return;
     double rvv[2];
-    sum_partials<2>(k.spart + sys * k.spart_stride + 2 * (size_t)spmv_blocks, (spmv_blocks + kGroup - 1) / kGroup,
-                    rvv);
+    sum_partials<2>(k.spart + sys * k.spart_stride + sums_at, sums, rvv);
     const double rv = rvv[0];
     if (!finite(rv) || rv == 0.0) {
         if (bx == 0 && threadIdx.x == 0) {
@@ -839,7 +968,7 @@ __global__ void __launch_bounds__(kVecThreads) k_s_update(Krylov k, int spmv_blo
 // Full step: x += alpha phat + omega shat, r = s - omega t, ||r||, (rhat, r),
 // full-step test, next rho and beta.  After a half-step stop (or an omega
 // breakdown) only x += alpha phat.
-__global__ void __launch_bounds__(kVecThreads) k_xr_update(Krylov k, int spmv_blocks) {
+__global__ void __launch_bounds__(kVecThreads) k_xr_update(Krylov k, int sums_at, int sums) {
     const int sys = blockIdx.y, bx = blockIdx.x;
     SysState &S = k.st[sys];
     int phase = S.phase;
@@ -850,8 +979,7 @@ __global__ void __launch_bounds__(kVecThreads) k_xr_update(Krylov k, int spmv_bl
     if (phase == PH_RUN) {
         // omega = (t, s) / (t, t) from the partials of t = A shat
         double tv[2];
-        sum_partials<2>(k.spart + sys * k.spart_stride + 2 * (size_t)spmv_blocks,
-                        (spmv_blocks + kGroup - 1) / kGroup, tv);
+        sum_partials<2>(k.spart + sys * k.spart_stride + sums_at, sums, tv);
         const double ts = tv[0], tt = tv[1];
         if (!finite(ts) || !finite(tt) || tt == 0.0) {
             if (bx == 0 && threadIdx.x == 0) {
@@ -966,21 +1094,22 @@ static int copy_blocks(size_t m) {
     return (int)g;
 }
 
-void launch_gather_blocks(const double *A, size_t a_stride, double *Ap, size_t ap_stride, const int32_t *src, int cnt,
-                          int nsys, hipStream_t s) {
+void launch_gather_pairs(const double *A, size_t a_stride, double *Ap, size_t ap_stride, const int32_t *dst,
+                         const int32_t *src, int cnt, int nsys, hipStream_t s) {
     if (cnt <= 0 || nsys <= 0) return;
-    k_gather_blocks<<<dim3(copy_blocks((size_t)cnt * 9), nsys), 256, 0, s>>>(A, a_stride, Ap, ap_stride, src, cnt);
+    k_gather_pairs<<<dim3(copy_blocks((size_t)cnt * 9), nsys), 256, 0, s>>>(A, a_stride, Ap, ap_stride, dst, src,
+                                                                             cnt);
 }
 
-void launch_factor_level(const DevSchedule &d, const double *Ap, double *L, double *U, double *Dinv, int32_t *bad,
-                         int q0, int q1, int nsys, hipStream_t s) {
+void launch_factor_level(const DevSchedule &d, const double *A, size_t a_stride, double *Ap, double *L, double *U,
+                         double *Dinv, float *Lf, float *Uf, float *Df, int32_t *bad, int q0, int q1, int nsys,
+                         hipStream_t s) {
     if (q1 <= q0 || nsys <= 0) return;
-    k_factor_level<<<dim3(row_blocks(q1 - q0), nsys), kRowThreads, 0, s>>>(d, Ap, L, U, Dinv, bad, q0, q1);
-}
-
-void launch_to_fp32(const double *src, float *dst, size_t count, hipStream_t s) {
-    if (count == 0) return;
-    k_to_fp32<<<copy_blocks(count), 256, 0, s>>>(src, dst, count);
+    const dim3 g(row_blocks(q1 - q0), nsys);
+    if (Lf)
+        k_factor_level<true><<<g, kRowThreads, 0, s>>>(d, A, a_stride, Ap, L, U, Dinv, Lf, Uf, Df, bad, q0, q1);
+    else
+        k_factor_level<false><<<g, kRowThreads, 0, s>>>(d, A, a_stride, Ap, L, U, Dinv, Lf, Uf, Df, bad, q0, q1);
 }
 
 template <typename T>
@@ -1062,20 +1191,24 @@ template void launch_usweep_tiles<float>(const DevSchedule &, const float *, siz
 template <int MODE>
 static void spmv_any(int variant, int n, const int32_t *ptr, const int32_t *col, const double *A, size_t a_stride,
                      const double *x, double *y, size_t vstride, const double *w1, double *part, size_t part_stride,
-                     uint32_t *tk, size_t tk_stride, SysState *st, int nsys, hipStream_t s) {
+                     uint32_t *tk, size_t tk_stride, SysState *st, int nsys, bool split, hipStream_t s) {
+    int waves = 1;
     with_variant(variant, [&](auto W, auto ST) {
         constexpr int w = decltype(W)::value;
         constexpr bool staged = decltype(ST)::value;
+        waves = spmv_grid(n, w) * w;
         k_spmv<MODE, w, staged><<<dim3(spmv_grid(n, w), nsys), 64 * w, 0, s>>>(
-            n, ptr, col, A, a_stride, x, y, vstride, w1, nullptr, part, part_stride, tk, tk_stride, st);
+            n, ptr, col, A, a_stride, x, y, vstride, w1, nullptr, part, part_stride, tk, tk_stride, st, split ? 1 : 0);
     });
+    if (MODE != SPMV_PLAIN && split)
+        k_spmv_total<MODE><<<dim3(1, nsys), kTotalThreads, 0, s>>>(part, part_stride, waves, st);
 }
 
 void launch_spmv(int n, const int32_t *ptr, const int32_t *col, const double *A, size_t a_stride, const double *x,
                  double *y, size_t vstride, int nsys, int variant, hipStream_t s) {
     if (n <= 0 || nsys <= 0) return;
     spmv_any<SPMV_PLAIN>(variant, n, ptr, col, A, a_stride, x, y, vstride, nullptr, nullptr, 0, nullptr, 0, nullptr,
-                         nsys, s);
+                         nsys, false, s);
 }
 
 void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad, double reduction, int max_iter,
@@ -1084,23 +1217,25 @@ void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad
 }
 
 void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
-                   hipStream_t s) {
+                   bool split, hipStream_t s) {
     spmv_any<SPMV_V>(variant, d.n, d.prow, d.pcol, Ap, a_stride, k.phat, k.v, k.vstride, k.rhat, k.spart,
-                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, s);
+                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, s);
 }
 
-void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, hipStream_t s) {
-    k_s_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(k, spmv_grid(n, variant_waves(spmv_variant)));
+void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, bool split, hipStream_t s) {
+    const SpmvSums at = spmv_sums(n, variant_waves(spmv_variant), split);
+    k_s_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(k, at.offset, at.count);
 }
 
 void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
-                   hipStream_t s) {
+                   bool split, hipStream_t s) {
     spmv_any<SPMV_T>(variant, d.n, d.prow, d.pcol, Ap, a_stride, k.shat, k.t, k.vstride, k.s, k.spart,
-                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, s);
+                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, s);
 }
 
-void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, hipStream_t s) {
-    k_xr_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(k, spmv_grid(n, variant_waves(spmv_variant)));
+void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, bool split, hipStream_t s) {
+    const SpmvSums at = spmv_sums(n, variant_waves(spmv_variant), split);
+    k_xr_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(k, at.offset, at.count);
 }
 
 void launch_permute_vec(const int32_t *perm, const double *in, double *out, int n, size_t vstride, int nsys,
@@ -1112,11 +1247,11 @@ void launch_permute_vec(const int32_t *perm, const double *in, double *out, int 
 
 void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *colidx, const double *A,
                    size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, int variant,
-                   hipStream_t s) {
+                   bool split, hipStream_t s) {
     if (d.n <= 0 || nsys <= 0) return;
     launch_permute_vec(d.perm, k.x, x_orig, d.n, k.vstride, nsys, true, s);
     spmv_any<SPMV_TRUE>(variant, d.n, rowptr, colidx, A, a_stride, x_orig, nullptr, 3 * (size_t)d.n, b_orig, k.part,
-                        k.part_stride, k.tickets, k.ticket_stride, k.st, nsys, s);
+                        k.part_stride, k.tickets, k.ticket_stride, k.st, nsys, split, s);
 }
 
 }  // namespace rs

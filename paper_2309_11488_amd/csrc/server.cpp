@@ -61,7 +61,7 @@ struct Pattern {
     std::vector<Instance *> inst;   // resident instances and those being created
     bool tuned = false;             // a tuner ran or runs; `opts` valid once opts_version > 0
     int opts_version = 0;
-    int32_t opts[4] = {};           // spmv variant, sweep variant, sweep tiles, sweep grid
+    int32_t opts[5] = {};           // spmv variant, sweep variant, sweep tiles, sweep grid, reduce split
 };
 
 struct Instance {
@@ -239,12 +239,13 @@ static int create_instance(rs_server *S, Slot *sl, Instance *I) {
     return st;
 }
 
-static void apply_opts(Instance *I, const int32_t (&o)[4]) {
+static void apply_opts(Instance *I, const int32_t (&o)[5]) {
     (void)bcsr_set_option(I->A, RS_OPT_SPMV_VARIANT, o[0]);
     (void)ilu0_set_option(I->M, RS_OPT_SPMV_VARIANT, o[0]);
     (void)ilu0_set_option(I->M, RS_OPT_SWEEP_VARIANT, o[1]);
     (void)ilu0_set_option(I->M, RS_OPT_SWEEP_TILES, o[2]);
     (void)ilu0_set_option(I->M, RS_OPT_SWEEP_GRID, o[3]);
+    (void)ilu0_set_option(I->M, RS_OPT_REDUCE_SPLIT, o[4]);
 }
 
 static void slot_main(rs_server *S, Slot *sl) {
@@ -284,7 +285,7 @@ static void slot_main(rs_server *S, Slot *sl) {
             }
             S->cv_ready.notify_all();
         }
-        int32_t opts[4];
+        int32_t opts[5];
         int version = 0;
         {
             std::lock_guard<std::mutex> lk(S->mu);
@@ -323,6 +324,7 @@ static void slot_main(rs_server *S, Slot *sl) {
                 P->opts[1] = tr.sweep_variant;
                 P->opts[2] = tr.sweep_tiles;
                 P->opts[3] = tr.sweep_grid;
+                P->opts[4] = tr.reduce_split;
                 I->opts_version = ++P->opts_version;
             } else if (hard_error(ts)) {
                 st = ts;

@@ -22,3 +22,4 @@ from .grids import (  # noqa: F401
     serving_classes,
     CONFIGS,
 )
+from .wells import Wells, make_wells  # noqa: F401

@@ -48,6 +48,7 @@ class GridSystem:
     trans: np.ndarray
     shape: tuple
     name: str = ""
+    cell_row: np.ndarray | None = None   # grid cell (i fastest) -> block row, -1 if inactive
 
     @property
     def nnzb(self) -> int:
@@ -105,7 +106,7 @@ def _pattern(nx, ny, nz, rng, active_frac, nnc_frac):
     keep = active[cu] & active[cv]
     u = cell2row[cu[keep]]
     v = cell2row[cv[keep]]
-    return n, u, v
+    return n, u, v, cell2row
 
 
 def _assemble(n, u, v, k, a, cmat, dpert):
@@ -140,7 +141,7 @@ def _assemble(n, u, v, k, a, cmat, dpert):
 
 def _one(nx, ny, nz, sigma, active_frac, nnc_frac, seed, n_rhs):
     rng = np.random.Generator(np.random.PCG64(seed))
-    n, u, v = _pattern(nx, ny, nz, rng, active_frac, nnc_frac)
+    n, u, v, cell2row = _pattern(nx, ny, nz, rng, active_frac, nnc_frac)
     k = np.exp(sigma * rng.standard_normal(n))
     a = rng.uniform(0.5, 1.5, n)
     if nnc_frac > 0.0:
@@ -154,16 +155,16 @@ def _one(nx, ny, nz, sigma, active_frac, nnc_frac, seed, n_rhs):
     dpert = 0.1 * rng.uniform(-1.0, 1.0, size=(n, 3, 3))
     rowptr, colidx, vals, trans = _assemble(n, u, v, k, a, cmat, dpert)
     b = rng.standard_normal((n_rhs, n, 3))
-    return n, rowptr, colidx, vals, b, trans
+    return n, rowptr, colidx, vals, b, trans, cell2row
 
 
 def make_grid_system(nx: int, ny: int, nz: int, *, sigma: float = 1.0,
                      active_frac: float | None = None, nnc_frac: float = 0.0,
                      seed: int = 0, n_rhs: int = 1, name: str = "") -> GridSystem:
     """One system on an ``nx x ny x nz`` grid (see the module recipe)."""
-    n, rowptr, colidx, vals, b, trans = _one(nx, ny, nz, sigma, active_frac, nnc_frac, seed, n_rhs)
+    n, rowptr, colidx, vals, b, trans, cell2row = _one(nx, ny, nz, sigma, active_frac, nnc_frac, seed, n_rhs)
     return GridSystem(n=n, rowptr=rowptr, colidx=colidx, vals=vals[None], b=b[None],
-                      trans=trans, shape=(nx, ny, nz), name=name)
+                      trans=trans, shape=(nx, ny, nz), name=name, cell_row=cell2row)
 
 
 def make_ensemble(nx: int, ny: int, nz: int, seeds, *, sigma: float = 1.0,
@@ -177,14 +178,14 @@ def make_ensemble(nx: int, ny: int, nz: int, seeds, *, sigma: float = 1.0,
     vals, bs = [], []
     first = None
     for s in seeds:
-        n, rowptr, colidx, v, b, trans = _one(nx, ny, nz, sigma, None, 0.0, s, n_rhs)
+        n, rowptr, colidx, v, b, trans, cell2row = _one(nx, ny, nz, sigma, None, 0.0, s, n_rhs)
         if first is None:
-            first = (n, rowptr, colidx, trans)
+            first = (n, rowptr, colidx, trans, cell2row)
         vals.append(v)
         bs.append(b)
-    n, rowptr, colidx, trans = first
+    n, rowptr, colidx, trans, cell2row = first
     return GridSystem(n=n, rowptr=rowptr, colidx=colidx, vals=np.stack(vals), b=np.stack(bs),
-                      trans=trans, shape=(nx, ny, nz), name=name)
+                      trans=trans, shape=(nx, ny, nz), name=name, cell_row=cell2row)
 
 
 # The five workload recipes: grid, permeability spread, mask, NNC fraction,

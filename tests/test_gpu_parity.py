@@ -275,6 +275,7 @@ def test_autotune_picks_valid_config_and_caches(solver_of, tmp_path, monkeypatch
     assert r["from_cache"] == 0 and r["candidates"] >= 10 and r["us_per_solve"] > 0
     assert rs.ilu0_get_option(M, rs.OPT_SPMV_VARIANT) == r["spmv_variant"]
     assert rs.ilu0_get_option(M, rs.OPT_SWEEP_TILES) == r["sweep_tiles"]
+    assert rs.ilu0_get_option(M, rs.OPT_REDUCE_SPLIT) == r["reduce_split"]
     x, st, info = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-8)
     for k in range(3):
         xo, _ = oracle.solve(s.rowptr, s.colidx, s.vals[k], s.b[k, 0], ordering=rs.ORDER_GRAPH_COLOUR,
@@ -284,6 +285,7 @@ def test_autotune_picks_valid_config_and_caches(solver_of, tmp_path, monkeypatch
     rs.ilu0_set_option(M, rs.OPT_SPMV_VARIANT, (r["spmv_variant"] + 1) % rs.N_ROW_VARIANTS)
     r2 = rs.ilu0_autotune(M, A, s.b[:, 0], reduction=1e-2, reps=1)
     assert r2["from_cache"] == 1 and r2["spmv_variant"] == r["spmv_variant"]
+    assert r2["reduce_split"] == r["reduce_split"]
     assert rs.ilu0_get_option(M, rs.OPT_SPMV_VARIANT) == r["spmv_variant"]
 
 
@@ -539,6 +541,26 @@ def test_jacobi_mixed_precision_and_fewer_levels():
     finally:
         rs.ilu0_destroy(M)
         rs.bcsr_destroy(A)
+
+
+@pytest.mark.parametrize("variant", [0, 2, 5])
+def test_reduce_split_modes_match_the_oracle(solver_of, variant):
+    """Both ways of adding the SpMVs' dot products give oracle-matching,
+    reproducible solutions."""
+    s = CASES["nnc"]
+    A, M, st, _ = solver_of(s, rs.ORDER_GRAPH_COLOUR)
+    xo, oinfo = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=rs.ORDER_GRAPH_COLOUR,
+                             reduction=1e-10)
+    rs.ilu0_set_option(M, rs.OPT_SPMV_VARIANT, variant)
+    for split in (0, 1):
+        rs.ilu0_set_option(M, rs.OPT_REDUCE_SPLIT, split)
+        assert rs.ilu0_get_option(M, rs.OPT_REDUCE_SPLIT) == split
+        x1, st1, i1 = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-10)
+        x2, st2, i2 = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-10)
+        assert st1 == st2 == rs.OK and np.array_equal(x1, x2)
+        assert np.linalg.norm(x1[0] - xo) <= 1e-8 * np.linalg.norm(xo)
+        assert i1[0]["half_steps"] == oinfo["half_steps"]
+        assert abs(i1[0]["true_rel_residual"] - oinfo["true_rel_residual"]) <= 1e-12 + 1e-3 * oinfo["true_rel_residual"]
 
 
 def test_device_memory_path():
