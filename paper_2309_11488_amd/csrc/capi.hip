@@ -122,22 +122,36 @@ hipEvent_t prof_event() {
     return e;
 }
 
+// Records an event pair on the stream around the scope.  With `dispatch`,
+// the events are instead handed to the single kernel launch inside the scope
+// (start(), stop()), which records them itself at the kernel's start and
+// end, so the time excludes the launch.
 struct ProfScope {
     int cls;
     hipStream_t s;
     double bytes;
-    hipEvent_t a = nullptr;
-    ProfScope(int c, hipStream_t st, double b) : cls(c), s(st), bytes(b) {
+    bool dispatch;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(int c, hipStream_t st, double by, bool disp = false) : cls(c), s(st), bytes(by), dispatch(disp) {
         if ((g_prof.mask >> cls) & 1) {
             a = prof_event();
-            if (a) (void)hipEventRecord(a, s);
+            if (a && dispatch) {
+                b = prof_event();
+                if (!b) a = nullptr;
+            } else if (a) {
+                (void)hipEventRecord(a, s);
+            }
         }
     }
+    hipEvent_t start() const { return a; }
+    hipEvent_t stop() const { return b; }
     ~ProfScope() {
         if (!a) return;
-        hipEvent_t b = prof_event();
-        if (!b) return;
-        (void)hipEventRecord(b, s);
+        if (!dispatch) {
+            b = prof_event();
+            if (!b) return;
+            (void)hipEventRecord(b, s);
+        }
         g_prof.pending.push_back({cls, a, b, bytes});
     }
 };
@@ -784,8 +798,9 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
     const double spmv_bytes = B * (76 * nnzb + 4 * n + 72 * n);
     if (parts & IT_APPLY1) apply_levels<T>(M, L, U, D, nullptr, k.phat, true, k, k.st, B, s);
     if (parts & IT_SPMV_V) {
-        ProfScope ps(PC_SPMV_V, s, spmv_bytes);
-        rs::launch_spmv_v(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), s);
+        ProfScope ps(PC_SPMV_V, s, spmv_bytes, true);
+        rs::launch_spmv_v(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), s, ps.start(),
+                          ps.stop());
     }
     if (!(parts & IT_REST)) return;
     { ProfScope ps(PC_VEC, s, B * 72 * n); rs::launch_s_update(M->n, k, B, M->spmv_variant, M->split(), s); }

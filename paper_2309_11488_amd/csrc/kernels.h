@@ -155,7 +155,9 @@ void launch_spmv(int n, const int32_t *ptr, const int32_t *col, const double *A,
 // bad[sys] < n marks a system whose factorisation hit a singular pivot.
 void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad, double reduction, int max_iter,
                   Krylov &k, int nsys, hipStream_t s);
-void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, bool split, hipStream_t s);
+// ev0 / ev1 (optional): events recorded by the dispatch at the kernel's start and end.
+void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, bool split,
+                   hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, bool split, hipStream_t s);
 void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, bool split, hipStream_t s);
 void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, bool split, hipStream_t s);

@@ -14,6 +14,7 @@
 // order and updates the BiCGStab scalars on the device.  The number of
 // workgroups depends only on the system size, so a system gives the same bits
 // alone and inside a batch.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -333,6 +334,11 @@ __device__ inline T stage_walk(const int32_t *__restrict__ ptr, const int32_t *_
     return acc;
 }
 
+// Row kernels are compiled to keep at least this many waves per SIMD (the
+// register budget that leaves; no spills at 5) so their dependent gathers
+// have enough waves in flight.
+constexpr int kRowWavesPerEU = 5;
+
 // LDS capacity (blocks) per pass: 160 (SpMV) or 80 (sweeps) per wave.
 constexpr int kSpmvCapPerWave = 160;
 constexpr int kSweepCapPerWave = 80;
@@ -539,7 +545,7 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
 // ------------------------------------------------------------------ sweeps
 
 template <typename T, bool FUSE_P, int W, bool STAGE>
-__global__ void __launch_bounds__(64 * W) k_lsweep(DevSchedule d, const T *__restrict__ L, size_t l_stride,
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRowWavesPerEU, 8))) k_lsweep(DevSchedule d, const T *__restrict__ L, size_t l_stride,
                                                         const double *__restrict__ in, T *__restrict__ y,
                                                         size_t vstride, const double *__restrict__ rv,
                                                         const double *__restrict__ vv, double *__restrict__ pv,
@@ -569,7 +575,7 @@ __global__ void __launch_bounds__(64 * W) k_lsweep(DevSchedule d, const T *__res
 }
 
 template <typename T, int W, bool STAGE>
-__global__ void __launch_bounds__(64 * W) k_usweep(DevSchedule d, const T *__restrict__ U, size_t u_stride,
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRowWavesPerEU, 8))) k_usweep(DevSchedule d, const T *__restrict__ U, size_t u_stride,
                                                         const T *__restrict__ Dinv, size_t d_stride,
                                                         const T *__restrict__ y, double *__restrict__ z,
                                                         size_t vstride, SysState *__restrict__ st, int q0, int q1) {
@@ -766,7 +772,7 @@ enum SpmvMode { SPMV_PLAIN = 0, SPMV_V = 1, SPMV_T = 2, SPMV_TRUE = 3 };
 //   SPMV_T:    t = A shat, reduce (t, s) and (t, t), omega = (t, s) / (t, t)
 //   SPMV_TRUE: reduce ||b - A x||^2 and ||b||^2, true relative residual
 template <int MODE, int W, bool STAGE>
-__global__ void __launch_bounds__(64 * W) k_spmv(int n, const int32_t *__restrict__ ptr,
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRowWavesPerEU, 8))) k_spmv(int n, const int32_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ col, const double *__restrict__ A,
                                                       size_t a_stride, const double *__restrict__ x,
                                                       double *__restrict__ y, size_t vstride,
@@ -776,7 +782,12 @@ __global__ void __launch_bounds__(64 * W) k_spmv(int n, const int32_t *__restric
                                                       SysState *__restrict__ st, int split) {
     int sys, bx;
     xcd_map(sys, bx);
-    if (MODE != SPMV_PLAIN && MODE != SPMV_TRUE && st[sys].phase != PH_RUN) return;
+    // whether the system still iterates.  t = A shat often runs after a
+    // half-step stop, so it tests first; v = A phat (which runs whenever its
+    // iteration starts) tests once the row walk's loads are in flight, which
+    // hides the latency of the test; a finished system's launch stores nothing
+    if (MODE == SPMV_T && st[sys].phase != PH_RUN) return;
+    const bool run = MODE != SPMV_V || st[sys].phase == PH_RUN;
     // workgroup bx walks row tiles [bx * per, (bx + 1) * per); per = 1 with
     // one workgroup per tile
     constexpr int R = W * kRowsPerWave;
@@ -794,6 +805,8 @@ __global__ void __launch_bounds__(64 * W) k_spmv(int n, const int32_t *__restric
         // latency overlaps the walk's
         const double w = (MODE != SPMV_PLAIN && rl.act) ? w1[k] : 0.0;
         const double acc = row_walk<W, STAGE, kSpmvCapPerWave, false>(ptr, col, As, qb0, qb1, rl, x + vo, 0.0);
+        asm volatile("" ::"v"(acc));   // the walk completes before the phase test below
+        if (!run) return;
         if (!rl.act) continue;
         if (MODE == SPMV_PLAIN) {
             y[k] = acc;
@@ -1188,17 +1201,26 @@ template void launch_usweep_tiles<float>(const DevSchedule &, const float *, siz
                                          const float *, double *, size_t, SysState *, int32_t *, SweepCtr *, int,
                                          int, hipStream_t);
 
+// ev0 / ev1 (optional): events the dispatch itself records at the SpMV
+// kernel's start and end (kernel time only, no launch overhead).
 template <int MODE>
 static void spmv_any(int variant, int n, const int32_t *ptr, const int32_t *col, const double *A, size_t a_stride,
                      const double *x, double *y, size_t vstride, const double *w1, double *part, size_t part_stride,
-                     uint32_t *tk, size_t tk_stride, SysState *st, int nsys, bool split, hipStream_t s) {
+                     uint32_t *tk, size_t tk_stride, SysState *st, int nsys, bool split, hipStream_t s,
+                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     int waves = 1;
     with_variant(variant, [&](auto W, auto ST) {
         constexpr int w = decltype(W)::value;
         constexpr bool staged = decltype(ST)::value;
         waves = spmv_grid(n, w) * w;
-        k_spmv<MODE, w, staged><<<dim3(spmv_grid(n, w), nsys), 64 * w, 0, s>>>(
-            n, ptr, col, A, a_stride, x, y, vstride, w1, nullptr, part, part_stride, tk, tk_stride, st, split ? 1 : 0);
+        const dim3 g(spmv_grid(n, w), nsys), b(64 * w);
+        if (ev0)
+            hipExtLaunchKernelGGL(k_spmv<MODE, w, staged>, g, b, 0, s, ev0, ev1, 0, n, ptr, col, A, a_stride, x, y,
+                                  vstride, w1, (const double *)nullptr, part, part_stride, tk, tk_stride, st,
+                                  split ? 1 : 0);
+        else
+            k_spmv<MODE, w, staged><<<g, b, 0, s>>>(n, ptr, col, A, a_stride, x, y, vstride, w1, nullptr, part,
+                                                    part_stride, tk, tk_stride, st, split ? 1 : 0);
     });
     if (MODE != SPMV_PLAIN && split)
         k_spmv_total<MODE><<<dim3(1, nsys), kTotalThreads, 0, s>>>(part, part_stride, waves, st);
@@ -1217,9 +1239,9 @@ void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad
 }
 
 void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
-                   bool split, hipStream_t s) {
+                   bool split, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     spmv_any<SPMV_V>(variant, d.n, d.prow, d.pcol, Ap, a_stride, k.phat, k.v, k.vstride, k.rhat, k.spart,
-                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, s);
+                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, s, ev0, ev1);
 }
 
 void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, bool split, hipStream_t s) {
