@@ -82,6 +82,10 @@ def lib():
         L.orc_solve_jacobi.argtypes = [ci, _I32P, _I32P, _F64P, vp, _F64P, ci, ci, cd, ci, _F64P,
                                        ct.POINTER(Info), _I32P, ct.POINTER(ci), ct.POINTER(ci)]
         L.orc_jacobi_matrix.argtypes = [ci, _I32P, _I32P, _F64P, _I32P, _I32P, _I32P, _F64P]
+        L.orc_wells_apply.argtypes = [ci, _I32P, _I32P, _F64P, _F64P, _F64P, _F64P, _F64P]
+        L.orc_wells_apply.restype = None
+        L.orc_solve_wells.argtypes = [ci, _I32P, _I32P, _F64P, vp, ci, vp, vp, vp, vp, vp, _F64P, ci, ci, cd, ci,
+                                      _F64P, ct.POINTER(Info), _I32P, ct.POINTER(ci), ct.POINTER(ci)]
         _lib = L
     return _lib
 
@@ -179,6 +183,15 @@ def inv3(a):
     return ok, out
 
 
+def wells_apply(well_ptr, perf_row, B, C, Dinv, x, y):
+    """y -= sum over wells of C^T D^-1 B x (Algorithm 5); returns the new y."""
+    y = _f64(y).copy()
+    n = y.reshape(-1, 3).shape[0]
+    lib().orc_wells_apply(len(well_ptr) - 1, _i32(well_ptr), _i32(perf_row), _f64(B), _f64(C), _f64(Dinv),
+                          _f64(x).reshape(n, 3), y.reshape(n, 3))
+    return y
+
+
 def jacobi_matrix(rowptr, colidx, vals, part):
     """(rowptr', colidx', vals') of the Jacobi matrix: blocks within one partition."""
     n = len(rowptr) - 1
@@ -213,12 +226,13 @@ def bicgstab(rowptr, colidx, vals, lu, dinv, b, *, precond=PREC_ILU_F64, reducti
 
 
 def solve(rowptr, colidx, vals, b, *, ordering=ORDER_NATURAL, precond=PREC_ILU_F64, reduction=1e-2,
-          max_iter=200, part=None):
+          max_iter=200, part=None, wells=None):
     """The whole path on one system in original order.
 
-    ``part`` (n partition ids) selects the Block-Jacobi-ILU0 preconditioner.
-    Returns (x[n,3], info dict with status, half_steps, r0_norm, final_norm,
-    true_rel_residual, n_sets, bad_row, perm).
+    ``part`` (n partition ids) selects the Block-Jacobi-ILU0 preconditioner;
+    ``wells`` = (well_ptr, perf_row, B, C, Dinv) adds standard wells kept
+    separate in the operator.  Returns (x[n,3], info dict with status,
+    half_steps, r0_norm, final_norm, true_rel_residual, n_sets, bad_row, perm).
     """
     n = len(rowptr) - 1
     x = np.zeros((n, 3), np.float64)
@@ -227,9 +241,15 @@ def solve(rowptr, colidx, vals, b, *, ordering=ORDER_NATURAL, precond=PREC_ILU_F
     nsets = ct.c_int(0)
     bad = ct.c_int(-1)
     part = None if part is None else _i32(part)
-    lib().orc_solve_jacobi(n, _i32(rowptr), _i32(colidx), _f64(vals), None if part is None else part.ctypes.data,
-                           _f64(b).reshape(n, 3), ordering, precond, reduction, max_iter, x, ct.byref(info), perm,
-                           ct.byref(nsets), ct.byref(bad))
+    nw, wargs = 0, [None] * 5
+    if wells is not None:
+        wp, pr, B, C, D = wells
+        keep = [_i32(wp), _i32(pr), _f64(B), _f64(C), _f64(D)]
+        nw = len(wp) - 1
+        wargs = [a.ctypes.data for a in keep]
+    lib().orc_solve_wells(n, _i32(rowptr), _i32(colidx), _f64(vals), None if part is None else part.ctypes.data, nw,
+                          *wargs, _f64(b).reshape(n, 3), ordering, precond, reduction, max_iter, x, ct.byref(info),
+                          perm, ct.byref(nsets), ct.byref(bad))
     d = info.as_dict()
     d.update(n_sets=nsets.value, bad_row=bad.value, perm=perm[:n])
     return x, d

@@ -39,6 +39,10 @@
  *     built from a "Jacobi matrix" that keeps only the blocks coupling rows
  *     of the same partition; the full matrix stays in the SpMV.  The ordering
  *     is computed on the Jacobi matrix's pattern.  The partition is an input.
+ *   - Standard wells kept separate (Section "Well Contributions",
+ *     Algorithm 5): the operator is y = A x - sum over wells of
+ *     C^T D^-1 B x; B and C hold one 4x3 block per perforated cell, D^-1 is
+ *     one 4x4 block per well.  The preconditioner is ILU0 of A alone.
  *   - Zero-diagonal check (Section "Profiling", runtime breakdown table):
  *     a missing diagonal block is a pattern error; a singular diagonal block
  *     during the decomposition is a zero pivot.
@@ -82,6 +86,10 @@ int orc_bicgstab_split(int n, const int *rowptr, const int *colidx, const double
 int orc_solve_jacobi(int n, const int *rowptr, const int *colidx, const double *vals, const int *part,
                      const double *b, int ordering, int precond_kind, double reduction, int max_iter, double *x,
                      orc_info *info, int *perm_out, int *n_sets, int *bad_row);
+int orc_solve_wells(int n, const int *rowptr, const int *colidx, const double *vals, const int *part, int n_wells,
+                    const int *well_ptr, const int *perf_row, const double *B, const double *C, const double *Dinv,
+                    const double *b, int ordering, int precond_kind, double reduction, int max_iter, double *x,
+                    orc_info *info, int *perm_out, int *n_sets, int *bad_row);
 
 /* ---------------------------------------------------------------- pattern */
 
@@ -432,6 +440,43 @@ static double dot(int m, const double *a, const double *b)
     return s;
 }
 
+/* ------------------------------------------------------------------ wells */
+
+typedef struct {
+    int n_wells;
+    const int *well_ptr;    /* perforations of well w: [well_ptr[w], well_ptr[w+1]) */
+    const int *perf_row;    /* block row of each perforation */
+    const double *B, *C;    /* 4x3 blocks, row-major, one per perforation */
+    const double *Dinv;     /* 4x4 blocks, row-major, one per well */
+} wells_t;
+
+/* Algorithm 5 for every well: t1 = B x, t2 = D^-1 t1, y -= C^T t2. */
+void orc_wells_apply(int n_wells, const int *well_ptr, const int *perf_row, const double *B, const double *C,
+                     const double *Dinv, const double *x, double *y)
+{
+    for (int w = 0; w < n_wells; ++w) {
+        double t1[4] = {0.0, 0.0, 0.0, 0.0}, t2[4];
+        for (int p = well_ptr[w]; p < well_ptr[w + 1]; ++p) {
+            const double *b = B + 12 * (size_t)p, *xc = x + 3 * (size_t)perf_row[p];
+            for (int i = 0; i < 4; ++i) t1[i] += b[3 * i] * xc[0] + b[3 * i + 1] * xc[1] + b[3 * i + 2] * xc[2];
+        }
+        const double *d = Dinv + 16 * (size_t)w;
+        for (int i = 0; i < 4; ++i) t2[i] = d[4 * i] * t1[0] + d[4 * i + 1] * t1[1] + d[4 * i + 2] * t1[2] + d[4 * i + 3] * t1[3];
+        for (int p = well_ptr[w]; p < well_ptr[w + 1]; ++p) {
+            const double *c = C + 12 * (size_t)p;
+            double *yc = y + 3 * (size_t)perf_row[p];
+            for (int j = 0; j < 3; ++j) yc[j] -= c[j] * t2[0] + c[3 + j] * t2[1] + c[6 + j] * t2[2] + c[9 + j] * t2[3];
+        }
+    }
+}
+
+static void op_apply(int n, const int *rowptr, const int *colidx, const double *vals, const wells_t *w,
+                     const double *x, double *y)
+{
+    orc_spmv(n, rowptr, colidx, vals, x, y);
+    if (w && w->n_wells > 0) orc_wells_apply(w->n_wells, w->well_ptr, w->perf_row, w->B, w->C, w->Dinv, x, y);
+}
+
 /* --------------------------------------------------------------- BiCGStab */
 
 typedef struct {
@@ -465,8 +510,9 @@ static void prec_apply(const precond *m, const double *v, double *z)
  * the test give ORC_NOT_CONVERGED with the last iterate in x.
  * trace (optional, 8 doubles per iteration): rho, (rhat,v), alpha, ||s||,
  * (t,s), (t,t), omega, ||r||. */
-static int bicgstab(int n, const int *rowptr, const int *colidx, const double *vals, const precond *m,
-                    const double *b, double reduction, int max_iter, double *x, orc_info *info, double *trace)
+static int bicgstab(int n, const int *rowptr, const int *colidx, const double *vals, const wells_t *wl,
+                    const precond *m, const double *b, double reduction, int max_iter, double *x, orc_info *info,
+                    double *trace)
 {
     size_t m3 = 3 * (size_t)n;
     size_t bytes = sizeof(double) * (m3 > 0 ? m3 : 1);
@@ -488,7 +534,7 @@ static int bicgstab(int n, const int *rowptr, const int *colidx, const double *v
         double beta = (rho / rho_old) * (alpha / omega);
         for (size_t i = 0; i < m3; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
         prec_apply(m, p, phat);
-        orc_spmv(n, rowptr, colidx, vals, phat, v);
+        op_apply(n, rowptr, colidx, vals, wl, phat, v);
         double rv = dot((int)m3, rhat, v);
         if (tr) { tr[0] = rho; tr[1] = rv; }
         if (!isfinite(rv)) { status = ORC_NON_FINITE; goto done; }
@@ -506,7 +552,7 @@ static int bicgstab(int n, const int *rowptr, const int *colidx, const double *v
             goto done;
         }
         prec_apply(m, s, shat);
-        orc_spmv(n, rowptr, colidx, vals, shat, t);
+        op_apply(n, rowptr, colidx, vals, wl, shat, t);
         double ts = dot((int)m3, t, s), tt = dot((int)m3, t, t);
         if (tr) { tr[4] = ts; tr[5] = tt; }
         if (!isfinite(ts) || !isfinite(tt)) { status = ORC_NON_FINITE; goto done; }
@@ -553,9 +599,22 @@ int orc_bicgstab(int n, const int *rowptr, const int *colidx, const double *vals
 
 /* As orc_bicgstab, with factors on their own pattern (mrow, mcol): the
  * preconditioner of a Jacobi matrix while the SpMV uses the full matrix. */
+static int bicgstab_wells(int n, const int *rowptr, const int *colidx, const double *vals, const wells_t *wells,
+                          const int *mrow, const int *mcol, const double *lu, const double *dinv, int precond_kind,
+                          const double *b, double reduction, int max_iter, double *x, orc_info *info, double *trace);
+
 int orc_bicgstab_split(int n, const int *rowptr, const int *colidx, const double *vals, const int *mrow,
                        const int *mcol, const double *lu, const double *dinv, int precond_kind, const double *b,
                        double reduction, int max_iter, double *x, orc_info *info, double *trace)
+{
+    return bicgstab_wells(n, rowptr, colidx, vals, NULL, mrow, mcol, lu, dinv, precond_kind, b, reduction, max_iter,
+                          x, info, trace);
+}
+
+/* The operator A (+ separate wells when given) with factors on (mrow, mcol). */
+static int bicgstab_wells(int n, const int *rowptr, const int *colidx, const double *vals, const wells_t *wells,
+                          const int *mrow, const int *mcol, const double *lu, const double *dinv, int precond_kind,
+                          const double *b, double reduction, int max_iter, double *x, orc_info *info, double *trace)
 {
     precond m = {precond_kind, n, mrow, mcol, lu, dinv, NULL, NULL};
     float *lu32 = NULL, *dinv32 = NULL;
@@ -568,7 +627,7 @@ int orc_bicgstab_split(int n, const int *rowptr, const int *colidx, const double
         m.lu32 = lu32;
         m.dinv32 = dinv32;
     }
-    int st = bicgstab(n, rowptr, colidx, vals, &m, b, reduction, max_iter, x, info, trace);
+    int st = bicgstab(n, rowptr, colidx, vals, wells, &m, b, reduction, max_iter, x, info, trace);
     free(lu32);
     free(dinv32);
     return st;
@@ -594,6 +653,18 @@ int orc_solve(int n, const int *rowptr, const int *colidx, const double *vals, c
 int orc_solve_jacobi(int n, const int *rowptr, const int *colidx, const double *vals, const int *part,
                      const double *b, int ordering, int precond_kind, double reduction, int max_iter, double *x,
                      orc_info *info, int *perm_out, int *n_sets, int *bad_row)
+{
+    return orc_solve_wells(n, rowptr, colidx, vals, part, 0, NULL, NULL, NULL, NULL, NULL, b, ordering, precond_kind,
+                           reduction, max_iter, x, info, perm_out, n_sets, bad_row);
+}
+
+/* As orc_solve_jacobi with n_wells standard wells kept separate (Algorithm
+ * 5) in the operator of the SpMVs and of the true residual; perf_row in
+ * A's original numbering.  The preconditioner ignores the wells. */
+int orc_solve_wells(int n, const int *rowptr, const int *colidx, const double *vals, const int *part, int n_wells,
+                    const int *well_ptr, const int *perf_row, const double *B, const double *C, const double *Dinv,
+                    const double *b, int ordering, int precond_kind, double reduction, int max_iter, double *x,
+                    orc_info *info, int *perm_out, int *n_sets, int *bad_row)
 {
     int st = orc_validate(n, rowptr, colidx, bad_row);
     memset(info, 0, sizeof *info);
@@ -638,11 +709,24 @@ int orc_solve_jacobi(int n, const int *rowptr, const int *colidx, const double *
     }
     for (int i = 0; i < n; ++i)
         for (int c = 0; c < 3; ++c) pb[3 * i + c] = b[3 * (size_t)perm[i] + c];
-    st = orc_bicgstab_split(n, prow, pcol, pvals, mrow, mcol, lu, dinv, precond_kind, pb, reduction, max_iter, px,
-                            info, NULL);
+    {
+        /* the wells in the new numbering */
+        int nperf = n_wells > 0 ? well_ptr[n_wells] : 0;
+        int *iperm = malloc(sizeof(int) * nn), *prow_w = malloc(sizeof(int) * (size_t)(nperf > 0 ? nperf : 1));
+        for (int i = 0; i < n; ++i) iperm[perm[i]] = i;
+        for (int p = 0; p < nperf; ++p) prow_w[p] = iperm[perf_row[p]];
+        wells_t wl = {n_wells, well_ptr, prow_w, B, C, Dinv};
+        st = bicgstab_wells(n, prow, pcol, pvals, n_wells > 0 ? &wl : NULL, mrow, mcol, lu, dinv, precond_kind, pb,
+                            reduction, max_iter, px, info, NULL);
+        free(iperm);
+        free(prow_w);
+    }
     for (int i = 0; i < n; ++i)
         for (int c = 0; c < 3; ++c) x[3 * (size_t)perm[i] + c] = px[3 * i + c];
-    orc_spmv(n, rowptr, colidx, vals, x, ax);
+    {
+        wells_t wl = {n_wells, well_ptr, perf_row, B, C, Dinv};
+        op_apply(n, rowptr, colidx, vals, n_wells > 0 ? &wl : NULL, x, ax);
+    }
     {
         double rr = 0.0, bb = 0.0;
         for (size_t i = 0; i < 3 * (size_t)n; ++i) {

@@ -482,3 +482,53 @@ def test_jacobi_levels_shrink_with_slabs():
     part = (np.arange(s.n) // (nx * ny * 3)).astype(np.int32)       # 4 slabs of 3 layers
     _, info = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=oracle.ORDER_LEVEL, part=part)
     assert info["n_sets"] == nx + ny + 3 - 2
+
+
+# ------------------------------------------------------------------- wells
+
+def coupled_dense(s, w, k=0):
+    """A - sum_w C_w^T D_w^-1 B_w as a dense matrix (Algorithm 4), built here from the blocks."""
+    A = to_dense(s.rowptr, s.colidx, s.vals[k])
+    for q in range(w.n_wells):
+        Bw = np.zeros((4, 3 * s.n))
+        Cw = np.zeros((4, 3 * s.n))
+        for p in range(w.well_ptr[q], w.well_ptr[q + 1]):
+            r = w.perf_row[p]
+            Bw[:, 3 * r:3 * r + 3] += w.B[k, p]
+            Cw[:, 3 * r:3 * r + 3] += w.C[k, p]
+        A -= Cw.T @ w.Dinv[k, q] @ Bw
+    return A
+
+
+def test_separate_wells_equal_wells_in_the_matrix():
+    """Algorithm 5 (wells applied after the SpMV) equals Algorithm 4 (wells folded into A)."""
+    from synth import make_wells
+    s = make_grid_system(7, 6, 5, active_frac=0.9, seed=41)
+    w = make_wells(s, 4, seed=42)
+    x = np.random.default_rng(43).standard_normal((s.n, 3))
+    y = oracle.wells_apply(w.well_ptr, w.perf_row, w.B[0], w.C[0], w.Dinv[0], x,
+                           oracle.spmv(s.rowptr, s.colidx, s.vals[0], x))
+    ref = coupled_dense(s, w) @ x.ravel()
+    assert np.abs(y.ravel() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_solve_with_wells_converges_to_the_coupled_system():
+    from synth import make_wells
+    s = make_grid_system(9, 7, 6, nnc_frac=0.03, seed=44)
+    w = make_wells(s, 5, seed=45)
+    xr = np.linalg.solve(coupled_dense(s, w), s.b[0, 0].ravel())
+    for ordering in (oracle.ORDER_NATURAL, oracle.ORDER_LEVEL, oracle.ORDER_COLOUR):
+        x, info = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=ordering, reduction=1e-12,
+                               wells=(w.well_ptr, w.perf_row, w.B[0], w.C[0], w.Dinv[0]))
+        assert info["status"] == oracle.OK and info["true_rel_residual"] <= 1e-11
+        assert np.linalg.norm(x.ravel() - xr) / np.linalg.norm(xr) < 1e-9
+
+
+def test_no_wells_is_plain():
+    s = make_grid_system(6, 5, 4, seed=46)
+    empty = (np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros((0, 4, 3)), np.zeros((0, 4, 3)),
+             np.zeros((0, 4, 4)))
+    x1, i1 = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=oracle.ORDER_LEVEL, reduction=1e-10)
+    x2, i2 = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=oracle.ORDER_LEVEL, reduction=1e-10,
+                          wells=empty)
+    assert np.array_equal(x1, x2) and i1["half_steps"] == i2["half_steps"]
