@@ -142,6 +142,24 @@ int bcsr_spmv(bcsr_t A, const double *x, double *y, int32_t first_sys, int32_t n
  * RS_INVALID_ARG). */
 int bcsr_set_option(bcsr_t A, int32_t option, int32_t value);
 
+/* bcsr_set_wells -- standard wells kept separate, Section "Well
+ * Contributions" (Algorithm 5): from now on every product with A (the
+ * solver's SpMVs, the true residual, bcsr_spmv) is y = A x - sum over wells
+ * w of C_w^T D_w^-1 B_w x.  The ILU0 preconditioner stays that of A.
+ *   n_wells          : wells (0 removes them)
+ *   well_ptr[n_wells+1], perf_row[n_perf] (host): the perforations of well w
+ *                      are [well_ptr[w], well_ptr[w+1]); perf_row gives each
+ *                      perforation's block row (n_perf = well_ptr[n_wells])
+ *   B, C (mem)       : batch * n_perf 4x3 blocks, row-major (one block row
+ *                      per well, a block per perforated cell)
+ *   Dinv (mem)       : batch * n_wells 4x4 blocks, the inverse of each well's
+ *                      diagonal block (the paper stores the inverse)
+ * Copies everything; synchronises `stream`.  Errors: RS_INVALID_ARG
+ * (well_ptr not starting at 0 or decreasing, a row out of range),
+ * RS_OUT_OF_MEMORY, RS_HIP_ERROR. */
+int bcsr_set_wells(bcsr_t A, int32_t n_wells, const int32_t *well_ptr, const int32_t *perf_row, const double *B,
+                   const double *C, const double *Dinv, int32_t mem, void *stream);
+
 /* bcsr_destroy -- free the handle (NULL is accepted). */
 int bcsr_destroy(bcsr_t A);
 

@@ -29,7 +29,7 @@ OPT_SPMV_VARIANT, OPT_SWEEP_VARIANT, OPT_REDUCE_SPLIT = 5, 6, 7
 N_ROW_VARIANTS = 6
 
 EXPORTS = (
-    "bcsr_create", "bcsr_set_values", "bcsr_get_dims", "bcsr_spmv", "bcsr_set_option", "bcsr_destroy", "ilu0_analyse",
+    "bcsr_create", "bcsr_set_values", "bcsr_set_wells", "bcsr_get_dims", "bcsr_spmv", "bcsr_set_option", "bcsr_destroy", "ilu0_analyse",
     "ilu0_get_schedule", "ilu0_get_sweep_levels", "ilu0_set_option", "ilu0_get_option", "ilu0_autotune",
     "ilu0_factor", "ilu0_get_factors", "ilu0_apply",
     "bicgstab_solve", "ilu0_destroy", "ilu0_analyse_host", "rsolve_profile_enable", "rsolve_profile_get",
@@ -108,6 +108,7 @@ def lib():
         P = ct.POINTER
         L.bcsr_create.argtypes = [i32, i32, i32, i32, vp, vp, vp, i32, vp, P(vp), P(i32)]
         L.bcsr_set_values.argtypes = [vp, vp, i32, i32, i32, vp]
+        L.bcsr_set_wells.argtypes = [vp, i32, vp, vp, vp, vp, vp, i32, vp]
         L.bcsr_get_dims.argtypes = [vp, P(i32), P(i32), P(i32)]
         L.bcsr_spmv.argtypes = [vp, vp, vp, i32, i32, i32, vp]
         L.bcsr_destroy.argtypes = [vp]
@@ -231,6 +232,20 @@ def bcsr_set_values(A, vals, first_sys=0, n_sys=None, *, stream=None):
         n_sys = 1 if vals.ndim == 3 else int(vals.shape[0])
     mem, (vp,) = _mem_ptr(vals)
     return _check(lib().bcsr_set_values(A, vp, first_sys, n_sys, mem, _stream(stream)), "bcsr_set_values")
+
+
+def bcsr_set_wells(A, well_ptr=None, perf_row=None, B=None, C=None, Dinv=None, *, stream=None):
+    """Standard wells kept separate (see rsolve.h); no arguments removes them.
+    B, C: (batch, n_perf, 4, 3) or (n_perf, 4, 3); Dinv: (batch, n_wells, 4, 4)."""
+    if well_ptr is None:
+        return _check(lib().bcsr_set_wells(A, 0, None, None, None, None, None, MEM_HOST, _stream(stream)),
+                      "bcsr_set_wells")
+    well_ptr, perf_row = _host(well_ptr, np.int32), _host(perf_row, np.int32)
+    if not _is_torch(B):
+        B, C, Dinv = _host(B, np.float64), _host(C, np.float64), _host(Dinv, np.float64)
+    mem, (bp, cp, dp) = _mem_ptr(B, C, Dinv)
+    return _check(lib().bcsr_set_wells(A, len(well_ptr) - 1, well_ptr.ctypes.data, perf_row.ctypes.data, bp, cp, dp,
+                                       mem, _stream(stream)), "bcsr_set_wells")
 
 
 def bcsr_get_dims(A):

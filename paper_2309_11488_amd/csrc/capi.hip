@@ -178,7 +178,36 @@ struct rs_bcsr {
     uint64_t hash = 0;
     std::vector<int32_t> h_rowptr, h_colidx;
     DevBuf rowptr, colidx, vals;
+    // standard wells kept separate (bcsr_set_wells), caller numbering
+    int nw = 0, np = 0;
+    long long wells_version = 0;
+    std::vector<int32_t> h_well_ptr, h_perf_row, h_row_ptr, h_row_perf, h_perf_well;
+    DevBuf w_well_ptr, w_perf_row, w_row_ptr, w_row_perf, w_perf_well, w_B, w_C, w_Dinv, w_t2;
+    // the wells as the caller-order SpMVs see them, systems from `first`
+    rs::WellsDev wells(int first = 0) const {
+        rs::WellsDev w;
+        if (nw == 0) return w;
+        w.nw = nw; w.np = np;
+        w.well_ptr = w_well_ptr.as<int32_t>(); w.perf_x = w_perf_row.as<int32_t>();
+        w.row_ptr = w_row_ptr.as<int32_t>(); w.row_perf = w_row_perf.as<int32_t>();
+        w.perf_well = w_perf_well.as<int32_t>();
+        w.B = w_B.as<double>() + (size_t)first * np * 12; w.C = w_C.as<double>() + (size_t)first * np * 12;
+        w.Dinv = w_Dinv.as<double>() + (size_t)first * nw * 16; w.t2 = w_t2.as<double>() + (size_t)first * nw * 4;
+        return w;
+    }
 };
+
+// Rows' perforation lists: row_ptr (n + 1) and row_perf, perforations of a
+// row ascending; rows given by row_of[p].
+static void perforation_index(int n, const std::vector<int32_t> &row_of, std::vector<int32_t> &row_ptr,
+                              std::vector<int32_t> &row_perf) {
+    row_ptr.assign((size_t)n + 1, 0);
+    for (int32_t r : row_of) row_ptr[r + 1]++;
+    for (int i = 0; i < n; ++i) row_ptr[i + 1] += row_ptr[i];
+    row_perf.assign(row_of.size(), 0);
+    std::vector<int32_t> next(row_ptr.begin(), row_ptr.end() - 1);
+    for (size_t p = 0; p < row_of.size(); ++p) row_perf[next[row_of[p]]++] = (int32_t)p;
+}
 
 // The analysis of one pattern: the host schedule and its device copy.
 // Immutable once built; every preconditioner handle of the pattern holds a
@@ -214,6 +243,12 @@ struct rs_ilu0 {
     int spmv_variant = rs::RV_W4_LDS;   // launch shape of the SpMVs
     int sweep_variant = rs::RV_W4_LDS;  // launch shape of the per-level sweeps
     int reduce_split = 0;               // RS_OPT_REDUCE_SPLIT
+    // the wells of the matrix last solved with, in the new numbering
+    const rs_bcsr *wells_of = nullptr;
+    long long wells_version = -1;
+    std::vector<int32_t> h_wperf_x, h_wrow_ptr, h_wrow_perf;
+    DevBuf wperf_x, wrow_ptr, wrow_perf, wt2;
+    rs::WellsDev wdev{};
     bool split() const { return reduce_split != 0; }
     // a BiCGStab iteration captured as HIP graphs, replayed on the caller's
     // stream: segment 0 = the whole iteration; 1 and 2 = the parts before and
@@ -372,6 +407,52 @@ int bcsr_set_option(bcsr_t A, int32_t option, int32_t value) {
     return fail(RS_INVALID_ARG, "bcsr_set_option: unknown option or bad value");
 }
 
+int bcsr_set_wells(bcsr_t A, int32_t n_wells, const int32_t *well_ptr, const int32_t *perf_row, const double *B,
+                   const double *C, const double *Dinv, int32_t mem, void *stream) {
+    if (!A || n_wells < 0 || (mem != RS_MEM_HOST && mem != RS_MEM_DEVICE))
+        return fail(RS_INVALID_ARG, "bcsr_set_wells: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    A->wells_version++;
+    if (n_wells == 0) {
+        A->nw = A->np = 0;
+        return RS_OK;
+    }
+    if (!well_ptr || !perf_row || !B || !C || !Dinv) return fail(RS_INVALID_ARG, "bcsr_set_wells: NULL array");
+    if (well_ptr[0] != 0) return fail(RS_INVALID_ARG, "bcsr_set_wells: well_ptr[0] must be 0");
+    for (int w = 0; w < n_wells; ++w)
+        if (well_ptr[w + 1] < well_ptr[w]) return fail(RS_INVALID_ARG, "bcsr_set_wells: well_ptr decreases");
+    const int np = well_ptr[n_wells];
+    for (int p = 0; p < np; ++p)
+        if (perf_row[p] < 0 || perf_row[p] >= A->n) return fail(RS_INVALID_ARG, "bcsr_set_wells: perforation row out of range");
+    A->nw = 0;   // until the copies below are in place
+    A->h_well_ptr.assign(well_ptr, well_ptr + n_wells + 1);
+    A->h_perf_row.assign(perf_row, perf_row + np);
+    A->h_perf_well.resize(np);
+    for (int w = 0; w < n_wells; ++w)
+        for (int p = well_ptr[w]; p < well_ptr[w + 1]; ++p) A->h_perf_well[p] = w;
+    perforation_index(A->n, A->h_perf_row, A->h_row_ptr, A->h_row_perf);
+    const size_t Bn = (size_t)A->batch;
+    const hipMemcpyKind kind = mem == RS_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIP_TRY(upload(A->w_well_ptr, A->h_well_ptr, s));
+    HIP_TRY(upload(A->w_perf_row, A->h_perf_row, s));
+    HIP_TRY(upload(A->w_row_ptr, A->h_row_ptr, s));
+    HIP_TRY(upload(A->w_row_perf, A->h_row_perf, s));
+    HIP_TRY(upload(A->w_perf_well, A->h_perf_well, s));
+    HIP_TRY(A->w_B.alloc(std::max<size_t>(Bn * np * 12, 1) * sizeof(double)));
+    HIP_TRY(A->w_C.alloc(std::max<size_t>(Bn * np * 12, 1) * sizeof(double)));
+    HIP_TRY(A->w_Dinv.alloc(Bn * n_wells * 16 * sizeof(double)));
+    HIP_TRY(A->w_t2.alloc(Bn * n_wells * 4 * sizeof(double)));
+    if (np) {
+        HIP_TRY(hipMemcpyAsync(A->w_B.p, B, Bn * np * 12 * sizeof(double), kind, s));
+        HIP_TRY(hipMemcpyAsync(A->w_C.p, C, Bn * np * 12 * sizeof(double), kind, s));
+    }
+    HIP_TRY(hipMemcpyAsync(A->w_Dinv.p, Dinv, Bn * n_wells * 16 * sizeof(double), kind, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    A->nw = n_wells;
+    A->np = np;
+    return RS_OK;
+}
+
 int bcsr_destroy(bcsr_t A) {
     delete A;
     return RS_OK;
@@ -405,7 +486,7 @@ int bcsr_spmv(bcsr_t A, const double *x, double *y, int32_t first_sys, int32_t n
     }
     const size_t per = (size_t)A->nnzb * 9;
     rs::launch_spmv(A->n, A->rowptr.as<int32_t>(), A->colidx.as<int32_t>(), A->vals.as<double>() + per * first_sys,
-                    per, xd, yd, 3 * (size_t)A->n, n_sys, A->spmv_variant, s);
+                    per, xd, yd, 3 * (size_t)A->n, n_sys, A->spmv_variant, A->wells(first_sys), s);
     HIP_TRY(hipGetLastError());
     if (mem != RS_MEM_DEVICE) {
         if (m) HIP_TRY(hipMemcpyAsync(y, yd, m * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -682,6 +763,36 @@ int ilu0_get_factors(ilu0_t M, int32_t sys, double *lu, double *dinv) {
     return RS_OK;
 }
 
+// The matrix's wells in the new numbering (rebuilt when A or its wells
+// change); ordered on `s`.
+static int ensure_wells(ilu0_t M, const rs_bcsr *A, hipStream_t s) {
+    if (A->nw == 0) {
+        M->wdev = rs::WellsDev{};
+        M->wells_of = A;
+        M->wells_version = A->wells_version;
+        return RS_OK;
+    }
+    if (M->wells_of != A || M->wells_version != A->wells_version) {
+        const std::vector<int32_t> &iperm = M->an->sch.iperm;
+        M->h_wperf_x.resize(A->np);
+        for (int p = 0; p < A->np; ++p) M->h_wperf_x[p] = iperm[A->h_perf_row[p]];
+        perforation_index(M->n, M->h_wperf_x, M->h_wrow_ptr, M->h_wrow_perf);
+        HIP_TRY(upload(M->wperf_x, M->h_wperf_x, s));
+        HIP_TRY(upload(M->wrow_ptr, M->h_wrow_ptr, s));
+        HIP_TRY(upload(M->wrow_perf, M->h_wrow_perf, s));
+        HIP_TRY(M->wt2.alloc((size_t)M->batch * A->nw * 4 * sizeof(double)));
+        M->wells_of = A;
+        M->wells_version = A->wells_version;
+    }
+    rs::WellsDev w = A->wells();
+    w.perf_x = M->wperf_x.as<int32_t>();
+    w.row_ptr = M->wrow_ptr.as<int32_t>();
+    w.row_perf = M->wrow_perf.as<int32_t>();
+    w.t2 = M->wt2.as<double>();
+    M->wdev = w;
+    return RS_OK;
+}
+
 // Allocate (first call) and bind the solve workspace; initialisation is
 // ordered on the caller's stream `s`.
 static int ensure_workspace(ilu0_t M, hipStream_t s) {
@@ -799,13 +910,13 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
     if (parts & IT_APPLY1) apply_levels<T>(M, L, U, D, nullptr, k.phat, true, k, k.st, B, s);
     if (parts & IT_SPMV_V) {
         ProfScope ps(PC_SPMV_V, s, spmv_bytes, true);
-        rs::launch_spmv_v(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), s, ps.start(),
-                          ps.stop());
+        rs::launch_spmv_v(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), M->wdev, s,
+                          ps.start(), ps.stop());
     }
     if (!(parts & IT_REST)) return;
     { ProfScope ps(PC_VEC, s, B * 72 * n); rs::launch_s_update(M->n, k, B, M->spmv_variant, M->split(), s); }
     apply_levels<T>(M, L, U, D, k.s, k.shat, false, k, k.st, B, s);
-    { ProfScope ps(PC_SPMV_T, s, spmv_bytes); rs::launch_spmv_t(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), s); }
+    { ProfScope ps(PC_SPMV_T, s, spmv_bytes); rs::launch_spmv_t(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), M->wdev, s); }
     { ProfScope ps(PC_VEC, s, B * 192 * n); rs::launch_xr_update(M->n, k, B, M->spmv_variant, M->split(), s); }
 }
 
@@ -822,7 +933,8 @@ static void enqueue_iteration_any(ilu0_t M, hipStream_t s, int parts) {
 static int replay_segment(ilu0_t M, int seg, int parts, hipStream_t s) {
     const long long key = (long long)M->precision | (long long)M->tile_sweeps << 2 | (long long)M->spmv_variant << 3 |
                           (long long)M->sweep_variant << 6 | (long long)(M->split() ? 1 : 0) << 9 |
-                          (long long)M->sweep_grid << 10;
+                          (long long)M->sweep_grid << 10 |
+                          (M->wdev.nw > 0 ? ((long long)(M->wells_version & 0xffffff) + 1) << 36 : 0);
     if (!M->gexec[seg] || M->graph_key[seg] != key) {
         if (M->gexec[seg]) (void)hipGraphExecDestroy(M->gexec[seg]);
         if (M->graph[seg]) (void)hipGraphDestroy(M->graph[seg]);
@@ -924,6 +1036,8 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
     hipStream_t s = (hipStream_t)stream;
     st = ensure_workspace(M, s);
     if (st != RS_OK) return st;
+    st = ensure_wells(M, A, s);
+    if (st != RS_OK) return st;
     const size_t m = 3 * (size_t)M->n * B;
     const double *bd = nullptr;
     st = stage_in(b, mem, M->bstage, m, s, &bd);
@@ -956,7 +1070,7 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
         if (all) break;
     }
     rs::launch_finish(M->an->dev, A->rowptr.as<int32_t>(), A->colidx.as<int32_t>(), A->vals.as<double>(),
-                      (size_t)A->nnzb * 9, bd, xd, k, B, M->spmv_variant, M->split(), s);
+                      (size_t)A->nnzb * 9, bd, xd, k, B, M->spmv_variant, M->split(), A->wells(), s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(M->h_ctr, k.lctr, 2 * sizeof(rs::SweepCtr), hipMemcpyDeviceToHost, s));

@@ -36,6 +36,19 @@ struct DevSchedule {
     const int32_t *lt_start, *lt_dptr, *lt_dep, *ut_start, *ut_dptr, *ut_dep;
 };
 
+// Standard wells kept separate (y -= C^T D^-1 B x for every well), as the
+// SpMV kernels see them.  nw == 0: no wells.
+struct WellsDev {
+    int nw = 0, np = 0;
+    const int32_t *well_ptr = nullptr;   // nw + 1: perforations of well w
+    const int32_t *perf_x = nullptr;     // np: row of the SpMV's x (and y) each perforation couples
+    const int32_t *row_ptr = nullptr;    // n + 1: perforations of output row i are row_perf[row_ptr[i] ..)
+    const int32_t *row_perf = nullptr;   // np, ascending within a row
+    const int32_t *perf_well = nullptr;  // np
+    const double *B = nullptr, *C = nullptr, *Dinv = nullptr;   // per system: np*12, np*12, nw*16
+    double *t2 = nullptr;                // per system: nw*4, D^-1 B x of the current x
+};
+
 // Work counter of one single-launch sweep kernel: tickets hand out (tile,
 // system) items in dependency order; the last workgroup to leave resets the
 // tickets and publishes the epoch that marks a tile as done in this sweep.
@@ -146,8 +159,9 @@ void launch_usweep_tiles(const DevSchedule &d, const T *U, size_t u_stride, cons
                          int grid, hipStream_t s);
 
 // Plain y = A x (rows in storage order), FP64.
+// y = A x (minus the separate wells, when w has any: t2 is computed first).
 void launch_spmv(int n, const int32_t *ptr, const int32_t *col, const double *A, size_t a_stride, const double *x,
-                 double *y, size_t vstride, int nsys, int variant, hipStream_t s);
+                 double *y, size_t vstride, int nsys, int variant, const WellsDev &w, hipStream_t s);
 
 // Solver kernels (new order, all nsys systems of the Krylov workspace).
 // The two SpMVs store per-workgroup partial sums; the s- and x/r-updates
@@ -155,16 +169,22 @@ void launch_spmv(int n, const int32_t *ptr, const int32_t *col, const double *A,
 // bad[sys] < n marks a system whose factorisation hit a singular pivot.
 void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad, double reduction, int max_iter,
                   Krylov &k, int nsys, hipStream_t s);
+// t2 = D^-1 (B x) for every well and system (x at stride xstride): the
+// first half of the separate well application, run before an SpMV of x.
+void launch_wells_t2(const WellsDev &w, const double *x, size_t xstride, int nsys, hipStream_t s);
+
 // ev0 / ev1 (optional): events recorded by the dispatch at the kernel's start and end.
 void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, bool split,
-                   hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                   const WellsDev &w, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, bool split, hipStream_t s);
-void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, bool split, hipStream_t s);
+void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, bool split,
+                   const WellsDev &w, hipStream_t s);
 void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, bool split, hipStream_t s);
 // x_orig[perm[i]] = x'[i]; then r = b - A x_orig with the caller's A, and the
 // true relative residual into the states.
 void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *colidx, const double *A,
-                   size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, int variant, bool split, hipStream_t s);
+                   size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, int variant, bool split,
+                   const WellsDev &w, hipStream_t s);
 
 // out[i] = in[perm[i]] (gather to the new order) and its inverse scatter;
 // the new-order side has stride vstride, the caller side 3n.

@@ -771,6 +771,46 @@ enum SpmvMode { SPMV_PLAIN = 0, SPMV_V = 1, SPMV_T = 2, SPMV_TRUE = 3 };
 //   SPMV_V:    v = A phat, reduce (rhat, v), alpha = rho / (rhat, v)
 //   SPMV_T:    t = A shat, reduce (t, s) and (t, t), omega = (t, s) / (t, t)
 //   SPMV_TRUE: reduce ||b - A x||^2 and ||b||^2, true relative residual
+// ------------------------------------------------------------------ wells
+
+// (C_p^T t2_w)_r summed over the perforations of output row i, in
+// perforation order (Algorithm 5's second half for one row component).
+__device__ inline double well_terms(const WellsDev &wl, int sys, int i, int r) {
+    double s = 0.0;
+    const double *Cs = wl.C + (size_t)sys * wl.np * 12;
+    const double *Ts = wl.t2 + (size_t)sys * wl.nw * 4;
+    for (int e = wl.row_ptr[i]; e < wl.row_ptr[i + 1]; ++e) {
+        const int p = wl.row_perf[e];
+        const double *c = Cs + (size_t)p * 12;
+        const double *t = Ts + (size_t)wl.perf_well[p] * 4;
+        s += c[r] * t[0] + c[3 + r] * t[1] + c[6 + r] * t[2] + c[9 + r] * t[3];
+    }
+    return s;
+}
+
+// t2_w = D_w^-1 (B_w x) for every well: one wave per well, lanes stride over
+// its perforations, then a fixed-order wave sum (Algorithm 5's first half).
+__global__ void __launch_bounds__(256) k_wells_t2(WellsDev wl, const double *__restrict__ x, size_t xstride) {
+    const int sys = blockIdx.y;
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (w >= wl.nw) return;
+    const double *xs = x + (size_t)sys * xstride;
+    const double *Bs = wl.B + (size_t)sys * wl.np * 12;
+    double t1[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int p = wl.well_ptr[w] + lane; p < wl.well_ptr[w + 1]; p += 64) {
+        const double *b = Bs + (size_t)p * 12, *xc = xs + 3 * (size_t)wl.perf_x[p];
+        const double x0 = xc[0], x1 = xc[1], x2 = xc[2];
+        for (int i = 0; i < 4; ++i) t1[i] += b[3 * i] * x0 + b[3 * i + 1] * x1 + b[3 * i + 2] * x2;
+    }
+    for (int i = 0; i < 4; ++i) t1[i] = wave_sum(t1[i]);
+    if (lane != 0) return;
+    const double *d = wl.Dinv + ((size_t)sys * wl.nw + w) * 16;
+    double *t2 = wl.t2 + ((size_t)sys * wl.nw + w) * 4;
+    for (int i = 0; i < 4; ++i) t2[i] = d[4 * i] * t1[0] + d[4 * i + 1] * t1[1] + d[4 * i + 2] * t1[2] + d[4 * i + 3] * t1[3];
+}
+
+// ------------------------------------------------------------------- SpMV
+
 template <int MODE, int W, bool STAGE>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRowWavesPerEU, 8))) k_spmv(int n, const int32_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ col, const double *__restrict__ A,
@@ -779,7 +819,7 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
                                                       const double *__restrict__ w1, const double *__restrict__ w2,
                                                       double *__restrict__ part, size_t part_stride,
                                                       uint32_t *__restrict__ tk, size_t tk_stride,
-                                                      SysState *__restrict__ st, int split) {
+                                                      SysState *__restrict__ st, int split, WellsDev wl) {
     int sys, bx;
     xcd_map(sys, bx);
     // whether the system still iterates.  t = A shat often runs after a
@@ -808,14 +848,15 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
         asm volatile("" ::"v"(acc));   // the walk completes before the phase test below
         if (!run) return;
         if (!rl.act) continue;
+        const double acc_w = wl.nw > 0 ? acc - well_terms(wl, sys, rl.q, rl.r) : acc;
         if (MODE == SPMV_PLAIN) {
-            y[k] = acc;
+            y[k] = acc_w;
         } else if (MODE == SPMV_V || MODE == SPMV_T) {
-            y[k] = acc;
-            v[0] += w * acc;
-            v[1] += acc * acc;
+            y[k] = acc_w;
+            v[0] += w * acc_w;
+            v[1] += acc_w * acc_w;
         } else {  // SPMV_TRUE: w1 = b
-            const double res = w - acc;
+            const double res = w - acc_w;
             v[0] += res * res;
             v[1] += w * w;
         }
@@ -1206,8 +1247,9 @@ template void launch_usweep_tiles<float>(const DevSchedule &, const float *, siz
 template <int MODE>
 static void spmv_any(int variant, int n, const int32_t *ptr, const int32_t *col, const double *A, size_t a_stride,
                      const double *x, double *y, size_t vstride, const double *w1, double *part, size_t part_stride,
-                     uint32_t *tk, size_t tk_stride, SysState *st, int nsys, bool split, hipStream_t s,
-                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+                     uint32_t *tk, size_t tk_stride, SysState *st, int nsys, bool split, const WellsDev &wl,
+                     hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+    if (wl.nw > 0) launch_wells_t2(wl, x, vstride, nsys, s);
     int waves = 1;
     with_variant(variant, [&](auto W, auto ST) {
         constexpr int w = decltype(W)::value;
@@ -1217,20 +1259,25 @@ static void spmv_any(int variant, int n, const int32_t *ptr, const int32_t *col,
         if (ev0)
             hipExtLaunchKernelGGL(k_spmv<MODE, w, staged>, g, b, 0, s, ev0, ev1, 0, n, ptr, col, A, a_stride, x, y,
                                   vstride, w1, (const double *)nullptr, part, part_stride, tk, tk_stride, st,
-                                  split ? 1 : 0);
+                                  split ? 1 : 0, wl);
         else
             k_spmv<MODE, w, staged><<<g, b, 0, s>>>(n, ptr, col, A, a_stride, x, y, vstride, w1, nullptr, part,
-                                                    part_stride, tk, tk_stride, st, split ? 1 : 0);
+                                                    part_stride, tk, tk_stride, st, split ? 1 : 0, wl);
     });
     if (MODE != SPMV_PLAIN && split)
         k_spmv_total<MODE><<<dim3(1, nsys), kTotalThreads, 0, s>>>(part, part_stride, waves, st);
 }
 
+void launch_wells_t2(const WellsDev &w, const double *x, size_t xstride, int nsys, hipStream_t s) {
+    if (w.nw <= 0 || nsys <= 0) return;
+    k_wells_t2<<<dim3((w.nw + 3) / 4, nsys), 256, 0, s>>>(w, x, xstride);
+}
+
 void launch_spmv(int n, const int32_t *ptr, const int32_t *col, const double *A, size_t a_stride, const double *x,
-                 double *y, size_t vstride, int nsys, int variant, hipStream_t s) {
+                 double *y, size_t vstride, int nsys, int variant, const WellsDev &w, hipStream_t s) {
     if (n <= 0 || nsys <= 0) return;
     spmv_any<SPMV_PLAIN>(variant, n, ptr, col, A, a_stride, x, y, vstride, nullptr, nullptr, 0, nullptr, 0, nullptr,
-                         nsys, false, s);
+                         nsys, false, w, s);
 }
 
 void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad, double reduction, int max_iter,
@@ -1239,9 +1286,9 @@ void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad
 }
 
 void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
-                   bool split, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                   bool split, const WellsDev &w, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     spmv_any<SPMV_V>(variant, d.n, d.prow, d.pcol, Ap, a_stride, k.phat, k.v, k.vstride, k.rhat, k.spart,
-                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, s, ev0, ev1);
+                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, w, s, ev0, ev1);
 }
 
 void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, bool split, hipStream_t s) {
@@ -1250,9 +1297,9 @@ void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, bool split, h
 }
 
 void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
-                   bool split, hipStream_t s) {
+                   bool split, const WellsDev &w, hipStream_t s) {
     spmv_any<SPMV_T>(variant, d.n, d.prow, d.pcol, Ap, a_stride, k.shat, k.t, k.vstride, k.s, k.spart,
-                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, s);
+                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, w, s);
 }
 
 void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, bool split, hipStream_t s) {
@@ -1269,11 +1316,11 @@ void launch_permute_vec(const int32_t *perm, const double *in, double *out, int 
 
 void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *colidx, const double *A,
                    size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, int variant,
-                   bool split, hipStream_t s) {
+                   bool split, const WellsDev &w, hipStream_t s) {
     if (d.n <= 0 || nsys <= 0) return;
     launch_permute_vec(d.perm, k.x, x_orig, d.n, k.vstride, nsys, true, s);
     spmv_any<SPMV_TRUE>(variant, d.n, rowptr, colidx, A, a_stride, x_orig, nullptr, 3 * (size_t)d.n, b_orig, k.part,
-                        k.part_stride, k.tickets, k.ticket_stride, k.st, nsys, split, s);
+                        k.part_stride, k.tickets, k.ticket_stride, k.st, nsys, split, w, s);
 }
 
 }  // namespace rs
