@@ -876,9 +876,12 @@ static void apply_levels(ilu0_t M, const T *L, const T *U, const T *D, const dou
             rs::launch_lsweep_tiles<T>(M->an->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, k.lflags,
                                        k.lctr, nsys, M->sweep_grid, s);
         else
+            // the upper sweep's first level (rows without upper blocks) is
+            // finished inside the lower sweep's launches
             for (int l = 0; l < S.nl_levels; ++l)
                 rs::launch_lsweep<T>(M->an->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, S.lset[l],
-                                     S.lset[l + 1], nsys, M->sweep_variant, s);
+                                     S.lset[l + 1], nsys, M->sweep_variant, D, (size_t)M->n * 9, out,
+                                     S.nu_levels > 0 ? S.uset[1] : 0, s);
     }
     {
         // U blocks + indices, inv(U_ii), row pointers and row list, y read, z written
@@ -888,7 +891,7 @@ static void apply_levels(ilu0_t M, const T *L, const T *U, const T *D, const dou
             rs::launch_usweep_tiles<T>(M->an->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, k.uflags,
                                        k.uctr, nsys, M->sweep_grid, s);
         else
-            for (int l = 0; l < S.nu_levels; ++l)
+            for (int l = 1; l < S.nu_levels; ++l)
                 rs::launch_usweep<T>(M->an->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, S.uset[l],
                                      S.uset[l + 1], nsys, M->sweep_variant, s);
     }

@@ -138,9 +138,12 @@ void launch_factor_level(const DevSchedule &d, const double *A, size_t a_stride,
 // set, the input is p = r + beta (p - omega v) computed on the fly (and
 // stored); otherwise `in`.  st may be NULL (no phase check).
 template <typename T>
+// When u0_end > 0, rows whose U-schedule position is below u0_end (the
+// upper sweep's first level: no upper blocks) also finish the upper sweep:
+// z_i = inv(U_ii) y_i (Dinv at d_stride per system), exactly as k_usweep.
 void launch_lsweep(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
                    bool fuse_p, const double *r, const double *v, double *p, SysState *st, int q0, int q1, int nsys,
-                   int variant, hipStream_t s);
+                   int variant, const T *Dinv, size_t d_stride, double *z, int u0_end, hipStream_t s);
 
 // Upper sweep z = inv(U_ii) (y - U z) for U-schedule rows [q0, q1).
 template <typename T>

@@ -17,6 +17,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include <algorithm>
 #include <type_traits>
 
@@ -549,7 +551,9 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
                                                         const double *__restrict__ in, T *__restrict__ y,
                                                         size_t vstride, const double *__restrict__ rv,
                                                         const double *__restrict__ vv, double *__restrict__ pv,
-                                                        SysState *__restrict__ st, int q0, int q1) {
+                                                        SysState *__restrict__ st, int q0, int q1,
+                                                        const T *__restrict__ Dinv, size_t d_stride,
+                                                        double *__restrict__ z, int u0_end) {
     int sys, bx;
     xcd_map(sys, bx);
     if (st && st[sys].phase != PH_RUN) return;
@@ -557,6 +561,7 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
     const int qb0 = q0 + bx * W * kRowsPerWave, qb1 = min(qb0 + W * kRowsPerWave, q1);
     const size_t vo = (size_t)sys * vstride;
     const int i = rl.act ? d.lrows[rl.q] : 0;
+    const int uq = (u0_end > 0 && rl.act) ? d.l2u[rl.q] : INT_MAX;
     T acc = 0;
     if (rl.act) {
         const size_t k = vo + 3 * (size_t)i + rl.r;
@@ -572,6 +577,15 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
     acc = row_walk<W, STAGE, kSweepCapPerWave, true>(d.lptr, d.lcol, L + (size_t)sys * l_stride, qb0, qb1, rl, y + vo,
                                                      acc);
     if (rl.act) y[vo + 3 * (size_t)i + rl.r] = acc;
+    if (u0_end > 0) {
+        // rows without upper blocks (the first level of the upper sweep)
+        // finish here: z_i = inv(U_ii) y_i, the arithmetic of k_usweep
+        const T t0 = __shfl(acc, rl.base, 64), t1 = __shfl(acc, rl.base + 1, 64), t2 = __shfl(acc, rl.base + 2, 64);
+        if (uq < u0_end) {
+            const T *dq = Dinv + (size_t)sys * d_stride + (size_t)uq * 9 + 3 * rl.r;
+            z[vo + 3 * (size_t)i + rl.r] = (double)dot3(dq[0], dq[1], dq[2], t0, t1, t2);
+        }
+    }
 }
 
 template <typename T, int W, bool STAGE>
@@ -592,7 +606,7 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
     const T t0 = __shfl(acc, rl.base, 64), t1 = __shfl(acc, rl.base + 1, 64), t2 = __shfl(acc, rl.base + 2, 64);
     if (!rl.act) return;
     const T *dq = Dinv + (size_t)sys * d_stride + (size_t)rl.q * 9 + 3 * rl.r;
-    const T zr = dq[0] * t0 + dq[1] * t1 + dq[2] * t2;
+    const T zr = dot3(dq[0], dq[1], dq[2], t0, t1, t2);
     z[vo + 3 * (size_t)i + rl.r] = (double)zr;
 }
 
@@ -755,7 +769,7 @@ __global__ void __launch_bounds__(kRowThreads) k_usweep_tiles(DevSchedule d, con
         }
         const T t0 = __shfl(acc, rl.base, 64), t1 = __shfl(acc, rl.base + 1, 64), t2 = __shfl(acc, rl.base + 2, 64);
         if (rl.act) {
-            const T zr = dq[0] * t0 + dq[1] * t1 + dq[2] * t2;
+            const T zr = dot3(dq[0], dq[1], dq[2], t0, t1, t2);
             __hip_atomic_store(z + vo + 3 * (size_t)i + rl.r, (double)zr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         publish_tile(flags + (size_t)w.sys * d.nut, w.tile, epoch);
@@ -1169,16 +1183,18 @@ void launch_factor_level(const DevSchedule &d, const double *A, size_t a_stride,
 template <typename T>
 void launch_lsweep(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
                    bool fuse_p, const double *r, const double *v, double *p, SysState *st, int q0, int q1, int nsys,
-                   int variant, hipStream_t s) {
+                   int variant, const T *Dinv, size_t d_stride, double *z, int u0_end, hipStream_t s) {
     if (q1 <= q0 || nsys <= 0) return;
     with_variant(variant, [&](auto W, auto ST) {
         constexpr int w = decltype(W)::value;
         constexpr bool staged = decltype(ST)::value;
         const dim3 g(row_blocks(q1 - q0, w), nsys);
         if (fuse_p)
-            k_lsweep<T, true, w, staged><<<g, 64 * w, 0, s>>>(d, L, l_stride, in, y, vstride, r, v, p, st, q0, q1);
+            k_lsweep<T, true, w, staged><<<g, 64 * w, 0, s>>>(d, L, l_stride, in, y, vstride, r, v, p, st, q0, q1,
+                                                              Dinv, d_stride, z, u0_end);
         else
-            k_lsweep<T, false, w, staged><<<g, 64 * w, 0, s>>>(d, L, l_stride, in, y, vstride, r, v, p, st, q0, q1);
+            k_lsweep<T, false, w, staged><<<g, 64 * w, 0, s>>>(d, L, l_stride, in, y, vstride, r, v, p, st, q0, q1,
+                                                               Dinv, d_stride, z, u0_end);
     });
 }
 
@@ -1196,10 +1212,10 @@ void launch_usweep(const DevSchedule &d, const T *U, size_t u_stride, const T *D
 
 template void launch_lsweep<double>(const DevSchedule &, const double *, size_t, const double *, double *, size_t,
                                     bool, const double *, const double *, double *, SysState *, int, int, int, int,
-                                    hipStream_t);
+                                    const double *, size_t, double *, int, hipStream_t);
 template void launch_lsweep<float>(const DevSchedule &, const float *, size_t, const double *, float *, size_t, bool,
                                    const double *, const double *, double *, SysState *, int, int, int, int,
-                                   hipStream_t);
+                                   const float *, size_t, double *, int, hipStream_t);
 template void launch_usweep<double>(const DevSchedule &, const double *, size_t, const double *, size_t,
                                     const double *, double *, size_t, SysState *, int, int, int, int, hipStream_t);
 template void launch_usweep<float>(const DevSchedule &, const float *, size_t, const float *, size_t, const float *,
