@@ -606,3 +606,70 @@ def test_c2_full_size_parity(solver_of, ordering):
     assert abs(info[0]["half_steps"] - oinfo["half_steps"]) <= 1
     x, st, info = rs.bicgstab_solve(M, A, s.b[0, 1:2], reduction=1e-2)
     assert st == rs.OK and info[0]["true_rel_residual"] <= 1e-2
+
+
+def test_c3_full_size_parity():
+    """The 100^3 grid (1M cells, sigma 2) at full size in the configuration the
+    benchmark times (graph colouring, autotuned launch shapes): FP64 factors
+    against the oracle's, the FP64 solution at 1e-10, FP32 factors as
+    roundings of the oracle's, and the mixed solve at 1e-2."""
+    s = config_system("c3")
+    A = rs.bcsr_create(s.rowptr, s.colidx, s.vals)
+    M = rs.ilu0_analyse(A, rs.ORDER_GRAPH_COLOUR)
+    try:
+        st, _ = rs.ilu0_factor(M, A, rs.PREC_FP64)
+        assert st == rs.OK
+        perm, prow, pcol, pv, ost, _, lu, dinv = oracle_factors(s, rs.ORDER_GRAPH_COLOUR)
+        assert ost == oracle.OK
+        glu, gdinv = rs.ilu0_get_factors(M, 0, s.n, s.nnzb)
+        assert rel_block_err(gdinv, dinv) <= 1e-12
+        offd = np.repeat(np.arange(s.n), np.diff(prow)) != pcol
+        assert rel_block_err(glu[offd], lu[offd]) <= 1e-12
+        del glu
+        rs.ilu0_autotune(M, A, s.b[:, 0], reduction=1e-2, reps=1)
+        x, st, info = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-10)
+        xo, oinfo = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=rs.ORDER_GRAPH_COLOUR,
+                                 reduction=1e-10)
+        assert st == oinfo["status"] == rs.OK
+        assert np.linalg.norm(x[0] - xo) <= 1e-8 * np.linalg.norm(xo)
+        # 1M rows summed in different orders: at 1e-10 the erratic BiCGStab
+        # residual of this sigma = 2 system crosses the threshold a few half
+        # steps apart on the two sides (x agrees to 1e-8 all the same)
+        assert abs(info[0]["half_steps"] - oinfo["half_steps"]) <= max(1, oinfo["half_steps"] // 5)
+        st, _ = rs.ilu0_factor(M, A, rs.PREC_FP32_FACTORS)
+        glu, gdinv = rs.ilu0_get_factors(M, 0, s.n, s.nnzb)
+        for g, o in ((glu[offd], lu[offd]), (gdinv, dinv)):
+            o32 = o.astype(np.float32)
+            assert np.all(np.abs(g - o32.astype(np.float64)) <= np.spacing(np.abs(o32)).astype(np.float64))
+        del glu
+        x, st, info = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-2)
+        _, oinfo = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=rs.ORDER_GRAPH_COLOUR,
+                                precond=oracle.PREC_ILU_F32, reduction=1e-2)
+        assert st == rs.OK and info[0]["true_rel_residual"] <= 1e-2
+        assert abs(info[0]["half_steps"] - oinfo["half_steps"]) <= 1
+    finally:
+        rs.ilu0_destroy(M)
+        rs.bcsr_destroy(A)
+
+
+def test_c4_full_size_batch_parity():
+    """The 64-member 40x40x30 ensemble at full size, FP32 factors, one batched
+    factorisation and solve in the autotuned configuration; every eighth
+    member checked against the oracle at 1e-8."""
+    s = config_system("c4")
+    A = rs.bcsr_create(s.rowptr, s.colidx, s.vals)
+    M = rs.ilu0_analyse(A, rs.ORDER_GRAPH_COLOUR)
+    try:
+        st, bad = rs.ilu0_factor(M, A, rs.PREC_FP32_FACTORS)
+        assert st == rs.OK and (bad == -1).all()
+        rs.ilu0_autotune(M, A, s.b[:, 0], reduction=1e-2, reps=1)
+        x, st, info = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-8)
+        assert st == rs.OK and all(i["status"] == rs.OK for i in info)
+        for k in range(0, 64, 8):
+            xo, oinfo = oracle.solve(s.rowptr, s.colidx, s.vals[k], s.b[k, 0], ordering=rs.ORDER_GRAPH_COLOUR,
+                                     precond=oracle.PREC_ILU_F32, reduction=1e-8)
+            assert np.linalg.norm(x[k] - xo) <= 1e-6 * np.linalg.norm(xo)
+            assert info[k]["true_rel_residual"] <= 1e-8 * (1 + 1e-6)
+    finally:
+        rs.ilu0_destroy(M)
+        rs.bcsr_destroy(A)
