@@ -93,7 +93,9 @@ enum rs_option {
     RS_OPT_SWEEP_VARIANT = 6, /* launch shape of the one-launch-per-level sweeps (same encoding) */
     RS_OPT_REDUCE_SPLIT = 7  /* dot products fused into the SpMVs: 0 (default) = each workgroup
                                 joins a ticket tree inside the SpMV; 1 = each wave only stores
-                                its partial and a one-workgroup kernel adds them */
+                                its partial and a one-workgroup kernel adds them; 2 = each wave
+                                stores its partial and every workgroup of the next vector kernel
+                                adds them (few partials: small systems) */
 };
 
 /* Per-system outcome of bicgstab_solve. */
@@ -143,7 +145,8 @@ int bcsr_spmv(bcsr_t A, const double *x, double *y, int32_t first_sys, int32_t n
 int bcsr_set_option(bcsr_t A, int32_t option, int32_t value);
 
 /* bcsr_set_wells -- standard wells kept separate, Section "Well
- * Contributions" (Algorithm 5): from now on every product with A (the
+ * Contributions" (Algorithm 5), with the block shapes Section "OPM Flow"
+ * gives for black oil (B, C: 4x3 blocks; D: 4x4): from now on every product with A (the
  * solver's SpMVs, the true residual, bcsr_spmv) is y = A x - sum over wells
  * w of C_w^T D_w^-1 B_w x.  The ILU0 preconditioner stays that of A.
  *   n_wells          : wells (0 removes them)

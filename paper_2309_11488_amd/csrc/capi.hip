@@ -249,7 +249,7 @@ struct rs_ilu0 {
     std::vector<int32_t> h_wperf_x, h_wrow_ptr, h_wrow_perf;
     DevBuf wperf_x, wrow_ptr, wrow_perf, wt2;
     rs::WellsDev wdev{};
-    bool split() const { return reduce_split != 0; }
+    int split() const { return reduce_split; }
     // a BiCGStab iteration captured as HIP graphs, replayed on the caller's
     // stream: segment 0 = the whole iteration; 1 and 2 = the parts before and
     // after v = A phat, used while that kernel is being timed with events
@@ -639,7 +639,7 @@ int ilu0_set_option(ilu0_t M, int32_t option, int32_t value) {
         M->spmv_variant = value;
         return RS_OK;
     case RS_OPT_REDUCE_SPLIT:
-        if (value < 0 || value > 1) break;
+        if (value < 0 || value > 2) break;
         M->reduce_split = value;
         return RS_OK;
     case RS_OPT_SWEEP_VARIANT:
@@ -893,7 +893,7 @@ static void apply_levels(ilu0_t M, const T *L, const T *U, const T *D, const dou
         else
             for (int l = 1; l < S.nu_levels; ++l)
                 rs::launch_usweep<T>(M->an->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, S.uset[l],
-                                     S.uset[l + 1], nsys, M->sweep_variant, s);
+                                     S.uset[l + 1], nsys, M->sweep_variant, fuse_p, s);
     }
 }
 
@@ -935,7 +935,7 @@ static void enqueue_iteration_any(ilu0_t M, hipStream_t s, int parts) {
 // graph: profiling is off while segments are captured.
 static int replay_segment(ilu0_t M, int seg, int parts, hipStream_t s) {
     const long long key = (long long)M->precision | (long long)M->tile_sweeps << 2 | (long long)M->spmv_variant << 3 |
-                          (long long)M->sweep_variant << 6 | (long long)(M->split() ? 1 : 0) << 9 |
+                          (long long)M->sweep_variant << 6 | (long long)M->split() << 8 |
                           (long long)M->sweep_grid << 10 |
                           (M->wdev.nw > 0 ? ((long long)(M->wells_version & 0xffffff) + 1) << 36 : 0);
     if (!M->gexec[seg] || M->graph_key[seg] != key) {
@@ -1130,6 +1130,10 @@ static std::string tune_key(ilu0_t M) {
     return r;
 }
 
+// Largest number of wave partials every consumer workgroup adds itself
+// (RS_OPT_REDUCE_SPLIT 2) that the autotuner tries.
+constexpr int kConsumerSumMax = 8192;
+
 int ilu0_autotune(ilu0_t M, bcsr_t A, const double *b, int32_t mem, double reduction, int32_t reps, void *stream,
                   rs_tune_result *out) {
     int st = check_pair(M, A);
@@ -1151,7 +1155,7 @@ int ilu0_autotune(ilu0_t M, bcsr_t A, const double *b, int32_t mem, double reduc
             rs_tune_result r{};
             if (ls >> k >> r.spmv_variant >> r.sweep_variant >> r.sweep_tiles >> r.sweep_grid >> r.reduce_split &&
                 k == key && r.spmv_variant >= 0 && r.spmv_variant < rs::RV_COUNT && r.sweep_variant >= 0 &&
-                r.sweep_variant < rs::RV_COUNT && r.sweep_grid >= 1 && (r.reduce_split == 0 || r.reduce_split == 1)) {
+                r.sweep_variant < rs::RV_COUNT && r.sweep_grid >= 1 && r.reduce_split >= 0 && r.reduce_split <= 2) {
                 res = r;
                 res.from_cache = 1;
             }
@@ -1220,9 +1224,15 @@ int ilu0_autotune(ilu0_t M, bcsr_t A, const double *b, int32_t mem, double reduc
         if (st != RS_OK) return st;
     }
     {
+        // the split reductions with the best configuration; consumers adding
+        // the wave partials themselves only while those stay few
         const Cfg c = bestc;
         st = time_cfg({c.spmv, c.sweep, c.tiles, c.grid, 1});
         if (st != RS_OK) return st;
+        if (rs::spmv_sums(M->n, rs::variant_waves(c.spmv), 2).count <= kConsumerSumMax) {
+            st = time_cfg({c.spmv, c.sweep, c.tiles, c.grid, 2});
+            if (st != RS_OK) return st;
+        }
     }
     apply(bestc);
     res = rs_tune_result{bestc.spmv, bestc.sweep, bestc.tiles, bestc.grid, best, ncand, 0, bestc.split};

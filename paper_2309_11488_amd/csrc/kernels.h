@@ -99,8 +99,10 @@ inline int variant_waves(int v) { return v % 3 == 0 ? 4 : (v % 3 == 1 ? 2 : 1); 
 // SpMV workgroups: one row tile each.
 inline int spmv_grid(int n, int waves) { return std::max(1, row_blocks(n, waves)); }
 
-// Split reduction of the dot products fused into an SpMV (RS_OPT_REDUCE_SPLIT):
-// waves store partials and a one-workgroup kernel adds them.
+// Reduction of the dot products fused into an SpMV (RS_OPT_REDUCE_SPLIT):
+// 0 = ticket tree in the SpMV, 1 = waves store partials and a one-workgroup
+// kernel adds them, 2 = waves store partials and every consumer workgroup
+// adds them itself.
 constexpr int kTotalThreads = 1024;   // threads of the one-workgroup summing kernel
 // Where the consumers of an SpMV's dot products find the sums they add (in
 // doubles from the start of the system's partials) and how many pairs:
@@ -109,9 +111,11 @@ constexpr int kTotalThreads = 1024;   // threads of the one-workgroup summing ke
 struct SpmvSums {
     int offset, count;
 };
-inline SpmvSums spmv_sums(int n, int waves, bool split) {
+inline SpmvSums spmv_sums(int n, int waves, int split) {
     const int g = spmv_grid(n, waves);
-    return split ? SpmvSums{2 * g * waves, 1} : SpmvSums{2 * g, (g + 31) / 32};
+    if (split == 1) return SpmvSums{2 * g * waves, 1};       // k_spmv_total's sum after the wave partials
+    if (split == 2) return SpmvSums{0, g * waves};           // the wave partials themselves
+    return SpmvSums{2 * g, (g + 31) / 32};                   // the ticket tree's group sums
 }
 // Reduction scratch of a system whose largest launch has `blocks` workgroups.
 inline size_t part_stride_for(int blocks) { return 2 * (size_t)blocks + 2 * ((size_t)blocks / 32 + 1) + 16; }
@@ -147,8 +151,11 @@ void launch_lsweep(const DevSchedule &d, const T *L, size_t l_stride, const doub
 
 // Upper sweep z = inv(U_ii) (y - U z) for U-schedule rows [q0, q1).
 template <typename T>
+// defer: test the system's phase after the walk's loads are issued (the
+// first application of an iteration, which runs whenever it is queued).
 void launch_usweep(const DevSchedule &d, const T *U, size_t u_stride, const T *Dinv, size_t d_stride, const T *y,
-                   double *z, size_t vstride, SysState *st, int q0, int q1, int nsys, int variant, hipStream_t s);
+                   double *z, size_t vstride, SysState *st, int q0, int q1, int nsys, int variant, bool defer,
+                   hipStream_t s);
 
 // Single-launch sweeps over all tiles of all nsys systems (L: lower
 // schedule, U: upper schedule).  grid = number of workgroups.
@@ -177,16 +184,16 @@ void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad
 void launch_wells_t2(const WellsDev &w, const double *x, size_t xstride, int nsys, hipStream_t s);
 
 // ev0 / ev1 (optional): events recorded by the dispatch at the kernel's start and end.
-void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, bool split,
+void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, int split,
                    const WellsDev &w, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, bool split, hipStream_t s);
-void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, bool split,
+void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, int split, hipStream_t s);
+void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, int split,
                    const WellsDev &w, hipStream_t s);
-void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, bool split, hipStream_t s);
+void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, int split, hipStream_t s);
 // x_orig[perm[i]] = x'[i]; then r = b - A x_orig with the caller's A, and the
 // true relative residual into the states.
 void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *colidx, const double *A,
-                   size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, int variant, bool split,
+                   size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, int variant, int split,
                    const WellsDev &w, hipStream_t s);
 
 // out[i] = in[perm[i]] (gather to the new order) and its inverse scatter;

@@ -556,19 +556,24 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
                                                         double *__restrict__ z, int u0_end) {
     int sys, bx;
     xcd_map(sys, bx);
-    if (st && st[sys].phase != PH_RUN) return;
+    // The fused sweep opens an iteration, which is queued only while the
+    // system runs (or past its end, rarely): its phase test waits until the
+    // walk's loads are in flight.  The other sweep may follow a half-step
+    // stop and tests first.
+    if (!FUSE_P && st && st[sys].phase != PH_RUN) return;
+    const bool run = !FUSE_P || !st || st[sys].phase == PH_RUN;
     const RowLane rl = row_lane<W>(bx, q0, q1);
     const int qb0 = q0 + bx * W * kRowsPerWave, qb1 = min(qb0 + W * kRowsPerWave, q1);
     const size_t vo = (size_t)sys * vstride;
     const int i = rl.act ? d.lrows[rl.q] : 0;
     const int uq = (u0_end > 0 && rl.act) ? d.l2u[rl.q] : INT_MAX;
+    const size_t k = vo + 3 * (size_t)i + rl.r;
     T acc = 0;
+    double p = 0.0;
     if (rl.act) {
-        const size_t k = vo + 3 * (size_t)i + rl.r;
         if (FUSE_P) {
             const double beta = st[sys].beta, omega = st[sys].omega;
-            const double p = rv[k] + beta * (pv[k] - omega * vv[k]);
-            pv[k] = p;
+            p = rv[k] + beta * (pv[k] - omega * vv[k]);
             acc = (T)p;
         } else {
             acc = (T)in[k];
@@ -576,7 +581,12 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
     }
     acc = row_walk<W, STAGE, kSweepCapPerWave, true>(d.lptr, d.lcol, L + (size_t)sys * l_stride, qb0, qb1, rl, y + vo,
                                                      acc);
-    if (rl.act) y[vo + 3 * (size_t)i + rl.r] = acc;
+    if (FUSE_P) {
+        asm volatile("" ::"v"(acc));
+        if (!run) return;
+        if (rl.act) pv[k] = p;
+    }
+    if (rl.act) y[k] = acc;
     if (u0_end > 0) {
         // rows without upper blocks (the first level of the upper sweep)
         // finish here: z_i = inv(U_ii) y_i, the arithmetic of k_usweep
@@ -592,10 +602,14 @@ template <typename T, int W, bool STAGE>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRowWavesPerEU, 8))) k_usweep(DevSchedule d, const T *__restrict__ U, size_t u_stride,
                                                         const T *__restrict__ Dinv, size_t d_stride,
                                                         const T *__restrict__ y, double *__restrict__ z,
-                                                        size_t vstride, SysState *__restrict__ st, int q0, int q1) {
+                                                        size_t vstride, SysState *__restrict__ st, int q0, int q1,
+                                                        int defer) {
     int sys, bx;
     xcd_map(sys, bx);
-    if (st && st[sys].phase != PH_RUN) return;
+    // defer: the phase test waits until the walk's loads are in flight
+    // (the sweep of an iteration's first application, as in k_lsweep)
+    if (!defer && st && st[sys].phase != PH_RUN) return;
+    const bool run = !st || st[sys].phase == PH_RUN;
     const RowLane rl = row_lane<W>(bx, q0, q1);
     const int qb0 = q0 + bx * W * kRowsPerWave, qb1 = min(qb0 + W * kRowsPerWave, q1);
     const size_t vo = (size_t)sys * vstride;
@@ -603,6 +617,8 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
     T acc = rl.act ? y[vo + 3 * (size_t)i + rl.r] : (T)0;
     acc = row_walk<W, STAGE, kSweepCapPerWave, true>(d.uptr, d.ucol, U + (size_t)sys * u_stride, qb0, qb1, rl, z + vo,
                                                      acc);
+    asm volatile("" ::"v"(acc));
+    if (!run) return;
     const T t0 = __shfl(acc, rl.base, 64), t1 = __shfl(acc, rl.base + 1, 64), t2 = __shfl(acc, rl.base + 2, 64);
     if (!rl.act) return;
     const T *dq = Dinv + (size_t)sys * d_stride + (size_t)rl.q * 9 + 3 * rl.r;
@@ -1200,13 +1216,15 @@ void launch_lsweep(const DevSchedule &d, const T *L, size_t l_stride, const doub
 
 template <typename T>
 void launch_usweep(const DevSchedule &d, const T *U, size_t u_stride, const T *Dinv, size_t d_stride, const T *y,
-                   double *z, size_t vstride, SysState *st, int q0, int q1, int nsys, int variant, hipStream_t s) {
+                   double *z, size_t vstride, SysState *st, int q0, int q1, int nsys, int variant, bool defer,
+                   hipStream_t s) {
     if (q1 <= q0 || nsys <= 0) return;
     with_variant(variant, [&](auto W, auto ST) {
         constexpr int w = decltype(W)::value;
         constexpr bool staged = decltype(ST)::value;
         k_usweep<T, w, staged><<<dim3(row_blocks(q1 - q0, w), nsys), 64 * w, 0, s>>>(d, U, u_stride, Dinv, d_stride, y,
-                                                                                   z, vstride, st, q0, q1);
+                                                                                   z, vstride, st, q0, q1,
+                                                                                   defer ? 1 : 0);
     });
 }
 
@@ -1217,9 +1235,10 @@ template void launch_lsweep<float>(const DevSchedule &, const float *, size_t, c
                                    const double *, const double *, double *, SysState *, int, int, int, int,
                                    const float *, size_t, double *, int, hipStream_t);
 template void launch_usweep<double>(const DevSchedule &, const double *, size_t, const double *, size_t,
-                                    const double *, double *, size_t, SysState *, int, int, int, int, hipStream_t);
+                                    const double *, double *, size_t, SysState *, int, int, int, int, bool,
+                                    hipStream_t);
 template void launch_usweep<float>(const DevSchedule &, const float *, size_t, const float *, size_t, const float *,
-                                   double *, size_t, SysState *, int, int, int, int, hipStream_t);
+                                   double *, size_t, SysState *, int, int, int, int, bool, hipStream_t);
 
 template <typename T>
 void launch_lsweep_tiles(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
@@ -1263,7 +1282,7 @@ template void launch_usweep_tiles<float>(const DevSchedule &, const float *, siz
 template <int MODE>
 static void spmv_any(int variant, int n, const int32_t *ptr, const int32_t *col, const double *A, size_t a_stride,
                      const double *x, double *y, size_t vstride, const double *w1, double *part, size_t part_stride,
-                     uint32_t *tk, size_t tk_stride, SysState *st, int nsys, bool split, const WellsDev &wl,
+                     uint32_t *tk, size_t tk_stride, SysState *st, int nsys, int split, const WellsDev &wl,
                      hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     if (wl.nw > 0) launch_wells_t2(wl, x, vstride, nsys, s);
     int waves = 1;
@@ -1275,12 +1294,12 @@ static void spmv_any(int variant, int n, const int32_t *ptr, const int32_t *col,
         if (ev0)
             hipExtLaunchKernelGGL(k_spmv<MODE, w, staged>, g, b, 0, s, ev0, ev1, 0, n, ptr, col, A, a_stride, x, y,
                                   vstride, w1, (const double *)nullptr, part, part_stride, tk, tk_stride, st,
-                                  split ? 1 : 0, wl);
+                                  split, wl);
         else
             k_spmv<MODE, w, staged><<<g, b, 0, s>>>(n, ptr, col, A, a_stride, x, y, vstride, w1, nullptr, part,
-                                                    part_stride, tk, tk_stride, st, split ? 1 : 0, wl);
+                                                    part_stride, tk, tk_stride, st, split, wl);
     });
-    if (MODE != SPMV_PLAIN && split)
+    if (MODE != SPMV_PLAIN && (split == 1 || (split == 2 && MODE == SPMV_TRUE)))
         k_spmv_total<MODE><<<dim3(1, nsys), kTotalThreads, 0, s>>>(part, part_stride, waves, st);
 }
 
@@ -1302,23 +1321,23 @@ void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad
 }
 
 void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
-                   bool split, const WellsDev &w, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                   int split, const WellsDev &w, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     spmv_any<SPMV_V>(variant, d.n, d.prow, d.pcol, Ap, a_stride, k.phat, k.v, k.vstride, k.rhat, k.spart,
                      k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, w, s, ev0, ev1);
 }
 
-void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, bool split, hipStream_t s) {
+void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, int split, hipStream_t s) {
     const SpmvSums at = spmv_sums(n, variant_waves(spmv_variant), split);
     k_s_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(k, at.offset, at.count);
 }
 
 void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
-                   bool split, const WellsDev &w, hipStream_t s) {
+                   int split, const WellsDev &w, hipStream_t s) {
     spmv_any<SPMV_T>(variant, d.n, d.prow, d.pcol, Ap, a_stride, k.shat, k.t, k.vstride, k.s, k.spart,
                      k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, w, s);
 }
 
-void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, bool split, hipStream_t s) {
+void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, int split, hipStream_t s) {
     const SpmvSums at = spmv_sums(n, variant_waves(spmv_variant), split);
     k_xr_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(k, at.offset, at.count);
 }
@@ -1332,7 +1351,7 @@ void launch_permute_vec(const int32_t *perm, const double *in, double *out, int 
 
 void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *colidx, const double *A,
                    size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, int variant,
-                   bool split, const WellsDev &w, hipStream_t s) {
+                   int split, const WellsDev &w, hipStream_t s) {
     if (d.n <= 0 || nsys <= 0) return;
     launch_permute_vec(d.perm, k.x, x_orig, d.n, k.vstride, nsys, true, s);
     spmv_any<SPMV_TRUE>(variant, d.n, rowptr, colidx, A, a_stride, x_orig, nullptr, 3 * (size_t)d.n, b_orig, k.part,

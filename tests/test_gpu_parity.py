@@ -552,7 +552,7 @@ def test_reduce_split_modes_match_the_oracle(solver_of, variant):
     xo, oinfo = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=rs.ORDER_GRAPH_COLOUR,
                              reduction=1e-10)
     rs.ilu0_set_option(M, rs.OPT_SPMV_VARIANT, variant)
-    for split in (0, 1):
+    for split in (0, 1, 2):
         rs.ilu0_set_option(M, rs.OPT_REDUCE_SPLIT, split)
         assert rs.ilu0_get_option(M, rs.OPT_REDUCE_SPLIT) == split
         x1, st1, i1 = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-10)
