@@ -83,6 +83,8 @@ def lib():
                                        ct.POINTER(Info), _I32P, ct.POINTER(ci), ct.POINTER(ci)]
         L.orc_jacobi_matrix.argtypes = [ci, _I32P, _I32P, _F64P, _I32P, _I32P, _I32P, _F64P]
         L.orc_wells_apply.argtypes = [ci, _I32P, _I32P, _F64P, _F64P, _F64P, _F64P, _F64P]
+        L.orc_gmres.argtypes = [ci, _I32P, _I32P, _F64P, _F64P, _F64P, ci, _F64P, ci, cd, ci, _F64P,
+                                ct.POINTER(Info), vp]
         L.orc_wells_apply.restype = None
         L.orc_solve_wells.argtypes = [ci, _I32P, _I32P, _F64P, vp, ci, vp, vp, vp, vp, vp, _F64P, ci, ci, cd, ci,
                                       _F64P, ct.POINTER(Info), _I32P, ct.POINTER(ci), ct.POINTER(ci)]
@@ -190,6 +192,45 @@ def wells_apply(well_ptr, perf_row, B, C, Dinv, x, y):
     lib().orc_wells_apply(len(well_ptr) - 1, _i32(well_ptr), _i32(perf_row), _f64(B), _f64(C), _f64(Dinv),
                           _f64(x).reshape(n, 3), y.reshape(n, 3))
     return y
+
+
+def gmres(rowptr, colidx, vals, lu, dinv, b, *, precond=PREC_ILU_F64, restart=30, reduction=1e-2, max_iter=200,
+          trace=False):
+    """Right-preconditioned GMRES(restart) on an already ordered system.
+    Returns (x, info dict[, residual estimate after every Arnoldi step])."""
+    n = len(rowptr) - 1
+    x = np.zeros((n, 3), np.float64)
+    info = Info()
+    tr = np.zeros(max(max_iter, 1), np.float64) if trace else None
+    lu = _f64(lu) if lu is not None else np.zeros((max(len(colidx), 1), 3, 3))
+    dinv = _f64(dinv) if dinv is not None else np.zeros((max(n, 1), 3, 3))
+    lib().orc_gmres(n, _i32(rowptr), _i32(colidx), _f64(vals), lu, dinv, precond, _f64(b).reshape(n, 3),
+                    int(restart), reduction, max_iter, x, ct.byref(info), tr.ctypes.data if tr is not None else None)
+    if trace:
+        return x, info.as_dict(), tr[:info.half_steps]
+    return x, info.as_dict()
+
+
+def solve_gmres(rowptr, colidx, vals, b, *, ordering=ORDER_NATURAL, precond=PREC_ILU_F64, restart=30,
+                reduction=1e-2, max_iter=200):
+    """The whole path with GMRES: ordering, reordered copy, ILU0, GMRES,
+    x back in the original order, true residual with the original A."""
+    perm = ordering_perm(rowptr, colidx, ordering)
+    prow, pcol, pv = permute(rowptr, colidx, vals, perm)
+    lu = dinv = None
+    if precond != PREC_NONE:
+        st, bad, lu, dinv = ilu0(prow, pcol, pv)
+        if st != OK:
+            return np.zeros((len(rowptr) - 1, 3)), {"status": st, "bad_row": int(perm[bad]) if bad >= 0 else -1}
+    b = _f64(b).reshape(-1, 3)
+    xp, info = gmres(prow, pcol, pv, lu, dinv, b[perm], precond=precond, restart=restart, reduction=reduction,
+                     max_iter=max_iter)
+    x = np.empty_like(xp)
+    x[perm] = xp
+    r = b - spmv(rowptr, colidx, vals, x)
+    info["true_rel_residual"] = float(np.linalg.norm(r) / np.linalg.norm(b)) if np.linalg.norm(b) > 0 else 0.0
+    info["perm"] = perm
+    return x, info
 
 
 def jacobi_matrix(rowptr, colidx, vals, part):

@@ -43,6 +43,13 @@
  *     Algorithm 5): the operator is y = A x - sum over wells of
  *     C^T D^-1 B x; B and C hold one 4x3 block per perforated cell, D^-1 is
  *     one 4x4 block per well.  The preconditioner is ILU0 of A alone.
+ *   - Restarted GMRES, the simulator's other Krylov solver (Section "OPM
+ *     Flow": bicgstab by default, or restarted GMRES): not written out in
+ *     the paper; right-preconditioned GMRES(m) as in Saad, "Iterative
+ *     Methods for Sparse Linear Systems" (GMRES with right
+ *     preconditioning), x0 = 0, Arnoldi with classical Gram-Schmidt applied
+ *     twice, Givens rotations for the small least-squares problem, the same
+ *     relative-reduction test on the residual estimate after every step.
  *   - Zero-diagonal check (Section "Profiling", runtime breakdown table):
  *     a missing diagonal block is a pattern error; a singular diagonal block
  *     during the decomposition is a zero pivot.
@@ -740,4 +747,122 @@ out:
     free(key); free(perm); free(prow); free(pcol); free(pvals); free(lu); free(dinv);
     free(pb); free(px); free(ax); free(jrow); free(jcol); free(jvals); free(mrow); free(mcol);
     return st;
+}
+
+/* ------------------------------------------------------------------ GMRES */
+
+/* Right-preconditioned GMRES(m) on an already ordered system, x0 = 0.  Each
+ * cycle: v_1 = r / ||r||; for j = 1..m: z = M^-1 v_j, w = A z; Gram-Schmidt
+ * of w against v_1..v_j twice (classical: all coefficients from the same w,
+ * then w -= V h; the second pass repeats it and adds its coefficients);
+ * h_{j+1,j} = ||w||; earlier Givens rotations applied to column j, a new one
+ * zeroes h_{j+1,j}; |g_{j+1}| is the residual norm of the current iterate.
+ * Stop when it is <= reduction * ||b||, after max_iter steps in total, or
+ * on h_{j+1,j} = 0; then y = H^-1 g (back substitution) and
+ * x += M^-1 (V y).  A cycle that ends otherwise restarts from the explicit
+ * residual r = b - A x.  info->half_steps counts the Arnoldi steps (one
+ * preconditioner application and one product with A each).  trace
+ * (optional): |g_{j+1}| after every step. */
+int orc_gmres(int n, const int *rowptr, const int *colidx, const double *vals, const double *lu, const double *dinv,
+              int precond_kind, const double *b, int m, double reduction, int max_iter, double *x, orc_info *info,
+              double *trace)
+{
+    size_t n3 = 3 * (size_t)n, nb = n3 > 0 ? n3 : 1;
+    if (m < 1) m = 1;
+    precond pc = {precond_kind, n, rowptr, colidx, lu, dinv, NULL, NULL};
+    float *lu32 = NULL, *dinv32 = NULL;
+    if (precond_kind == ORC_PREC_ILU_F32) {
+        size_t nnz = (size_t)rowptr[n];
+        lu32 = malloc(sizeof(float) * 9 * (nnz > 0 ? nnz : 1));
+        dinv32 = malloc(sizeof(float) * 9 * (size_t)(n > 0 ? n : 1));
+        for (size_t e = 0; e < 9 * nnz; ++e) lu32[e] = (float)lu[e];
+        for (size_t e = 0; e < 9 * (size_t)n; ++e) dinv32[e] = (float)dinv[e];
+        pc.lu32 = lu32;
+        pc.dinv32 = dinv32;
+    }
+    double *V = malloc(sizeof(double) * nb * (size_t)(m + 1)), *z = malloc(sizeof(double) * nb);
+    double *w = malloc(sizeof(double) * nb), *r = malloc(sizeof(double) * nb);
+    double *H = calloc((size_t)(m + 1) * m, sizeof(double)), *cs = malloc(sizeof(double) * m);
+    double *sn = malloc(sizeof(double) * m), *g = malloc(sizeof(double) * (m + 1));
+    double *h = malloc(sizeof(double) * (m + 1)), *y = malloc(sizeof(double) * m);
+    int status = ORC_NOT_CONVERGED, steps = 0;
+    for (size_t e = 0; e < n3; ++e) { x[e] = 0.0; r[e] = b[e]; }
+    double beta = sqrt(dot((int)n3, r, r));
+    const double tol = reduction * beta;
+    double last = beta;
+    info->r0_norm = beta;
+    if (!isfinite(beta)) { status = ORC_NON_FINITE; goto done; }
+    if (beta == 0.0) { status = ORC_OK; goto done; }
+    for (;;) {
+        for (size_t e = 0; e < n3; ++e) V[e] = r[e] / beta;
+        for (int i = 0; i <= m; ++i) g[i] = 0.0;
+        g[0] = beta;
+        int jend = 0, stop = 0;
+        double hn = 0.0;
+        for (int j = 0; j < m; ++j) {
+            double *vj = V + (size_t)j * nb;
+            prec_apply(&pc, vj, z);
+            orc_spmv(n, rowptr, colidx, vals, z, w);
+            for (int i = 0; i <= j; ++i) H[i + (size_t)j * (m + 1)] = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int i = 0; i <= j; ++i) h[i] = dot((int)n3, w, V + (size_t)i * nb);
+                for (size_t e = 0; e < n3; ++e) {
+                    double acc = w[e];
+                    for (int i = 0; i <= j; ++i) acc -= h[i] * V[(size_t)i * nb + e];
+                    w[e] = acc;
+                }
+                for (int i = 0; i <= j; ++i) H[i + (size_t)j * (m + 1)] += h[i];
+            }
+            hn = sqrt(dot((int)n3, w, w));
+            double *col = H + (size_t)j * (m + 1);
+            col[j + 1] = hn;
+            for (int k = 0; k < j; ++k) {
+                const double t = cs[k] * col[k] + sn[k] * col[k + 1];
+                col[k + 1] = -sn[k] * col[k] + cs[k] * col[k + 1];
+                col[k] = t;
+            }
+            const double d = sqrt(col[j] * col[j] + col[j + 1] * col[j + 1]);
+            cs[j] = d > 0.0 ? col[j] / d : 1.0;
+            sn[j] = d > 0.0 ? col[j + 1] / d : 0.0;
+            col[j] = d;
+            col[j + 1] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++steps;
+            jend = j + 1;
+            last = fabs(g[j + 1]);
+            if (trace) trace[steps - 1] = last;
+            if (!isfinite(last) || !isfinite(hn)) { status = ORC_NON_FINITE; goto done; }
+            if (last <= tol) { status = ORC_OK; stop = 1; break; }
+            if (steps >= max_iter) { stop = 1; break; }
+            if (hn == 0.0) break;
+            for (size_t e = 0; e < n3; ++e) V[(size_t)(j + 1) * nb + e] = w[e] / hn;
+        }
+        for (int i = jend - 1; i >= 0; --i) {
+            double acc = g[i];
+            for (int k = i + 1; k < jend; ++k) acc -= H[i + (size_t)k * (m + 1)] * y[k];
+            y[i] = acc / H[i + (size_t)i * (m + 1)];
+        }
+        for (size_t e = 0; e < n3; ++e) {
+            double acc = 0.0;
+            for (int i = 0; i < jend; ++i) acc += y[i] * V[(size_t)i * nb + e];
+            w[e] = acc;
+        }
+        prec_apply(&pc, w, z);
+        for (size_t e = 0; e < n3; ++e) x[e] += z[e];
+        if (stop) break;
+        orc_spmv(n, rowptr, colidx, vals, x, w);
+        for (size_t e = 0; e < n3; ++e) r[e] = b[e] - w[e];
+        beta = sqrt(dot((int)n3, r, r));
+        last = beta;
+        if (!isfinite(beta)) { status = ORC_NON_FINITE; break; }
+        if (beta <= tol) { status = ORC_OK; break; }
+    }
+done:
+    info->status = status;
+    info->half_steps = steps;
+    info->final_norm = last;
+    free(lu32); free(dinv32); free(V); free(z); free(w); free(r); free(H); free(cs); free(sn); free(g); free(h);
+    free(y);
+    return status;
 }

@@ -532,3 +532,72 @@ def test_no_wells_is_plain():
     x2, i2 = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=oracle.ORDER_LEVEL, reduction=1e-10,
                           wells=empty)
     assert np.array_equal(x1, x2) and i1["half_steps"] == i2["half_steps"]
+
+
+# ------------------------------------------------------------------- GMRES
+
+def test_gmres_estimate_is_the_minimal_residual_over_the_krylov_space():
+    """After k steps |g_k| equals ||b - A x_k|| of the returned iterate, and
+    that is the least-squares minimum over the Krylov space of A M^-1 (brute
+    force with dense matrices)."""
+    s = make_grid_system(5, 4, 3, seed=61)
+    n3 = 3 * s.n
+    st, _, lu, dinv = oracle.ilu0(s.rowptr, s.colidx, s.vals[0])
+    A = to_dense(s.rowptr, s.colidx, s.vals[0])
+    Minv = np.column_stack([oracle.apply(s.rowptr, s.colidx, lu, dinv, e.reshape(-1, 3)).ravel()
+                            for e in np.eye(n3)])
+    AM = A @ Minv
+    b = s.b[0, 0].ravel()
+    prev = np.inf
+    for k in range(1, 6):
+        x, info, tr = oracle.gmres(s.rowptr, s.colidx, s.vals[0], lu, dinv, b, restart=30, reduction=0.0,
+                                   max_iter=k, trace=True)
+        assert info["half_steps"] == k and len(tr) == k
+        true = np.linalg.norm(b - A @ x.ravel())
+        assert abs(true - tr[-1]) <= 1e-10 * np.linalg.norm(b)
+        K = np.column_stack([np.linalg.matrix_power(AM, i) @ b for i in range(k)])
+        c, *_ = np.linalg.lstsq(AM @ K, b, rcond=None)
+        best = np.linalg.norm(b - AM @ K @ c)
+        assert abs(best - tr[-1]) <= 1e-8 * np.linalg.norm(b)
+        assert tr[-1] <= prev * (1 + 1e-12)          # minimal residual: never grows within a cycle
+        prev = tr[-1]
+
+
+def test_gmres_finite_termination_with_three_eigenvalues():
+    """Unpreconditioned GMRES on a matrix with three distinct eigenvalues
+    (diagonal blocks diag(1, 2, 3)) is exact after three steps."""
+    n = 10
+    rowptr, colidx = chain_pattern(n)
+    vals = np.zeros((len(colidx), 3, 3))
+    for i in range(n):
+        for p in range(rowptr[i], rowptr[i + 1]):
+            if colidx[p] == i:
+                vals[p] = np.diag([1.0, 2.0, 3.0])
+    b = np.random.default_rng(62).standard_normal((n, 3))
+    x, info = oracle.gmres(rowptr, colidx, vals, None, None, b, precond=oracle.PREC_NONE, restart=30,
+                           reduction=1e-14, max_iter=10)
+    assert info["status"] == oracle.OK and info["half_steps"] == 3
+    assert np.allclose(x, b / np.array([1.0, 2.0, 3.0]), rtol=1e-13, atol=0)
+
+
+def test_gmres_exact_preconditioner_one_step():
+    rowptr, colidx = chain_pattern(12)
+    vals = random_values(rowptr, colidx, seed=63)
+    st, _, lu, dinv = oracle.ilu0(rowptr, colidx, vals)
+    b = np.random.default_rng(64).standard_normal((12, 3))
+    x, info = oracle.gmres(rowptr, colidx, vals, lu, dinv, b, restart=30, reduction=1e-12, max_iter=10)
+    assert info["status"] == oracle.OK and info["half_steps"] == 1
+    A = to_dense(rowptr, colidx, vals)
+    assert np.linalg.norm(A @ x.ravel() - b.ravel()) <= 1e-12 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("restart", [2, 30])
+def test_gmres_dense_solve(restart):
+    s = make_grid_system(10, 8, 6, nnc_frac=0.03, seed=65)
+    A = to_dense(s.rowptr, s.colidx, s.vals[0])
+    xr = np.linalg.solve(A, s.b[0, 0].ravel())
+    for ordering in (oracle.ORDER_NATURAL, oracle.ORDER_LEVEL, oracle.ORDER_COLOUR):
+        x, info = oracle.solve_gmres(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=ordering, restart=restart,
+                                     reduction=1e-12, max_iter=500)
+        assert info["status"] == oracle.OK and info["true_rel_residual"] <= 1e-11
+        assert np.linalg.norm(x.ravel() - xr) / np.linalg.norm(xr) < 1e-9
