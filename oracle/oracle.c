@@ -757,10 +757,11 @@ out:
  * then w -= V h; the second pass repeats it and adds its coefficients);
  * h_{j+1,j} = ||w||; earlier Givens rotations applied to column j, a new one
  * zeroes h_{j+1,j}; |g_{j+1}| is the residual norm of the current iterate.
- * Stop when it is <= reduction * ||b||, after max_iter steps in total, or
- * on h_{j+1,j} = 0; then y = H^-1 g (back substitution) and
- * x += M^-1 (V y).  A cycle that ends otherwise restarts from the explicit
- * residual r = b - A x.  info->half_steps counts the Arnoldi steps (one
+ * A cycle ends when it is <= reduction * ||b||, after max_iter steps in
+ * total (none when max_iter <= 0), on h_{j+1,j} = 0, or after m steps; then
+ * y = H^-1 g (back substitution) and x += M^-1 (V y).  The first two end
+ * the solve; otherwise the next cycle starts from the explicit residual
+ * r = b - A x (and the solve ends if its norm meets the test).  info->half_steps counts the Arnoldi steps (one
  * preconditioner application and one product with A each).  trace
  * (optional): |g_{j+1}| after every step. */
 int orc_gmres(int n, const int *rowptr, const int *colidx, const double *vals, const double *lu, const double *dinv,
@@ -793,6 +794,7 @@ int orc_gmres(int n, const int *rowptr, const int *colidx, const double *vals, c
     info->r0_norm = beta;
     if (!isfinite(beta)) { status = ORC_NON_FINITE; goto done; }
     if (beta == 0.0) { status = ORC_OK; goto done; }
+    if (max_iter <= 0) goto done;
     for (;;) {
         for (size_t e = 0; e < n3; ++e) V[e] = r[e] / beta;
         for (int i = 0; i <= m; ++i) g[i] = 0.0;

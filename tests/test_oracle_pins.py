@@ -601,3 +601,34 @@ def test_gmres_dense_solve(restart):
                                      reduction=1e-12, max_iter=500)
         assert info["status"] == oracle.OK and info["true_rel_residual"] <= 1e-11
         assert np.linalg.norm(x.ravel() - xr) / np.linalg.norm(xr) < 1e-9
+
+
+def test_gmres_restart_one_is_the_minimal_residual_iteration():
+    """GMRES(1) restarts after every step from the explicit residual, so it is
+    the preconditioned minimal residual iteration x += a M^-1 r with
+    a = (A M^-1 r, r) / ||A M^-1 r||^2 (written out with dense matrices)."""
+    s = make_grid_system(5, 4, 3, seed=66)
+    n3 = 3 * s.n
+    st, _, lu, dinv = oracle.ilu0(s.rowptr, s.colidx, s.vals[0])
+    A = to_dense(s.rowptr, s.colidx, s.vals[0])
+    Minv = np.column_stack([oracle.apply(s.rowptr, s.colidx, lu, dinv, e.reshape(-1, 3)).ravel()
+                            for e in np.eye(n3)])
+    b = s.b[0, 0].ravel()
+    xr = np.zeros(n3)
+    for k in range(1, 7):
+        r = b - A @ xr
+        q = A @ (Minv @ r)
+        xr = xr + (q @ r) / (q @ q) * (Minv @ r)
+        x, info = oracle.gmres(s.rowptr, s.colidx, s.vals[0], lu, dinv, b, restart=1, reduction=0.0, max_iter=k)
+        assert info["half_steps"] == k
+        assert np.linalg.norm(x.ravel() - xr) <= 1e-11 * np.linalg.norm(xr)
+        assert abs(info["final_norm"] - np.linalg.norm(b - A @ xr)) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_gmres_no_steps():
+    s = make_grid_system(4, 3, 2, seed=67)
+    st, _, lu, dinv = oracle.ilu0(s.rowptr, s.colidx, s.vals[0])
+    x, info = oracle.gmres(s.rowptr, s.colidx, s.vals[0], lu, dinv, s.b[0, 0], restart=5, max_iter=0)
+    assert info["status"] == oracle.NOT_CONVERGED and info["half_steps"] == 0 and not x.any()
+    x, info = oracle.gmres(s.rowptr, s.colidx, s.vals[0], lu, dinv, np.zeros((s.n, 3)), restart=5, max_iter=10)
+    assert info["status"] == oracle.OK and info["half_steps"] == 0 and not x.any()
