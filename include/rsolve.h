@@ -98,10 +98,11 @@ enum rs_option {
                                 adds them (few partials: small systems) */
 };
 
-/* Per-system outcome of bicgstab_solve. */
+/* Per-system outcome of bicgstab_solve and gmres_solve. */
 typedef struct {
     int32_t status;            /* rs_status of this system */
-    int32_t half_steps;        /* 2i-1 when stopping at the half step of iteration i, 2i at its end */
+    int32_t half_steps;        /* BiCGStab: 2i-1 when stopping at the half step of iteration i, 2i at
+                                  its end; GMRES: Arnoldi steps */
     double r0_norm;            /* ||b||_2 (x0 = 0) */
     double final_norm;         /* recursively updated residual norm at the stop */
     double true_rel_residual;  /* ||b - A x||_2 / ||b||_2 with the caller's A, FP64 */
@@ -276,6 +277,28 @@ int ilu0_apply(ilu0_t M, const double *v, double *z, int32_t first_sys, int32_t 
 int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduction, int32_t max_iter,
                    int32_t mem, void *stream, solve_info *info);
 
+/* gmres_solve -- right-preconditioned restarted GMRES(restart) for every
+ * system of A, the simulator's alternative Krylov solver (Section "OPM
+ * Flow"), on the same factors, sweeps and SpMV as bicgstab_solve.  x0 = 0;
+ * each cycle builds an orthonormal basis of up to `restart` (1..32) Krylov
+ * vectors of A M^-1 (classical Gram-Schmidt applied twice) and minimises the
+ * residual over it with Givens rotations; the residual estimate is tested
+ * after every Arnoldi step against reduction * ||b||, and a cycle that ends
+ * without meeting it restarts from the explicit residual b - A x.  max_iter
+ * counts Arnoldi steps (one preconditioner application and one product with
+ * A each); info[i].half_steps receives the steps taken and final_norm the
+ * last residual estimate (or explicit residual norm after a restart).
+ * A breakdown of the basis (h_{j+1,j} = 0) zeroes the estimate, so it
+ * ends the solve as converged.
+ * b, x: batch * n_brows * 3 doubles (mem).  Workspace: restart basis
+ * vectors per system, allocated on first use and kept by the handle.
+ * Errors: RS_INVALID_ARG (also for a matrix with separate wells),
+ * RS_NOT_FACTORED, RS_PATTERN_MISMATCH, RS_OUT_OF_MEMORY, RS_HIP_ERROR.
+ * Returns the worst status over the systems, as bicgstab_solve (never
+ * RS_BREAKDOWN).  Synchronises `stream`. */
+int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart, double reduction,
+                int32_t max_iter, int32_t mem, void *stream, solve_info *info);
+
 /* ilu0_destroy -- free the handle (NULL is accepted). */
 int ilu0_destroy(ilu0_t M);
 
@@ -289,7 +312,8 @@ int ilu0_analyse_host(int32_t n_brows, const int32_t *row_ptr, const int32_t *co
  * recorded on the launch stream (bit c of mask enables class c:
  * 0 = one ILU0 factorisation, 1 = one lower sweep, 2 = one upper sweep,
  * 3 = one v = A phat launch, 4 = one vector-update launch, 5 = one
- * t = A shat launch).
+ * t = A shat launch (and GMRES's products with A), 6 = one GMRES
+ * Gram-Schmidt launch).
  * Resets the counters.  Process-wide, not thread-safe; 0 disables. */
 int rsolve_profile_enable(int32_t mask);
 

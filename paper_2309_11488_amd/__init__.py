@@ -32,12 +32,13 @@ EXPORTS = (
     "bcsr_create", "bcsr_set_values", "bcsr_set_wells", "bcsr_get_dims", "bcsr_spmv", "bcsr_set_option", "bcsr_destroy", "ilu0_analyse",
     "ilu0_get_schedule", "ilu0_get_sweep_levels", "ilu0_set_option", "ilu0_get_option", "ilu0_autotune",
     "ilu0_factor", "ilu0_get_factors", "ilu0_apply",
-    "bicgstab_solve", "ilu0_destroy", "ilu0_analyse_host", "rsolve_profile_enable", "rsolve_profile_get",
+    "bicgstab_solve", "gmres_solve", "ilu0_destroy", "ilu0_analyse_host", "rsolve_profile_enable", "rsolve_profile_get",
     "ilu0_analyse_shared", "ilu0_analyse_jacobi", "bcsr_partition", "server_create", "server_request_bytes", "server_analysis_bytes", "server_add_pattern",
     "server_submit", "server_poll", "server_wait", "server_get_stats",
     "server_destroy", "rsolve_status_string", "rsolve_last_error",
 )
-PROF_FACTOR, PROF_LSWEEP, PROF_USWEEP, PROF_SPMV_V, PROF_VEC, PROF_SPMV_T = 0, 1, 2, 3, 4, 5
+PROF_FACTOR, PROF_LSWEEP, PROF_USWEEP, PROF_SPMV_V, PROF_VEC, PROF_SPMV_T, PROF_GM = 0, 1, 2, 3, 4, 5, 6
+GMRES_MAX_RESTART = 32
 
 
 class SolveInfo(ct.Structure):
@@ -126,6 +127,7 @@ def lib():
         L.ilu0_get_factors.argtypes = [vp, i32, vp, vp]
         L.ilu0_apply.argtypes = [vp, vp, vp, i32, i32, i32, vp]
         L.bicgstab_solve.argtypes = [vp, vp, vp, vp, dbl, i32, i32, vp, vp]
+        L.gmres_solve.argtypes = [vp, vp, vp, vp, i32, dbl, i32, i32, vp, vp]
         L.ilu0_destroy.argtypes = [vp]
         L.ilu0_analyse_host.argtypes = [i32, vp, vp, i32, vp, P(i32), P(i32)]
         L.rsolve_profile_enable.argtypes = [i32]
@@ -390,6 +392,21 @@ def bicgstab_solve(M, A, b, x=None, reduction=1e-2, max_iter=200, *, stream=None
     return x, st, [i.as_dict() for i in info]
 
 
+def gmres_solve(M, A, b, x=None, restart=30, reduction=1e-2, max_iter=200, *, stream=None):
+    """Restarted GMRES on every system of A (max_iter counts Arnoldi steps).
+    Returns (x, status, [info dict per system]); half_steps = Arnoldi steps."""
+    _, _, batch = bcsr_get_dims(A)
+    if not _is_torch(b):
+        b = _host(b, np.float64)
+        if x is None:
+            x = np.zeros_like(b)
+    mem, (bp, xp) = _mem_ptr(b, x)
+    info = (SolveInfo * batch)()
+    st = lib().gmres_solve(M, A, bp, xp, int(restart), float(reduction), int(max_iter), mem, _stream(stream), info)
+    _check(st, "gmres_solve", ok=(OK, NOT_CONVERGED, NON_FINITE, ZERO_PIVOT))
+    return x, st, [i.as_dict() for i in info]
+
+
 def ilu0_destroy(M):
     if M:
         lib().ilu0_destroy(M)
@@ -437,6 +454,9 @@ class Solver:
 
     def solve(self, b, x=None, reduction=1e-2, max_iter=200):
         return bicgstab_solve(self.M, self.A, b, x, reduction, max_iter, stream=self.stream)
+
+    def solve_gmres(self, b, x=None, restart=30, reduction=1e-2, max_iter=200):
+        return gmres_solve(self.M, self.A, b, x, restart, reduction, max_iter, stream=self.stream)
 
     def close(self):
         ilu0_destroy(self.M)

@@ -94,7 +94,8 @@ hipError_t upload(DevBuf &buf, const std::vector<int32_t> &v, hipStream_t s) {
 // iteration, can be timed apart from t = A shat, which exits early in an
 // iteration that stopped at its half step.
 enum ProfClass {
-    PC_FACTOR = 0, PC_LSWEEP = 1, PC_USWEEP = 2, PC_SPMV_V = 3, PC_VEC = 4, PC_SPMV_T = 5, PC_COUNT = 6
+    PC_FACTOR = 0, PC_LSWEEP = 1, PC_USWEEP = 2, PC_SPMV_V = 3, PC_VEC = 4, PC_SPMV_T = 5, PC_GM = 6,
+    PC_COUNT = 7
 };
 
 struct Prof {
@@ -233,6 +234,9 @@ struct rs_ilu0 {
     // solve workspace
     DevBuf work, ywork, part, spart, tickets, state, bstage, xstage, flags, ctrs;
     Krylov k{};
+    // GMRES workspace: Krylov basis, per-system cycle state, reduction partials
+    DevBuf gm_basis, gm_state, gm_part;
+    int last_gm_steps = 1;
     SysState *h_state = nullptr;
     rs::SweepCtr *h_ctr = nullptr;
     int chunk = 1;
@@ -1092,6 +1096,173 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
         needed = std::max(needed, (S.half_steps + 1) / 2);
     }
     M->last_iters = needed;
+    return worst;
+}
+
+}  // extern "C"
+
+// Queue one Arnoldi step (column j) of every iterating system on `s`.
+template <typename T>
+static void gm_step(ilu0_t M, const T *L, const T *U, const T *D, const rs::GmWork &g, int j, hipStream_t s) {
+    Krylov &k = M->k;
+    const int B = M->batch;
+    const double n = M->n, nnzb = M->nnzb, vb = (double)B * 24 * n;
+    // z = M^-1 v_j, w = A z
+    apply_levels<T>(M, L, U, D, g.V + (size_t)j * g.colstride, k.phat, false, k, k.st, B, s);
+    {
+        ProfScope ps(PC_SPMV_T, s, B * (76 * nnzb + 4 * n + 48 * n));
+        rs::launch_spmv_running(M->an->dev, M->pvals.as<double>(), (size_t)M->nnzb * 9, k.phat, k.t, k.vstride, k.st,
+                                B, M->spmv_variant, M->wdev, s);
+    }
+    const int jv = j + 1;
+    { ProfScope ps(PC_GM, s, vb * (jv + 1)); rs::launch_gm_dots(g, jv, k.t, M->n, B, s); }
+    { ProfScope ps(PC_GM, s, vb * (jv + 2)); rs::launch_gm_orth(g, jv, k.t, false, M->n, B, s); }
+    { ProfScope ps(PC_GM, s, vb * (jv + 2)); rs::launch_gm_orth(g, jv, k.t, true, M->n, B, s); }
+}
+
+// End of a cycle: x += M^-1 (V y) for every system not done, then the
+// restart of those still iterating from r = P b - A x.
+template <typename T>
+static void gm_cycle_end(ilu0_t M, const T *L, const T *U, const T *D, const rs::GmWork &g, hipStream_t s) {
+    Krylov &k = M->k;
+    const int B = M->batch;
+    const double n = M->n, nnzb = M->nnzb, vb = (double)B * 24 * n;
+    { ProfScope ps(PC_VEC, s, vb * (rs::kGmMax + 1)); rs::launch_gm_combine(g, k.s, M->n, B, s); }
+    apply_levels<T>(M, L, U, D, k.s, k.phat, false, k, nullptr, B, s);
+    { ProfScope ps(PC_VEC, s, vb * 3); rs::launch_gm_xupdate(g, k.x, k.phat, M->n, B, s); }
+    rs::launch_gm_phase(g, B, s);
+    {
+        ProfScope ps(PC_SPMV_T, s, B * (76 * nnzb + 4 * n + 48 * n));
+        rs::launch_spmv_running(M->an->dev, M->pvals.as<double>(), (size_t)M->nnzb * 9, k.x, k.t, k.vstride, k.st, B,
+                                M->spmv_variant, M->wdev, s);
+    }
+    { ProfScope ps(PC_VEC, s, vb * 3); rs::launch_gm_restart(g, k.rhat, k.t, k.r, M->n, B, s); }
+    { ProfScope ps(PC_VEC, s, vb * 2); rs::launch_gm_normalise(g, k.r, 0, 0, M->n, B, s); }
+}
+
+static void gm_step_any(ilu0_t M, const rs::GmWork &g, int j, hipStream_t s) {
+    if (M->precision == RS_PREC_FP32_FACTORS)
+        gm_step<float>(M, M->Lf.as<float>(), M->Uf.as<float>(), M->Dinvf.as<float>(), g, j, s);
+    else
+        gm_step<double>(M, M->L.as<double>(), M->U.as<double>(), M->Dinv.as<double>(), g, j, s);
+}
+
+static void gm_cycle_end_any(ilu0_t M, const rs::GmWork &g, hipStream_t s) {
+    if (M->precision == RS_PREC_FP32_FACTORS)
+        gm_cycle_end<float>(M, M->Lf.as<float>(), M->Uf.as<float>(), M->Dinvf.as<float>(), g, s);
+    else
+        gm_cycle_end<double>(M, M->L.as<double>(), M->U.as<double>(), M->Dinv.as<double>(), g, s);
+}
+
+extern "C" {
+
+int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart, double reduction, int32_t max_iter,
+                int32_t mem, void *stream, solve_info *info) {
+    int st = check_pair(M, A);
+    if (st != RS_OK) return st;
+    if (!b || !x || !(reduction >= 0.0) || max_iter < 0 || restart < 1 || restart > rs::kGmMax ||
+        (mem != RS_MEM_HOST && mem != RS_MEM_DEVICE))
+        return fail(RS_INVALID_ARG, "gmres_solve: bad arguments");
+    if (!M->factored) return fail(RS_NOT_FACTORED, "gmres_solve: call ilu0_factor first");
+    if (A->nw > 0) return fail(RS_INVALID_ARG, "gmres_solve: matrices with separate wells are not supported");
+    const int B = M->batch;
+    if (M->n == 0) {
+        if (info)
+            for (int i = 0; i < B; ++i) info[i] = solve_info{RS_OK, 0, 0.0, 0.0, 0.0};
+        return RS_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    st = ensure_workspace(M, s);
+    if (st != RS_OK) return st;
+    st = ensure_wells(M, A, s);
+    if (st != RS_OK) return st;
+    Krylov &k = M->k;
+    // basis: restart columns (the column a cycle's last step would add is
+    // never used); zeroed once, so the padding of every column stays zero
+    const size_t colstride = (size_t)B * k.vstride;
+    const size_t basis_bytes = (size_t)restart * colstride * sizeof(double);
+    if (!M->gm_basis.p || M->gm_basis.bytes < basis_bytes) {
+        HIP_TRY(M->gm_basis.alloc(basis_bytes));
+        HIP_TRY(hipMemsetAsync(M->gm_basis.p, 0, M->gm_basis.bytes, s));
+    }
+    HIP_TRY(M->gm_state.alloc((size_t)B * sizeof(rs::GmState)));
+    HIP_TRY(M->gm_part.alloc((size_t)B * rs::gm_part_stride() * sizeof(double)));
+    rs::GmWork g{M->gm_basis.as<double>(), colstride, k.vstride, M->gm_part.as<double>(), rs::gm_part_stride(),
+                 k.tickets, k.ticket_stride, M->gm_state.as<rs::GmState>(), k.st};
+    const size_t m = 3 * (size_t)M->n * B;
+    const double *bd = nullptr;
+    st = stage_in(b, mem, M->bstage, m, s, &bd);
+    if (st != RS_OK) return st;
+    double *xd = x;
+    if (mem != RS_MEM_DEVICE) {
+        HIP_TRY(M->xstage.alloc(m * sizeof(double)));
+        xd = M->xstage.as<double>();
+    }
+    {
+        // r = rhat = P b, x = 0, ||b||, the initial tests; the first cycle
+        // starts from v_0 = r / ||b||
+        ProfScope ps(PC_VEC, s, (double)B * 152 * M->n);
+        rs::launch_setup(M->an->dev, bd, M->bad.as<int32_t>(), reduction, max_iter, k, B, s);
+    }
+    rs::launch_gm_init(g, B, s);
+    rs::launch_gm_normalise(g, k.r, 0, 0, M->n, B, s);
+    HIP_TRY(hipGetLastError());
+    auto poll = [&](bool &any_run, bool &all_done) -> int {
+        HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        any_run = false;
+        all_done = true;
+        for (int i = 0; i < B; ++i) {
+            any_run |= M->h_state[i].phase == rs::PH_RUN;
+            all_done &= M->h_state[i].phase == rs::PH_DONE;
+        }
+        return RS_OK;
+    };
+    bool any_run = true, all_done = false;
+    st = poll(any_run, all_done);
+    if (st != RS_OK) return st;
+    // Every cycle advances each system not yet done by at least one step,
+    // so max_iter + 1 cycles always suffice.
+    long long queued = 0;
+    long long next_poll = M->predict ? std::max(M->chunk, M->last_gm_steps) : M->chunk;
+    for (int cycle = 0; !all_done && cycle <= max_iter; ++cycle) {
+        for (int j = 0; j < restart; ++j) {
+            gm_step_any(M, g, j, s);
+            ++queued;
+            if (j + 1 == restart) break;
+            if (queued >= next_poll) {
+                st = poll(any_run, all_done);
+                if (st != RS_OK) return st;
+                next_poll = queued + M->chunk;
+                if (!any_run) break;
+            }
+            rs::launch_gm_normalise(g, k.t, j + 1, 1, M->n, B, s);
+        }
+        gm_cycle_end_any(M, g, s);
+        HIP_TRY(hipGetLastError());
+        st = poll(any_run, all_done);
+        if (st != RS_OK) return st;
+    }
+    rs::launch_finish(M->an->dev, A->rowptr.as<int32_t>(), A->colidx.as<int32_t>(), A->vals.as<double>(),
+                      (size_t)A->nnzb * 9, bd, xd, k, B, M->spmv_variant, M->split(), A->wells(), s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(M->h_ctr, k.lctr, 2 * sizeof(rs::SweepCtr), hipMemcpyDeviceToHost, s));
+    if (mem != RS_MEM_DEVICE) HIP_TRY(hipMemcpyAsync(x, xd, m * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (M->h_ctr[0].error || M->h_ctr[1].error) {
+        HIP_TRY(hipMemsetAsync(M->ctrs.p, 0, 2 * sizeof(rs::SweepCtr), s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return fail(RS_HIP_ERROR, "sweep dependency wait exceeded its limit");
+    }
+    int worst = RS_OK, needed = 1;
+    for (int i = 0; i < B; ++i) {
+        const SysState &S = M->h_state[i];
+        if (info) info[i] = solve_info{S.status, S.half_steps, S.r0norm, S.last_norm, S.true_res};
+        if (status_rank(S.status) > status_rank(worst)) worst = S.status;
+        needed = std::max(needed, S.half_steps);
+    }
+    M->last_gm_steps = needed;
     return worst;
 }
 

@@ -49,6 +49,18 @@ struct WellsDev {
     double *t2 = nullptr;                // per system: nw*4, D^-1 B x of the current x
 };
 
+// Restarted GMRES: per-system state of the current cycle (Hessenberg matrix
+// after the Givens rotations, the rotations, the rotated right-hand side g,
+// the Gram-Schmidt coefficients of the current pass).
+constexpr int kGmMax = 32;   // largest restart length
+struct GmState {
+    double H[kGmMax + 1][kGmMax];
+    double cs[kGmMax], sn[kGmMax], g[kGmMax + 1], h[kGmMax + 1];
+    double beta, hn;
+    int32_t jend;   // Arnoldi columns of the current cycle
+    int32_t pad;
+};
+
 // Work counter of one single-launch sweep kernel: tickets hand out (tile,
 // system) items in dependency order; the last workgroup to leave resets the
 // tickets and publishes the epoch that marks a tile as done in this sweep.
@@ -195,6 +207,48 @@ void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, int split, h
 void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *colidx, const double *A,
                    size_t a_stride, const double *b_orig, double *x_orig, Krylov &k, int nsys, int variant, int split,
                    const WellsDev &w, hipStream_t s);
+
+// y = A x on the reordered matrix for the systems still iterating (new
+// order, x and y at stride vstride), minus the separate wells.
+void launch_spmv_running(const DevSchedule &d, const double *Ap, size_t a_stride, const double *x, double *y,
+                         size_t vstride, SysState *st, int nsys, int variant, const WellsDev &w, hipStream_t s);
+
+// GMRES workspace as the kernels see it.  Vectors of all systems at stride
+// vstride; Krylov basis column c of system s at V + c * colstride + s * vstride.
+struct GmWork {
+    double *V;
+    size_t colstride, vstride;
+    double *part;        // reduction partials, pstride doubles per system
+    size_t pstride;
+    uint32_t *tickets;   // reduction counters, tkstride per system
+    size_t tkstride;
+    GmState *gm;
+    SysState *st;
+};
+inline size_t gm_part_stride() { return (size_t)(kGmMax + 1) * (kVecMaxBlocks + kVecMaxBlocks / 32 + 1) + 16; }
+
+// GMRES building blocks; each acts on the systems still iterating (phase
+// PH_RUN) unless stated otherwise.
+// A cycle's start after the setup: beta = ||r||, g = beta e_1.
+void launch_gm_init(const GmWork &g, int nsys, hipStream_t s);
+// V column `col` = src / beta (from_w = 0) or src / h_{j+1,j} (from_w = 1).
+void launch_gm_normalise(const GmWork &g, const double *src, int col, int from_w, int n, int nsys, hipStream_t s);
+// First classical Gram-Schmidt pass: h_i = (w, v_i), i < jv; column jv - 1
+// of H = h.
+void launch_gm_dots(const GmWork &g, int jv, const double *w, int n, int nsys, hipStream_t s);
+// w -= V h with the current coefficients; then either the second pass's
+// coefficients (added to H's column jv - 1) or, when `last`, ||w|| =
+// h_{jv,jv-1}, the Givens update of the column and the step's tests.
+void launch_gm_orth(const GmWork &g, int jv, double *w, bool last, int n, int nsys, hipStream_t s);
+// End of a cycle, for every system not done: y = H^-1 g, u = V y.
+void launch_gm_combine(const GmWork &g, double *u, int n, int nsys, hipStream_t s);
+// x += z for every system not done.
+void launch_gm_xupdate(const GmWork &g, double *x, const double *z, int n, int nsys, hipStream_t s);
+// After the update: PH_HALF -> PH_DONE.
+void launch_gm_phase(const GmWork &g, int nsys, hipStream_t s);
+// Restart: r = rhs - w, beta = ||r||, the reduction test, a fresh cycle.
+void launch_gm_restart(const GmWork &g, const double *rhs, const double *w, double *r, int n, int nsys,
+                       hipStream_t s);
 
 // out[i] = in[perm[i]] (gather to the new order) and its inverse scatter;
 // the new-order side has stride vstride, the caller side 3n.

@@ -795,12 +795,13 @@ __global__ void __launch_bounds__(kRowThreads) k_usweep_tiles(DevSchedule d, con
 
 // -------------------------------------------------------------------- SpMV
 
-enum SpmvMode { SPMV_PLAIN = 0, SPMV_V = 1, SPMV_T = 2, SPMV_TRUE = 3 };
+enum SpmvMode { SPMV_PLAIN = 0, SPMV_V = 1, SPMV_T = 2, SPMV_TRUE = 3, SPMV_RUN = 4 };
 
 // y = A x over rows in storage order, with the epilogue of the mode:
 //   SPMV_V:    v = A phat, reduce (rhat, v), alpha = rho / (rhat, v)
 //   SPMV_T:    t = A shat, reduce (t, s) and (t, t), omega = (t, s) / (t, t)
 //   SPMV_TRUE: reduce ||b - A x||^2 and ||b||^2, true relative residual
+//   SPMV_RUN:  y only, for the systems still iterating (GMRES)
 // ------------------------------------------------------------------ wells
 
 // (C_p^T t2_w)_r summed over the perforations of output row i, in
@@ -856,7 +857,7 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
     // half-step stop, so it tests first; v = A phat (which runs whenever its
     // iteration starts) tests once the row walk's loads are in flight, which
     // hides the latency of the test; a finished system's launch stores nothing
-    if (MODE == SPMV_T && st[sys].phase != PH_RUN) return;
+    if ((MODE == SPMV_T || MODE == SPMV_RUN) && st[sys].phase != PH_RUN) return;
     const bool run = MODE != SPMV_V || st[sys].phase == PH_RUN;
     // workgroup bx walks row tiles [bx * per, (bx + 1) * per); per = 1 with
     // one workgroup per tile
@@ -873,13 +874,13 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
         const size_t k = vo + 3 * (size_t)rl.q + rl.r;
         // the dot-product operand is loaded before the row walk, so its
         // latency overlaps the walk's
-        const double w = (MODE != SPMV_PLAIN && rl.act) ? w1[k] : 0.0;
+        const double w = (MODE != SPMV_PLAIN && MODE != SPMV_RUN && rl.act) ? w1[k] : 0.0;
         const double acc = row_walk<W, STAGE, kSpmvCapPerWave, false>(ptr, col, As, qb0, qb1, rl, x + vo, 0.0);
         asm volatile("" ::"v"(acc));   // the walk completes before the phase test below
         if (!run) return;
         if (!rl.act) continue;
         const double acc_w = wl.nw > 0 ? acc - well_terms(wl, sys, rl.q, rl.r) : acc;
-        if (MODE == SPMV_PLAIN) {
+        if (MODE == SPMV_PLAIN || MODE == SPMV_RUN) {
             y[k] = acc_w;
         } else if (MODE == SPMV_V || MODE == SPMV_T) {
             y[k] = acc_w;
@@ -891,7 +892,7 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
             v[1] += w * w;
         }
     }
-    if (MODE == SPMV_PLAIN) return;
+    if (MODE == SPMV_PLAIN || MODE == SPMV_RUN) return;
     if (split) {
         // one partial per wave (no workgroup barrier); k_spmv_total adds
         // them after the kernel boundary
@@ -1134,6 +1135,219 @@ __global__ void __launch_bounds__(kVecThreads) k_xr_update(Krylov k, int sums_at
     }
 }
 
+// ------------------------------------------------------------------ GMRES
+//
+// Right-preconditioned restarted GMRES (the simulator's alternative Krylov
+// solver, Section "OPM Flow"), x0 = 0.  All vectors in the new order, padded
+// to whole tiles with zeros.  The Arnoldi vector w is orthogonalised against
+// the cycle's basis by classical Gram-Schmidt applied twice: each pass takes
+// all its coefficients from one w (one reduction of jv dot products), so a
+// step needs three grid reductions however long the basis is.  The kernels
+// below stream w and the basis columns once per pass; every thread owns one
+// entry per 256-entry tile and tiles are grid-strided, so each thread's
+// partial sums follow a fixed order that depends only on the system size.
+// The scalar work of a step (Givens rotations, tests) runs in the workgroup
+// that completes the last reduction, after every other workgroup of its
+// launch has passed its phase test.
+
+constexpr int kGmThreads = 256;
+
+__device__ inline void gm_cycle_start(GmState &G, double beta) {
+    G.beta = beta;
+    G.g[0] = beta;
+    for (int i = 1; i <= kGmMax; ++i) G.g[i] = 0.0;
+    G.jend = 0;
+}
+
+__global__ void k_gm_init(GmWork g, int nsys) {
+    const int sys = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sys >= nsys || g.st[sys].phase != PH_RUN) return;
+    gm_cycle_start(g.gm[sys], g.st[sys].r0norm);
+}
+
+__global__ void __launch_bounds__(kGmThreads) k_gm_normalise(GmWork g, const double *__restrict__ src, int col,
+                                                             int from_w) {
+    const int sys = blockIdx.y;
+    if (g.st[sys].phase != PH_RUN) return;
+    const double sc = from_w ? g.gm[sys].hn : g.gm[sys].beta;
+    const size_t vo = (size_t)sys * g.vstride;
+    double *dst = g.V + (size_t)col * g.colstride + vo;
+    for (size_t e = (size_t)blockIdx.x * kGmThreads + threadIdx.x; e < g.vstride; e += (size_t)gridDim.x * kGmThreads)
+        dst[e] = src[vo + e] / sc;
+}
+
+// h_i = (w, v_i) for i < jv (NV >= jv).
+template <int NV>
+__global__ void __launch_bounds__(kGmThreads) k_gm_dots(GmWork g, int jv, const double *__restrict__ w) {
+    const int sys = blockIdx.y, bx = blockIdx.x;
+    if (g.st[sys].phase != PH_RUN) return;
+    const size_t vo = (size_t)sys * g.vstride;
+    const double *V = g.V + vo;
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (size_t e = (size_t)bx * kGmThreads + threadIdx.x; e < g.vstride; e += (size_t)gridDim.x * kGmThreads) {
+        double v[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = i < jv ? V[(size_t)i * g.colstride + e] : 0.0;
+        const double we = w[vo + e];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] = __builtin_fma(we, v[i], acc[i]);
+    }
+    if (grid_reduce<NV>(acc, g.part + sys * g.pstride, g.tickets + sys * g.tkstride, gridDim.x, bx) &&
+        threadIdx.x == 0) {
+        GmState &G = g.gm[sys];
+        for (int i = 0; i < jv; ++i) {
+            G.h[i] = acc[i];
+            G.H[i][jv - 1] = acc[i];
+        }
+    }
+}
+
+// The Givens step of Arnoldi column j once h_{j+1,j} = sqrt(nrm2) is known:
+// earlier rotations applied to the column, a new rotation that zeroes
+// h_{j+1,j}, the rotated right-hand side, and the tests on its last entry
+// (the residual norm of the cycle's current iterate).
+__device__ inline void gm_givens(GmState &G, SysState &S, int j, double nrm2) {
+    const double hn = sqrt(nrm2);
+    G.H[j + 1][j] = hn;
+    for (int k = 0; k < j; ++k) {
+        const double a = G.H[k][j], b = G.H[k + 1][j];
+        G.H[k][j] = G.cs[k] * a + G.sn[k] * b;
+        G.H[k + 1][j] = -G.sn[k] * a + G.cs[k] * b;
+    }
+    const double a = G.H[j][j], b = G.H[j + 1][j];
+    const double d = sqrt(a * a + b * b);
+    const double c = d > 0.0 ? a / d : 1.0, sn = d > 0.0 ? b / d : 0.0;
+    G.cs[j] = c;
+    G.sn[j] = sn;
+    G.H[j][j] = d;
+    G.H[j + 1][j] = 0.0;
+    const double gj = G.g[j];
+    G.g[j + 1] = -sn * gj;
+    G.g[j] = c * gj;
+    G.hn = hn;
+    G.jend = j + 1;
+    S.half_steps += 1;
+    const double last = fabs(G.g[j + 1]);
+    S.last_norm = last;
+    if (!finite(last) || !finite(hn)) { S.status = RS_NON_FINITE; S.phase = PH_DONE; }
+    else if (last <= S.tol) { S.status = RS_OK; S.phase = PH_HALF; }
+    else if (S.half_steps >= S.max_iter) { S.status = RS_NOT_CONVERGED; S.phase = PH_HALF; }
+    // h_{j+1,j} = 0 (the Krylov space is invariant) gives sn = 0 and a zero
+    // estimate, so the first test has already ended the solve
+}
+
+// w -= sum_i h_i v_i (i ascending), then the next pass's coefficients
+// (w, v_i) or, when LAST, ||w||^2 and the Givens step.
+template <int NV, bool LAST>
+__global__ void __launch_bounds__(kGmThreads) k_gm_orth(GmWork g, int jv, double *__restrict__ w) {
+    const int sys = blockIdx.y, bx = blockIdx.x;
+    if (g.st[sys].phase != PH_RUN) return;
+    const size_t vo = (size_t)sys * g.vstride;
+    const double *V = g.V + vo;
+    double h[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) h[i] = i < jv ? g.gm[sys].h[i] : 0.0;
+    constexpr int NA = LAST ? 1 : NV;
+    double acc[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) acc[i] = 0.0;
+    for (size_t e = (size_t)bx * kGmThreads + threadIdx.x; e < g.vstride; e += (size_t)gridDim.x * kGmThreads) {
+        double v[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = i < jv ? V[(size_t)i * g.colstride + e] : 0.0;
+        double a = w[vo + e];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) a = __builtin_fma(-h[i], v[i], a);
+        w[vo + e] = a;
+        if (LAST) {
+            acc[0] = __builtin_fma(a, a, acc[0]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < NA; ++i) acc[i] = __builtin_fma(a, v[i], acc[i]);
+        }
+    }
+    if (grid_reduce<NA>(acc, g.part + sys * g.pstride, g.tickets + sys * g.tkstride, gridDim.x, bx) &&
+        threadIdx.x == 0) {
+        GmState &G = g.gm[sys];
+        if (LAST) {
+            gm_givens(G, g.st[sys], jv - 1, acc[0]);
+        } else {
+            for (int i = 0; i < jv; ++i) {
+                G.h[i] = acc[i];
+                G.H[i][jv - 1] += acc[i];
+            }
+        }
+    }
+}
+
+// y = H^-1 g by back substitution (every workgroup the same way), u = V y.
+__global__ void __launch_bounds__(kGmThreads) k_gm_combine(GmWork g, double *__restrict__ u) {
+    const int sys = blockIdx.y;
+    if (g.st[sys].phase == PH_DONE) return;
+    __shared__ double y[kGmMax];
+    __shared__ int s_jend;
+    const GmState &G = g.gm[sys];
+    if (threadIdx.x == 0) {
+        const int jend = min(max(G.jend, 0), kGmMax);
+        for (int i = jend - 1; i >= 0; --i) {
+            double a = G.g[i];
+            for (int k = i + 1; k < jend; ++k) a -= G.H[i][k] * y[k];
+            y[i] = a / G.H[i][i];
+        }
+        s_jend = jend;
+    }
+    __syncthreads();
+    const int jend = s_jend;
+    const size_t vo = (size_t)sys * g.vstride;
+    const double *V = g.V + vo;
+    for (size_t e = (size_t)blockIdx.x * kGmThreads + threadIdx.x; e < g.vstride;
+         e += (size_t)gridDim.x * kGmThreads) {
+        double a = 0.0;
+#pragma unroll 8
+        for (int i = 0; i < jend; ++i) a = __builtin_fma(y[i], V[(size_t)i * g.colstride + e], a);
+        u[vo + e] = a;
+    }
+}
+
+__global__ void __launch_bounds__(kGmThreads) k_gm_xupdate(GmWork g, double *__restrict__ x,
+                                                           const double *__restrict__ z) {
+    const int sys = blockIdx.y;
+    if (g.st[sys].phase == PH_DONE) return;
+    const size_t vo = (size_t)sys * g.vstride;
+    for (size_t e = (size_t)blockIdx.x * kGmThreads + threadIdx.x; e < g.vstride; e += (size_t)gridDim.x * kGmThreads)
+        x[vo + e] += z[vo + e];
+}
+
+__global__ void k_gm_phase(GmWork g, int nsys) {
+    const int sys = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sys >= nsys) return;
+    if (g.st[sys].phase == PH_HALF) g.st[sys].phase = PH_DONE;
+}
+
+__global__ void __launch_bounds__(kGmThreads) k_gm_restart(GmWork g, const double *__restrict__ rhs,
+                                                           const double *__restrict__ w, double *__restrict__ r) {
+    const int sys = blockIdx.y, bx = blockIdx.x;
+    if (g.st[sys].phase != PH_RUN) return;
+    const size_t vo = (size_t)sys * g.vstride;
+    double acc[1] = {0.0};
+    for (size_t e = (size_t)bx * kGmThreads + threadIdx.x; e < g.vstride; e += (size_t)gridDim.x * kGmThreads) {
+        const double re = rhs[vo + e] - w[vo + e];
+        r[vo + e] = re;
+        acc[0] = __builtin_fma(re, re, acc[0]);
+    }
+    if (grid_reduce<1>(acc, g.part + sys * g.pstride, g.tickets + sys * g.tkstride, gridDim.x, bx) &&
+        threadIdx.x == 0) {
+        SysState &S = g.st[sys];
+        const double beta = sqrt(acc[0]);
+        S.last_norm = beta;
+        if (!finite(beta)) { S.status = RS_NON_FINITE; S.phase = PH_DONE; }
+        else if (beta <= S.tol) { S.status = RS_OK; S.phase = PH_DONE; }
+        else gm_cycle_start(g.gm[sys], beta);
+    }
+}
+
 // New-order side at stride vstride, caller side at stride 3n.
 __global__ void k_permute_vec(const int32_t *__restrict__ perm, const double *__restrict__ in,
                               double *__restrict__ out, int n, size_t vstride, int scatter) {
@@ -1299,7 +1513,7 @@ static void spmv_any(int variant, int n, const int32_t *ptr, const int32_t *col,
             k_spmv<MODE, w, staged><<<g, b, 0, s>>>(n, ptr, col, A, a_stride, x, y, vstride, w1, nullptr, part,
                                                     part_stride, tk, tk_stride, st, split, wl);
     });
-    if (MODE != SPMV_PLAIN && (split == 1 || (split == 2 && MODE == SPMV_TRUE)))
+    if (MODE != SPMV_PLAIN && MODE != SPMV_RUN && (split == 1 || (split == 2 && MODE == SPMV_TRUE)))
         k_spmv_total<MODE><<<dim3(1, nsys), kTotalThreads, 0, s>>>(part, part_stride, waves, st);
 }
 
@@ -1356,6 +1570,78 @@ void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *c
     launch_permute_vec(d.perm, k.x, x_orig, d.n, k.vstride, nsys, true, s);
     spmv_any<SPMV_TRUE>(variant, d.n, rowptr, colidx, A, a_stride, x_orig, nullptr, 3 * (size_t)d.n, b_orig, k.part,
                         k.part_stride, k.tickets, k.ticket_stride, k.st, nsys, split, w, s);
+}
+
+// ------------------------------------------------------------------ GMRES
+
+void launch_spmv_running(const DevSchedule &d, const double *Ap, size_t a_stride, const double *x, double *y,
+                         size_t vstride, SysState *st, int nsys, int variant, const WellsDev &w, hipStream_t s) {
+    if (d.n <= 0 || nsys <= 0) return;
+    spmv_any<SPMV_RUN>(variant, d.n, d.prow, d.pcol, Ap, a_stride, x, y, vstride, nullptr, nullptr, 0, nullptr, 0,
+                       st, nsys, 0, w, s);
+}
+
+// Workgroups of the GMRES vector kernels: one per 1024 entries of a padded
+// vector, at most kVecMaxBlocks (the partial buffers are sized for that).
+static int gm_blocks(int n) { return vec_blocks(n); }
+
+// Call f(NV) with the smallest compiled coefficient count >= jv.
+template <typename F>
+static void with_nv(int jv, F &&f) {
+    if (jv <= 2) f(std::integral_constant<int, 2>{});
+    else if (jv <= 4) f(std::integral_constant<int, 4>{});
+    else if (jv <= 8) f(std::integral_constant<int, 8>{});
+    else if (jv <= 16) f(std::integral_constant<int, 16>{});
+    else f(std::integral_constant<int, kGmMax + 1>{});
+}
+
+void launch_gm_init(const GmWork &g, int nsys, hipStream_t s) {
+    if (nsys <= 0) return;
+    k_gm_init<<<(nsys + 63) / 64, 64, 0, s>>>(g, nsys);
+}
+
+void launch_gm_normalise(const GmWork &g, const double *src, int col, int from_w, int n, int nsys, hipStream_t s) {
+    if (n <= 0 || nsys <= 0) return;
+    k_gm_normalise<<<dim3(gm_blocks(n), nsys), kGmThreads, 0, s>>>(g, src, col, from_w);
+}
+
+void launch_gm_dots(const GmWork &g, int jv, const double *w, int n, int nsys, hipStream_t s) {
+    if (n <= 0 || nsys <= 0 || jv < 1 || jv > kGmMax) return;
+    with_nv(jv, [&](auto NV) {
+        k_gm_dots<decltype(NV)::value><<<dim3(gm_blocks(n), nsys), kGmThreads, 0, s>>>(g, jv, w);
+    });
+}
+
+void launch_gm_orth(const GmWork &g, int jv, double *w, bool last, int n, int nsys, hipStream_t s) {
+    if (n <= 0 || nsys <= 0 || jv < 1 || jv > kGmMax) return;
+    with_nv(jv, [&](auto NV) {
+        constexpr int nv = decltype(NV)::value;
+        if (last)
+            k_gm_orth<nv, true><<<dim3(gm_blocks(n), nsys), kGmThreads, 0, s>>>(g, jv, w);
+        else
+            k_gm_orth<nv, false><<<dim3(gm_blocks(n), nsys), kGmThreads, 0, s>>>(g, jv, w);
+    });
+}
+
+void launch_gm_combine(const GmWork &g, double *u, int n, int nsys, hipStream_t s) {
+    if (n <= 0 || nsys <= 0) return;
+    k_gm_combine<<<dim3(gm_blocks(n), nsys), kGmThreads, 0, s>>>(g, u);
+}
+
+void launch_gm_xupdate(const GmWork &g, double *x, const double *z, int n, int nsys, hipStream_t s) {
+    if (n <= 0 || nsys <= 0) return;
+    k_gm_xupdate<<<dim3(gm_blocks(n), nsys), kGmThreads, 0, s>>>(g, x, z);
+}
+
+void launch_gm_phase(const GmWork &g, int nsys, hipStream_t s) {
+    if (nsys <= 0) return;
+    k_gm_phase<<<(nsys + 63) / 64, 64, 0, s>>>(g, nsys);
+}
+
+void launch_gm_restart(const GmWork &g, const double *rhs, const double *w, double *r, int n, int nsys,
+                       hipStream_t s) {
+    if (n <= 0 || nsys <= 0) return;
+    k_gm_restart<<<dim3(gm_blocks(n), nsys), kGmThreads, 0, s>>>(g, rhs, w, r);
 }
 
 }  // namespace rs
