@@ -47,7 +47,7 @@ WORKLOADS = {
 }
 ORDER = {"natural": 0, "level": 1, "colour": 2}
 PREC = {"fp64": 0, "fp32": 1}
-CLASS = {"factor": 0, "lsweep": 1, "usweep": 2, "spmv": 3, "vec": 4, "spmv_t": 5}
+CLASS = {"factor": 0, "lsweep": 1, "usweep": 2, "spmv": 3, "vec": 4, "spmv_t": 5, "gm": 6}
 
 
 def log(*a):
@@ -63,7 +63,11 @@ def parse():
     ap.add_argument("--ordering", default="colour", choices=sorted(ORDER))
     ap.add_argument("--precision", default=None, choices=sorted(PREC))
     ap.add_argument("--reduction", type=float, default=None)
-    ap.add_argument("--roofline", default="spmv", choices=sorted(CLASS))
+    ap.add_argument("--roofline", default=None, choices=sorted(CLASS),
+                    help="kernel class of the roofline object (default: spmv; gm with --solver gmres)")
+    ap.add_argument("--solver", default="bicgstab", choices=["bicgstab", "gmres"],
+                    help="Krylov solver on the same factors (gmres: restarted, --restart m)")
+    ap.add_argument("--restart", type=int, default=30, help="GMRES restart length (1..32)")
     ap.add_argument("--jacobi", type=int, default=0, metavar="P",
                     help="Block-Jacobi-ILU0 with P transmissibility-weighted partitions (0: plain ILU0)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -102,7 +106,7 @@ def measured_traffic(workload, cls):
     return ent.get("bytes_per_unit")
 
 
-def cpu_baseline(s, rhs, ordering, precision, reduction, budget_s, part=None):
+def cpu_baseline(s, rhs, ordering, precision, reduction, budget_s, part=None, restart=0):
     """The oracle as it stands, single-threaded, on whole steps of the same workload."""
     import numpy as np
 
@@ -123,8 +127,12 @@ def cpu_baseline(s, rhs, ordering, precision, reduction, budget_s, part=None):
                 mrow, mcol, mv = oracle.permute(jrow, jcol, jv, perm)
             st, _, lu, dinv = oracle.ilu0(mrow, mcol, mv)
             for j in range(rhs):
-                x, info = oracle.bicgstab(prow, pcol, pv, lu, dinv, s.b[sysk, j][perm], precond=prec,
-                                          reduction=reduction, mrow=mrow, mcol=mcol)
+                if restart:
+                    x, info = oracle.gmres(prow, pcol, pv, lu, dinv, s.b[sysk, j][perm], precond=prec,
+                                           restart=restart, reduction=reduction)
+                else:
+                    x, info = oracle.bicgstab(prow, pcol, pv, lu, dinv, s.b[sysk, j][perm], precond=prec,
+                                              reduction=reduction, mrow=mrow, mcol=mcol)
                 xo = np.empty_like(x)
                 xo[perm] = x
                 solves += 1
@@ -156,6 +164,11 @@ def main():
     from synth import config_system
 
     wl = WORKLOADS[args.workload]
+    gmres = args.solver == "gmres"
+    if gmres and args.jacobi:
+        sys.exit("bench.py: --solver gmres runs on the plain ILU0 preconditioner only")
+    if args.roofline is None:
+        args.roofline = "gm" if gmres else "spmv"
     precision = args.precision or wl["precision"]
     reduction = args.reduction if args.reduction is not None else wl["reduction"]
     ordering = ORDER[args.ordering]
@@ -195,7 +208,10 @@ def main():
         st, bad = rs.ilu0_factor(M, A, prec)
         assert st == rs.OK, (st, bad)
         for j in range(rhs):
-            _, st, info = rs.bicgstab_solve(M, A, b[j], x[j], reduction, 200)
+            if gmres:
+                _, st, info = rs.gmres_solve(M, A, b[j], x[j], args.restart, reduction, 200)
+            else:
+                _, st, info = rs.bicgstab_solve(M, A, b[j], x[j], reduction, 200)
             if record:
                 for i in info:
                     half_steps.append(i["half_steps"])
@@ -236,10 +252,12 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        v, nsol, dt = cpu_baseline(s, rhs, ordering, precision, reduction, args.cpu_seconds, part)
+        v, nsol, dt = cpu_baseline(s, rhs, ordering, precision, reduction, args.cpu_seconds, part,
+                                   args.restart if gmres else 0)
         cpu = {"value": v, "unit": "solves/s", "cores": 1, "kind": "oracle",
                "sample": f"{nsol} solves of the same workload (ordering, reordered copy, ILU0 per step, "
-                         f"then BiCGStab per right-hand side) in {dt:.1f}s, single-threaded C oracle"}
+                         f"then {'GMRES' if gmres else 'BiCGStab'} per right-hand side) in {dt:.1f}s, "
+                         f"single-threaded C oracle"}
         log(f"cpu oracle: {v:.3f} solves/s ({nsol} solves in {dt:.1f}s)")
 
     rs.ilu0_destroy(M)
@@ -252,11 +270,13 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {args.calibrate_copy} MiB read + {args.calibrate_copy} MiB written, 3 times")
     out = {
-        "metric": "BiCGStab-ILU0 solves/sec at 1e-2 reduction (HBM GB/s vs roofline of the dominant kernel)",
+        "metric": (f"GMRES({args.restart})-ILU0" if gmres else "BiCGStab-ILU0") +
+                  " solves/sec at 1e-2 reduction (HBM GB/s vs roofline of the dominant kernel)",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if precision == "fp64" else "f64+f32-factors", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl['desc']}", "ordering": args.ordering, "precision": precision,
+                   "solver": f"gmres({args.restart})" if gmres else "bicgstab",
                    "reduction": reduction, "max_iter": 200, "n_brows": s.n, "nnzb": s.nnzb, "batch": s.batch,
                    "rhs_per_step": rhs, "sets": n_sets, "sweep_levels": [nl, nu],
                    "jacobi_partitions": args.jacobi or None,

@@ -1123,11 +1123,13 @@ static void gm_step(ilu0_t M, const T *L, const T *U, const T *D, const rs::GmWo
 // End of a cycle: x += M^-1 (V y) for every system not done, then the
 // restart of those still iterating from r = P b - A x.
 template <typename T>
-static void gm_cycle_end(ilu0_t M, const T *L, const T *U, const T *D, const rs::GmWork &g, hipStream_t s) {
+static void gm_cycle_end(ilu0_t M, const T *L, const T *U, const T *D, const rs::GmWork &g, int cols,
+                         hipStream_t s) {
     Krylov &k = M->k;
     const int B = M->batch;
     const double n = M->n, nnzb = M->nnzb, vb = (double)B * 24 * n;
-    { ProfScope ps(PC_VEC, s, vb * (rs::kGmMax + 1)); rs::launch_gm_combine(g, k.s, M->n, B, s); }
+    // (cols = steps queued in the cycle, an upper bound of every system's basis)
+    { ProfScope ps(PC_VEC, s, vb * (cols + 1)); rs::launch_gm_combine(g, k.s, M->n, B, s); }
     apply_levels<T>(M, L, U, D, k.s, k.phat, false, k, nullptr, B, s);
     { ProfScope ps(PC_VEC, s, vb * 3); rs::launch_gm_xupdate(g, k.x, k.phat, M->n, B, s); }
     rs::launch_gm_phase(g, B, s);
@@ -1147,11 +1149,11 @@ static void gm_step_any(ilu0_t M, const rs::GmWork &g, int j, hipStream_t s) {
         gm_step<double>(M, M->L.as<double>(), M->U.as<double>(), M->Dinv.as<double>(), g, j, s);
 }
 
-static void gm_cycle_end_any(ilu0_t M, const rs::GmWork &g, hipStream_t s) {
+static void gm_cycle_end_any(ilu0_t M, const rs::GmWork &g, int cols, hipStream_t s) {
     if (M->precision == RS_PREC_FP32_FACTORS)
-        gm_cycle_end<float>(M, M->Lf.as<float>(), M->Uf.as<float>(), M->Dinvf.as<float>(), g, s);
+        gm_cycle_end<float>(M, M->Lf.as<float>(), M->Uf.as<float>(), M->Dinvf.as<float>(), g, cols, s);
     else
-        gm_cycle_end<double>(M, M->L.as<double>(), M->U.as<double>(), M->Dinv.as<double>(), g, s);
+        gm_cycle_end<double>(M, M->L.as<double>(), M->U.as<double>(), M->Dinv.as<double>(), g, cols, s);
 }
 
 extern "C" {
@@ -1226,9 +1228,11 @@ int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart,
     long long queued = 0;
     long long next_poll = M->predict ? std::max(M->chunk, M->last_gm_steps) : M->chunk;
     for (int cycle = 0; !all_done && cycle <= max_iter; ++cycle) {
+        int cols = 0;
         for (int j = 0; j < restart; ++j) {
             gm_step_any(M, g, j, s);
             ++queued;
+            cols = j + 1;
             if (j + 1 == restart) break;
             if (queued >= next_poll) {
                 st = poll(any_run, all_done);
@@ -1238,7 +1242,7 @@ int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart,
             }
             rs::launch_gm_normalise(g, k.t, j + 1, 1, M->n, B, s);
         }
-        gm_cycle_end_any(M, g, s);
+        gm_cycle_end_any(M, g, cols, s);
         HIP_TRY(hipGetLastError());
         st = poll(any_run, all_done);
         if (st != RS_OK) return st;

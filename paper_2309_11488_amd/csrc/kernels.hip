@@ -132,7 +132,7 @@ __device__ bool grid_reduce(double (&v)[NV], double *part, uint32_t *tickets, in
     if (!last) return false;
     double acc[NV];
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    constexpr int U = 4;
+    constexpr int U = NV <= 2 ? 4 : 1;   // same order either way; wide NV keeps registers
     for (int b0 = 0; b0 < ng; b0 += U * (int)blockDim.x) {
         double t[U][NV];
 #pragma unroll
@@ -1176,23 +1176,31 @@ __global__ void __launch_bounds__(kGmThreads) k_gm_normalise(GmWork g, const dou
         dst[e] = src[vo + e] / sc;
 }
 
-// h_i = (w, v_i) for i < jv (NV >= jv).
-template <int NV>
+// h_i = (w, v_i) for i < jv (NV >= jv).  Each thread loads IT entries of w
+// and of every column before it multiplies, so IT * (NV + 1) loads are in
+// flight per thread.
+template <int NV, int IT>
 __global__ void __launch_bounds__(kGmThreads) k_gm_dots(GmWork g, int jv, const double *__restrict__ w) {
     const int sys = blockIdx.y, bx = blockIdx.x;
     if (g.st[sys].phase != PH_RUN) return;
-    const size_t vo = (size_t)sys * g.vstride;
+    const size_t vo = (size_t)sys * g.vstride, chunk = (size_t)kGmThreads * IT;
     const double *V = g.V + vo;
     double acc[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    for (size_t e = (size_t)bx * kGmThreads + threadIdx.x; e < g.vstride; e += (size_t)gridDim.x * kGmThreads) {
-        double v[NV];
+    for (size_t e0 = (size_t)bx * chunk + threadIdx.x; e0 < g.vstride; e0 += (size_t)gridDim.x * chunk) {
+        double v[IT][NV], we[IT];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) v[i] = i < jv ? V[(size_t)i * g.colstride + e] : 0.0;
-        const double we = w[vo + e];
+        for (int u = 0; u < IT; ++u) {
+            const size_t e = e0 + (size_t)u * kGmThreads;
+            we[u] = w[vo + e];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] = __builtin_fma(we, v[i], acc[i]);
+            for (int i = 0; i < NV; ++i) v[u][i] = i < jv ? V[(size_t)i * g.colstride + e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < IT; ++u)
+#pragma unroll
+            for (int i = 0; i < NV; ++i) acc[i] = __builtin_fma(we[u], v[u][i], acc[i]);
     }
     if (grid_reduce<NV>(acc, g.part + sys * g.pstride, g.tickets + sys * g.tkstride, gridDim.x, bx) &&
         threadIdx.x == 0) {
@@ -1239,12 +1247,12 @@ __device__ inline void gm_givens(GmState &G, SysState &S, int j, double nrm2) {
 }
 
 // w -= sum_i h_i v_i (i ascending), then the next pass's coefficients
-// (w, v_i) or, when LAST, ||w||^2 and the Givens step.
-template <int NV, bool LAST>
+// (w, v_i) or, when LAST, ||w||^2 and the Givens step.  Loads as k_gm_dots.
+template <int NV, bool LAST, int IT>
 __global__ void __launch_bounds__(kGmThreads) k_gm_orth(GmWork g, int jv, double *__restrict__ w) {
     const int sys = blockIdx.y, bx = blockIdx.x;
     if (g.st[sys].phase != PH_RUN) return;
-    const size_t vo = (size_t)sys * g.vstride;
+    const size_t vo = (size_t)sys * g.vstride, chunk = (size_t)kGmThreads * IT;
     const double *V = g.V + vo;
     double h[NV];
 #pragma unroll
@@ -1253,19 +1261,26 @@ __global__ void __launch_bounds__(kGmThreads) k_gm_orth(GmWork g, int jv, double
     double acc[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) acc[i] = 0.0;
-    for (size_t e = (size_t)bx * kGmThreads + threadIdx.x; e < g.vstride; e += (size_t)gridDim.x * kGmThreads) {
-        double v[NV];
+    for (size_t e0 = (size_t)bx * chunk + threadIdx.x; e0 < g.vstride; e0 += (size_t)gridDim.x * chunk) {
+        double v[IT][NV], a[IT];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) v[i] = i < jv ? V[(size_t)i * g.colstride + e] : 0.0;
-        double a = w[vo + e];
+        for (int u = 0; u < IT; ++u) {
+            const size_t e = e0 + (size_t)u * kGmThreads;
+            a[u] = w[vo + e];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) a = __builtin_fma(-h[i], v[i], a);
-        w[vo + e] = a;
-        if (LAST) {
-            acc[0] = __builtin_fma(a, a, acc[0]);
-        } else {
+            for (int i = 0; i < NV; ++i) v[u][i] = i < jv ? V[(size_t)i * g.colstride + e] : 0.0;
+        }
 #pragma unroll
-            for (int i = 0; i < NA; ++i) acc[i] = __builtin_fma(a, v[i], acc[i]);
+        for (int u = 0; u < IT; ++u) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) a[u] = __builtin_fma(-h[i], v[u][i], a[u]);
+            w[vo + e0 + (size_t)u * kGmThreads] = a[u];
+            if (LAST) {
+                acc[0] = __builtin_fma(a[u], a[u], acc[0]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < NA; ++i) acc[i] = __builtin_fma(a[u], v[u][i], acc[i]);
+            }
         }
     }
     if (grid_reduce<NA>(acc, g.part + sys * g.pstride, g.tickets + sys * g.tkstride, gridDim.x, bx) &&
@@ -1581,18 +1596,24 @@ void launch_spmv_running(const DevSchedule &d, const double *Ap, size_t a_stride
                        st, nsys, 0, w, s);
 }
 
-// Workgroups of the GMRES vector kernels: one per 1024 entries of a padded
-// vector, at most kVecMaxBlocks (the partial buffers are sized for that).
-static int gm_blocks(int n) { return vec_blocks(n); }
+// Workgroups of the GMRES vector kernels: one per 256 * items entries of a
+// padded vector (a multiple of 1024), at most kVecMaxBlocks (the partial
+// buffers are sized for that).
+static int gm_blocks(int n, int items = 1) {
+    const size_t g = vec_stride(n) / ((size_t)kGmThreads * items);
+    return (int)std::max<size_t>(1, std::min<size_t>(g, kVecMaxBlocks));
+}
 
-// Call f(NV) with the smallest compiled coefficient count >= jv.
+// Call f(NV, IT) with the smallest compiled coefficient count NV >= jv and
+// the entries per thread that keep about 16 loads in flight per thread.
 template <typename F>
 static void with_nv(int jv, F &&f) {
-    if (jv <= 2) f(std::integral_constant<int, 2>{});
-    else if (jv <= 4) f(std::integral_constant<int, 4>{});
-    else if (jv <= 8) f(std::integral_constant<int, 8>{});
-    else if (jv <= 16) f(std::integral_constant<int, 16>{});
-    else f(std::integral_constant<int, kGmMax + 1>{});
+    using std::integral_constant;
+    if (jv <= 2) f(integral_constant<int, 2>{}, integral_constant<int, 4>{});
+    else if (jv <= 4) f(integral_constant<int, 4>{}, integral_constant<int, 4>{});
+    else if (jv <= 8) f(integral_constant<int, 8>{}, integral_constant<int, 2>{});
+    else if (jv <= 16) f(integral_constant<int, 16>{}, integral_constant<int, 1>{});
+    else f(integral_constant<int, kGmMax + 1>{}, integral_constant<int, 1>{});
 }
 
 void launch_gm_init(const GmWork &g, int nsys, hipStream_t s) {
@@ -1607,19 +1628,21 @@ void launch_gm_normalise(const GmWork &g, const double *src, int col, int from_w
 
 void launch_gm_dots(const GmWork &g, int jv, const double *w, int n, int nsys, hipStream_t s) {
     if (n <= 0 || nsys <= 0 || jv < 1 || jv > kGmMax) return;
-    with_nv(jv, [&](auto NV) {
-        k_gm_dots<decltype(NV)::value><<<dim3(gm_blocks(n), nsys), kGmThreads, 0, s>>>(g, jv, w);
+    with_nv(jv, [&](auto NV, auto IT) {
+        constexpr int it = decltype(IT)::value;
+        k_gm_dots<decltype(NV)::value, it><<<dim3(gm_blocks(n, it), nsys), kGmThreads, 0, s>>>(g, jv, w);
     });
 }
 
 void launch_gm_orth(const GmWork &g, int jv, double *w, bool last, int n, int nsys, hipStream_t s) {
     if (n <= 0 || nsys <= 0 || jv < 1 || jv > kGmMax) return;
-    with_nv(jv, [&](auto NV) {
-        constexpr int nv = decltype(NV)::value;
+    with_nv(jv, [&](auto NV, auto IT) {
+        constexpr int nv = decltype(NV)::value, it = decltype(IT)::value;
+        const dim3 grid(gm_blocks(n, it), nsys);
         if (last)
-            k_gm_orth<nv, true><<<dim3(gm_blocks(n), nsys), kGmThreads, 0, s>>>(g, jv, w);
+            k_gm_orth<nv, true, it><<<grid, kGmThreads, 0, s>>>(g, jv, w);
         else
-            k_gm_orth<nv, false><<<dim3(gm_blocks(n), nsys), kGmThreads, 0, s>>>(g, jv, w);
+            k_gm_orth<nv, false, it><<<grid, kGmThreads, 0, s>>>(g, jv, w);
     });
 }
 
