@@ -8,9 +8,15 @@ solved one after another at a residual reduction of 1e-2 (max 200
 iterations), plain FP64.  The metric is BiCGStab-ILU0 solves per second.
 
 Prints ONE JSON line on stdout (progress goes to stderr).  The roofline
-object is measured live with HIP events on the solve stream around every
-launch of the reported kernel class; the CPU baseline is the project's
-single-threaded oracle on a bounded sample of the same workload.
+object is for the dominant kernel class: an untimed pre-pass step times
+every class and picks the one with the most device time.  During the timed
+steps the units of that class are timed with HIP events on the solve
+stream while the rest of each iteration replays as graph segments: a
+single-kernel unit (an SpMV, a vector update) records dispatch events at
+the kernel's own start and end; a triangular sweep (one launch per level)
+replays as a graph segment of its own between two events; a factorisation
+is bracketed by events around its level launches.  The CPU baseline is the
+project's single-threaded oracle on a bounded sample of the same workload.
 """
 
 from __future__ import annotations
@@ -63,8 +69,9 @@ def parse():
     ap.add_argument("--ordering", default="colour", choices=sorted(ORDER))
     ap.add_argument("--precision", default=None, choices=sorted(PREC))
     ap.add_argument("--reduction", type=float, default=None)
-    ap.add_argument("--roofline", default=None, choices=sorted(CLASS),
-                    help="kernel class of the roofline object (default: spmv; gm with --solver gmres)")
+    ap.add_argument("--roofline", default="auto", choices=["auto", "off"] + sorted(CLASS),
+                    help="kernel class of the roofline object (auto: the class with the most device time in a "
+                         "profiled pre-pass step)")
     ap.add_argument("--solver", default="bicgstab", choices=["bicgstab", "gmres"],
                     help="Krylov solver on the same factors (gmres: restarted, --restart m)")
     ap.add_argument("--restart", type=int, default=30, help="GMRES restart length (1..32)")
@@ -167,8 +174,6 @@ def main():
     gmres = args.solver == "gmres"
     if gmres and args.jacobi:
         sys.exit("bench.py: --solver gmres runs on the plain ILU0 preconditioner only")
-    if args.roofline is None:
-        args.roofline = "gm" if gmres else "spmv"
     precision = args.precision or wl["precision"]
     reduction = args.reduction if args.reduction is not None else wl["reduction"]
     ordering = ORDER[args.ordering]
@@ -204,10 +209,18 @@ def main():
         tune = rs.ilu0_autotune(M, A, b[0], reduction, reps=3)
         log(f"autotune: {tune} in {time.perf_counter() - t:.2f}s")
 
+    sample = {"mask": 0, "step": 0}
+
     def step(record=False):
+        if sample["mask"]:
+            rs.rsolve_profile_set_mask(sample["mask"])      # every factorisation
         st, bad = rs.ilu0_factor(M, A, prec)
         assert st == rs.OK, (st, bad)
         for j in range(rhs):
+            if sample["mask"]:
+                # one right-hand side per step is timed, rotating over the
+                # positions, so the timing's own cost stays small
+                rs.rsolve_profile_set_mask(sample["mask"] if j == sample["step"] % rhs else 0)
             if gmres:
                 _, st, info = rs.gmres_solve(M, A, b[j], x[j], args.restart, reduction, 200)
             else:
@@ -218,20 +231,46 @@ def main():
                     true_res.append(i["true_rel_residual"])
                     statuses.append(i["status"])
 
-    # the profiled configuration is captured into the iteration graph during
-    # warm-up; enabling again with the same mask only clears the counters
-    rs.rsolve_profile_enable(1 << CLASS[args.roofline])
+    # pre-pass (untimed): one step with every kernel class timed, to find the
+    # class with the most device time
     for _ in range(args.warmup):
         step()
+    classes = ["factor", "lsweep", "usweep", "spmv", "spmv_t", "vec"] + (["gm"] if gmres else [])
+    rs.rsolve_profile_enable(sum(1 << CLASS[c] for c in classes))
+    step()
     torch.cuda.synchronize()
-    rs.rsolve_profile_enable(1 << CLASS[args.roofline])
+    class_times = {}
+    for c in classes:
+        ms, units, byts = rs.rsolve_profile_get(CLASS[c])
+        if units:
+            class_times[c] = {"ms": ms, "units": units, "us_per_unit": ms * 1e3 / units,
+                              "gbs": byts / (ms / 1e3) / 1e9 if ms > 0 else None}
+    total_ms = sum(v["ms"] for v in class_times.values())
+    for v in class_times.values():
+        v["share"] = v["ms"] / total_ms if total_ms else None
+    dominant = max(class_times, key=lambda c: class_times[c]["ms"])
+    log("pre-pass device time per class: " + ", ".join(
+        f"{c} {v['share'] * 100:.1f}% ({v['us_per_unit']:.2f} us/unit, {v['gbs'] or 0:.0f} GB/s)"
+        for c, v in sorted(class_times.items(), key=lambda kv: -kv[1]["ms"])))
+    if args.roofline == "auto":
+        args.roofline = dominant
+    # the timed class's units record events between graph segments, which
+    # one more warm-up step captures ("off": nothing timed, for a check of
+    # the timing's own cost)
+    tmask = 0 if args.roofline == "off" else 1 << CLASS[args.roofline]
+    sample.update(mask=tmask, step=0)
+    rs.rsolve_profile_enable(tmask)
+    step()
+    torch.cuda.synchronize()
+    rs.rsolve_profile_enable(tmask)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        sample["step"] = i
         step(record=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms, units, byts = rs.rsolve_profile_get(CLASS[args.roofline])
+    ms, units, byts = rs.rsolve_profile_get(CLASS[args.roofline]) if tmask else (0.0, 0, 0.0)
     rs.rsolve_profile_enable(0)
     elapsed = t1 - t0
     n_solves = args.steps * rhs * s.batch
@@ -246,9 +285,11 @@ def main():
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                 "kernel": args.roofline, "units_timed": units, "us_per_unit": per_unit_s * 1e6,
-                "algorithmic_bytes_per_unit": per_unit_bytes}
+                "algorithmic_bytes_per_unit": per_unit_bytes, "dominant_in_prepass": dominant,
+                "sampling": "every factorisation; one right-hand side per step for the solve classes, rotating"
+                            if rhs > 1 else "every unit"}
     log(f"roofline {args.roofline}: {units} units, {per_unit_s * 1e6:.2f} us/unit, "
-        f"{per_unit_bytes / 1e6:.2f} MB/unit -> {achieved:.1f} GB/s")
+        f"{per_unit_bytes / 1e6:.2f} MB/unit -> {achieved or 0:.1f} GB/s")
 
     cpu = None
     if not args.no_cpu:
@@ -284,6 +325,7 @@ def main():
                    "launch_config": tune},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "kernel_classes": class_times,
     }
     print(json.dumps(out), flush=True)
 

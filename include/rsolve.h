@@ -310,12 +310,18 @@ int ilu0_analyse_host(int32_t n_brows, const int32_t *row_ptr, const int32_t *co
 
 /* rsolve_profile_enable -- time classes of kernel work with HIP events
  * recorded on the launch stream (bit c of mask enables class c:
- * 0 = one ILU0 factorisation, 1 = one lower sweep, 2 = one upper sweep,
- * 3 = one v = A phat launch, 4 = one vector-update launch, 5 = one
- * t = A shat launch (and GMRES's products with A), 6 = one GMRES
- * Gram-Schmidt launch).
+ * 0 = one ILU0 factorisation, 1 = one lower sweep (all its level
+ * launches), 2 = one upper sweep, 3 = one v = A phat launch, 4 = one
+ * vector-update launch, 5 = one t = A shat launch (and GMRES's products
+ * with A), 6 = one GMRES Gram-Schmidt launch).  Single-kernel units record
+ * dispatch events (the kernel's own start and end); with graphs on, a
+ * timed sweep replays as a graph segment of its own between two events.
  * Resets the counters.  Process-wide, not thread-safe; 0 disables. */
 int rsolve_profile_enable(int32_t mask);
+
+/* rsolve_profile_set_mask -- change the timed classes without clearing the
+ * counters (e.g. to time a sample of the solves).  Process-wide. */
+int rsolve_profile_set_mask(int32_t mask);
 
 /* rsolve_profile_get -- accumulated device milliseconds, units timed and
  * algorithmic bytes moved (the bytes the method must read and write, not

@@ -32,7 +32,7 @@ EXPORTS = (
     "bcsr_create", "bcsr_set_values", "bcsr_set_wells", "bcsr_get_dims", "bcsr_spmv", "bcsr_set_option", "bcsr_destroy", "ilu0_analyse",
     "ilu0_get_schedule", "ilu0_get_sweep_levels", "ilu0_set_option", "ilu0_get_option", "ilu0_autotune",
     "ilu0_factor", "ilu0_get_factors", "ilu0_apply",
-    "bicgstab_solve", "gmres_solve", "ilu0_destroy", "ilu0_analyse_host", "rsolve_profile_enable", "rsolve_profile_get",
+    "bicgstab_solve", "gmres_solve", "ilu0_destroy", "ilu0_analyse_host", "rsolve_profile_enable", "rsolve_profile_set_mask", "rsolve_profile_get",
     "ilu0_analyse_shared", "ilu0_analyse_jacobi", "bcsr_partition", "server_create", "server_request_bytes", "server_analysis_bytes", "server_add_pattern",
     "server_submit", "server_poll", "server_wait", "server_get_stats",
     "server_destroy", "rsolve_status_string", "rsolve_last_error",
@@ -131,6 +131,7 @@ def lib():
         L.ilu0_destroy.argtypes = [vp]
         L.ilu0_analyse_host.argtypes = [i32, vp, vp, i32, vp, P(i32), P(i32)]
         L.rsolve_profile_enable.argtypes = [i32]
+        L.rsolve_profile_set_mask.argtypes = [i32]
         L.rsolve_profile_get.argtypes = [i32, P(dbl), P(ct.c_int64), P(dbl)]
         L.server_create.argtypes = [P(ServerConfig), P(vp)]
         L.server_request_bytes.argtypes = [i32, i32, i32, P(ct.c_size_t)]
@@ -425,6 +426,11 @@ def ilu0_analyse_host(rowptr, colidx, ordering=ORDER_LEVEL_SET):
 
 def rsolve_profile_enable(mask):
     return _check(lib().rsolve_profile_enable(int(mask)), "rsolve_profile_enable")
+
+
+def rsolve_profile_set_mask(mask):
+    """Change the timed classes without clearing the counters."""
+    return _check(lib().rsolve_profile_set_mask(int(mask)), "rsolve_profile_set_mask")
 
 
 def rsolve_profile_get(cls):

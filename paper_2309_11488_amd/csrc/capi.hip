@@ -7,6 +7,7 @@
 #include <chrono>
 #include <climits>
 #include <fstream>
+#include <map>
 #include <memory>
 #include <sstream>
 #include <cstdio>
@@ -255,21 +256,23 @@ struct rs_ilu0 {
     rs::WellsDev wdev{};
     int split() const { return reduce_split; }
     // a BiCGStab iteration captured as HIP graphs, replayed on the caller's
-    // stream: segment 0 = the whole iteration; 1 and 2 = the parts before and
-    // after v = A phat, used while that kernel is being timed with events
+    // stream: one segment per set of consecutive parts of the iteration (the
+    // whole iteration, or the runs between the parts of a kernel class that
+    // is being timed with events and so launched directly)
     bool use_graph = true;
     hipStream_t cap_stream = nullptr;
-    hipGraph_t graph[3] = {};
-    hipGraphExec_t gexec[3] = {};
-    long long graph_key[3] = {-1, -1, -1};
+    struct Segment {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        long long key = -1;
+    };
+    std::map<int, Segment> segments;   // by iteration parts
     void drop_graph() {
-        for (int i = 0; i < 3; ++i) {
-            if (gexec[i]) (void)hipGraphExecDestroy(gexec[i]);
-            if (graph[i]) (void)hipGraphDestroy(graph[i]);
-            gexec[i] = nullptr;
-            graph[i] = nullptr;
-            graph_key[i] = -1;
+        for (auto &kv : segments) {
+            if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+            if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
         }
+        segments.clear();
     }
     ~rs_ilu0() {
         drop_graph();
@@ -863,47 +866,92 @@ static int sweep_error(ilu0_t M, hipStream_t s) {
 
 }  // extern "C"
 
+// Algorithmic bytes of one lower sweep: L blocks with their column indices,
+// row pointer and row list, the input (r, p, v read and p written when
+// fused), y written once, and for the rows that also finish the upper sweep
+// (upper level 0) their inv(U_ii) and z.
+static double lower_bytes(ilu0_t M, double tb, bool fuse_p, int nsys) {
+    const rs::Schedule &S = M->an->sch;
+    const double n = M->n, in_b = fuse_p ? 96 : 24;
+    const double fold = S.nu_levels > 0 ? S.uset[1] : 0;
+    return nsys * ((9 * tb + 4) * S.nL + (8 + 4 + in_b + 3 * tb) * n + (9 * tb + 24) * fold);
+}
+
+// Algorithmic bytes of the upper sweep's launches (levels 1 and up): U
+// blocks with indices, inv(U_ii), row pointer and row list, y read, z written.
+static double upper_bytes(ilu0_t M, double tb, int nsys) {
+    const rs::Schedule &S = M->an->sch;
+    const double rows = M->n - (S.nu_levels > 0 ? S.uset[1] : 0);
+    return nsys * ((9 * tb + 4) * S.nU + (8 + 3 * tb + 9 * tb + 24) * rows);
+}
+
+// Lower sweep of one preconditioner application M^{-1} in -> out (new
+// order).  Timed as one unit (events around its launches).
+template <typename T>
+static void lower_levels(ilu0_t M, const T *L, const T *D, const double *in, double *out, bool fuse_p, Krylov &k,
+                         SysState *st, int nsys, hipStream_t s) {
+    const rs::Schedule &S = M->an->sch;
+    const size_t vs = k.vstride;
+    T *y = (T *)k.y;
+    ProfScope ps(PC_LSWEEP, s, lower_bytes(M, sizeof(T), fuse_p, nsys), M->tile_sweeps);
+    if (M->tile_sweeps) {
+        rs::launch_lsweep_tiles<T>(M->an->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, k.lflags,
+                                   k.lctr, nsys, M->sweep_grid, s, ps.start(), ps.stop());
+        return;
+    }
+    // the upper sweep's first level (rows without upper blocks) is finished
+    // inside the lower sweep's launches
+    const int u0_end = S.nu_levels > 0 ? S.uset[1] : 0;
+    for (int l = 0; l < S.nl_levels; ++l)
+        rs::launch_lsweep<T>(M->an->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, S.lset[l],
+                             S.lset[l + 1], nsys, M->sweep_variant, D, (size_t)M->n * 9, out, u0_end, s);
+}
+
+// Upper sweep levels 1 and up (level 0 is done by the lower sweep), timed
+// as one unit.
+template <typename T>
+static void upper_levels(ilu0_t M, const T *U, const T *D, double *out, bool fuse_p, Krylov &k, SysState *st,
+                         int nsys, hipStream_t s) {
+    const rs::Schedule &S = M->an->sch;
+    const size_t vs = k.vstride;
+    const T *y = (const T *)k.y;
+    ProfScope ps(PC_USWEEP, s, upper_bytes(M, sizeof(T), nsys), M->tile_sweeps);
+    if (M->tile_sweeps) {
+        rs::launch_usweep_tiles<T>(M->an->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, k.uflags,
+                                   k.uctr, nsys, M->sweep_grid, s, ps.start(), ps.stop());
+        return;
+    }
+    for (int l = 1; l < S.nu_levels; ++l)
+        rs::launch_usweep<T>(M->an->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, S.uset[l],
+                             S.uset[l + 1], nsys, M->sweep_variant, fuse_p, s);
+}
+
 // One preconditioner application M^{-1} in -> out (new order), all levels.
 template <typename T>
 static void apply_levels(ilu0_t M, const T *L, const T *U, const T *D, const double *in, double *out, bool fuse_p,
                          Krylov &k, SysState *st, int nsys, hipStream_t s) {
-    const rs::Schedule &S = M->an->sch;
-    const size_t vs = k.vstride;
-    const double n = M->n, tb = sizeof(T), B = nsys;
-    T *y = (T *)k.y;
-    {
-        // L blocks + column indices, row pointers and row list, the input
-        // (r, p, v read and p written when fused), y written once
-        const double bytes = B * ((9 * tb + 4) * S.nL + 8 * n + (fuse_p ? 96 : 24) * n + 3 * tb * n);
-        ProfScope ps(PC_LSWEEP, s, bytes);
-        if (M->tile_sweeps)
-            rs::launch_lsweep_tiles<T>(M->an->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, k.lflags,
-                                       k.lctr, nsys, M->sweep_grid, s);
-        else
-            // the upper sweep's first level (rows without upper blocks) is
-            // finished inside the lower sweep's launches
-            for (int l = 0; l < S.nl_levels; ++l)
-                rs::launch_lsweep<T>(M->an->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, S.lset[l],
-                                     S.lset[l + 1], nsys, M->sweep_variant, D, (size_t)M->n * 9, out,
-                                     S.nu_levels > 0 ? S.uset[1] : 0, s);
-    }
-    {
-        // U blocks + indices, inv(U_ii), row pointers and row list, y read, z written
-        const double bytes = B * ((9 * tb + 4) * S.nU + 9 * tb * n + 8 * n + 3 * tb * n + 24 * n);
-        ProfScope ps(PC_USWEEP, s, bytes);
-        if (M->tile_sweeps)
-            rs::launch_usweep_tiles<T>(M->an->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, k.uflags,
-                                       k.uctr, nsys, M->sweep_grid, s);
-        else
-            for (int l = 1; l < S.nu_levels; ++l)
-                rs::launch_usweep<T>(M->an->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, S.uset[l],
-                                     S.uset[l + 1], nsys, M->sweep_variant, fuse_p, s);
-    }
+    lower_levels<T>(M, L, D, in, out, fuse_p, k, st, nsys, s);
+    upper_levels<T>(M, U, D, out, fuse_p, k, st, nsys, s);
 }
 
-// Parts of an iteration: 1 = first preconditioner apply, 2 = v = A phat,
-// 4 = the rest (half-step update, second apply, t = A shat, full step).
-enum { IT_APPLY1 = 1, IT_SPMV_V = 2, IT_REST = 4, IT_ALL = 7 };
+// Parts of a BiCGStab iteration, in order: the two sweeps of the first
+// preconditioner application (p updated on the fly), v = A phat, the
+// half-step update, the two sweeps of the second application, t = A shat,
+// the full-step update.
+enum {
+    P_L1 = 1, P_U1 = 2, P_SPMV_V = 4, P_SUPD = 8, P_L2 = 16, P_U2 = 32, P_SPMV_T = 64, P_XR = 128, P_ALL = 255
+};
+
+// The iteration parts that hold launches of the kernel classes in `mask`.
+static int class_parts(int mask) {
+    int parts = 0;
+    if ((mask >> PC_LSWEEP) & 1) parts |= P_L1 | P_L2;
+    if ((mask >> PC_USWEEP) & 1) parts |= P_U1 | P_U2;
+    if ((mask >> PC_SPMV_V) & 1) parts |= P_SPMV_V;
+    if ((mask >> PC_SPMV_T) & 1) parts |= P_SPMV_T;
+    if ((mask >> PC_VEC) & 1) parts |= P_SUPD | P_XR;
+    return parts;
+}
 
 template <typename T>
 static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipStream_t s, int parts) {
@@ -914,17 +962,28 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
     // values + column indices, row pointers, x gathered once, y written, one
     // more vector read by the fused dot product
     const double spmv_bytes = B * (76 * nnzb + 4 * n + 72 * n);
-    if (parts & IT_APPLY1) apply_levels<T>(M, L, U, D, nullptr, k.phat, true, k, k.st, B, s);
-    if (parts & IT_SPMV_V) {
+    if (parts & P_L1) lower_levels<T>(M, L, D, nullptr, k.phat, true, k, k.st, B, s);
+    if (parts & P_U1) upper_levels<T>(M, U, D, k.phat, true, k, k.st, B, s);
+    if (parts & P_SPMV_V) {
         ProfScope ps(PC_SPMV_V, s, spmv_bytes, true);
         rs::launch_spmv_v(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), M->wdev, s,
                           ps.start(), ps.stop());
     }
-    if (!(parts & IT_REST)) return;
-    { ProfScope ps(PC_VEC, s, B * 72 * n); rs::launch_s_update(M->n, k, B, M->spmv_variant, M->split(), s); }
-    apply_levels<T>(M, L, U, D, k.s, k.shat, false, k, k.st, B, s);
-    { ProfScope ps(PC_SPMV_T, s, spmv_bytes); rs::launch_spmv_t(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), M->wdev, s); }
-    { ProfScope ps(PC_VEC, s, B * 192 * n); rs::launch_xr_update(M->n, k, B, M->spmv_variant, M->split(), s); }
+    if (parts & P_SUPD) {
+        ProfScope ps(PC_VEC, s, B * 72 * n, true);
+        rs::launch_s_update(M->n, k, B, M->spmv_variant, M->split(), s, ps.start(), ps.stop());
+    }
+    if (parts & P_L2) lower_levels<T>(M, L, D, k.s, k.shat, false, k, k.st, B, s);
+    if (parts & P_U2) upper_levels<T>(M, U, D, k.shat, false, k, k.st, B, s);
+    if (parts & P_SPMV_T) {
+        ProfScope ps(PC_SPMV_T, s, spmv_bytes, true);
+        rs::launch_spmv_t(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), M->wdev, s,
+                          ps.start(), ps.stop());
+    }
+    if (parts & P_XR) {
+        ProfScope ps(PC_VEC, s, B * 192 * n, true);
+        rs::launch_xr_update(M->n, k, B, M->spmv_variant, M->split(), s, ps.start(), ps.stop());
+    }
 }
 
 static void enqueue_iteration_any(ilu0_t M, hipStream_t s, int parts) {
@@ -934,52 +993,76 @@ static void enqueue_iteration_any(ilu0_t M, hipStream_t s, int parts) {
         enqueue_iteration<double>(M, M->L.as<double>(), M->U.as<double>(), M->Dinv.as<double>(), s, parts);
 }
 
-// Replay graph segment `seg` holding `parts` (captured on a private stream
+// Replay the graph segment holding `parts` (captured on a private stream
 // the first time this configuration is seen).  Nothing is timed inside a
 // graph: profiling is off while segments are captured.
-static int replay_segment(ilu0_t M, int seg, int parts, hipStream_t s) {
+static int replay_segment(ilu0_t M, int parts, hipStream_t s) {
     const long long key = (long long)M->precision | (long long)M->tile_sweeps << 2 | (long long)M->spmv_variant << 3 |
                           (long long)M->sweep_variant << 6 | (long long)M->split() << 8 |
                           (long long)M->sweep_grid << 10 |
                           (M->wdev.nw > 0 ? ((long long)(M->wells_version & 0xffffff) + 1) << 36 : 0);
-    if (!M->gexec[seg] || M->graph_key[seg] != key) {
-        if (M->gexec[seg]) (void)hipGraphExecDestroy(M->gexec[seg]);
-        if (M->graph[seg]) (void)hipGraphDestroy(M->graph[seg]);
-        M->gexec[seg] = nullptr;
-        M->graph[seg] = nullptr;
+    rs_ilu0::Segment &seg = M->segments[parts];
+    if (!seg.exec || seg.key != key) {
+        if (seg.exec) (void)hipGraphExecDestroy(seg.exec);
+        if (seg.graph) (void)hipGraphDestroy(seg.graph);
+        seg.exec = nullptr;
+        seg.graph = nullptr;
         if (!M->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&M->cap_stream, hipStreamNonBlocking));
         const int mask = g_prof.mask;
         g_prof.mask = 0;
         hipError_t e = hipStreamBeginCapture(M->cap_stream, hipStreamCaptureModeRelaxed);
         if (e == hipSuccess) {
             enqueue_iteration_any(M, M->cap_stream, parts);
-            e = hipStreamEndCapture(M->cap_stream, &M->graph[seg]);
+            e = hipStreamEndCapture(M->cap_stream, &seg.graph);
         }
         g_prof.mask = mask;
         HIP_TRY(e);
-        HIP_TRY(hipGraphInstantiate(&M->gexec[seg], M->graph[seg], nullptr, nullptr, 0));
-        M->graph_key[seg] = key;
+        HIP_TRY(hipGraphInstantiate(&seg.exec, seg.graph, nullptr, nullptr, 0));
+        seg.key = key;
     }
-    HIP_TRY(hipGraphLaunch(M->gexec[seg], s));
+    HIP_TRY(hipGraphLaunch(seg.exec, s));
     return RS_OK;
 }
 
 // Queue one BiCGStab iteration on `s`.  With graphs on, the iteration is
-// one replay; while v = A phat is timed, it runs as a direct launch between
-// two replays; when any other kernel class is timed, all launches are direct.
+// one replay.  While kernel classes are timed, each of their parts is timed
+// on its own: a per-level sweep replays as a graph segment of its own
+// between two events (the unit is the whole sweep), a single launch runs
+// directly and records dispatch events; the runs of untimed parts between
+// them replay as graph segments.
 static int run_iteration(ilu0_t M, hipStream_t s) {
-    const int mask = g_prof.mask;
-    if (!M->use_graph || (mask & ~(1 << PC_SPMV_V))) {
-        enqueue_iteration_any(M, s, IT_ALL);
+    if (!M->use_graph) {
+        enqueue_iteration_any(M, s, P_ALL);
         HIP_TRY(hipGetLastError());
         return RS_OK;
     }
-    if (!mask) return replay_segment(M, 0, IT_ALL, s);
-    int st = replay_segment(M, 1, IT_APPLY1, s);
-    if (st != RS_OK) return st;
-    enqueue_iteration_any(M, s, IT_SPMV_V);
-    HIP_TRY(hipGetLastError());
-    return replay_segment(M, 2, IT_REST, s);
+    const int timed = class_parts(g_prof.mask);
+    if (!timed) return replay_segment(M, P_ALL, s);
+    const double tb = M->precision == RS_PREC_FP32_FACTORS ? 4 : 8;
+    int run = 0;
+    for (int part = 1; part <= P_XR; part <<= 1) {
+        if (!(timed & part)) {
+            run |= part;
+            continue;
+        }
+        if (run) {
+            const int st = replay_segment(M, run, s);
+            if (st != RS_OK) return st;
+            run = 0;
+        }
+        const bool sweep = part == P_L1 || part == P_U1 || part == P_L2 || part == P_U2;
+        if (sweep && !M->tile_sweeps) {
+            const bool lower = part == P_L1 || part == P_L2;
+            ProfScope ps(lower ? PC_LSWEEP : PC_USWEEP, s,
+                         lower ? lower_bytes(M, tb, part == P_L1, M->batch) : upper_bytes(M, tb, M->batch));
+            const int st = replay_segment(M, part, s);
+            if (st != RS_OK) return st;
+        } else {
+            enqueue_iteration_any(M, s, part);
+            HIP_TRY(hipGetLastError());
+        }
+    }
+    return run ? replay_segment(M, run, s) : RS_OK;
 }
 
 extern "C" {
@@ -1102,6 +1185,7 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
 }  // extern "C"
 
 // Queue one Arnoldi step (column j) of every iterating system on `s`.
+// Timed launches record their own dispatch events.
 template <typename T>
 static void gm_step(ilu0_t M, const T *L, const T *U, const T *D, const rs::GmWork &g, int j, hipStream_t s) {
     Krylov &k = M->k;
@@ -1110,14 +1194,23 @@ static void gm_step(ilu0_t M, const T *L, const T *U, const T *D, const rs::GmWo
     // z = M^-1 v_j, w = A z
     apply_levels<T>(M, L, U, D, g.V + (size_t)j * g.colstride, k.phat, false, k, k.st, B, s);
     {
-        ProfScope ps(PC_SPMV_T, s, B * (76 * nnzb + 4 * n + 48 * n));
+        ProfScope ps(PC_SPMV_T, s, B * (76 * nnzb + 4 * n + 48 * n), true);
         rs::launch_spmv_running(M->an->dev, M->pvals.as<double>(), (size_t)M->nnzb * 9, k.phat, k.t, k.vstride, k.st,
-                                B, M->spmv_variant, M->wdev, s);
+                                B, M->spmv_variant, M->wdev, s, ps.start(), ps.stop());
     }
     const int jv = j + 1;
-    { ProfScope ps(PC_GM, s, vb * (jv + 1)); rs::launch_gm_dots(g, jv, k.t, M->n, B, s); }
-    { ProfScope ps(PC_GM, s, vb * (jv + 2)); rs::launch_gm_orth(g, jv, k.t, false, M->n, B, s); }
-    { ProfScope ps(PC_GM, s, vb * (jv + 2)); rs::launch_gm_orth(g, jv, k.t, true, M->n, B, s); }
+    {
+        ProfScope ps(PC_GM, s, vb * (jv + 1), true);
+        rs::launch_gm_dots(g, jv, k.t, M->n, B, s, ps.start(), ps.stop());
+    }
+    {
+        ProfScope ps(PC_GM, s, vb * (jv + 2), true);
+        rs::launch_gm_orth(g, jv, k.t, false, M->n, B, s, ps.start(), ps.stop());
+    }
+    {
+        ProfScope ps(PC_GM, s, vb * (jv + 2), true);
+        rs::launch_gm_orth(g, jv, k.t, true, M->n, B, s, ps.start(), ps.stop());
+    }
 }
 
 // End of a cycle: x += M^-1 (V y) for every system not done, then the
@@ -1128,18 +1221,30 @@ static void gm_cycle_end(ilu0_t M, const T *L, const T *U, const T *D, const rs:
     Krylov &k = M->k;
     const int B = M->batch;
     const double n = M->n, nnzb = M->nnzb, vb = (double)B * 24 * n;
-    // (cols = steps queued in the cycle, an upper bound of every system's basis)
-    { ProfScope ps(PC_VEC, s, vb * (cols + 1)); rs::launch_gm_combine(g, k.s, M->n, B, s); }
+    {
+        // (cols = steps queued in the cycle, an upper bound of every system's basis)
+        ProfScope ps(PC_VEC, s, vb * (cols + 1), true);
+        rs::launch_gm_combine(g, k.s, M->n, B, s, ps.start(), ps.stop());
+    }
     apply_levels<T>(M, L, U, D, k.s, k.phat, false, k, nullptr, B, s);
-    { ProfScope ps(PC_VEC, s, vb * 3); rs::launch_gm_xupdate(g, k.x, k.phat, M->n, B, s); }
+    {
+        ProfScope ps(PC_VEC, s, vb * 3, true);
+        rs::launch_gm_xupdate(g, k.x, k.phat, M->n, B, s, ps.start(), ps.stop());
+    }
     rs::launch_gm_phase(g, B, s);
     {
-        ProfScope ps(PC_SPMV_T, s, B * (76 * nnzb + 4 * n + 48 * n));
+        ProfScope ps(PC_SPMV_T, s, B * (76 * nnzb + 4 * n + 48 * n), true);
         rs::launch_spmv_running(M->an->dev, M->pvals.as<double>(), (size_t)M->nnzb * 9, k.x, k.t, k.vstride, k.st, B,
-                                M->spmv_variant, M->wdev, s);
+                                M->spmv_variant, M->wdev, s, ps.start(), ps.stop());
     }
-    { ProfScope ps(PC_VEC, s, vb * 3); rs::launch_gm_restart(g, k.rhat, k.t, k.r, M->n, B, s); }
-    { ProfScope ps(PC_VEC, s, vb * 2); rs::launch_gm_normalise(g, k.r, 0, 0, M->n, B, s); }
+    {
+        ProfScope ps(PC_VEC, s, vb * 3, true);
+        rs::launch_gm_restart(g, k.rhat, k.t, k.r, M->n, B, s, ps.start(), ps.stop());
+    }
+    {
+        ProfScope ps(PC_VEC, s, vb * 2, true);
+        rs::launch_gm_normalise(g, k.r, 0, 0, M->n, B, s, ps.start(), ps.stop());
+    }
 }
 
 static void gm_step_any(ilu0_t M, const rs::GmWork &g, int j, hipStream_t s) {
@@ -1240,7 +1345,8 @@ int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart,
                 next_poll = queued + M->chunk;
                 if (!any_run) break;
             }
-            rs::launch_gm_normalise(g, k.t, j + 1, 1, M->n, B, s);
+            ProfScope ps(PC_VEC, s, (double)B * 48 * M->n, true);
+            rs::launch_gm_normalise(g, k.t, j + 1, 1, M->n, B, s, ps.start(), ps.stop());
         }
         gm_cycle_end_any(M, g, cols, s);
         HIP_TRY(hipGetLastError());
@@ -1278,6 +1384,11 @@ int rsolve_profile_enable(int32_t mask) {
         g_prof.bytes[c] = 0.0;
         g_prof.units[c] = 0;
     }
+    return RS_OK;
+}
+
+int rsolve_profile_set_mask(int32_t mask) {
+    g_prof.mask = mask;
     return RS_OK;
 }
 

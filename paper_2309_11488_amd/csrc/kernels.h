@@ -159,7 +159,8 @@ template <typename T>
 // z_i = inv(U_ii) y_i (Dinv at d_stride per system), exactly as k_usweep.
 void launch_lsweep(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
                    bool fuse_p, const double *r, const double *v, double *p, SysState *st, int q0, int q1, int nsys,
-                   int variant, const T *Dinv, size_t d_stride, double *z, int u0_end, hipStream_t s);
+                   int variant, const T *Dinv, size_t d_stride, double *z, int u0_end, hipStream_t s,
+                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Upper sweep z = inv(U_ii) (y - U z) for U-schedule rows [q0, q1).
 template <typename T>
@@ -167,18 +168,22 @@ template <typename T>
 // first application of an iteration, which runs whenever it is queued).
 void launch_usweep(const DevSchedule &d, const T *U, size_t u_stride, const T *Dinv, size_t d_stride, const T *y,
                    double *z, size_t vstride, SysState *st, int q0, int q1, int nsys, int variant, bool defer,
-                   hipStream_t s);
+                   hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+// ev0 / ev1 (optional, every launcher below that takes them): events the
+// dispatch records at the kernel's start and end.
 
 // Single-launch sweeps over all tiles of all nsys systems (L: lower
 // schedule, U: upper schedule).  grid = number of workgroups.
 template <typename T>
 void launch_lsweep_tiles(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
                          bool fuse_p, const double *r, const double *v, double *p, SysState *st, int32_t *flags,
-                         SweepCtr *ctr, int nsys, int grid, hipStream_t s);
+                         SweepCtr *ctr, int nsys, int grid, hipStream_t s, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
 template <typename T>
 void launch_usweep_tiles(const DevSchedule &d, const T *U, size_t u_stride, const T *Dinv, size_t d_stride,
                          const T *y, double *z, size_t vstride, SysState *st, int32_t *flags, SweepCtr *ctr, int nsys,
-                         int grid, hipStream_t s);
+                         int grid, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Plain y = A x (rows in storage order), FP64.
 // y = A x (minus the separate wells, when w has any: t2 is computed first).
@@ -198,10 +203,12 @@ void launch_wells_t2(const WellsDev &w, const double *x, size_t xstride, int nsy
 // ev0 / ev1 (optional): events recorded by the dispatch at the kernel's start and end.
 void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, int split,
                    const WellsDev &w, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, int split, hipStream_t s);
+void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, int split, hipStream_t s,
+                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, int split,
-                   const WellsDev &w, hipStream_t s);
-void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, int split, hipStream_t s);
+                   const WellsDev &w, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, int split, hipStream_t s,
+                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // x_orig[perm[i]] = x'[i]; then r = b - A x_orig with the caller's A, and the
 // true relative residual into the states.
 void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *colidx, const double *A,
@@ -211,7 +218,8 @@ void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *c
 // y = A x on the reordered matrix for the systems still iterating (new
 // order, x and y at stride vstride), minus the separate wells.
 void launch_spmv_running(const DevSchedule &d, const double *Ap, size_t a_stride, const double *x, double *y,
-                         size_t vstride, SysState *st, int nsys, int variant, const WellsDev &w, hipStream_t s);
+                         size_t vstride, SysState *st, int nsys, int variant, const WellsDev &w, hipStream_t s,
+                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // GMRES workspace as the kernels see it.  Vectors of all systems at stride
 // vstride; Krylov basis column c of system s at V + c * colstride + s * vstride.
@@ -232,23 +240,28 @@ inline size_t gm_part_stride() { return (size_t)(kGmMax + 1) * (kVecMaxBlocks + 
 // A cycle's start after the setup: beta = ||r||, g = beta e_1.
 void launch_gm_init(const GmWork &g, int nsys, hipStream_t s);
 // V column `col` = src / beta (from_w = 0) or src / h_{j+1,j} (from_w = 1).
-void launch_gm_normalise(const GmWork &g, const double *src, int col, int from_w, int n, int nsys, hipStream_t s);
+void launch_gm_normalise(const GmWork &g, const double *src, int col, int from_w, int n, int nsys, hipStream_t s,
+                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // First classical Gram-Schmidt pass: h_i = (w, v_i), i < jv; column jv - 1
 // of H = h.
-void launch_gm_dots(const GmWork &g, int jv, const double *w, int n, int nsys, hipStream_t s);
+void launch_gm_dots(const GmWork &g, int jv, const double *w, int n, int nsys, hipStream_t s,
+                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // w -= V h with the current coefficients; then either the second pass's
 // coefficients (added to H's column jv - 1) or, when `last`, ||w|| =
 // h_{jv,jv-1}, the Givens update of the column and the step's tests.
-void launch_gm_orth(const GmWork &g, int jv, double *w, bool last, int n, int nsys, hipStream_t s);
+void launch_gm_orth(const GmWork &g, int jv, double *w, bool last, int n, int nsys, hipStream_t s,
+                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // End of a cycle, for every system not done: y = H^-1 g, u = V y.
-void launch_gm_combine(const GmWork &g, double *u, int n, int nsys, hipStream_t s);
+void launch_gm_combine(const GmWork &g, double *u, int n, int nsys, hipStream_t s, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
 // x += z for every system not done.
-void launch_gm_xupdate(const GmWork &g, double *x, const double *z, int n, int nsys, hipStream_t s);
+void launch_gm_xupdate(const GmWork &g, double *x, const double *z, int n, int nsys, hipStream_t s,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // After the update: PH_HALF -> PH_DONE.
 void launch_gm_phase(const GmWork &g, int nsys, hipStream_t s);
 // Restart: r = rhs - w, beta = ||r||, the reduction test, a fresh cycle.
 void launch_gm_restart(const GmWork &g, const double *rhs, const double *w, double *r, int n, int nsys,
-                       hipStream_t s);
+                       hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // out[i] = in[perm[i]] (gather to the new order) and its inverse scatter;
 // the new-order side has stride vstride, the caller side 3n.

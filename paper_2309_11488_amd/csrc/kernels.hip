@@ -1407,6 +1407,17 @@ static int copy_blocks(size_t m) {
     return (int)g;
 }
 
+// Launch with optional dispatch-recorded events (start and end of the
+// kernel itself); arguments are converted to the kernel's parameter types.
+template <typename... P, typename... A>
+static void launch_ev(void (*kernel)(P...), dim3 g, dim3 b, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                      A... args) {
+    if (ev0)
+        hipExtLaunchKernelGGL(kernel, g, b, 0, s, ev0, ev1, 0, static_cast<P>(args)...);
+    else
+        hipLaunchKernelGGL(kernel, g, b, 0, s, static_cast<P>(args)...);
+}
+
 void launch_gather_pairs(const double *A, size_t a_stride, double *Ap, size_t ap_stride, const int32_t *dst,
                          const int32_t *src, int cnt, int nsys, hipStream_t s) {
     if (cnt <= 0 || nsys <= 0) return;
@@ -1428,83 +1439,84 @@ void launch_factor_level(const DevSchedule &d, const double *A, size_t a_stride,
 template <typename T>
 void launch_lsweep(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
                    bool fuse_p, const double *r, const double *v, double *p, SysState *st, int q0, int q1, int nsys,
-                   int variant, const T *Dinv, size_t d_stride, double *z, int u0_end, hipStream_t s) {
+                   int variant, const T *Dinv, size_t d_stride, double *z, int u0_end, hipStream_t s, hipEvent_t ev0,
+                   hipEvent_t ev1) {
     if (q1 <= q0 || nsys <= 0) return;
     with_variant(variant, [&](auto W, auto ST) {
         constexpr int w = decltype(W)::value;
         constexpr bool staged = decltype(ST)::value;
         const dim3 g(row_blocks(q1 - q0, w), nsys);
         if (fuse_p)
-            k_lsweep<T, true, w, staged><<<g, 64 * w, 0, s>>>(d, L, l_stride, in, y, vstride, r, v, p, st, q0, q1,
-                                                              Dinv, d_stride, z, u0_end);
+            launch_ev(k_lsweep<T, true, w, staged>, g, dim3(64 * w), s, ev0, ev1, d, L, l_stride, in, y, vstride, r,
+                      v, p, st, q0, q1, Dinv, d_stride, z, u0_end);
         else
-            k_lsweep<T, false, w, staged><<<g, 64 * w, 0, s>>>(d, L, l_stride, in, y, vstride, r, v, p, st, q0, q1,
-                                                               Dinv, d_stride, z, u0_end);
+            launch_ev(k_lsweep<T, false, w, staged>, g, dim3(64 * w), s, ev0, ev1, d, L, l_stride, in, y, vstride, r,
+                      v, p, st, q0, q1, Dinv, d_stride, z, u0_end);
     });
 }
 
 template <typename T>
 void launch_usweep(const DevSchedule &d, const T *U, size_t u_stride, const T *Dinv, size_t d_stride, const T *y,
                    double *z, size_t vstride, SysState *st, int q0, int q1, int nsys, int variant, bool defer,
-                   hipStream_t s) {
+                   hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (q1 <= q0 || nsys <= 0) return;
     with_variant(variant, [&](auto W, auto ST) {
         constexpr int w = decltype(W)::value;
         constexpr bool staged = decltype(ST)::value;
-        k_usweep<T, w, staged><<<dim3(row_blocks(q1 - q0, w), nsys), 64 * w, 0, s>>>(d, U, u_stride, Dinv, d_stride, y,
-                                                                                   z, vstride, st, q0, q1,
-                                                                                   defer ? 1 : 0);
+        launch_ev(k_usweep<T, w, staged>, dim3(row_blocks(q1 - q0, w), nsys), dim3(64 * w), s, ev0, ev1, d, U,
+                  u_stride, Dinv, d_stride, y, z, vstride, st, q0, q1, defer ? 1 : 0);
     });
 }
 
 template void launch_lsweep<double>(const DevSchedule &, const double *, size_t, const double *, double *, size_t,
                                     bool, const double *, const double *, double *, SysState *, int, int, int, int,
-                                    const double *, size_t, double *, int, hipStream_t);
+                                    const double *, size_t, double *, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_lsweep<float>(const DevSchedule &, const float *, size_t, const double *, float *, size_t, bool,
                                    const double *, const double *, double *, SysState *, int, int, int, int,
-                                   const float *, size_t, double *, int, hipStream_t);
+                                   const float *, size_t, double *, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_usweep<double>(const DevSchedule &, const double *, size_t, const double *, size_t,
                                     const double *, double *, size_t, SysState *, int, int, int, int, bool,
-                                    hipStream_t);
+                                    hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_usweep<float>(const DevSchedule &, const float *, size_t, const float *, size_t, const float *,
-                                   double *, size_t, SysState *, int, int, int, int, bool, hipStream_t);
+                                   double *, size_t, SysState *, int, int, int, int, bool, hipStream_t, hipEvent_t,
+                                   hipEvent_t);
 
 template <typename T>
 void launch_lsweep_tiles(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
                          bool fuse_p, const double *r, const double *v, double *p, SysState *st, int32_t *flags,
-                         SweepCtr *ctr, int nsys, int grid, hipStream_t s) {
+                         SweepCtr *ctr, int nsys, int grid, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (d.nlt <= 0 || nsys <= 0) return;
     grid = std::max(1, std::min(grid, d.nlt * nsys));
     if (fuse_p)
-        k_lsweep_tiles<T, true><<<grid, kRowThreads, 0, s>>>(d, L, l_stride, in, y, vstride, r, v, p, st, flags, ctr,
-                                                             nsys);
+        launch_ev(k_lsweep_tiles<T, true>, dim3(grid), dim3(kRowThreads), s, ev0, ev1, d, L, l_stride, in, y,
+                  vstride, r, v, p, st, flags, ctr, nsys);
     else
-        k_lsweep_tiles<T, false><<<grid, kRowThreads, 0, s>>>(d, L, l_stride, in, y, vstride, r, v, p, st, flags,
-                                                              ctr, nsys);
+        launch_ev(k_lsweep_tiles<T, false>, dim3(grid), dim3(kRowThreads), s, ev0, ev1, d, L, l_stride, in, y,
+                  vstride, r, v, p, st, flags, ctr, nsys);
 }
 
 template <typename T>
 void launch_usweep_tiles(const DevSchedule &d, const T *U, size_t u_stride, const T *Dinv, size_t d_stride,
                          const T *y, double *z, size_t vstride, SysState *st, int32_t *flags, SweepCtr *ctr, int nsys,
-                         int grid, hipStream_t s) {
+                         int grid, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (d.nut <= 0 || nsys <= 0) return;
     grid = std::max(1, std::min(grid, d.nut * nsys));
-    k_usweep_tiles<T><<<grid, kRowThreads, 0, s>>>(d, U, u_stride, Dinv, d_stride, y, z, vstride, st, flags, ctr,
-                                                   nsys);
+    launch_ev(k_usweep_tiles<T>, dim3(grid), dim3(kRowThreads), s, ev0, ev1, d, U, u_stride, Dinv, d_stride, y, z,
+              vstride, st, flags, ctr, nsys);
 }
 
 template void launch_lsweep_tiles<double>(const DevSchedule &, const double *, size_t, const double *, double *,
                                           size_t, bool, const double *, const double *, double *, SysState *,
-                                          int32_t *, SweepCtr *, int, int, hipStream_t);
+                                          int32_t *, SweepCtr *, int, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_lsweep_tiles<float>(const DevSchedule &, const float *, size_t, const double *, float *,
                                          size_t, bool, const double *, const double *, double *, SysState *,
-                                         int32_t *, SweepCtr *, int, int, hipStream_t);
+                                         int32_t *, SweepCtr *, int, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_usweep_tiles<double>(const DevSchedule &, const double *, size_t, const double *, size_t,
                                           const double *, double *, size_t, SysState *, int32_t *, SweepCtr *, int,
-                                          int, hipStream_t);
+                                          int, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_usweep_tiles<float>(const DevSchedule &, const float *, size_t, const float *, size_t,
                                          const float *, double *, size_t, SysState *, int32_t *, SweepCtr *, int,
-                                         int, hipStream_t);
+                                         int, hipStream_t, hipEvent_t, hipEvent_t);
 
 // ev0 / ev1 (optional): events the dispatch itself records at the SpMV
 // kernel's start and end (kernel time only, no launch overhead).
@@ -1555,20 +1567,22 @@ void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Kryl
                      k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, w, s, ev0, ev1);
 }
 
-void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, int split, hipStream_t s) {
+void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, int split, hipStream_t s, hipEvent_t ev0,
+                     hipEvent_t ev1) {
     const SpmvSums at = spmv_sums(n, variant_waves(spmv_variant), split);
-    k_s_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(k, at.offset, at.count);
+    launch_ev(k_s_update, dim3(vec_blocks(n), nsys), dim3(kVecThreads), s, ev0, ev1, k, at.offset, at.count);
 }
 
 void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
-                   int split, const WellsDev &w, hipStream_t s) {
+                   int split, const WellsDev &w, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     spmv_any<SPMV_T>(variant, d.n, d.prow, d.pcol, Ap, a_stride, k.shat, k.t, k.vstride, k.s, k.spart,
-                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, w, s);
+                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, w, s, ev0, ev1);
 }
 
-void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, int split, hipStream_t s) {
+void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, int split, hipStream_t s, hipEvent_t ev0,
+                      hipEvent_t ev1) {
     const SpmvSums at = spmv_sums(n, variant_waves(spmv_variant), split);
-    k_xr_update<<<dim3(vec_blocks(n), nsys), kVecThreads, 0, s>>>(k, at.offset, at.count);
+    launch_ev(k_xr_update, dim3(vec_blocks(n), nsys), dim3(kVecThreads), s, ev0, ev1, k, at.offset, at.count);
 }
 
 void launch_permute_vec(const int32_t *perm, const double *in, double *out, int n, size_t vstride, int nsys,
@@ -1590,10 +1604,11 @@ void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *c
 // ------------------------------------------------------------------ GMRES
 
 void launch_spmv_running(const DevSchedule &d, const double *Ap, size_t a_stride, const double *x, double *y,
-                         size_t vstride, SysState *st, int nsys, int variant, const WellsDev &w, hipStream_t s) {
+                         size_t vstride, SysState *st, int nsys, int variant, const WellsDev &w, hipStream_t s,
+                         hipEvent_t ev0, hipEvent_t ev1) {
     if (d.n <= 0 || nsys <= 0) return;
     spmv_any<SPMV_RUN>(variant, d.n, d.prow, d.pcol, Ap, a_stride, x, y, vstride, nullptr, nullptr, 0, nullptr, 0,
-                       st, nsys, 0, w, s);
+                       st, nsys, 0, w, s, ev0, ev1);
 }
 
 // Workgroups of the GMRES vector kernels: one per 256 * items entries of a
@@ -1621,39 +1636,45 @@ void launch_gm_init(const GmWork &g, int nsys, hipStream_t s) {
     k_gm_init<<<(nsys + 63) / 64, 64, 0, s>>>(g, nsys);
 }
 
-void launch_gm_normalise(const GmWork &g, const double *src, int col, int from_w, int n, int nsys, hipStream_t s) {
+void launch_gm_normalise(const GmWork &g, const double *src, int col, int from_w, int n, int nsys, hipStream_t s,
+                         hipEvent_t ev0, hipEvent_t ev1) {
     if (n <= 0 || nsys <= 0) return;
-    k_gm_normalise<<<dim3(gm_blocks(n), nsys), kGmThreads, 0, s>>>(g, src, col, from_w);
+    launch_ev(k_gm_normalise, dim3(gm_blocks(n), nsys), dim3(kGmThreads), s, ev0, ev1, g, src, col, from_w);
 }
 
-void launch_gm_dots(const GmWork &g, int jv, const double *w, int n, int nsys, hipStream_t s) {
+void launch_gm_dots(const GmWork &g, int jv, const double *w, int n, int nsys, hipStream_t s, hipEvent_t ev0,
+                    hipEvent_t ev1) {
     if (n <= 0 || nsys <= 0 || jv < 1 || jv > kGmMax) return;
     with_nv(jv, [&](auto NV, auto IT) {
         constexpr int it = decltype(IT)::value;
-        k_gm_dots<decltype(NV)::value, it><<<dim3(gm_blocks(n, it), nsys), kGmThreads, 0, s>>>(g, jv, w);
+        launch_ev(k_gm_dots<decltype(NV)::value, it>, dim3(gm_blocks(n, it), nsys), dim3(kGmThreads), s, ev0, ev1, g,
+                  jv, w);
     });
 }
 
-void launch_gm_orth(const GmWork &g, int jv, double *w, bool last, int n, int nsys, hipStream_t s) {
+void launch_gm_orth(const GmWork &g, int jv, double *w, bool last, int n, int nsys, hipStream_t s, hipEvent_t ev0,
+                    hipEvent_t ev1) {
     if (n <= 0 || nsys <= 0 || jv < 1 || jv > kGmMax) return;
     with_nv(jv, [&](auto NV, auto IT) {
         constexpr int nv = decltype(NV)::value, it = decltype(IT)::value;
         const dim3 grid(gm_blocks(n, it), nsys);
         if (last)
-            k_gm_orth<nv, true, it><<<grid, kGmThreads, 0, s>>>(g, jv, w);
+            launch_ev(k_gm_orth<nv, true, it>, grid, dim3(kGmThreads), s, ev0, ev1, g, jv, w);
         else
-            k_gm_orth<nv, false, it><<<grid, kGmThreads, 0, s>>>(g, jv, w);
+            launch_ev(k_gm_orth<nv, false, it>, grid, dim3(kGmThreads), s, ev0, ev1, g, jv, w);
     });
 }
 
-void launch_gm_combine(const GmWork &g, double *u, int n, int nsys, hipStream_t s) {
+void launch_gm_combine(const GmWork &g, double *u, int n, int nsys, hipStream_t s, hipEvent_t ev0,
+                       hipEvent_t ev1) {
     if (n <= 0 || nsys <= 0) return;
-    k_gm_combine<<<dim3(gm_blocks(n), nsys), kGmThreads, 0, s>>>(g, u);
+    launch_ev(k_gm_combine, dim3(gm_blocks(n), nsys), dim3(kGmThreads), s, ev0, ev1, g, u);
 }
 
-void launch_gm_xupdate(const GmWork &g, double *x, const double *z, int n, int nsys, hipStream_t s) {
+void launch_gm_xupdate(const GmWork &g, double *x, const double *z, int n, int nsys, hipStream_t s,
+                       hipEvent_t ev0, hipEvent_t ev1) {
     if (n <= 0 || nsys <= 0) return;
-    k_gm_xupdate<<<dim3(gm_blocks(n), nsys), kGmThreads, 0, s>>>(g, x, z);
+    launch_ev(k_gm_xupdate, dim3(gm_blocks(n), nsys), dim3(kGmThreads), s, ev0, ev1, g, x, z);
 }
 
 void launch_gm_phase(const GmWork &g, int nsys, hipStream_t s) {
@@ -1662,9 +1683,9 @@ void launch_gm_phase(const GmWork &g, int nsys, hipStream_t s) {
 }
 
 void launch_gm_restart(const GmWork &g, const double *rhs, const double *w, double *r, int n, int nsys,
-                       hipStream_t s) {
+                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (n <= 0 || nsys <= 0) return;
-    k_gm_restart<<<dim3(gm_blocks(n), nsys), kGmThreads, 0, s>>>(g, rhs, w, r);
+    launch_ev(k_gm_restart, dim3(gm_blocks(n), nsys), dim3(kGmThreads), s, ev0, ev1, g, rhs, w, r);
 }
 
 }  // namespace rs
