@@ -1142,10 +1142,31 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
         ProfScope ps(PC_VEC, s, (double)B * 152 * M->n);
         rs::launch_setup(M->an->dev, bd, M->bad.as<int32_t>(), reduction, max_iter, k, B, s);
     }
+    // x back to the caller's order, the true residual, and the results to the host
+    auto finish = [&]() -> int {
+        rs::launch_finish(M->an->dev, A->rowptr.as<int32_t>(), A->colidx.as<int32_t>(), A->vals.as<double>(),
+                          (size_t)A->nnzb * 9, bd, xd, k, B, M->spmv_variant, M->split(), A->wells(), s);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(M->h_ctr, k.lctr, 2 * sizeof(rs::SweepCtr), hipMemcpyDeviceToHost, s));
+        if (mem != RS_MEM_DEVICE) HIP_TRY(hipMemcpyAsync(x, xd, m * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return RS_OK;
+    };
+    auto all_done = [&]() {
+        bool all = true;
+        for (int i = 0; i < B; ++i) all &= (M->h_state[i].phase == rs::PH_DONE);
+        return all;
+    };
+    // The first poll comes after as many iterations as the previous solve
+    // needed and carries the finishing work with it, so a solve that ends
+    // there costs one host synchronisation; otherwise the finishing work is
+    // simply repeated after the last iteration.
     int done_iters = 0;
-    bool first = true;
+    bool first = true, finished = false;
     while (done_iters < max_iter) {
-        int c = first && M->predict ? std::max(M->chunk, M->last_iters) : M->chunk;
+        const bool predicted = first && M->predict;
+        int c = predicted ? std::max(M->chunk, M->last_iters) : M->chunk;
         c = std::min(c, max_iter - done_iters);
         first = false;
         for (int i = 0; i < c; ++i) {
@@ -1153,19 +1174,23 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
             if (st != RS_OK) return st;
         }
         done_iters += c;
+        if (predicted) {
+            st = finish();
+            if (st != RS_OK) return st;
+            if (all_done()) {
+                finished = true;
+                break;
+            }
+            continue;
+        }
         HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        bool all = true;
-        for (int i = 0; i < B; ++i) all &= (M->h_state[i].phase == rs::PH_DONE);
-        if (all) break;
+        if (all_done()) break;
     }
-    rs::launch_finish(M->an->dev, A->rowptr.as<int32_t>(), A->colidx.as<int32_t>(), A->vals.as<double>(),
-                      (size_t)A->nnzb * 9, bd, xd, k, B, M->spmv_variant, M->split(), A->wells(), s);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(M->h_ctr, k.lctr, 2 * sizeof(rs::SweepCtr), hipMemcpyDeviceToHost, s));
-    if (mem != RS_MEM_DEVICE) HIP_TRY(hipMemcpyAsync(x, xd, m * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    if (!finished) {
+        st = finish();
+        if (st != RS_OK) return st;
+    }
     if (M->h_ctr[0].error || M->h_ctr[1].error) {
         HIP_TRY(hipMemsetAsync(M->ctrs.p, 0, 2 * sizeof(rs::SweepCtr), s));
         HIP_TRY(hipStreamSynchronize(s));
