@@ -85,6 +85,8 @@ def lib():
         L.orc_wells_apply.argtypes = [ci, _I32P, _I32P, _F64P, _F64P, _F64P, _F64P, _F64P]
         L.orc_gmres.argtypes = [ci, _I32P, _I32P, _F64P, _F64P, _F64P, ci, _F64P, ci, cd, ci, _F64P,
                                 ct.POINTER(Info), vp]
+        L.orc_gmres_wells.argtypes = [ci, _I32P, _I32P, _F64P, ci, vp, vp, vp, vp, vp, _F64P, _F64P, ci, _F64P,
+                                      ci, cd, ci, _F64P, ct.POINTER(Info), vp]
         L.orc_wells_apply.restype = None
         L.orc_solve_wells.argtypes = [ci, _I32P, _I32P, _F64P, vp, ci, vp, vp, vp, vp, vp, _F64P, ci, ci, cd, ci,
                                       _F64P, ct.POINTER(Info), _I32P, ct.POINTER(ci), ct.POINTER(ci)]
@@ -195,8 +197,10 @@ def wells_apply(well_ptr, perf_row, B, C, Dinv, x, y):
 
 
 def gmres(rowptr, colidx, vals, lu, dinv, b, *, precond=PREC_ILU_F64, restart=30, reduction=1e-2, max_iter=200,
-          trace=False):
+          trace=False, wells=None):
     """Right-preconditioned GMRES(restart) on an already ordered system.
+    ``wells`` = (well_ptr, perf_row, B, C, Dinv) in this system's numbering
+    adds standard wells kept separate to every product with A.
     Returns (x, info dict[, residual estimate after every Arnoldi step])."""
     n = len(rowptr) - 1
     x = np.zeros((n, 3), np.float64)
@@ -204,17 +208,26 @@ def gmres(rowptr, colidx, vals, lu, dinv, b, *, precond=PREC_ILU_F64, restart=30
     tr = np.zeros(max(max_iter, 1), np.float64) if trace else None
     lu = _f64(lu) if lu is not None else np.zeros((max(len(colidx), 1), 3, 3))
     dinv = _f64(dinv) if dinv is not None else np.zeros((max(n, 1), 3, 3))
-    lib().orc_gmres(n, _i32(rowptr), _i32(colidx), _f64(vals), lu, dinv, precond, _f64(b).reshape(n, 3),
-                    int(restart), reduction, max_iter, x, ct.byref(info), tr.ctypes.data if tr is not None else None)
+    trp = tr.ctypes.data if tr is not None else None
+    if wells is None:
+        lib().orc_gmres(n, _i32(rowptr), _i32(colidx), _f64(vals), lu, dinv, precond, _f64(b).reshape(n, 3),
+                        int(restart), reduction, max_iter, x, ct.byref(info), trp)
+    else:
+        wp, pr, B, C, D = (_i32(wells[0]), _i32(wells[1]), _f64(wells[2]), _f64(wells[3]), _f64(wells[4]))
+        lib().orc_gmres_wells(n, _i32(rowptr), _i32(colidx), _f64(vals), len(wp) - 1, wp.ctypes.data,
+                              pr.ctypes.data, B.ctypes.data, C.ctypes.data, D.ctypes.data, lu, dinv, precond,
+                              _f64(b).reshape(n, 3), int(restart), reduction, max_iter, x, ct.byref(info), trp)
     if trace:
         return x, info.as_dict(), tr[:info.half_steps]
     return x, info.as_dict()
 
 
 def solve_gmres(rowptr, colidx, vals, b, *, ordering=ORDER_NATURAL, precond=PREC_ILU_F64, restart=30,
-                reduction=1e-2, max_iter=200):
+                reduction=1e-2, max_iter=200, wells=None):
     """The whole path with GMRES: ordering, reordered copy, ILU0, GMRES,
-    x back in the original order, true residual with the original A."""
+    x back in the original order, true residual with the original operator
+    (``wells`` = (well_ptr, perf_row, B, C, Dinv) in the caller's numbering:
+    standard wells kept separate)."""
     perm = ordering_perm(rowptr, colidx, ordering)
     prow, pcol, pv = permute(rowptr, colidx, vals, perm)
     lu = dinv = None
@@ -223,11 +236,19 @@ def solve_gmres(rowptr, colidx, vals, b, *, ordering=ORDER_NATURAL, precond=PREC
         if st != OK:
             return np.zeros((len(rowptr) - 1, 3)), {"status": st, "bad_row": int(perm[bad]) if bad >= 0 else -1}
     b = _f64(b).reshape(-1, 3)
+    pw = None
+    if wells is not None:
+        iperm = np.empty_like(perm)
+        iperm[perm] = np.arange(len(perm), dtype=perm.dtype)
+        pw = (wells[0], iperm[_i32(wells[1])], wells[2], wells[3], wells[4])
     xp, info = gmres(prow, pcol, pv, lu, dinv, b[perm], precond=precond, restart=restart, reduction=reduction,
-                     max_iter=max_iter)
+                     max_iter=max_iter, wells=pw)
     x = np.empty_like(xp)
     x[perm] = xp
-    r = b - spmv(rowptr, colidx, vals, x)
+    ax = spmv(rowptr, colidx, vals, x)
+    if wells is not None:
+        ax = wells_apply(wells[0], wells[1], wells[2], wells[3], wells[4], x, ax)
+    r = b - ax.reshape(-1, 3)
     info["true_rel_residual"] = float(np.linalg.norm(r) / np.linalg.norm(b)) if np.linalg.norm(b) > 0 else 0.0
     info["perm"] = perm
     return x, info

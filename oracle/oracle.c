@@ -764,9 +764,9 @@ out:
  * r = b - A x (and the solve ends if its norm meets the test).  info->half_steps counts the Arnoldi steps (one
  * preconditioner application and one product with A each).  trace
  * (optional): |g_{j+1}| after every step. */
-int orc_gmres(int n, const int *rowptr, const int *colidx, const double *vals, const double *lu, const double *dinv,
-              int precond_kind, const double *b, int m, double reduction, int max_iter, double *x, orc_info *info,
-              double *trace)
+static int gmres_core(int n, const int *rowptr, const int *colidx, const double *vals, const wells_t *wl,
+                      const double *lu, const double *dinv, int precond_kind, const double *b, int m, double reduction,
+                      int max_iter, double *x, orc_info *info, double *trace)
 {
     size_t n3 = 3 * (size_t)n, nb = n3 > 0 ? n3 : 1;
     if (m < 1) m = 1;
@@ -804,7 +804,7 @@ int orc_gmres(int n, const int *rowptr, const int *colidx, const double *vals, c
         for (int j = 0; j < m; ++j) {
             double *vj = V + (size_t)j * nb;
             prec_apply(&pc, vj, z);
-            orc_spmv(n, rowptr, colidx, vals, z, w);
+            op_apply(n, rowptr, colidx, vals, wl, z, w);
             for (int i = 0; i <= j; ++i) H[i + (size_t)j * (m + 1)] = 0.0;
             for (int pass = 0; pass < 2; ++pass) {
                 for (int i = 0; i <= j; ++i) h[i] = dot((int)n3, w, V + (size_t)i * nb);
@@ -853,7 +853,7 @@ int orc_gmres(int n, const int *rowptr, const int *colidx, const double *vals, c
         prec_apply(&pc, w, z);
         for (size_t e = 0; e < n3; ++e) x[e] += z[e];
         if (stop) break;
-        orc_spmv(n, rowptr, colidx, vals, x, w);
+        op_apply(n, rowptr, colidx, vals, wl, x, w);
         for (size_t e = 0; e < n3; ++e) r[e] = b[e] - w[e];
         beta = sqrt(dot((int)n3, r, r));
         last = beta;
@@ -867,4 +867,25 @@ done:
     free(lu32); free(dinv32); free(V); free(z); free(w); free(r); free(H); free(cs); free(sn); free(g); free(h);
     free(y);
     return status;
+}
+
+int orc_gmres(int n, const int *rowptr, const int *colidx, const double *vals, const double *lu, const double *dinv,
+              int precond_kind, const double *b, int m, double reduction, int max_iter, double *x, orc_info *info,
+              double *trace)
+{
+    return gmres_core(n, rowptr, colidx, vals, NULL, lu, dinv, precond_kind, b, m, reduction, max_iter, x, info,
+                      trace);
+}
+
+/* The same with standard wells kept separate (Algorithm 5) in every product
+ * with A: the operator is A x - sum_w C_w^T D_w^-1 B_w x; the
+ * preconditioner stays ILU0 of A.  Wells in this system's numbering. */
+int orc_gmres_wells(int n, const int *rowptr, const int *colidx, const double *vals, int n_wells, const int *well_ptr,
+                    const int *perf_row, const double *B, const double *C, const double *Dinv, const double *lu,
+                    const double *dinv, int precond_kind, const double *b, int m, double reduction, int max_iter,
+                    double *x, orc_info *info, double *trace)
+{
+    wells_t wl = {n_wells, well_ptr, perf_row, B, C, Dinv};
+    return gmres_core(n, rowptr, colidx, vals, n_wells > 0 ? &wl : NULL, lu, dinv, precond_kind, b, m, reduction,
+                      max_iter, x, info, trace);
 }

@@ -632,3 +632,31 @@ def test_gmres_no_steps():
     assert info["status"] == oracle.NOT_CONVERGED and info["half_steps"] == 0 and not x.any()
     x, info = oracle.gmres(s.rowptr, s.colidx, s.vals[0], lu, dinv, np.zeros((s.n, 3)), restart=5, max_iter=10)
     assert info["status"] == oracle.OK and info["half_steps"] == 0 and not x.any()
+
+
+@pytest.mark.parametrize("restart", [3, 30])
+def test_gmres_with_wells_converges_to_the_coupled_system(restart):
+    """GMRES with standard wells kept separate solves the coupled system
+    A - sum_w C_w^T D_w^-1 B_w (dense, Algorithm 4) for every ordering, and
+    its first step's estimate is the minimal residual over span{b} of that
+    operator times M^-1 (so the wells enter the Arnoldi products)."""
+    from synth import make_wells
+    s = make_grid_system(9, 7, 6, nnc_frac=0.03, seed=68)
+    w = make_wells(s, 5, seed=69)
+    wells = (w.well_ptr, w.perf_row, w.B[0], w.C[0], w.Dinv[0])
+    Ac = coupled_dense(s, w)
+    b = s.b[0, 0].ravel()
+    xr = np.linalg.solve(Ac, b)
+    for ordering in (oracle.ORDER_NATURAL, oracle.ORDER_LEVEL, oracle.ORDER_COLOUR):
+        x, info = oracle.solve_gmres(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=ordering, restart=restart,
+                                     reduction=1e-12, max_iter=2000, wells=wells)
+        assert info["status"] == oracle.OK and info["true_rel_residual"] <= 1e-11
+        assert np.linalg.norm(x.ravel() - xr) / np.linalg.norm(xr) < 1e-9
+    st, _, lu, dinv = oracle.ilu0(s.rowptr, s.colidx, s.vals[0])
+    Minv = np.column_stack([oracle.apply(s.rowptr, s.colidx, lu, dinv, e.reshape(-1, 3)).ravel()
+                            for e in np.eye(3 * s.n)])
+    q = Ac @ (Minv @ b)
+    best = np.linalg.norm(b - (q @ b) / (q @ q) * q)
+    _, info = oracle.gmres(s.rowptr, s.colidx, s.vals[0], lu, dinv, b, restart=restart, reduction=0.0, max_iter=1,
+                           wells=wells)
+    assert abs(info["final_norm"] - best) <= 1e-10 * np.linalg.norm(b)
