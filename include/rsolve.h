@@ -290,10 +290,11 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
  * last residual estimate (or explicit residual norm after a restart).
  * A breakdown of the basis (h_{j+1,j} = 0) zeroes the estimate, so it
  * ends the solve as converged.
- * b, x: batch * n_brows * 3 doubles (mem).  Workspace: restart basis
- * vectors per system, allocated on first use and kept by the handle.
- * Errors: RS_INVALID_ARG (also for a matrix with separate wells),
- * RS_NOT_FACTORED, RS_PATTERN_MISMATCH, RS_OUT_OF_MEMORY, RS_HIP_ERROR.
+ * Standard wells set on A (bcsr_set_wells) enter every product with A, as
+ * in bicgstab_solve.  b, x: batch * n_brows * 3 doubles (mem).  Workspace:
+ * restart basis vectors per system, allocated on first use and kept by the
+ * handle.  Errors: RS_INVALID_ARG, RS_NOT_FACTORED, RS_PATTERN_MISMATCH,
+ * RS_OUT_OF_MEMORY, RS_HIP_ERROR.
  * Returns the worst status over the systems, as bicgstab_solve (never
  * RS_BREAKDOWN).  Synchronises `stream`. */
 int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart, double reduction,

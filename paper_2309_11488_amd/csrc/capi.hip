@@ -1296,7 +1296,6 @@ int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart,
         (mem != RS_MEM_HOST && mem != RS_MEM_DEVICE))
         return fail(RS_INVALID_ARG, "gmres_solve: bad arguments");
     if (!M->factored) return fail(RS_NOT_FACTORED, "gmres_solve: call ilu0_factor first");
-    if (A->nw > 0) return fail(RS_INVALID_ARG, "gmres_solve: matrices with separate wells are not supported");
     const int B = M->batch;
     if (M->n == 0) {
         if (info)

@@ -132,10 +132,6 @@ def test_gmres_degenerate_inputs():
                 sol.solve_gmres(s.b[:, 0], restart=restart)
         x, st, info = sol.solve_gmres(s.b[:, 0], restart=rs.GMRES_MAX_RESTART, reduction=1e-8, max_iter=300)
         assert st == rs.OK and info[0]["true_rel_residual"] <= 1e-7
-        w = make_wells(s, 2, seed=77)
-        rs.bcsr_set_wells(sol.A, w.well_ptr, w.perf_row, w.B, w.C, w.Dinv)
-        with pytest.raises(rs.RsolveError):
-            sol.solve_gmres(s.b[:, 0])
 
 
 def test_gmres_then_bicgstab_on_one_handle():
@@ -165,3 +161,23 @@ def test_gmres_full_size_96k(precision):
         tol = 1e-9 if precision == rs.PREC_FP64 else 1e-6
         assert np.linalg.norm(x[0] - xo) <= tol * np.linalg.norm(xo)
     assert info[0]["true_rel_residual"] <= 1e-2
+
+
+@pytest.mark.parametrize("ordering", ORDERINGS)
+@pytest.mark.parametrize("restart", [4, 30])
+def test_gmres_with_wells_matches_oracle(ordering, restart):
+    """Standard wells kept separate (Algorithm 5) in every product with A."""
+    s = make_grid_system(14, 11, 9, active_frac=0.9, nnc_frac=0.02, seed=51)
+    w = make_wells(s, 6, seed=52)
+    with rs.Solver(s.rowptr, s.colidx, s.vals, ordering=ordering) as sol:
+        rs.bcsr_set_wells(sol.A, w.well_ptr, w.perf_row, w.B, w.C, w.Dinv)
+        sol.factor()
+        x, st, info = sol.solve_gmres(s.b[:, 0], restart=restart, reduction=1e-10, max_iter=2000)
+    xo, oinfo = oracle.solve_gmres(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=ordering, restart=restart,
+                                   reduction=1e-10, max_iter=2000,
+                                   wells=(w.well_ptr, w.perf_row, w.B[0], w.C[0], w.Dinv[0]))
+    assert st == oinfo["status"] == rs.OK
+    assert np.linalg.norm(x[0] - xo) <= 1e-8 * np.linalg.norm(xo)
+    assert abs(info[0]["half_steps"] - oinfo["half_steps"]) <= 1, (info, oinfo)
+    assert info[0]["true_rel_residual"] <= 1e-9
+    assert info[0]["true_rel_residual"] == pytest.approx(oinfo["true_rel_residual"], rel=0.5, abs=1e-12)
