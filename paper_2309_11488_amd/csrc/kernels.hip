@@ -384,8 +384,21 @@ __device__ inline void row3_store(float *p, const double (&v)[3]) {
     p[0] = (float)v[0]; p[1] = (float)v[1]; p[2] = (float)v[2];
 }
 // out = row (a0 a1 a2) times the 3x3 block m
-__device__ inline void row3_mul(const double (&a)[3], const double *__restrict__ m, double (&out)[3]) {
-    for (int c = 0; c < 3; ++c) out[c] = a[0] * m[c] + a[1] * m[3 + c] + a[2] * m[6 + c];
+// out = a m for a 3x3 block m of another block row, which all three lanes of
+// this block row need whole: lane r loads row r of m (mr = m + 3r) and the
+// rows are exchanged with shuffles, so each lane issues three loads instead
+// of nine.  All three lanes of the row must take this call together.
+__device__ inline void row3_mul(const double (&a)[3], const double *__restrict__ mr, int base, double (&out)[3]) {
+    const double r0 = mr[0], r1 = mr[1], r2 = mr[2];
+    double m[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        m[k][0] = __shfl(r0, base + k, 64);
+        m[k][1] = __shfl(r1, base + k, 64);
+        m[k][2] = __shfl(r2, base + k, 64);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c] = __builtin_fma(a[2], m[2][c], __builtin_fma(a[1], m[1][c], a[0] * m[0][c]));
 }
 
 // Block ILU0, one level of the lower schedule.  Lane r of row i owns row r of
@@ -442,13 +455,13 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
             for (int t = 0; t < kFactorMax; ++t) {
                 if (e0 + t >= e1) continue;
                 double l[3];
-                row3_mul(lv[t], Ds + (size_t)dq[t] * 9, l);
+                row3_mul(lv[t], Ds + (size_t)dq[t] * 9 + 3 * r, rl.base, l);
                 lv[t][0] = l[0]; lv[t][1] = l[1]; lv[t][2] = l[2];
                 const int u1 = d.upd_ptr[e0 + t + 1];
                 for (int u = d.upd_ptr[e0 + t]; u < u1; ++u) {
                     const int code = d.upd[2 * u], fs = d.upd[2 * u + 1];
                     double pr[3];
-                    row3_mul(l, Us + (size_t)fs * 9, pr);
+                    row3_mul(l, Us + (size_t)fs * 9 + 3 * r, rl.base, pr);
                     const int kind = code & 3, pos = code >> 2;
                     if (kind == 1) {
                         dr[0] -= pr[0]; dr[1] -= pr[1]; dr[2] -= pr[2];
@@ -494,12 +507,12 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
                 double *le = Ls + (size_t)e * 9 + 3 * r;
                 double a[3], l[3];
                 row3_load(le, a);
-                row3_mul(a, Ds + (size_t)d.ldq[e] * 9, l);
+                row3_mul(a, Ds + (size_t)d.ldq[e] * 9 + 3 * r, rl.base, l);
                 row3_store(le, l);
                 for (int u = d.upd_ptr[e]; u < d.upd_ptr[e + 1]; ++u) {
                     const int code = d.upd[2 * u], fs = d.upd[2 * u + 1];
                     double pr[3];
-                    row3_mul(l, Us + (size_t)fs * 9, pr);
+                    row3_mul(l, Us + (size_t)fs * 9 + 3 * r, rl.base, pr);
                     const int kind = code & 3, pos = code >> 2;
                     if (kind == 1) {
                         dr[0] -= pr[0]; dr[1] -= pr[1]; dr[2] -= pr[2];
