@@ -300,6 +300,13 @@ int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx
         }
     }
 
+    s.lconsec.assign(s.nl_levels, 1);
+    for (int l = 0; l < s.nl_levels; ++l)
+        for (int q = s.lset[l]; q < s.lset[l + 1]; ++q)
+            if (s.lrows[q] != s.lrows[s.lset[l]] + (q - s.lset[l])) {
+                s.lconsec[l] = 0;
+                break;
+            }
     std::vector<int32_t> lpos(n);
     for (int q = 0; q < n; ++q) lpos[s.lrows[q]] = q;
     make_tiles(n, s.nl_levels, s.lset, tile_rows, s.lptr, s.lcol, lpos, s.ltiles);

@@ -48,6 +48,7 @@ struct Schedule {
     // lower sweep
     int nl_levels = 0, nL = 0;
     std::vector<int32_t> lrows, lset, lptr, lcol, lsrc, ldq, l2u;
+    std::vector<char> lconsec;   // per lower level: its rows are consecutive in the new order
     // upper sweep
     int nu_levels = 0, nU = 0;
     std::vector<int32_t> urows, uset, uptr, ucol, usrc, dsrc;

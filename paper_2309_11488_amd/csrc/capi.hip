@@ -722,7 +722,8 @@ int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *ba
             rs::launch_factor_level(d, A->vals.as<double>(), per, M->pvals.as<double>(), M->L.as<double>(),
                                     M->U.as<double>(), M->Dinv.as<double>(), f32 ? M->Lf.as<float>() : nullptr,
                                     f32 ? M->Uf.as<float>() : nullptr, f32 ? M->Dinvf.as<float>() : nullptr,
-                                    M->bad.as<int32_t>(), S.lset[l], S.lset[l + 1], M->batch, s);
+                                    M->bad.as<int32_t>(), S.lset[l], S.lset[l + 1],
+                                    S.lconsec[l] && S.rest_dst.empty(), M->batch, s);
     }
     HIP_TRY(hipGetLastError());
     M->bad_host.assign(B, 0);

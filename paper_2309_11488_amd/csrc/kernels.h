@@ -145,10 +145,13 @@ void launch_gather_pairs(const double *A, size_t a_stride, double *Ap, size_t ap
 // One level of the block ILU0 factorisation: L-schedule rows [q0, q1).
 // Reads the caller's blocks A, writes the reordered copy Ap of every block
 // it reads (the SpMV operand), the FP64 factors and, when Lf is not null,
-// their FP32 roundings.
+// their FP32 roundings.  staged: the rows are consecutive in the new order
+// and the factor writes every block of their reordered rows (no blocks
+// outside the preconditioner's matrix), so workgroups may collect their
+// part of Ap in LDS and store it contiguously.
 void launch_factor_level(const DevSchedule &d, const double *A, size_t a_stride, double *Ap, double *L, double *U,
-                         double *Dinv, float *Lf, float *Uf, float *Df, int32_t *bad, int q0, int q1, int nsys,
-                         hipStream_t s);
+                         double *Dinv, float *Lf, float *Uf, float *Df, int32_t *bad, int q0, int q1, bool staged,
+                         int nsys, hipStream_t s);
 
 // Lower sweep y = L^{-1} in for L-schedule rows [q0, q1).  When fuse_p is
 // set, the input is p = r + beta (p - omega v) computed on the fly (and

@@ -408,14 +408,21 @@ __device__ inline void row3_mul(const double (&a)[3], const double *__restrict__
 // adjugate; a singular or non-finite pivot is reported by its new index.
 // The row's blocks come straight from the caller's matrix and are also
 // written to the reordered copy used by the SpMV, so no separate gather
-// pass reads A.
-template <bool F32>
+// pass reads A.  With STAGED (the launch's rows are consecutive in the new
+// order, and every block of their reordered rows is written here), a
+// workgroup whose rows hold at most kApCap blocks collects that copy in LDS
+// and writes its contiguous range out with consecutive stores, instead of
+// every lane storing 8-byte pieces spread over 21 rows.
+constexpr int kApCap = 640;
+
+template <bool F32, bool STAGED>
 __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, const double *__restrict__ A,
                                                               size_t a_stride, double *__restrict__ Ap,
                                                               double *__restrict__ L, double *__restrict__ U,
                                                               double *__restrict__ Dinv, float *__restrict__ Lf,
                                                               float *__restrict__ Uf, float *__restrict__ Df,
                                                               int32_t *__restrict__ bad, int q0, int q1) {
+    __shared__ double sap[STAGED ? kApCap * 9 : 1];
     int sys, bx;
     xcd_map(sys, bx);
     const RowLane rl = row_lane<kWavesPerBlock>(bx, q0, q1);
@@ -425,6 +432,23 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
     double *Us = U + (size_t)sys * d.nU * 9;
     double *Ds = Dinv + (size_t)sys * d.n * 9;
     const int r = rl.r;
+    // the workgroup's range of the reordered copy (rows consecutive)
+    int ap0 = 0, apn = kApCap + 1;
+    if (STAGED) {
+        const int qb0 = q0 + bx * kRowsPerBlock, qb1 = min(qb0 + kRowsPerBlock, q1);
+        const int i0 = d.lrows[qb0];
+        ap0 = d.prow[i0];
+        apn = d.prow[i0 + (qb1 - qb0)] - ap0;
+    }
+    const bool stage = STAGED && apn <= kApCap;
+    auto ap_store = [&](int pos, const double (&v)[3]) {
+        if (stage) {
+            double *t = sap + (size_t)(pos - ap0) * 9 + 3 * r;
+            t[0] = v[0]; t[1] = v[1]; t[2] = v[2];
+        } else {
+            row3_store(Aps + (size_t)pos * 9 + 3 * r, v);
+        }
+    };
     double dr[3] = {0.0, 0.0, 0.0};
     int uq = 0;
     if (rl.act) {
@@ -432,7 +456,7 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
         uq = d.l2u[q];
         const int e0 = d.lptr[q], e1 = d.lptr[q + 1], f0 = d.uptr[uq], f1 = d.uptr[uq + 1];
         row3_load(As + (size_t)d.dsrc_a[uq] * 9 + 3 * r, dr);
-        row3_store(Aps + (size_t)d.dsrc[uq] * 9 + 3 * r, dr);
+        ap_store(d.dsrc[uq], dr);
         if (e1 - e0 <= kFactorMax && f1 - f0 <= kFactorMax) {
             double lv[kFactorMax][3], uv[kFactorMax][3];
             int dq[kFactorMax];
@@ -447,10 +471,10 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
                 if (f0 + t < f1) row3_load(As + (size_t)d.usrc_a[f0 + t] * 9 + 3 * r, uv[t]);
 #pragma unroll
             for (int t = 0; t < kFactorMax; ++t)
-                if (e0 + t < e1) row3_store(Aps + (size_t)d.lsrc[e0 + t] * 9 + 3 * r, lv[t]);
+                if (e0 + t < e1) ap_store(d.lsrc[e0 + t], lv[t]);
 #pragma unroll
             for (int t = 0; t < kFactorMax; ++t)
-                if (f0 + t < f1) row3_store(Aps + (size_t)d.usrc[f0 + t] * 9 + 3 * r, uv[t]);
+                if (f0 + t < f1) ap_store(d.usrc[f0 + t], uv[t]);
 #pragma unroll
             for (int t = 0; t < kFactorMax; ++t) {
                 if (e0 + t >= e1) continue;
@@ -494,13 +518,13 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
             for (int f = f0; f < f1; ++f) {
                 double a[3];
                 row3_load(As + (size_t)d.usrc_a[f] * 9 + 3 * r, a);
-                row3_store(Aps + (size_t)d.usrc[f] * 9 + 3 * r, a);
+                ap_store(d.usrc[f], a);
                 row3_store(Us + (size_t)f * 9 + 3 * r, a);
             }
             for (int e = e0; e < e1; ++e) {
                 double a[3];
                 row3_load(As + (size_t)d.lsrc_a[e] * 9 + 3 * r, a);
-                row3_store(Aps + (size_t)d.lsrc[e] * 9 + 3 * r, a);
+                ap_store(d.lsrc[e], a);
                 row3_store(Ls + (size_t)e * 9 + 3 * r, a);
             }
             for (int e = e0; e < e1; ++e) {
@@ -535,6 +559,12 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
                 }
             }
         }
+    }
+    if (stage) {
+        // the workgroup's part of the reordered copy, consecutive stores
+        __syncthreads();
+        double *dst = Aps + (size_t)ap0 * 9;
+        for (int k = threadIdx.x; k < apn * 9; k += kRowThreads) dst[k] = sap[k];
     }
     // gather the three rows of U_ii from the row's lanes
     double a[9];
@@ -1439,14 +1469,21 @@ void launch_gather_pairs(const double *A, size_t a_stride, double *Ap, size_t ap
 }
 
 void launch_factor_level(const DevSchedule &d, const double *A, size_t a_stride, double *Ap, double *L, double *U,
-                         double *Dinv, float *Lf, float *Uf, float *Df, int32_t *bad, int q0, int q1, int nsys,
-                         hipStream_t s) {
+                         double *Dinv, float *Lf, float *Uf, float *Df, int32_t *bad, int q0, int q1, bool staged,
+                         int nsys, hipStream_t s) {
     if (q1 <= q0 || nsys <= 0) return;
     const dim3 g(row_blocks(q1 - q0), nsys);
-    if (Lf)
-        k_factor_level<true><<<g, kRowThreads, 0, s>>>(d, A, a_stride, Ap, L, U, Dinv, Lf, Uf, Df, bad, q0, q1);
-    else
-        k_factor_level<false><<<g, kRowThreads, 0, s>>>(d, A, a_stride, Ap, L, U, Dinv, Lf, Uf, Df, bad, q0, q1);
+    auto go = [&](auto F32, auto STG) {
+        k_factor_level<decltype(F32)::value, decltype(STG)::value><<<g, kRowThreads, 0, s>>>(
+            d, A, a_stride, Ap, L, U, Dinv, Lf, Uf, Df, bad, q0, q1);
+    };
+    using T = std::true_type;
+    using F = std::false_type;
+    if (Lf) {
+        if (staged) go(T{}, T{}); else go(T{}, F{});
+    } else {
+        if (staged) go(F{}, T{}); else go(F{}, F{});
+    }
 }
 
 template <typename T>
