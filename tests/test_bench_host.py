@@ -1,0 +1,40 @@
+"""bench.py's host-side contract: one GPU only, and its byte models."""
+
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=ROOT, timeout=120)
+    assert p.returncode == 2
+    line = json.loads(p.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
+
+
+def test_traffic_is_reported_only_for_the_measured_kernels(monkeypatch):
+    """bench.py reports the committed HBM traffic of a kernel class only
+    while the kernel sources carry the digest the counters were taken with."""
+    sys.path.insert(0, ROOT)
+    import bench
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+        rec = json.load(fh)
+    assert {"c2:lsweep", "c3:spmv", "c4:factor"} <= set(rec)
+    key = "c2:lsweep"
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: rec[key]["kernel_digest"])
+    assert bench.measured_traffic("c2", "lsweep") == rec[key]["bytes_per_unit"] > 0
+    monkeypatch.setattr(bench, "kernel_source_digest", lambda: "0" * 16)
+    assert bench.measured_traffic("c2", "lsweep") is None
+
+
+@pytest.mark.parametrize("workload", ["c1", "c2", "c3", "c4", "c5"])
+def test_workload_descriptions(workload):
+    sys.path.insert(0, ROOT)
+    import bench
+    assert workload in bench.WORKLOADS and bench.WORKLOADS[workload]["desc"]
