@@ -1350,15 +1350,37 @@ int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart,
         }
         return RS_OK;
     };
-    bool any_run = true, all_done = false;
-    st = poll(any_run, all_done);
-    if (st != RS_OK) return st;
+    // x back to the caller's order, the true residual, and the results to the host
+    auto finish = [&]() -> int {
+        rs::launch_finish(M->an->dev, A->rowptr.as<int32_t>(), A->colidx.as<int32_t>(), A->vals.as<double>(),
+                          (size_t)A->nnzb * 9, bd, xd, k, B, M->spmv_variant, M->split(), A->wells(), s);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(M->h_ctr, k.lctr, 2 * sizeof(rs::SweepCtr), hipMemcpyDeviceToHost, s));
+        if (mem != RS_MEM_DEVICE) HIP_TRY(hipMemcpyAsync(x, xd, m * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return RS_OK;
+    };
+    auto done_all = [&]() {
+        bool all = true;
+        for (int i = 0; i < B; ++i) all &= M->h_state[i].phase == rs::PH_DONE;
+        return all;
+    };
+    bool any_run = true, all_done = false, finished = false;
+    if (!M->predict) {
+        st = poll(any_run, all_done);
+        if (st != RS_OK) return st;
+    }
     // Every cycle advances each system not yet done by at least one step,
-    // so max_iter + 1 cycles always suffice.
+    // so max_iter + 1 cycles always suffice.  With prediction the first
+    // poll comes after as many steps as the previous solve needed; a cycle
+    // that a poll ends (no system iterating) queues the finishing work with
+    // its end, so a solve that stops there costs two host synchronisations.
     long long queued = 0;
     long long next_poll = M->predict ? std::max(M->chunk, M->last_gm_steps) : M->chunk;
     for (int cycle = 0; !all_done && cycle <= max_iter; ++cycle) {
         int cols = 0;
+        bool stopped = false;
         for (int j = 0; j < restart; ++j) {
             gm_step_any(M, g, j, s);
             ++queued;
@@ -1368,23 +1390,32 @@ int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart,
                 st = poll(any_run, all_done);
                 if (st != RS_OK) return st;
                 next_poll = queued + M->chunk;
-                if (!any_run) break;
+                if (!any_run) {
+                    stopped = true;
+                    break;
+                }
             }
             ProfScope ps(PC_VEC, s, (double)B * 48 * M->n, true);
             rs::launch_gm_normalise(g, k.t, j + 1, 1, M->n, B, s, ps.start(), ps.stop());
         }
         gm_cycle_end_any(M, g, cols, s);
         HIP_TRY(hipGetLastError());
+        if (stopped) {
+            st = finish();
+            if (st != RS_OK) return st;
+            if (done_all()) {
+                finished = true;
+                break;
+            }
+            continue;
+        }
         st = poll(any_run, all_done);
         if (st != RS_OK) return st;
     }
-    rs::launch_finish(M->an->dev, A->rowptr.as<int32_t>(), A->colidx.as<int32_t>(), A->vals.as<double>(),
-                      (size_t)A->nnzb * 9, bd, xd, k, B, M->spmv_variant, M->split(), A->wells(), s);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(M->h_ctr, k.lctr, 2 * sizeof(rs::SweepCtr), hipMemcpyDeviceToHost, s));
-    if (mem != RS_MEM_DEVICE) HIP_TRY(hipMemcpyAsync(x, xd, m * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    if (!finished) {
+        st = finish();
+        if (st != RS_OK) return st;
+    }
     if (M->h_ctr[0].error || M->h_ctr[1].error) {
         HIP_TRY(hipMemsetAsync(M->ctrs.p, 0, 2 * sizeof(rs::SweepCtr), s));
         HIP_TRY(hipStreamSynchronize(s));
