@@ -276,12 +276,15 @@ int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx
     }
 
     // update lists: for L block (i,k), every j > k in row k that row i also
-    // holds, ascending j, in the order Algorithm 2 applies them
+    // holds, ascending j, in the order Algorithm 2 applies them.  U_kj is
+    // named by its U position, or, when row k has no lower blocks (so
+    // nothing updates it and U_kj is A'_kj), by ~(its A' position).
     s.upd_ptr.assign(s.nL + 1, 0);
     for (int q = 0; q < n; ++q) {
         const int i = s.lrows[q];
         for (int e = s.lptr[q]; e < s.lptr[q + 1]; ++e) {
             const int k = s.lcol[e];
+            const bool k_no_lower = mcol[mrow[k]] == k;
             const int32_t *ib = mcol + mrow[i], *ie = mcol + mrow[i + 1];
             for (int p = mrow[k]; p < mrow[k + 1]; ++p) {
                 const int j = mcol[p];
@@ -294,7 +297,7 @@ int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx
                 else if (j == i) code = 1;
                 else code = 4 * a2u[t] + 2;
                 s.upd.push_back(code);
-                s.upd.push_back(a2u[p]);
+                s.upd.push_back(k_no_lower ? ~s.usrc[a2u[p]] : a2u[p]);
             }
             s.upd_ptr[e + 1] = (int32_t)(s.upd.size() / 2);
         }

@@ -53,8 +53,10 @@ struct Schedule {
     int nu_levels = 0, nU = 0;
     std::vector<int32_t> urows, uset, uptr, ucol, usrc, dsrc;
     // factor: for each L block e, updates upd[upd_ptr[e] .. upd_ptr[e+1])
-    // as pairs (target code, U block position of U_kj); target code =
-    // 4 * position + kind, kind 0 = L block, 1 = diagonal of the row, 2 = U block.
+    // as pairs (target code, source of U_kj); target code = 4 * position +
+    // kind, kind 0 = L block, 1 = diagonal of the row, 2 = U block; source =
+    // U block position, or ~(A' position) when row k has no lower blocks
+    // (then U_kj equals A'_kj, which the reordered copy holds).
     std::vector<int32_t> upd_ptr, upd;
     int max_lrow = 0, max_urow = 0;
     // row tiles of the single-launch sweeps: tile t covers schedule

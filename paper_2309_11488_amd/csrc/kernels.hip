@@ -485,7 +485,7 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
                 for (int u = d.upd_ptr[e0 + t]; u < u1; ++u) {
                     const int code = d.upd[2 * u], fs = d.upd[2 * u + 1];
                     double pr[3];
-                    row3_mul(l, Us + (size_t)fs * 9 + 3 * r, rl.base, pr);
+                    row3_mul(l, (fs >= 0 ? Us + (size_t)fs * 9 : Aps + (size_t)~fs * 9) + 3 * r, rl.base, pr);
                     const int kind = code & 3, pos = code >> 2;
                     if (kind == 1) {
                         dr[0] -= pr[0]; dr[1] -= pr[1]; dr[2] -= pr[2];
@@ -507,10 +507,14 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
                     if (F32) row3_store(Lf + ((size_t)sys * d.nL + e0 + t) * 9 + 3 * r, lv[t]);
                     else row3_store(Ls + (size_t)(e0 + t) * 9 + 3 * r, lv[t]);
                 }
+            // with FP32 factors the FP64 U is only read by later levels'
+            // updates, which take a row without lower blocks from the
+            // reordered copy instead
+            const bool keep_u = !F32 || e1 > e0;
 #pragma unroll
             for (int t = 0; t < kFactorMax; ++t)
                 if (f0 + t < f1) {
-                    row3_store(Us + (size_t)(f0 + t) * 9 + 3 * r, uv[t]);
+                    if (keep_u) row3_store(Us + (size_t)(f0 + t) * 9 + 3 * r, uv[t]);
                     if (F32) row3_store(Uf + ((size_t)sys * d.nU + f0 + t) * 9 + 3 * r, uv[t]);
                 }
         } else {
@@ -536,7 +540,7 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
                 for (int u = d.upd_ptr[e]; u < d.upd_ptr[e + 1]; ++u) {
                     const int code = d.upd[2 * u], fs = d.upd[2 * u + 1];
                     double pr[3];
-                    row3_mul(l, Us + (size_t)fs * 9 + 3 * r, rl.base, pr);
+                    row3_mul(l, (fs >= 0 ? Us + (size_t)fs * 9 : Aps + (size_t)~fs * 9) + 3 * r, rl.base, pr);
                     const int kind = code & 3, pos = code >> 2;
                     if (kind == 1) {
                         dr[0] -= pr[0]; dr[1] -= pr[1]; dr[2] -= pr[2];
