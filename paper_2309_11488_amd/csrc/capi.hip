@@ -261,10 +261,20 @@ struct rs_ilu0 {
     // is being timed with events and so launched directly)
     bool use_graph = true;
     hipStream_t cap_stream = nullptr;
+    // every setting a captured iteration depends on
+    struct GraphKey {
+        int precision = -1, tile_sweeps = 0, spmv_variant = 0, sweep_variant = 0, split = 0, sweep_grid = 0;
+        long long wells = 0;   // 0: no wells, else the wells' version + 1
+        bool operator==(const GraphKey &o) const {
+            return precision == o.precision && tile_sweeps == o.tile_sweeps && spmv_variant == o.spmv_variant &&
+                   sweep_variant == o.sweep_variant && split == o.split && sweep_grid == o.sweep_grid &&
+                   wells == o.wells;
+        }
+    };
     struct Segment {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
-        long long key = -1;
+        GraphKey key;
     };
     std::map<int, Segment> segments;   // by iteration parts
     void drop_graph() {
@@ -998,12 +1008,16 @@ static void enqueue_iteration_any(ilu0_t M, hipStream_t s, int parts) {
 // the first time this configuration is seen).  Nothing is timed inside a
 // graph: profiling is off while segments are captured.
 static int replay_segment(ilu0_t M, int parts, hipStream_t s) {
-    const long long key = (long long)M->precision | (long long)M->tile_sweeps << 2 | (long long)M->spmv_variant << 3 |
-                          (long long)M->sweep_variant << 6 | (long long)M->split() << 8 |
-                          (long long)M->sweep_grid << 10 |
-                          (M->wdev.nw > 0 ? ((long long)(M->wells_version & 0xffffff) + 1) << 36 : 0);
+    rs_ilu0::GraphKey key;
+    key.precision = M->precision;
+    key.tile_sweeps = M->tile_sweeps;
+    key.spmv_variant = M->spmv_variant;
+    key.sweep_variant = M->sweep_variant;
+    key.split = M->split();
+    key.sweep_grid = M->sweep_grid;
+    key.wells = M->wdev.nw > 0 ? (long long)M->wells_version + 1 : 0;
     rs_ilu0::Segment &seg = M->segments[parts];
-    if (!seg.exec || seg.key != key) {
+    if (!seg.exec || !(seg.key == key)) {
         if (seg.exec) (void)hipGraphExecDestroy(seg.exec);
         if (seg.graph) (void)hipGraphDestroy(seg.graph);
         seg.exec = nullptr;

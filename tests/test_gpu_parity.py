@@ -563,6 +563,24 @@ def test_reduce_split_modes_match_the_oracle(solver_of, variant):
         assert abs(i1[0]["true_rel_residual"] - oinfo["true_rel_residual"]) <= 1e-12 + 1e-3 * oinfo["true_rel_residual"]
 
 
+def test_graph_recaptured_for_every_setting(solver_of):
+    """A captured iteration is replayed only under the settings it was
+    captured with: after each change of sweep shape and dot-product split
+    (pairs whose settings once shared a cache key among them) the replayed
+    solve equals the eager solve under the same settings."""
+    s = CASES["nnc"]
+    A, M, _, _ = solver_of(s, rs.ORDER_GRAPH_COLOUR)
+    rs.ilu0_set_option(M, rs.OPT_SPMV_VARIANT, 0)
+    for sweep, split in ((4, 0), (0, 1), (4, 0), (2, 2), (0, 0)):
+        rs.ilu0_set_option(M, rs.OPT_SWEEP_VARIANT, sweep)
+        rs.ilu0_set_option(M, rs.OPT_REDUCE_SPLIT, split)
+        rs.ilu0_set_option(M, rs.OPT_USE_GRAPH, 0)
+        xe, ste, ie = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-10)
+        rs.ilu0_set_option(M, rs.OPT_USE_GRAPH, 1)
+        xg, stg, ig = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-10)
+        assert ste == stg == rs.OK and np.array_equal(xe, xg) and ie == ig, (sweep, split)
+
+
 def test_device_memory_path():
     torch = pytest.importorskip("torch")
     s = CASES["nnc"]
