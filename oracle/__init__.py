@@ -61,7 +61,7 @@ def lib():
         ci, cd, vp = ct.c_int, ct.c_double, ct.c_void_p
         L.orc_validate.argtypes = [ci, _I32P, _I32P, ct.POINTER(ci)]
         L.orc_level_sets.argtypes = [ci, _I32P, _I32P, _I32P, _I32P]
-        L.orc_greedy_colour.argtypes = [ci, _I32P, _I32P, _I32P, _I32P]
+        L.orc_dsatur_colour.argtypes = [ci, _I32P, _I32P, _I32P, _I32P]
         L.orc_permute.argtypes = [ci, _I32P, _I32P, _F64P, _I32P, _I32P, _I32P, _F64P]
         L.orc_permute.restype = None
         L.orc_ilu0.argtypes = [ci, _I32P, _I32P, _F64P, _F64P, ct.POINTER(ci)]
@@ -118,12 +118,13 @@ def level_sets(rowptr, colidx):
     return nl, level, perm
 
 
-def greedy_colour(rowptr, colidx):
-    """(n_colours, colour[n], perm[n]) of greedy first-fit colouring."""
+def dsatur_colour(rowptr, colidx):
+    """(n_colours, colour[n], perm[n]) of the DSatur colouring (Brelaz 1979;
+    ties by degree, then by the smaller index)."""
     n = len(rowptr) - 1
     col = np.zeros(n, np.int32)
     perm = np.zeros(n, np.int32)
-    nc = lib().orc_greedy_colour(n, _i32(rowptr), _i32(colidx), col, perm)
+    nc = lib().orc_dsatur_colour(n, _i32(rowptr), _i32(colidx), col, perm)
     return nc, col, perm
 
 
@@ -132,7 +133,7 @@ def ordering_perm(rowptr, colidx, ordering):
     if ordering == ORDER_LEVEL:
         return level_sets(rowptr, colidx)[2]
     if ordering == ORDER_COLOUR:
-        return greedy_colour(rowptr, colidx)[2]
+        return dsatur_colour(rowptr, colidx)[2]
     return np.arange(n, dtype=np.int32)
 
 

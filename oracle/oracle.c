@@ -25,8 +25,10 @@
  *     substitutions are reconstructed from the equations.
  *   - Level scheduling and graph colouring: Section "ILU0" of the
  *     implementation chapter.  LS levels respect direct and indirect lower
- *     dependencies; GC is greedy first-fit in natural order on the
- *     symmetrised graph (the paper does not name its colouring algorithm).
+ *     dependencies; GC is DSatur (Brelaz, "New methods to color the
+ *     vertices of a graph", CACM 1979) on the symmetrised graph, ties broken
+ *     by degree, then by the smaller index (the paper does not name its
+ *     colouring algorithm; fewer colours mean fewer launches).
  *     Rows are then sorted stably by (level or colour, original index) and a
  *     reordered copy of the matrix and of b is made.
  *   - BiCGStab: named in Section "Bicgstab solver" (spmv, axpy, norm, dot)
@@ -156,41 +158,120 @@ int orc_level_sets(int n, const int *rowptr, const int *colidx, int *level, int 
     return nlev;
 }
 
-/* Greedy first-fit colouring in natural order on the symmetrised graph
- * (i ~ j when (i,j) or (j,i) is in S, i != j).  Rows sorted stably by colour.
- * Returns the number of colours. */
-int orc_greedy_colour(int n, const int *rowptr, const int *colidx, int *colour, int *perm)
+/* DSatur colouring (Brelaz 1979) on the symmetrised graph (i ~ j when (i,j)
+ * or (j,i) is in S, i != j).  n times: among the uncoloured rows take the one
+ * whose neighbours hold the most distinct colours (its saturation), ties to
+ * the one with more neighbours, then to the smaller index, and give it the
+ * smallest colour none of its neighbours holds.  Rows are then sorted stably
+ * by colour.  Returns the number of colours.
+ *
+ * The candidates sit in a binary heap ordered by (saturation, neighbours,
+ * -index); a row whose saturation grows is pushed again and its older
+ * entries are skipped when they surface. */
+typedef struct { int sat, deg, row; } orc_dsat;
+
+static int dsat_first(orc_dsat a, orc_dsat b)
+{
+    if (a.sat != b.sat) return a.sat > b.sat;
+    if (a.deg != b.deg) return a.deg > b.deg;
+    return a.row < b.row;
+}
+
+static void dsat_push(orc_dsat *h, int *len, orc_dsat k)
+{
+    int i = (*len)++;
+    h[i] = k;
+    while (i > 0) {
+        int up = (i - 1) / 2;
+        if (!dsat_first(h[i], h[up])) break;
+        orc_dsat t = h[i]; h[i] = h[up]; h[up] = t;
+        i = up;
+    }
+}
+
+static orc_dsat dsat_pop(orc_dsat *h, int *len)
+{
+    orc_dsat top = h[0];
+    h[0] = h[--(*len)];
+    int i = 0;
+    for (;;) {
+        int a = 2 * i + 1, b = a + 1, m = i;
+        if (a < *len && dsat_first(h[a], h[m])) m = a;
+        if (b < *len && dsat_first(h[b], h[m])) m = b;
+        if (m == i) break;
+        orc_dsat t = h[i]; h[i] = h[m]; h[m] = t;
+        i = m;
+    }
+    return top;
+}
+
+int orc_dsatur_colour(int n, const int *rowptr, const int *colidx, int *colour, int *perm)
 {
     int nnz = rowptr[n];
+    size_t nn = (size_t)(n > 0 ? n : 1), ne = (size_t)(nnz > 0 ? 2 * (size_t)nnz : 1);
     /* transpose pattern, to see (j,i) entries from row i */
-    int *tptr = calloc((size_t)n + 1, sizeof(int));
+    int *tptr = calloc(nn + 1, sizeof(int));
     int *tcol = malloc(sizeof(int) * (size_t)(nnz > 0 ? nnz : 1));
-    int *fill = malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
-    int *mark = malloc(sizeof(int) * (size_t)(n + 2));
+    int *fill = malloc(sizeof(int) * nn);
     for (int p = 0; p < nnz; ++p) tptr[colidx[p] + 1]++;
     for (int i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
     memcpy(fill, tptr, sizeof(int) * (size_t)n);
     for (int i = 0; i < n; ++i)
         for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) tcol[fill[colidx[p]]++] = i;
-    for (int c = 0; c < n + 2; ++c) mark[c] = -1;
-    int ncol = 0;
-    for (int i = 0; i < n; ++i) colour[i] = -1;
+    /* neighbour lists: row i's pattern and its transpose, self and repeats dropped */
+    int *aptr = malloc(sizeof(int) * (nn + 1)), *adj = malloc(sizeof(int) * ne);
+    int *stamp = malloc(sizeof(int) * (nn + 1));
+    for (int i = 0; i <= n; ++i) stamp[i] = -1;
+    aptr[0] = 0;
     for (int i = 0; i < n; ++i) {
-        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-            int j = colidx[p];
-            if (j != i && colour[j] >= 0) mark[colour[j]] = i;
-        }
-        for (int p = tptr[i]; p < tptr[i + 1]; ++p) {
-            int j = tcol[p];
-            if (j != i && colour[j] >= 0) mark[colour[j]] = i;
-        }
+        int len = aptr[i];
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p)
+            if (colidx[p] != i && stamp[colidx[p]] != i) { stamp[colidx[p]] = i; adj[len++] = colidx[p]; }
+        for (int p = tptr[i]; p < tptr[i + 1]; ++p)
+            if (tcol[p] != i && stamp[tcol[p]] != i) { stamp[tcol[p]] = i; adj[len++] = tcol[p]; }
+        aptr[i + 1] = len;
+    }
+    int *sat = calloc(nn, sizeof(int));
+    orc_dsat *heap = malloc(sizeof(orc_dsat) * (nn + (size_t)aptr[n] + 1));
+    int hlen = 0, ncol = 0, tick = 0;
+    for (int c = 0; c <= n; ++c) stamp[c] = -1;
+    for (int i = 0; i < n; ++i) {
+        colour[i] = -1;
+        orc_dsat k = {0, aptr[i + 1] - aptr[i], i};
+        dsat_push(heap, &hlen, k);
+    }
+    for (int done = 0; done < n;) {
+        orc_dsat k = dsat_pop(heap, &hlen);
+        int v = k.row;
+        if (colour[v] >= 0 || k.sat != sat[v]) continue;   /* stale entry */
+        /* smallest colour absent from v's neighbours */
+        ++tick;
+        for (int p = aptr[v]; p < aptr[v + 1]; ++p)
+            if (colour[adj[p]] >= 0) stamp[colour[adj[p]]] = tick;
         int c = 0;
-        while (mark[c] == i) ++c;
-        colour[i] = c;
+        while (stamp[c] == tick) ++c;
+        colour[v] = c;
         if (c + 1 > ncol) ncol = c + 1;
+        ++done;
+        /* saturation of each uncoloured neighbour, counted afresh */
+        for (int p = aptr[v]; p < aptr[v + 1]; ++p) {
+            int j = adj[p];
+            if (colour[j] >= 0) continue;
+            ++tick;
+            int s = 0;
+            for (int q = aptr[j]; q < aptr[j + 1]; ++q) {
+                int cj = colour[adj[q]];
+                if (cj >= 0 && stamp[cj] != tick) { stamp[cj] = tick; ++s; }
+            }
+            if (s != sat[j]) {
+                sat[j] = s;
+                orc_dsat e = {s, aptr[j + 1] - aptr[j], j};
+                dsat_push(heap, &hlen, e);
+            }
+        }
     }
     sort_by_key(n, colour, ncol, perm);
-    free(tptr); free(tcol); free(fill); free(mark);
+    free(tptr); free(tcol); free(fill); free(aptr); free(adj); free(stamp); free(sat); free(heap);
     return ncol;
 }
 
@@ -699,7 +780,7 @@ int orc_solve_wells(int n, const int *rowptr, const int *colidx, const double *v
     }
     int sets = n;
     if (ordering == ORC_ORDER_LEVEL) sets = orc_level_sets(n, jrow, jcol, key, perm);
-    else if (ordering == ORC_ORDER_COLOUR) sets = orc_greedy_colour(n, jrow, jcol, key, perm);
+    else if (ordering == ORC_ORDER_COLOUR) sets = orc_dsatur_colour(n, jrow, jcol, key, perm);
     else for (int i = 0; i < n; ++i) perm[i] = i;
     if (n_sets) *n_sets = sets;
     if (perm_out) memcpy(perm_out, perm, sizeof(int) * (size_t)n);

@@ -1,5 +1,5 @@
 // Host analysis of a BCSR pattern: validation, orderings (natural, level
-// scheduling, greedy graph colouring), the reordered pattern, lower/upper
+// scheduling, DSatur graph colouring), the reordered pattern, lower/upper
 // sweep schedules and the ILU0 update lists.
 //
 // Orderings follow Section "ILU0" of the paper's implementation chapter:
@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <queue>
+#include <tuple>
 #include <utility>
 
 #include "../../include/rsolve.h"
@@ -73,29 +74,62 @@ static int depth_upper(int n, const int32_t *rowptr, const int32_t *colidx, std:
     return depth;
 }
 
-// Greedy first-fit colouring in natural order; two rows conflict when either
-// holds the other in its pattern.
-static int greedy_colour(int n, const int32_t *rowptr, const int32_t *colidx, std::vector<int32_t> &colour) {
+// DSatur colouring (Brelaz 1979); two rows conflict when either holds the
+// other in its pattern.  The next row coloured is the uncoloured one with the
+// most distinct colours among its neighbours, then the most neighbours, then
+// the lowest index; it takes the lowest colour its neighbours leave free.
+// Saturation only grows: when row v takes colour c, a neighbour's saturation
+// grows by one unless another of its coloured neighbours already holds c, and
+// its queue entry is renewed (entries whose saturation is stale are skipped).
+static int dsatur_colour(int n, const int32_t *rowptr, const int32_t *colidx, std::vector<int32_t> &colour) {
     const int nnz = rowptr[n];
-    std::vector<int32_t> tptr(n + 1, 0), tcol(std::max(nnz, 1));
-    for (int p = 0; p < nnz; ++p) tptr[colidx[p] + 1]++;
-    for (int i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
+    // symmetrised neighbour lists without the row itself, sorted, unique
+    std::vector<int32_t> cnt(n + 1, 0);
+    for (int i = 0; i < n; ++i)
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p)
+            if (colidx[p] != i) { ++cnt[i + 1]; ++cnt[colidx[p] + 1]; }
+    for (int i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> nb(std::max(2 * nnz, 1)), at(cnt.begin(), cnt.end() - 1);
+    for (int i = 0; i < n; ++i)
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p)
+            if (colidx[p] != i) { nb[at[i]++] = colidx[p]; nb[at[colidx[p]]++] = i; }
+    std::vector<int32_t> nptr(n + 1, 0);
     {
-        std::vector<int32_t> pos(tptr.begin(), tptr.end() - 1);
-        for (int i = 0; i < n; ++i)
-            for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) tcol[pos[colidx[p]]++] = i;
+        int w = 0;
+        for (int i = 0; i < n; ++i) {
+            int32_t *b = nb.data() + cnt[i], *e = nb.data() + cnt[i + 1];
+            std::sort(b, e);
+            e = std::unique(b, e);
+            nptr[i] = w;
+            for (int32_t *q = b; q < e; ++q) nb[w++] = *q;
+        }
+        nptr[n] = w;
     }
+    std::vector<int32_t> sat(n, 0), seen(n + 1, -1);
     colour.assign(n, -1);
-    std::vector<int32_t> seen(n + 2, -1);
+    // (saturation, neighbours, -row): the largest comes out first
+    using Entry = std::tuple<int32_t, int32_t, int32_t>;
+    std::priority_queue<Entry> q;
+    for (int i = 0; i < n; ++i) q.emplace(0, nptr[i + 1] - nptr[i], -i);
     int ncol = 0;
-    for (int i = 0; i < n; ++i) {
-        auto mark = [&](int j) { if (j != i && colour[j] >= 0) seen[colour[j]] = i; };
-        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) mark(colidx[p]);
-        for (int p = tptr[i]; p < tptr[i + 1]; ++p) mark(tcol[p]);
+    while (!q.empty()) {
+        const auto [s, d, mv] = q.top();
+        q.pop();
+        const int v = -mv;
+        if (colour[v] >= 0 || s != sat[v]) continue;
+        for (int p = nptr[v]; p < nptr[v + 1]; ++p)
+            if (colour[nb[p]] >= 0) seen[colour[nb[p]]] = v;
         int c = 0;
-        while (seen[c] == i) ++c;
-        colour[i] = c;
+        while (seen[c] == v) ++c;
+        colour[v] = c;
         ncol = std::max(ncol, c + 1);
+        for (int p = nptr[v]; p < nptr[v + 1]; ++p) {
+            const int j = nb[p];
+            if (colour[j] >= 0) continue;
+            bool held = false;
+            for (int r = nptr[j]; r < nptr[j + 1] && !held; ++r) held = nb[r] != v && colour[nb[r]] == c;
+            if (!held) q.emplace(++sat[j], nptr[j + 1] - nptr[j], -j);
+        }
     }
     return ncol;
 }
@@ -107,7 +141,7 @@ int make_ordering(int n, const int32_t *rowptr, const int32_t *colidx, int order
     if (ordering == RS_ORDER_LEVEL_SET) {
         nsets = depth_lower(n, rowptr, colidx, key);
     } else if (ordering == RS_ORDER_GRAPH_COLOUR) {
-        nsets = greedy_colour(n, rowptr, colidx, key);
+        nsets = dsatur_colour(n, rowptr, colidx, key);
     } else {
         perm.resize(n);
         set_ptr.resize(n + 1);

@@ -38,12 +38,18 @@ def test_status_strings():
 
 
 @pytest.mark.parametrize("ordering", [rs.ORDER_NATURAL, rs.ORDER_LEVEL_SET, rs.ORDER_GRAPH_COLOUR])
-@pytest.mark.parametrize("case", ["c1", "mask_nnc", "c2"])
+@pytest.mark.parametrize("case", ["c1", "mask_nnc", "c2", "random"])
 def test_host_ordering_matches_oracle(ordering, case):
     if case == "c1":
         s = config_system("c1")
     elif case == "c2":
         s = config_system("c2", n_rhs=1)
+    elif case == "random":
+        # irregular degrees and many ties of saturation and degree
+        rng = np.random.default_rng(8)
+        pairs = {(int(a), int(b)) for a, b in rng.integers(0, 300, (900, 2)) if a != b}
+        rp, ci = pattern_from_pairs(300, sorted(pairs))
+        s = type("P", (), {"rowptr": rp, "colidx": ci, "n": 300})
     else:
         s = make_grid_system(15, 11, 7, active_frac=0.8, nnc_frac=0.04, seed=3)
     st, perm, ns, bad = rs.ilu0_analyse_host(s.rowptr, s.colidx, ordering)
@@ -52,7 +58,7 @@ def test_host_ordering_matches_oracle(ordering, case):
         nl, _, operm = oracle.level_sets(s.rowptr, s.colidx)
         assert ns == nl
     elif ordering == rs.ORDER_GRAPH_COLOUR:
-        nc, _, operm = oracle.greedy_colour(s.rowptr, s.colidx)
+        nc, _, operm = oracle.dsatur_colour(s.rowptr, s.colidx)
         assert ns == nc
     else:
         operm = np.arange(s.n, dtype=np.int32)

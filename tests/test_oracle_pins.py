@@ -96,26 +96,67 @@ def test_level_sets_respect_dependencies():
 
 
 @pytest.mark.parametrize("shape", [(20, 20, 10), (5, 6, 7)])
-def test_greedy_colour_full_grid_is_red_black(shape):
+def test_dsatur_full_grid_is_red_black(shape):
+    """DSatur colours a bipartite graph with two colours (Brelaz 1979); the
+    first row coloured is the lowest-index row of highest degree, interior
+    cell (1, 1, 1), so colour 0 is the odd parity class."""
     s = make_grid_system(*shape, seed=2)
-    nc, col, perm = oracle.greedy_colour(s.rowptr, s.colidx)
+    nc, col, perm = oracle.dsatur_colour(s.rowptr, s.colidx)
     assert nc == 2
     nx, ny, _ = shape
     c = np.arange(s.n)
-    assert np.array_equal(col, (c % nx + (c // nx) % ny + c // (nx * ny)) % 2)
+    assert np.array_equal(col, 1 - (c % nx + (c // nx) % ny + c // (nx * ny)) % 2)
+    assert np.array_equal(perm, np.argsort(col, kind="stable"))
 
 
-def test_greedy_colour_is_proper_on_nnc_pattern():
+def _ring(m, first=0):
+    return [(first + k, first + (k + 1) % m) for k in range(m)]
+
+
+@pytest.mark.parametrize("m", [4, 5, 6, 7, 12, 13])
+def test_dsatur_cycles_and_wheels(m):
+    """Closed forms DSatur reaches exactly: a cycle needs 2 colours when even
+    and 3 when odd; a wheel (hub joined to every row of a cycle) one more."""
+    rp, ci = pattern_from_pairs(m, _ring(m))
+    assert oracle.dsatur_colour(rp, ci)[0] == (2 if m % 2 == 0 else 3)
+    rp, ci = pattern_from_pairs(m + 1, _ring(m, 1) + [(0, k) for k in range(1, m + 1)])
+    nc, col, _ = oracle.dsatur_colour(rp, ci)
+    assert nc == (3 if m % 2 == 0 else 4) and col[0] == 0   # the hub has the highest degree
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 9])
+def test_dsatur_complete_graph(m):
+    """K_m needs m colours; with every degree equal, rows go in index order."""
+    rp, ci = dense_pattern(m)
+    nc, col, perm = oracle.dsatur_colour(rp, ci)
+    assert nc == m and np.array_equal(col, np.arange(m)) and np.array_equal(perm, np.arange(m))
+
+
+@pytest.mark.parametrize("k", [3, 6, 10])
+def test_dsatur_crown_graph_two_colours(k):
+    """Crown graph (u_i ~ w_j for i != j), rows interleaved u0, w0, u1, w1 ...:
+    first-fit in natural order needs k colours on it, DSatur two."""
+    pairs = [(2 * i, 2 * j + 1) for i in range(k) for j in range(k) if i != j]
+    rp, ci = pattern_from_pairs(2 * k, pairs)
+    nc, col, _ = oracle.dsatur_colour(rp, ci)
+    assert nc == 2
+    assert np.all(col[0::2] == col[0]) and np.all(col[1::2] == 1 - col[0])
+
+
+def test_dsatur_is_proper_on_nnc_pattern():
     s = make_grid_system(14, 12, 8, active_frac=0.85, nnc_frac=0.02, seed=5)
-    nc, col, perm = oracle.greedy_colour(s.rowptr, s.colidx)
+    nc, col, perm = oracle.dsatur_colour(s.rowptr, s.colidx)
+    maxdeg = 0
     for i in range(s.n):
-        for j in s.colidx[s.rowptr[i]:s.rowptr[i + 1]]:
-            if j != i:
-                assert col[i] != col[j]
-    # first fit: every row with colour c > 0 touches colours 0..c-1
-    for i in range(s.n):
-        nb = {col[j] for j in s.colidx[s.rowptr[i]:s.rowptr[i + 1]] if j != i}
-        assert set(range(col[i])) <= nb
+        nbr = [j for j in s.colidx[s.rowptr[i]:s.rowptr[i + 1]] if j != i]
+        maxdeg = max(maxdeg, len(nbr))
+        for j in nbr:
+            assert col[i] != col[j]
+        # each row took the lowest colour free when it was coloured, and its
+        # neighbours keep their colours: it touches every colour below its own
+        assert set(range(col[i])) <= {col[j] for j in nbr}
+    assert nc <= maxdeg + 1
+    assert np.array_equal(perm, np.argsort(col, kind="stable"))
 
 
 def test_permute_is_similarity():
