@@ -214,6 +214,11 @@ def main():
     period = max(rhs, 4) + 1
     sample = {"mask": 0, "count": 0}
 
+    def solve(j):
+        if gmres:
+            return rs.gmres_solve(M, A, b[j], x[j], args.restart, reduction, 200)
+        return rs.bicgstab_solve(M, A, b[j], x[j], reduction, 200)
+
     def step(record=False):
         if sample["mask"]:
             rs.rsolve_profile_set_mask(sample["mask"])      # every factorisation
@@ -223,10 +228,7 @@ def main():
             if sample["mask"]:
                 rs.rsolve_profile_set_mask(sample["mask"] if sample["count"] % period == 0 else 0)
                 sample["count"] += 1
-            if gmres:
-                _, st, info = rs.gmres_solve(M, A, b[j], x[j], args.restart, reduction, 200)
-            else:
-                _, st, info = rs.bicgstab_solve(M, A, b[j], x[j], reduction, 200)
+            _, st, info = solve(j)
             if record:
                 for i in info:
                     half_steps.append(i["half_steps"])
@@ -292,6 +294,26 @@ def main():
     log(f"roofline {args.roofline}: {units} units, {per_unit_s * 1e6:.2f} us/unit, "
         f"{per_unit_bytes / 1e6:.2f} MB/unit -> {achieved or 0:.1f} GB/s")
 
+    # the two phases on their own, after the timed region and untimed by
+    # events: factorisations back to back, then solves on the last factors
+    reps = max(3, args.steps // 2)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        rs.ilu0_factor(M, A, prec)
+    torch.cuda.synchronize()
+    factor_ms = (time.perf_counter() - t) / reps * 1e3
+    t = time.perf_counter()
+    for _ in range(reps):
+        for j in range(rhs):
+            solve(j)
+    torch.cuda.synchronize()
+    solve_ms = (time.perf_counter() - t) / (reps * rhs) * 1e3
+    phases = {"factor_ms": factor_ms, "solve_ms": solve_ms, "solves_per_s_without_factor": s.batch / solve_ms * 1e3,
+              "note": f"{reps} factorisations, then {reps * rhs} solve calls of {s.batch} system(s) each"}
+    log(f"phases: factorisation {factor_ms:.3f} ms, solve {solve_ms:.3f} ms per call -> "
+        f"{phases['solves_per_s_without_factor']:.1f} solves/s without factorisation")
+
     cpu = None
     if not args.no_cpu:
         v, nsol, dt = cpu_baseline(s, rhs, ordering, precision, reduction, args.cpu_seconds, part,
@@ -326,6 +348,7 @@ def main():
                    "launch_config": tune},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "phases": phases,
         "kernel_classes": class_times,
     }
     print(json.dumps(out), flush=True)
