@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <queue>
 #include <tuple>
 #include <utility>
@@ -74,6 +75,43 @@ static int depth_upper(int n, const int32_t *rowptr, const int32_t *colidx, std:
     return depth;
 }
 
+// DSatur's result on a bipartite graph, without its queue.  Whenever DSatur
+// starts a connected component every uncoloured row has saturation 0, so it
+// takes the component's row with the most neighbours (lowest index first)
+// and gives it colour 0; from then on each row it picks in that component
+// sees one colour only, and takes the other: the colour of a row is the
+// parity of its distance from that first row.  One breadth-first pass per
+// component gives parities relative to its lowest row, checks that no edge
+// joins equal parities and finds the first row; the component is flipped
+// when that row's parity is 1.  Returns false (colour undefined) when the
+// graph is not bipartite.
+static bool bipartite_colour(int n, const std::vector<int32_t> &nptr, const std::vector<int32_t> &nb,
+                             std::vector<int32_t> &colour) {
+    colour.assign(n, -1);
+    std::vector<int32_t> members;
+    members.reserve(1024);
+    for (int s = 0; s < n; ++s) {
+        if (colour[s] >= 0) continue;
+        members.clear();
+        members.push_back(s);
+        colour[s] = 0;
+        int first = s;
+        for (size_t h = 0; h < members.size(); ++h) {
+            const int v = members[h];
+            const int dv = nptr[v + 1] - nptr[v], df = nptr[first + 1] - nptr[first];
+            if (dv > df || (dv == df && v < first)) first = v;
+            for (int p = nptr[v]; p < nptr[v + 1]; ++p) {
+                const int j = nb[p];
+                if (colour[j] < 0) { colour[j] = 1 - colour[v]; members.push_back(j); }
+                else if (colour[j] == colour[v]) return false;
+            }
+        }
+        if (colour[first] == 1)
+            for (int32_t v : members) colour[v] = 1 - colour[v];
+    }
+    return true;
+}
+
 // DSatur colouring (Brelaz 1979); two rows conflict when either holds the
 // other in its pattern.  The next row coloured is the uncoloured one with the
 // most distinct colours among its neighbours, then the most neighbours, then
@@ -83,40 +121,98 @@ static int depth_upper(int n, const int32_t *rowptr, const int32_t *colidx, std:
 // its queue entry is renewed (entries whose saturation is stale are skipped).
 static int dsatur_colour(int n, const int32_t *rowptr, const int32_t *colidx, std::vector<int32_t> &colour) {
     const int nnz = rowptr[n];
-    // symmetrised neighbour lists without the row itself, sorted, unique
-    std::vector<int32_t> cnt(n + 1, 0);
-    for (int i = 0; i < n; ++i)
-        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p)
-            if (colidx[p] != i) { ++cnt[i + 1]; ++cnt[colidx[p] + 1]; }
-    for (int i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
-    std::vector<int32_t> nb(std::max(2 * nnz, 1)), at(cnt.begin(), cnt.end() - 1);
-    for (int i = 0; i < n; ++i)
-        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p)
-            if (colidx[p] != i) { nb[at[i]++] = colidx[p]; nb[at[colidx[p]]++] = i; }
-    std::vector<int32_t> nptr(n + 1, 0);
+    // symmetrised neighbour lists without the row itself, ascending, unique:
+    // the merge of row i (sorted) with column i (the transpose built row by
+    // row, so sorted too)
+    std::vector<int32_t> tptr(n + 1, 0), tcol(std::max(nnz, 1));
+    for (int p = 0; p < nnz; ++p) tptr[colidx[p] + 1]++;
+    for (int i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
     {
-        int w = 0;
-        for (int i = 0; i < n; ++i) {
-            int32_t *b = nb.data() + cnt[i], *e = nb.data() + cnt[i + 1];
-            std::sort(b, e);
-            e = std::unique(b, e);
-            nptr[i] = w;
-            for (int32_t *q = b; q < e; ++q) nb[w++] = *q;
-        }
-        nptr[n] = w;
+        std::vector<int32_t> at(tptr.begin(), tptr.end() - 1);
+        for (int i = 0; i < n; ++i)
+            for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) tcol[at[colidx[p]]++] = i;
     }
+    std::vector<int32_t> nptr(n + 1, 0), nb;
+    nb.reserve(std::max(2 * nnz, 1));
+    for (int i = 0; i < n; ++i) {
+        int a = rowptr[i], b = tptr[i];
+        const int ae = rowptr[i + 1], be = tptr[i + 1];
+        while (a < ae || b < be) {
+            int v;
+            if (b >= be || (a < ae && colidx[a] < tcol[b])) v = colidx[a++];
+            else if (a >= ae || tcol[b] < colidx[a]) v = tcol[b++];
+            else { v = colidx[a++]; ++b; }
+            if (v != i) nb.push_back(v);
+        }
+        nptr[i + 1] = (int32_t)nb.size();
+    }
+    if (bipartite_colour(n, nptr, nb, colour)) return n == 0 ? 0 : *std::max_element(colour.begin(), colour.end()) + 1;
     std::vector<int32_t> sat(n, 0), seen(n + 1, -1);
     colour.assign(n, -1);
-    // (saturation, neighbours, -row): the largest comes out first
+    // Rows of saturation 0 keep their key until they leave it: they wait in
+    // one list by (neighbours descending, index ascending), read by a cursor
+    // that only moves forward.  Rows of saturation 1 and up, which always
+    // come first, sit in the queue below.
+    int maxd = 0;
+    for (int i = 0; i < n; ++i) maxd = std::max(maxd, nptr[i + 1] - nptr[i]);
+    std::vector<int32_t> zero(n);
+    {
+        std::vector<int32_t> at(maxd + 2, 0);   // counting sort, degree descending
+        for (int i = 0; i < n; ++i) ++at[maxd - (nptr[i + 1] - nptr[i]) + 1];
+        for (int d = 0; d <= maxd; ++d) at[d + 1] += at[d];
+        for (int i = 0; i < n; ++i) zero[at[maxd - (nptr[i + 1] - nptr[i])]++] = i;
+    }
+    // The queue: with at most kBucketDegree neighbours per row, one bucket per
+    // (saturation, neighbours) pair, each a min-heap of row indices, scanned
+    // from the highest pair down; else one heap of (saturation, neighbours,
+    // -row).  Entries whose saturation is stale are dropped when they surface.
+    constexpr int kBucketDegree = 255;
+    const bool buckets = maxd <= kBucketDegree;
+    const int w = maxd + 1;
+    std::vector<std::vector<int32_t>> bk(buckets ? (size_t)w * w : 0);
+    int top = -1;
     using Entry = std::tuple<int32_t, int32_t, int32_t>;
     std::priority_queue<Entry> q;
-    for (int i = 0; i < n; ++i) q.emplace(0, nptr[i + 1] - nptr[i], -i);
+    auto push = [&](int j) {
+        const int d = nptr[j + 1] - nptr[j];
+        if (buckets) {
+            const int b = sat[j] * w + d;
+            bk[b].push_back(j);
+            std::push_heap(bk[b].begin(), bk[b].end(), std::greater<int32_t>());
+            top = std::max(top, b);
+        } else {
+            q.emplace(sat[j], d, -j);
+        }
+    };
+    // the uncoloured row of highest positive saturation, or -1
+    auto pop_best = [&]() -> int {
+        if (buckets) {
+            while (top >= 0) {
+                std::vector<int32_t> &h = bk[top];
+                if (h.empty()) { --top; continue; }
+                std::pop_heap(h.begin(), h.end(), std::greater<int32_t>());
+                const int r = h.back();
+                h.pop_back();
+                if (colour[r] < 0 && sat[r] * w + (nptr[r + 1] - nptr[r]) == top) return r;
+            }
+            return -1;
+        }
+        while (!q.empty()) {
+            const auto [s, d, mr] = q.top();
+            q.pop();
+            if (colour[-mr] < 0 && s == sat[-mr]) return -mr;
+        }
+        return -1;
+    };
+    size_t zc = 0;
     int ncol = 0;
-    while (!q.empty()) {
-        const auto [s, d, mv] = q.top();
-        q.pop();
-        const int v = -mv;
-        if (colour[v] >= 0 || s != sat[v]) continue;
+    for (int done = 0; done < n; ++done) {
+        int v = pop_best();
+        if (v < 0) {
+            // no row of positive saturation is left uncoloured
+            while (colour[zero[zc]] >= 0 || sat[zero[zc]] != 0) ++zc;
+            v = zero[zc];
+        }
         for (int p = nptr[v]; p < nptr[v + 1]; ++p)
             if (colour[nb[p]] >= 0) seen[colour[nb[p]]] = v;
         int c = 0;
@@ -128,7 +224,10 @@ static int dsatur_colour(int n, const int32_t *rowptr, const int32_t *colidx, st
             if (colour[j] >= 0) continue;
             bool held = false;
             for (int r = nptr[j]; r < nptr[j + 1] && !held; ++r) held = nb[r] != v && colour[nb[r]] == c;
-            if (!held) q.emplace(++sat[j], nptr[j + 1] - nptr[j], -j);
+            if (!held) {
+                ++sat[j];
+                push(j);
+            }
         }
     }
     return ncol;

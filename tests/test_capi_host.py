@@ -38,7 +38,7 @@ def test_status_strings():
 
 
 @pytest.mark.parametrize("ordering", [rs.ORDER_NATURAL, rs.ORDER_LEVEL_SET, rs.ORDER_GRAPH_COLOUR])
-@pytest.mark.parametrize("case", ["c1", "mask_nnc", "c2", "random"])
+@pytest.mark.parametrize("case", ["c1", "mask_nnc", "c2", "random", "hub", "mask_only"])
 def test_host_ordering_matches_oracle(ordering, case):
     if case == "c1":
         s = config_system("c1")
@@ -50,6 +50,17 @@ def test_host_ordering_matches_oracle(ordering, case):
         pairs = {(int(a), int(b)) for a, b in rng.integers(0, 300, (900, 2)) if a != b}
         rp, ci = pattern_from_pairs(300, sorted(pairs))
         s = type("P", (), {"rowptr": rp, "colidx": ci, "n": 300})
+    elif case == "hub":
+        # a row with 400 neighbours (past the bucketed queue's degree bound)
+        # on a graph that is not bipartite
+        rng = np.random.default_rng(9)
+        pairs = {(0, k) for k in range(1, 401)}
+        pairs |= {(int(a), int(b)) for a, b in rng.integers(1, 500, (800, 2)) if a != b}
+        rp, ci = pattern_from_pairs(500, sorted(pairs))
+        s = type("P", (), {"rowptr": rp, "colidx": ci, "n": 500})
+    elif case == "mask_only":
+        # bipartite, in many components, some of them single rows
+        s = make_grid_system(15, 11, 7, active_frac=0.45, nnc_frac=0.0, seed=4)
     else:
         s = make_grid_system(15, 11, 7, active_frac=0.8, nnc_frac=0.04, seed=3)
     st, perm, ns, bad = rs.ilu0_analyse_host(s.rowptr, s.colidx, ordering)
