@@ -67,6 +67,12 @@ enum rs_status {
     RS_NOT_FACTORED = -10   /* solve or apply before a successful ilu0_factor */
 };
 
+/* Row orderings of Section "ILU0": the caller's order (sequential ILU), level
+ * scheduling (a row's level is one more than its lower neighbours' deepest),
+ * or graph colouring by DSatur (Brelaz 1979: the uncoloured row whose
+ * neighbours hold the most distinct colours next, ties to more neighbours,
+ * then to the lower index; each takes the lowest free colour).  Rows are
+ * sorted stably by level or colour. */
 enum rs_ordering { RS_ORDER_NATURAL = 0, RS_ORDER_LEVEL_SET = 1, RS_ORDER_GRAPH_COLOUR = 2 };
 enum rs_precision { RS_PREC_FP64 = 0, RS_PREC_FP32_FACTORS = 1 };
 enum rs_mem { RS_MEM_HOST = 0, RS_MEM_DEVICE = 1 };
