@@ -94,8 +94,9 @@ enum rs_option {
     RS_OPT_PREDICT_POLL = 4, /* 1 (default): the first poll comes after as many iterations as the
                                 previous solve on this handle needed (iterations queued past
                                 convergence return at once) */
-    RS_OPT_SPMV_VARIANT = 5, /* launch shape of the SpMVs: 0..5 = {4, 2, 1} waves per workgroup
-                                with blocks staged in LDS, then the same three reading directly */
+    RS_OPT_SPMV_VARIANT = 5, /* launch shape of the SpMVs: 0..8 = {4, 2, 1} waves per workgroup
+                                with blocks staged in LDS, then the same three reading directly,
+                                then the same three staged in LDS with non-temporal loads */
     RS_OPT_SWEEP_VARIANT = 6, /* launch shape of the one-launch-per-level sweeps (same encoding) */
     RS_OPT_REDUCE_SPLIT = 7  /* dot products fused into the SpMVs: 0 (default) = each workgroup
                                 joins a ticket tree inside the SpMV; 1 = each wave only stores

@@ -26,7 +26,7 @@ PREC_FP64, PREC_FP32_FACTORS = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 OPT_SWEEP_TILES, OPT_SWEEP_GRID, OPT_POLL_CHUNK, OPT_USE_GRAPH, OPT_PREDICT_POLL = 0, 1, 2, 3, 4
 OPT_SPMV_VARIANT, OPT_SWEEP_VARIANT, OPT_REDUCE_SPLIT = 5, 6, 7
-N_ROW_VARIANTS = 6
+N_ROW_VARIANTS = 9
 
 EXPORTS = (
     "bcsr_create", "bcsr_set_values", "bcsr_set_wells", "bcsr_get_dims", "bcsr_spmv", "bcsr_set_option", "bcsr_destroy", "ilu0_analyse",

@@ -1478,7 +1478,7 @@ static std::string tune_key(ilu0_t M) {
     std::ostringstream k;
     k << "n=" << M->n << ",nnzb=" << M->nnzb << ",batch=" << M->batch << ",ord=" << M->an->sch.ordering
       << ",prec=" << M->precision << ",nl=" << M->an->sch.nl_levels << ",nu=" << M->an->sch.nu_levels
-      << ",m=" << M->an->sch.nnz_m << ",fmt=2"
+      << ",m=" << M->an->sch.nnz_m << ",fmt=3"
       << ",arch=" << prop.gcnArchName << ",cu=" << prop.multiProcessorCount;
     std::string r = k.str();
     for (char &c : r)

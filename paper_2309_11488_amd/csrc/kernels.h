@@ -103,10 +103,11 @@ inline int row_blocks(int rows, int waves = kWavesPerBlock) {
 }
 
 // Launch shapes of the row kernels (SpMV, per-level sweeps): 4, 2 or 1
-// waves per workgroup, blocks staged through LDS or read directly.  The
-// arithmetic and its order are the same in every shape.
+// waves per workgroup, blocks staged through LDS or read directly, or staged
+// with non-temporal loads.  The arithmetic and its order are the same in
+// every shape.
 enum RowVariant { RV_W4_LDS = 0, RV_W2_LDS = 1, RV_W1_LDS = 2, RV_W4_DIRECT = 3, RV_W2_DIRECT = 4, RV_W1_DIRECT = 5,
-                  RV_COUNT = 6 };
+                  RV_W4_LDS_NT = 6, RV_W2_LDS_NT = 7, RV_W1_LDS_NT = 8, RV_COUNT = 9 };
 inline int variant_waves(int v) { return v % 3 == 0 ? 4 : (v % 3 == 1 ? 2 : 1); }
 // SpMV workgroups: one row tile each.
 inline int spmv_grid(int n, int waves) { return std::max(1, row_blocks(n, waves)); }

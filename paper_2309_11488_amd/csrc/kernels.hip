@@ -237,20 +237,32 @@ struct Stage {
 // the last unit with the same data), so the compiler cannot sink a load
 // into a branch and serialise the copy.  Reads stay inside the 16-byte
 // units that overlap the range (allocations are padded for that).
-template <typename T, int CAP, int NT>
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// NTL: blocks and column indices, read once per launch, are loaded
+// non-temporally, so the caches keep the gathered x entries instead (pays
+// when x outgrows an XCD's L2; the autotuner decides).
+template <typename T, int CAP, int NT, bool NTL = false>
 __device__ inline int stage_copy(const T *__restrict__ val, const int32_t *__restrict__ col, int base, int cnt,
                                  Stage<T, CAP, NT> &st) {
     using S = Stage<T, CAP, NT>;
     const char *first = (const char *)(val + (size_t)base * 9);
     const int mis = (int)((uintptr_t)first & 15);
-    const uint4 *src = (const uint4 *)(first - mis);
+    const u32x4 *src = (const u32x4 *)(first - mis);
     const int units = (mis + cnt * 9 * (int)sizeof(T) + 15) / 16;
     uint4 t[S::kPerThread];
 #pragma unroll
-    for (int u = 0; u < S::kPerThread; ++u) t[u] = src[min(u * NT + (int)threadIdx.x, units - 1)];
+    for (int u = 0; u < S::kPerThread; ++u) {
+        const u32x4 *a = src + min(u * NT + (int)threadIdx.x, units - 1);
+        const u32x4 w = NTL ? __builtin_nontemporal_load(a) : *a;
+        t[u] = make_uint4(w.x, w.y, w.z, w.w);
+    }
     int32_t c[S::kColsPerThread];
 #pragma unroll
-    for (int u = 0; u < S::kColsPerThread; ++u) c[u] = col[base + min(u * NT + (int)threadIdx.x, cnt - 1)];
+    for (int u = 0; u < S::kColsPerThread; ++u) {
+        const int32_t *a = col + base + min(u * NT + (int)threadIdx.x, cnt - 1);
+        c[u] = NTL ? __builtin_nontemporal_load(a) : *a;
+    }
 #pragma unroll
     for (int u = 0; u < S::kPerThread; ++u) st.v[min(u * NT + (int)threadIdx.x, units - 1)] = t[u];
 #pragma unroll
@@ -319,7 +331,7 @@ __device__ inline T direct_walk(const int32_t *__restrict__ ptr, const int32_t *
 }
 
 // Walk the blocks of this lane's row, staged through LDS pass by pass.
-template <int CAP, bool SUB, typename T, typename TX, int NT>
+template <int CAP, bool SUB, bool NTL, typename T, typename TX, int NT>
 __device__ inline T stage_walk(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
                                const T *__restrict__ val, int qb0, int qb1, const RowLane &L, const TX *__restrict__ x,
                                T acc, Stage<T, CAP, NT> &st) {
@@ -328,7 +340,7 @@ __device__ inline T stage_walk(const int32_t *__restrict__ ptr, const int32_t *_
     for (int base = e0; base < e1; base += CAP) {
         const int cnt = min(CAP, e1 - base);
         __syncthreads();
-        const int shift = stage_copy<T, CAP, NT>(val, col, base, cnt, st);
+        const int shift = stage_copy<T, CAP, NT, NTL>(val, col, base, cnt, st);
         __syncthreads();
         acc = walk_pass<SUB, false>((const T *)st.v, st.c, shift, base, max(my0, base), min(my1, base + cnt), L.r,
                                     x, acc);
@@ -347,13 +359,13 @@ constexpr int kSweepCapPerWave = 80;
 constexpr int kSweepCap = 4 * kSweepCapPerWave;   // single-launch sweeps: 4-wave workgroups
 
 // Row walk of a workgroup of W waves: staged through LDS or direct.
-template <int W, bool STAGE, int CAPW, bool SUB, typename T, typename TX>
+template <int W, int STAGE, int CAPW, bool SUB, typename T, typename TX>
 __device__ inline T row_walk(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
                              const T *__restrict__ val, int qb0, int qb1, const RowLane &L, const TX *__restrict__ x,
                              T acc) {
-    if constexpr (STAGE) {
+    if constexpr (STAGE != 0) {
         __shared__ Stage<T, CAPW * W, 64 * W> sv;
-        return stage_walk<CAPW * W, SUB>(ptr, col, val, qb0, qb1, L, x, acc, sv);
+        return stage_walk<CAPW * W, SUB, STAGE == 2>(ptr, col, val, qb0, qb1, L, x, acc, sv);
     } else {
         return direct_walk<SUB>(ptr, col, val, L, x, acc);
     }
@@ -593,7 +605,7 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
 
 // ------------------------------------------------------------------ sweeps
 
-template <typename T, bool FUSE_P, int W, bool STAGE>
+template <typename T, bool FUSE_P, int W, int STAGE>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRowWavesPerEU, 8))) k_lsweep(DevSchedule d, const T *__restrict__ L, size_t l_stride,
                                                         const double *__restrict__ in, T *__restrict__ y,
                                                         size_t vstride, const double *__restrict__ rv,
@@ -645,7 +657,7 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
     }
 }
 
-template <typename T, int W, bool STAGE>
+template <typename T, int W, int STAGE>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRowWavesPerEU, 8))) k_usweep(DevSchedule d, const T *__restrict__ U, size_t u_stride,
                                                         const T *__restrict__ Dinv, size_t d_stride,
                                                         const T *__restrict__ y, double *__restrict__ z,
@@ -889,7 +901,7 @@ __global__ void __launch_bounds__(256) k_wells_t2(WellsDev wl, const double *__r
 
 // ------------------------------------------------------------------- SpMV
 
-template <int MODE, int W, bool STAGE>
+template <int MODE, int W, int STAGE>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRowWavesPerEU, 8))) k_spmv(int n, const int32_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ col, const double *__restrict__ A,
                                                       size_t a_stride, const double *__restrict__ x,
@@ -1424,19 +1436,26 @@ __global__ void k_permute_vec(const int32_t *__restrict__ perm, const double *__
 
 }  // namespace
 
-// Call f(waves, staged) with compile-time constants for a RowVariant.
+// Call f(waves, staging) with compile-time constants for a RowVariant
+// (staging 0: direct loads, 1: LDS, 2: LDS with non-temporal loads).
 template <typename F>
 static void with_variant(int v, F &&f) {
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
     using I4 = std::integral_constant<int, 4>;
+    using Direct = std::integral_constant<int, 0>;
+    using Lds = std::integral_constant<int, 1>;
+    using LdsNt = std::integral_constant<int, 2>;
     switch (v) {
-    case RV_W2_LDS: f(I2{}, std::true_type{}); break;
-    case RV_W1_LDS: f(I1{}, std::true_type{}); break;
-    case RV_W4_DIRECT: f(I4{}, std::false_type{}); break;
-    case RV_W2_DIRECT: f(I2{}, std::false_type{}); break;
-    case RV_W1_DIRECT: f(I1{}, std::false_type{}); break;
-    default: f(I4{}, std::true_type{}); break;
+    case RV_W2_LDS: f(I2{}, Lds{}); break;
+    case RV_W1_LDS: f(I1{}, Lds{}); break;
+    case RV_W4_DIRECT: f(I4{}, Direct{}); break;
+    case RV_W2_DIRECT: f(I2{}, Direct{}); break;
+    case RV_W1_DIRECT: f(I1{}, Direct{}); break;
+    case RV_W4_LDS_NT: f(I4{}, LdsNt{}); break;
+    case RV_W2_LDS_NT: f(I2{}, LdsNt{}); break;
+    case RV_W1_LDS_NT: f(I1{}, LdsNt{}); break;
+    default: f(I4{}, Lds{}); break;
     }
 }
 
@@ -1498,7 +1517,7 @@ void launch_lsweep(const DevSchedule &d, const T *L, size_t l_stride, const doub
     if (q1 <= q0 || nsys <= 0) return;
     with_variant(variant, [&](auto W, auto ST) {
         constexpr int w = decltype(W)::value;
-        constexpr bool staged = decltype(ST)::value;
+        constexpr int staged = decltype(ST)::value;
         const dim3 g(row_blocks(q1 - q0, w), nsys);
         if (fuse_p)
             launch_ev(k_lsweep<T, true, w, staged>, g, dim3(64 * w), s, ev0, ev1, d, L, l_stride, in, y, vstride, r,
@@ -1516,7 +1535,7 @@ void launch_usweep(const DevSchedule &d, const T *U, size_t u_stride, const T *D
     if (q1 <= q0 || nsys <= 0) return;
     with_variant(variant, [&](auto W, auto ST) {
         constexpr int w = decltype(W)::value;
-        constexpr bool staged = decltype(ST)::value;
+        constexpr int staged = decltype(ST)::value;
         launch_ev(k_usweep<T, w, staged>, dim3(row_blocks(q1 - q0, w), nsys), dim3(64 * w), s, ev0, ev1, d, U,
                   u_stride, Dinv, d_stride, y, z, vstride, st, q0, q1, defer ? 1 : 0);
     });
@@ -1583,7 +1602,7 @@ static void spmv_any(int variant, int n, const int32_t *ptr, const int32_t *col,
     int waves = 1;
     with_variant(variant, [&](auto W, auto ST) {
         constexpr int w = decltype(W)::value;
-        constexpr bool staged = decltype(ST)::value;
+        constexpr int staged = decltype(ST)::value;
         waves = spmv_grid(n, w) * w;
         const dim3 g(spmv_grid(n, w), nsys), b(64 * w);
         if (ev0)
