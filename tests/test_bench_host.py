@@ -38,3 +38,31 @@ def test_workload_descriptions(workload):
     sys.path.insert(0, ROOT)
     import bench
     assert workload in bench.WORKLOADS and bench.WORKLOADS[workload]["desc"]
+
+
+def test_rcm_renumbering_is_a_similarity():
+    """bench.py --pre rcm hands the solver P A P^T and P b (P from reverse
+    Cuthill-McKee): products with the renumbered matrix are the original's,
+    renumbered."""
+    import numpy as np
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+
+    sys.path.insert(0, ROOT)
+    import bench
+    import oracle
+    from synth import make_grid_system
+
+    s = make_grid_system(9, 8, 6, active_frac=0.9, nnc_frac=0.03, seed=21, n_rhs=2)
+    r = bench.rcm_renumbered(s)
+    perm = reverse_cuthill_mckee(sp.csr_matrix((np.ones(s.nnzb), s.colidx, s.rowptr), shape=(s.n, s.n)),
+                                 symmetric_mode=True)
+    assert r.nnzb == s.nnzb and np.all(np.diff(r.rowptr) >= 1)
+    for i in range(r.n):
+        row = r.colidx[r.rowptr[i]:r.rowptr[i + 1]]
+        assert np.all(np.diff(row) > 0)
+    x = np.random.default_rng(22).standard_normal((s.n, 3))
+    y = oracle.spmv(s.rowptr, s.colidx, s.vals[0], x)
+    y2 = oracle.spmv(r.rowptr, r.colidx, r.vals[0], x[perm])
+    assert np.allclose(y2, y[perm], rtol=1e-13, atol=1e-12)
+    assert np.array_equal(r.b, s.b[:, :, perm])
