@@ -1072,6 +1072,15 @@ __global__ void __launch_bounds__(kVecThreads) k_setup(int n, const int32_t *__r
 // ||s||; half-step test.
 __global__ void __launch_bounds__(kVecThreads) k_s_update(Krylov k, int sums_at, int sums) {
     const int sys = blockIdx.y, bx = blockIdx.x;
+    const size_t vo = (size_t)sys * k.vstride, tiles = k.vstride / kVecTile;
+    // the first tile's vectors are requested before the state and the
+    // partial sums, so those round trips overlap
+    double r0[kVecItems], w0[kVecItems];
+    if ((size_t)bx < tiles) {
+        const size_t e0 = vo + (size_t)bx * kVecTile + threadIdx.x;
+#pragma unroll
+        for (int u = 0; u < kVecItems; ++u) { r0[u] = k.r[e0 + u * kVecThreads]; w0[u] = k.v[e0 + u * kVecThreads]; }
+    }
     SysState &S = k.st[sys];
     if (S.phase != PH_RUN) return;
     double rvv[2];
@@ -1086,13 +1095,17 @@ __global__ void __launch_bounds__(kVecThreads) k_s_update(Krylov k, int sums_at,
     }
     const double alpha = S.rho / rv;
     if (bx == 0 && threadIdx.x == 0) S.alpha = alpha;
-    const size_t vo = (size_t)sys * k.vstride, tiles = k.vstride / kVecTile;
     double v[1] = {0.0};
     for (size_t t = bx; t < tiles; t += gridDim.x) {
         const size_t e0 = vo + t * kVecTile + threadIdx.x;
         double r[kVecItems], w[kVecItems];
+        if (t == (size_t)bx) {
 #pragma unroll
-        for (int u = 0; u < kVecItems; ++u) { r[u] = k.r[e0 + u * kVecThreads]; w[u] = k.v[e0 + u * kVecThreads]; }
+            for (int u = 0; u < kVecItems; ++u) { r[u] = r0[u]; w[u] = w0[u]; }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kVecItems; ++u) { r[u] = k.r[e0 + u * kVecThreads]; w[u] = k.v[e0 + u * kVecThreads]; }
+        }
 #pragma unroll
         for (int u = 0; u < kVecItems; ++u) {
             const double sv = r[u] - alpha * w[u];
@@ -1114,6 +1127,19 @@ __global__ void __launch_bounds__(kVecThreads) k_s_update(Krylov k, int sums_at,
 // breakdown) only x += alpha phat.
 __global__ void __launch_bounds__(kVecThreads) k_xr_update(Krylov k, int sums_at, int sums) {
     const int sys = blockIdx.y, bx = blockIdx.x;
+    const size_t vo = (size_t)sys * k.vstride, tiles = k.vstride / kVecTile;
+    // the first tile's vectors are requested before the state and the
+    // partial sums, so those round trips overlap
+    double x0[kVecItems], ph0[kVecItems], sh0[kVecItems], s0[kVecItems], t0[kVecItems], rh0[kVecItems];
+    if ((size_t)bx < tiles) {
+        const size_t e0 = vo + (size_t)bx * kVecTile + threadIdx.x;
+#pragma unroll
+        for (int u = 0; u < kVecItems; ++u) {
+            const size_t e = e0 + u * kVecThreads;
+            x0[u] = k.x[e]; ph0[u] = k.phat[e]; sh0[u] = k.shat[e];
+            s0[u] = k.s[e]; t0[u] = k.t[e]; rh0[u] = k.rhat[e];
+        }
+    }
     SysState &S = k.st[sys];
     int phase = S.phase;
     if (phase == PH_DONE) return;
@@ -1140,23 +1166,33 @@ __global__ void __launch_bounds__(kVecThreads) k_xr_update(Krylov k, int sums_at
         }
         if (bx == 0 && threadIdx.x == 0) S.omega = omega;
     }
-    const size_t vo = (size_t)sys * k.vstride, tiles = k.vstride / kVecTile;
     double v[2] = {0.0, 0.0};
     for (size_t t = bx; t < tiles; t += gridDim.x) {
         const size_t e0 = vo + t * kVecTile + threadIdx.x;
+        const bool first = t == (size_t)bx;
         if (phase == PH_HALF) {
             double xv[kVecItems], ph[kVecItems];
 #pragma unroll
-            for (int u = 0; u < kVecItems; ++u) { xv[u] = k.x[e0 + u * kVecThreads]; ph[u] = k.phat[e0 + u * kVecThreads]; }
+            for (int u = 0; u < kVecItems; ++u) {
+                xv[u] = first ? x0[u] : k.x[e0 + u * kVecThreads];
+                ph[u] = first ? ph0[u] : k.phat[e0 + u * kVecThreads];
+            }
 #pragma unroll
             for (int u = 0; u < kVecItems; ++u) k.x[e0 + u * kVecThreads] = xv[u] + alpha * ph[u];
         } else {
             double xv[kVecItems], ph[kVecItems], sh[kVecItems], sv[kVecItems], tv[kVecItems], rh[kVecItems];
+            if (first) {
 #pragma unroll
-            for (int u = 0; u < kVecItems; ++u) {
-                const size_t e = e0 + u * kVecThreads;
-                xv[u] = k.x[e]; ph[u] = k.phat[e]; sh[u] = k.shat[e];
-                sv[u] = k.s[e]; tv[u] = k.t[e]; rh[u] = k.rhat[e];
+                for (int u = 0; u < kVecItems; ++u) {
+                    xv[u] = x0[u]; ph[u] = ph0[u]; sh[u] = sh0[u]; sv[u] = s0[u]; tv[u] = t0[u]; rh[u] = rh0[u];
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < kVecItems; ++u) {
+                    const size_t e = e0 + u * kVecThreads;
+                    xv[u] = k.x[e]; ph[u] = k.phat[e]; sh[u] = k.shat[e];
+                    sv[u] = k.s[e]; tv[u] = k.t[e]; rh[u] = k.rhat[e];
+                }
             }
 #pragma unroll
             for (int u = 0; u < kVecItems; ++u) {
