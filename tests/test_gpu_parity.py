@@ -29,6 +29,9 @@ def cases():
         "thin": make_grid_system(1, 1, 200, seed=5),
         "ragged": make_grid_system(5, 17, 1, seed=6),     # 85 rows: one full tile + 1
         "one": make_grid_system(1, 1, 1, seed=7),
+        # bipartite, in many components with single-row islands (the
+        # analysis colours such patterns without its queue)
+        "islands": make_grid_system(15, 11, 7, active_frac=0.45, seed=8),
     }
     return out
 
@@ -139,7 +142,7 @@ def test_factor_parity_dense_pattern(solver_of, n):
 
 
 @pytest.mark.parametrize("ordering", ORDERINGS)
-@pytest.mark.parametrize("name", ["c1", "nnc", "ragged"])
+@pytest.mark.parametrize("name", ["c1", "nnc", "ragged", "islands"])
 @pytest.mark.parametrize("precision", [rs.PREC_FP64, rs.PREC_FP32_FACTORS])
 def test_apply_parity(solver_of, name, ordering, precision):
     s = CASES[name]
@@ -168,7 +171,7 @@ def test_fp32_factors_are_rounded_fp64_factors(solver_of):
 
 
 @pytest.mark.parametrize("ordering", ORDERINGS)
-@pytest.mark.parametrize("name", ["c1", "nnc", "thin", "ragged", "one"])
+@pytest.mark.parametrize("name", ["c1", "nnc", "thin", "ragged", "one", "islands"])
 def test_solve_parity_tight(solver_of, name, ordering):
     s = CASES[name]
     A, M, st, _ = solver_of(s, ordering)
