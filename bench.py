@@ -385,7 +385,10 @@ def solve_bytes(n, nnzb, half_steps, precision):
     """Algorithmic HBM bytes of one request: value upload (device copy), ILU0
     factorisation, BiCGStab half-steps and the true-residual SpMV."""
     per_iter = (304 if precision == "fp64" else 232) * nnzb + 712 * n
-    factor = 148 * nnzb + (108 * nnzb if precision == "fp32" else 0)
+    # factorisation: read A, write the reordered copy A', the factors and
+    # their indices; with FP32 factors only inv(U_ii) is also kept in FP64
+    # (the grids of the stream are bipartite: no row with lower blocks has U)
+    factor = (220 * nnzb) if precision == "fp64" else (184 * nnzb + 72 * n)
     upload = 144 * nnzb
     spmv = 76 * nnzb + 52 * n
     return upload + factor + half_steps * per_iter / 2 + spmv

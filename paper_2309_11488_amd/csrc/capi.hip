@@ -221,6 +221,9 @@ struct Analysis {
     DevBuf perm, prow, pcol, psrc, lrows, lptr, lcol, lsrc, ldq, l2u, upd_ptr, upd, urows, uptr, ucol, usrc, dsrc;
     DevBuf lsrc_a, usrc_a, dsrc_a, rest_dst, rest_src;
     DevBuf lt_start, lt_dptr, lt_dep, ut_start, ut_dptr, ut_dep;
+    // U blocks of rows with lower blocks: with FP32 factors the only U the
+    // factorisation keeps in FP64 (later levels' updates read it)
+    double u_kept = 0;
 };
 
 struct rs_ilu0 {
@@ -518,6 +521,8 @@ static int build_analysis(const rs_bcsr *A, int32_t ordering, const int32_t *par
     rs::build_schedule(A->n, A->nnzb, A->h_rowptr.data(), A->h_colidx.data(), ordering, an->sch, rs::kRowsPerBlock,
                        part);
     const rs::Schedule &S = an->sch;
+    for (int q = 0; q < S.n; ++q)
+        if (S.lptr[q + 1] > S.lptr[q]) an->u_kept += S.uptr[S.l2u[q] + 1] - S.uptr[S.l2u[q]];
     hipError_t e = hipSuccess;
     struct Up { DevBuf *b; const std::vector<int32_t> *v; } ups[] = {
         {&an->perm, &S.perm}, {&an->prow, &S.prow}, {&an->pcol, &S.pcol}, {&an->psrc, &S.psrc},
@@ -715,13 +720,18 @@ int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *ba
     const size_t per = (size_t)M->nnzb * 9;
     {
         // the factor reads A once (blocks and caller positions), writes the
-        // reordered copy A' (the SpMV operand) and L / U / inv(U_ii), reads
+        // reordered copy A' (the SpMV operand) and the factors, reads
         // inv(U_kk) once per lower block and U_kj once per update, plus the
-        // schedule's index lists; FP32 copies written alongside
+        // schedule's index lists.  FP64 factors: L, U and inv(U_ii) in FP64.
+        // FP32 factors: L, U and inv(U_ii) in FP32, and in FP64 only what
+        // later levels read: inv(U_ii) and the U rows of rows with lower
+        // blocks (a row without them is read from A')
         const double nnzb = M->nnzb, n = M->n, nupd = (double)S.upd.size() / 2;
-        double bytes = 72 * nnzb + 72 * nnzb + 72 * nnzb + 72 * (double)S.nL + 72 * nupd +
+        const bool fp32 = precision == RS_PREC_FP32_FACTORS;
+        const double fp64_factor = fp32 ? 72 * (n + M->an->u_kept) : 72 * nnzb;
+        double bytes = 72 * nnzb + 72 * nnzb + fp64_factor + 72 * (double)S.nL + 72 * nupd +
                        4 * (4.0 * S.nL + 3.0 * S.nU + 5 * n) + 8 * nupd;
-        if (precision == RS_PREC_FP32_FACTORS) bytes += 36 * nnzb;
+        if (fp32) bytes += 36 * nnzb;
         if (S.jacobi) bytes += 152 * (double)S.rest_dst.size();
         ProfScope ps(PC_FACTOR, s, B * bytes);
         const DevSchedule &d = M->an->dev;
