@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
 INVALID, BAD_PATTERN, MISSING_DIAG, ZERO_PIVOT, NON_FINITE = -1, -3, -4, -5, -6
-ORDER_NATURAL, ORDER_LEVEL, ORDER_COLOUR = 0, 1, 2
+ORDER_NATURAL, ORDER_LEVEL, ORDER_COLOUR, ORDER_RCM_LEVEL = 0, 1, 2, 3
 PREC_ILU_F64, PREC_ILU_F32, PREC_NONE = 0, 1, 2
 
 
@@ -62,6 +62,7 @@ def lib():
         L.orc_validate.argtypes = [ci, _I32P, _I32P, ct.POINTER(ci)]
         L.orc_level_sets.argtypes = [ci, _I32P, _I32P, _I32P, _I32P]
         L.orc_dsatur_colour.argtypes = [ci, _I32P, _I32P, _I32P, _I32P]
+        L.orc_rcm_levels.argtypes = [ci, _I32P, _I32P, _I32P, _I32P]
         L.orc_permute.argtypes = [ci, _I32P, _I32P, _F64P, _I32P, _I32P, _I32P, _F64P]
         L.orc_permute.restype = None
         L.orc_ilu0.argtypes = [ci, _I32P, _I32P, _F64P, _F64P, ct.POINTER(ci)]
@@ -88,6 +89,8 @@ def lib():
         L.orc_gmres_wells.argtypes = [ci, _I32P, _I32P, _F64P, ci, vp, vp, vp, vp, vp, _F64P, _F64P, ci, _F64P,
                                       ci, cd, ci, _F64P, ct.POINTER(Info), vp]
         L.orc_wells_apply.restype = None
+        L.orc_bicgstab_wells.argtypes = [ci, _I32P, _I32P, _F64P, ci, vp, vp, vp, vp, vp, _F64P, _F64P, ci, _F64P,
+                                         cd, ci, _F64P, ct.POINTER(Info), vp]
         L.orc_solve_wells.argtypes = [ci, _I32P, _I32P, _F64P, vp, ci, vp, vp, vp, vp, vp, _F64P, ci, ci, cd, ci,
                                       _F64P, ct.POINTER(Info), _I32P, ct.POINTER(ci), ct.POINTER(ci)]
         _lib = L
@@ -128,12 +131,24 @@ def dsatur_colour(rowptr, colidx):
     return nc, col, perm
 
 
+def rcm_levels(rowptr, colidx):
+    """(n_levels, level[n], perm[n]) of level scheduling after a reverse
+    Cuthill-McKee renumbering (rows by level, then RCM position)."""
+    n = len(rowptr) - 1
+    level = np.zeros(max(n, 1), np.int32)
+    perm = np.zeros(max(n, 1), np.int32)
+    nl = lib().orc_rcm_levels(n, _i32(rowptr), _i32(colidx), level, perm)
+    return nl, level[:n], perm[:n]
+
+
 def ordering_perm(rowptr, colidx, ordering):
     n = len(rowptr) - 1
     if ordering == ORDER_LEVEL:
         return level_sets(rowptr, colidx)[2]
     if ordering == ORDER_COLOUR:
         return dsatur_colour(rowptr, colidx)[2]
+    if ordering == ORDER_RCM_LEVEL:
+        return rcm_levels(rowptr, colidx)[2]
     return np.arange(n, dtype=np.int32)
 
 
@@ -267,11 +282,15 @@ def jacobi_matrix(rowptr, colidx, vals, part):
 
 
 def bicgstab(rowptr, colidx, vals, lu, dinv, b, *, precond=PREC_ILU_F64, reduction=1e-2, max_iter=200,
-             trace=False, mrow=None, mcol=None):
+             trace=False, mrow=None, mcol=None, wells=None):
     """BiCGStab on an already ordered system.  Returns (x, info dict[, trace (k, 8)]).
 
     The factors lu / dinv live on (mrow, mcol) when given (a Jacobi matrix's
-    pattern), else on the matrix's own pattern."""
+    pattern), else on the matrix's own pattern.  ``wells`` = (well_ptr,
+    perf_row, B, C, Dinv) in this system's numbering adds standard wells kept
+    separate to every product with A (factors on the matrix's pattern).
+    The trace holds, per iteration: rho, (rhat, v), alpha, ||s||, (t, s),
+    (t, t), omega, ||r||."""
     n = len(rowptr) - 1
     x = np.zeros((n, 3), np.float64)
     info = Info()
@@ -280,9 +299,17 @@ def bicgstab(rowptr, colidx, vals, lu, dinv, b, *, precond=PREC_ILU_F64, reducti
     mcol = _i32(colidx if mcol is None else mcol)
     lu = _f64(lu) if lu is not None else np.zeros((max(len(mcol), 1), 3, 3))
     dinv = _f64(dinv) if dinv is not None else np.zeros((max(n, 1), 3, 3))
-    lib().orc_bicgstab_split(n, _i32(rowptr), _i32(colidx), _f64(vals), mrow, mcol, lu, dinv, precond,
-                             _f64(b).reshape(n, 3), reduction, max_iter, x, ct.byref(info),
-                             tr.ctypes.data if tr is not None else None)
+    trp = tr.ctypes.data if tr is not None else None
+    if wells is not None:
+        if mrow is not None and not (np.array_equal(mrow, _i32(rowptr)) and np.array_equal(mcol, _i32(colidx))):
+            raise ValueError("bicgstab with wells takes factors on the matrix's own pattern")
+        wp, pr, B, C, D = (_i32(wells[0]), _i32(wells[1]), _f64(wells[2]), _f64(wells[3]), _f64(wells[4]))
+        lib().orc_bicgstab_wells(n, _i32(rowptr), _i32(colidx), _f64(vals), len(wp) - 1, wp.ctypes.data,
+                                 pr.ctypes.data, B.ctypes.data, C.ctypes.data, D.ctypes.data, lu, dinv, precond,
+                                 _f64(b).reshape(n, 3), reduction, max_iter, x, ct.byref(info), trp)
+    else:
+        lib().orc_bicgstab_split(n, _i32(rowptr), _i32(colidx), _f64(vals), mrow, mcol, lu, dinv, precond,
+                                 _f64(b).reshape(n, 3), reduction, max_iter, x, ct.byref(info), trp)
     if trace:
         return x, info.as_dict(), tr
     return x, info.as_dict()

@@ -56,8 +56,11 @@
  *     a missing diagonal block is a pattern error; a singular diagonal block
  *     during the decomposition is a zero pivot.
  *
- * parity unpinned: the mixed-precision apply's FP32 summation order (its
- * result is pinned only by error bounds, not bit for bit).
+ * The mixed-precision apply (FP32 factors and arithmetic) follows one
+ * reading of its rounding: input rounded to FP32, each product and each sum
+ * rounded separately in row order; a hand-derived fixture pins it bit for
+ * bit.  The GPU path contracts multiply-adds, so it is compared with this
+ * apply within an element-wise FP32 error bound, not bit for bit.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -76,6 +79,7 @@
 #define ORC_ORDER_NATURAL 0
 #define ORC_ORDER_LEVEL 1
 #define ORC_ORDER_COLOUR 2
+#define ORC_ORDER_RCM_LEVEL 3
 
 #define ORC_PREC_ILU_F64 0
 #define ORC_PREC_ILU_F32 1
@@ -155,6 +159,110 @@ int orc_level_sets(int n, const int *rowptr, const int *colidx, int *level, int 
         if (lv + 1 > nlev) nlev = lv + 1;
     }
     sort_by_key(n, level, nlev, perm);
+    return nlev;
+}
+
+/* Reverse Cuthill-McKee renumbering, then level scheduling of the
+ * renumbered rows (a level-reducing reordering before level sets).
+ * Graph: i ~ j when (i,j) or (j,i) is in S, i != j.  Cuthill-McKee (1969):
+ * while rows are left unnumbered, start a new breadth-first search at the
+ * unnumbered row with the fewest neighbours (the smallest index on a tie);
+ * each row taken from the front of the queue appends its unnumbered
+ * neighbours in order of increasing neighbour count (smaller index first
+ * on a tie).  Reverse the whole sequence: pos[row] = n - 1 - (its place).
+ * Then level(row) = 1 + max level over its neighbours with a smaller pos
+ * (0 if none), visiting rows by increasing pos.  perm lists rows by
+ * (level, pos).  Returns the number of levels. */
+static int cmp_int(const void *a, const void *b)
+{
+    int x = *(const int *)a, y = *(const int *)b;
+    return (x > y) - (x < y);
+}
+
+int orc_rcm_levels(int n, const int *rowptr, const int *colidx, int *level, int *perm)
+{
+    size_t nnz = (size_t)rowptr[n];
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    /* neighbour lists: row entries and column entries, sorted, duplicates dropped */
+    int *cnt = calloc(nn + 1, sizeof(int));
+    for (int i = 0; i < n; ++i)
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            int j = colidx[p];
+            if (j == i) continue;
+            cnt[i + 1]++;
+            cnt[j + 1]++;
+        }
+    for (int i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    int *adj = malloc(sizeof(int) * (2 * nnz + 1)), *fill = malloc(sizeof(int) * nn);
+    for (int i = 0; i < n; ++i) fill[i] = cnt[i];
+    for (int i = 0; i < n; ++i)
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            int j = colidx[p];
+            if (j == i) continue;
+            adj[fill[i]++] = j;
+            adj[fill[j]++] = i;
+        }
+    int *deg = malloc(sizeof(int) * nn);
+    for (int i = 0; i < n; ++i) {
+        /* row i's list starts at cnt[i]: sorted, duplicates dropped, its
+         * first deg[i] entries hold the neighbours */
+        int *a = adj + cnt[i];
+        int m = cnt[i + 1] - cnt[i];
+        qsort(a, (size_t)m, sizeof(int), cmp_int);
+        int u = 0;
+        for (int k = 0; k < m; ++k)
+            if (u == 0 || a[k] != a[u - 1]) a[u++] = a[k];
+        deg[i] = u;
+    }
+    int *order = malloc(sizeof(int) * nn), *seen = calloc(nn, sizeof(int));
+    int *cand = malloc(sizeof(int) * nn);
+    int len = 0;
+    while (len < n) {
+        int s = -1;
+        for (int i = 0; i < n; ++i)
+            if (!seen[i] && (s < 0 || deg[i] < deg[s])) s = i;
+        seen[s] = 1;
+        order[len++] = s;
+        for (int h = len - 1; h < len; ++h) {
+            int v = order[h], m = 0;
+            for (int k = 0; k < deg[v]; ++k) {
+                int j = adj[cnt[v] + k];
+                if (!seen[j]) cand[m++] = j;
+            }
+            /* insertion sort by (neighbour count, index) */
+            for (int a = 1; a < m; ++a) {
+                int x = cand[a], b = a - 1;
+                while (b >= 0 && (deg[cand[b]] > deg[x] || (deg[cand[b]] == deg[x] && cand[b] > x))) {
+                    cand[b + 1] = cand[b];
+                    --b;
+                }
+                cand[b + 1] = x;
+            }
+            for (int a = 0; a < m; ++a) {
+                seen[cand[a]] = 1;
+                order[len++] = cand[a];
+            }
+        }
+    }
+    int *pos = malloc(sizeof(int) * nn);
+    for (int k = 0; k < n; ++k) pos[order[k]] = n - 1 - k;
+    int nlev = 0;
+    for (int k = n - 1; k >= 0; --k) {
+        int v = order[k], lv = 0;
+        for (int a = 0; a < deg[v]; ++a) {
+            int j = adj[cnt[v] + a];
+            if (pos[j] < pos[v] && level[j] + 1 > lv) lv = level[j] + 1;
+        }
+        level[v] = lv;
+        if (lv + 1 > nlev) nlev = lv + 1;
+    }
+    /* rows by (level, pos): counting by level over rows in pos order */
+    int *c2 = calloc((size_t)nlev + 1, sizeof(int));
+    for (int i = 0; i < n; ++i) c2[level[i] + 1]++;
+    for (int l = 0; l < nlev; ++l) c2[l + 1] += c2[l];
+    for (int k = n - 1; k >= 0; --k) perm[c2[level[order[k]]]++] = order[k];
+    free(c2); free(pos); free(cand); free(seen); free(order); free(deg); free(fill); free(adj);
+    free(cnt);
     return nlev;
 }
 
@@ -781,6 +889,7 @@ int orc_solve_wells(int n, const int *rowptr, const int *colidx, const double *v
     int sets = n;
     if (ordering == ORC_ORDER_LEVEL) sets = orc_level_sets(n, jrow, jcol, key, perm);
     else if (ordering == ORC_ORDER_COLOUR) sets = orc_dsatur_colour(n, jrow, jcol, key, perm);
+    else if (ordering == ORC_ORDER_RCM_LEVEL) sets = orc_rcm_levels(n, jrow, jcol, key, perm);
     else for (int i = 0; i < n; ++i) perm[i] = i;
     if (n_sets) *n_sets = sets;
     if (perm_out) memcpy(perm_out, perm, sizeof(int) * (size_t)n);
@@ -969,4 +1078,17 @@ int orc_gmres_wells(int n, const int *rowptr, const int *colidx, const double *v
     wells_t wl = {n_wells, well_ptr, perf_row, B, C, Dinv};
     return gmres_core(n, rowptr, colidx, vals, n_wells > 0 ? &wl : NULL, lu, dinv, precond_kind, b, m, reduction,
                       max_iter, x, info, trace);
+}
+
+/* BiCGStab on an already ordered system with n_wells standard wells kept
+ * separate in the operator (Algorithm 5), factors on the matrix's own
+ * pattern; trace as orc_bicgstab. */
+int orc_bicgstab_wells(int n, const int *rowptr, const int *colidx, const double *vals, int n_wells,
+                       const int *well_ptr, const int *perf_row, const double *B, const double *C, const double *Dinv,
+                       const double *lu, const double *dinv, int precond_kind, const double *b, double reduction,
+                       int max_iter, double *x, orc_info *info, double *trace)
+{
+    wells_t wl = {n_wells, well_ptr, perf_row, B, C, Dinv};
+    return bicgstab_wells(n, rowptr, colidx, vals, n_wells > 0 ? &wl : NULL, rowptr, colidx, lu, dinv, precond_kind,
+                          b, reduction, max_iter, x, info, trace);
 }

@@ -15,8 +15,8 @@ import scipy.linalg as sla
 
 import oracle
 from synth import config_system, make_grid_system
-from tests.helpers import (chain_pattern, dense_pattern, pattern_from_pairs, pattern_set, random_values,
-                           read_golden, split_lu, to_dense)
+from tests.helpers import (BREAKDOWN_CASES, breakdown_as_well, chain_pattern, dense_pattern, pattern_from_pairs,
+                           pattern_set, random_values, read_golden, split_lu, to_dense)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -38,6 +38,77 @@ def test_golden_two_block_ilu0():
     x, info = oracle.bicgstab(rowptr, colidx, vals, lu, dinv, g["B"], reduction=1e-12)
     assert info["status"] == oracle.OK and info["half_steps"] == 1
     np.testing.assert_allclose(x.ravel(), g["X"], rtol=0, atol=1e-14)
+
+
+def _fp32_fixture():
+    g = read_golden(os.path.join(GOLDEN, "apply_f32_two_block.txt"))
+    rowptr, colidx = dense_pattern(2)
+    lu = np.zeros((4, 3, 3))
+    lu[1], lu[2] = g["U01"], g["L10"]          # diagonal blocks are not read by the apply
+    dinv = np.stack([g["DINV0"], g["DINV1"]])
+    return rowptr, colidx, lu, dinv, g["V"].reshape(2, 3), g["Z"].reshape(2, 3)
+
+
+def _apply_variant(lu, dinv, v, acc_dtype, round_input, fused=False):
+    """A deliberately different reading of the FP32 apply on the 2-block
+    fixture: products and sums in acc_dtype, the input rounded to FP32 or
+    not, or FP32 with fused multiply-adds (every value of this fixture is
+    exact in FP64, so rounding the FP64 result once is the fused result)."""
+    f32 = np.float32
+    L, U, D0, D1 = (m.astype(f32).astype(acc_dtype) for m in (lu[2], lu[1], dinv[0], dinv[1]))
+    vv = (v.astype(f32) if round_input else v).astype(acc_dtype)
+
+    def d3(b, x):
+        if fused:
+            t = f32(np.float64(b[0]) * np.float64(x[0]))
+            t = f32(np.float64(b[1]) * np.float64(x[1]) + np.float64(t))
+            return f32(np.float64(b[2]) * np.float64(x[2]) + np.float64(t))
+        return (b[0] * x[0] + b[1] * x[1]) + b[2] * x[2]
+
+    y0 = vv[0]
+    y1 = np.array([vv[1, r] - d3(L[r], y0) for r in range(3)], acc_dtype)
+    z1 = np.array([d3(D1[r], y1) for r in range(3)], acc_dtype)
+    acc = np.array([y0[r] - d3(U[r], z1) for r in range(3)], acc_dtype)
+    z0 = np.array([d3(D0[r], acc) for r in range(3)], acc_dtype)
+    return np.stack([z0, z1]).astype(np.float64)
+
+
+def test_golden_fp32_apply_bit_for_bit():
+    """The mixed-precision apply (FP32 factors, FP32 input, every product and
+    sum of both sweeps rounded to FP32 in row order) reproduces a fixture
+    derived by hand bit for bit; readings that accumulate in FP64, keep the
+    input in FP64 or fuse multiply-adds all miss it."""
+    rowptr, colidx, lu, dinv, v, z = _fp32_fixture()
+    got = oracle.apply_f32(rowptr, colidx, lu, dinv, v)
+    assert np.array_equal(got, z)
+    for variant in (_apply_variant(lu, dinv, v, np.float64, True), _apply_variant(lu, dinv, v, np.float64, False),
+                    _apply_variant(lu, dinv, v, np.float32, True, fused=True)):
+        assert not np.array_equal(variant, z)
+    assert np.array_equal(_apply_variant(lu, dinv, v, np.float32, True), z)
+
+
+# ----------------------------------------------------------------- breakdown
+
+@pytest.mark.parametrize("case", sorted(BREAKDOWN_CASES))
+def test_bicgstab_breakdown_branches(case):
+    """Each breakdown branch of BiCGStab ((rhat, v) = 0, (t, t) = 0,
+    omega = 0, rho = 0) on hand-derived exact cases: the status, the half
+    steps taken and x (after omega = 0, x keeps x + alpha phat) are exact.
+    Unpreconditioned on the 3x3 operator itself, and as the identity with
+    one standard well kept separate under ILU0 (the path the GPU runs)."""
+    c = BREAKDOWN_CASES[case]
+    K = np.asarray(c["K"], np.float64)
+    b = np.asarray(c["b"], np.float64)
+    rowptr, colidx = np.array([0, 1], np.int32), np.array([0], np.int32)
+    x, info = oracle.bicgstab(rowptr, colidx, K[None], None, None, b, precond=oracle.PREC_NONE, reduction=0.1)
+    assert info["status"] == oracle.BREAKDOWN and info["half_steps"] == c["half"]
+    assert np.array_equal(x.ravel(), np.asarray(c["x"], np.float64))
+    rp, ci, vals, wp, pr, B, C, Dinv = breakdown_as_well(K)
+    for ordering in (oracle.ORDER_NATURAL, oracle.ORDER_LEVEL):
+        xw, iw = oracle.solve(rp, ci, vals[0], b, ordering=ordering, reduction=0.1,
+                              wells=(wp, pr, B[0], C[0], Dinv[0]))
+        assert iw["status"] == oracle.BREAKDOWN and iw["half_steps"] == c["half"]
+        assert np.array_equal(xw.ravel(), np.asarray(c["x"], np.float64))
 
 
 # --------------------------------------------------------------- validation
@@ -93,6 +164,71 @@ def test_level_sets_respect_dependencies():
     for lv in range(nl):
         rows = perm[level[perm] == lv]
         assert np.all(np.diff(rows) > 0)
+
+
+@pytest.mark.parametrize("shape", [(20, 20, 10), (7, 3, 5), (1, 1, 9), (12, 1, 4)])
+def test_rcm_levels_of_a_full_grid(shape):
+    """Reverse Cuthill-McKee on a full nx*ny*nz grid starts from cell 0 (a
+    corner: fewest neighbours, lowest index), so the breadth-first layers are
+    the planes i + j + k = d and every neighbour of a cell sits one layer
+    away.  Reversed, each layer precedes the one before it, so a cell's
+    lower neighbours are its neighbours one layer further out: its level is
+    (nx - 1) + (ny - 1) + (nz - 1) - (i + j + k), and there are
+    nx + ny + nz - 2 levels (a chain: its cells in reverse)."""
+    nx, ny, nz = shape
+    s = make_grid_system(nx, ny, nz, seed=2)
+    nl, level, perm = oracle.rcm_levels(s.rowptr, s.colidx)
+    i, j, k = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    d = (i + j + k).transpose(2, 1, 0).ravel()        # cells numbered i fastest
+    assert nl == nx + ny + nz - 2
+    assert np.array_equal(level, d.max() - d)
+    assert np.array_equal(np.sort(perm), np.arange(s.n)) and np.all(np.diff(level[perm]) >= 0)
+    if nx == ny == 1:
+        assert np.array_equal(perm, np.arange(s.n)[::-1])
+
+
+@pytest.mark.parametrize("case", ["c1", "grid", "chain", "nnc", "nnc_dense"])
+def test_rcm_matches_scipy(case):
+    """The Cuthill-McKee part equals scipy's reverse_cuthill_mckee where its
+    start rows coincide with this definition's (scipy picks each component's
+    start among the rows of fewest neighbours through an unstable sort; on
+    these patterns it takes the lowest index): the levels computed on
+    scipy's renumbering, rows sorted by (level, position), give the same
+    permutation."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+    s = {"c1": lambda: config_system("c1"), "grid": lambda: make_grid_system(7, 5, 3, seed=1),
+         "chain": lambda: make_grid_system(1, 1, 50, seed=2),
+         "nnc": lambda: make_grid_system(17, 13, 9, active_frac=0.85, nnc_frac=0.03, seed=4),
+         "nnc_dense": lambda: make_grid_system(30, 20, 10, active_frac=0.9, nnc_frac=0.05, seed=9)}[case]()
+    n = s.n
+    a = sp.csr_matrix((np.ones(s.nnzb), s.colidx, s.rowptr), shape=(n, n))
+    r = reverse_cuthill_mckee(a, symmetric_mode=True)
+    pos = np.empty(n, np.int64)
+    pos[r] = np.arange(n)
+    q = a[r][:, r].tocsr()
+    q.sort_indices()
+    nl_s, lev_new, _ = oracle.level_sets(q.indptr.astype(np.int32), q.indices.astype(np.int32))
+    lev = np.empty(n, np.int64)
+    lev[r] = lev_new
+    nl, level, perm = oracle.rcm_levels(s.rowptr, s.colidx)
+    assert nl == nl_s and np.array_equal(level, lev)
+    assert np.array_equal(perm, np.lexsort((pos, lev)))
+
+
+def test_rcm_levels_respect_dependencies_and_shorten_nnc_schedules():
+    """On a masked grid with 2% non-neighbour connections: every row's
+    neighbours that precede it in the RCM numbering sit on lower levels,
+    and the schedule is far shorter than plain level scheduling's."""
+    s = config_system("c2", n_rhs=1)
+    nl, level, perm = oracle.rcm_levels(s.rowptr, s.colidx)
+    pos = np.empty(s.n, np.int64)
+    pos[perm] = np.arange(s.n)
+    rows = np.repeat(np.arange(s.n), np.diff(s.rowptr))
+    off = rows != s.colidx
+    before = pos[s.colidx[off]] < pos[rows[off]]
+    assert np.all(level[s.colidx[off]][before] < level[rows[off]][before])
+    assert nl < oracle.level_sets(s.rowptr, s.colidx)[0] / 20
 
 
 @pytest.mark.parametrize("shape", [(20, 20, 10), (5, 6, 7)])
@@ -701,3 +837,23 @@ def test_gmres_with_wells_converges_to_the_coupled_system(restart):
     _, info = oracle.gmres(s.rowptr, s.colidx, s.vals[0], lu, dinv, b, restart=restart, reduction=0.0, max_iter=1,
                            wells=wells)
     assert abs(info["final_norm"] - best) <= 1e-10 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("case", ["c1", "nnc"])
+@pytest.mark.parametrize("ordering", [oracle.ORDER_NATURAL, oracle.ORDER_LEVEL, oracle.ORDER_COLOUR])
+def test_fp32_apply_within_its_error_bound(case, ordering):
+    """The FP32 apply stays within the first-order FP32 error bound of the
+    exact apply of the same rounded factors and input (computed here in
+    FP64): the bound the GPU's FP32 apply is held to as well."""
+    from tests.helpers import fp32_apply_bound
+    s = config_system("c1") if case == "c1" else make_grid_system(17, 13, 9, active_frac=0.85, nnc_frac=0.03,
+                                                                  seed=4, sigma=2.0)
+    perm = oracle.ordering_perm(s.rowptr, s.colidx, ordering)
+    prow, pcol, pv = oracle.permute(s.rowptr, s.colidx, s.vals[0], perm)
+    _, _, lu, dinv = oracle.ilu0(prow, pcol, pv)
+    v = np.random.default_rng(3).standard_normal((s.n, 3))
+    r32 = [a.astype(np.float32).astype(np.float64) for a in (lu, dinv, v)]
+    z32 = oracle.apply_f32(prow, pcol, lu, dinv, v)
+    exact = oracle.apply(prow, pcol, *r32)
+    assert np.all(np.abs(z32 - exact) <= fp32_apply_bound(prow, pcol, *r32) / 2)
+    assert not np.array_equal(z32, exact)
