@@ -72,8 +72,20 @@ enum rs_status {
  * or graph colouring by DSatur (Brelaz 1979: the uncoloured row whose
  * neighbours hold the most distinct colours next, ties to more neighbours,
  * then to the lower index; each takes the lowest free colour).  Rows are
- * sorted stably by level or colour. */
-enum rs_ordering { RS_ORDER_NATURAL = 0, RS_ORDER_LEVEL_SET = 1, RS_ORDER_GRAPH_COLOUR = 2 };
+ * sorted stably by level or colour.
+ * RS_ORDER_RCM_LEVEL_SET: level scheduling after a reverse Cuthill-McKee
+ * renumbering (Cuthill and McKee 1969), the level-reducing reordering that
+ * the paper's comparison of level sets and graph colouring calls for on
+ * patterns whose non-neighbour connections chain distant rows.  On the
+ * symmetrised graph (i ~ j when either block is stored): each breadth-first
+ * search starts at the unnumbered row with the fewest neighbours (lowest
+ * index on a tie); a row taken from the queue appends its unnumbered
+ * neighbours by increasing neighbour count (lower index on a tie); the
+ * sequence is reversed (position n-1-k for the k-th row numbered).  A
+ * row's level is one more than the deepest level of its neighbours at
+ * lower positions (0 if none); rows are sorted by (level, position). */
+enum rs_ordering { RS_ORDER_NATURAL = 0, RS_ORDER_LEVEL_SET = 1, RS_ORDER_GRAPH_COLOUR = 2,
+                   RS_ORDER_RCM_LEVEL_SET = 3 };
 enum rs_precision { RS_PREC_FP64 = 0, RS_PREC_FP32_FACTORS = 1 };
 enum rs_mem { RS_MEM_HOST = 0, RS_MEM_DEVICE = 1 };
 
@@ -92,17 +104,24 @@ enum rs_option {
                                 synchronous copies) made meanwhile by other threads: set 0 when
                                 solving from several threads */
     RS_OPT_PREDICT_POLL = 4, /* 1 (default): the first poll comes after as many iterations as the
-                                previous solve on this handle needed (iterations queued past
-                                convergence return at once) */
+                                last converged solve on this handle needed, at most 50
+                                (iterations queued past convergence return at once); solves that
+                                end without converging leave the prediction unchanged */
     RS_OPT_SPMV_VARIANT = 5, /* launch shape of the SpMVs: 0..8 = {4, 2, 1} waves per workgroup
                                 with blocks staged in LDS, then the same three reading directly,
                                 then the same three staged in LDS with non-temporal loads */
     RS_OPT_SWEEP_VARIANT = 6, /* launch shape of the one-launch-per-level sweeps (same encoding) */
-    RS_OPT_REDUCE_SPLIT = 7  /* dot products fused into the SpMVs: 0 (default) = each workgroup
+    RS_OPT_REDUCE_SPLIT = 7, /* dot products fused into the SpMVs: 0 (default) = each workgroup
                                 joins a ticket tree inside the SpMV; 1 = each wave only stores
                                 its partial and a one-workgroup kernel adds them; 2 = each wave
                                 stores its partial and every workgroup of the next vector kernel
                                 adds them (few partials: small systems) */
+    RS_OPT_SPIN_LIMIT = 8    /* polls before a single-launch sweep's dependency wait gives up
+                                (default 4194304, >= 0).  A wait that gives up lets its tile go
+                                on, so the launch still ends; the solve then returns RS_HIP_ERROR
+                                and the handle's sweep counters and tile flags are reset, so the
+                                next call starts clean.  A small value forces that error path
+                                (for tests of the recovery) */
 };
 
 /* Per-system outcome of bicgstab_solve and gmres_solve. */
@@ -113,6 +132,13 @@ typedef struct {
     double r0_norm;            /* ||b||_2 (x0 = 0) */
     double final_norm;         /* recursively updated residual norm at the stop */
     double true_rel_residual;  /* ||b - A x||_2 / ||b||_2 with the caller's A, FP64 */
+    double factor_ms;          /* device time of the ILU0 factorisation the solve used (HIP events
+                                  around its launches on the stream of that ilu0_factor call;
+                                  whole batch) */
+    double solve_ms;           /* device time of this solve call on its stream, from the first
+                                  kernel (permutation of b, initial residual) to the end of the
+                                  true residual (HIP events; whole batch; host gaps between
+                                  polls included) */
 } solve_info;
 
 /* bcsr_create -- validate a BCSR pattern and copy pattern and values to the
@@ -178,7 +204,8 @@ int bcsr_destroy(bcsr_t A);
  * pattern): the ordering (RS_ORDER_*), the reordered pattern, lower and
  * upper sweep schedules and the factor update lists; all copied to the
  * device (complete on return, usable from any stream).  Section "ILU0" of
- * the implementation chapter. */
+ * the implementation chapter.  Errors: RS_INVALID_ARG (ordering not an
+ * rs_ordering), RS_OUT_OF_MEMORY, RS_HIP_ERROR. */
 int ilu0_analyse(bcsr_t A, int32_t ordering, ilu0_t *out);
 
 /* ilu0_analyse_jacobi -- as ilu0_analyse for the Block-Jacobi-ILU0
@@ -211,11 +238,14 @@ int bcsr_partition(int32_t n_brows, int32_t nnzb, const int32_t *row_ptr, const 
  * only immutable parts of `like`, so `like` may be in use on another thread. */
 int ilu0_analyse_shared(bcsr_t A, ilu0_t like, ilu0_t *out);
 
-/* ilu0_get_schedule -- perm[new] = old (host, n_brows ints, may be NULL);
- * *n_sets = number of levels (LS), colours (GC) or lower-sweep levels
+/* ilu0_get_schedule -- the reordering of Section "ILU0" of the
+ * implementation chapter, as analysed: perm[new] = old (host, n_brows ints,
+ * may be NULL), the permutation P of b' = P b and A' = P A P^T;
+ * *n_sets = number of levels (LS, RCM then LS), colours (GC) or one per row
  * (natural order); set_ptr (host, n_sets + 1 ints, may be NULL) = the start
- * of each level/colour in the new order (LS, GC) or in the lower-sweep
- * schedule (natural). */
+ * of each level/colour in the new order (natural: i).  Rows of one set have
+ * no dependency on each other, so one launch per set may process them
+ * together.  Host only; errors: RS_INVALID_ARG. */
 int ilu0_get_schedule(ilu0_t M, int32_t *perm, int32_t *n_sets, int32_t *set_ptr);
 
 /* ilu0_get_sweep_levels -- number of levels of the lower and upper sweep
@@ -274,13 +304,25 @@ int ilu0_get_factors(ilu0_t M, int32_t sys, double *lu, double *dinv);
 int ilu0_apply(ilu0_t M, const double *v, double *z, int32_t first_sys, int32_t n_sys, int32_t mem,
                void *stream);
 
-/* bicgstab_solve -- preconditioned BiCGStab for every system of A (b, x:
- * batch * n_brows * 3 doubles, mem) with x0 = 0, stopping when the residual
- * 2-norm, tested after each half and full step, falls to reduction * ||b||
- * or after max_iter iterations.  info (host, batch entries, may be NULL)
- * receives each system's outcome, including the true FP64 residual.
- * Returns the worst status over the systems (errors first, then
- * RS_BREAKDOWN, RS_NOT_CONVERGED, RS_OK).  Synchronises `stream`. */
+/* bicgstab_solve -- BiCGStab (Section "Bicgstab solver": the Krylov solver
+ * of the simulator, relative residual reduction 1e-2 and 200 iterations by
+ * default) right-preconditioned by the factors of the last ilu0_factor
+ * (equations 3-4), for every system of A (b, x: batch * n_brows * 3
+ * doubles, mem, caller's row order) with x0 = 0.  Each iteration tests the
+ * recursively updated residual's 2-norm after its half step (on s) and its
+ * full step (on r) against reduction * ||b||; max_iter full iterations at
+ * most.  A failed solve is not fatal (Section "Fallback"): x holds the last
+ * iterate and the status says why, so the caller may switch solvers.
+ * info (host, batch entries, may be NULL) receives each system's outcome,
+ * including the true FP64 residual ||b - A x|| / ||b|| and the device times
+ * of the factorisation and the solve.  Returns the worst status over the
+ * systems (errors first, then RS_BREAKDOWN, RS_NOT_CONVERGED, RS_OK).
+ * Statuses: RS_BREAKDOWN when rho, (rhat,v), (t,t) or omega is exactly zero
+ * (after omega = 0, x keeps its half-step update); RS_NON_FINITE when a
+ * reduction is NaN or Inf; RS_ZERO_PIVOT for a system whose factorisation
+ * failed; errors RS_INVALID_ARG (reduction < 0, max_iter < 0, NULL
+ * vectors), RS_NOT_FACTORED, RS_PATTERN_MISMATCH, RS_OUT_OF_MEMORY,
+ * RS_HIP_ERROR.  Synchronises `stream`. */
 int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduction, int32_t max_iter,
                    int32_t mem, void *stream, solve_info *info);
 
@@ -321,9 +363,17 @@ int ilu0_analyse_host(int32_t n_brows, const int32_t *row_ptr, const int32_t *co
  * 0 = one ILU0 factorisation, 1 = one lower sweep (all its level
  * launches), 2 = one upper sweep, 3 = one v = A phat launch, 4 = one
  * vector-update launch, 5 = one t = A shat launch (and GMRES's products
- * with A), 6 = one GMRES Gram-Schmidt launch).  Single-kernel units record
- * dispatch events (the kernel's own start and end); with graphs on, a
- * timed sweep replays as a graph segment of its own between two events.
+ * with A), 6 = one GMRES Gram-Schmidt launch, 7 = one preconditioner
+ * application (both sweeps)).  Single-kernel units record dispatch events
+ * (the kernel's own start and end); with graphs on, a timed sweep or
+ * application replays as a graph segment of its own between two events.
+ * Algorithmic bytes per unit (nL, nU: blocks of L and U; N rows; tb = 8
+ * for FP64 factors, 4 for FP32): factorisation 148 nnzb; lower sweep
+ * (9 tb + 4) nL + 52 N; upper sweep (9 tb + 4)(nU + N) + 48 N (inv(U_ii)
+ * with U); application the sum of both; v = A phat and t = A shat 76 nnzb
+ * + 52 N; vector updates the vectors they read and write.  The fused work
+ * a kernel also does (the p update in the first lower sweep, the dot
+ * product in the SpMV) is not counted.
  * Resets the counters.  Process-wide, not thread-safe; 0 disables. */
 int rsolve_profile_enable(int32_t mask);
 
@@ -350,8 +400,10 @@ int rsolve_profile_get(int32_t cls, double *ms, int64_t *units, double *bytes);
  * head of the queue does not fit, idle instances are freed, least recently
  * used first.  Each request is factored (`precision`) and solved exactly as
  * ilu0_factor / bicgstab_solve would, so results do not depend on the mix;
- * with `autotune`, the first instance of a pattern runs ilu0_autotune and
- * later instances take its launch configuration. */
+ * with `autotune`, the first request of a pattern runs ilu0_autotune on its
+ * instance, and every other request of that pattern waits (in its slot)
+ * until the tuning has ended and then runs with the tuned configuration, so
+ * all results of a pattern come from one launch configuration. */
 typedef struct rs_server *server_t;
 
 typedef struct {
@@ -377,7 +429,9 @@ typedef struct {
     int64_t queued, running, completed;
     int64_t instances;      /* resident instances now */
     int64_t created, evicted, analyses;
-    size_t reserved_bytes, peak_reserved_bytes;
+    size_t reserved_bytes, peak_reserved_bytes;   /* the budget's account of footprints */
+    size_t device_used_bytes;   /* hipMemGetInfo total - free now (the whole process and device) */
+    size_t device_total_bytes;  /* hipMemGetInfo total */
 } server_stats;
 
 /* server_create -- start max_slots worker threads on the current device.

@@ -21,11 +21,11 @@ LIB_PATH = os.path.join(HERE, "librsolve.so")
 OK, NOT_CONVERGED, BREAKDOWN, PENDING = 0, 1, 2, 3
 INVALID_ARG, UNSUPPORTED_BLOCK_SIZE, BAD_PATTERN, MISSING_DIAGONAL = -1, -2, -3, -4
 ZERO_PIVOT, NON_FINITE, OUT_OF_MEMORY, HIP_ERROR, PATTERN_MISMATCH, NOT_FACTORED = -5, -6, -7, -8, -9, -10
-ORDER_NATURAL, ORDER_LEVEL_SET, ORDER_GRAPH_COLOUR = 0, 1, 2
+ORDER_NATURAL, ORDER_LEVEL_SET, ORDER_GRAPH_COLOUR, ORDER_RCM_LEVEL_SET = 0, 1, 2, 3
 PREC_FP64, PREC_FP32_FACTORS = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 OPT_SWEEP_TILES, OPT_SWEEP_GRID, OPT_POLL_CHUNK, OPT_USE_GRAPH, OPT_PREDICT_POLL = 0, 1, 2, 3, 4
-OPT_SPMV_VARIANT, OPT_SWEEP_VARIANT, OPT_REDUCE_SPLIT = 5, 6, 7
+OPT_SPMV_VARIANT, OPT_SWEEP_VARIANT, OPT_REDUCE_SPLIT, OPT_SPIN_LIMIT = 5, 6, 7, 8
 N_ROW_VARIANTS = 9
 
 EXPORTS = (
@@ -37,13 +37,14 @@ EXPORTS = (
     "server_submit", "server_poll", "server_wait", "server_get_stats",
     "server_destroy", "rsolve_status_string", "rsolve_last_error",
 )
-PROF_FACTOR, PROF_LSWEEP, PROF_USWEEP, PROF_SPMV_V, PROF_VEC, PROF_SPMV_T, PROF_GM = 0, 1, 2, 3, 4, 5, 6
+PROF_FACTOR, PROF_LSWEEP, PROF_USWEEP, PROF_SPMV_V, PROF_VEC, PROF_SPMV_T, PROF_GM, PROF_APPLY = 0, 1, 2, 3, 4, 5, 6, 7
 GMRES_MAX_RESTART = 32
 
 
 class SolveInfo(ct.Structure):
     _fields_ = [("status", ct.c_int32), ("half_steps", ct.c_int32), ("r0_norm", ct.c_double),
-                ("final_norm", ct.c_double), ("true_rel_residual", ct.c_double)]
+                ("final_norm", ct.c_double), ("true_rel_residual", ct.c_double), ("factor_ms", ct.c_double),
+                ("solve_ms", ct.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -75,7 +76,8 @@ class ServerTiming(ct.Structure):
 class ServerStats(ct.Structure):
     _fields_ = [("queued", ct.c_int64), ("running", ct.c_int64), ("completed", ct.c_int64),
                 ("instances", ct.c_int64), ("created", ct.c_int64), ("evicted", ct.c_int64),
-                ("analyses", ct.c_int64), ("reserved_bytes", ct.c_size_t), ("peak_reserved_bytes", ct.c_size_t)]
+                ("analyses", ct.c_int64), ("reserved_bytes", ct.c_size_t), ("peak_reserved_bytes", ct.c_size_t),
+                ("device_used_bytes", ct.c_size_t), ("device_total_bytes", ct.c_size_t)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -112,18 +112,12 @@ static bool bipartite_colour(int n, const std::vector<int32_t> &nptr, const std:
     return true;
 }
 
-// DSatur colouring (Brelaz 1979); two rows conflict when either holds the
-// other in its pattern.  The next row coloured is the uncoloured one with the
-// most distinct colours among its neighbours, then the most neighbours, then
-// the lowest index; it takes the lowest colour its neighbours leave free.
-// Saturation only grows: when row v takes colour c, a neighbour's saturation
-// grows by one unless another of its coloured neighbours already holds c, and
-// its queue entry is renewed (entries whose saturation is stale are skipped).
-static int dsatur_colour(int n, const int32_t *rowptr, const int32_t *colidx, std::vector<int32_t> &colour) {
+// Symmetrised neighbour lists without the row itself, ascending, unique:
+// the merge of row i (sorted) with column i (the transpose built row by
+// row, so sorted too).  Neighbours of i: nb[nptr[i] .. nptr[i+1]).
+static void symmetric_neighbours(int n, const int32_t *rowptr, const int32_t *colidx, std::vector<int32_t> &nptr,
+                                 std::vector<int32_t> &nb) {
     const int nnz = rowptr[n];
-    // symmetrised neighbour lists without the row itself, ascending, unique:
-    // the merge of row i (sorted) with column i (the transpose built row by
-    // row, so sorted too)
     std::vector<int32_t> tptr(n + 1, 0), tcol(std::max(nnz, 1));
     for (int p = 0; p < nnz; ++p) tptr[colidx[p] + 1]++;
     for (int i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
@@ -132,7 +126,8 @@ static int dsatur_colour(int n, const int32_t *rowptr, const int32_t *colidx, st
         for (int i = 0; i < n; ++i)
             for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) tcol[at[colidx[p]]++] = i;
     }
-    std::vector<int32_t> nptr(n + 1, 0), nb;
+    nptr.assign(n + 1, 0);
+    nb.clear();
     nb.reserve(std::max(2 * nnz, 1));
     for (int i = 0; i < n; ++i) {
         int a = rowptr[i], b = tptr[i];
@@ -146,6 +141,83 @@ static int dsatur_colour(int n, const int32_t *rowptr, const int32_t *colidx, st
         }
         nptr[i + 1] = (int32_t)nb.size();
     }
+}
+
+// Reverse Cuthill-McKee renumbering followed by level scheduling (the
+// level-reducing reordering for patterns whose non-neighbour connections
+// chain distant rows; Section "ILU0" of the implementation chapter and the
+// comparison of level sets with graph colouring in the results).  On the
+// symmetrised graph, Cuthill and McKee (1969): every breadth-first search
+// starts at the unnumbered row with the fewest neighbours (lowest index on
+// a tie); a row leaving the queue appends its unnumbered neighbours by
+// increasing neighbour count (lower index on a tie).  Reversing the
+// sequence gives each row its position.  A row's level is one more than the
+// deepest level among its neighbours at lower positions (0 if none).
+// perm lists rows by (level, position); set_ptr holds the level starts.
+static int rcm_levels(int n, const int32_t *rowptr, const int32_t *colidx, std::vector<int32_t> &perm,
+                      std::vector<int32_t> &set_ptr) {
+    std::vector<int32_t> nptr, nb;
+    symmetric_neighbours(n, rowptr, colidx, nptr, nb);
+    auto deg = [&](int v) { return nptr[v + 1] - nptr[v]; };
+    auto before = [&](int a, int b) { return deg(a) < deg(b) || (deg(a) == deg(b) && a < b); };
+    // start rows: all rows by (neighbours, index); a cursor skips numbered ones
+    std::vector<int32_t> starts(n);
+    for (int i = 0; i < n; ++i) starts[i] = i;
+    std::stable_sort(starts.begin(), starts.end(), [&](int a, int b) { return deg(a) < deg(b); });
+    std::vector<int32_t> seq;
+    seq.reserve(n);
+    std::vector<char> taken(n, 0);
+    std::vector<int32_t> cand;
+    size_t cursor = 0;
+    while ((int)seq.size() < n) {
+        while (taken[starts[cursor]]) ++cursor;
+        const int s0 = starts[cursor];
+        taken[s0] = 1;
+        seq.push_back(s0);
+        for (size_t h = seq.size() - 1; h < seq.size(); ++h) {
+            const int v = seq[h];
+            cand.clear();
+            for (int p = nptr[v]; p < nptr[v + 1]; ++p)
+                if (!taken[nb[p]]) cand.push_back(nb[p]);
+            std::sort(cand.begin(), cand.end(), before);
+            for (int32_t c : cand) {
+                taken[c] = 1;
+                seq.push_back(c);
+            }
+        }
+    }
+    // position of row v: n - 1 - (its place in seq); visit rows by position
+    std::vector<int32_t> pos(n), level(n, 0);
+    for (int k = 0; k < n; ++k) pos[seq[k]] = n - 1 - k;
+    int nlev = n > 0 ? 1 : 0;
+    for (int k = n - 1; k >= 0; --k) {
+        const int v = seq[k];
+        int lv = 0;
+        for (int p = nptr[v]; p < nptr[v + 1]; ++p)
+            if (pos[nb[p]] < pos[v]) lv = std::max(lv, level[nb[p]] + 1);
+        level[v] = lv;
+        nlev = std::max(nlev, lv + 1);
+    }
+    // rows by (level, position): count per level, then place rows in position order
+    set_ptr.assign(nlev + 1, 0);
+    for (int i = 0; i < n; ++i) set_ptr[level[i] + 1]++;
+    for (int l = 0; l < nlev; ++l) set_ptr[l + 1] += set_ptr[l];
+    std::vector<int32_t> next(set_ptr.begin(), set_ptr.end() - 1);
+    perm.resize(n);
+    for (int k = n - 1; k >= 0; --k) perm[next[level[seq[k]]]++] = seq[k];
+    return nlev;
+}
+
+// DSatur colouring (Brelaz 1979); two rows conflict when either holds the
+// other in its pattern.  The next row coloured is the uncoloured one with the
+// most distinct colours among its neighbours, then the most neighbours, then
+// the lowest index; it takes the lowest colour its neighbours leave free.
+// Saturation only grows: when row v takes colour c, a neighbour's saturation
+// grows by one unless another of its coloured neighbours already holds c, and
+// its queue entry is renewed (entries whose saturation is stale are skipped).
+static int dsatur_colour(int n, const int32_t *rowptr, const int32_t *colidx, std::vector<int32_t> &colour) {
+    std::vector<int32_t> nptr, nb;
+    symmetric_neighbours(n, rowptr, colidx, nptr, nb);
     if (bipartite_colour(n, nptr, nb, colour)) return n == 0 ? 0 : *std::max_element(colour.begin(), colour.end()) + 1;
     std::vector<int32_t> sat(n, 0), seen(n + 1, -1);
     colour.assign(n, -1);
@@ -241,6 +313,8 @@ int make_ordering(int n, const int32_t *rowptr, const int32_t *colidx, int order
         nsets = depth_lower(n, rowptr, colidx, key);
     } else if (ordering == RS_ORDER_GRAPH_COLOUR) {
         nsets = dsatur_colour(n, rowptr, colidx, key);
+    } else if (ordering == RS_ORDER_RCM_LEVEL_SET) {
+        return rcm_levels(n, rowptr, colidx, perm, set_ptr);
     } else {
         perm.resize(n);
         set_ptr.resize(n + 1);

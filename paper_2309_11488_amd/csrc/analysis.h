@@ -12,9 +12,10 @@ namespace rs {
 // RS_BAD_PATTERN or RS_MISSING_DIAGONAL; *bad_row names the row.
 int validate_pattern(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx, int *bad_row);
 
-// perm[new] = old for the three orderings, and set_ptr = the first new
-// position of each level/colour.  Returns the number of levels (level sets),
-// colours (graph colouring) or n (natural order: one row per set).
+// perm[new] = old for the four orderings, and set_ptr = the first new
+// position of each level/colour.  Returns the number of levels (level sets,
+// reverse Cuthill-McKee then level sets), colours (graph colouring) or n
+// (natural order: one row per set).
 int make_ordering(int n, const int32_t *rowptr, const int32_t *colidx, int ordering, std::vector<int32_t> &perm,
                   std::vector<int32_t> &set_ptr);
 int make_ordering(int n, const int32_t *rowptr, const int32_t *colidx, int ordering, std::vector<int32_t> &perm);

@@ -96,7 +96,7 @@ hipError_t upload(DevBuf &buf, const std::vector<int32_t> &v, hipStream_t s) {
 // iteration that stopped at its half step.
 enum ProfClass {
     PC_FACTOR = 0, PC_LSWEEP = 1, PC_USWEEP = 2, PC_SPMV_V = 3, PC_VEC = 4, PC_SPMV_T = 5, PC_GM = 6,
-    PC_COUNT = 7
+    PC_APPLY = 7, PC_COUNT = 8
 };
 
 struct Prof {
@@ -134,8 +134,9 @@ struct ProfScope {
     double bytes;
     bool dispatch;
     hipEvent_t a = nullptr, b = nullptr;
-    ProfScope(int c, hipStream_t st, double by, bool disp = false) : cls(c), s(st), bytes(by), dispatch(disp) {
-        if ((g_prof.mask >> cls) & 1) {
+    ProfScope(int c, hipStream_t st, double by, bool disp = false, bool on = true)
+        : cls(c), s(st), bytes(by), dispatch(disp) {
+        if (on && ((g_prof.mask >> cls) & 1)) {
             a = prof_event();
             if (a && dispatch) {
                 b = prof_event();
@@ -244,8 +245,12 @@ struct rs_ilu0 {
     SysState *h_state = nullptr;
     rs::SweepCtr *h_ctr = nullptr;
     int chunk = 1;
-    bool predict = true;       // first poll after as many iterations as the previous solve needed
+    bool predict = true;       // first poll after as many iterations as the last converged solve needed
     int last_iters = 1;
+    int spin_limit = rs::kSpinLimitDefault;   // polls before a tile dependency wait gives up
+    // device time of the last factorisation and of the current solve call
+    hipEvent_t ev_f0 = nullptr, ev_f1 = nullptr, ev_s0 = nullptr, ev_s1 = nullptr;
+    double factor_ms = 0.0;
     bool tile_sweeps = true;   // single-launch sweeps (else one launch per level)
     int sweep_grid = 1024;     // workgroups of a single-launch sweep
     int spmv_variant = rs::RV_W4_LDS;   // launch shape of the SpMVs
@@ -267,11 +272,12 @@ struct rs_ilu0 {
     // every setting a captured iteration depends on
     struct GraphKey {
         int precision = -1, tile_sweeps = 0, spmv_variant = 0, sweep_variant = 0, split = 0, sweep_grid = 0;
+        int spin = 0;
         long long wells = 0;   // 0: no wells, else the wells' version + 1
         bool operator==(const GraphKey &o) const {
             return precision == o.precision && tile_sweeps == o.tile_sweeps && spmv_variant == o.spmv_variant &&
                    sweep_variant == o.sweep_variant && split == o.split && sweep_grid == o.sweep_grid &&
-                   wells == o.wells;
+                   spin == o.spin && wells == o.wells;
         }
     };
     struct Segment {
@@ -289,6 +295,8 @@ struct rs_ilu0 {
     }
     ~rs_ilu0() {
         drop_graph();
+        for (hipEvent_t e : {ev_f0, ev_f1, ev_s0, ev_s1})
+            if (e) (void)hipEventDestroy(e);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         if (h_state) (void)hipHostFree(h_state);
         if (h_ctr) (void)hipHostFree(h_ctr);
@@ -337,7 +345,7 @@ const char *rsolve_status_string(int status) {
 int ilu0_analyse_host(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t ordering, int32_t *perm,
                       int32_t *n_sets, int32_t *bad_row) {
     if (bad_row) *bad_row = -1;
-    if (n < 0 || !row_ptr || (n > 0 && !col_idx) || ordering < 0 || ordering > 2)
+    if (n < 0 || !row_ptr || (n > 0 && !col_idx) || ordering < 0 || ordering > RS_ORDER_RCM_LEVEL_SET)
         return fail(RS_INVALID_ARG, "ilu0_analyse_host: bad arguments");
     int bad = -1;
     const int nnzb = row_ptr[n];
@@ -571,14 +579,17 @@ static rs_ilu0 *new_ilu0(const rs_bcsr *A, std::shared_ptr<const Analysis> an) {
     M->nnzb = A->nnzb;
     M->batch = A->batch;
     M->hash = A->hash;
-    // few, wide colours: one launch per colour; many thin levels: one launch per sweep
-    M->tile_sweeps = an->sch.ordering != RS_ORDER_GRAPH_COLOUR;
+    // many thin levels (natural order, level sets): one launch per sweep;
+    // few wide colours or levels (colouring, RCM then level sets): one
+    // launch per colour or level
+    M->tile_sweeps = an->sch.ordering == RS_ORDER_NATURAL || an->sch.ordering == RS_ORDER_LEVEL_SET;
     M->an = std::move(an);
     return M;
 }
 
 int ilu0_analyse(bcsr_t A, int32_t ordering, ilu0_t *out) {
-    if (!A || !out || ordering < 0 || ordering > 2) return fail(RS_INVALID_ARG, "ilu0_analyse: bad arguments");
+    if (!A || !out || ordering < 0 || ordering > RS_ORDER_RCM_LEVEL_SET)
+        return fail(RS_INVALID_ARG, "ilu0_analyse: bad arguments");
     *out = nullptr;
     std::shared_ptr<Analysis> an;
     const int st = build_analysis(A, ordering, nullptr, an);
@@ -588,7 +599,7 @@ int ilu0_analyse(bcsr_t A, int32_t ordering, ilu0_t *out) {
 }
 
 int ilu0_analyse_jacobi(bcsr_t A, int32_t ordering, const int32_t *part, ilu0_t *out) {
-    if (!A || !out || !part || ordering < 0 || ordering > 2)
+    if (!A || !out || !part || ordering < 0 || ordering > RS_ORDER_RCM_LEVEL_SET)
         return fail(RS_INVALID_ARG, "ilu0_analyse_jacobi: bad arguments");
     *out = nullptr;
     std::shared_ptr<Analysis> an;
@@ -668,6 +679,10 @@ int ilu0_set_option(ilu0_t M, int32_t option, int32_t value) {
         if (value < 0 || value >= rs::RV_COUNT) break;
         M->sweep_variant = value;
         return RS_OK;
+    case RS_OPT_SPIN_LIMIT:
+        if (value < 0) break;
+        M->spin_limit = value;
+        return RS_OK;
     default:
         break;
     }
@@ -685,6 +700,7 @@ int ilu0_get_option(ilu0_t M, int32_t option, int32_t *value) {
     case RS_OPT_SPMV_VARIANT: *value = M->spmv_variant; return RS_OK;
     case RS_OPT_SWEEP_VARIANT: *value = M->sweep_variant; return RS_OK;
     case RS_OPT_REDUCE_SPLIT: *value = M->reduce_split; return RS_OK;
+    case RS_OPT_SPIN_LIMIT: *value = M->spin_limit; return RS_OK;
     default: return fail(RS_INVALID_ARG, "ilu0_get_option: unknown option");
     }
 }
@@ -716,23 +732,17 @@ int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *ba
         HIP_TRY(M->Dinvf.alloc(B * M->n * 9 * sizeof(float)));
     }
     M->factored = false;
+    if (!M->ev_f0) HIP_TRY(hipEventCreate(&M->ev_f0));
+    if (!M->ev_f1) HIP_TRY(hipEventCreate(&M->ev_f1));
+    HIP_TRY(hipEventRecord(M->ev_f0, s));
     HIP_TRY(hipMemsetAsync(M->bad.p, 0x7f, B * sizeof(int32_t), s));
     const size_t per = (size_t)M->nnzb * 9;
     {
-        // the factor reads A once (blocks and caller positions), writes the
-        // reordered copy A' (the SpMV operand) and the factors, reads
-        // inv(U_kk) once per lower block and U_kj once per update, plus the
-        // schedule's index lists.  FP64 factors: L, U and inv(U_ii) in FP64.
-        // FP32 factors: L, U and inv(U_ii) in FP32, and in FP64 only what
-        // later levels read: inv(U_ii) and the U rows of rows with lower
-        // blocks (a row without them is read from A')
-        const double nnzb = M->nnzb, n = M->n, nupd = (double)S.upd.size() / 2;
-        const bool fp32 = precision == RS_PREC_FP32_FACTORS;
-        const double fp64_factor = fp32 ? 72 * (n + M->an->u_kept) : 72 * nnzb;
-        double bytes = 72 * nnzb + 72 * nnzb + fp64_factor + 72 * (double)S.nL + 72 * nupd +
-                       4 * (4.0 * S.nL + 3.0 * S.nU + 5 * n) + 8 * nupd;
-        if (fp32) bytes += 36 * nnzb;
-        if (S.jacobi) bytes += 152 * (double)S.rest_dst.size();
+        // algorithmic bytes of the method: every block of the
+        // preconditioner's matrix read, updated in place and written once
+        // (148 per block with its index); Block-Jacobi also copies the
+        // dropped blocks into A' (144 each)
+        const double bytes = 148.0 * S.nnz_m + 144.0 * (double)S.rest_dst.size();
         ProfScope ps(PC_FACTOR, s, B * bytes);
         const DevSchedule &d = M->an->dev;
         rs::launch_gather_pairs(A->vals.as<double>(), per, M->pvals.as<double>(), per, d.rest_dst, d.rest_src,
@@ -746,9 +756,14 @@ int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *ba
                                     S.lconsec[l] && S.rest_dst.empty(), M->batch, s);
     }
     HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(M->ev_f1, s));
     M->bad_host.assign(B, 0);
     HIP_TRY(hipMemcpyAsync(M->bad_host.data(), M->bad.p, B * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    {
+        float ms = 0.f;
+        M->factor_ms = hipEventElapsedTime(&ms, M->ev_f0, M->ev_f1) == hipSuccess ? ms : 0.0;
+    }
     int worst = RS_OK;
     for (size_t i = 0; i < B; ++i) {
         const int32_t b = M->bad_host[i];
@@ -871,39 +886,63 @@ static int ensure_workspace(ilu0_t M, hipStream_t s) {
     return RS_OK;
 }
 
+// After a single-launch sweep gave up a dependency wait: clear the sweep
+// counters and every tile flag together (epochs restart from zero, so no
+// flag may keep an epoch of an earlier sweep), once the stream has drained.
+static int sweep_reset(ilu0_t M, hipStream_t s) {
+    const size_t nf = (size_t)M->batch * ((size_t)M->an->sch.ltiles.n + M->an->sch.utiles.n);
+    HIP_TRY(hipMemsetAsync(M->ctrs.p, 0, 2 * sizeof(rs::SweepCtr), s));
+    if (nf) HIP_TRY(hipMemsetAsync(M->flags.p, 0, nf * sizeof(int32_t), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return fail(RS_HIP_ERROR, "sweep dependency wait exceeded its limit");
+}
+
+// Events bracketing a solve call on its stream (created on first use); the
+// start is recorded here.
+static int solve_events(ilu0_t M, hipStream_t s) {
+    if (!M->ev_s0) HIP_TRY(hipEventCreate(&M->ev_s0));
+    if (!M->ev_s1) HIP_TRY(hipEventCreate(&M->ev_s1));
+    HIP_TRY(hipEventRecord(M->ev_s0, s));
+    return RS_OK;
+}
+
+static double elapsed_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    return hipEventElapsedTime(&ms, a, b) == hipSuccess ? ms : 0.0;
+}
+
+// Largest number of iterations (GMRES: steps) a solve queues before its
+// first poll when predicting from the previous solve.
+constexpr int kPredictMax = 50;
+
 // Non-zero when a single-launch sweep reported a dependency wait that ran
-// past its spin limit (clears the flag).
+// past its spin limit (resets the sweep state).
 static int sweep_error(ilu0_t M, hipStream_t s) {
     rs::SweepCtr c[2];
     HIP_TRY(hipMemcpyAsync(c, M->ctrs.p, sizeof c, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (c[0].error || c[1].error) {
-        HIP_TRY(hipMemsetAsync(M->ctrs.p, 0, sizeof c, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        return fail(RS_HIP_ERROR, "sweep dependency wait exceeded its limit");
-    }
+    if (c[0].error || c[1].error) return sweep_reset(M, s);
     return RS_OK;
 }
 
 }  // extern "C"
 
-// Algorithmic bytes of one lower sweep: L blocks with their column indices,
-// row pointer and row list, the input (r, p, v read and p written when
-// fused), y written once, and for the rows that also finish the upper sweep
-// (upper level 0) their inv(U_ii) and z.
-static double lower_bytes(ilu0_t M, double tb, bool fuse_p, int nsys) {
+// Algorithmic bytes of a preconditioner application (equations 3-4), the
+// method's minimum whatever the launches: every factor block once with its
+// column index (9 tb + 4 bytes, tb = factor element size), a row pointer,
+// and the vectors: the lower sweep reads its input and writes y (52 N with
+// the row pointer), the upper sweep reads y and writes z (48 N), inv(U_ii)
+// counted with U.  Fused work (the p update of an iteration's first lower
+// sweep) is not counted.  The lower launches also finish the rows without
+// upper blocks, whose inv(U_ii) and z are counted with the upper sweep.
+static double lower_bytes(ilu0_t M, double tb, int nsys) {
     const rs::Schedule &S = M->an->sch;
-    const double n = M->n, in_b = fuse_p ? 96 : 24;
-    const double fold = S.nu_levels > 0 ? S.uset[1] : 0;
-    return nsys * ((9 * tb + 4) * S.nL + (8 + 4 + in_b + 3 * tb) * n + (9 * tb + 24) * fold);
+    return nsys * ((9 * tb + 4) * S.nL + 52.0 * M->n);
 }
 
-// Algorithmic bytes of the upper sweep's launches (levels 1 and up): U
-// blocks with indices, inv(U_ii), row pointer and row list, y read, z written.
 static double upper_bytes(ilu0_t M, double tb, int nsys) {
     const rs::Schedule &S = M->an->sch;
-    const double rows = M->n - (S.nu_levels > 0 ? S.uset[1] : 0);
-    return nsys * ((9 * tb + 4) * S.nU + (8 + 3 * tb + 9 * tb + 24) * rows);
+    return nsys * ((9 * tb + 4) * ((double)S.nU + M->n) + 48.0 * M->n);
 }
 
 // Lower sweep of one preconditioner application M^{-1} in -> out (new
@@ -914,10 +953,10 @@ static void lower_levels(ilu0_t M, const T *L, const T *D, const double *in, dou
     const rs::Schedule &S = M->an->sch;
     const size_t vs = k.vstride;
     T *y = (T *)k.y;
-    ProfScope ps(PC_LSWEEP, s, lower_bytes(M, sizeof(T), fuse_p, nsys), M->tile_sweeps);
+    ProfScope ps(PC_LSWEEP, s, lower_bytes(M, sizeof(T), nsys), M->tile_sweeps);
     if (M->tile_sweeps) {
         rs::launch_lsweep_tiles<T>(M->an->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, k.lflags,
-                                   k.lctr, nsys, M->sweep_grid, s, ps.start(), ps.stop());
+                                   k.lctr, nsys, M->sweep_grid, M->spin_limit, s, ps.start(), ps.stop());
         return;
     }
     // the upper sweep's first level (rows without upper blocks) is finished
@@ -939,7 +978,7 @@ static void upper_levels(ilu0_t M, const T *U, const T *D, double *out, bool fus
     ProfScope ps(PC_USWEEP, s, upper_bytes(M, sizeof(T), nsys), M->tile_sweeps);
     if (M->tile_sweeps) {
         rs::launch_usweep_tiles<T>(M->an->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, k.uflags,
-                                   k.uctr, nsys, M->sweep_grid, s, ps.start(), ps.stop());
+                                   k.uctr, nsys, M->sweep_grid, M->spin_limit, s, ps.start(), ps.stop());
         return;
     }
     for (int l = 1; l < S.nu_levels; ++l)
@@ -951,6 +990,8 @@ static void upper_levels(ilu0_t M, const T *U, const T *D, double *out, bool fus
 template <typename T>
 static void apply_levels(ilu0_t M, const T *L, const T *U, const T *D, const double *in, double *out, bool fuse_p,
                          Krylov &k, SysState *st, int nsys, hipStream_t s) {
+    const double tb = sizeof(T);
+    ProfScope ps(PC_APPLY, s, lower_bytes(M, tb, nsys) + upper_bytes(M, tb, nsys));
     lower_levels<T>(M, L, D, in, out, fuse_p, k, st, nsys, s);
     upper_levels<T>(M, U, D, out, fuse_p, k, st, nsys, s);
 }
@@ -963,11 +1004,18 @@ enum {
     P_L1 = 1, P_U1 = 2, P_SPMV_V = 4, P_SUPD = 8, P_L2 = 16, P_U2 = 32, P_SPMV_T = 64, P_XR = 128, P_ALL = 255
 };
 
+// An application is timed as one unit only while neither of its sweeps is
+// timed on its own.
+static bool apply_unit(int mask) {
+    return ((mask >> PC_APPLY) & 1) && !((mask >> PC_LSWEEP) & 1) && !((mask >> PC_USWEEP) & 1);
+}
+
 // The iteration parts that hold launches of the kernel classes in `mask`.
 static int class_parts(int mask) {
     int parts = 0;
     if ((mask >> PC_LSWEEP) & 1) parts |= P_L1 | P_L2;
     if ((mask >> PC_USWEEP) & 1) parts |= P_U1 | P_U2;
+    if (apply_unit(mask)) parts |= P_L1 | P_U1 | P_L2 | P_U2;
     if ((mask >> PC_SPMV_V) & 1) parts |= P_SPMV_V;
     if ((mask >> PC_SPMV_T) & 1) parts |= P_SPMV_T;
     if ((mask >> PC_VEC) & 1) parts |= P_SUPD | P_XR;
@@ -979,12 +1027,18 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
     Krylov &k = M->k;
     const int B = M->batch;
     const size_t per = (size_t)M->nnzb * 9;
-    const double n = M->n, nnzb = M->nnzb;
-    // values + column indices, row pointers, x gathered once, y written, one
-    // more vector read by the fused dot product
-    const double spmv_bytes = B * (76 * nnzb + 4 * n + 72 * n);
-    if (parts & P_L1) lower_levels<T>(M, L, D, nullptr, k.phat, true, k, k.st, B, s);
-    if (parts & P_U1) upper_levels<T>(M, U, D, k.phat, true, k, k.st, B, s);
+    const double n = M->n, nnzb = M->nnzb, tb = sizeof(T);
+    // algorithmic bytes of y = A x: values and column indices, row
+    // pointers, x read once, y written (the fused dot product's second
+    // vector is not counted)
+    const double spmv_bytes = B * (76 * nnzb + 52 * n);
+    const double apply_bytes = lower_bytes(M, tb, B) + upper_bytes(M, tb, B);
+    {
+        // an application is timed whole or not at all
+        ProfScope pa(PC_APPLY, s, apply_bytes, false, (parts & P_L1) && (parts & P_U1));
+        if (parts & P_L1) lower_levels<T>(M, L, D, nullptr, k.phat, true, k, k.st, B, s);
+        if (parts & P_U1) upper_levels<T>(M, U, D, k.phat, true, k, k.st, B, s);
+    }
     if (parts & P_SPMV_V) {
         ProfScope ps(PC_SPMV_V, s, spmv_bytes, true);
         rs::launch_spmv_v(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), M->wdev, s,
@@ -994,8 +1048,11 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
         ProfScope ps(PC_VEC, s, B * 72 * n, true);
         rs::launch_s_update(M->n, k, B, M->spmv_variant, M->split(), s, ps.start(), ps.stop());
     }
-    if (parts & P_L2) lower_levels<T>(M, L, D, k.s, k.shat, false, k, k.st, B, s);
-    if (parts & P_U2) upper_levels<T>(M, U, D, k.shat, false, k, k.st, B, s);
+    {
+        ProfScope pa(PC_APPLY, s, apply_bytes, false, (parts & P_L2) && (parts & P_U2));
+        if (parts & P_L2) lower_levels<T>(M, L, D, k.s, k.shat, false, k, k.st, B, s);
+        if (parts & P_U2) upper_levels<T>(M, U, D, k.shat, false, k, k.st, B, s);
+    }
     if (parts & P_SPMV_T) {
         ProfScope ps(PC_SPMV_T, s, spmv_bytes, true);
         rs::launch_spmv_t(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), M->wdev, s,
@@ -1025,6 +1082,7 @@ static int replay_segment(ilu0_t M, int parts, hipStream_t s) {
     key.sweep_variant = M->sweep_variant;
     key.split = M->split();
     key.sweep_grid = M->sweep_grid;
+    key.spin = M->spin_limit;
     key.wells = M->wdev.nw > 0 ? (long long)M->wells_version + 1 : 0;
     rs_ilu0::Segment &seg = M->segments[parts];
     if (!seg.exec || !(seg.key == key)) {
@@ -1064,6 +1122,7 @@ static int run_iteration(ilu0_t M, hipStream_t s) {
     const int timed = class_parts(g_prof.mask);
     if (!timed) return replay_segment(M, P_ALL, s);
     const double tb = M->precision == RS_PREC_FP32_FACTORS ? 4 : 8;
+    const bool whole = apply_unit(g_prof.mask);
     int run = 0;
     for (int part = 1; part <= P_XR; part <<= 1) {
         if (!(timed & part)) {
@@ -1075,11 +1134,19 @@ static int run_iteration(ilu0_t M, hipStream_t s) {
             if (st != RS_OK) return st;
             run = 0;
         }
+        if (whole && (part == P_L1 || part == P_L2)) {
+            // a whole application (both sweeps) as one graph segment between two events
+            ProfScope ps(PC_APPLY, s, lower_bytes(M, tb, M->batch) + upper_bytes(M, tb, M->batch));
+            const int st = replay_segment(M, part | (part << 1), s);
+            if (st != RS_OK) return st;
+            part <<= 1;   // its upper sweep is done
+            continue;
+        }
         const bool sweep = part == P_L1 || part == P_U1 || part == P_L2 || part == P_U2;
         if (sweep && !M->tile_sweeps) {
             const bool lower = part == P_L1 || part == P_L2;
             ProfScope ps(lower ? PC_LSWEEP : PC_USWEEP, s,
-                         lower ? lower_bytes(M, tb, part == P_L1, M->batch) : upper_bytes(M, tb, M->batch));
+                         lower ? lower_bytes(M, tb, M->batch) : upper_bytes(M, tb, M->batch));
             const int st = replay_segment(M, part, s);
             if (st != RS_OK) return st;
         } else {
@@ -1145,7 +1212,7 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
     const int B = M->batch;
     if (M->n == 0) {
         if (info)
-            for (int i = 0; i < B; ++i) info[i] = solve_info{RS_OK, 0, 0.0, 0.0, 0.0};
+            for (int i = 0; i < B; ++i) info[i] = solve_info{RS_OK, 0, 0.0, 0.0, 0.0, M->factor_ms, 0.0};
         return RS_OK;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -1163,6 +1230,8 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
         xd = M->xstage.as<double>();
     }
     Krylov &k = M->k;
+    st = solve_events(M, s);
+    if (st != RS_OK) return st;
     {
         ProfScope ps(PC_VEC, s, (double)B * 152 * M->n);
         rs::launch_setup(M->an->dev, bd, M->bad.as<int32_t>(), reduction, max_iter, k, B, s);
@@ -1172,6 +1241,7 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
         rs::launch_finish(M->an->dev, A->rowptr.as<int32_t>(), A->colidx.as<int32_t>(), A->vals.as<double>(),
                           (size_t)A->nnzb * 9, bd, xd, k, B, M->spmv_variant, M->split(), A->wells(), s);
         HIP_TRY(hipGetLastError());
+        HIP_TRY(hipEventRecord(M->ev_s1, s));
         HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(M->h_ctr, k.lctr, 2 * sizeof(rs::SweepCtr), hipMemcpyDeviceToHost, s));
         if (mem != RS_MEM_DEVICE) HIP_TRY(hipMemcpyAsync(x, xd, m * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1216,19 +1286,17 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
         st = finish();
         if (st != RS_OK) return st;
     }
-    if (M->h_ctr[0].error || M->h_ctr[1].error) {
-        HIP_TRY(hipMemsetAsync(M->ctrs.p, 0, 2 * sizeof(rs::SweepCtr), s));
-        HIP_TRY(hipStreamSynchronize(s));
-        return fail(RS_HIP_ERROR, "sweep dependency wait exceeded its limit");
-    }
+    if (M->h_ctr[0].error || M->h_ctr[1].error) return sweep_reset(M, s);
+    const double solve_ms = elapsed_ms(M->ev_s0, M->ev_s1);
     int worst = RS_OK, needed = 1;
     for (int i = 0; i < B; ++i) {
         const SysState &S = M->h_state[i];
-        if (info) info[i] = solve_info{S.status, S.half_steps, S.r0norm, S.last_norm, S.true_res};
+        if (info) info[i] = solve_info{S.status, S.half_steps, S.r0norm, S.last_norm, S.true_res, M->factor_ms, solve_ms};
         if (status_rank(S.status) > status_rank(worst)) worst = S.status;
         needed = std::max(needed, (S.half_steps + 1) / 2);
     }
-    M->last_iters = needed;
+    // the prediction learns from converged solves only, and stays small
+    if (worst == RS_OK) M->last_iters = std::min(needed, kPredictMax);
     return worst;
 }
 
@@ -1324,7 +1392,7 @@ int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart,
     const int B = M->batch;
     if (M->n == 0) {
         if (info)
-            for (int i = 0; i < B; ++i) info[i] = solve_info{RS_OK, 0, 0.0, 0.0, 0.0};
+            for (int i = 0; i < B; ++i) info[i] = solve_info{RS_OK, 0, 0.0, 0.0, 0.0, M->factor_ms, 0.0};
         return RS_OK;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -1354,6 +1422,8 @@ int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart,
         HIP_TRY(M->xstage.alloc(m * sizeof(double)));
         xd = M->xstage.as<double>();
     }
+    st = solve_events(M, s);
+    if (st != RS_OK) return st;
     {
         // r = rhat = P b, x = 0, ||b||, the initial tests; the first cycle
         // starts from v_0 = r / ||b||
@@ -1379,6 +1449,7 @@ int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart,
         rs::launch_finish(M->an->dev, A->rowptr.as<int32_t>(), A->colidx.as<int32_t>(), A->vals.as<double>(),
                           (size_t)A->nnzb * 9, bd, xd, k, B, M->spmv_variant, M->split(), A->wells(), s);
         HIP_TRY(hipGetLastError());
+        HIP_TRY(hipEventRecord(M->ev_s1, s));
         HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(M->h_ctr, k.lctr, 2 * sizeof(rs::SweepCtr), hipMemcpyDeviceToHost, s));
         if (mem != RS_MEM_DEVICE) HIP_TRY(hipMemcpyAsync(x, xd, m * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1440,19 +1511,16 @@ int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart,
         st = finish();
         if (st != RS_OK) return st;
     }
-    if (M->h_ctr[0].error || M->h_ctr[1].error) {
-        HIP_TRY(hipMemsetAsync(M->ctrs.p, 0, 2 * sizeof(rs::SweepCtr), s));
-        HIP_TRY(hipStreamSynchronize(s));
-        return fail(RS_HIP_ERROR, "sweep dependency wait exceeded its limit");
-    }
+    if (M->h_ctr[0].error || M->h_ctr[1].error) return sweep_reset(M, s);
+    const double solve_ms = elapsed_ms(M->ev_s0, M->ev_s1);
     int worst = RS_OK, needed = 1;
     for (int i = 0; i < B; ++i) {
         const SysState &S = M->h_state[i];
-        if (info) info[i] = solve_info{S.status, S.half_steps, S.r0norm, S.last_norm, S.true_res};
+        if (info) info[i] = solve_info{S.status, S.half_steps, S.r0norm, S.last_norm, S.true_res, M->factor_ms, solve_ms};
         if (status_rank(S.status) > status_rank(worst)) worst = S.status;
         needed = std::max(needed, S.half_steps);
     }
-    M->last_gm_steps = needed;
+    if (worst == RS_OK) M->last_gm_steps = std::min(needed, kPredictMax);
     return worst;
 }
 

@@ -178,16 +178,18 @@ void launch_usweep(const DevSchedule &d, const T *U, size_t u_stride, const T *D
 // dispatch records at the kernel's start and end.
 
 // Single-launch sweeps over all tiles of all nsys systems (L: lower
-// schedule, U: upper schedule).  grid = number of workgroups.
+// schedule, U: upper schedule).  grid = number of workgroups; spin = polls
+// before a dependency wait gives up (sets ctr->error and goes on).
+constexpr int kSpinLimitDefault = 1 << 22;
 template <typename T>
 void launch_lsweep_tiles(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
                          bool fuse_p, const double *r, const double *v, double *p, SysState *st, int32_t *flags,
-                         SweepCtr *ctr, int nsys, int grid, hipStream_t s, hipEvent_t ev0 = nullptr,
+                         SweepCtr *ctr, int nsys, int grid, int spin, hipStream_t s, hipEvent_t ev0 = nullptr,
                          hipEvent_t ev1 = nullptr);
 template <typename T>
 void launch_usweep_tiles(const DevSchedule &d, const T *U, size_t u_stride, const T *Dinv, size_t d_stride,
                          const T *y, double *z, size_t vstride, SysState *st, int32_t *flags, SweepCtr *ctr, int nsys,
-                         int grid, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                         int grid, int spin, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Plain y = A x (rows in storage order), FP64.
 // y = A x (minus the separate wells, when w has any: t2 is computed first).

@@ -694,9 +694,9 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
 // its factor blocks into LDS (independent of the solution), then waits until
 // every tile it depends on carries this sweep's epoch, computes, writes its
 // rows with agent-coherent stores, waits for those stores to complete and
-// publishes its own flag.  Waits are bounded: past kSpinLimit polls the
-// counter's error word is set and the tile proceeds (no hang).
-constexpr int kSpinLimit = 1 << 22;
+// publishes its own flag.  Waits are bounded: past `spin` polls (the
+// handle's RS_OPT_SPIN_LIMIT) the counter's error word is set and the tile
+// proceeds (no hang).
 
 struct TileWalk {
     int item, tile, sys;
@@ -728,13 +728,13 @@ __device__ inline void leave_sweep(SweepCtr *ctr, uint32_t epoch) {
 }
 
 __device__ inline void wait_tiles(const int32_t *__restrict__ dptr, const int32_t *__restrict__ dep,
-                                  const int32_t *flags, int tile, uint32_t epoch, SweepCtr *ctr) {
+                                  const int32_t *flags, int tile, uint32_t epoch, SweepCtr *ctr, int spin) {
     for (int i = dptr[tile] + threadIdx.x; i < dptr[tile + 1]; i += blockDim.x) {
         const int32_t *f = flags + dep[i];
         int spins = 0;
         while ((uint32_t)__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
             __builtin_amdgcn_s_sleep(1);
-            if (++spins > kSpinLimit) {
+            if (++spins > spin) {
                 __hip_atomic_fetch_or(&ctr->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
@@ -756,7 +756,7 @@ __global__ void __launch_bounds__(kRowThreads) k_lsweep_tiles(DevSchedule d, con
                                                               const double *__restrict__ rv,
                                                               const double *__restrict__ vv, double *__restrict__ pv,
                                                               SysState *__restrict__ st, int32_t *__restrict__ flags,
-                                                              SweepCtr *__restrict__ ctr, int nsys) {
+                                                              SweepCtr *__restrict__ ctr, int nsys, int spin) {
     __shared__ Stage<T, kSweepCap> sv;
     const uint32_t epoch = __hip_atomic_load(&ctr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
     const int total = d.nlt * nsys;
@@ -784,7 +784,7 @@ __global__ void __launch_bounds__(kRowThreads) k_lsweep_tiles(DevSchedule d, con
                 acc = (T)in[k];
             }
         }
-        wait_tiles(d.lt_dptr, d.lt_dep, flags + (size_t)w.sys * d.nlt, w.tile, epoch, ctr);
+        wait_tiles(d.lt_dptr, d.lt_dep, flags + (size_t)w.sys * d.nlt, w.tile, epoch, ctr, spin);
         __syncthreads();
         for (int base = e0; base < e1; base += kSweepCap) {
             if (base != e0) {
@@ -808,7 +808,7 @@ __global__ void __launch_bounds__(kRowThreads) k_usweep_tiles(DevSchedule d, con
                                                               size_t d_stride, const T *__restrict__ y,
                                                               double *__restrict__ z, size_t vstride,
                                                               SysState *__restrict__ st, int32_t *__restrict__ flags,
-                                                              SweepCtr *__restrict__ ctr, int nsys) {
+                                                              SweepCtr *__restrict__ ctr, int nsys, int spin) {
     __shared__ Stage<T, kSweepCap> sv;
     const uint32_t epoch = __hip_atomic_load(&ctr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
     const int total = d.nut * nsys;
@@ -830,7 +830,7 @@ __global__ void __launch_bounds__(kRowThreads) k_usweep_tiles(DevSchedule d, con
             const T *dp = Dinv + (size_t)w.sys * d_stride + (size_t)rl.q * 9 + 3 * rl.r;
             dq[0] = dp[0]; dq[1] = dp[1]; dq[2] = dp[2];
         }
-        wait_tiles(d.ut_dptr, d.ut_dep, flags + (size_t)w.sys * d.nut, w.tile, epoch, ctr);
+        wait_tiles(d.ut_dptr, d.ut_dep, flags + (size_t)w.sys * d.nut, w.tile, epoch, ctr, spin);
         __syncthreads();
         for (int base = e0; base < e1; base += kSweepCap) {
             if (base != e0) {
@@ -1593,39 +1593,39 @@ template void launch_usweep<float>(const DevSchedule &, const float *, size_t, c
 template <typename T>
 void launch_lsweep_tiles(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
                          bool fuse_p, const double *r, const double *v, double *p, SysState *st, int32_t *flags,
-                         SweepCtr *ctr, int nsys, int grid, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                         SweepCtr *ctr, int nsys, int grid, int spin, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (d.nlt <= 0 || nsys <= 0) return;
     grid = std::max(1, std::min(grid, d.nlt * nsys));
     if (fuse_p)
         launch_ev(k_lsweep_tiles<T, true>, dim3(grid), dim3(kRowThreads), s, ev0, ev1, d, L, l_stride, in, y,
-                  vstride, r, v, p, st, flags, ctr, nsys);
+                  vstride, r, v, p, st, flags, ctr, nsys, spin);
     else
         launch_ev(k_lsweep_tiles<T, false>, dim3(grid), dim3(kRowThreads), s, ev0, ev1, d, L, l_stride, in, y,
-                  vstride, r, v, p, st, flags, ctr, nsys);
+                  vstride, r, v, p, st, flags, ctr, nsys, spin);
 }
 
 template <typename T>
 void launch_usweep_tiles(const DevSchedule &d, const T *U, size_t u_stride, const T *Dinv, size_t d_stride,
                          const T *y, double *z, size_t vstride, SysState *st, int32_t *flags, SweepCtr *ctr, int nsys,
-                         int grid, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                         int grid, int spin, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (d.nut <= 0 || nsys <= 0) return;
     grid = std::max(1, std::min(grid, d.nut * nsys));
     launch_ev(k_usweep_tiles<T>, dim3(grid), dim3(kRowThreads), s, ev0, ev1, d, U, u_stride, Dinv, d_stride, y, z,
-              vstride, st, flags, ctr, nsys);
+              vstride, st, flags, ctr, nsys, spin);
 }
 
 template void launch_lsweep_tiles<double>(const DevSchedule &, const double *, size_t, const double *, double *,
                                           size_t, bool, const double *, const double *, double *, SysState *,
-                                          int32_t *, SweepCtr *, int, int, hipStream_t, hipEvent_t, hipEvent_t);
+                                          int32_t *, SweepCtr *, int, int, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_lsweep_tiles<float>(const DevSchedule &, const float *, size_t, const double *, float *,
                                          size_t, bool, const double *, const double *, double *, SysState *,
-                                         int32_t *, SweepCtr *, int, int, hipStream_t, hipEvent_t, hipEvent_t);
+                                         int32_t *, SweepCtr *, int, int, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_usweep_tiles<double>(const DevSchedule &, const double *, size_t, const double *, size_t,
                                           const double *, double *, size_t, SysState *, int32_t *, SweepCtr *, int,
-                                          int, hipStream_t, hipEvent_t, hipEvent_t);
+                                          int, int, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_usweep_tiles<float>(const DevSchedule &, const float *, size_t, const float *, size_t,
                                          const float *, double *, size_t, SysState *, int32_t *, SweepCtr *, int,
-                                         int, hipStream_t, hipEvent_t, hipEvent_t);
+                                         int, int, hipStream_t, hipEvent_t, hipEvent_t);
 
 // ev0 / ev1 (optional): events the dispatch itself records at the SpMV
 // kernel's start and end (kernel time only, no launch overhead).

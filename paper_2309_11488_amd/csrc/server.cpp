@@ -60,6 +60,7 @@ struct Pattern {
     size_t inst_bytes = 0, an_bytes = 0;
     std::vector<Instance *> inst;   // resident instances and those being created
     bool tuned = false;             // a tuner ran or runs; `opts` valid once opts_version > 0
+    bool tune_done = false;         // the tuner has ended (requests of the pattern wait for it)
     int opts_version = 0;
     int32_t opts[5] = {};           // spmv variant, sweep variant, sweep tiles, sweep grid, reduce split
 };
@@ -123,7 +124,7 @@ struct rs_server {
     server_config cfg{};
     int device = 0;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done, cv_ready;
+    std::condition_variable cv_work, cv_done, cv_ready, cv_tuned;
     std::deque<Request *> queue;
     std::unordered_map<int64_t, Request *> live;
     std::vector<Pattern *> patterns;
@@ -285,6 +286,19 @@ static void slot_main(rs_server *S, Slot *sl) {
             }
             S->cv_ready.notify_all();
         }
+        // with autotune, the first request of a pattern tunes it; the others
+        // wait here until the tuner has ended, so every result of the
+        // pattern comes from the same launch configuration
+        bool tune = false;
+        if (st == RS_OK && S->cfg.autotune) {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (!P->tuned) {
+                P->tuned = true;          // one tuner per pattern
+                tune = true;
+            } else {
+                S->cv_tuned.wait(lk, [&] { return P->tune_done; });
+            }
+        }
         int32_t opts[5];
         int version = 0;
         {
@@ -307,28 +321,26 @@ static void slot_main(rs_server *S, Slot *sl) {
         }
         const Clock::time_point t2 = Clock::now();
         r->timing.factor_ms = ms_between(t1, t2);
-        bool tune = false;
-        if (st == RS_OK && S->cfg.autotune) {
-            std::lock_guard<std::mutex> lk(S->mu);
-            if (!P->tuned) {
-                P->tuned = true;          // one tuner per pattern; other instances keep defaults until it ends
-                tune = true;
-            }
-        }
         if (tune) {
+            // a factorisation that failed tunes nothing; the waiting requests
+            // then keep the default configuration
             rs_tune_result tr{};
-            const int ts = ilu0_autotune(I->M, I->A, r->b, r->mem, r->reduction, 1, sl->stream, &tr);
-            if (ts == RS_OK) {
+            const int ts = st == RS_OK ? ilu0_autotune(I->M, I->A, r->b, r->mem, r->reduction, 1, sl->stream, &tr)
+                                       : st;
+            {
                 std::lock_guard<std::mutex> lk(S->mu);
-                P->opts[0] = tr.spmv_variant;
-                P->opts[1] = tr.sweep_variant;
-                P->opts[2] = tr.sweep_tiles;
-                P->opts[3] = tr.sweep_grid;
-                P->opts[4] = tr.reduce_split;
-                I->opts_version = ++P->opts_version;
-            } else if (hard_error(ts)) {
-                st = ts;
+                if (ts == RS_OK) {
+                    P->opts[0] = tr.spmv_variant;
+                    P->opts[1] = tr.sweep_variant;
+                    P->opts[2] = tr.sweep_tiles;
+                    P->opts[3] = tr.sweep_grid;
+                    P->opts[4] = tr.reduce_split;
+                    I->opts_version = ++P->opts_version;
+                }
+                P->tune_done = true;
             }
+            S->cv_tuned.notify_all();
+            if (ts != RS_OK && hard_error(ts)) st = ts;
         }
         const Clock::time_point t3 = Clock::now();
         r->timing.tune_ms = ms_between(t2, t3);
@@ -369,7 +381,7 @@ extern "C" {
 
 int server_create(const server_config *cfg, server_t *out) {
     if (!cfg || !out || cfg->max_slots < 1 || cfg->max_slots > 64 || cfg->hbm_budget_bytes == 0 ||
-        cfg->ordering < 0 || cfg->ordering > 2 || (cfg->precision != RS_PREC_FP64 && cfg->precision != RS_PREC_FP32_FACTORS))
+        cfg->ordering < 0 || cfg->ordering > RS_ORDER_RCM_LEVEL_SET || (cfg->precision != RS_PREC_FP64 && cfg->precision != RS_PREC_FP32_FACTORS))
         return RS_INVALID_ARG;
     *out = nullptr;
     rs_server *S = new rs_server();
@@ -501,6 +513,10 @@ int server_wait(server_t S, int64_t ticket, solve_info *info, server_timing *tim
 
 int server_get_stats(server_t S, server_stats *out) {
     if (!S || !out) return RS_INVALID_ARG;
+    size_t fr = 0, tot = 0;
+    if (hipSetDevice(S->device) != hipSuccess || hipMemGetInfo(&fr, &tot) != hipSuccess) fr = tot = 0;
+    out->device_used_bytes = tot - fr;
+    out->device_total_bytes = tot;
     std::lock_guard<std::mutex> lk(S->mu);
     out->queued = (int64_t)S->queue.size();
     out->running = S->running;

@@ -37,7 +37,8 @@ def test_status_strings():
     assert rs.status_string(12345) == "unknown status"
 
 
-@pytest.mark.parametrize("ordering", [rs.ORDER_NATURAL, rs.ORDER_LEVEL_SET, rs.ORDER_GRAPH_COLOUR])
+@pytest.mark.parametrize("ordering", [rs.ORDER_NATURAL, rs.ORDER_LEVEL_SET, rs.ORDER_GRAPH_COLOUR,
+                                      rs.ORDER_RCM_LEVEL_SET])
 @pytest.mark.parametrize("case", ["c1", "mask_nnc", "c2", "random", "hub", "mask_only"])
 def test_host_ordering_matches_oracle(ordering, case):
     if case == "c1":
@@ -71,6 +72,9 @@ def test_host_ordering_matches_oracle(ordering, case):
     elif ordering == rs.ORDER_GRAPH_COLOUR:
         nc, _, operm = oracle.dsatur_colour(s.rowptr, s.colidx)
         assert ns == nc
+    elif ordering == rs.ORDER_RCM_LEVEL_SET:
+        nl, _, operm = oracle.rcm_levels(s.rowptr, s.colidx)
+        assert ns == nl
     else:
         operm = np.arange(s.n, dtype=np.int32)
         assert ns == s.n
@@ -100,7 +104,7 @@ def test_host_analysis_nonsymmetric_pattern():
     # (0,2) present without (2,0): orderings still valid permutations
     rowptr = np.array([0, 2, 4, 5], np.int32)
     colidx = np.array([0, 2, 0, 1, 2], np.int32)
-    for ordering in (0, 1, 2):
+    for ordering in (0, 1, 2, 3):
         st, perm, ns, _ = rs.ilu0_analyse_host(rowptr, colidx, ordering)
         assert st == rs.OK
         assert sorted(perm.tolist()) == [0, 1, 2]

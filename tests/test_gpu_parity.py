@@ -15,11 +15,12 @@ import pytest
 import oracle
 import paper_2309_11488_amd as rs
 from synth import config_system, make_ensemble, make_grid_system
-from tests.helpers import chain_pattern, dense_pattern, random_values
+from tests.helpers import (BREAKDOWN_CASES, breakdown_as_well, chain_pattern, dense_pattern,
+                           fp32_apply_bound, outcome, random_values, trajectory_check)
 
 pytestmark = pytest.mark.gpu
 
-ORDERINGS = [rs.ORDER_NATURAL, rs.ORDER_LEVEL_SET, rs.ORDER_GRAPH_COLOUR]
+ORDERINGS = [rs.ORDER_NATURAL, rs.ORDER_LEVEL_SET, rs.ORDER_GRAPH_COLOUR, rs.ORDER_RCM_LEVEL_SET]
 
 
 def cases():
@@ -150,12 +151,20 @@ def test_apply_parity(solver_of, name, ordering, precision):
     v = np.random.default_rng(3).standard_normal((1, s.n, 3))
     z = rs.ilu0_apply(M, v)
     perm, prow, pcol, pv, _, _, lu, dinv = oracle_factors(s, ordering)
-    f = oracle.apply if precision == rs.PREC_FP64 else oracle.apply_f32
-    zp = f(prow, pcol, lu, dinv, v[0][perm])
-    zo = np.empty_like(zp)
-    zo[perm] = zp
-    tol = 1e-12 if precision == rs.PREC_FP64 else 1e-5
-    assert np.linalg.norm(z[0] - zo) <= tol * np.linalg.norm(zo)
+    if precision == rs.PREC_FP64:
+        zp = oracle.apply(prow, pcol, lu, dinv, v[0][perm])
+        zo = np.empty_like(zp)
+        zo[perm] = zp
+        assert np.linalg.norm(z[0] - zo) <= 1e-12 * np.linalg.norm(zo)
+    else:
+        # FP32 factors, input and arithmetic on both sides, in different
+        # orders of rounding (the GPU fuses multiply-adds): element by
+        # element within the first-order FP32 error bound of two such
+        # evaluations of the same rounded data
+        zp = oracle.apply_f32(prow, pcol, lu, dinv, v[0][perm])
+        r32 = [a.astype(np.float32).astype(np.float64) for a in (lu, dinv, v[0][perm])]
+        bound = fp32_apply_bound(prow, pcol, *r32)
+        assert np.all(np.abs(z[0][perm] - zp) <= bound)
 
 
 def test_fp32_factors_are_rounded_fp64_factors(solver_of):
@@ -203,7 +212,7 @@ def test_sweep_modes_agree(solver_of, name, ordering, tiles):
     rs.ilu0_set_option(M, rs.OPT_SWEEP_TILES, 1 - tiles)
     z2 = rs.ilu0_apply(M, v)
     x2, st2, info2 = rs.bicgstab_solve(M, A, s.b[0], reduction=1e-8)
-    assert np.array_equal(z, z2) and np.array_equal(x, x2) and info == info2
+    assert np.array_equal(z, z2) and np.array_equal(x, x2) and outcome(info) == outcome(info2)
 
 
 @pytest.mark.parametrize("precision", [rs.PREC_FP64, rs.PREC_FP32_FACTORS])
@@ -220,7 +229,7 @@ def test_graph_replays_equal_eager(solver_of, ordering, precision):
         for k in range(3):
             x, st, info = rs.bicgstab_solve(M, A, s.b[:, 0] * (k + 1), reduction=1e-9)
             rs.ilu0_apply(M, s.b[0, 0][None])           # eager work between replays
-            assert np.array_equal(x, ref[k][0]) and info == ref[k][2]
+            assert np.array_equal(x, ref[k][0]) and outcome(info) == outcome(ref[k][2])
     rs.ilu0_set_option(M, rs.OPT_SWEEP_TILES, 1 - rs.ilu0_get_option(M, rs.OPT_SWEEP_TILES))
     x, st, info = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-9)   # recaptured
     assert np.array_equal(x, ref[0][0])
@@ -229,7 +238,7 @@ def test_graph_replays_equal_eager(solver_of, ordering, precision):
     try:
         for k in range(3):
             x, st, info = rs.bicgstab_solve(M, A, s.b[:, 0] * (k + 1), reduction=1e-9)
-            assert np.array_equal(x, ref[k][0]) and info == ref[k][2]
+            assert np.array_equal(x, ref[k][0]) and outcome(info) == outcome(ref[k][2])
         ms, units, byts = rs.rsolve_profile_get(rs.PROF_SPMV_V)
         assert units > 0 and ms > 0 and byts > 0
     finally:
@@ -259,12 +268,12 @@ def test_row_variants(solver_of, precision):
         z = rs.ilu0_apply(M, x)
         xs, st, info = rs.bicgstab_solve(M, A, s.b[0], reduction=1e-9)
         ref = (z, xs, info) if ref is None else ref
-        assert np.array_equal(z, ref[0]) and np.array_equal(xs, ref[1]) and info == ref[2], v
+        assert np.array_equal(z, ref[0]) and np.array_equal(xs, ref[1]) and outcome(info) == outcome(ref[2]), v
     for v in range(rs.N_ROW_VARIANTS):
         rs.ilu0_set_option(M, rs.OPT_SPMV_VARIANT, v)
         xs, st, info = rs.bicgstab_solve(M, A, s.b[0], reduction=1e-9)
         xs2, _, info2 = rs.bicgstab_solve(M, A, s.b[0], reduction=1e-9)
-        assert np.array_equal(xs, xs2) and info == info2, v
+        assert np.array_equal(xs, xs2) and outcome(info) == outcome(info2), v
         # FP32 sweeps round the rounding differences of alpha and omega once more
         tol = 1e-10 if precision == rs.PREC_FP64 else 1e-7
         assert np.linalg.norm(xs - ref[1]) <= tol * np.linalg.norm(ref[1]), v
@@ -345,7 +354,7 @@ def test_repeat_solve_bitwise(solver_of):
     A, M, _, _ = solver_of(s, rs.ORDER_GRAPH_COLOUR)
     x1, _, i1 = rs.bicgstab_solve(M, A, s.b[0], reduction=1e-8)
     x2, _, i2 = rs.bicgstab_solve(M, A, s.b[0], reduction=1e-8)
-    assert np.array_equal(x1, x2) and i1 == i2
+    assert np.array_equal(x1, x2) and outcome(i1) == outcome(i2)
 
 
 def test_status_paths(solver_of):
@@ -584,7 +593,7 @@ def test_graph_recaptured_for_every_setting(solver_of):
         xe, ste, ie = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-10)
         rs.ilu0_set_option(M, rs.OPT_USE_GRAPH, 1)
         xg, stg, ig = rs.bicgstab_solve(M, A, s.b[:, 0], reduction=1e-10)
-        assert ste == stg == rs.OK and np.array_equal(xe, xg) and ie == ig, (sweep, split)
+        assert ste == stg == rs.OK and np.array_equal(xe, xg) and outcome(ie) == outcome(ig), (sweep, split)
 
 
 def test_device_memory_path():
@@ -611,7 +620,7 @@ def test_device_memory_path():
         rs.bcsr_destroy(A)
 
 
-@pytest.mark.parametrize("ordering", [rs.ORDER_GRAPH_COLOUR, rs.ORDER_LEVEL_SET])
+@pytest.mark.parametrize("ordering", [rs.ORDER_GRAPH_COLOUR, rs.ORDER_LEVEL_SET, rs.ORDER_RCM_LEVEL_SET])
 def test_c2_full_size_parity(solver_of, ordering):
     """The 46x112x22 masked grid with 2% NNCs at full size: factors on sampled
     rows, and the solution at 1e-10 for the first right-hand side."""

@@ -10,7 +10,7 @@ from synth import make_ensemble, make_grid_system, make_wells
 
 pytestmark = pytest.mark.gpu
 
-ORDERINGS = [rs.ORDER_NATURAL, rs.ORDER_LEVEL_SET, rs.ORDER_GRAPH_COLOUR]
+ORDERINGS = [rs.ORDER_NATURAL, rs.ORDER_LEVEL_SET, rs.ORDER_GRAPH_COLOUR, rs.ORDER_RCM_LEVEL_SET]
 
 
 def system():
