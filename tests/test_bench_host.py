@@ -25,12 +25,46 @@ def test_traffic_is_reported_only_for_the_measured_kernels(monkeypatch):
     import bench
     with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
         rec = json.load(fh)
-    assert {"c2:lsweep", "c3:spmv", "c4:factor"} <= set(rec)
-    key = "c2:lsweep"
-    monkeypatch.setattr(bench, "kernel_source_digest", lambda: rec[key]["kernel_digest"])
-    assert bench.measured_traffic("c2", "lsweep") == rec[key]["bytes_per_unit"] > 0
-    monkeypatch.setattr(bench, "kernel_source_digest", lambda: "0" * 16)
-    assert bench.measured_traffic("c2", "lsweep") is None
+    assert rec
+    for key, ent in rec.items():
+        wl, cls = key.split(":")
+        monkeypatch.setattr(bench, "kernel_source_digest", lambda: ent["kernel_digest"])
+        assert bench.measured_traffic(wl, cls) == ent["bytes_per_unit"] > 0
+        monkeypatch.setattr(bench, "kernel_source_digest", lambda: "0" * 16)
+        assert bench.measured_traffic(wl, cls) is None
+
+
+def test_method_bytes_follow_the_byte_model():
+    """The algorithmic bytes bench.py divides by time: SpMV 76 nnzb + 52 N,
+    application 76 nnzb + 100 N (FP64 factors) or 40 nnzb + 100 N (FP32),
+    one iteration 304 nnzb + 712 N resp. 232 nnzb + 712 N, factorisation
+    148 nnzb."""
+    sys.path.insert(0, ROOT)
+    import bench
+    n, nnzb = 1_000_000, 6_940_000
+    m = bench.method_bytes(n, nnzb, "fp64")
+    assert m["spmv"] == 76 * nnzb + 52 * n and m["apply"] == 76 * nnzb + 100 * n and m["factor"] == 148 * nnzb
+    assert m["iteration"] == 304 * nnzb + 712 * n
+    m = bench.method_bytes(n, nnzb, "fp32")
+    assert m["apply"] == 40 * nnzb + 100 * n and m["iteration"] == 232 * nnzb + 712 * n
+
+
+def test_default_run_is_the_large_grid_in_fp64():
+    """With no flags bench.py measures the 100^3 grid with plain FP64 factors
+    at a reduction of 1e-2 (the mixed-precision and 1e-6 runs ride along)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    a = bench.parse([])
+    assert a.workload == "c3" and a.precision is None and a.reduction is None and a.steps == 20
+    wl = bench.WORKLOADS["c3"]
+    assert wl["precision"] == "fp64" and wl["reduction"] == 1e-2 and "100x100x100" in wl["desc"]
+
+
+def test_host_cpu_is_described():
+    sys.path.insert(0, ROOT)
+    import bench
+    h = bench.host_cpu()
+    assert h["nproc"] >= 1 and h["usable_cpus"] >= 1
 
 
 @pytest.mark.parametrize("workload", ["c1", "c2", "c3", "c4", "c5"])
@@ -38,31 +72,3 @@ def test_workload_descriptions(workload):
     sys.path.insert(0, ROOT)
     import bench
     assert workload in bench.WORKLOADS and bench.WORKLOADS[workload]["desc"]
-
-
-def test_rcm_renumbering_is_a_similarity():
-    """bench.py --pre rcm hands the solver P A P^T and P b (P from reverse
-    Cuthill-McKee): products with the renumbered matrix are the original's,
-    renumbered."""
-    import numpy as np
-    import scipy.sparse as sp
-    from scipy.sparse.csgraph import reverse_cuthill_mckee
-
-    sys.path.insert(0, ROOT)
-    import bench
-    import oracle
-    from synth import make_grid_system
-
-    s = make_grid_system(9, 8, 6, active_frac=0.9, nnc_frac=0.03, seed=21, n_rhs=2)
-    r = bench.rcm_renumbered(s)
-    perm = reverse_cuthill_mckee(sp.csr_matrix((np.ones(s.nnzb), s.colidx, s.rowptr), shape=(s.n, s.n)),
-                                 symmetric_mode=True)
-    assert r.nnzb == s.nnzb and np.all(np.diff(r.rowptr) >= 1)
-    for i in range(r.n):
-        row = r.colidx[r.rowptr[i]:r.rowptr[i + 1]]
-        assert np.all(np.diff(row) > 0)
-    x = np.random.default_rng(22).standard_normal((s.n, 3))
-    y = oracle.spmv(s.rowptr, s.colidx, s.vals[0], x)
-    y2 = oracle.spmv(r.rowptr, r.colidx, r.vals[0], x[perm])
-    assert np.allclose(y2, y[perm], rtol=1e-13, atol=1e-12)
-    assert np.array_equal(r.b, s.b[:, :, perm])
