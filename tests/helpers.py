@@ -102,8 +102,11 @@ TIMING_KEYS = ("factor_ms", "solve_ms")
 
 
 def outcome(info):
-    """A solve's per-system results without its device timings, which differ
-    from run to run (compare these when results must be bitwise equal)."""
+    """A solve's per-system results (a list of info dicts, or one dict)
+    without its device timings, which differ from run to run (compare these
+    when results must be bitwise equal)."""
+    if isinstance(info, dict):
+        info = [info]
     return [{k: v for k, v in i.items() if k not in TIMING_KEYS} for i in info]
 
 

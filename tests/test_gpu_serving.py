@@ -129,6 +129,44 @@ def test_autotuned_server_matches_oracle():
             assert st == rs.OK and np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
 
 
+def test_autotuned_results_same_alone_and_in_the_mix():
+    """With the launch-shape autotuner on (the benchmark's serving setup),
+    requests of a pattern wait until its tuner has ended, so every request of
+    the pattern runs one launch configuration: each request's result is the
+    same bit for bit whether it ran alone (submitted and collected one at a
+    time) or in a mix of concurrent requests on the same server."""
+    reqs = requests(20)
+    with rs.Server(max_slots=4, ordering=rs.ORDER_GRAPH_COLOUR, autotune=True) as srv:
+        pid = register(srv, SYS)
+        alone = []
+        for s in reqs:
+            t = srv.submit(pid[id(s)], s.vals[0], s.b[0, 0], reduction=1e-8)
+            alone.append(srv.wait(t))
+        tickets = [srv.submit(pid[id(s)], s.vals[0], s.b[0, 0], reduction=1e-8) for s in reqs]
+        mixed = [srv.wait(t) for t in tickets]
+    assert len({g[3]["slot"] for g in mixed}) > 1
+    for (x1, st1, i1, _), (x2, st2, i2, _) in zip(alone, mixed):
+        assert st1 == st2 == rs.OK
+        assert np.array_equal(x1, x2) and outcome(i1) == outcome(i2)
+
+
+def test_one_million_cell_request_matches_oracle():
+    """A request of the largest size class (the 100^3 grid, sigma 2)
+    through the server, FP64 factors, reduction 1e-10: x within 1e-8 of the
+    oracle's solution under the same ordering."""
+    s = config_system("c3")
+    b = s.b[0, 0]
+    with rs.Server(max_slots=2, ordering=rs.ORDER_GRAPH_COLOUR, precision=rs.PREC_FP64) as srv:
+        p = srv.add_pattern(s.rowptr, s.colidx)
+        x, st, info, tm = srv.wait(srv.submit(p, s.vals[0], b, reduction=1e-10))
+    assert st == rs.OK and info["true_rel_residual"] <= 1e-9
+    xo, oinfo = oracle.solve(s.rowptr, s.colidx, s.vals[0], b, ordering=rs.ORDER_GRAPH_COLOUR, reduction=1e-10)
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    print(f"1M-cell request: rel err vs oracle {err:.2e}, half steps {info['half_steps']} "
+          f"(oracle {oinfo['half_steps']}), total {tm['total_ms']:.1f} ms")
+    assert err <= 1e-8
+
+
 def test_bad_pattern_and_unknown_pattern_are_rejected():
     s = SYS[0]
     with rs.Server(max_slots=1) as srv:
