@@ -638,6 +638,12 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
             acc = (T)in[k];
         }
     }
+    // inv(U_ii) of a row the launch finishes is requested before the walk
+    T dq[3] = {0, 0, 0};
+    if (uq < u0_end) {
+        const T *dp = Dinv + (size_t)sys * d_stride + (size_t)uq * 9 + 3 * rl.r;
+        dq[0] = dp[0]; dq[1] = dp[1]; dq[2] = dp[2];
+    }
     acc = row_walk<W, STAGE, kSweepCapPerWave, true>(d.lptr, d.lcol, L + (size_t)sys * l_stride, qb0, qb1, rl, y + vo,
                                                      acc);
     if (FUSE_P) {
@@ -650,10 +656,7 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
         // rows without upper blocks (the first level of the upper sweep)
         // finish here: z_i = inv(U_ii) y_i, the arithmetic of k_usweep
         const T t0 = __shfl(acc, rl.base, 64), t1 = __shfl(acc, rl.base + 1, 64), t2 = __shfl(acc, rl.base + 2, 64);
-        if (uq < u0_end) {
-            const T *dq = Dinv + (size_t)sys * d_stride + (size_t)uq * 9 + 3 * rl.r;
-            z[vo + 3 * (size_t)i + rl.r] = (double)dot3(dq[0], dq[1], dq[2], t0, t1, t2);
-        }
+        if (uq < u0_end) z[vo + 3 * (size_t)i + rl.r] = (double)dot3(dq[0], dq[1], dq[2], t0, t1, t2);
     }
 }
 
@@ -674,13 +677,18 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
     const size_t vo = (size_t)sys * vstride;
     const int i = rl.act ? d.urows[rl.q] : 0;
     T acc = rl.act ? y[vo + 3 * (size_t)i + rl.r] : (T)0;
+    // inv(U_ii) is requested before the walk
+    T dq[3] = {0, 0, 0};
+    if (rl.act) {
+        const T *dp = Dinv + (size_t)sys * d_stride + (size_t)rl.q * 9 + 3 * rl.r;
+        dq[0] = dp[0]; dq[1] = dp[1]; dq[2] = dp[2];
+    }
     acc = row_walk<W, STAGE, kSweepCapPerWave, true>(d.uptr, d.ucol, U + (size_t)sys * u_stride, qb0, qb1, rl, z + vo,
                                                      acc);
     asm volatile("" ::"v"(acc));
     if (!run) return;
     const T t0 = __shfl(acc, rl.base, 64), t1 = __shfl(acc, rl.base + 1, 64), t2 = __shfl(acc, rl.base + 2, 64);
     if (!rl.act) return;
-    const T *dq = Dinv + (size_t)sys * d_stride + (size_t)rl.q * 9 + 3 * rl.r;
     const T zr = dot3(dq[0], dq[1], dq[2], t0, t1, t2);
     z[vo + 3 * (size_t)i + rl.r] = (double)zr;
 }
