@@ -304,6 +304,27 @@ int ilu0_get_factors(ilu0_t M, int32_t sys, double *lu, double *dinv);
 int ilu0_apply(ilu0_t M, const double *v, double *z, int32_t first_sys, int32_t n_sys, int32_t mem,
                void *stream);
 
+/* ilu0_apply_noalloc -- ilu0_apply for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and the same results bit for bit,
+ * with v and z device pointers (caller order, n_sys * n_brows * 3 doubles,
+ * caller-owned) and every intermediate (the new-order input and output, the
+ * lower sweep's y, the single-launch sweeps' tile flags and counters) in a
+ * fixed workspace of RS_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each GPU it runs on until the process ends.  Calls no hipMalloc, hipFree
+ * or allocating library routine.  n_sys systems of n_brows block rows need
+ * about 72 * n_brows * n_sys bytes (3 vectors) plus 8 bytes per sweep tile:
+ * up to about 1.1M block rows for one system; larger calls return
+ * RS_OUT_OF_MEMORY with the sizes in rsolve_last_error().  Every call on a
+ * GPU shares that GPU's workspace, whatever the handle: calls that overlap
+ * on one GPU (two streams, two host threads) race and must be ordered by
+ * the caller.  Stream-ordered; with single-launch sweeps on
+ * (RS_OPT_SWEEP_TILES) it also synchronises `stream` to read the sweeps'
+ * error word (RS_HIP_ERROR when a dependency wait gave up), so only the
+ * per-level sweeps may be captured in a graph.  Errors as ilu0_apply. */
+#define RS_NOALLOC_SCRATCH_BYTES (80u << 20)
+int ilu0_apply_noalloc(ilu0_t M, const double *v, double *z, int32_t first_sys, int32_t n_sys, void *stream);
+
 /* bicgstab_solve -- BiCGStab (Section "Bicgstab solver": the Krylov solver
  * of the simulator, relative residual reduction 1e-2 and 200 iterations by
  * default) right-preconditioned by the factors of the last ilu0_factor

@@ -31,7 +31,7 @@ N_ROW_VARIANTS = 9
 EXPORTS = (
     "bcsr_create", "bcsr_set_values", "bcsr_set_wells", "bcsr_get_dims", "bcsr_spmv", "bcsr_set_option", "bcsr_destroy", "ilu0_analyse",
     "ilu0_get_schedule", "ilu0_get_sweep_levels", "ilu0_set_option", "ilu0_get_option", "ilu0_autotune",
-    "ilu0_factor", "ilu0_get_factors", "ilu0_apply",
+    "ilu0_factor", "ilu0_get_factors", "ilu0_apply", "ilu0_apply_noalloc",
     "bicgstab_solve", "gmres_solve", "ilu0_destroy", "ilu0_analyse_host", "rsolve_profile_enable", "rsolve_profile_set_mask", "rsolve_profile_get",
     "ilu0_analyse_shared", "ilu0_analyse_jacobi", "bcsr_partition", "server_create", "server_request_bytes", "server_analysis_bytes", "server_add_pattern",
     "server_submit", "server_poll", "server_wait", "server_get_stats",
@@ -128,6 +128,7 @@ def lib():
         L.ilu0_autotune.argtypes = [vp, vp, vp, i32, dbl, i32, vp, ct.POINTER(TuneResult)]
         L.ilu0_get_factors.argtypes = [vp, i32, vp, vp]
         L.ilu0_apply.argtypes = [vp, vp, vp, i32, i32, i32, vp]
+        L.ilu0_apply_noalloc.argtypes = [vp, vp, vp, i32, i32, vp]
         L.bicgstab_solve.argtypes = [vp, vp, vp, vp, dbl, i32, i32, vp, vp]
         L.gmres_solve.argtypes = [vp, vp, vp, vp, i32, dbl, i32, i32, vp, vp]
         L.ilu0_destroy.argtypes = [vp]
@@ -378,6 +379,16 @@ def ilu0_apply(M, v, z=None, first_sys=0, n_sys=1, *, stream=None):
             z = np.zeros_like(v)
     mem, (vp, zp) = _mem_ptr(v, z)
     _check(lib().ilu0_apply(M, vp, zp, first_sys, n_sys, mem, _stream(stream)), "ilu0_apply")
+    return z
+
+
+def ilu0_apply_noalloc(M, v, z, first_sys=0, n_sys=1, *, stream=None):
+    """ilu0_apply with every intermediate in the library's fixed per-GPU
+    workspace (no device allocation): v and z are device tensors."""
+    if not (_is_torch(v) and _is_torch(z)):
+        raise TypeError("ilu0_apply_noalloc: v and z must be CUDA tensors")
+    _, (vp, zp) = _mem_ptr(v, z)
+    _check(lib().ilu0_apply_noalloc(M, vp, zp, first_sys, n_sys, _stream(stream)), "ilu0_apply_noalloc")
     return z
 
 

@@ -9,6 +9,7 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <sstream>
 #include <cstdio>
 #include <cstdlib>
@@ -949,11 +950,11 @@ static double upper_bytes(ilu0_t M, double tb, int nsys) {
 // order).  Timed as one unit (events around its launches).
 template <typename T>
 static void lower_levels(ilu0_t M, const T *L, const T *D, const double *in, double *out, bool fuse_p, Krylov &k,
-                         SysState *st, int nsys, hipStream_t s) {
+                         SysState *st, int nsys, hipStream_t s, bool prof = true) {
     const rs::Schedule &S = M->an->sch;
     const size_t vs = k.vstride;
     T *y = (T *)k.y;
-    ProfScope ps(PC_LSWEEP, s, lower_bytes(M, sizeof(T), nsys), M->tile_sweeps);
+    ProfScope ps(PC_LSWEEP, s, lower_bytes(M, sizeof(T), nsys), M->tile_sweeps, prof);
     if (M->tile_sweeps) {
         rs::launch_lsweep_tiles<T>(M->an->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, k.lflags,
                                    k.lctr, nsys, M->sweep_grid, M->spin_limit, s, ps.start(), ps.stop());
@@ -971,11 +972,11 @@ static void lower_levels(ilu0_t M, const T *L, const T *D, const double *in, dou
 // as one unit.
 template <typename T>
 static void upper_levels(ilu0_t M, const T *U, const T *D, double *out, bool fuse_p, Krylov &k, SysState *st,
-                         int nsys, hipStream_t s) {
+                         int nsys, hipStream_t s, bool prof = true) {
     const rs::Schedule &S = M->an->sch;
     const size_t vs = k.vstride;
     const T *y = (const T *)k.y;
-    ProfScope ps(PC_USWEEP, s, upper_bytes(M, sizeof(T), nsys), M->tile_sweeps);
+    ProfScope ps(PC_USWEEP, s, upper_bytes(M, sizeof(T), nsys), M->tile_sweeps, prof);
     if (M->tile_sweeps) {
         rs::launch_usweep_tiles<T>(M->an->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, k.uflags,
                                    k.uctr, nsys, M->sweep_grid, M->spin_limit, s, ps.start(), ps.stop());
@@ -989,11 +990,11 @@ static void upper_levels(ilu0_t M, const T *U, const T *D, double *out, bool fus
 // One preconditioner application M^{-1} in -> out (new order), all levels.
 template <typename T>
 static void apply_levels(ilu0_t M, const T *L, const T *U, const T *D, const double *in, double *out, bool fuse_p,
-                         Krylov &k, SysState *st, int nsys, hipStream_t s) {
+                         Krylov &k, SysState *st, int nsys, hipStream_t s, bool prof = true) {
     const double tb = sizeof(T);
-    ProfScope ps(PC_APPLY, s, lower_bytes(M, tb, nsys) + upper_bytes(M, tb, nsys));
-    lower_levels<T>(M, L, D, in, out, fuse_p, k, st, nsys, s);
-    upper_levels<T>(M, U, D, out, fuse_p, k, st, nsys, s);
+    ProfScope ps(PC_APPLY, s, lower_bytes(M, tb, nsys) + upper_bytes(M, tb, nsys), false, prof);
+    lower_levels<T>(M, L, D, in, out, fuse_p, k, st, nsys, s, prof);
+    upper_levels<T>(M, U, D, out, fuse_p, k, st, nsys, s, prof);
 }
 
 // Parts of a BiCGStab iteration, in order: the two sweeps of the first
@@ -1193,6 +1194,120 @@ int ilu0_apply(ilu0_t M, const double *v, double *z, int32_t first_sys, int32_t 
     HIP_TRY(hipGetLastError());
     if (mem != RS_MEM_DEVICE) HIP_TRY(hipMemcpyAsync(z, zd, m * sizeof(double), hipMemcpyDeviceToHost, s));
     return sweep_error(M, s);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------ allocation-free apply
+
+// Workspace of ilu0_apply_noalloc: one file-scope array per GPU, held until
+// the process ends.  On the host, `scratch` names a stand-in, not device
+// memory: host code uses only the address hipGetSymbolAddress returns for
+// the current device (noalloc_scratch), never the name itself.
+static __device__ __align__(256) unsigned char scratch[RS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's `scratch`, looked up once per
+// device with that device current.
+int noalloc_scratch(unsigned char **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(RS_HIP_ERROR, "ilu0_apply_noalloc: device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(RS_HIP_ERROR, "ilu0_apply_noalloc: no device address for the workspace");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (unsigned char *)g_scratch_ptr[dev];
+    return RS_OK;
+}
+
+// Carving of the workspace for n_sys systems of M: the new-order input, the
+// lower sweep's y, the new-order output (each n_sys * vstride doubles), the
+// single-launch sweeps' tile flags, and their two counters; each part
+// 256-byte aligned.
+struct NoAllocLayout {
+    size_t vin, y, vout, flags, ctrs, end, nflags;
+};
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+NoAllocLayout noalloc_layout(const rs_ilu0 *M, int n_sys) {
+    NoAllocLayout l{};
+    const size_t vec = align256((size_t)n_sys * rs::vec_stride(M->n) * sizeof(double));
+    l.nflags = (size_t)n_sys * ((size_t)M->an->sch.ltiles.n + M->an->sch.utiles.n);
+    l.vin = 0;
+    l.y = vec;
+    l.vout = 2 * vec;
+    l.flags = 3 * vec;
+    l.ctrs = l.flags + align256(l.nflags * sizeof(int32_t));
+    l.end = l.ctrs + align256(2 * sizeof(rs::SweepCtr));
+    return l;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ilu0_apply_noalloc(ilu0_t M, const double *v, double *z, int32_t first_sys, int32_t n_sys, void *stream) {
+    if (!M || !v || !z || first_sys < 0 || n_sys < 0 || first_sys + n_sys > M->batch)
+        return fail(RS_INVALID_ARG, "ilu0_apply_noalloc: bad arguments");
+    if (!M->factored) return fail(RS_NOT_FACTORED, "ilu0_apply_noalloc: not factored");
+    if (n_sys == 0 || M->n == 0) return RS_OK;
+    const NoAllocLayout lay = noalloc_layout(M, n_sys);
+    if (lay.end > (size_t)RS_NOALLOC_SCRATCH_BYTES)
+        return fail(RS_OUT_OF_MEMORY, "ilu0_apply_noalloc: " + std::to_string(n_sys) + " system(s) of " +
+                                          std::to_string(M->n) + " block rows need " + std::to_string(lay.end) +
+                                          " bytes of workspace, above its fixed size of " +
+                                          std::to_string((size_t)RS_NOALLOC_SCRATCH_BYTES));
+    unsigned char *base = nullptr;
+    int st = noalloc_scratch(&base);
+    if (st != RS_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Krylov k{};
+    k.vstride = rs::vec_stride(M->n);
+    double *vin = (double *)(base + lay.vin), *vout = (double *)(base + lay.vout);
+    k.y = base + lay.y;
+    k.lflags = (int32_t *)(base + lay.flags);
+    k.uflags = k.lflags + (size_t)n_sys * M->an->sch.ltiles.n;
+    k.lctr = (rs::SweepCtr *)(base + lay.ctrs);
+    k.uctr = k.lctr + 1;
+    // the workspace keeps the last call's contents (any handle's): the
+    // sweeps' epochs start again from zero
+    if (M->tile_sweeps)
+        rs::launch_fill_u32((uint32_t *)(base + lay.flags), (lay.end - lay.flags) / sizeof(uint32_t), 0u, s);
+    const rs::Schedule &S = M->an->sch;
+    rs::launch_permute_vec(M->an->dev.perm, v, vin, M->n, k.vstride, n_sys, false, s);
+    if (M->precision == RS_PREC_FP32_FACTORS)
+        apply_levels<float>(M, M->Lf.as<float>() + (size_t)first_sys * S.nL * 9,
+                            M->Uf.as<float>() + (size_t)first_sys * S.nU * 9,
+                            M->Dinvf.as<float>() + (size_t)first_sys * M->n * 9, vin, vout, false, k, nullptr,
+                            n_sys, s, false);
+    else
+        apply_levels<double>(M, M->L.as<double>() + (size_t)first_sys * S.nL * 9,
+                             M->U.as<double>() + (size_t)first_sys * S.nU * 9,
+                             M->Dinv.as<double>() + (size_t)first_sys * M->n * 9, vin, vout, false, k, nullptr,
+                             n_sys, s, false);
+    rs::launch_permute_vec(M->an->dev.perm, vout, z, M->n, k.vstride, n_sys, true, s);
+    HIP_TRY(hipGetLastError());
+    if (!M->tile_sweeps) return RS_OK;
+    // a single-launch sweep whose dependency wait gave up leaves its error word set
+    rs::SweepCtr c[2];
+    HIP_TRY(hipMemcpyAsync(c, k.lctr, sizeof c, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c[0].error || c[1].error) {
+        rs::launch_fill_u32((uint32_t *)(base + lay.flags), (lay.end - lay.flags) / sizeof(uint32_t), 0u, s);
+        HIP_TRY(hipStreamSynchronize(s));
+        return fail(RS_HIP_ERROR, "ilu0_apply_noalloc: sweep dependency wait exceeded its limit");
+    }
+    return RS_OK;
 }
 
 static int status_rank(int s) {

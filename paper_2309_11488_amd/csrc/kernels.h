@@ -269,6 +269,10 @@ void launch_gm_phase(const GmWork &g, int nsys, hipStream_t s);
 void launch_gm_restart(const GmWork &g, const double *rhs, const double *w, double *r, int n, int nsys,
                        hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
+// p[0 .. count) = value, by a kernel (no memset node when the stream is
+// being captured).
+void launch_fill_u32(uint32_t *p, size_t count, uint32_t value, hipStream_t s);
+
 // out[i] = in[perm[i]] (gather to the new order) and its inverse scatter;
 // the new-order side has stride vstride, the caller side 3n.
 void launch_permute_vec(const int32_t *perm, const double *in, double *out, int n, size_t vstride, int nsys,

@@ -1466,6 +1466,12 @@ __global__ void __launch_bounds__(kGmThreads) k_gm_restart(GmWork g, const doubl
     }
 }
 
+// p[0 .. count) = value.
+__global__ void k_fill_u32(uint32_t *__restrict__ p, size_t count, uint32_t value) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x)
+        p[e] = value;
+}
+
 // New-order side at stride vstride, caller side at stride 3n.
 __global__ void k_permute_vec(const int32_t *__restrict__ perm, const double *__restrict__ in,
                               double *__restrict__ out, int n, size_t vstride, int scatter) {
@@ -1707,6 +1713,11 @@ void launch_permute_vec(const int32_t *perm, const double *in, double *out, int 
     if (n <= 0 || nsys <= 0) return;
     k_permute_vec<<<dim3(copy_blocks(3 * (size_t)n), nsys), 256, 0, s>>>(perm, in, out, n, vstride,
                                                                          scatter ? 1 : 0);
+}
+
+void launch_fill_u32(uint32_t *p, size_t count, uint32_t value, hipStream_t s) {
+    if (count == 0) return;
+    k_fill_u32<<<copy_blocks(count), 256, 0, s>>>(p, count, value);
 }
 
 void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *colidx, const double *A,
