@@ -104,6 +104,9 @@ def parse(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-configuration autotuner")
+    ap.add_argument("--fuse", type=int, default=1, choices=[0, 1],
+                    help="RS_OPT_FUSE_SPMV: the upper launch of the rows without lower blocks also forms their "
+                         "rows of the following SpMV (where the pattern allows it)")
     ap.add_argument("--slots", type=int, default=8, help="request stream: concurrent worker slots")
     ap.add_argument("--requests", type=int, default=2000, help="request stream (c5): requests per arrival rate")
     ap.add_argument("--loads", default="0.5,0.8,1.0",
@@ -259,6 +262,7 @@ class Problem:
         self.analyse_ms = (time.perf_counter() - t) * 1e3
         self.nl, self.nu = rs.ilu0_get_sweep_levels(self.base)
         _, self.n_sets, _ = rs.ilu0_get_schedule(self.base, s.n)
+        self.fused_rows = rs.ilu0_get_option(self.base, rs.OPT_FUSED_ROWS)
 
     def _analyse(self):
         rs = self.rs
@@ -274,6 +278,7 @@ class Problem:
         M = self.base if not self.handles else rs.ilu0_analyse_shared(self.A, self.base)
         st, bad = rs.ilu0_factor(M, self.A, PREC[precision])
         assert st == rs.OK, (st, bad)
+        rs.ilu0_set_option(M, rs.OPT_FUSE_SPMV, self.args.fuse)
         tune = None
         if not self.args.no_tune:
             t = time.perf_counter()
@@ -503,6 +508,7 @@ def main():
                    "solver": f"gmres({args.restart})" if gmres else "bicgstab",
                    "reduction": reduction, "max_iter": 200, "n_brows": s.n, "nnzb": s.nnzb, "batch": s.batch,
                    "rhs_per_step": rhs, "sets": P.n_sets, "sweep_levels": [P.nl, P.nu],
+                   "fuse_spmv": args.fuse, "fused_rows": P.fused_rows,
                    "jacobi_partitions": args.jacobi or None,
                    "mean_half_steps": head["mean_half_steps"],
                    "max_true_rel_residual": head["max_true_rel_residual"], "statuses": head["statuses"],

@@ -116,12 +116,25 @@ enum rs_option {
                                 its partial and a one-workgroup kernel adds them; 2 = each wave
                                 stores its partial and every workgroup of the next vector kernel
                                 adds them (few partials: small systems) */
-    RS_OPT_SPIN_LIMIT = 8    /* polls before a single-launch sweep's dependency wait gives up
+    RS_OPT_SPIN_LIMIT = 8,   /* polls before a single-launch sweep's dependency wait gives up
                                 (default 4194304, >= 0).  A wait that gives up lets its tile go
                                 on, so the launch still ends; the solve then returns RS_HIP_ERROR
                                 and the handle's sweep counters and tile flags are reset, so the
                                 next call starts clean.  A small value forces that error path
                                 (for tests of the recovery) */
+    RS_OPT_FUSE_SPMV = 9,    /* 1 (default): where the rows without lower blocks are the first rows
+                                of the analysed order (at least a quarter of them) and share one
+                                upper level (graph colouring of a grid: the first colour),
+                                BiCGStab's upper launch of those rows reads each of their rows
+                                of A' once for the sweep and for their rows of the SpMV that
+                                follows (their U rows equal their rows of A'); the SpMV then
+                                covers the other rows.  Same z; v and t of those rows add the
+                                diagonal's term last, and the dot products' summation order
+                                changes: the solve agrees with the unfused one to rounding.
+                                Used with per-level sweeps, reduction split 0 and no separate
+                                wells; 0: never */
+    RS_OPT_FUSED_ROWS = 10   /* read only (ilu0_get_option): how many rows the analysed pattern
+                                lets RS_OPT_FUSE_SPMV fuse (0: none) */
 };
 
 /* Per-system outcome of bicgstab_solve and gmres_solve. */

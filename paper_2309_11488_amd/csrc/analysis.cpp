@@ -510,6 +510,29 @@ int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx
         }
     }
 
+    // rows whose upper launch can also form their part of y = A' x (see
+    // Schedule::fuse_n0)
+    if (!part && n > 0) {
+        int n0 = 0;
+        while (n0 < n && s.pcol[s.prow[n0]] == n0) ++n0;   // leading rows whose first block is the diagonal
+        bool ok = n0 > 0 && 4 * (long long)n0 >= n;   // a quarter of the rows at least
+        for (int i = 0; ok && i < n0; ++i)   // no lower block, at least one upper block
+            ok = s.pcol[s.prow[i]] == i && s.prow[i + 1] - s.prow[i] >= 2;
+        for (int i = n0; ok && i < n; ++i)    // every later row holds a lower block
+            ok = s.pcol[s.prow[i]] < i;
+        if (ok) {
+            const int lf = udep[0];
+            ok = lf >= 1 && s.uset[lf + 1] - s.uset[lf] >= n0;
+            for (int i = 0; ok && i < n0; ++i) ok = s.urows[s.uset[lf] + i] == i;
+            if (ok) {
+                s.fuse_n0 = n0;
+                s.fuse_q0 = s.uset[lf];
+                s.fuse_level = lf;
+                s.fuse_nnz = s.prow[n0];
+            }
+        }
+    }
+
     s.lconsec.assign(s.nl_levels, 1);
     for (int l = 0; l < s.nl_levels; ++l)
         for (int q = s.lset[l]; q < s.lset[l + 1]; ++q)

@@ -60,6 +60,15 @@ struct Schedule {
     // (then U_kj equals A'_kj, which the reordered copy holds).
     std::vector<int32_t> upd_ptr, upd;
     int max_lrow = 0, max_urow = 0;
+    // Rows without lower blocks, when they are exactly the first fuse_n0
+    // rows of the new order (at least a quarter of all rows), all hold
+    // upper blocks and all sit at the start of one upper level (U-schedule positions fuse_q0 + i for row i): their
+    // U rows are their rows of A' (nothing updates them), so the upper launch
+    // of that level can also form their rows of the next product with A'.
+    // fuse_n0 = 0 when the pattern has no such structure (or with a
+    // partition).  fuse_nnz = A' blocks of those rows.
+    int fuse_n0 = 0, fuse_q0 = 0, fuse_level = -1;
+    long long fuse_nnz = 0;
     // row tiles of the single-launch sweeps: tile t covers schedule
     // positions [start[t], start[t+1]) inside one level, and must wait for
     // the tiles dep[dep_ptr[t] .. dep_ptr[t+1]) (earlier tiles holding rows

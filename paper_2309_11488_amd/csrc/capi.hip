@@ -238,7 +238,7 @@ struct rs_ilu0 {
     DevBuf pvals, L, U, Dinv, Lf, Uf, Dinvf, bad;
     std::vector<int32_t> bad_host;
     // solve workspace
-    DevBuf work, ywork, part, spart, tickets, state, bstage, xstage, flags, ctrs;
+    DevBuf work, ywork, part, spart, fpart, tickets, state, bstage, xstage, flags, ctrs;
     Krylov k{};
     // GMRES workspace: Krylov basis, per-system cycle state, reduction partials
     DevBuf gm_basis, gm_state, gm_part;
@@ -257,6 +257,7 @@ struct rs_ilu0 {
     int spmv_variant = rs::RV_W4_LDS;   // launch shape of the SpMVs
     int sweep_variant = rs::RV_W4_LDS;  // launch shape of the per-level sweeps
     int reduce_split = 0;               // RS_OPT_REDUCE_SPLIT
+    bool fuse_spmv = true;              // RS_OPT_FUSE_SPMV
     // the wells of the matrix last solved with, in the new numbering
     const rs_bcsr *wells_of = nullptr;
     long long wells_version = -1;
@@ -273,12 +274,12 @@ struct rs_ilu0 {
     // every setting a captured iteration depends on
     struct GraphKey {
         int precision = -1, tile_sweeps = 0, spmv_variant = 0, sweep_variant = 0, split = 0, sweep_grid = 0;
-        int spin = 0;
+        int spin = 0, fuse = 0;
         long long wells = 0;   // 0: no wells, else the wells' version + 1
         bool operator==(const GraphKey &o) const {
             return precision == o.precision && tile_sweeps == o.tile_sweeps && spmv_variant == o.spmv_variant &&
                    sweep_variant == o.sweep_variant && split == o.split && sweep_grid == o.sweep_grid &&
-                   spin == o.spin && wells == o.wells;
+                   spin == o.spin && fuse == o.fuse && wells == o.wells;
         }
     };
     struct Segment {
@@ -567,6 +568,7 @@ static int build_analysis(const rs_bcsr *A, int32_t ordering, const int32_t *par
     d.lsrc_a = an->lsrc_a.as<int32_t>(); d.usrc_a = an->usrc_a.as<int32_t>(); d.dsrc_a = an->dsrc_a.as<int32_t>();
     d.nrest = (int)S.rest_dst.size();
     d.rest_dst = an->rest_dst.as<int32_t>(); d.rest_src = an->rest_src.as<int32_t>();
+    d.fuse_n0 = S.fuse_n0; d.fuse_q0 = S.fuse_q0;
     d.nlt = S.ltiles.n; d.nut = S.utiles.n;
     d.lt_start = an->lt_start.as<int32_t>(); d.lt_dptr = an->lt_dptr.as<int32_t>(); d.lt_dep = an->lt_dep.as<int32_t>();
     d.ut_start = an->ut_start.as<int32_t>(); d.ut_dptr = an->ut_dptr.as<int32_t>(); d.ut_dep = an->ut_dep.as<int32_t>();
@@ -684,6 +686,10 @@ int ilu0_set_option(ilu0_t M, int32_t option, int32_t value) {
         if (value < 0) break;
         M->spin_limit = value;
         return RS_OK;
+    case RS_OPT_FUSE_SPMV:
+        if (value != 0 && value != 1) break;
+        M->fuse_spmv = value != 0;
+        return RS_OK;
     default:
         break;
     }
@@ -702,6 +708,8 @@ int ilu0_get_option(ilu0_t M, int32_t option, int32_t *value) {
     case RS_OPT_SWEEP_VARIANT: *value = M->sweep_variant; return RS_OK;
     case RS_OPT_REDUCE_SPLIT: *value = M->reduce_split; return RS_OK;
     case RS_OPT_SPIN_LIMIT: *value = M->spin_limit; return RS_OK;
+    case RS_OPT_FUSE_SPMV: *value = M->fuse_spmv ? 1 : 0; return RS_OK;
+    case RS_OPT_FUSED_ROWS: *value = M->an->sch.fuse_n0; return RS_OK;
     default: return fail(RS_INVALID_ARG, "ilu0_get_option: unknown option");
     }
 }
@@ -852,6 +860,8 @@ static int ensure_workspace(ilu0_t M, hipStream_t s) {
     if (!M->part.p || M->k.part_stride != pstride) HIP_TRY(M->part.alloc(B * pstride * sizeof(double)));
     const size_t sstride = rs::part_stride_for(rs::row_blocks(std::max(M->n, 1), 1));
     if (!M->spart.p) HIP_TRY(M->spart.alloc(B * sstride * sizeof(double)));
+    const size_t fstride = rs::part_stride_for(rs::fuse_blocks(M->an->sch.fuse_n0, 1));
+    if (!M->fpart.p) HIP_TRY(M->fpart.alloc(B * fstride * sizeof(double)));
     if (!M->tickets.p) {
         HIP_TRY(M->tickets.alloc(B * tstride * sizeof(uint32_t)));
         HIP_TRY(hipMemsetAsync(M->tickets.p, 0, B * tstride * sizeof(uint32_t), s));
@@ -879,6 +889,8 @@ static int ensure_workspace(ilu0_t M, hipStream_t s) {
     k.ticket_stride = tstride;
     k.spart = M->spart.as<double>();
     k.spart_stride = sstride;
+    k.fpart = M->fpart.as<double>();
+    k.fpart_stride = fstride;
     k.st = M->state.as<SysState>();
     k.lflags = M->flags.as<int32_t>();
     k.uflags = k.lflags + B * (size_t)M->an->sch.ltiles.n;
@@ -968,23 +980,48 @@ static void lower_levels(ilu0_t M, const T *L, const T *D, const double *in, dou
                              S.lset[l + 1], nsys, M->sweep_variant, D, (size_t)M->n * 9, out, u0_end, s);
 }
 
+// Whether BiCGStab's iterations fuse the upper launch of the rows without
+// lower blocks with their rows of the SpMV that follows (RS_OPT_FUSE_SPMV).
+static bool fused_iteration(const rs_ilu0 *M) {
+    return M->fuse_spmv && M->an->sch.fuse_n0 > 0 && !M->tile_sweeps && M->split() == 0 && M->wdev.nw == 0;
+}
+
+// Algorithmic bytes of the SpMV rows a fused upper launch forms (their
+// blocks with column indices, row pointers, x and the product).
+static double fused_spmv_bytes(ilu0_t M, int nsys) {
+    const rs::Schedule &S = M->an->sch;
+    return nsys * (76.0 * (double)S.fuse_nnz + 52.0 * S.fuse_n0);
+}
+
 // Upper sweep levels 1 and up (level 0 is done by the lower sweep), timed
-// as one unit.
+// as one unit.  fmode != FUSE_NONE: the launch of the rows without lower
+// blocks also forms their rows of fout = A' out (the product of the
+// application's result), with the dot products against fw1.
 template <typename T>
 static void upper_levels(ilu0_t M, const T *U, const T *D, double *out, bool fuse_p, Krylov &k, SysState *st,
-                         int nsys, hipStream_t s, bool prof = true) {
+                         int nsys, hipStream_t s, bool prof = true, int fmode = rs::FUSE_NONE,
+                         double *fout = nullptr, const double *fw1 = nullptr) {
     const rs::Schedule &S = M->an->sch;
     const size_t vs = k.vstride;
     const T *y = (const T *)k.y;
-    ProfScope ps(PC_USWEEP, s, upper_bytes(M, sizeof(T), nsys), M->tile_sweeps, prof);
+    const double fb = fmode != rs::FUSE_NONE ? fused_spmv_bytes(M, nsys) : 0.0;
+    ProfScope ps(PC_USWEEP, s, upper_bytes(M, sizeof(T), nsys) + fb, M->tile_sweeps, prof);
     if (M->tile_sweeps) {
         rs::launch_usweep_tiles<T>(M->an->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, k.uflags,
                                    k.uctr, nsys, M->sweep_grid, M->spin_limit, s, ps.start(), ps.stop());
         return;
     }
-    for (int l = 1; l < S.nu_levels; ++l)
-        rs::launch_usweep<T>(M->an->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, S.uset[l],
+    for (int l = 1; l < S.nu_levels; ++l) {
+        int q0 = S.uset[l];
+        if (fmode != rs::FUSE_NONE && l == S.fuse_level) {
+            rs::launch_usweep_spmv<T>(M->an->dev, M->pvals.as<double>(), (size_t)M->nnzb * 9, D, (size_t)M->n * 9,
+                                      y, out, fout, fw1, k, nsys, fmode, M->spmv_variant, fuse_p, s);
+            q0 += S.fuse_n0;
+            if (q0 >= S.uset[l + 1]) continue;
+        }
+        rs::launch_usweep<T>(M->an->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, q0,
                              S.uset[l + 1], nsys, M->sweep_variant, fuse_p, s);
+    }
 }
 
 // One preconditioner application M^{-1} in -> out (new order), all levels.
@@ -1032,36 +1069,45 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
     // algorithmic bytes of y = A x: values and column indices, row
     // pointers, x read once, y written (the fused dot product's second
     // vector is not counted)
-    const double spmv_bytes = B * (76 * nnzb + 52 * n);
-    const double apply_bytes = lower_bytes(M, tb, B) + upper_bytes(M, tb, B);
+    // with the fused upper launch, the rows without lower blocks of v and t
+    // (and their bytes) move from the SpMV into the application
+    const bool fz = fused_iteration(M);
+    const int r0 = fz ? M->an->sch.fuse_n0 : 0;
+    const double fb = fz ? fused_spmv_bytes(M, B) : 0.0;
+    const double spmv_bytes = B * (76 * nnzb + 52 * n) - fb;
+    const double apply_bytes = lower_bytes(M, tb, B) + upper_bytes(M, tb, B) + fb;
     {
         // an application is timed whole or not at all
         ProfScope pa(PC_APPLY, s, apply_bytes, false, (parts & P_L1) && (parts & P_U1));
         if (parts & P_L1) lower_levels<T>(M, L, D, nullptr, k.phat, true, k, k.st, B, s);
-        if (parts & P_U1) upper_levels<T>(M, U, D, k.phat, true, k, k.st, B, s);
+        if (parts & P_U1)
+            upper_levels<T>(M, U, D, k.phat, true, k, k.st, B, s, true, fz ? rs::FUSE_V : rs::FUSE_NONE, k.v,
+                            k.rhat);
     }
     if (parts & P_SPMV_V) {
         ProfScope ps(PC_SPMV_V, s, spmv_bytes, true);
-        rs::launch_spmv_v(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), M->wdev, s,
-                          ps.start(), ps.stop());
+        rs::launch_spmv_v(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), M->wdev, r0,
+                          s, ps.start(), ps.stop());
     }
     if (parts & P_SUPD) {
         ProfScope ps(PC_VEC, s, B * 72 * n, true);
-        rs::launch_s_update(M->n, k, B, M->spmv_variant, M->split(), s, ps.start(), ps.stop());
+        rs::launch_s_update(M->an->dev, k, B, M->spmv_variant, M->split(), fz, s, ps.start(), ps.stop());
     }
     {
         ProfScope pa(PC_APPLY, s, apply_bytes, false, (parts & P_L2) && (parts & P_U2));
         if (parts & P_L2) lower_levels<T>(M, L, D, k.s, k.shat, false, k, k.st, B, s);
-        if (parts & P_U2) upper_levels<T>(M, U, D, k.shat, false, k, k.st, B, s);
+        if (parts & P_U2)
+            upper_levels<T>(M, U, D, k.shat, false, k, k.st, B, s, true, fz ? rs::FUSE_T : rs::FUSE_NONE, k.t,
+                            k.s);
     }
     if (parts & P_SPMV_T) {
         ProfScope ps(PC_SPMV_T, s, spmv_bytes, true);
-        rs::launch_spmv_t(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), M->wdev, s,
-                          ps.start(), ps.stop());
+        rs::launch_spmv_t(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), M->wdev, r0,
+                          s, ps.start(), ps.stop());
     }
     if (parts & P_XR) {
         ProfScope ps(PC_VEC, s, B * 192 * n, true);
-        rs::launch_xr_update(M->n, k, B, M->spmv_variant, M->split(), s, ps.start(), ps.stop());
+        rs::launch_xr_update(M->an->dev, k, B, M->spmv_variant, M->split(), fz, s, ps.start(), ps.stop());
     }
 }
 
@@ -1084,6 +1130,7 @@ static int replay_segment(ilu0_t M, int parts, hipStream_t s) {
     key.split = M->split();
     key.sweep_grid = M->sweep_grid;
     key.spin = M->spin_limit;
+    key.fuse = fused_iteration(M) ? 1 : 0;
     key.wells = M->wdev.nw > 0 ? (long long)M->wells_version + 1 : 0;
     rs_ilu0::Segment &seg = M->segments[parts];
     if (!seg.exec || !(seg.key == key)) {

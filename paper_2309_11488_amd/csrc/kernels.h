@@ -31,6 +31,9 @@ struct DevSchedule {
     const int32_t *lsrc_a, *usrc_a, *dsrc_a;   // caller-order sources of the factor's blocks
     int nrest;                                 // A' blocks the factor does not read (Block-Jacobi)
     const int32_t *rest_dst, *rest_src;
+    // rows 0 .. fuse_n0 hold no lower blocks and sit at U-schedule
+    // positions fuse_q0 + i of one upper level (0: no such rows)
+    int fuse_n0, fuse_q0;
     // sweep tiles (see Schedule::Tiles)
     int nlt, nut;
     const int32_t *lt_start, *lt_dptr, *lt_dep, *ut_start, *ut_dptr, *ut_dep;
@@ -82,6 +85,8 @@ struct Krylov {
     size_t ticket_stride;
     double *spart;      // per-workgroup partials of the two SpMVs, nsys * spart_stride
     size_t spart_stride;
+    double *fpart;      // partials of the products formed by the fused upper launch, nsys * fpart_stride
+    size_t fpart_stride;
     SysState *st;       // nsys states
     int32_t *lflags, *uflags;  // per (system, tile): epoch of the sweep that finished it
     SweepCtr *lctr, *uctr;
@@ -207,14 +212,36 @@ void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad
 void launch_wells_t2(const WellsDev &w, const double *x, size_t xstride, int nsys, hipStream_t s);
 
 // ev0 / ev1 (optional): events recorded by the dispatch at the kernel's start and end.
+// r0: rows [r0, n) only (the fused upper launch formed rows [0, r0)).
 void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, int split,
-                   const WellsDev &w, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, int split, hipStream_t s,
-                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                   const WellsDev &w, int r0, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// fused: the product's rows [0, d.fuse_n0) came from the fused upper
+// launch, whose group sums are added after those of the SpMV.
+void launch_s_update(const DevSchedule &d, Krylov &k, int nsys, int spmv_variant, int split, bool fused,
+                     hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, int split,
-                   const WellsDev &w, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, int split, hipStream_t s,
-                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                   const WellsDev &w, int r0, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+void launch_xr_update(const DevSchedule &d, Krylov &k, int nsys, int spmv_variant, int split, bool fused,
+                      hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+// Which product the fused upper launch forms.
+enum FuseMode { FUSE_NONE = 0, FUSE_V = 1, FUSE_T = 2 };
+
+// Upper launch of the rows [0, d.fuse_n0) (U-schedule positions fuse_q0 +
+// i) fused with the product that follows the application: z_i as
+// launch_usweep, and out_i = (A' z)_i with the dot-product partials of
+// the mode (FUSE_V: (w1, out), (out, out) for v = A phat with w1 = rhat;
+// FUSE_T: the same for t = A shat with w1 = s) stored as group sums in
+// k.fpart.
+// defer as launch_usweep.  The launch takes the waves per workgroup and the
+// load kind of the SpMV shape spmv_variant; fuse_blocks(d.fuse_n0, waves)
+// workgroups.
+template <typename T>
+void launch_usweep_spmv(const DevSchedule &d, const double *Ap, size_t a_stride, const T *Dinv, size_t d_stride,
+                        const T *y, double *z, double *out, const double *w1, Krylov &k, int nsys, int mode,
+                        int spmv_variant, bool defer, hipStream_t s, hipEvent_t ev0 = nullptr,
+                        hipEvent_t ev1 = nullptr);
+inline int fuse_blocks(int n0, int waves) { return std::max(1, row_blocks(n0, waves)); }
 // x_orig[perm[i]] = x'[i]; then r = b - A x_orig with the caller's A, and the
 // true relative residual into the states.
 void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *colidx, const double *A,

@@ -353,10 +353,13 @@ __device__ inline T stage_walk(const int32_t *__restrict__ ptr, const int32_t *_
 // have enough waves in flight.
 constexpr int kRowWavesPerEU = 5;
 
-// LDS capacity (blocks) per pass: 160 (SpMV) or 80 (sweeps) per wave.
+// LDS capacity (blocks) per pass: 160 (SpMV) or 128 (per-level sweeps) per
+// wave, so a workgroup of 7-block rows copies its blocks in one pass; the
+// single-launch sweeps' tiles keep 80 per wave (more workgroups resident to
+// wait on their dependencies).
 constexpr int kSpmvCapPerWave = 160;
-constexpr int kSweepCapPerWave = 80;
-constexpr int kSweepCap = 4 * kSweepCapPerWave;   // single-launch sweeps: 4-wave workgroups
+constexpr int kSweepCapPerWave = 128;
+constexpr int kSweepCap = 4 * 80;   // single-launch sweeps: 4-wave workgroups
 
 // Row walk of a workgroup of W waves: staged through LDS or direct.
 template <int W, int STAGE, int CAPW, bool SUB, typename T, typename TX>
@@ -917,7 +920,7 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
                                                       const double *__restrict__ w1, const double *__restrict__ w2,
                                                       double *__restrict__ part, size_t part_stride,
                                                       uint32_t *__restrict__ tk, size_t tk_stride,
-                                                      SysState *__restrict__ st, int split, WellsDev wl) {
+                                                      SysState *__restrict__ st, int split, WellsDev wl, int r0) {
     int sys, bx;
     xcd_map(sys, bx);
     // whether the system still iterates.  t = A shat often runs after a
@@ -928,16 +931,17 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
     const bool run = MODE != SPMV_V || st[sys].phase == PH_RUN;
     // workgroup bx walks row tiles [bx * per, (bx + 1) * per); per = 1 with
     // one workgroup per tile
+    // rows [r0, n): the fused upper launch formed rows [0, r0)
     constexpr int R = W * kRowsPerWave;
-    const int ntiles = (n + R - 1) / R;
+    const int ntiles = (n - r0 + R - 1) / R;
     const int per = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
     const int t0 = bx * per, t1 = min(t0 + per, ntiles);
     const size_t vo = (size_t)sys * vstride;
     const double *As = A + (size_t)sys * a_stride;
     double v[2] = {0.0, 0.0};
     for (int t = t0; t < t1; ++t) {
-        const RowLane rl = row_lane<W>(t, 0, n);
-        const int qb0 = t * R, qb1 = min(qb0 + R, n);
+        const RowLane rl = row_lane<W>(t, r0, n);
+        const int qb0 = r0 + t * R, qb1 = min(qb0 + R, n);
         const size_t k = vo + 3 * (size_t)rl.q + rl.r;
         // the dot-product operand is loaded before the row walk, so its
         // latency overlaps the walk's
@@ -979,6 +983,104 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
                threadIdx.x == 0) {
         st[sys].true_res = v[1] > 0.0 ? sqrt(v[0]) / sqrt(v[1]) : 0.0;
     }
+}
+
+// ------------------------------------- upper sweep fused with the product
+
+// LDS capacity (blocks of A') per wave of the fused upper launch.
+constexpr int kFuseCapPerWave = 160;
+
+// The rows 0 .. n0 of the new order hold no lower blocks (Schedule::fuse_n0):
+// nothing updates them, so their U row is their row of A' past the
+// diagonal, and all of them sit in one upper level.  One launch over those
+// rows walks each A' row once and gives both
+//   the upper sweep  z_i = inv(U_ii) (y_i - sum_j U_ij z_j), in the factor
+//                    type T with the operations and order of k_usweep
+//                    ((T) of an FP64 block of A' is the stored factor), and
+//   the next product out_i = sum_j A'_ij z_j + A'_ii z_i in FP64: the
+//                    off-diagonal terms summed in the walk, ascending, the
+//                    diagonal's term added once z_i is known (k_spmv adds
+//                    the diagonal first: the same terms, another rounding),
+// plus that product's dot-product partials (MODE SPMV_V: (rhat, v) with w1 =
+// rhat; SPMV_T: (s, t) and (t, t) with w1 = s), reduced to group sums as
+// k_spmv does.  Every upper column of such a row is a row with lower blocks,
+// whose z the earlier upper levels or the lower launches have finished.
+// defer: the phase test waits until the walk's loads are in flight (the
+// iteration's first application).
+template <typename T, int MODE, int W, bool NTL>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRowWavesPerEU, 8)))
+k_usweep_spmv(DevSchedule d, const double *__restrict__ Ap, size_t a_stride, const T *__restrict__ Dinv,
+              size_t d_stride, const T *__restrict__ y, double *__restrict__ z, double *__restrict__ out,
+              const double *__restrict__ w1, size_t vstride, SysState *__restrict__ st, double *__restrict__ part,
+              size_t part_stride, uint32_t *__restrict__ tk, size_t tk_stride, int defer) {
+    constexpr int CAP = kFuseCapPerWave * W, NT = 64 * W;
+    __shared__ Stage<double, CAP, NT> sv;
+    int sys, bx;
+    xcd_map(sys, bx);
+    if (!defer && st[sys].phase != PH_RUN) return;
+    const int n0 = d.fuse_n0;
+    const RowLane rl = row_lane<W>(bx, 0, n0);
+    const int qb0 = bx * W * kRowsPerWave, qb1 = min(qb0 + W * kRowsPerWave, n0);
+    const size_t vo = (size_t)sys * vstride;
+    const size_t k = vo + 3 * (size_t)rl.q + rl.r;
+    const double *As = Ap + (size_t)sys * a_stride;
+    T acc = 0;
+    T dq[3] = {0, 0, 0};
+    double w = 0.0;
+    if (rl.act) {
+        acc = y[k];
+        const T *dp = Dinv + (size_t)sys * d_stride + (size_t)(d.fuse_q0 + rl.q) * 9 + 3 * rl.r;
+        dq[0] = dp[0]; dq[1] = dp[1]; dq[2] = dp[2];
+        w = w1[k];
+    }
+    const int e0 = d.prow[qb0], e1 = d.prow[qb1];
+    // the lane's row: diagonal at my0, upper blocks [my0 + 1, my1)
+    const int my0 = rl.act ? d.prow[rl.q] : 0, my1 = rl.act ? d.prow[rl.q + 1] : 0;
+    const double *x = z + vo;
+    double dg[3] = {0.0, 0.0, 0.0};
+    double av = 0.0;
+    for (int base = e0; base < e1; base += CAP) {
+        const int cnt = min(CAP, e1 - base);
+        __syncthreads();
+        const int shift = stage_copy<double, CAP, NT, NTL>(As, d.pcol, base, cnt, sv);
+        __syncthreads();
+        const double *vals = (const double *)sv.v + shift;
+        if (rl.act && my0 >= base && my0 < base + cnt) {
+            const double *b = vals + (my0 - base) * 9 + 3 * rl.r;
+            dg[0] = b[0]; dg[1] = b[1]; dg[2] = b[2];
+        }
+        const int lo = max(my0 + 1, base), hi = min(my1, base + cnt);
+        for (int e = lo; e < hi; e += 8) {
+            double xv[8][3];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = sv.c[min(e + u, hi - 1) - base];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) xv[u][c] = x[3 * j + c];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (e + u < hi) {
+                    const double *b = vals + (e + u - base) * 9 + 3 * rl.r;
+                    acc -= dot3((T)b[0], (T)b[1], (T)b[2], (T)xv[u][0], (T)xv[u][1], (T)xv[u][2]);
+                    av += dot3(b[0], b[1], b[2], xv[u][0], xv[u][1], xv[u][2]);
+                }
+        }
+    }
+    asm volatile("" ::"v"(acc), "v"(av));
+    if (st[sys].phase != PH_RUN) return;
+    const T t0 = __shfl(acc, rl.base, 64), t1 = __shfl(acc, rl.base + 1, 64), t2 = __shfl(acc, rl.base + 2, 64);
+    const double zr = (double)dot3(dq[0], dq[1], dq[2], t0, t1, t2);
+    const double z0 = __shfl(zr, rl.base, 64), z1 = __shfl(zr, rl.base + 1, 64), z2 = __shfl(zr, rl.base + 2, 64);
+    av += dot3(dg[0], dg[1], dg[2], z0, z1, z2);
+    double v[2] = {0.0, 0.0};
+    if (rl.act) {
+        z[k] = zr;
+        out[k] = av;
+        v[0] = w * av;
+        v[1] = av * av;
+    }
+    group_reduce<2>(v, part + sys * part_stride, tk + sys * tk_stride, gridDim.x, bx);
 }
 
 // ---------------------------------------------------------------- vectors
@@ -1078,7 +1180,7 @@ __global__ void __launch_bounds__(kVecThreads) k_setup(int n, const int32_t *__r
 
 // alpha = rho / (rhat, v) from the partials of v = A phat; s = r - alpha v,
 // ||s||; half-step test.
-__global__ void __launch_bounds__(kVecThreads) k_s_update(Krylov k, int sums_at, int sums) {
+__global__ void __launch_bounds__(kVecThreads) k_s_update(Krylov k, int sums_at, int sums, int fsums_at, int fsums) {
     const int sys = blockIdx.y, bx = blockIdx.x;
     const size_t vo = (size_t)sys * k.vstride, tiles = k.vstride / kVecTile;
     // the first tile's vectors are requested before the state and the
@@ -1093,6 +1195,12 @@ __global__ void __launch_bounds__(kVecThreads) k_s_update(Krylov k, int sums_at,
     if (S.phase != PH_RUN) return;
     double rvv[2];
     sum_partials<2>(k.spart + sys * k.spart_stride + sums_at, sums, rvv);
+    if (fsums > 0) {
+        // rows [0, fuse_n0) of v came from the fused upper launch
+        double f[2];
+        sum_partials<2>(k.fpart + sys * k.fpart_stride + fsums_at, fsums, f);
+        rvv[0] += f[0];
+    }
     const double rv = rvv[0];
     if (!finite(rv) || rv == 0.0) {
         if (bx == 0 && threadIdx.x == 0) {
@@ -1133,7 +1241,7 @@ __global__ void __launch_bounds__(kVecThreads) k_s_update(Krylov k, int sums_at,
 // Full step: x += alpha phat + omega shat, r = s - omega t, ||r||, (rhat, r),
 // full-step test, next rho and beta.  After a half-step stop (or an omega
 // breakdown) only x += alpha phat.
-__global__ void __launch_bounds__(kVecThreads) k_xr_update(Krylov k, int sums_at, int sums) {
+__global__ void __launch_bounds__(kVecThreads) k_xr_update(Krylov k, int sums_at, int sums, int fsums_at, int fsums) {
     const int sys = blockIdx.y, bx = blockIdx.x;
     const size_t vo = (size_t)sys * k.vstride, tiles = k.vstride / kVecTile;
     // the first tile's vectors are requested before the state and the
@@ -1158,6 +1266,13 @@ __global__ void __launch_bounds__(kVecThreads) k_xr_update(Krylov k, int sums_at
         // omega = (t, s) / (t, t) from the partials of t = A shat
         double tv[2];
         sum_partials<2>(k.spart + sys * k.spart_stride + sums_at, sums, tv);
+        if (fsums > 0) {
+            // rows [0, fuse_n0) of t came from the fused upper launch
+            double f[2];
+            sum_partials<2>(k.fpart + sys * k.fpart_stride + fsums_at, fsums, f);
+            tv[0] += f[0];
+            tv[1] += f[1];
+        }
         const double ts = tv[0], tt = tv[1];
         if (!finite(ts) || !finite(tt) || tt == 0.0) {
             if (bx == 0 && threadIdx.x == 0) {
@@ -1647,21 +1762,21 @@ template <int MODE>
 static void spmv_any(int variant, int n, const int32_t *ptr, const int32_t *col, const double *A, size_t a_stride,
                      const double *x, double *y, size_t vstride, const double *w1, double *part, size_t part_stride,
                      uint32_t *tk, size_t tk_stride, SysState *st, int nsys, int split, const WellsDev &wl,
-                     hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+                     hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int r0 = 0) {
     if (wl.nw > 0) launch_wells_t2(wl, x, vstride, nsys, s);
     int waves = 1;
     with_variant(variant, [&](auto W, auto ST) {
         constexpr int w = decltype(W)::value;
         constexpr int staged = decltype(ST)::value;
-        waves = spmv_grid(n, w) * w;
-        const dim3 g(spmv_grid(n, w), nsys), b(64 * w);
+        waves = spmv_grid(n - r0, w) * w;
+        const dim3 g(spmv_grid(n - r0, w), nsys), b(64 * w);
         if (ev0)
             hipExtLaunchKernelGGL(k_spmv<MODE, w, staged>, g, b, 0, s, ev0, ev1, 0, n, ptr, col, A, a_stride, x, y,
                                   vstride, w1, (const double *)nullptr, part, part_stride, tk, tk_stride, st,
-                                  split, wl);
+                                  split, wl, r0);
         else
             k_spmv<MODE, w, staged><<<g, b, 0, s>>>(n, ptr, col, A, a_stride, x, y, vstride, w1, nullptr, part,
-                                                    part_stride, tk, tk_stride, st, split, wl);
+                                                    part_stride, tk, tk_stride, st, split, wl, r0);
     });
     if (MODE != SPMV_PLAIN && MODE != SPMV_RUN && (split == 1 || (split == 2 && MODE == SPMV_TRUE)))
         k_spmv_total<MODE><<<dim3(1, nsys), kTotalThreads, 0, s>>>(part, part_stride, waves, st);
@@ -1685,28 +1800,67 @@ void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad
 }
 
 void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
-                   int split, const WellsDev &w, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                   int split, const WellsDev &w, int r0, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     spmv_any<SPMV_V>(variant, d.n, d.prow, d.pcol, Ap, a_stride, k.phat, k.v, k.vstride, k.rhat, k.spart,
-                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, w, s, ev0, ev1);
+                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, w, s, ev0, ev1, r0);
 }
 
-void launch_s_update(int n, Krylov &k, int nsys, int spmv_variant, int split, hipStream_t s, hipEvent_t ev0,
-                     hipEvent_t ev1) {
-    const SpmvSums at = spmv_sums(n, variant_waves(spmv_variant), split);
-    launch_ev(k_s_update, dim3(vec_blocks(n), nsys), dim3(kVecThreads), s, ev0, ev1, k, at.offset, at.count);
+// Where the consumer of a fused product finds the fused launch's group sums
+// (the fused launch takes the waves per workgroup of the SpMV's shape).
+static SpmvSums fused_sums(const DevSchedule &d, bool fused, int spmv_variant) {
+    if (!fused) return SpmvSums{0, 0};
+    const int g = fuse_blocks(d.fuse_n0, variant_waves(spmv_variant));
+    return SpmvSums{2 * g, (g + 31) / 32};
+}
+
+void launch_s_update(const DevSchedule &d, Krylov &k, int nsys, int spmv_variant, int split, bool fused,
+                     hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    const SpmvSums at = spmv_sums(d.n - (fused ? d.fuse_n0 : 0), variant_waves(spmv_variant), split);
+    const SpmvSums f = fused_sums(d, fused, spmv_variant);
+    launch_ev(k_s_update, dim3(vec_blocks(d.n), nsys), dim3(kVecThreads), s, ev0, ev1, k, at.offset, at.count,
+              f.offset, f.count);
 }
 
 void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
-                   int split, const WellsDev &w, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                   int split, const WellsDev &w, int r0, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     spmv_any<SPMV_T>(variant, d.n, d.prow, d.pcol, Ap, a_stride, k.shat, k.t, k.vstride, k.s, k.spart,
-                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, w, s, ev0, ev1);
+                     k.spart_stride, k.tickets, k.ticket_stride, k.st, nsys, split, w, s, ev0, ev1, r0);
 }
 
-void launch_xr_update(int n, Krylov &k, int nsys, int spmv_variant, int split, hipStream_t s, hipEvent_t ev0,
-                      hipEvent_t ev1) {
-    const SpmvSums at = spmv_sums(n, variant_waves(spmv_variant), split);
-    launch_ev(k_xr_update, dim3(vec_blocks(n), nsys), dim3(kVecThreads), s, ev0, ev1, k, at.offset, at.count);
+void launch_xr_update(const DevSchedule &d, Krylov &k, int nsys, int spmv_variant, int split, bool fused,
+                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    const SpmvSums at = spmv_sums(d.n - (fused ? d.fuse_n0 : 0), variant_waves(spmv_variant), split);
+    const SpmvSums f = fused_sums(d, fused, spmv_variant);
+    launch_ev(k_xr_update, dim3(vec_blocks(d.n), nsys), dim3(kVecThreads), s, ev0, ev1, k, at.offset, at.count,
+              f.offset, f.count);
 }
+
+template <typename T>
+void launch_usweep_spmv(const DevSchedule &d, const double *Ap, size_t a_stride, const T *Dinv, size_t d_stride,
+                        const T *y, double *z, double *out, const double *w1, Krylov &k, int nsys, int mode,
+                        int spmv_variant, bool defer, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (d.fuse_n0 <= 0 || nsys <= 0) return;
+    // the SpMV's launch shape: its waves per workgroup, and non-temporal
+    // matrix loads for the shapes that use them (direct shapes stage too:
+    // the product walk rereads the staged blocks)
+    with_variant(spmv_variant, [&](auto Wc, auto ST) {
+        constexpr int w = decltype(Wc)::value;
+        constexpr bool nt = decltype(ST)::value == 2;
+        const dim3 g(fuse_blocks(d.fuse_n0, w), nsys), b(64 * w);
+        auto go = [&](auto kern) {
+            launch_ev(kern, g, b, s, ev0, ev1, d, Ap, a_stride, Dinv, d_stride, y, z, out, w1, k.vstride, k.st,
+                      k.fpart, k.fpart_stride, k.tickets, k.ticket_stride, defer ? 1 : 0);
+        };
+        if (mode == FUSE_V) go(k_usweep_spmv<T, SPMV_V, w, nt>);
+        else go(k_usweep_spmv<T, SPMV_T, w, nt>);
+    });
+}
+template void launch_usweep_spmv<double>(const DevSchedule &, const double *, size_t, const double *, size_t,
+                                         const double *, double *, double *, const double *, Krylov &, int, int,
+                                         int, bool, hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_usweep_spmv<float>(const DevSchedule &, const double *, size_t, const float *, size_t,
+                                        const float *, double *, double *, const double *, Krylov &, int, int,
+                                        int, bool, hipStream_t, hipEvent_t, hipEvent_t);
 
 void launch_permute_vec(const int32_t *perm, const double *in, double *out, int n, size_t vstride, int nsys,
                         bool scatter, hipStream_t s) {
