@@ -946,16 +946,23 @@ static int sweep_error(ilu0_t M, hipStream_t s) {
 // and the vectors: the lower sweep reads its input and writes y (52 N with
 // the row pointer), the upper sweep reads y and writes z (48 N), inv(U_ii)
 // counted with U.  Fused work (the p update of an iteration's first lower
-// sweep) is not counted.  The lower launches also finish the rows without
-// upper blocks, whose inv(U_ii) and z are counted with the upper sweep.
+// sweep) is not counted.  With one launch per level, the lower launches also
+// finish the rows without upper blocks (the upper sweep's first level): their
+// inv(U_ii) and z move from the upper sweep's count to the lower one's.
+static double fold_bytes(ilu0_t M, double tb) {
+    const rs::Schedule &S = M->an->sch;
+    if (M->tile_sweeps || S.nu_levels == 0) return 0.0;
+    return (9 * tb + 4 + 48.0) * S.uset[1];
+}
+
 static double lower_bytes(ilu0_t M, double tb, int nsys) {
     const rs::Schedule &S = M->an->sch;
-    return nsys * ((9 * tb + 4) * S.nL + 52.0 * M->n);
+    return nsys * ((9 * tb + 4) * S.nL + 52.0 * M->n + fold_bytes(M, tb));
 }
 
 static double upper_bytes(ilu0_t M, double tb, int nsys) {
     const rs::Schedule &S = M->an->sch;
-    return nsys * ((9 * tb + 4) * ((double)S.nU + M->n) + 48.0 * M->n);
+    return nsys * ((9 * tb + 4) * ((double)S.nU + M->n) + 48.0 * M->n - fold_bytes(M, tb));
 }
 
 // Lower sweep of one preconditioner application M^{-1} in -> out (new
@@ -1170,6 +1177,8 @@ static int run_iteration(ilu0_t M, hipStream_t s) {
     const int timed = class_parts(g_prof.mask);
     if (!timed) return replay_segment(M, P_ALL, s);
     const double tb = M->precision == RS_PREC_FP32_FACTORS ? 4 : 8;
+    // the SpMV rows a fused upper launch forms count with the application
+    const double fb = fused_iteration(M) ? fused_spmv_bytes(M, M->batch) : 0.0;
     const bool whole = apply_unit(g_prof.mask);
     int run = 0;
     for (int part = 1; part <= P_XR; part <<= 1) {
@@ -1184,7 +1193,7 @@ static int run_iteration(ilu0_t M, hipStream_t s) {
         }
         if (whole && (part == P_L1 || part == P_L2)) {
             // a whole application (both sweeps) as one graph segment between two events
-            ProfScope ps(PC_APPLY, s, lower_bytes(M, tb, M->batch) + upper_bytes(M, tb, M->batch));
+            ProfScope ps(PC_APPLY, s, lower_bytes(M, tb, M->batch) + upper_bytes(M, tb, M->batch) + fb);
             const int st = replay_segment(M, part | (part << 1), s);
             if (st != RS_OK) return st;
             part <<= 1;   // its upper sweep is done
@@ -1194,7 +1203,7 @@ static int run_iteration(ilu0_t M, hipStream_t s) {
         if (sweep && !M->tile_sweeps) {
             const bool lower = part == P_L1 || part == P_L2;
             ProfScope ps(lower ? PC_LSWEEP : PC_USWEEP, s,
-                         lower ? lower_bytes(M, tb, M->batch) : upper_bytes(M, tb, M->batch));
+                         lower ? lower_bytes(M, tb, M->batch) : upper_bytes(M, tb, M->batch) + fb);
             const int st = replay_segment(M, part, s);
             if (st != RS_OK) return st;
         } else {

@@ -654,7 +654,8 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
         if (!run) return;
         if (rl.act) pv[k] = p;
     }
-    if (rl.act) y[k] = acc;
+    // y of a row the launch finishes is read by no later launch
+    if (rl.act && uq >= u0_end) y[k] = acc;
     if (u0_end > 0) {
         // rows without upper blocks (the first level of the upper sweep)
         // finish here: z_i = inv(U_ii) y_i, the arithmetic of k_usweep
