@@ -258,6 +258,10 @@ struct rs_ilu0 {
     int sweep_variant = rs::RV_W4_LDS;  // launch shape of the per-level sweeps
     int reduce_split = 0;               // RS_OPT_REDUCE_SPLIT
     bool fuse_spmv = true;              // RS_OPT_FUSE_SPMV
+    // FP64 factors of a pattern with fused rows: the factorisation stored no
+    // U for those rows (their upper launches read A'); U is filled from A'
+    // when a consumer of U needs it (single-launch sweeps, ilu0_get_factors)
+    bool u_missing = false;
     // the wells of the matrix last solved with, in the new numbering
     const rs_bcsr *wells_of = nullptr;
     long long wells_version = -1;
@@ -714,6 +718,19 @@ int ilu0_get_option(ilu0_t M, int32_t option, int32_t *value) {
     }
 }
 
+// U blocks of the fused rows, when the FP64 factorisation did not store
+// them, for a consumer that reads U: copied from A' on `s` (once per
+// factorisation).
+static int ensure_u(ilu0_t M, hipStream_t s) {
+    if (!M->u_missing) return RS_OK;
+    const rs::Schedule &S = M->an->sch;
+    rs::launch_fill_u(M->an->dev, M->pvals.as<double>(), (size_t)M->nnzb * 9, M->U.as<double>(), (size_t)S.nU * 9,
+                      S.uptr[S.fuse_q0], S.uptr[S.fuse_q0 + S.fuse_n0], M->batch, s);
+    HIP_TRY(hipGetLastError());
+    M->u_missing = false;
+    return RS_OK;
+}
+
 static int check_pair(ilu0_t M, bcsr_t A) {
     if (!M || !A) return fail(RS_INVALID_ARG, "NULL handle");
     if (M->hash != A->hash || M->n != A->n || M->nnzb != A->nnzb)
@@ -757,12 +774,16 @@ int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *ba
         rs::launch_gather_pairs(A->vals.as<double>(), per, M->pvals.as<double>(), per, d.rest_dst, d.rest_src,
                                 d.nrest, M->batch, s);
         const bool f32 = precision == RS_PREC_FP32_FACTORS;
+        // FP64 U of the fused rows is their rows of A', which their upper
+        // launches read instead
+        const bool skip_u0 = !f32 && S.fuse_n0 > 0;
         for (int l = 0; l < S.nl_levels; ++l)
             rs::launch_factor_level(d, A->vals.as<double>(), per, M->pvals.as<double>(), M->L.as<double>(),
                                     M->U.as<double>(), M->Dinv.as<double>(), f32 ? M->Lf.as<float>() : nullptr,
                                     f32 ? M->Uf.as<float>() : nullptr, f32 ? M->Dinvf.as<float>() : nullptr,
                                     M->bad.as<int32_t>(), S.lset[l], S.lset[l + 1],
-                                    S.lconsec[l] && S.rest_dst.empty(), M->batch, s);
+                                    S.lconsec[l] && S.rest_dst.empty(), skip_u0, M->batch, s);
+        M->u_missing = skip_u0;
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(M->ev_f1, s));
@@ -790,6 +811,9 @@ int ilu0_get_factors(ilu0_t M, int32_t sys, double *lu, double *dinv) {
     if (!M || sys < 0 || sys >= M->batch) return fail(RS_INVALID_ARG, "ilu0_get_factors: bad arguments");
     if (!M->factored) return fail(RS_NOT_FACTORED, "ilu0_get_factors: not factored");
     HIP_TRY(hipDeviceSynchronize());   // the factorisation may still run on any stream
+    int st = ensure_u(M, nullptr);
+    if (st != RS_OK) return st;
+    HIP_TRY(hipDeviceSynchronize());
     const rs::Schedule &S = M->an->sch;
     if (lu) std::memset(lu, 0, sizeof(double) * 9 * (size_t)M->nnzb);   // diagonal, blocks outside a Jacobi matrix
     std::vector<double> L((size_t)S.nL * 9), U((size_t)S.nU * 9), D((size_t)M->n * 9);
@@ -1018,11 +1042,15 @@ static void upper_levels(ilu0_t M, const T *U, const T *D, double *out, bool fus
                                    k.uctr, nsys, M->sweep_grid, M->spin_limit, s, ps.start(), ps.stop());
         return;
     }
+    // the fused rows' upper launch reads their rows of A': always inside
+    // BiCGStab's fused iteration, and for every application with FP64
+    // factors (whose factorisation stored no U for them)
+    const bool via_ap = fmode != rs::FUSE_NONE || (sizeof(T) == sizeof(double) && S.fuse_n0 > 0);
     for (int l = 1; l < S.nu_levels; ++l) {
         int q0 = S.uset[l];
-        if (fmode != rs::FUSE_NONE && l == S.fuse_level) {
+        if (via_ap && l == S.fuse_level) {
             rs::launch_usweep_spmv<T>(M->an->dev, M->pvals.as<double>(), (size_t)M->nnzb * 9, D, (size_t)M->n * 9,
-                                      y, out, fout, fw1, k, nsys, fmode, M->spmv_variant, fuse_p, s);
+                                      y, out, fout, fw1, st, k, nsys, fmode, M->spmv_variant, fuse_p, s);
             q0 += S.fuse_n0;
             if (q0 >= S.uset[l + 1]) continue;
         }
@@ -1224,6 +1252,7 @@ int ilu0_apply(ilu0_t M, const double *v, double *z, int32_t first_sys, int32_t 
     hipStream_t s = (hipStream_t)stream;
     int st = ensure_workspace(M, s);
     if (st != RS_OK) return st;
+    if (M->tile_sweeps && (st = ensure_u(M, s)) != RS_OK) return st;   // the single-launch sweeps read U
     const size_t m = 3 * (size_t)M->n * n_sys;
     const double *vd = nullptr;
     st = stage_in(v, mem, M->bstage, m, s, &vd);
@@ -1327,6 +1356,7 @@ int ilu0_apply_noalloc(ilu0_t M, const double *v, double *z, int32_t first_sys, 
     int st = noalloc_scratch(&base);
     if (st != RS_OK) return st;
     hipStream_t s = (hipStream_t)stream;
+    if (M->tile_sweeps && (st = ensure_u(M, s)) != RS_OK) return st;   // the single-launch sweeps read U
     Krylov k{};
     k.vstride = rs::vec_stride(M->n);
     double *vin = (double *)(base + lay.vin), *vout = (double *)(base + lay.vout);
@@ -1391,6 +1421,7 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
     if (st != RS_OK) return st;
     st = ensure_wells(M, A, s);
     if (st != RS_OK) return st;
+    if (M->tile_sweeps && (st = ensure_u(M, s)) != RS_OK) return st;   // the single-launch sweeps read U
     const size_t m = 3 * (size_t)M->n * B;
     const double *bd = nullptr;
     st = stage_in(b, mem, M->bstage, m, s, &bd);
@@ -1571,6 +1602,7 @@ int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart,
     if (st != RS_OK) return st;
     st = ensure_wells(M, A, s);
     if (st != RS_OK) return st;
+    if (M->tile_sweeps && (st = ensure_u(M, s)) != RS_OK) return st;   // the single-launch sweeps read U
     Krylov &k = M->k;
     // basis: restart columns (the column a cycle's last step would add is
     // never used); zeroed once, so the padding of every column stays zero

@@ -155,9 +155,15 @@ void launch_gather_pairs(const double *A, size_t a_stride, double *Ap, size_t ap
 // and the factor writes every block of their reordered rows (no blocks
 // outside the preconditioner's matrix), so workgroups may collect their
 // part of Ap in LDS and store it contiguously.
+// skip_u0: with FP64 factors, rows without lower blocks store no U (their U
+// rows are their rows of A'; see launch_fill_u).
 void launch_factor_level(const DevSchedule &d, const double *A, size_t a_stride, double *Ap, double *L, double *U,
                          double *Dinv, float *Lf, float *Uf, float *Df, int32_t *bad, int q0, int q1, bool staged,
-                         int nsys, hipStream_t s);
+                         bool skip_u0, int nsys, hipStream_t s);
+// U[f] = A'[usrc[f]] for U positions [f0, f1) of every system (per-system
+// strides a_stride and u_stride, in doubles).
+void launch_fill_u(const DevSchedule &d, const double *Ap, size_t a_stride, double *U, size_t u_stride, int f0, int f1,
+                   int nsys, hipStream_t s);
 
 // Lower sweep y = L^{-1} in for L-schedule rows [q0, q1).  When fuse_p is
 // set, the input is p = r + beta (p - omega v) computed on the fly (and
@@ -228,18 +234,20 @@ void launch_xr_update(const DevSchedule &d, Krylov &k, int nsys, int spmv_varian
 enum FuseMode { FUSE_NONE = 0, FUSE_V = 1, FUSE_T = 2 };
 
 // Upper launch of the rows [0, d.fuse_n0) (U-schedule positions fuse_q0 +
-// i) fused with the product that follows the application: z_i as
-// launch_usweep, and out_i = (A' z)_i with the dot-product partials of
-// the mode (FUSE_V: (w1, out), (out, out) for v = A phat with w1 = rhat;
-// FUSE_T: the same for t = A shat with w1 = s) stored as group sums in
-// k.fpart.
+// i) from their rows of A', fused with the product that follows the
+// application: z_i as launch_usweep, and out_i = (A' z)_i with the
+// dot-product partials of the mode (FUSE_V: (w1, out), (out, out) for v =
+// A phat with w1 = rhat; FUSE_T: the same for t = A shat with w1 = s)
+// stored as group sums in k.fpart; FUSE_NONE: z alone (out, w1 unused).
 // defer as launch_usweep.  The launch takes the waves per workgroup and the
 // load kind of the SpMV shape spmv_variant; fuse_blocks(d.fuse_n0, waves)
 // workgroups.
+// st may be NULL (no phase test: every system is computed); k supplies the
+// vector stride and the partials of the product.
 template <typename T>
 void launch_usweep_spmv(const DevSchedule &d, const double *Ap, size_t a_stride, const T *Dinv, size_t d_stride,
-                        const T *y, double *z, double *out, const double *w1, Krylov &k, int nsys, int mode,
-                        int spmv_variant, bool defer, hipStream_t s, hipEvent_t ev0 = nullptr,
+                        const T *y, double *z, double *out, const double *w1, SysState *st, Krylov &k, int nsys,
+                        int mode, int spmv_variant, bool defer, hipStream_t s, hipEvent_t ev0 = nullptr,
                         hipEvent_t ev1 = nullptr);
 inline int fuse_blocks(int n0, int waves) { return std::max(1, row_blocks(n0, waves)); }
 // x_orig[perm[i]] = x'[i]; then r = b - A x_orig with the caller's A, and the

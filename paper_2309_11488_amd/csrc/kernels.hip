@@ -436,7 +436,7 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
                                                               double *__restrict__ L, double *__restrict__ U,
                                                               double *__restrict__ Dinv, float *__restrict__ Lf,
                                                               float *__restrict__ Uf, float *__restrict__ Df,
-                                                              int32_t *__restrict__ bad, int q0, int q1) {
+                                                              int32_t *__restrict__ bad, int q0, int q1, int skip_u0) {
     __shared__ double sap[STAGED ? kApCap * 9 : 1];
     int sys, bx;
     xcd_map(sys, bx);
@@ -525,7 +525,7 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
             // with FP32 factors the FP64 U is only read by later levels'
             // updates, which take a row without lower blocks from the
             // reordered copy instead
-            const bool keep_u = !F32 || e1 > e0;
+            const bool keep_u = e1 > e0 || (!F32 && !skip_u0);
 #pragma unroll
             for (int t = 0; t < kFactorMax; ++t)
                 if (f0 + t < f1) {
@@ -1004,7 +1004,9 @@ constexpr int kFuseCapPerWave = 160;
 //                    the diagonal first: the same terms, another rounding),
 // plus that product's dot-product partials (MODE SPMV_V: (rhat, v) with w1 =
 // rhat; SPMV_T: (s, t) and (t, t) with w1 = s), reduced to group sums as
-// k_spmv does.  Every upper column of such a row is a row with lower blocks,
+// k_spmv does.  MODE SPMV_PLAIN gives the sweep alone (a preconditioner
+// application outside BiCGStab's fused iteration; with FP64 factors the
+// factorisation then stores no U for these rows).  Every upper column of such a row is a row with lower blocks,
 // whose z the earlier upper levels or the lower launches have finished.
 // defer: the phase test waits until the walk's loads are in flight (the
 // iteration's first application).
@@ -1018,13 +1020,15 @@ k_usweep_spmv(DevSchedule d, const double *__restrict__ Ap, size_t a_stride, con
     __shared__ Stage<double, CAP, NT> sv;
     int sys, bx;
     xcd_map(sys, bx);
-    if (!defer && st[sys].phase != PH_RUN) return;
+    // st may be NULL (an application outside a solve: no phase test)
+    if (!defer && st && st[sys].phase != PH_RUN) return;
     const int n0 = d.fuse_n0;
     const RowLane rl = row_lane<W>(bx, 0, n0);
     const int qb0 = bx * W * kRowsPerWave, qb1 = min(qb0 + W * kRowsPerWave, n0);
     const size_t vo = (size_t)sys * vstride;
     const size_t k = vo + 3 * (size_t)rl.q + rl.r;
     const double *As = Ap + (size_t)sys * a_stride;
+    constexpr bool PRODUCT = MODE != SPMV_PLAIN;
     T acc = 0;
     T dq[3] = {0, 0, 0};
     double w = 0.0;
@@ -1032,7 +1036,7 @@ k_usweep_spmv(DevSchedule d, const double *__restrict__ Ap, size_t a_stride, con
         acc = y[k];
         const T *dp = Dinv + (size_t)sys * d_stride + (size_t)(d.fuse_q0 + rl.q) * 9 + 3 * rl.r;
         dq[0] = dp[0]; dq[1] = dp[1]; dq[2] = dp[2];
-        w = w1[k];
+        if (PRODUCT) w = w1[k];
     }
     const int e0 = d.prow[qb0], e1 = d.prow[qb1];
     // the lane's row: diagonal at my0, upper blocks [my0 + 1, my1)
@@ -1046,7 +1050,7 @@ k_usweep_spmv(DevSchedule d, const double *__restrict__ Ap, size_t a_stride, con
         const int shift = stage_copy<double, CAP, NT, NTL>(As, d.pcol, base, cnt, sv);
         __syncthreads();
         const double *vals = (const double *)sv.v + shift;
-        if (rl.act && my0 >= base && my0 < base + cnt) {
+        if (PRODUCT && rl.act && my0 >= base && my0 < base + cnt) {
             const double *b = vals + (my0 - base) * 9 + 3 * rl.r;
             dg[0] = b[0]; dg[1] = b[1]; dg[2] = b[2];
         }
@@ -1064,14 +1068,18 @@ k_usweep_spmv(DevSchedule d, const double *__restrict__ Ap, size_t a_stride, con
                 if (e + u < hi) {
                     const double *b = vals + (e + u - base) * 9 + 3 * rl.r;
                     acc -= dot3((T)b[0], (T)b[1], (T)b[2], (T)xv[u][0], (T)xv[u][1], (T)xv[u][2]);
-                    av += dot3(b[0], b[1], b[2], xv[u][0], xv[u][1], xv[u][2]);
+                    if (PRODUCT) av += dot3(b[0], b[1], b[2], xv[u][0], xv[u][1], xv[u][2]);
                 }
         }
     }
     asm volatile("" ::"v"(acc), "v"(av));
-    if (st[sys].phase != PH_RUN) return;
+    if (st && st[sys].phase != PH_RUN) return;
     const T t0 = __shfl(acc, rl.base, 64), t1 = __shfl(acc, rl.base + 1, 64), t2 = __shfl(acc, rl.base + 2, 64);
     const double zr = (double)dot3(dq[0], dq[1], dq[2], t0, t1, t2);
+    if (!PRODUCT) {
+        if (rl.act) z[k] = zr;
+        return;
+    }
     const double z0 = __shfl(zr, rl.base, 64), z1 = __shfl(zr, rl.base + 1, 64), z2 = __shfl(zr, rl.base + 2, 64);
     av += dot3(dg[0], dg[1], dg[2], z0, z1, z2);
     double v[2] = {0.0, 0.0};
@@ -1582,6 +1590,20 @@ __global__ void __launch_bounds__(kGmThreads) k_gm_restart(GmWork g, const doubl
     }
 }
 
+// U[f] = A'[usrc[f]] for U positions [f0, f1) of every system: the U blocks
+// of rows without lower blocks, equal to their blocks of A', for the
+// consumers that read U (single-launch sweeps, the host copy of the factors)
+// when the FP64 factorisation did not store them.
+__global__ void k_fill_u(const int32_t *__restrict__ usrc, const double *__restrict__ Ap, size_t a_stride,
+                         double *__restrict__ U, size_t u_stride, int f0, int f1) {
+    const int sys = blockIdx.y;
+    const size_t total = (size_t)(f1 - f0) * 9;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        const size_t f = f0 + t / 9, e = t % 9;
+        U[sys * u_stride + f * 9 + e] = Ap[sys * a_stride + (size_t)usrc[f] * 9 + e];
+    }
+}
+
 // p[0 .. count) = value.
 __global__ void k_fill_u32(uint32_t *__restrict__ p, size_t count, uint32_t value) {
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x)
@@ -1659,12 +1681,12 @@ void launch_gather_pairs(const double *A, size_t a_stride, double *Ap, size_t ap
 
 void launch_factor_level(const DevSchedule &d, const double *A, size_t a_stride, double *Ap, double *L, double *U,
                          double *Dinv, float *Lf, float *Uf, float *Df, int32_t *bad, int q0, int q1, bool staged,
-                         int nsys, hipStream_t s) {
+                         bool skip_u0, int nsys, hipStream_t s) {
     if (q1 <= q0 || nsys <= 0) return;
     const dim3 g(row_blocks(q1 - q0), nsys);
     auto go = [&](auto F32, auto STG) {
         k_factor_level<decltype(F32)::value, decltype(STG)::value><<<g, kRowThreads, 0, s>>>(
-            d, A, a_stride, Ap, L, U, Dinv, Lf, Uf, Df, bad, q0, q1);
+            d, A, a_stride, Ap, L, U, Dinv, Lf, Uf, Df, bad, q0, q1, skip_u0 ? 1 : 0);
     };
     using T = std::true_type;
     using F = std::false_type;
@@ -1838,8 +1860,8 @@ void launch_xr_update(const DevSchedule &d, Krylov &k, int nsys, int spmv_varian
 
 template <typename T>
 void launch_usweep_spmv(const DevSchedule &d, const double *Ap, size_t a_stride, const T *Dinv, size_t d_stride,
-                        const T *y, double *z, double *out, const double *w1, Krylov &k, int nsys, int mode,
-                        int spmv_variant, bool defer, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                        const T *y, double *z, double *out, const double *w1, SysState *st, Krylov &k, int nsys,
+                        int mode, int spmv_variant, bool defer, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (d.fuse_n0 <= 0 || nsys <= 0) return;
     // the SpMV's launch shape: its waves per workgroup, and non-temporal
     // matrix loads for the shapes that use them (direct shapes stage too:
@@ -1849,25 +1871,32 @@ void launch_usweep_spmv(const DevSchedule &d, const double *Ap, size_t a_stride,
         constexpr bool nt = decltype(ST)::value == 2;
         const dim3 g(fuse_blocks(d.fuse_n0, w), nsys), b(64 * w);
         auto go = [&](auto kern) {
-            launch_ev(kern, g, b, s, ev0, ev1, d, Ap, a_stride, Dinv, d_stride, y, z, out, w1, k.vstride, k.st,
+            launch_ev(kern, g, b, s, ev0, ev1, d, Ap, a_stride, Dinv, d_stride, y, z, out, w1, k.vstride, st,
                       k.fpart, k.fpart_stride, k.tickets, k.ticket_stride, defer ? 1 : 0);
         };
         if (mode == FUSE_V) go(k_usweep_spmv<T, SPMV_V, w, nt>);
-        else go(k_usweep_spmv<T, SPMV_T, w, nt>);
+        else if (mode == FUSE_T) go(k_usweep_spmv<T, SPMV_T, w, nt>);
+        else go(k_usweep_spmv<T, SPMV_PLAIN, w, nt>);
     });
 }
 template void launch_usweep_spmv<double>(const DevSchedule &, const double *, size_t, const double *, size_t,
-                                         const double *, double *, double *, const double *, Krylov &, int, int,
-                                         int, bool, hipStream_t, hipEvent_t, hipEvent_t);
+                                         const double *, double *, double *, const double *, SysState *, Krylov &,
+                                         int, int, int, bool, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_usweep_spmv<float>(const DevSchedule &, const double *, size_t, const float *, size_t,
-                                        const float *, double *, double *, const double *, Krylov &, int, int,
-                                        int, bool, hipStream_t, hipEvent_t, hipEvent_t);
+                                        const float *, double *, double *, const double *, SysState *, Krylov &,
+                                        int, int, int, bool, hipStream_t, hipEvent_t, hipEvent_t);
 
 void launch_permute_vec(const int32_t *perm, const double *in, double *out, int n, size_t vstride, int nsys,
                         bool scatter, hipStream_t s) {
     if (n <= 0 || nsys <= 0) return;
     k_permute_vec<<<dim3(copy_blocks(3 * (size_t)n), nsys), 256, 0, s>>>(perm, in, out, n, vstride,
                                                                          scatter ? 1 : 0);
+}
+
+void launch_fill_u(const DevSchedule &d, const double *Ap, size_t a_stride, double *U, size_t u_stride, int f0, int f1,
+                   int nsys, hipStream_t s) {
+    if (f1 <= f0 || nsys <= 0) return;
+    k_fill_u<<<dim3(copy_blocks((size_t)(f1 - f0) * 9), nsys), 256, 0, s>>>(d.usrc, Ap, a_stride, U, u_stride, f0, f1);
 }
 
 void launch_fill_u32(uint32_t *p, size_t count, uint32_t value, hipStream_t s) {

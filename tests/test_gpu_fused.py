@@ -138,3 +138,36 @@ def test_c3_fused_and_unfused_at_full_size():
     assert abs(inf[0]["half_steps"] - iu[0]["half_steps"]) <= max(2, 0.05 * iu[0]["half_steps"])
     xo, _ = oracle.solve(s.rowptr, s.colidx, s.vals[0], b, ordering=rs.ORDER_GRAPH_COLOUR, reduction=1e-10)
     assert np.linalg.norm(xf[0] - xo) <= 1e-8 * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("precision", [rs.PREC_FP64, rs.PREC_FP32_FACTORS])
+def test_apply_outside_a_solve_ignores_the_solvers_state(precision):
+    """With FP64 factors the upper launch of the rows without lower blocks
+    reads their rows of A' (the factorisation stores no U for them) in every
+    application.  A preconditioner application after a finished solve (whose
+    systems are all done) and GMRES's end-of-cycle application compute every
+    system: ilu0_apply gives the same bits before and after a solve, with
+    one launch per level and with single-launch sweeps (which read U, filled
+    from A' on first use)."""
+    s = make_ensemble(12, 10, 7, seeds=[41, 42, 43])
+    v = np.random.default_rng(3).standard_normal((s.batch, s.n, 3))
+    with rs.Solver(s.rowptr, s.colidx, s.vals, ordering=rs.ORDER_GRAPH_COLOUR, precision=precision) as sol:
+        sol.factor()
+        assert rs.ilu0_get_option(sol.M, rs.OPT_FUSED_ROWS) > 0
+        z0 = rs.ilu0_apply(sol.M, v, None, 0, s.batch)
+        sol.solve(s.b[:, 0], reduction=1e-8)
+        z1 = rs.ilu0_apply(sol.M, v, None, 0, s.batch)
+        rs.ilu0_set_option(sol.M, rs.OPT_SWEEP_TILES, 1)
+        z2 = rs.ilu0_apply(sol.M, v, None, 0, s.batch)
+        sol.factor()                                   # U of the fused rows dropped again
+        z3 = rs.ilu0_apply(sol.M, v, None, 0, s.batch)
+        lu, dinv = rs.ilu0_get_factors(sol.M, 1, s.n, s.nnzb)
+    assert np.array_equal(z0, z1) and np.array_equal(z0, z2) and np.array_equal(z0, z3)
+    perm = oracle.ordering_perm(s.rowptr, s.colidx, rs.ORDER_GRAPH_COLOUR)
+    prow, pcol, pv = oracle.permute(s.rowptr, s.colidx, s.vals[1], perm)
+    st, _, olu, odinv = oracle.ilu0(prow, pcol, pv)
+    assert st == oracle.OK
+    if precision == rs.PREC_FP64:       # U of the fused rows, filled from A', is the oracle's U
+        offd = np.array([pcol[p] != i for i in range(s.n) for p in range(prow[i], prow[i + 1])], bool)
+        assert np.abs(lu[offd] - olu[offd]).max() <= 1e-12 * np.abs(olu[offd]).max()
+        assert np.abs(dinv - odinv).max() <= 1e-12 * np.abs(odinv).max()
