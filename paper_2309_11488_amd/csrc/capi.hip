@@ -258,9 +258,11 @@ struct rs_ilu0 {
     int sweep_variant = rs::RV_W4_LDS;  // launch shape of the per-level sweeps
     int reduce_split = 0;               // RS_OPT_REDUCE_SPLIT
     bool fuse_spmv = true;              // RS_OPT_FUSE_SPMV
-    // FP64 factors of a pattern with fused rows: the factorisation stored no
-    // U for those rows (their upper launches read A'); U is filled from A'
-    // when a consumer of U needs it (single-launch sweeps, ilu0_get_factors)
+    // a pattern with fused rows: the factorisation stored no U of the
+    // factor type for those rows (their fused upper launches read A'); it is
+    // filled from A' when a consumer of U needs it (single-launch sweeps,
+    // per-level sweeps of FP32 factors outside the fused iteration,
+    // ilu0_get_factors)
     bool u_missing = false;
     // the wells of the matrix last solved with, in the new numbering
     const rs_bcsr *wells_of = nullptr;
@@ -718,17 +720,29 @@ int ilu0_get_option(ilu0_t M, int32_t option, int32_t *value) {
     }
 }
 
-// U blocks of the fused rows, when the FP64 factorisation did not store
-// them, for a consumer that reads U: copied from A' on `s` (once per
-// factorisation).
+// U blocks of the fused rows, when the factorisation did not store them,
+// for a consumer that reads U: copied from A' (rounded to FP32 with FP32
+// factors) on `s`, once per factorisation.
 static int ensure_u(ilu0_t M, hipStream_t s) {
     if (!M->u_missing) return RS_OK;
     const rs::Schedule &S = M->an->sch;
-    rs::launch_fill_u(M->an->dev, M->pvals.as<double>(), (size_t)M->nnzb * 9, M->U.as<double>(), (size_t)S.nU * 9,
-                      S.uptr[S.fuse_q0], S.uptr[S.fuse_q0 + S.fuse_n0], M->batch, s);
+    const int f0 = S.uptr[S.fuse_q0], f1 = S.uptr[S.fuse_q0 + S.fuse_n0];
+    if (M->precision == RS_PREC_FP32_FACTORS)
+        rs::launch_fill_u<float>(M->an->dev, M->pvals.as<double>(), (size_t)M->nnzb * 9, M->Uf.as<float>(),
+                                 (size_t)S.nU * 9, f0, f1, M->batch, s);
+    else
+        rs::launch_fill_u<double>(M->an->dev, M->pvals.as<double>(), (size_t)M->nnzb * 9, M->U.as<double>(),
+                                  (size_t)S.nU * 9, f0, f1, M->batch, s);
     HIP_TRY(hipGetLastError());
     M->u_missing = false;
     return RS_OK;
+}
+
+// Whether the coming launches read U of the fused rows: single-launch
+// sweeps always, and with FP32 factors every upper launch outside BiCGStab's
+// fused iteration (per-level upper launches of FP64 factors read A').
+static bool reads_u(const rs_ilu0 *M, bool fused) {
+    return M->tile_sweeps || (M->precision == RS_PREC_FP32_FACTORS && !fused);
 }
 
 static int check_pair(ilu0_t M, bcsr_t A) {
@@ -774,9 +788,9 @@ int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *ba
         rs::launch_gather_pairs(A->vals.as<double>(), per, M->pvals.as<double>(), per, d.rest_dst, d.rest_src,
                                 d.nrest, M->batch, s);
         const bool f32 = precision == RS_PREC_FP32_FACTORS;
-        // FP64 U of the fused rows is their rows of A', which their upper
-        // launches read instead
-        const bool skip_u0 = !f32 && S.fuse_n0 > 0;
+        // the U of the fused rows is their rows of A', which their upper
+        // launches read instead (filled in later for a consumer of U)
+        const bool skip_u0 = S.fuse_n0 > 0;
         for (int l = 0; l < S.nl_levels; ++l)
             rs::launch_factor_level(d, A->vals.as<double>(), per, M->pvals.as<double>(), M->L.as<double>(),
                                     M->U.as<double>(), M->Dinv.as<double>(), f32 ? M->Lf.as<float>() : nullptr,
@@ -1252,7 +1266,7 @@ int ilu0_apply(ilu0_t M, const double *v, double *z, int32_t first_sys, int32_t 
     hipStream_t s = (hipStream_t)stream;
     int st = ensure_workspace(M, s);
     if (st != RS_OK) return st;
-    if (M->tile_sweeps && (st = ensure_u(M, s)) != RS_OK) return st;   // the single-launch sweeps read U
+    if (reads_u(M, false) && (st = ensure_u(M, s)) != RS_OK) return st;
     const size_t m = 3 * (size_t)M->n * n_sys;
     const double *vd = nullptr;
     st = stage_in(v, mem, M->bstage, m, s, &vd);
@@ -1356,7 +1370,7 @@ int ilu0_apply_noalloc(ilu0_t M, const double *v, double *z, int32_t first_sys, 
     int st = noalloc_scratch(&base);
     if (st != RS_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    if (M->tile_sweeps && (st = ensure_u(M, s)) != RS_OK) return st;   // the single-launch sweeps read U
+    if (reads_u(M, false) && (st = ensure_u(M, s)) != RS_OK) return st;
     Krylov k{};
     k.vstride = rs::vec_stride(M->n);
     double *vin = (double *)(base + lay.vin), *vout = (double *)(base + lay.vout);
@@ -1421,7 +1435,7 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
     if (st != RS_OK) return st;
     st = ensure_wells(M, A, s);
     if (st != RS_OK) return st;
-    if (M->tile_sweeps && (st = ensure_u(M, s)) != RS_OK) return st;   // the single-launch sweeps read U
+    if (reads_u(M, fused_iteration(M)) && (st = ensure_u(M, s)) != RS_OK) return st;
     const size_t m = 3 * (size_t)M->n * B;
     const double *bd = nullptr;
     st = stage_in(b, mem, M->bstage, m, s, &bd);
@@ -1602,7 +1616,7 @@ int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart,
     if (st != RS_OK) return st;
     st = ensure_wells(M, A, s);
     if (st != RS_OK) return st;
-    if (M->tile_sweeps && (st = ensure_u(M, s)) != RS_OK) return st;   // the single-launch sweeps read U
+    if (reads_u(M, false) && (st = ensure_u(M, s)) != RS_OK) return st;
     Krylov &k = M->k;
     // basis: restart columns (the column a cycle's last step would add is
     // never used); zeroed once, so the padding of every column stays zero

@@ -155,14 +155,16 @@ void launch_gather_pairs(const double *A, size_t a_stride, double *Ap, size_t ap
 // and the factor writes every block of their reordered rows (no blocks
 // outside the preconditioner's matrix), so workgroups may collect their
 // part of Ap in LDS and store it contiguously.
-// skip_u0: with FP64 factors, rows without lower blocks store no U (their U
-// rows are their rows of A'; see launch_fill_u).
+// skip_u0: rows without lower blocks store no U in the factor type (FP64 U,
+// or the FP32 U of FP32 factors; their U rows are their rows of A': see
+// launch_fill_u).
 void launch_factor_level(const DevSchedule &d, const double *A, size_t a_stride, double *Ap, double *L, double *U,
                          double *Dinv, float *Lf, float *Uf, float *Df, int32_t *bad, int q0, int q1, bool staged,
                          bool skip_u0, int nsys, hipStream_t s);
-// U[f] = A'[usrc[f]] for U positions [f0, f1) of every system (per-system
-// strides a_stride and u_stride, in doubles).
-void launch_fill_u(const DevSchedule &d, const double *Ap, size_t a_stride, double *U, size_t u_stride, int f0, int f1,
+// U[f] = A'[usrc[f]], rounded to T, for U positions [f0, f1) of every
+// system (per-system strides a_stride and u_stride, in elements).
+template <typename T>
+void launch_fill_u(const DevSchedule &d, const double *Ap, size_t a_stride, T *U, size_t u_stride, int f0, int f1,
                    int nsys, hipStream_t s);
 
 // Lower sweep y = L^{-1} in for L-schedule rows [q0, q1).  When fuse_p is

@@ -530,7 +530,7 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
             for (int t = 0; t < kFactorMax; ++t)
                 if (f0 + t < f1) {
                     if (keep_u) row3_store(Us + (size_t)(f0 + t) * 9 + 3 * r, uv[t]);
-                    if (F32) row3_store(Uf + ((size_t)sys * d.nU + f0 + t) * 9 + 3 * r, uv[t]);
+                    if (F32 && (e1 > e0 || !skip_u0)) row3_store(Uf + ((size_t)sys * d.nU + f0 + t) * 9 + 3 * r, uv[t]);
                 }
         } else {
             // long rows: the same steps on the row's blocks in global memory
@@ -1590,17 +1590,19 @@ __global__ void __launch_bounds__(kGmThreads) k_gm_restart(GmWork g, const doubl
     }
 }
 
-// U[f] = A'[usrc[f]] for U positions [f0, f1) of every system: the U blocks
-// of rows without lower blocks, equal to their blocks of A', for the
-// consumers that read U (single-launch sweeps, the host copy of the factors)
-// when the FP64 factorisation did not store them.
+// U[f] = A'[usrc[f]] (in the factor type T) for U positions [f0, f1) of
+// every system: the U blocks of rows without lower blocks, equal to their
+// blocks of A', for the consumers that read U (per-level sweeps of FP32
+// factors outside the fused iteration, single-launch sweeps, the host copy
+// of the factors) when the factorisation did not store them.
+template <typename T>
 __global__ void k_fill_u(const int32_t *__restrict__ usrc, const double *__restrict__ Ap, size_t a_stride,
-                         double *__restrict__ U, size_t u_stride, int f0, int f1) {
+                         T *__restrict__ U, size_t u_stride, int f0, int f1) {
     const int sys = blockIdx.y;
     const size_t total = (size_t)(f1 - f0) * 9;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
         const size_t f = f0 + t / 9, e = t % 9;
-        U[sys * u_stride + f * 9 + e] = Ap[sys * a_stride + (size_t)usrc[f] * 9 + e];
+        U[sys * u_stride + f * 9 + e] = (T)Ap[sys * a_stride + (size_t)usrc[f] * 9 + e];
     }
 }
 
@@ -1893,11 +1895,17 @@ void launch_permute_vec(const int32_t *perm, const double *in, double *out, int 
                                                                          scatter ? 1 : 0);
 }
 
-void launch_fill_u(const DevSchedule &d, const double *Ap, size_t a_stride, double *U, size_t u_stride, int f0, int f1,
+template <typename T>
+void launch_fill_u(const DevSchedule &d, const double *Ap, size_t a_stride, T *U, size_t u_stride, int f0, int f1,
                    int nsys, hipStream_t s) {
     if (f1 <= f0 || nsys <= 0) return;
-    k_fill_u<<<dim3(copy_blocks((size_t)(f1 - f0) * 9), nsys), 256, 0, s>>>(d.usrc, Ap, a_stride, U, u_stride, f0, f1);
+    k_fill_u<T><<<dim3(copy_blocks((size_t)(f1 - f0) * 9), nsys), 256, 0, s>>>(d.usrc, Ap, a_stride, U, u_stride, f0,
+                                                                             f1);
 }
+template void launch_fill_u<double>(const DevSchedule &, const double *, size_t, double *, size_t, int, int, int,
+                                    hipStream_t);
+template void launch_fill_u<float>(const DevSchedule &, const double *, size_t, float *, size_t, int, int, int,
+                                   hipStream_t);
 
 void launch_fill_u32(uint32_t *p, size_t count, uint32_t value, hipStream_t s) {
     if (count == 0) return;
