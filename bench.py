@@ -107,6 +107,9 @@ def parse(argv=None):
     ap.add_argument("--fuse", type=int, default=1, choices=[0, 1],
                     help="RS_OPT_FUSE_SPMV: the upper launch of the rows without lower blocks also forms their "
                          "rows of the following SpMV (where the pattern allows it)")
+    ap.add_argument("--y-input", type=int, default=1, choices=[0, 1],
+                    help="RS_OPT_Y_INPUT: the applications read the y of the rows without lower blocks from their "
+                         "input and store no y (where the pattern allows it)")
     ap.add_argument("--slots", type=int, default=8, help="request stream: concurrent worker slots")
     ap.add_argument("--requests", type=int, default=2000, help="request stream (c5): requests per arrival rate")
     ap.add_argument("--loads", default="0.5,0.8,1.0",
@@ -263,6 +266,7 @@ class Problem:
         self.nl, self.nu = rs.ilu0_get_sweep_levels(self.base)
         _, self.n_sets, _ = rs.ilu0_get_schedule(self.base, s.n)
         self.fused_rows = rs.ilu0_get_option(self.base, rs.OPT_FUSED_ROWS)
+        self.y_input_pattern = rs.ilu0_get_option(self.base, rs.OPT_Y_INPUT_PATTERN)
 
     def _analyse(self):
         rs = self.rs
@@ -279,6 +283,7 @@ class Problem:
         st, bad = rs.ilu0_factor(M, self.A, PREC[precision])
         assert st == rs.OK, (st, bad)
         rs.ilu0_set_option(M, rs.OPT_FUSE_SPMV, self.args.fuse)
+        rs.ilu0_set_option(M, rs.OPT_Y_INPUT, self.args.y_input)
         tune = None
         if not self.args.no_tune:
             t = time.perf_counter()
@@ -509,6 +514,7 @@ def main():
                    "reduction": reduction, "max_iter": 200, "n_brows": s.n, "nnzb": s.nnzb, "batch": s.batch,
                    "rhs_per_step": rhs, "sets": P.n_sets, "sweep_levels": [P.nl, P.nu],
                    "fuse_spmv": args.fuse, "fused_rows": P.fused_rows,
+                   "y_input": args.y_input, "y_input_pattern": P.y_input_pattern,
                    "jacobi_partitions": args.jacobi or None,
                    "mean_half_steps": head["mean_half_steps"],
                    "max_true_rel_residual": head["max_true_rel_residual"], "statuses": head["statuses"],

@@ -133,8 +133,21 @@ enum rs_option {
                                 changes: the solve agrees with the unfused one to rounding.
                                 Used with per-level sweeps, reduction split 0 and no separate
                                 wells; 0: never */
-    RS_OPT_FUSED_ROWS = 10   /* read only (ilu0_get_option): how many rows the analysed pattern
+    RS_OPT_FUSED_ROWS = 10,  /* read only (ilu0_get_option): how many rows the analysed pattern
                                 lets RS_OPT_FUSE_SPMV fuse (0: none) */
+    RS_OPT_Y_INPUT = 11,     /* 1 (default): where the analysed pattern allows it (RS_OPT_Y_INPUT_PATTERN),
+                                a preconditioner application stores no intermediate y = L^-1 v.
+                                The rows without lower blocks have y = v, so the launches read
+                                their v directly and their lower launch is left out (BiCGStab's
+                                first application keeps one vector launch that updates p on
+                                those rows); every other row finishes in the lower launch.  Used
+                                with per-level sweeps when the upper launch of those rows reads
+                                A' (FP64 factors, or the RS_OPT_FUSE_SPMV iteration).  The same
+                                bits either way; 0: always store y */
+    RS_OPT_Y_INPUT_PATTERN = 12  /* read only: 1 when the analysed pattern has two lower levels,
+                                the first being the RS_OPT_FUSED_ROWS rows, and none of the other
+                                rows holds an upper block (graph colouring of a bipartite
+                                pattern such as a 7-point grid) */
 };
 
 /* Per-system outcome of bicgstab_solve and gmres_solve. */

@@ -69,6 +69,14 @@ struct Schedule {
     // partition).  fuse_nnz = A' blocks of those rows.
     int fuse_n0 = 0, fuse_q0 = 0, fuse_level = -1;
     long long fuse_nnz = 0;
+    // y_in = 1: besides the fuse_n0 rows there are exactly two lower levels
+    // (every other row's lower neighbours are among those rows) and none of
+    // the other rows holds an upper block.  The y of a row without lower
+    // blocks is the sweep's input itself, and every other row finishes in
+    // the lower launch (z_i = inv(U_ii) y_i), so an application needs no
+    // stored y: the launches read the input instead (bipartite patterns
+    // under graph colouring, e.g. the 7-point grids).
+    int y_in = 0;
     // row tiles of the single-launch sweeps: tile t covers schedule
     // positions [start[t], start[t+1]) inside one level, and must wait for
     // the tiles dep[dep_ptr[t] .. dep_ptr[t+1]) (earlier tiles holding rows

@@ -258,6 +258,7 @@ struct rs_ilu0 {
     int sweep_variant = rs::RV_W4_LDS;  // launch shape of the per-level sweeps
     int reduce_split = 0;               // RS_OPT_REDUCE_SPLIT
     bool fuse_spmv = true;              // RS_OPT_FUSE_SPMV
+    bool y_input = true;                // RS_OPT_Y_INPUT
     // a pattern with fused rows: the factorisation stored no U of the
     // factor type for those rows (their fused upper launches read A'); it is
     // filled from A' when a consumer of U needs it (single-launch sweeps,
@@ -280,12 +281,12 @@ struct rs_ilu0 {
     // every setting a captured iteration depends on
     struct GraphKey {
         int precision = -1, tile_sweeps = 0, spmv_variant = 0, sweep_variant = 0, split = 0, sweep_grid = 0;
-        int spin = 0, fuse = 0;
+        int spin = 0, fuse = 0, yin = 0;
         long long wells = 0;   // 0: no wells, else the wells' version + 1
         bool operator==(const GraphKey &o) const {
             return precision == o.precision && tile_sweeps == o.tile_sweeps && spmv_variant == o.spmv_variant &&
                    sweep_variant == o.sweep_variant && split == o.split && sweep_grid == o.sweep_grid &&
-                   spin == o.spin && fuse == o.fuse && wells == o.wells;
+                   spin == o.spin && fuse == o.fuse && yin == o.yin && wells == o.wells;
         }
     };
     struct Segment {
@@ -696,6 +697,10 @@ int ilu0_set_option(ilu0_t M, int32_t option, int32_t value) {
         if (value != 0 && value != 1) break;
         M->fuse_spmv = value != 0;
         return RS_OK;
+    case RS_OPT_Y_INPUT:
+        if (value != 0 && value != 1) break;
+        M->y_input = value != 0;
+        return RS_OK;
     default:
         break;
     }
@@ -716,6 +721,8 @@ int ilu0_get_option(ilu0_t M, int32_t option, int32_t *value) {
     case RS_OPT_SPIN_LIMIT: *value = M->spin_limit; return RS_OK;
     case RS_OPT_FUSE_SPMV: *value = M->fuse_spmv ? 1 : 0; return RS_OK;
     case RS_OPT_FUSED_ROWS: *value = M->an->sch.fuse_n0; return RS_OK;
+    case RS_OPT_Y_INPUT: *value = M->y_input ? 1 : 0; return RS_OK;
+    case RS_OPT_Y_INPUT_PATTERN: *value = M->an->sch.y_in; return RS_OK;
     default: return fail(RS_INVALID_ARG, "ilu0_get_option: unknown option");
     }
 }
@@ -1003,11 +1010,21 @@ static double upper_bytes(ilu0_t M, double tb, int nsys) {
     return nsys * ((9 * tb + 4) * ((double)S.nU + M->n) + 48.0 * M->n - fold_bytes(M, tb));
 }
 
+// Whether an application reads the y of the rows without lower blocks from
+// its input instead of storing it (Schedule::y_in): per-level sweeps, and
+// the upper launch of those rows reads A' (FP64 factors, or BiCGStab's
+// fused iteration), which takes y in FP64.
+static bool y_from_input(const rs_ilu0 *M, bool fp64, bool fused) {
+    return M->y_input && M->an->sch.y_in && !M->tile_sweeps && (fp64 || fused);
+}
+
 // Lower sweep of one preconditioner application M^{-1} in -> out (new
-// order).  Timed as one unit (events around its launches).
+// order).  Timed as one unit (events around its launches).  yin (see
+// y_from_input): the first level's rows take y = their input (p, updated
+// first, or `in`) and the second level's launch reads it from there.
 template <typename T>
 static void lower_levels(ilu0_t M, const T *L, const T *D, const double *in, double *out, bool fuse_p, Krylov &k,
-                         SysState *st, int nsys, hipStream_t s, bool prof = true) {
+                         SysState *st, int nsys, hipStream_t s, bool prof = true, bool yin = false) {
     const rs::Schedule &S = M->an->sch;
     const size_t vs = k.vstride;
     T *y = (T *)k.y;
@@ -1020,9 +1037,16 @@ static void lower_levels(ilu0_t M, const T *L, const T *D, const double *in, dou
     // the upper sweep's first level (rows without upper blocks) is finished
     // inside the lower sweep's launches
     const int u0_end = S.nu_levels > 0 ? S.uset[1] : 0;
+    if (yin) {
+        if (fuse_p) rs::launch_p_update(M->an->dev, k, nsys, s);
+        rs::launch_lsweep<T>(M->an->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, S.lset[1],
+                             S.lset[2], nsys, M->sweep_variant, D, (size_t)M->n * 9, out, u0_end,
+                             fuse_p ? k.p : in, s);
+        return;
+    }
     for (int l = 0; l < S.nl_levels; ++l)
         rs::launch_lsweep<T>(M->an->dev, L, (size_t)S.nL * 9, in, y, vs, fuse_p, k.r, k.v, k.p, st, S.lset[l],
-                             S.lset[l + 1], nsys, M->sweep_variant, D, (size_t)M->n * 9, out, u0_end, s);
+                             S.lset[l + 1], nsys, M->sweep_variant, D, (size_t)M->n * 9, out, u0_end, nullptr, s);
 }
 
 // Whether BiCGStab's iterations fuse the upper launch of the rows without
@@ -1042,10 +1066,12 @@ static double fused_spmv_bytes(ilu0_t M, int nsys) {
 // as one unit.  fmode != FUSE_NONE: the launch of the rows without lower
 // blocks also forms their rows of fout = A' out (the product of the
 // application's result), with the dot products against fw1.
+// yd: the input the rows without lower blocks take as y (when the lower
+// sweep ran with yin), else NULL.
 template <typename T>
 static void upper_levels(ilu0_t M, const T *U, const T *D, double *out, bool fuse_p, Krylov &k, SysState *st,
                          int nsys, hipStream_t s, bool prof = true, int fmode = rs::FUSE_NONE,
-                         double *fout = nullptr, const double *fw1 = nullptr) {
+                         double *fout = nullptr, const double *fw1 = nullptr, const double *yd = nullptr) {
     const rs::Schedule &S = M->an->sch;
     const size_t vs = k.vstride;
     const T *y = (const T *)k.y;
@@ -1064,7 +1090,7 @@ static void upper_levels(ilu0_t M, const T *U, const T *D, double *out, bool fus
         int q0 = S.uset[l];
         if (via_ap && l == S.fuse_level) {
             rs::launch_usweep_spmv<T>(M->an->dev, M->pvals.as<double>(), (size_t)M->nnzb * 9, D, (size_t)M->n * 9,
-                                      y, out, fout, fw1, st, k, nsys, fmode, M->spmv_variant, fuse_p, s);
+                                      y, yd, out, fout, fw1, st, k, nsys, fmode, M->spmv_variant, fuse_p, s);
             q0 += S.fuse_n0;
             if (q0 >= S.uset[l + 1]) continue;
         }
@@ -1079,8 +1105,10 @@ static void apply_levels(ilu0_t M, const T *L, const T *U, const T *D, const dou
                          Krylov &k, SysState *st, int nsys, hipStream_t s, bool prof = true) {
     const double tb = sizeof(T);
     ProfScope ps(PC_APPLY, s, lower_bytes(M, tb, nsys) + upper_bytes(M, tb, nsys), false, prof);
-    lower_levels<T>(M, L, D, in, out, fuse_p, k, st, nsys, s, prof);
-    upper_levels<T>(M, U, D, out, fuse_p, k, st, nsys, s, prof);
+    const bool yin = y_from_input(M, sizeof(T) == sizeof(double), false);
+    lower_levels<T>(M, L, D, in, out, fuse_p, k, st, nsys, s, prof, yin);
+    upper_levels<T>(M, U, D, out, fuse_p, k, st, nsys, s, prof, rs::FUSE_NONE, nullptr, nullptr,
+                    yin ? (fuse_p ? k.p : in) : nullptr);
 }
 
 // Parts of a BiCGStab iteration, in order: the two sweeps of the first
@@ -1121,6 +1149,7 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
     // with the fused upper launch, the rows without lower blocks of v and t
     // (and their bytes) move from the SpMV into the application
     const bool fz = fused_iteration(M);
+    const bool yin = y_from_input(M, sizeof(T) == sizeof(double), fz);
     const int r0 = fz ? M->an->sch.fuse_n0 : 0;
     const double fb = fz ? fused_spmv_bytes(M, B) : 0.0;
     const double spmv_bytes = B * (76 * nnzb + 52 * n) - fb;
@@ -1128,10 +1157,10 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
     {
         // an application is timed whole or not at all
         ProfScope pa(PC_APPLY, s, apply_bytes, false, (parts & P_L1) && (parts & P_U1));
-        if (parts & P_L1) lower_levels<T>(M, L, D, nullptr, k.phat, true, k, k.st, B, s);
+        if (parts & P_L1) lower_levels<T>(M, L, D, nullptr, k.phat, true, k, k.st, B, s, true, yin);
         if (parts & P_U1)
             upper_levels<T>(M, U, D, k.phat, true, k, k.st, B, s, true, fz ? rs::FUSE_V : rs::FUSE_NONE, k.v,
-                            k.rhat);
+                            k.rhat, yin ? k.p : nullptr);
     }
     if (parts & P_SPMV_V) {
         ProfScope ps(PC_SPMV_V, s, spmv_bytes, true);
@@ -1144,10 +1173,10 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
     }
     {
         ProfScope pa(PC_APPLY, s, apply_bytes, false, (parts & P_L2) && (parts & P_U2));
-        if (parts & P_L2) lower_levels<T>(M, L, D, k.s, k.shat, false, k, k.st, B, s);
+        if (parts & P_L2) lower_levels<T>(M, L, D, k.s, k.shat, false, k, k.st, B, s, true, yin);
         if (parts & P_U2)
             upper_levels<T>(M, U, D, k.shat, false, k, k.st, B, s, true, fz ? rs::FUSE_T : rs::FUSE_NONE, k.t,
-                            k.s);
+                            k.s, yin ? k.s : nullptr);
     }
     if (parts & P_SPMV_T) {
         ProfScope ps(PC_SPMV_T, s, spmv_bytes, true);
@@ -1180,6 +1209,7 @@ static int replay_segment(ilu0_t M, int parts, hipStream_t s) {
     key.sweep_grid = M->sweep_grid;
     key.spin = M->spin_limit;
     key.fuse = fused_iteration(M) ? 1 : 0;
+    key.yin = M->y_input ? 1 : 0;
     key.wells = M->wdev.nw > 0 ? (long long)M->wells_version + 1 : 0;
     rs_ilu0::Segment &seg = M->segments[parts];
     if (!seg.exec || !(seg.key == key)) {

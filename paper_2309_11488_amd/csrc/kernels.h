@@ -170,14 +170,22 @@ void launch_fill_u(const DevSchedule &d, const double *Ap, size_t a_stride, T *U
 // Lower sweep y = L^{-1} in for L-schedule rows [q0, q1).  When fuse_p is
 // set, the input is p = r + beta (p - omega v) computed on the fly (and
 // stored); otherwise `in`.  st may be NULL (no phase check).
-template <typename T>
 // When u0_end > 0, rows whose U-schedule position is below u0_end (the
 // upper sweep's first level: no upper blocks) also finish the upper sweep:
 // z_i = inv(U_ii) y_i (Dinv at d_stride per system), exactly as k_usweep.
+// yd (may be NULL): the rows' lower neighbours hold no lower blocks, so
+// their y is the application's input itself, read from yd (FP64, at
+// vstride per system) instead of y; the launch stores no y, so every row it
+// covers must finish here (U-schedule position below u0_end).
+template <typename T>
 void launch_lsweep(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
                    bool fuse_p, const double *r, const double *v, double *p, SysState *st, int q0, int q1, int nsys,
-                   int variant, const T *Dinv, size_t d_stride, double *z, int u0_end, hipStream_t s,
-                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                   int variant, const T *Dinv, size_t d_stride, double *z, int u0_end, const double *yd,
+                   hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// p = r + beta (p - omega v) for the rows [0, d.fuse_n0) of every system
+// still iterating (the lower sweep of rows without lower blocks, when the
+// sweeps read their y from p: see launch_lsweep's yd).
+void launch_p_update(const DevSchedule &d, Krylov &k, int nsys, hipStream_t s);
 
 // Upper sweep z = inv(U_ii) (y - U z) for U-schedule rows [q0, q1).
 template <typename T>
@@ -245,12 +253,13 @@ enum FuseMode { FUSE_NONE = 0, FUSE_V = 1, FUSE_T = 2 };
 // load kind of the SpMV shape spmv_variant; fuse_blocks(d.fuse_n0, waves)
 // workgroups.
 // st may be NULL (no phase test: every system is computed); k supplies the
-// vector stride and the partials of the product.
+// vector stride and the partials of the product.  yd (may be NULL): y of
+// these rows is the application's input, read from yd (FP64) instead of y.
 template <typename T>
 void launch_usweep_spmv(const DevSchedule &d, const double *Ap, size_t a_stride, const T *Dinv, size_t d_stride,
-                        const T *y, double *z, double *out, const double *w1, SysState *st, Krylov &k, int nsys,
-                        int mode, int spmv_variant, bool defer, hipStream_t s, hipEvent_t ev0 = nullptr,
-                        hipEvent_t ev1 = nullptr);
+                        const T *y, const double *yd, double *z, double *out, const double *w1, SysState *st,
+                        Krylov &k, int nsys, int mode, int spmv_variant, bool defer, hipStream_t s,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 inline int fuse_blocks(int n0, int waves) { return std::max(1, row_blocks(n0, waves)); }
 // x_orig[perm[i]] = x'[i]; then r = b - A x_orig with the caller's A, and the
 // true relative residual into the states.

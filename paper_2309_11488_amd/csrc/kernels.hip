@@ -608,14 +608,18 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
 
 // ------------------------------------------------------------------ sweeps
 
-template <typename T, bool FUSE_P, int W, int STAGE>
+// YIN: the rows' lower neighbours hold no lower blocks, so their y is the
+// application's input itself: the walk reads it from yd (FP64, rounded to
+// T as the stored y would be), and no y is stored (every row of such a
+// launch finishes here).
+template <typename T, bool FUSE_P, int W, int STAGE, bool YIN>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRowWavesPerEU, 8))) k_lsweep(DevSchedule d, const T *__restrict__ L, size_t l_stride,
                                                         const double *__restrict__ in, T *__restrict__ y,
                                                         size_t vstride, const double *__restrict__ rv,
                                                         const double *__restrict__ vv, double *__restrict__ pv,
                                                         SysState *__restrict__ st, int q0, int q1,
                                                         const T *__restrict__ Dinv, size_t d_stride,
-                                                        double *__restrict__ z, int u0_end) {
+                                                        double *__restrict__ z, int u0_end, const double *yd) {
     int sys, bx;
     xcd_map(sys, bx);
     // The fused sweep opens an iteration, which is queued only while the
@@ -647,15 +651,19 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
         const T *dp = Dinv + (size_t)sys * d_stride + (size_t)uq * 9 + 3 * rl.r;
         dq[0] = dp[0]; dq[1] = dp[1]; dq[2] = dp[2];
     }
-    acc = row_walk<W, STAGE, kSweepCapPerWave, true>(d.lptr, d.lcol, L + (size_t)sys * l_stride, qb0, qb1, rl, y + vo,
-                                                     acc);
+    if constexpr (YIN)
+        acc = row_walk<W, STAGE, kSweepCapPerWave, true>(d.lptr, d.lcol, L + (size_t)sys * l_stride, qb0, qb1, rl,
+                                                         yd + vo, acc);
+    else
+        acc = row_walk<W, STAGE, kSweepCapPerWave, true>(d.lptr, d.lcol, L + (size_t)sys * l_stride, qb0, qb1, rl,
+                                                         y + vo, acc);
     if (FUSE_P) {
         asm volatile("" ::"v"(acc));
         if (!run) return;
         if (rl.act) pv[k] = p;
     }
     // y of a row the launch finishes is read by no later launch
-    if (rl.act && uq >= u0_end) y[k] = acc;
+    if (!YIN && rl.act && uq >= u0_end) y[k] = acc;
     if (u0_end > 0) {
         // rows without upper blocks (the first level of the upper sweep)
         // finish here: z_i = inv(U_ii) y_i, the arithmetic of k_usweep
@@ -1010,10 +1018,12 @@ constexpr int kFuseCapPerWave = 160;
 // whose z the earlier upper levels or the lower launches have finished.
 // defer: the phase test waits until the walk's loads are in flight (the
 // iteration's first application).
-template <typename T, int MODE, int W, bool NTL>
+// TY: the type y is read in (T, or FP64 when y is the application's input
+// itself, rounded to T as the stored y would be).
+template <typename T, int MODE, int W, bool NTL, typename TY>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRowWavesPerEU, 8)))
 k_usweep_spmv(DevSchedule d, const double *__restrict__ Ap, size_t a_stride, const T *__restrict__ Dinv,
-              size_t d_stride, const T *__restrict__ y, double *__restrict__ z, double *__restrict__ out,
+              size_t d_stride, const TY *__restrict__ y, double *__restrict__ z, double *__restrict__ out,
               const double *__restrict__ w1, size_t vstride, SysState *__restrict__ st, double *__restrict__ part,
               size_t part_stride, uint32_t *__restrict__ tk, size_t tk_stride, int defer) {
     constexpr int CAP = kFuseCapPerWave * W, NT = 64 * W;
@@ -1033,7 +1043,7 @@ k_usweep_spmv(DevSchedule d, const double *__restrict__ Ap, size_t a_stride, con
     T dq[3] = {0, 0, 0};
     double w = 0.0;
     if (rl.act) {
-        acc = y[k];
+        acc = (T)y[k];
         const T *dp = Dinv + (size_t)sys * d_stride + (size_t)(d.fuse_q0 + rl.q) * 9 + 3 * rl.r;
         dq[0] = dp[0]; dq[1] = dp[1]; dq[2] = dp[2];
         if (PRODUCT) w = w1[k];
@@ -1184,6 +1194,35 @@ __global__ void __launch_bounds__(kVecThreads) k_setup(int n, const int32_t *__r
         else if (r0 == 0.0) { S.status = RS_OK; S.phase = PH_DONE; }
         else if (max_iter <= 0) { S.status = RS_NOT_CONVERGED; S.phase = PH_DONE; }
         else { S.status = RS_NOT_CONVERGED; S.phase = PH_RUN; }
+    }
+}
+
+// p = r + beta (p - omega v) on the first m entries of every system's
+// vectors: the rows that hold no lower blocks (the first m / 3 rows of the
+// new order), whose y is p itself, so the sweeps that follow read it from
+// p.  The same arithmetic as the p update of a fused lower sweep.  It opens
+// an iteration (queued whenever the iteration is): the phase test waits
+// until the tile's loads are in flight.  Loads past m are clamped to the
+// last entry; stores stop at m (the other rows' p is the next launch's).
+__global__ void __launch_bounds__(kVecThreads) k_p_update(Krylov k, int m) {
+    const int sys = blockIdx.y;
+    const size_t vo = (size_t)sys * k.vstride;
+    const int tiles = (m + kVecTile - 1) / kVecTile;
+    const SysState &S = k.st[sys];
+    for (int t = blockIdx.x; t < tiles; t += gridDim.x) {
+        double r[kVecItems], p[kVecItems], v[kVecItems];
+#pragma unroll
+        for (int u = 0; u < kVecItems; ++u) {
+            const size_t e = vo + min(t * kVecTile + u * kVecThreads + (int)threadIdx.x, m - 1);
+            r[u] = k.r[e]; p[u] = k.p[e]; v[u] = k.v[e];
+        }
+        if (S.phase != PH_RUN) return;
+        const double beta = S.beta, omega = S.omega;
+#pragma unroll
+        for (int u = 0; u < kVecItems; ++u) {
+            const int e = t * kVecTile + u * kVecThreads + (int)threadIdx.x;
+            if (e < m) k.p[vo + e] = r[u] + beta * (p[u] - omega * v[u]);
+        }
     }
 }
 
@@ -1702,19 +1741,24 @@ void launch_factor_level(const DevSchedule &d, const double *A, size_t a_stride,
 template <typename T>
 void launch_lsweep(const DevSchedule &d, const T *L, size_t l_stride, const double *in, T *y, size_t vstride,
                    bool fuse_p, const double *r, const double *v, double *p, SysState *st, int q0, int q1, int nsys,
-                   int variant, const T *Dinv, size_t d_stride, double *z, int u0_end, hipStream_t s, hipEvent_t ev0,
-                   hipEvent_t ev1) {
+                   int variant, const T *Dinv, size_t d_stride, double *z, int u0_end, const double *yd,
+                   hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (q1 <= q0 || nsys <= 0) return;
     with_variant(variant, [&](auto W, auto ST) {
         constexpr int w = decltype(W)::value;
         constexpr int staged = decltype(ST)::value;
         const dim3 g(row_blocks(q1 - q0, w), nsys);
-        if (fuse_p)
-            launch_ev(k_lsweep<T, true, w, staged>, g, dim3(64 * w), s, ev0, ev1, d, L, l_stride, in, y, vstride, r,
-                      v, p, st, q0, q1, Dinv, d_stride, z, u0_end);
-        else
-            launch_ev(k_lsweep<T, false, w, staged>, g, dim3(64 * w), s, ev0, ev1, d, L, l_stride, in, y, vstride, r,
-                      v, p, st, q0, q1, Dinv, d_stride, z, u0_end);
+        auto go = [&](auto kern) {
+            launch_ev(kern, g, dim3(64 * w), s, ev0, ev1, d, L, l_stride, in, y, vstride, r, v, p, st, q0, q1, Dinv,
+                      d_stride, z, u0_end, yd);
+        };
+        if (yd) {
+            if (fuse_p) go(k_lsweep<T, true, w, staged, true>);
+            else go(k_lsweep<T, false, w, staged, true>);
+        } else {
+            if (fuse_p) go(k_lsweep<T, true, w, staged, false>);
+            else go(k_lsweep<T, false, w, staged, false>);
+        }
     });
 }
 
@@ -1733,10 +1777,12 @@ void launch_usweep(const DevSchedule &d, const T *U, size_t u_stride, const T *D
 
 template void launch_lsweep<double>(const DevSchedule &, const double *, size_t, const double *, double *, size_t,
                                     bool, const double *, const double *, double *, SysState *, int, int, int, int,
-                                    const double *, size_t, double *, int, hipStream_t, hipEvent_t, hipEvent_t);
+                                    const double *, size_t, double *, int, const double *, hipStream_t, hipEvent_t,
+                                    hipEvent_t);
 template void launch_lsweep<float>(const DevSchedule &, const float *, size_t, const double *, float *, size_t, bool,
                                    const double *, const double *, double *, SysState *, int, int, int, int,
-                                   const float *, size_t, double *, int, hipStream_t, hipEvent_t, hipEvent_t);
+                                   const float *, size_t, double *, int, const double *, hipStream_t, hipEvent_t,
+                                   hipEvent_t);
 template void launch_usweep<double>(const DevSchedule &, const double *, size_t, const double *, size_t,
                                     const double *, double *, size_t, SysState *, int, int, int, int, bool,
                                     hipStream_t, hipEvent_t, hipEvent_t);
@@ -1846,6 +1892,13 @@ void launch_s_update(const DevSchedule &d, Krylov &k, int nsys, int spmv_variant
               f.offset, f.count);
 }
 
+void launch_p_update(const DevSchedule &d, Krylov &k, int nsys, hipStream_t s) {
+    const int m = 3 * d.fuse_n0;
+    if (m <= 0 || nsys <= 0) return;
+    const int g = std::min((m + kVecTile - 1) / kVecTile, kVecMaxBlocks);
+    k_p_update<<<dim3(g, nsys), kVecThreads, 0, s>>>(k, m);
+}
+
 void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
                    int split, const WellsDev &w, int r0, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     spmv_any<SPMV_T>(variant, d.n, d.prow, d.pcol, Ap, a_stride, k.shat, k.t, k.vstride, k.s, k.spart,
@@ -1862,8 +1915,9 @@ void launch_xr_update(const DevSchedule &d, Krylov &k, int nsys, int spmv_varian
 
 template <typename T>
 void launch_usweep_spmv(const DevSchedule &d, const double *Ap, size_t a_stride, const T *Dinv, size_t d_stride,
-                        const T *y, double *z, double *out, const double *w1, SysState *st, Krylov &k, int nsys,
-                        int mode, int spmv_variant, bool defer, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                        const T *y, const double *yd, double *z, double *out, const double *w1, SysState *st,
+                        Krylov &k, int nsys, int mode, int spmv_variant, bool defer, hipStream_t s, hipEvent_t ev0,
+                        hipEvent_t ev1) {
     if (d.fuse_n0 <= 0 || nsys <= 0) return;
     // the SpMV's launch shape: its waves per workgroup, and non-temporal
     // matrix loads for the shapes that use them (direct shapes stage too:
@@ -1872,21 +1926,29 @@ void launch_usweep_spmv(const DevSchedule &d, const double *Ap, size_t a_stride,
         constexpr int w = decltype(Wc)::value;
         constexpr bool nt = decltype(ST)::value == 2;
         const dim3 g(fuse_blocks(d.fuse_n0, w), nsys), b(64 * w);
-        auto go = [&](auto kern) {
-            launch_ev(kern, g, b, s, ev0, ev1, d, Ap, a_stride, Dinv, d_stride, y, z, out, w1, k.vstride, st,
+        auto go = [&](auto kern, auto yp) {
+            launch_ev(kern, g, b, s, ev0, ev1, d, Ap, a_stride, Dinv, d_stride, yp, z, out, w1, k.vstride, st,
                       k.fpart, k.fpart_stride, k.tickets, k.ticket_stride, defer ? 1 : 0);
         };
-        if (mode == FUSE_V) go(k_usweep_spmv<T, SPMV_V, w, nt>);
-        else if (mode == FUSE_T) go(k_usweep_spmv<T, SPMV_T, w, nt>);
-        else go(k_usweep_spmv<T, SPMV_PLAIN, w, nt>);
+        auto by_mode = [&](auto yp) {
+            using TY = std::remove_const_t<std::remove_pointer_t<decltype(yp)>>;
+            if (mode == FUSE_V) go(k_usweep_spmv<T, SPMV_V, w, nt, TY>, yp);
+            else if (mode == FUSE_T) go(k_usweep_spmv<T, SPMV_T, w, nt, TY>, yp);
+            else go(k_usweep_spmv<T, SPMV_PLAIN, w, nt, TY>, yp);
+        };
+        if constexpr (std::is_same_v<T, double>) by_mode(yd ? yd : y);
+        else if (yd) by_mode(yd);
+        else by_mode(y);
     });
 }
 template void launch_usweep_spmv<double>(const DevSchedule &, const double *, size_t, const double *, size_t,
-                                         const double *, double *, double *, const double *, SysState *, Krylov &,
-                                         int, int, int, bool, hipStream_t, hipEvent_t, hipEvent_t);
+                                         const double *, const double *, double *, double *, const double *,
+                                         SysState *, Krylov &, int, int, int, bool, hipStream_t, hipEvent_t,
+                                         hipEvent_t);
 template void launch_usweep_spmv<float>(const DevSchedule &, const double *, size_t, const float *, size_t,
-                                        const float *, double *, double *, const double *, SysState *, Krylov &,
-                                        int, int, int, bool, hipStream_t, hipEvent_t, hipEvent_t);
+                                        const float *, const double *, double *, double *, const double *,
+                                        SysState *, Krylov &, int, int, int, bool, hipStream_t, hipEvent_t,
+                                        hipEvent_t);
 
 void launch_permute_vec(const int32_t *perm, const double *in, double *out, int n, size_t vstride, int nsys,
                         bool scatter, hipStream_t s) {

@@ -171,3 +171,77 @@ def test_apply_outside_a_solve_ignores_the_solvers_state(precision):
         offd = np.array([pcol[p] != i for i in range(s.n) for p in range(prow[i], prow[i + 1])], bool)
         assert np.abs(lu[offd] - olu[offd]).max() <= 1e-12 * np.abs(olu[offd]).max()
         assert np.abs(dinv - odinv).max() <= 1e-12 * np.abs(odinv).max()
+
+
+def _solves(sol, b, red):
+    """BiCGStab with the fused iteration, BiCGStab without it, GMRES(5) and
+    one application per system, on the current options."""
+    out = []
+    for fuse in (1, 0):
+        rs.ilu0_set_option(sol.M, rs.OPT_FUSE_SPMV, fuse)
+        out.append(rs.bicgstab_solve(sol.M, sol.A, b, reduction=red))
+    rs.ilu0_set_option(sol.M, rs.OPT_FUSE_SPMV, 1)
+    out.append(rs.gmres_solve(sol.M, sol.A, b, restart=5, reduction=red))
+    v = np.ascontiguousarray(b.reshape(b.shape[0], -1, 3))
+    out.append(rs.ilu0_apply(sol.M, v, None, 0, b.shape[0]))
+    return out
+
+
+@pytest.mark.parametrize("precision", [rs.PREC_FP64, rs.PREC_FP32_FACTORS])
+@pytest.mark.parametrize("grid", [(20, 20, 10), (7, 5, 3), (9, 1, 1), (33, 17, 5)])
+def test_y_from_the_input_gives_the_same_bits(grid, precision):
+    """Bipartite grids under graph colouring: the applications read the y
+    of the first colour from their input and store no y (RS_OPT_Y_INPUT).
+    Every result -- BiCGStab with and without the fused iteration, GMRES
+    and a lone application, on a batch of two systems, graphs replayed --
+    has the same bits as with y stored, and the solve meets the oracle."""
+    s = make_ensemble(*grid, seeds=[sum(grid), sum(grid) + 1])
+    b = s.b[:, 0]
+    with rs.Solver(s.rowptr, s.colidx, s.vals, ordering=rs.ORDER_GRAPH_COLOUR, precision=precision) as sol:
+        assert sol.factor()[0] == rs.OK
+        assert rs.ilu0_get_option(sol.M, rs.OPT_Y_INPUT_PATTERN) == 1
+        assert rs.ilu0_get_option(sol.M, rs.OPT_Y_INPUT) == 1
+        on = _solves(sol, b, 1e-10)
+        rs.ilu0_set_option(sol.M, rs.OPT_Y_INPUT, 0)
+        off = _solves(sol, b, 1e-10)
+        rs.ilu0_set_option(sol.M, rs.OPT_Y_INPUT, 1)
+        again = _solves(sol, b, 1e-10)
+    for a, c, d in zip(on[:3], off[:3], again[:3]):
+        assert a[1] == c[1] == d[1] == rs.OK
+        assert np.array_equal(a[0], c[0]) and np.array_equal(a[0], d[0])
+        assert outcome(a[2]) == outcome(c[2]) == outcome(d[2])
+    assert np.array_equal(on[3], off[3]) and np.array_equal(on[3], again[3])
+    for k in range(s.batch):
+        xo, _ = oracle.solve(s.rowptr, s.colidx, s.vals[k], s.b[k, 0], ordering=rs.ORDER_GRAPH_COLOUR,
+                             reduction=1e-10)
+        assert np.linalg.norm(on[0][0][k] - xo) <= 1e-8 * np.linalg.norm(xo)
+
+
+def test_y_from_the_input_stays_off_where_the_pattern_does_not_allow_it():
+    """Level sets on a grid (many lower levels), a grid with non-neighbour
+    connections under colouring (more than two colours), single-row islands
+    (no fused rows), and single-launch sweeps: y is stored, and the solves
+    match the oracle."""
+    grid = make_grid_system(12, 9, 7, seed=3)
+    nnc = make_grid_system(12, 9, 7, nnc_frac=0.02, seed=6)
+    islands = make_grid_system(15, 11, 7, active_frac=0.45, seed=8)
+    for s, ordering in ((grid, rs.ORDER_LEVEL_SET), (nnc, rs.ORDER_GRAPH_COLOUR), (islands, rs.ORDER_GRAPH_COLOUR)):
+        with rs.Solver(s.rowptr, s.colidx, s.vals, ordering=ordering) as sol:
+            sol.factor()
+            assert rs.ilu0_get_option(sol.M, rs.OPT_Y_INPUT_PATTERN) == 0
+            x, st, info = sol.solve(s.b[:, 0], reduction=1e-10)
+        xo, _ = oracle.solve(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=ordering, reduction=1e-10)
+        assert st == rs.OK and np.linalg.norm(x[0] - xo) <= 1e-8 * np.linalg.norm(xo)
+    with rs.Solver(grid.rowptr, grid.colidx, grid.vals, ordering=rs.ORDER_GRAPH_COLOUR) as sol:
+        sol.factor()
+        assert rs.ilu0_get_option(sol.M, rs.OPT_Y_INPUT_PATTERN) == 1
+        xl, _, il = sol.solve(grid.b[:, 0], reduction=1e-10)
+        rs.ilu0_set_option(sol.M, rs.OPT_SWEEP_TILES, 1)
+        xt, _, it = sol.solve(grid.b[:, 0], reduction=1e-10)
+    xo, _ = oracle.solve(grid.rowptr, grid.colidx, grid.vals[0], grid.b[0, 0], ordering=rs.ORDER_GRAPH_COLOUR,
+                         reduction=1e-10)
+    for x in (xl, xt):
+        assert np.linalg.norm(x[0] - xo) <= 1e-8 * np.linalg.norm(xo)
+    with pytest.raises(rs.RsolveError):
+        with rs.Solver(grid.rowptr, grid.colidx, grid.vals) as sol:
+            rs.ilu0_set_option(sol.M, rs.OPT_Y_INPUT_PATTERN, 1)
