@@ -798,12 +798,21 @@ int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *ba
         // the U of the fused rows is their rows of A', which their upper
         // launches read instead (filled in later for a consumer of U)
         const bool skip_u0 = S.fuse_n0 > 0;
-        for (int l = 0; l < S.nl_levels; ++l)
+        // a first level made of those rows is a copy and a pivot inversion
+        const bool first = S.fuse_n0 > 0 && S.nl_levels > 0 && S.lset[1] == S.fuse_n0 && S.lconsec[0] &&
+                           S.rest_dst.empty();
+        for (int l = 0; l < S.nl_levels; ++l) {
+            if (l == 0 && first) {
+                rs::launch_factor_first(d, A->vals.as<double>(), per, M->pvals.as<double>(), M->Dinv.as<double>(),
+                                        f32 ? M->Dinvf.as<float>() : nullptr, M->bad.as<int32_t>(), M->batch, s);
+                continue;
+            }
             rs::launch_factor_level(d, A->vals.as<double>(), per, M->pvals.as<double>(), M->L.as<double>(),
                                     M->U.as<double>(), M->Dinv.as<double>(), f32 ? M->Lf.as<float>() : nullptr,
                                     f32 ? M->Uf.as<float>() : nullptr, f32 ? M->Dinvf.as<float>() : nullptr,
                                     M->bad.as<int32_t>(), S.lset[l], S.lset[l + 1],
                                     S.lconsec[l] && S.rest_dst.empty(), skip_u0, M->batch, s);
+        }
         M->u_missing = skip_u0;
     }
     HIP_TRY(hipGetLastError());

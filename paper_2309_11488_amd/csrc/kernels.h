@@ -161,6 +161,13 @@ void launch_gather_pairs(const double *A, size_t a_stride, double *Ap, size_t ap
 void launch_factor_level(const DevSchedule &d, const double *A, size_t a_stride, double *Ap, double *L, double *U,
                          double *Dinv, float *Lf, float *Uf, float *Df, int32_t *bad, int q0, int q1, bool staged,
                          bool skip_u0, int nsys, hipStream_t s);
+// The first level of the factorisation when it is the rows [0, d.fuse_n0)
+// of the new order (rows without lower blocks, U-schedule positions fuse_q0
+// + i): their blocks of the reordered copy Ap (copied from the caller's A),
+// inv(U_ii) = inv(A_ii) into Dinv (and its FP32 rounding into Df when not
+// null), a singular or non-finite pivot reported in bad; no U stored.
+void launch_factor_first(const DevSchedule &d, const double *A, size_t a_stride, double *Ap, double *Dinv,
+                         float *Df, int32_t *bad, int nsys, hipStream_t s);
 // U[f] = A'[usrc[f]], rounded to T, for U positions [f0, f1) of every
 // system (per-system strides a_stride and u_stride, in elements).
 template <typename T>

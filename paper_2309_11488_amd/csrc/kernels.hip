@@ -416,6 +416,20 @@ __device__ inline void row3_mul(const double (&a)[3], const double *__restrict__
     for (int c = 0; c < 3; ++c) out[c] = __builtin_fma(a[2], m[2][c], __builtin_fma(a[1], m[1][c], a[0] * m[0][c]));
 }
 
+// Row r of inv(a) for a 3x3 block a (row-major) from the adjugate: the
+// cofactors of row r's column, divided by the determinant (expanded along
+// the first row), which is returned.
+__device__ inline double inv3_row(const double (&a)[9], int r, double (&inv)[3]) {
+    const double c00 = a[4] * a[8] - a[5] * a[7];
+    const double c01 = a[5] * a[6] - a[3] * a[8];
+    const double c02 = a[3] * a[7] - a[4] * a[6];
+    const double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+    if (r == 0) { inv[0] = c00 / det; inv[1] = (a[2] * a[7] - a[1] * a[8]) / det; inv[2] = (a[1] * a[5] - a[2] * a[4]) / det; }
+    else if (r == 1) { inv[0] = c01 / det; inv[1] = (a[0] * a[8] - a[2] * a[6]) / det; inv[2] = (a[2] * a[3] - a[0] * a[5]) / det; }
+    else { inv[0] = c02 / det; inv[1] = (a[1] * a[6] - a[0] * a[7]) / det; inv[2] = (a[0] * a[4] - a[1] * a[3]) / det; }
+    return det;
+}
+
 // Block ILU0, one level of the lower schedule.  Lane r of row i owns row r of
 // every block of block row i.  In Algorithm 2's order: for each lower block
 // (i,k), k ascending, L_ik = a_ik inv(U_kk); then a_ij -= L_ik U_kj over the
@@ -593,17 +607,66 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
         a[3 * rr + 2] = __shfl(dr[2], rl.base + rr, 64);
     }
     if (!rl.act) return;
-    const double c00 = a[4] * a[8] - a[5] * a[7];
-    const double c01 = a[5] * a[6] - a[3] * a[8];
-    const double c02 = a[3] * a[7] - a[4] * a[6];
-    const double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
     double inv[3];
-    if (r == 0) { inv[0] = c00 / det; inv[1] = (a[2] * a[7] - a[1] * a[8]) / det; inv[2] = (a[1] * a[5] - a[2] * a[4]) / det; }
-    else if (r == 1) { inv[0] = c01 / det; inv[1] = (a[0] * a[8] - a[2] * a[6]) / det; inv[2] = (a[2] * a[3] - a[0] * a[5]) / det; }
-    else { inv[0] = c02 / det; inv[1] = (a[1] * a[6] - a[0] * a[7]) / det; inv[2] = (a[0] * a[4] - a[1] * a[3]) / det; }
+    const double det = inv3_row(a, r, inv);
     row3_store(Ds + (size_t)uq * 9 + 3 * r, inv);
     if (F32) row3_store(Df + ((size_t)sys * d.n + uq) * 9 + 3 * r, inv);
     if (r == 0 && (det == 0.0 || !finite(det))) atomicMin(bad + sys, d.lrows[rl.q]);
+}
+
+// The first level of the factorisation when it is the rows [0, fuse_n0) of
+// the new order (no lower blocks: Schedule::fuse_n0).  Nothing updates these
+// rows, so their part of the reordered copy is the caller's blocks moved to
+// new positions and inv(U_ii) = inv(A_ii); their U is not stored (the
+// upper launches read it from the copy).  A workgroup copies the blocks of
+// kFirstRows consecutive rows, one 8-byte element per thread and step, so
+// consecutive threads load and store consecutive elements, then inverts
+// their diagonal blocks (the first block of each row), one row per thread.
+constexpr int kFirstRows = 64;
+constexpr int kFirstUnroll = 4;
+
+template <bool F32>
+__global__ void __launch_bounds__(kRowThreads) k_factor_first(DevSchedule d, const double *__restrict__ A,
+                                                              size_t a_stride, double *__restrict__ Ap,
+                                                              double *__restrict__ Dinv, float *__restrict__ Df,
+                                                              int32_t *__restrict__ bad) {
+    const int sys = blockIdx.y;
+    const int n0 = d.fuse_n0;
+    const int i0 = blockIdx.x * kFirstRows, i1 = min(i0 + kFirstRows, n0);
+    const double *As = A + (size_t)sys * a_stride;
+    double *Aps = Ap + (size_t)sys * d.nnzb * 9;
+    const long long t0 = 9LL * d.prow[i0], t1 = 9LL * d.prow[i1];
+    for (long long tb = t0; tb < t1; tb += kFirstUnroll * kRowThreads) {
+        double v[kFirstUnroll];
+#pragma unroll
+        for (int u = 0; u < kFirstUnroll; ++u) {
+            const long long t = min(tb + u * kRowThreads + (int)threadIdx.x, t1 - 1);
+            const int p = (int)(t / 9);
+            v[u] = As[(size_t)d.psrc[p] * 9 + (int)(t - 9LL * p)];
+        }
+#pragma unroll
+        for (int u = 0; u < kFirstUnroll; ++u) {
+            const long long t = tb + u * kRowThreads + (int)threadIdx.x;
+            if (t < t1) Aps[t] = v[u];
+        }
+    }
+    const int i = i0 + (int)threadIdx.x;
+    if (i >= i1) return;
+    const int uq = d.fuse_q0 + i;
+    const double *src = As + (size_t)d.dsrc_a[uq] * 9;
+    double a[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) a[e] = src[e];
+    double *Ds = Dinv + ((size_t)sys * d.n + uq) * 9;
+    double det = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        double inv[3];
+        det = inv3_row(a, r, inv);
+        row3_store(Ds + 3 * r, inv);
+        if (F32) row3_store(Df + ((size_t)sys * d.n + uq) * 9 + 3 * r, inv);
+    }
+    if (det == 0.0 || !finite(det)) atomicMin(bad + sys, i);
 }
 
 // ------------------------------------------------------------------ sweeps
@@ -1736,6 +1799,14 @@ void launch_factor_level(const DevSchedule &d, const double *A, size_t a_stride,
     } else {
         if (staged) go(F{}, T{}); else go(F{}, F{});
     }
+}
+
+void launch_factor_first(const DevSchedule &d, const double *A, size_t a_stride, double *Ap, double *Dinv,
+                         float *Df, int32_t *bad, int nsys, hipStream_t s) {
+    if (d.fuse_n0 <= 0 || nsys <= 0) return;
+    const dim3 g((d.fuse_n0 + kFirstRows - 1) / kFirstRows, nsys);
+    if (Df) k_factor_first<true><<<g, kRowThreads, 0, s>>>(d, A, a_stride, Ap, Dinv, Df, bad);
+    else k_factor_first<false><<<g, kRowThreads, 0, s>>>(d, A, a_stride, Ap, Dinv, Df, bad);
 }
 
 template <typename T>

@@ -380,11 +380,14 @@ def test_status_paths(solver_of):
     assert np.linalg.norm(x[0] - xo) <= 1e-10 * np.linalg.norm(xo)
 
 
-def test_zero_pivot_reports_oracle_row(solver_of):
+@pytest.mark.parametrize("row", [1234, 1235])
+def test_zero_pivot_reports_oracle_row(solver_of, row):
+    """A zero block row (L_ik = 0 and U_ii = 0 whatever the ordering); two
+    neighbouring rows, so that under graph colouring one of them is in the
+    first colour (the factorisation's first level, rows without lower
+    blocks) and the other in the second."""
     s = CASES["c1"]
     vz = s.vals.copy()
-    row = 1234
-    # a zero block row: L_ik = 0 and U_ii = 0 whatever the ordering
     vz[0, s.rowptr[row]:s.rowptr[row + 1]] = 0.0
     for ordering in ORDERINGS:
         A, M, st, bad = solver_of(s, ordering, vals=vz)
