@@ -110,6 +110,9 @@ def parse(argv=None):
     ap.add_argument("--y-input", type=int, default=1, choices=[0, 1],
                     help="RS_OPT_Y_INPUT: the applications read the y of the rows without lower blocks from their "
                          "input and store no y (where the pattern allows it)")
+    ap.add_argument("--factor-async", type=int, default=1, choices=[0, 1],
+                    help="RS_OPT_FACTOR_ASYNC: each step's ilu0_factor only queues the factorisation (a singular "
+                         "pivot shows in the solve's statuses); 0: it waits for it")
     ap.add_argument("--slots", type=int, default=8, help="request stream: concurrent worker slots")
     ap.add_argument("--requests", type=int, default=2000, help="request stream (c5): requests per arrival rate")
     ap.add_argument("--loads", default="0.5,0.8,1.0",
@@ -284,6 +287,8 @@ class Problem:
         assert st == rs.OK, (st, bad)
         rs.ilu0_set_option(M, rs.OPT_FUSE_SPMV, self.args.fuse)
         rs.ilu0_set_option(M, rs.OPT_Y_INPUT, self.args.y_input)
+        # the first factorisation above waited and was checked; the steps' own are queued
+        rs.ilu0_set_option(M, rs.OPT_FACTOR_ASYNC, self.args.factor_async)
         tune = None
         if not self.args.no_tune:
             t = time.perf_counter()
@@ -515,6 +520,7 @@ def main():
                    "rhs_per_step": rhs, "sets": P.n_sets, "sweep_levels": [P.nl, P.nu],
                    "fuse_spmv": args.fuse, "fused_rows": P.fused_rows,
                    "y_input": args.y_input, "y_input_pattern": P.y_input_pattern,
+                   "factor_async": args.factor_async,
                    "jacobi_partitions": args.jacobi or None,
                    "mean_half_steps": head["mean_half_steps"],
                    "max_true_rel_residual": head["max_true_rel_residual"], "statuses": head["statuses"],

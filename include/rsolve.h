@@ -144,10 +144,17 @@ enum rs_option {
                                 with per-level sweeps when the upper launch of those rows reads
                                 A' (FP64 factors, or the RS_OPT_FUSE_SPMV iteration).  The same
                                 bits either way; 0: always store y */
-    RS_OPT_Y_INPUT_PATTERN = 12  /* read only: 1 when the analysed pattern has two lower levels,
+    RS_OPT_Y_INPUT_PATTERN = 12, /* read only: 1 when the analysed pattern has two lower levels,
                                 the first being the RS_OPT_FUSED_ROWS rows, and none of the other
                                 rows holds an upper block (graph colouring of a bipartite
                                 pattern such as a 7-point grid) */
+    RS_OPT_FACTOR_ASYNC = 13 /* 0 (default): ilu0_factor waits for the factorisation and returns its
+                                status.  1: ilu0_factor only queues it on its stream and returns
+                                RS_OK (bad_row untouched); a singular pivot then shows as
+                                RS_ZERO_PIVOT in the statuses of the next solve, and
+                                ilu0_factor_status waits for it and gives what the waiting call
+                                would have returned.  A solve or application on another stream
+                                must wait for the factorisation's stream first. */
 };
 
 /* Per-system outcome of bicgstab_solve and gmres_solve. */
@@ -314,8 +321,14 @@ int ilu0_autotune(ilu0_t M, bcsr_t A, const double *b, int32_t mem, double reduc
  * rounded to FP32 for the sweeps.  bad_row (host, batch ints, may be NULL)
  * receives, per system, the original index of the first singular pivot
  * block or -1.  Returns RS_ZERO_PIVOT if any system failed.  Synchronises
- * `stream`. */
+ * `stream` (unless RS_OPT_FACTOR_ASYNC is set: then stream-ordered). */
 int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *bad_row);
+
+/* ilu0_factor_status -- the status and bad_row (as ilu0_factor) of the
+ * handle's last factorisation; waits for it when it was queued with
+ * RS_OPT_FACTOR_ASYNC (the pivot test of Algorithm 2's inverse, as
+ * ilu0_factor).  RS_NOT_FACTORED before any factorisation. */
+int ilu0_factor_status(ilu0_t M, int32_t *bad_row);
 
 /* ilu0_get_factors -- copy system `sys`'s factors to host, in the reordered
  * pattern (rows in new order, columns renumbered and ascending, as P A P^T):

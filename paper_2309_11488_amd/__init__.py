@@ -26,13 +26,13 @@ PREC_FP64, PREC_FP32_FACTORS = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 OPT_SWEEP_TILES, OPT_SWEEP_GRID, OPT_POLL_CHUNK, OPT_USE_GRAPH, OPT_PREDICT_POLL = 0, 1, 2, 3, 4
 OPT_SPMV_VARIANT, OPT_SWEEP_VARIANT, OPT_REDUCE_SPLIT, OPT_SPIN_LIMIT, OPT_FUSE_SPMV, OPT_FUSED_ROWS = 5, 6, 7, 8, 9, 10
-OPT_Y_INPUT, OPT_Y_INPUT_PATTERN = 11, 12
+OPT_Y_INPUT, OPT_Y_INPUT_PATTERN, OPT_FACTOR_ASYNC = 11, 12, 13
 N_ROW_VARIANTS = 9
 
 EXPORTS = (
     "bcsr_create", "bcsr_set_values", "bcsr_set_wells", "bcsr_get_dims", "bcsr_spmv", "bcsr_set_option", "bcsr_destroy", "ilu0_analyse",
     "ilu0_get_schedule", "ilu0_get_sweep_levels", "ilu0_set_option", "ilu0_get_option", "ilu0_autotune",
-    "ilu0_factor", "ilu0_get_factors", "ilu0_apply", "ilu0_apply_noalloc",
+    "ilu0_factor", "ilu0_factor_status", "ilu0_get_factors", "ilu0_apply", "ilu0_apply_noalloc",
     "bicgstab_solve", "gmres_solve", "ilu0_destroy", "ilu0_analyse_host", "rsolve_profile_enable", "rsolve_profile_set_mask", "rsolve_profile_get",
     "ilu0_analyse_shared", "ilu0_analyse_jacobi", "bcsr_partition", "server_create", "server_request_bytes", "server_analysis_bytes", "server_add_pattern",
     "server_submit", "server_poll", "server_wait", "server_get_stats",
@@ -126,6 +126,7 @@ def lib():
         L.ilu0_set_option.argtypes = [vp, i32, i32]
         L.ilu0_get_option.argtypes = [vp, i32, P(i32)]
         L.ilu0_factor.argtypes = [vp, vp, i32, vp, vp]
+        L.ilu0_factor_status.argtypes = [vp, vp]
         L.ilu0_autotune.argtypes = [vp, vp, vp, i32, dbl, i32, vp, ct.POINTER(TuneResult)]
         L.ilu0_get_factors.argtypes = [vp, i32, vp, vp]
         L.ilu0_apply.argtypes = [vp, vp, vp, i32, i32, i32, vp]
@@ -363,6 +364,15 @@ def ilu0_factor(M, A, precision=PREC_FP64, *, stream=None):
     bad = np.full(batch, -1, np.int32)
     st = lib().ilu0_factor(M, A, precision, _stream(stream), bad.ctypes.data)
     _check(st, "ilu0_factor", ok=(OK, ZERO_PIVOT))
+    return st, bad
+
+
+def ilu0_factor_status(M, batch):
+    """Status and bad_row per system of the last factorisation (waits for a
+    queued one)."""
+    bad = np.full(batch, -1, np.int32)
+    st = lib().ilu0_factor_status(M, bad.ctypes.data)
+    _check(st, "ilu0_factor_status", ok=(OK, ZERO_PIVOT))
     return st, bad
 
 

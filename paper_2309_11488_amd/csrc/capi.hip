@@ -252,6 +252,11 @@ struct rs_ilu0 {
     // device time of the last factorisation and of the current solve call
     hipEvent_t ev_f0 = nullptr, ev_f1 = nullptr, ev_s0 = nullptr, ev_s1 = nullptr;
     double factor_ms = 0.0;
+    // RS_OPT_FACTOR_ASYNC: the last factorisation was queued and its result
+    // not read yet (factor_status and bad_orig hold it once it is)
+    bool factor_async = false, factor_pending = false;
+    int factor_status = RS_OK;
+    std::vector<int32_t> bad_orig;
     bool tile_sweeps = true;   // single-launch sweeps (else one launch per level)
     int sweep_grid = 1024;     // workgroups of a single-launch sweep
     int spmv_variant = rs::RV_W4_LDS;   // launch shape of the SpMVs
@@ -294,7 +299,9 @@ struct rs_ilu0 {
         hipGraphExec_t exec = nullptr;
         GraphKey key;
     };
-    std::map<int, Segment> segments;   // by iteration parts
+    // by iteration parts, plus kRepShift times the number of whole
+    // iterations a segment of P_ALL holds beyond one
+    std::map<int, Segment> segments;
     void drop_graph() {
         for (auto &kv : segments) {
             if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
@@ -701,6 +708,10 @@ int ilu0_set_option(ilu0_t M, int32_t option, int32_t value) {
         if (value != 0 && value != 1) break;
         M->y_input = value != 0;
         return RS_OK;
+    case RS_OPT_FACTOR_ASYNC:
+        if (value != 0 && value != 1) break;
+        M->factor_async = value != 0;
+        return RS_OK;
     default:
         break;
     }
@@ -723,6 +734,7 @@ int ilu0_get_option(ilu0_t M, int32_t option, int32_t *value) {
     case RS_OPT_FUSED_ROWS: *value = M->an->sch.fuse_n0; return RS_OK;
     case RS_OPT_Y_INPUT: *value = M->y_input ? 1 : 0; return RS_OK;
     case RS_OPT_Y_INPUT_PATTERN: *value = M->an->sch.y_in; return RS_OK;
+    case RS_OPT_FACTOR_ASYNC: *value = M->factor_async ? 1 : 0; return RS_OK;
     default: return fail(RS_INVALID_ARG, "ilu0_get_option: unknown option");
     }
 }
@@ -750,6 +762,36 @@ static int ensure_u(ilu0_t M, hipStream_t s) {
 // fused iteration (per-level upper launches of FP64 factors read A').
 static bool reads_u(const rs_ilu0 *M, bool fused) {
     return M->tile_sweeps || (M->precision == RS_PREC_FP32_FACTORS && !fused);
+}
+
+// The result of the handle's last factorisation, which has completed and
+// whose first singular pivots (new numbering) are in bad_host: device time,
+// per-system bad rows (original numbering, -1 when none), status.
+static int factor_result(ilu0_t M, int32_t *bad_row) {
+    const size_t B = (size_t)M->batch;
+    float ms = 0.f;
+    M->factor_ms = hipEventElapsedTime(&ms, M->ev_f0, M->ev_f1) == hipSuccess ? ms : 0.0;
+    int worst = RS_OK;
+    M->bad_orig.assign(B, -1);
+    for (size_t i = 0; i < B; ++i) {
+        const int32_t b = M->bad_host[i];
+        const int32_t orig = (b >= 0 && b < M->n) ? M->an->sch.perm[b] : -1;
+        M->bad_orig[i] = orig;
+        if (orig >= 0) worst = RS_ZERO_PIVOT;
+    }
+    if (bad_row) std::copy(M->bad_orig.begin(), M->bad_orig.end(), bad_row);
+    M->factor_status = worst;
+    M->factor_pending = false;
+    if (worst != RS_OK) g_err = "ilu0_factor: singular pivot block";
+    return worst;
+}
+
+// Device time of the last factorisation for a solve's info: a queued one
+// has completed once the solve that follows it on the same stream has.
+static double factor_time(ilu0_t M) {
+    if (!M->factor_pending) return M->factor_ms;
+    float ms = 0.f;
+    return hipEventElapsedTime(&ms, M->ev_f0, M->ev_f1) == hipSuccess ? ms : 0.0;
 }
 
 static int check_pair(ilu0_t M, bcsr_t A) {
@@ -811,30 +853,35 @@ int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *ba
                                     M->U.as<double>(), M->Dinv.as<double>(), f32 ? M->Lf.as<float>() : nullptr,
                                     f32 ? M->Uf.as<float>() : nullptr, f32 ? M->Dinvf.as<float>() : nullptr,
                                     M->bad.as<int32_t>(), S.lset[l], S.lset[l + 1],
-                                    S.lconsec[l] && S.rest_dst.empty(), skip_u0, M->batch, s);
+                                    S.lconsec[l] && S.rest_dst.empty(), skip_u0, l == S.nl_levels - 1, M->batch,
+                                    s);
         }
         M->u_missing = skip_u0;
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventRecord(M->ev_f1, s));
+    M->precision = precision;
+    M->factored = true;
+    M->factor_pending = true;
+    if (M->factor_async) return RS_OK;
     M->bad_host.assign(B, 0);
     HIP_TRY(hipMemcpyAsync(M->bad_host.data(), M->bad.p, B * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    {
-        float ms = 0.f;
-        M->factor_ms = hipEventElapsedTime(&ms, M->ev_f0, M->ev_f1) == hipSuccess ? ms : 0.0;
+    return factor_result(M, bad_row);
+}
+
+int ilu0_factor_status(ilu0_t M, int32_t *bad_row) {
+    if (!M) return fail(RS_INVALID_ARG, "ilu0_factor_status: NULL handle");
+    if (!M->factored) return fail(RS_NOT_FACTORED, "ilu0_factor_status: not factored");
+    if (M->factor_pending) {
+        HIP_TRY(hipEventSynchronize(M->ev_f1));
+        M->bad_host.assign(M->batch, 0);
+        HIP_TRY(hipMemcpy(M->bad_host.data(), M->bad.p, M->batch * sizeof(int32_t), hipMemcpyDeviceToHost));
+        return factor_result(M, bad_row);
     }
-    int worst = RS_OK;
-    for (size_t i = 0; i < B; ++i) {
-        const int32_t b = M->bad_host[i];
-        const int32_t orig = (b >= 0 && b < M->n) ? S.perm[b] : -1;
-        if (bad_row) bad_row[i] = orig;
-        if (orig >= 0) worst = RS_ZERO_PIVOT;
-    }
-    M->precision = precision;
-    M->factored = true;
-    if (worst != RS_OK) g_err = "ilu0_factor: singular pivot block";
-    return worst;
+    if (bad_row) std::copy(M->bad_orig.begin(), M->bad_orig.end(), bad_row);
+    if (M->factor_status != RS_OK) g_err = "ilu0_factor: singular pivot block";
+    return M->factor_status;
 }
 
 int ilu0_get_factors(ilu0_t M, int32_t sys, double *lu, double *dinv) {
@@ -1208,7 +1255,11 @@ static void enqueue_iteration_any(ilu0_t M, hipStream_t s, int parts) {
 // Replay the graph segment holding `parts` (captured on a private stream
 // the first time this configuration is seen).  Nothing is timed inside a
 // graph: profiling is off while segments are captured.
-static int replay_segment(ilu0_t M, int parts, hipStream_t s) {
+// A graph segment of `reps` consecutive whole iterations is keyed as parts
+// P_ALL + (reps - 1) * kRepShift.
+constexpr int kRepShift = 1 << 16;
+
+static int replay_segment(ilu0_t M, int parts, hipStream_t s, int reps = 1) {
     rs_ilu0::GraphKey key;
     key.precision = M->precision;
     key.tile_sweeps = M->tile_sweeps;
@@ -1220,7 +1271,7 @@ static int replay_segment(ilu0_t M, int parts, hipStream_t s) {
     key.fuse = fused_iteration(M) ? 1 : 0;
     key.yin = M->y_input ? 1 : 0;
     key.wells = M->wdev.nw > 0 ? (long long)M->wells_version + 1 : 0;
-    rs_ilu0::Segment &seg = M->segments[parts];
+    rs_ilu0::Segment &seg = M->segments[parts + (reps - 1) * kRepShift];
     if (!seg.exec || !(seg.key == key)) {
         if (seg.exec) (void)hipGraphExecDestroy(seg.exec);
         if (seg.graph) (void)hipGraphDestroy(seg.graph);
@@ -1231,7 +1282,7 @@ static int replay_segment(ilu0_t M, int parts, hipStream_t s) {
         g_prof.mask = 0;
         hipError_t e = hipStreamBeginCapture(M->cap_stream, hipStreamCaptureModeRelaxed);
         if (e == hipSuccess) {
-            enqueue_iteration_any(M, M->cap_stream, parts);
+            for (int i = 0; i < reps; ++i) enqueue_iteration_any(M, M->cap_stream, parts);
             e = hipStreamEndCapture(M->cap_stream, &seg.graph);
         }
         g_prof.mask = mask;
@@ -1293,6 +1344,27 @@ static int run_iteration(ilu0_t M, hipStream_t s) {
         }
     }
     return run ? replay_segment(M, run, s) : RS_OK;
+}
+
+// Queue `count` BiCGStab iterations on `s`.  Without kernel-class timing,
+// runs of 8, 4, 2 and 1 whole iterations replay as one graph each: the
+// launches inside a graph follow one another with no gap, while every graph
+// launch costs a few microseconds of idle device time at its boundary.
+static int run_iterations(ilu0_t M, int count, hipStream_t s) {
+    if (M->use_graph && !class_parts(g_prof.mask)) {
+        for (int reps = 8; reps >= 1; reps >>= 1)
+            while (count >= reps) {
+                const int st = replay_segment(M, P_ALL, s, reps);
+                if (st != RS_OK) return st;
+                count -= reps;
+            }
+        return RS_OK;
+    }
+    for (int i = 0; i < count; ++i) {
+        const int st = run_iteration(M, s);
+        if (st != RS_OK) return st;
+    }
+    return RS_OK;
 }
 
 extern "C" {
@@ -1466,7 +1538,7 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
     const int B = M->batch;
     if (M->n == 0) {
         if (info)
-            for (int i = 0; i < B; ++i) info[i] = solve_info{RS_OK, 0, 0.0, 0.0, 0.0, M->factor_ms, 0.0};
+            for (int i = 0; i < B; ++i) info[i] = solve_info{RS_OK, 0, 0.0, 0.0, 0.0, factor_time(M), 0.0};
         return RS_OK;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -1519,10 +1591,8 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
         int c = predicted ? std::max(M->chunk, M->last_iters) : M->chunk;
         c = std::min(c, max_iter - done_iters);
         first = false;
-        for (int i = 0; i < c; ++i) {
-            st = run_iteration(M, s);
-            if (st != RS_OK) return st;
-        }
+        st = run_iterations(M, c, s);
+        if (st != RS_OK) return st;
         done_iters += c;
         if (predicted) {
             st = finish();
@@ -1546,7 +1616,7 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
     int worst = RS_OK, needed = 1;
     for (int i = 0; i < B; ++i) {
         const SysState &S = M->h_state[i];
-        if (info) info[i] = solve_info{S.status, S.half_steps, S.r0norm, S.last_norm, S.true_res, M->factor_ms, solve_ms};
+        if (info) info[i] = solve_info{S.status, S.half_steps, S.r0norm, S.last_norm, S.true_res, factor_time(M), solve_ms};
         if (status_rank(S.status) > status_rank(worst)) worst = S.status;
         needed = std::max(needed, (S.half_steps + 1) / 2);
     }
@@ -1647,7 +1717,7 @@ int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart,
     const int B = M->batch;
     if (M->n == 0) {
         if (info)
-            for (int i = 0; i < B; ++i) info[i] = solve_info{RS_OK, 0, 0.0, 0.0, 0.0, M->factor_ms, 0.0};
+            for (int i = 0; i < B; ++i) info[i] = solve_info{RS_OK, 0, 0.0, 0.0, 0.0, factor_time(M), 0.0};
         return RS_OK;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -1772,7 +1842,7 @@ int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart,
     int worst = RS_OK, needed = 1;
     for (int i = 0; i < B; ++i) {
         const SysState &S = M->h_state[i];
-        if (info) info[i] = solve_info{S.status, S.half_steps, S.r0norm, S.last_norm, S.true_res, M->factor_ms, solve_ms};
+        if (info) info[i] = solve_info{S.status, S.half_steps, S.r0norm, S.last_norm, S.true_res, factor_time(M), solve_ms};
         if (status_rank(S.status) > status_rank(worst)) worst = S.status;
         needed = std::max(needed, S.half_steps);
     }

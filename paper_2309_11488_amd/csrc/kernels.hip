@@ -450,7 +450,8 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
                                                               double *__restrict__ L, double *__restrict__ U,
                                                               double *__restrict__ Dinv, float *__restrict__ Lf,
                                                               float *__restrict__ Uf, float *__restrict__ Df,
-                                                              int32_t *__restrict__ bad, int q0, int q1, int skip_u0) {
+                                                              int32_t *__restrict__ bad, int q0, int q1, int skip_u0,
+                                                              int last) {
     __shared__ double sap[STAGED ? kApCap * 9 : 1];
     int sys, bx;
     xcd_map(sys, bx);
@@ -609,7 +610,8 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
     if (!rl.act) return;
     double inv[3];
     const double det = inv3_row(a, r, inv);
-    row3_store(Ds + (size_t)uq * 9 + 3 * r, inv);
+    // with FP32 factors the FP64 pivot inverses serve only later levels
+    if (!F32 || !last) row3_store(Ds + (size_t)uq * 9 + 3 * r, inv);
     if (F32) row3_store(Df + ((size_t)sys * d.n + uq) * 9 + 3 * r, inv);
     if (r == 0 && (det == 0.0 || !finite(det))) atomicMin(bad + sys, d.lrows[rl.q]);
 }
@@ -1785,12 +1787,12 @@ void launch_gather_pairs(const double *A, size_t a_stride, double *Ap, size_t ap
 
 void launch_factor_level(const DevSchedule &d, const double *A, size_t a_stride, double *Ap, double *L, double *U,
                          double *Dinv, float *Lf, float *Uf, float *Df, int32_t *bad, int q0, int q1, bool staged,
-                         bool skip_u0, int nsys, hipStream_t s) {
+                         bool skip_u0, bool last, int nsys, hipStream_t s) {
     if (q1 <= q0 || nsys <= 0) return;
     const dim3 g(row_blocks(q1 - q0), nsys);
     auto go = [&](auto F32, auto STG) {
         k_factor_level<decltype(F32)::value, decltype(STG)::value><<<g, kRowThreads, 0, s>>>(
-            d, A, a_stride, Ap, L, U, Dinv, Lf, Uf, Df, bad, q0, q1, skip_u0 ? 1 : 0);
+            d, A, a_stride, Ap, L, U, Dinv, Lf, Uf, Df, bad, q0, q1, skip_u0 ? 1 : 0, last ? 1 : 0);
     };
     using T = std::true_type;
     using F = std::false_type;

@@ -214,3 +214,50 @@ def test_rcm_ordering_shortens_the_nnc_schedule():
         rs.ilu0_destroy(M1)
         rs.ilu0_destroy(M3)
         rs.bcsr_destroy(A)
+
+
+def test_queued_factorisation_gives_the_same_results():
+    """RS_OPT_FACTOR_ASYNC: ilu0_factor only queues the factorisation.  The
+    solves that follow on the same stream give the bits of the waiting
+    call's solves, report the factorisation's device time, and
+    ilu0_factor_status gives the waiting call's status.  A singular pivot in
+    one system of a batch surfaces as RS_ZERO_PIVOT in that system's solve
+    status and in ilu0_factor_status with the waiting call's bad rows."""
+    s = make_grid_system(20, 20, 10, seed=4)
+    batch = 3
+    vals = np.repeat(s.vals, batch, axis=0)
+    vals[1] *= 1.5
+    b = np.repeat(s.b[:, 0], batch, axis=0)
+    bad_vals = vals.copy()
+    bad_vals[2, s.rowptr[777]:s.rowptr[778]] = 0.0
+    for prec in (rs.PREC_FP64, rs.PREC_FP32_FACTORS):
+        with rs.Solver(s.rowptr, s.colidx, vals, ordering=rs.ORDER_GRAPH_COLOUR, precision=prec) as sol:
+            with pytest.raises(rs.RsolveError) as e:
+                rs.ilu0_factor_status(sol.M, batch)
+            assert e.value.status == rs.NOT_FACTORED
+            assert rs.ilu0_get_option(sol.M, rs.OPT_FACTOR_ASYNC) == 0
+            assert sol.factor()[0] == rs.OK
+            x0, st0, i0 = sol.solve(b, reduction=1e-8)
+            rs.ilu0_set_option(sol.M, rs.OPT_FACTOR_ASYNC, 1)
+            st, bad = sol.factor()
+            assert st == rs.OK and list(bad) == [-1] * batch
+            x1, st1, i1 = sol.solve(b, reduction=1e-8)
+            assert st0 == st1 == rs.OK and np.array_equal(x0, x1) and outcome(i0) == outcome(i1)
+            assert all(i["factor_ms"] > 0 for i in i1)
+            st, bad = rs.ilu0_factor_status(sol.M, batch)
+            assert st == rs.OK and list(bad) == [-1] * batch
+            # a singular pivot in system 2
+            rs.ilu0_set_option(sol.M, rs.OPT_FACTOR_ASYNC, 0)
+            sst, sbad = sol.factor(bad_vals)
+            assert sst == rs.ZERO_PIVOT and sbad[2] >= 0 and sbad[0] == sbad[1] == -1
+            rs.ilu0_set_option(sol.M, rs.OPT_FACTOR_ASYNC, 1)
+            st, _ = sol.factor(bad_vals)
+            assert st == rs.OK
+            x2, st2, i2 = sol.solve(b, reduction=1e-8)
+            assert st2 == rs.ZERO_PIVOT
+            assert [i["status"] for i in i2] == [rs.OK, rs.OK, rs.ZERO_PIVOT]
+            assert np.array_equal(x2[:2], x0[:2])
+            qst, qbad = rs.ilu0_factor_status(sol.M, batch)
+            assert qst == rs.ZERO_PIVOT and np.array_equal(qbad, sbad)
+            # the answer stays until the next factorisation
+            assert rs.ilu0_factor_status(sol.M, batch)[0] == rs.ZERO_PIVOT
