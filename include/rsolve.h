@@ -477,7 +477,9 @@ typedef struct {
 typedef struct {
     double queue_ms;    /* submission to admission */
     double analyse_ms;  /* instance creation: handles, analysis or its reuse, allocation (0 when resident) */
-    double factor_ms;   /* value upload and ILU0 factorisation */
+    double factor_ms;   /* value upload and queueing the ILU0 factorisation (waiting for it on the
+                           first request of a pattern with autotune; its device time is in the
+                           request's solve_info.factor_ms) */
     double tune_ms;     /* autotuning (first instance of a pattern) */
     double solve_ms;    /* BiCGStab, true residual, result copy */
     double total_ms;    /* submission to completion */

@@ -237,6 +237,9 @@ static int create_instance(rs_server *S, Slot *sl, Instance *I) {
         else if (st == RS_OK) ++S->analyses;
     }
     if (st == RS_OK) st = ilu0_set_option(I->M, RS_OPT_USE_GRAPH, 0);
+    // the factorisation is only queued: its pivot check reaches the request
+    // through the solve's status, and the worker does not wait in between
+    if (st == RS_OK) st = ilu0_set_option(I->M, RS_OPT_FACTOR_ASYNC, 1);
     return st;
 }
 
@@ -318,6 +321,8 @@ static void slot_main(rs_server *S, Slot *sl) {
         if (st == RS_OK) {
             int32_t bad = -1;
             st = ilu0_factor(I->M, I->A, S->cfg.precision, sl->stream, &bad);
+            // the tuner times solves of this factorisation: it must be sound
+            if (st == RS_OK && tune) st = ilu0_factor_status(I->M, &bad);
         }
         const Clock::time_point t2 = Clock::now();
         r->timing.factor_ms = ms_between(t1, t2);
