@@ -148,13 +148,22 @@ enum rs_option {
                                 the first being the RS_OPT_FUSED_ROWS rows, and none of the other
                                 rows holds an upper block (graph colouring of a bipartite
                                 pattern such as a 7-point grid) */
-    RS_OPT_FACTOR_ASYNC = 13 /* 0 (default): ilu0_factor waits for the factorisation and returns its
+    RS_OPT_FACTOR_ASYNC = 13, /* 0 (default): ilu0_factor waits for the factorisation and returns its
                                 status.  1: ilu0_factor only queues it on its stream and returns
                                 RS_OK (bad_row untouched); a singular pivot then shows as
                                 RS_ZERO_PIVOT in the statuses of the next solve, and
                                 ilu0_factor_status waits for it and gives what the waiting call
                                 would have returned.  A solve or application on another stream
                                 must wait for the factorisation's stream first. */
+    RS_OPT_LOWER_PARTS = 14  /* 1 (default): with FP64 factors, in BiCGStab's fused iteration on a
+                                pattern of RS_OPT_Y_INPUT_PATTERN, the SpMV v = A phat also forms,
+                                from the same FP64 blocks, the sums sum_k A'_ik inv(U_kk) r_k and
+                                sum_k A'_ik inv(U_kk) v_k of each row with lower blocks (its lower
+                                blocks are L_ik = A'_ik inv(U_kk) on such a pattern); the
+                                iteration's second application then forms sum_k L_ik s_k as their
+                                combination for s = r - alpha v instead of reading L again.  The
+                                same mathematics (Algorithm 2, equations 3-4), other rounding: the
+                                solves agree with the option off to rounding; 0: off */
 };
 
 /* Per-system outcome of bicgstab_solve and gmres_solve. */

@@ -26,7 +26,7 @@ PREC_FP64, PREC_FP32_FACTORS = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 OPT_SWEEP_TILES, OPT_SWEEP_GRID, OPT_POLL_CHUNK, OPT_USE_GRAPH, OPT_PREDICT_POLL = 0, 1, 2, 3, 4
 OPT_SPMV_VARIANT, OPT_SWEEP_VARIANT, OPT_REDUCE_SPLIT, OPT_SPIN_LIMIT, OPT_FUSE_SPMV, OPT_FUSED_ROWS = 5, 6, 7, 8, 9, 10
-OPT_Y_INPUT, OPT_Y_INPUT_PATTERN, OPT_FACTOR_ASYNC = 11, 12, 13
+OPT_Y_INPUT, OPT_Y_INPUT_PATTERN, OPT_FACTOR_ASYNC, OPT_LOWER_PARTS = 11, 12, 13, 14
 N_ROW_VARIANTS = 9
 
 EXPORTS = (

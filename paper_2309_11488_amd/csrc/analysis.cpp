@@ -535,8 +535,14 @@ int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx
     // (see Schedule::y_in) the upper levels: the rows without upper blocks
     // (all rows from fuse_n0 on), then the fuse_n0 rows
     if (s.fuse_n0 > 0 && s.nl_levels == 2 && s.lset[1] == s.fuse_n0 && s.nu_levels == 2 && s.fuse_level == 1 &&
-        s.uset[1] == n - s.fuse_n0)
-        s.y_in = 1;
+        s.uset[1] == n - s.fuse_n0) {
+        // both schedules keep rows ascending inside a level: the second
+        // lower level is rows [fuse_n0, n), the first upper level the same
+        // rows at positions 0 .. n - fuse_n0
+        bool ok = true;
+        for (int q = s.fuse_n0; ok && q < n; ++q) ok = s.lrows[q] == q && s.urows[q - s.fuse_n0] == q;
+        s.y_in = ok ? 1 : 0;
+    }
 
     s.lconsec.assign(s.nl_levels, 1);
     for (int l = 0; l < s.nl_levels; ++l)

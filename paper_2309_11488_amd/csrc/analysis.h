@@ -75,7 +75,9 @@ struct Schedule {
     // blocks is the sweep's input itself, and every other row finishes in
     // the lower launch (z_i = inv(U_ii) y_i), so an application needs no
     // stored y: the launches read the input instead (bipartite patterns
-    // under graph colouring, e.g. the 7-point grids).
+    // under graph colouring, e.g. the 7-point grids).  Then row i >=
+    // fuse_n0 sits at L-schedule position i and U-schedule position
+    // i - fuse_n0.
     int y_in = 0;
     // row tiles of the single-launch sweeps: tile t covers schedule
     // positions [start[t], start[t+1]) inside one level, and must wait for

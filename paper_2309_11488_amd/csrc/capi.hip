@@ -264,6 +264,8 @@ struct rs_ilu0 {
     int reduce_split = 0;               // RS_OPT_REDUCE_SPLIT
     bool fuse_spmv = true;              // RS_OPT_FUSE_SPMV
     bool y_input = true;                // RS_OPT_Y_INPUT
+    bool lower_parts = true;            // RS_OPT_LOWER_PARTS
+    DevBuf lpwork;                      // its two vectors (allocated on first use)
     // a pattern with fused rows: the factorisation stored no U of the
     // factor type for those rows (their fused upper launches read A'); it is
     // filled from A' when a consumer of U needs it (single-launch sweeps,
@@ -286,12 +288,12 @@ struct rs_ilu0 {
     // every setting a captured iteration depends on
     struct GraphKey {
         int precision = -1, tile_sweeps = 0, spmv_variant = 0, sweep_variant = 0, split = 0, sweep_grid = 0;
-        int spin = 0, fuse = 0, yin = 0;
+        int spin = 0, fuse = 0, yin = 0, lp = 0;
         long long wells = 0;   // 0: no wells, else the wells' version + 1
         bool operator==(const GraphKey &o) const {
             return precision == o.precision && tile_sweeps == o.tile_sweeps && spmv_variant == o.spmv_variant &&
                    sweep_variant == o.sweep_variant && split == o.split && sweep_grid == o.sweep_grid &&
-                   spin == o.spin && fuse == o.fuse && yin == o.yin && wells == o.wells;
+                   spin == o.spin && fuse == o.fuse && yin == o.yin && lp == o.lp && wells == o.wells;
         }
     };
     struct Segment {
@@ -712,6 +714,10 @@ int ilu0_set_option(ilu0_t M, int32_t option, int32_t value) {
         if (value != 0 && value != 1) break;
         M->factor_async = value != 0;
         return RS_OK;
+    case RS_OPT_LOWER_PARTS:
+        if (value != 0 && value != 1) break;
+        M->lower_parts = value != 0;
+        return RS_OK;
     default:
         break;
     }
@@ -735,6 +741,7 @@ int ilu0_get_option(ilu0_t M, int32_t option, int32_t *value) {
     case RS_OPT_Y_INPUT: *value = M->y_input ? 1 : 0; return RS_OK;
     case RS_OPT_Y_INPUT_PATTERN: *value = M->an->sch.y_in; return RS_OK;
     case RS_OPT_FACTOR_ASYNC: *value = M->factor_async ? 1 : 0; return RS_OK;
+    case RS_OPT_LOWER_PARTS: *value = M->lower_parts ? 1 : 0; return RS_OK;
     default: return fail(RS_INVALID_ARG, "ilu0_get_option: unknown option");
     }
 }
@@ -992,6 +999,7 @@ static int ensure_workspace(ilu0_t M, hipStream_t s) {
     k.spart_stride = sstride;
     k.fpart = M->fpart.as<double>();
     k.fpart_stride = fstride;
+    k.lp = M->lpwork.p ? M->lpwork.as<double>() : nullptr;
     k.st = M->state.as<SysState>();
     k.lflags = M->flags.as<int32_t>();
     k.uflags = k.lflags + B * (size_t)M->an->sch.ltiles.n;
@@ -1078,6 +1086,15 @@ static bool y_from_input(const rs_ilu0 *M, bool fp64, bool fused) {
 // order).  Timed as one unit (events around its launches).  yin (see
 // y_from_input): the first level's rows take y = their input (p, updated
 // first, or `in`) and the second level's launch reads it from there.
+// Algorithmic bytes of the lower parts: the fused upper launch reads r and
+// writes inv(U_kk) r_k and inv(U_kk) v_k on its rows (72 per row); the SpMV
+// reads those and writes a_i, b_i (48 per row); the second application's
+// lower launch reads s, a, b and inv(U_ii), writes shat (168 per row)
+// instead of its L blocks.
+static double lp_upper_extra(ilu0_t M, int nsys) { return nsys * 72.0 * M->an->sch.fuse_n0; }
+static double lp_spmv_extra(ilu0_t M, int nsys) { return nsys * 48.0 * M->n; }
+static double lp_lower_bytes(ilu0_t M, int nsys) { return nsys * 168.0 * (M->n - M->an->sch.fuse_n0); }
+
 template <typename T>
 static void lower_levels(ilu0_t M, const T *L, const T *D, const double *in, double *out, bool fuse_p, Krylov &k,
                          SysState *st, int nsys, hipStream_t s, bool prof = true, bool yin = false) {
@@ -1118,20 +1135,41 @@ static double fused_spmv_bytes(ilu0_t M, int nsys) {
     return nsys * (76.0 * (double)S.fuse_nnz + 52.0 * S.fuse_n0);
 }
 
+// Whether BiCGStab's iterations form the lower parts of the second
+// application inside v = A phat (RS_OPT_LOWER_PARTS): the fused iteration
+// on a two-level pattern with FP64 factors, reading y from the input.
+static bool lower_parts_iteration(const rs_ilu0 *M) {
+    return M->lower_parts && M->precision == RS_PREC_FP64 && fused_iteration(M) && y_from_input(M, true, true);
+}
+
+// Its two workspace vectors, allocated on first use (and kept).
+static int ensure_lower_parts(ilu0_t M, hipStream_t s) {
+    if (M->lpwork.p) return RS_OK;
+    const size_t vec = std::max<size_t>((size_t)M->batch * rs::vec_stride(M->n), 1);
+    HIP_TRY(M->lpwork.alloc(2 * vec * sizeof(double)));
+    HIP_TRY(hipMemsetAsync(M->lpwork.p, 0, 2 * vec * sizeof(double), s));
+    M->k.lp = M->lpwork.as<double>();
+    return RS_OK;
+}
+
+
 // Upper sweep levels 1 and up (level 0 is done by the lower sweep), timed
 // as one unit.  fmode != FUSE_NONE: the launch of the rows without lower
 // blocks also forms their rows of fout = A' out (the product of the
 // application's result), with the dot products against fw1.
 // yd: the input the rows without lower blocks take as y (when the lower
 // sweep ran with yin), else NULL.
+// lp: also the lower parts' vectors of the rows without lower blocks
+// (lower_parts_iteration, first application).
 template <typename T>
 static void upper_levels(ilu0_t M, const T *U, const T *D, double *out, bool fuse_p, Krylov &k, SysState *st,
                          int nsys, hipStream_t s, bool prof = true, int fmode = rs::FUSE_NONE,
-                         double *fout = nullptr, const double *fw1 = nullptr, const double *yd = nullptr) {
+                         double *fout = nullptr, const double *fw1 = nullptr, const double *yd = nullptr,
+                         bool lp = false) {
     const rs::Schedule &S = M->an->sch;
     const size_t vs = k.vstride;
     const T *y = (const T *)k.y;
-    const double fb = fmode != rs::FUSE_NONE ? fused_spmv_bytes(M, nsys) : 0.0;
+    const double fb = (fmode != rs::FUSE_NONE ? fused_spmv_bytes(M, nsys) : 0.0) + (lp ? lp_upper_extra(M, nsys) : 0.0);
     ProfScope ps(PC_USWEEP, s, upper_bytes(M, sizeof(T), nsys) + fb, M->tile_sweeps, prof);
     if (M->tile_sweeps) {
         rs::launch_usweep_tiles<T>(M->an->dev, U, (size_t)S.nU * 9, D, (size_t)M->n * 9, y, out, vs, st, k.uflags,
@@ -1146,7 +1184,8 @@ static void upper_levels(ilu0_t M, const T *U, const T *D, double *out, bool fus
         int q0 = S.uset[l];
         if (via_ap && l == S.fuse_level) {
             rs::launch_usweep_spmv<T>(M->an->dev, M->pvals.as<double>(), (size_t)M->nnzb * 9, D, (size_t)M->n * 9,
-                                      y, yd, out, fout, fw1, st, k, nsys, fmode, M->spmv_variant, fuse_p, s);
+                                      y, yd, out, fout, fw1, st, k, nsys, fmode, M->spmv_variant, fuse_p, s,
+                                      nullptr, nullptr, lp);
             q0 += S.fuse_n0;
             if (q0 >= S.uset[l + 1]) continue;
         }
@@ -1206,30 +1245,44 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
     // (and their bytes) move from the SpMV into the application
     const bool fz = fused_iteration(M);
     const bool yin = y_from_input(M, sizeof(T) == sizeof(double), fz);
+    const bool lp = sizeof(T) == sizeof(double) && lower_parts_iteration(M);
     const int r0 = fz ? M->an->sch.fuse_n0 : 0;
     const double fb = fz ? fused_spmv_bytes(M, B) : 0.0;
     const double spmv_bytes = B * (76 * nnzb + 52 * n) - fb;
     const double apply_bytes = lower_bytes(M, tb, B) + upper_bytes(M, tb, B) + fb;
     {
         // an application is timed whole or not at all
-        ProfScope pa(PC_APPLY, s, apply_bytes, false, (parts & P_L1) && (parts & P_U1));
+        ProfScope pa(PC_APPLY, s, apply_bytes + (lp ? lp_upper_extra(M, B) : 0.0), false,
+                     (parts & P_L1) && (parts & P_U1));
         if (parts & P_L1) lower_levels<T>(M, L, D, nullptr, k.phat, true, k, k.st, B, s, true, yin);
         if (parts & P_U1)
             upper_levels<T>(M, U, D, k.phat, true, k, k.st, B, s, true, fz ? rs::FUSE_V : rs::FUSE_NONE, k.v,
-                            k.rhat, yin ? k.p : nullptr);
+                            k.rhat, yin ? k.p : nullptr, lp);
     }
     if (parts & P_SPMV_V) {
-        ProfScope ps(PC_SPMV_V, s, spmv_bytes, true);
-        rs::launch_spmv_v(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), M->wdev, r0,
-                          s, ps.start(), ps.stop());
+        ProfScope ps(PC_SPMV_V, s, spmv_bytes + (lp ? lp_spmv_extra(M, B) : 0.0), true);
+        if (lp)
+            rs::launch_spmv_lp(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, s, ps.start(),
+                               ps.stop());
+        else
+            rs::launch_spmv_v(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), M->wdev,
+                              r0, s, ps.start(), ps.stop());
     }
     if (parts & P_SUPD) {
         ProfScope ps(PC_VEC, s, B * 72 * n, true);
         rs::launch_s_update(M->an->dev, k, B, M->spmv_variant, M->split(), fz, s, ps.start(), ps.stop());
     }
     {
-        ProfScope pa(PC_APPLY, s, apply_bytes, false, (parts & P_L2) && (parts & P_U2));
-        if (parts & P_L2) lower_levels<T>(M, L, D, k.s, k.shat, false, k, k.st, B, s, true, yin);
+        ProfScope pa(PC_APPLY, s, lp ? lp_lower_bytes(M, B) + upper_bytes(M, tb, B) + fb : apply_bytes, false,
+                     (parts & P_L2) && (parts & P_U2));
+        if ((parts & P_L2) && lp) {
+            // the second level's rows from the SpMV's lower parts; the first
+            // level's y is s itself
+            ProfScope pl(PC_LSWEEP, s, lp_lower_bytes(M, B), false);
+            rs::launch_lower_parts(M->an->dev, (const double *)D, (size_t)M->n * 9, k, B, s);
+        } else if (parts & P_L2) {
+            lower_levels<T>(M, L, D, k.s, k.shat, false, k, k.st, B, s, true, yin);
+        }
         if (parts & P_U2)
             upper_levels<T>(M, U, D, k.shat, false, k, k.st, B, s, true, fz ? rs::FUSE_T : rs::FUSE_NONE, k.t,
                             k.s, yin ? k.s : nullptr);
@@ -1270,6 +1323,7 @@ static int replay_segment(ilu0_t M, int parts, hipStream_t s, int reps = 1) {
     key.spin = M->spin_limit;
     key.fuse = fused_iteration(M) ? 1 : 0;
     key.yin = M->y_input ? 1 : 0;
+    key.lp = M->lower_parts ? 1 : 0;
     key.wells = M->wdev.nw > 0 ? (long long)M->wells_version + 1 : 0;
     rs_ilu0::Segment &seg = M->segments[parts + (reps - 1) * kRepShift];
     if (!seg.exec || !(seg.key == key)) {
@@ -1311,6 +1365,15 @@ static int run_iteration(ilu0_t M, hipStream_t s) {
     const double tb = M->precision == RS_PREC_FP32_FACTORS ? 4 : 8;
     // the SpMV rows a fused upper launch forms count with the application
     const double fb = fused_iteration(M) ? fused_spmv_bytes(M, M->batch) : 0.0;
+    const bool lp = lower_parts_iteration(M);
+    // per part: the first application's upper launch also forms the lower
+    // parts' vectors; the second application's lower launch reads them
+    auto lo_bytes = [&](int part) {
+        return lp && part == P_L2 ? lp_lower_bytes(M, M->batch) : lower_bytes(M, tb, M->batch);
+    };
+    auto up_bytes = [&](int part) {
+        return upper_bytes(M, tb, M->batch) + fb + (lp && part == P_U1 ? lp_upper_extra(M, M->batch) : 0.0);
+    };
     const bool whole = apply_unit(g_prof.mask);
     int run = 0;
     for (int part = 1; part <= P_XR; part <<= 1) {
@@ -1325,7 +1388,7 @@ static int run_iteration(ilu0_t M, hipStream_t s) {
         }
         if (whole && (part == P_L1 || part == P_L2)) {
             // a whole application (both sweeps) as one graph segment between two events
-            ProfScope ps(PC_APPLY, s, lower_bytes(M, tb, M->batch) + upper_bytes(M, tb, M->batch) + fb);
+            ProfScope ps(PC_APPLY, s, lo_bytes(part) + up_bytes(part << 1));
             const int st = replay_segment(M, part | (part << 1), s);
             if (st != RS_OK) return st;
             part <<= 1;   // its upper sweep is done
@@ -1334,8 +1397,7 @@ static int run_iteration(ilu0_t M, hipStream_t s) {
         const bool sweep = part == P_L1 || part == P_U1 || part == P_L2 || part == P_U2;
         if (sweep && !M->tile_sweeps) {
             const bool lower = part == P_L1 || part == P_L2;
-            ProfScope ps(lower ? PC_LSWEEP : PC_USWEEP, s,
-                         lower ? lower_bytes(M, tb, M->batch) : upper_bytes(M, tb, M->batch) + fb);
+            ProfScope ps(lower ? PC_LSWEEP : PC_USWEEP, s, lower ? lo_bytes(part) : up_bytes(part));
             const int st = replay_segment(M, part, s);
             if (st != RS_OK) return st;
         } else {
@@ -1547,6 +1609,7 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
     st = ensure_wells(M, A, s);
     if (st != RS_OK) return st;
     if (reads_u(M, fused_iteration(M)) && (st = ensure_u(M, s)) != RS_OK) return st;
+    if (lower_parts_iteration(M) && (st = ensure_lower_parts(M, s)) != RS_OK) return st;
     const size_t m = 3 * (size_t)M->n * B;
     const double *bd = nullptr;
     st = stage_in(b, mem, M->bstage, m, s, &bd);

@@ -87,6 +87,7 @@ struct Krylov {
     size_t spart_stride;
     double *fpart;      // partials of the products formed by the fused upper launch, nsys * fpart_stride
     size_t fpart_stride;
+    double *lp;         // lower parts of the second application (k_spmv_lp): 6 values per row, 2 vstride per system, or NULL
     SysState *st;       // nsys states
     int32_t *lflags, *uflags;  // per (system, tile): epoch of the sweep that finished it
     SweepCtr *lctr, *uctr;
@@ -263,11 +264,27 @@ enum FuseMode { FUSE_NONE = 0, FUSE_V = 1, FUSE_T = 2 };
 // st may be NULL (no phase test: every system is computed); k supplies the
 // vector stride and the partials of the product.  yd (may be NULL): y of
 // these rows is the application's input, read from yd (FP64) instead of y.
+// lp (FP64 factors, mode FUSE_V): also k.lp = (inv(U_kk) r_k, inv(U_kk)
+// v_k) for these rows (see launch_spmv_lp).
 template <typename T>
 void launch_usweep_spmv(const DevSchedule &d, const double *Ap, size_t a_stride, const T *Dinv, size_t d_stride,
                         const T *y, const double *yd, double *z, double *out, const double *w1, SysState *st,
                         Krylov &k, int nsys, int mode, int spmv_variant, bool defer, hipStream_t s,
-                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool lp = false);
+// Lower parts of BiCGStab's second application on a two-level pattern
+// (Schedule::y_in) with FP64 factors.  launch_spmv_lp: v = A phat on the
+// rows [fuse_n0, n) exactly as launch_spmv_v with r0 = fuse_n0 (same bits,
+// same partials), and in the same walk a_i = sum_k A'_ik inv(U_kk) r_k and
+// b_i = sum_k A'_ik inv(U_kk) v_k over the row's lower blocks (k <
+// fuse_n0), stored in k.lp at row i.  launch_lower_parts (after the half
+// step): shat_i = inv(U_ii) (s_i - (a_i - alpha b_i)) for the rows
+// [fuse_n0, n) (the second level, all finished there), which equals the
+// lower launch's inv(U_ii) (s_i - sum_k L_ik s_k) up to rounding, since
+// L_ik = A'_ik inv(U_kk) there.
+void launch_spmv_lp(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
+                    hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+void launch_lower_parts(const DevSchedule &d, const double *Dinv, size_t d_stride, Krylov &k, int nsys,
+                        hipStream_t s);
 inline int fuse_blocks(int n0, int waves) { return std::max(1, row_blocks(n0, waves)); }
 // x_orig[perm[i]] = x'[i]; then r = b - A x_orig with the caller's A, and the
 // true relative residual into the states.

@@ -1090,8 +1090,13 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRo
 k_usweep_spmv(DevSchedule d, const double *__restrict__ Ap, size_t a_stride, const T *__restrict__ Dinv,
               size_t d_stride, const TY *__restrict__ y, double *__restrict__ z, double *__restrict__ out,
               const double *__restrict__ w1, size_t vstride, SysState *__restrict__ st, double *__restrict__ part,
-              size_t part_stride, uint32_t *__restrict__ tk, size_t tk_stride, int defer) {
+              size_t part_stride, uint32_t *__restrict__ tk, size_t tk_stride, int defer,
+              const double *__restrict__ rr, double *__restrict__ P) {
     constexpr int CAP = kFuseCapPerWave * W, NT = 64 * W;
+    // lower parts (FP64 factors, v = A phat): inv(U_kk) r_k and inv(U_kk)
+    // v_k of these rows, six values per row in P (see k_spmv_lp)
+    constexpr bool LPC = sizeof(T) == sizeof(double) && MODE == SPMV_V;
+    const bool lp = LPC && P != nullptr;
     __shared__ Stage<double, CAP, NT> sv;
     int sys, bx;
     xcd_map(sys, bx);
@@ -1106,12 +1111,13 @@ k_usweep_spmv(DevSchedule d, const double *__restrict__ Ap, size_t a_stride, con
     constexpr bool PRODUCT = MODE != SPMV_PLAIN;
     T acc = 0;
     T dq[3] = {0, 0, 0};
-    double w = 0.0;
+    double w = 0.0, rk = 0.0;
     if (rl.act) {
         acc = (T)y[k];
         const T *dp = Dinv + (size_t)sys * d_stride + (size_t)(d.fuse_q0 + rl.q) * 9 + 3 * rl.r;
         dq[0] = dp[0]; dq[1] = dp[1]; dq[2] = dp[2];
         if (PRODUCT) w = w1[k];
+        if (lp) rk = rr[k];
     }
     const int e0 = d.prow[qb0], e1 = d.prow[qb1];
     // the lane's row: diagonal at my0, upper blocks [my0 + 1, my1)
@@ -1157,6 +1163,19 @@ k_usweep_spmv(DevSchedule d, const double *__restrict__ Ap, size_t a_stride, con
     }
     const double z0 = __shfl(zr, rl.base, 64), z1 = __shfl(zr, rl.base + 1, 64), z2 = __shfl(zr, rl.base + 2, 64);
     av += dot3(dg[0], dg[1], dg[2], z0, z1, z2);
+    if constexpr (LPC) {
+        if (lp) {
+            const double r0v = __shfl(rk, rl.base, 64), r1v = __shfl(rk, rl.base + 1, 64),
+                         r2v = __shfl(rk, rl.base + 2, 64);
+            const double v0 = __shfl(av, rl.base, 64), v1 = __shfl(av, rl.base + 1, 64),
+                         v2 = __shfl(av, rl.base + 2, 64);
+            if (rl.act) {
+                double *pp = P + 2 * vo + 6 * (size_t)rl.q + rl.r;
+                pp[0] = dot3((double)dq[0], (double)dq[1], (double)dq[2], r0v, r1v, r2v);
+                pp[3] = dot3((double)dq[0], (double)dq[1], (double)dq[2], v0, v1, v2);
+            }
+        }
+    }
     double v[2] = {0.0, 0.0};
     if (rl.act) {
         z[k] = zr;
@@ -1165,6 +1184,117 @@ k_usweep_spmv(DevSchedule d, const double *__restrict__ Ap, size_t a_stride, con
         v[1] = av * av;
     }
     group_reduce<2>(v, part + sys * part_stride, tk + sys * tk_stride, gridDim.x, bx);
+}
+
+// v = A phat on the rows [r0, n) (the rows with lower blocks of a two-level
+// pattern, r0 = fuse_n0: every other row's y is its input, see
+// Schedule::y_in), with k_spmv's arithmetic, order, partition and group
+// sums, and in the same walk the lower parts of the iteration's second
+// preconditioner application.  Row i's lower blocks are A'_ik, k < r0, and
+// L_ik = A'_ik inv(U_kk) (row k has no lower blocks, so ILU0 leaves A'_ik
+// alone and U_kk = A'_kk): with P_k = (inv(U_kk) r_k, inv(U_kk) v_k) (six
+// values per row, from the fused upper launch), the sums a_i = sum_k A'_ik
+// inv(U_kk) r_k and b_i = sum_k A'_ik inv(U_kk) v_k give sum_k L_ik s_k =
+// a_i - alpha b_i for s = r - alpha v once alpha is known (k_lower_parts).
+// (a_i, b_i) go to P at row i.  The FP64 block is read once for all three
+// sums.  P holds 6 values per row (2 vstride per system).
+template <int W, bool NTL>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(kRowWavesPerEU, 8)))
+k_spmv_lp(int n, int r0, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+          const double *__restrict__ A, size_t a_stride, const double *__restrict__ x, double *__restrict__ y,
+          size_t vstride, const double *__restrict__ w1, double *P, double *__restrict__ part,
+          size_t part_stride, uint32_t *__restrict__ tk, size_t tk_stride, SysState *__restrict__ st) {
+    constexpr int CAP = kSpmvCapPerWave * W, NT = 64 * W;
+    __shared__ Stage<double, CAP, NT> sv;
+    int sys, bx;
+    xcd_map(sys, bx);
+    const bool run = st[sys].phase == PH_RUN;   // tested once the walk's loads are in flight
+    constexpr int R = W * kRowsPerWave;
+    const RowLane rl = row_lane<W>(bx, r0, n);
+    const int qb0 = r0 + bx * R, qb1 = min(qb0 + R, n);
+    const size_t vo = (size_t)sys * vstride;
+    const size_t k = vo + 3 * (size_t)rl.q + rl.r;
+    const double *As = A + (size_t)sys * a_stride;
+    const double w = rl.act ? w1[k] : 0.0;
+    const int e0 = ptr[qb0], e1 = ptr[qb1];
+    const int my0 = rl.act ? ptr[rl.q] : 0, my1 = rl.act ? ptr[rl.q + 1] : 0;
+    double acc = 0.0, pa = 0.0, pb = 0.0;
+    for (int base = e0; base < e1; base += CAP) {
+        const int cnt = min(CAP, e1 - base);
+        __syncthreads();
+        const int shift = stage_copy<double, CAP, NT, NTL>(As, col, base, cnt, sv);
+        __syncthreads();
+        const double *vals = (const double *)sv.v + shift;
+        const int lo = max(my0, base), hi = min(my1, base + cnt);
+        for (int e = lo; e < hi; e += 4) {
+            double xv[4][3], av[4][3], bv[4][3];
+            bool low[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = sv.c[min(e + u, hi - 1) - base];
+                low[u] = j < r0;
+                const int jl = low[u] ? j : 0;
+                const double *pj = P + 2 * vo + 6 * (size_t)jl;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xv[u][c] = x[vo + 3 * (size_t)j + c];
+                    av[u][c] = pj[c];
+                    bv[u][c] = pj[3 + c];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (e + u < hi) {
+                    const double *b = vals + (e + u - base) * 9 + 3 * rl.r;
+                    acc += dot3(b[0], b[1], b[2], xv[u][0], xv[u][1], xv[u][2]);
+                    if (low[u]) {
+                        pa += dot3(b[0], b[1], b[2], av[u][0], av[u][1], av[u][2]);
+                        pb += dot3(b[0], b[1], b[2], bv[u][0], bv[u][1], bv[u][2]);
+                    }
+                }
+        }
+    }
+    asm volatile("" ::"v"(acc), "v"(pa), "v"(pb));
+    if (!run) return;
+    double v[2] = {0.0, 0.0};
+    if (rl.act) {
+        y[k] = acc;
+        double *pp = P + 2 * vo + 6 * (size_t)rl.q + rl.r;
+        pp[0] = pa;
+        pp[3] = pb;
+        v[0] = w * acc;
+        v[1] = acc * acc;
+    }
+    group_reduce<2>(v, part + sys * part_stride, tk + sys * tk_stride, gridDim.x, bx);
+}
+
+// The second preconditioner application's lower launch for the rows
+// [n0, n) of a two-level pattern (Schedule::y_in: row i at U-schedule
+// position i - n0; all rows finish here): z_i = inv(U_ii) (s_i - (a_i -
+// alpha b_i)) with (a_i, b_i) from k_spmv_lp in P and alpha of the half step.
+__global__ void __launch_bounds__(kRowThreads) k_lower_parts(int n0, int n, const double *__restrict__ Dinv,
+                                                             size_t d_stride, const double *__restrict__ s,
+                                                             const double *__restrict__ P, double *__restrict__ z,
+                                                             size_t vstride, SysState *__restrict__ st) {
+    int sys, bx;
+    xcd_map(sys, bx);
+    const RowLane rl = row_lane<kWavesPerBlock>(bx, n0, n);
+    const size_t vo = (size_t)sys * vstride;
+    const size_t k = vo + 3 * (size_t)rl.q + rl.r;
+    double sv = 0.0, pa = 0.0, pb = 0.0, dq[3] = {0.0, 0.0, 0.0};
+    if (rl.act) {
+        sv = s[k];
+        const double *pp = P + 2 * vo + 6 * (size_t)rl.q + rl.r;
+        pa = pp[0];
+        pb = pp[3];
+        const double *dp = Dinv + (size_t)sys * d_stride + (size_t)(rl.q - n0) * 9 + 3 * rl.r;
+        dq[0] = dp[0]; dq[1] = dp[1]; dq[2] = dp[2];
+    }
+    if (st[sys].phase != PH_RUN) return;
+    const double alpha = st[sys].alpha;
+    const double t = sv - (pa - alpha * pb);
+    const double t0 = __shfl(t, rl.base, 64), t1 = __shfl(t, rl.base + 1, 64), t2 = __shfl(t, rl.base + 2, 64);
+    if (rl.act) z[k] = dot3(dq[0], dq[1], dq[2], t0, t1, t2);
 }
 
 // ---------------------------------------------------------------- vectors
@@ -1990,7 +2120,7 @@ template <typename T>
 void launch_usweep_spmv(const DevSchedule &d, const double *Ap, size_t a_stride, const T *Dinv, size_t d_stride,
                         const T *y, const double *yd, double *z, double *out, const double *w1, SysState *st,
                         Krylov &k, int nsys, int mode, int spmv_variant, bool defer, hipStream_t s, hipEvent_t ev0,
-                        hipEvent_t ev1) {
+                        hipEvent_t ev1, bool lp) {
     if (d.fuse_n0 <= 0 || nsys <= 0) return;
     // the SpMV's launch shape: its waves per workgroup, and non-temporal
     // matrix loads for the shapes that use them (direct shapes stage too:
@@ -2001,7 +2131,8 @@ void launch_usweep_spmv(const DevSchedule &d, const double *Ap, size_t a_stride,
         const dim3 g(fuse_blocks(d.fuse_n0, w), nsys), b(64 * w);
         auto go = [&](auto kern, auto yp) {
             launch_ev(kern, g, b, s, ev0, ev1, d, Ap, a_stride, Dinv, d_stride, yp, z, out, w1, k.vstride, st,
-                      k.fpart, k.fpart_stride, k.tickets, k.ticket_stride, defer ? 1 : 0);
+                      k.fpart, k.fpart_stride, k.tickets, k.ticket_stride, defer ? 1 : 0, (const double *)k.r,
+                      lp ? k.lp : (double *)nullptr);
         };
         auto by_mode = [&](auto yp) {
             using TY = std::remove_const_t<std::remove_pointer_t<decltype(yp)>>;
@@ -2017,11 +2148,34 @@ void launch_usweep_spmv(const DevSchedule &d, const double *Ap, size_t a_stride,
 template void launch_usweep_spmv<double>(const DevSchedule &, const double *, size_t, const double *, size_t,
                                          const double *, const double *, double *, double *, const double *,
                                          SysState *, Krylov &, int, int, int, bool, hipStream_t, hipEvent_t,
-                                         hipEvent_t);
+                                         hipEvent_t, bool);
 template void launch_usweep_spmv<float>(const DevSchedule &, const double *, size_t, const float *, size_t,
                                         const float *, const double *, double *, double *, const double *,
                                         SysState *, Krylov &, int, int, int, bool, hipStream_t, hipEvent_t,
-                                        hipEvent_t);
+                                        hipEvent_t, bool);
+
+void launch_spmv_lp(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant,
+                    hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    const int r0 = d.fuse_n0;
+    if (d.n - r0 <= 0 || nsys <= 0) return;
+    // the SpMV's launch shape (waves per workgroup, load kind); direct
+    // shapes stage too
+    with_variant(variant, [&](auto Wc, auto ST) {
+        constexpr int w = decltype(Wc)::value;
+        constexpr bool nt = decltype(ST)::value == 2;
+        launch_ev(k_spmv_lp<w, nt>, dim3(spmv_grid(d.n - r0, w), nsys), dim3(64 * w), s, ev0, ev1, d.n, r0, d.prow,
+                  d.pcol, Ap, a_stride, (const double *)k.phat, k.v, k.vstride, (const double *)k.rhat, k.lp,
+                  k.spart, k.spart_stride, k.tickets, k.ticket_stride, k.st);
+    });
+}
+
+void launch_lower_parts(const DevSchedule &d, const double *Dinv, size_t d_stride, Krylov &k, int nsys,
+                        hipStream_t s) {
+    const int n0 = d.fuse_n0;
+    if (d.n <= n0 || nsys <= 0) return;
+    k_lower_parts<<<dim3(row_blocks(d.n - n0), nsys), kRowThreads, 0, s>>>(n0, d.n, Dinv, d_stride, k.s, k.lp,
+                                                                           k.shat, k.vstride, k.st);
+}
 
 void launch_permute_vec(const int32_t *perm, const double *in, double *out, int n, size_t vstride, int nsys,
                         bool scatter, hipStream_t s) {

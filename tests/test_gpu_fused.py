@@ -199,6 +199,8 @@ def test_y_from_the_input_gives_the_same_bits(grid, precision):
     b = s.b[:, 0]
     with rs.Solver(s.rowptr, s.colidx, s.vals, ordering=rs.ORDER_GRAPH_COLOUR, precision=precision) as sol:
         assert sol.factor()[0] == rs.OK
+        # the lower parts need y from the input; they round differently
+        rs.ilu0_set_option(sol.M, rs.OPT_LOWER_PARTS, 0)
         assert rs.ilu0_get_option(sol.M, rs.OPT_Y_INPUT_PATTERN) == 1
         assert rs.ilu0_get_option(sol.M, rs.OPT_Y_INPUT) == 1
         on = _solves(sol, b, 1e-10)
@@ -245,3 +247,35 @@ def test_y_from_the_input_stays_off_where_the_pattern_does_not_allow_it():
     with pytest.raises(rs.RsolveError):
         with rs.Solver(grid.rowptr, grid.colidx, grid.vals) as sol:
             rs.ilu0_set_option(sol.M, rs.OPT_Y_INPUT_PATTERN, 1)
+
+
+@pytest.mark.parametrize("grid", [(20, 20, 10), (7, 5, 3), (33, 17, 5)])
+def test_lower_parts_agree_with_the_lower_launch(grid):
+    """FP64 factors, bipartite grids under graph colouring: BiCGStab's second
+    application with its lower parts formed in v = A phat
+    (RS_OPT_LOWER_PARTS) agrees with the lower launch that reads L to
+    rounding (x within 1e-10 at a reduction of 1e-10, half steps within 2),
+    on a batch of two with graphs replayed and eager; each configuration is
+    deterministic and the batch members equal their solves alone."""
+    s = make_ensemble(*grid, seeds=[sum(grid) + 7, sum(grid) + 8])
+    b = s.b[:, 0]
+    with rs.Solver(s.rowptr, s.colidx, s.vals, ordering=rs.ORDER_GRAPH_COLOUR) as sol:
+        sol.factor()
+        assert rs.ilu0_get_option(sol.M, rs.OPT_LOWER_PARTS) == 1
+        x1, st1, i1 = sol.solve(b, reduction=1e-10)
+        x1b, _, i1b = sol.solve(b, reduction=1e-10)
+        rs.ilu0_set_option(sol.M, rs.OPT_USE_GRAPH, 0)
+        x1e, _, i1e = sol.solve(b, reduction=1e-10)
+        rs.ilu0_set_option(sol.M, rs.OPT_USE_GRAPH, 1)
+        rs.ilu0_set_option(sol.M, rs.OPT_LOWER_PARTS, 0)
+        x0, st0, i0 = sol.solve(b, reduction=1e-10)
+    assert st1 == st0 == rs.OK
+    assert np.array_equal(x1, x1b) and np.array_equal(x1, x1e) and outcome(i1) == outcome(i1b) == outcome(i1e)
+    for k in range(s.batch):
+        assert np.linalg.norm(x1[k] - x0[k]) <= 1e-10 * np.linalg.norm(x0[k])
+        assert abs(i1[k]["half_steps"] - i0[k]["half_steps"]) <= 2
+        assert i1[k]["true_rel_residual"] <= 1e-9
+        with rs.Solver(s.rowptr, s.colidx, s.vals[k:k + 1], ordering=rs.ORDER_GRAPH_COLOUR) as one:
+            one.factor()
+            xa, _, ia = one.solve(s.b[k:k + 1, 0], reduction=1e-10)
+        assert np.array_equal(xa[0], x1[k]) and outcome(ia) == outcome([i1[k]])
