@@ -150,6 +150,7 @@ static size_t instance_bytes(int32_t n, int32_t nnzb, int32_t precision) {
                + 8 * (2 * N / 21 + 8192)             // reduction partials
                + (1 << 20);                          // small buffers
     if (precision == RS_PREC_FP32_FACTORS) b += 36 * Z;
+    else b += 8 * 2 * vec;                           // lower parts of the second application (two-level patterns)
     return (size_t)b;
 }
 
