@@ -428,8 +428,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU only: the solver runs on a single MI355X; "
-                                   "run bench.py with --gpus 1"}), flush=True)
+        print(json.dumps({"error": "bench.py measures one GPU only: the solver runs on a single MI355X "
+                                   "(a system or request per GPU is how it would spread); run it with --gpus 1"}),
+              flush=True)
         sys.exit(2)
 
     if args.workload == "c5":

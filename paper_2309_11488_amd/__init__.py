@@ -106,7 +106,7 @@ def lib():
         except ImportError:  # pragma: no cover - host-only callers
             pass
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2309_11488_amd.build`")
         L = ct.CDLL(LIB_PATH)
         i32, vp, dbl = ct.c_int32, ct.c_void_p, ct.c_double
         P = ct.POINTER
