@@ -318,7 +318,10 @@ def measure(P, precision, reduction, steps, warmup, roofline="auto", key=None, l
     M, tune = P.handle(precision, reduction)
     prec = PREC[precision]
     rec = {"half": [], "res": [], "status": [], "factor_ms": [], "solve_ms": []}
-    period = max(rhs, 4) + 1          # one solve in every `period` is timed when a solve class is
+    # when a solve class is timed, one solve in every `period` records its
+    # events: two of the timed steps' solves (the sampled solves launch
+    # eagerly, with events between kernels)
+    period = max((steps * rhs + 1) // 2, 1)
     sample = {"mask": 0, "count": 0}
 
     def solve(j):

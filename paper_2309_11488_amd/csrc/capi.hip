@@ -1633,7 +1633,8 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(M->ev_s1, s));
         HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(M->h_ctr, k.lctr, 2 * sizeof(rs::SweepCtr), hipMemcpyDeviceToHost, s));
+        // only single-launch sweeps touch the sweep counters
+        if (M->tile_sweeps) HIP_TRY(hipMemcpyAsync(M->h_ctr, k.lctr, 2 * sizeof(rs::SweepCtr), hipMemcpyDeviceToHost, s));
         if (mem != RS_MEM_DEVICE) HIP_TRY(hipMemcpyAsync(x, xd, m * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         return RS_OK;
@@ -1674,7 +1675,7 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
         st = finish();
         if (st != RS_OK) return st;
     }
-    if (M->h_ctr[0].error || M->h_ctr[1].error) return sweep_reset(M, s);
+    if (M->tile_sweeps && (M->h_ctr[0].error || M->h_ctr[1].error)) return sweep_reset(M, s);
     const double solve_ms = elapsed_ms(M->ev_s0, M->ev_s1);
     int worst = RS_OK, needed = 1;
     for (int i = 0; i < B; ++i) {
@@ -1840,7 +1841,8 @@ int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart,
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(M->ev_s1, s));
         HIP_TRY(hipMemcpyAsync(M->h_state, k.st, B * sizeof(SysState), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(M->h_ctr, k.lctr, 2 * sizeof(rs::SweepCtr), hipMemcpyDeviceToHost, s));
+        // only single-launch sweeps touch the sweep counters
+        if (M->tile_sweeps) HIP_TRY(hipMemcpyAsync(M->h_ctr, k.lctr, 2 * sizeof(rs::SweepCtr), hipMemcpyDeviceToHost, s));
         if (mem != RS_MEM_DEVICE) HIP_TRY(hipMemcpyAsync(x, xd, m * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         return RS_OK;
@@ -1900,7 +1902,7 @@ int gmres_solve(ilu0_t M, bcsr_t A, const double *b, double *x, int32_t restart,
         st = finish();
         if (st != RS_OK) return st;
     }
-    if (M->h_ctr[0].error || M->h_ctr[1].error) return sweep_reset(M, s);
+    if (M->tile_sweeps && (M->h_ctr[0].error || M->h_ctr[1].error)) return sweep_reset(M, s);
     const double solve_ms = elapsed_ms(M->ev_s0, M->ev_s1);
     int worst = RS_OK, needed = 1;
     for (int i = 0; i < B; ++i) {
