@@ -544,6 +544,15 @@ int build_schedule(int n, int nnzb, const int32_t *rowptr, const int32_t *colidx
         s.y_in = ok ? 1 : 0;
     }
 
+    s.lnarrow.assign(s.nl_levels, 1);
+    for (int l = 0; l < s.nl_levels; ++l)
+        for (int q = s.lset[l]; q < s.lset[l + 1]; ++q) {
+            const int uq = s.l2u[q];
+            if (s.lptr[q + 1] - s.lptr[q] > 6 || s.uptr[uq + 1] - s.uptr[uq] > 6) {
+                s.lnarrow[l] = 0;
+                break;
+            }
+        }
     s.lconsec.assign(s.nl_levels, 1);
     for (int l = 0; l < s.nl_levels; ++l)
         for (int q = s.lset[l]; q < s.lset[l + 1]; ++q)

@@ -50,6 +50,7 @@ struct Schedule {
     int nl_levels = 0, nL = 0;
     std::vector<int32_t> lrows, lset, lptr, lcol, lsrc, ldq, l2u;
     std::vector<char> lconsec;   // per lower level: its rows are consecutive in the new order
+    std::vector<char> lnarrow;   // per lower level: no row holds more than 6 lower or 6 upper blocks
     // upper sweep
     int nu_levels = 0, nU = 0;
     std::vector<int32_t> urows, uset, uptr, ucol, usrc, dsrc;

@@ -860,8 +860,8 @@ int ilu0_factor(ilu0_t M, bcsr_t A, int32_t precision, void *stream, int32_t *ba
                                     M->U.as<double>(), M->Dinv.as<double>(), f32 ? M->Lf.as<float>() : nullptr,
                                     f32 ? M->Uf.as<float>() : nullptr, f32 ? M->Dinvf.as<float>() : nullptr,
                                     M->bad.as<int32_t>(), S.lset[l], S.lset[l + 1],
-                                    S.lconsec[l] && S.rest_dst.empty(), skip_u0, l == S.nl_levels - 1, M->batch,
-                                    s);
+                                    S.lconsec[l] && S.rest_dst.empty(), skip_u0, l == S.nl_levels - 1,
+                                    S.lnarrow[l] != 0, M->batch, s);
         }
         M->u_missing = skip_u0;
     }

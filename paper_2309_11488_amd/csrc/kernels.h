@@ -160,9 +160,11 @@ void launch_gather_pairs(const double *A, size_t a_stride, double *Ap, size_t ap
 // or the FP32 U of FP32 factors; their U rows are their rows of A': see
 // launch_fill_u).  last: the last level, whose FP64 pivot inverses no
 // later level reads (with FP32 factors only the FP32 copy is stored).
+// narrow: no row of the level holds more than 6 lower or 6 upper blocks
+// (Schedule::lnarrow), which a kernel with fewer registers per lane serves.
 void launch_factor_level(const DevSchedule &d, const double *A, size_t a_stride, double *Ap, double *L, double *U,
                          double *Dinv, float *Lf, float *Uf, float *Df, int32_t *bad, int q0, int q1, bool staged,
-                         bool skip_u0, bool last, int nsys, hipStream_t s);
+                         bool skip_u0, bool last, bool narrow, int nsys, hipStream_t s);
 // The first level of the factorisation when it is the rows [0, d.fuse_n0)
 // of the new order (rows without lower blocks, U-schedule positions fuse_q0
 // + i): their blocks of the reordered copy Ap (copied from the caller's A),

@@ -389,9 +389,12 @@ __global__ void k_gather_pairs(const double *__restrict__ A, size_t a_stride, do
 
 // ------------------------------------------------------------------ factor
 
-// Rows with at most kFactorMax lower and kFactorMax upper blocks keep their
-// slices in registers; longer rows work through global memory.
-constexpr int kFactorMax = 8;
+// Rows with at most FM lower and FM upper blocks keep their slices in
+// registers; longer rows work through global memory.  FM is the level's
+// register width: kFactorNarrow when every row of the level fits it (the
+// 7-point grids under colouring), else kFactorWide.  The narrow kernel's
+// 148 VGPRs allow three waves per SIMD, the wide kernel's 176 two.
+constexpr int kFactorNarrow = 6, kFactorWide = 8;
 
 __device__ inline void row3_load(const double *p, double (&v)[3]) { v[0] = p[0]; v[1] = p[1]; v[2] = p[2]; }
 __device__ inline void row3_store(double *p, const double (&v)[3]) { p[0] = v[0]; p[1] = v[1]; p[2] = v[2]; }
@@ -444,7 +447,7 @@ __device__ inline double inv3_row(const double (&a)[9], int r, double (&inv)[3])
 // every lane storing 8-byte pieces spread over 21 rows.
 constexpr int kApCap = 640;
 
-template <bool F32, bool STAGED>
+template <bool F32, bool STAGED, int FM>
 __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, const double *__restrict__ A,
                                                               size_t a_stride, double *__restrict__ Ap,
                                                               double *__restrict__ L, double *__restrict__ U,
@@ -487,26 +490,26 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
         const int e0 = d.lptr[q], e1 = d.lptr[q + 1], f0 = d.uptr[uq], f1 = d.uptr[uq + 1];
         row3_load(As + (size_t)d.dsrc_a[uq] * 9 + 3 * r, dr);
         ap_store(d.dsrc[uq], dr);
-        if (e1 - e0 <= kFactorMax && f1 - f0 <= kFactorMax) {
-            double lv[kFactorMax][3], uv[kFactorMax][3];
-            int dq[kFactorMax];
+        if (e1 - e0 <= FM && f1 - f0 <= FM) {
+            double lv[FM][3], uv[FM][3];
+            int dq[FM];
 #pragma unroll
-            for (int t = 0; t < kFactorMax; ++t)
+            for (int t = 0; t < FM; ++t)
                 if (e0 + t < e1) {
                     row3_load(As + (size_t)d.lsrc_a[e0 + t] * 9 + 3 * r, lv[t]);
                     dq[t] = d.ldq[e0 + t];
                 }
 #pragma unroll
-            for (int t = 0; t < kFactorMax; ++t)
+            for (int t = 0; t < FM; ++t)
                 if (f0 + t < f1) row3_load(As + (size_t)d.usrc_a[f0 + t] * 9 + 3 * r, uv[t]);
 #pragma unroll
-            for (int t = 0; t < kFactorMax; ++t)
+            for (int t = 0; t < FM; ++t)
                 if (e0 + t < e1) ap_store(d.lsrc[e0 + t], lv[t]);
 #pragma unroll
-            for (int t = 0; t < kFactorMax; ++t)
+            for (int t = 0; t < FM; ++t)
                 if (f0 + t < f1) ap_store(d.usrc[f0 + t], uv[t]);
 #pragma unroll
-            for (int t = 0; t < kFactorMax; ++t) {
+            for (int t = 0; t < FM; ++t) {
                 if (e0 + t >= e1) continue;
                 double l[3];
                 row3_mul(lv[t], Ds + (size_t)dq[t] * 9 + 3 * r, rl.base, l);
@@ -521,17 +524,17 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
                         dr[0] -= pr[0]; dr[1] -= pr[1]; dr[2] -= pr[2];
                     } else if (kind == 0) {
 #pragma unroll
-                        for (int j = 0; j < kFactorMax; ++j)
+                        for (int j = 0; j < FM; ++j)
                             if (j == pos - e0) { lv[j][0] -= pr[0]; lv[j][1] -= pr[1]; lv[j][2] -= pr[2]; }
                     } else {
 #pragma unroll
-                        for (int j = 0; j < kFactorMax; ++j)
+                        for (int j = 0; j < FM; ++j)
                             if (j == pos - f0) { uv[j][0] -= pr[0]; uv[j][1] -= pr[1]; uv[j][2] -= pr[2]; }
                     }
                 }
             }
 #pragma unroll
-            for (int t = 0; t < kFactorMax; ++t)
+            for (int t = 0; t < FM; ++t)
                 if (e0 + t < e1) {
                     // later levels never read L: with FP32 factors only the FP32 copy is kept
                     if (F32) row3_store(Lf + ((size_t)sys * d.nL + e0 + t) * 9 + 3 * r, lv[t]);
@@ -542,7 +545,7 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
             // reordered copy instead
             const bool keep_u = e1 > e0 || (!F32 && !skip_u0);
 #pragma unroll
-            for (int t = 0; t < kFactorMax; ++t)
+            for (int t = 0; t < FM; ++t)
                 if (f0 + t < f1) {
                     if (keep_u) row3_store(Us + (size_t)(f0 + t) * 9 + 3 * r, uv[t]);
                     if (F32 && (e1 > e0 || !skip_u0)) row3_store(Uf + ((size_t)sys * d.nU + f0 + t) * 9 + 3 * r, uv[t]);
@@ -1917,19 +1920,23 @@ void launch_gather_pairs(const double *A, size_t a_stride, double *Ap, size_t ap
 
 void launch_factor_level(const DevSchedule &d, const double *A, size_t a_stride, double *Ap, double *L, double *U,
                          double *Dinv, float *Lf, float *Uf, float *Df, int32_t *bad, int q0, int q1, bool staged,
-                         bool skip_u0, bool last, int nsys, hipStream_t s) {
+                         bool skip_u0, bool last, bool narrow, int nsys, hipStream_t s) {
     if (q1 <= q0 || nsys <= 0) return;
     const dim3 g(row_blocks(q1 - q0), nsys);
-    auto go = [&](auto F32, auto STG) {
-        k_factor_level<decltype(F32)::value, decltype(STG)::value><<<g, kRowThreads, 0, s>>>(
+    auto go = [&](auto F32, auto STG, auto FM) {
+        k_factor_level<decltype(F32)::value, decltype(STG)::value, decltype(FM)::value><<<g, kRowThreads, 0, s>>>(
             d, A, a_stride, Ap, L, U, Dinv, Lf, Uf, Df, bad, q0, q1, skip_u0 ? 1 : 0, last ? 1 : 0);
+    };
+    auto width = [&](auto F32, auto STG) {
+        if (narrow) go(F32, STG, std::integral_constant<int, kFactorNarrow>{});
+        else go(F32, STG, std::integral_constant<int, kFactorWide>{});
     };
     using T = std::true_type;
     using F = std::false_type;
     if (Lf) {
-        if (staged) go(T{}, T{}); else go(T{}, F{});
+        if (staged) width(T{}, T{}); else width(T{}, F{});
     } else {
-        if (staged) go(F{}, T{}); else go(F{}, F{});
+        if (staged) width(F{}, T{}); else width(F{}, F{});
     }
 }
 
