@@ -467,13 +467,25 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
     const int r = rl.r;
     // the workgroup's range of the reordered copy (rows consecutive)
     int ap0 = 0, apn = kApCap + 1;
+    // and of L (the L blocks of consecutive L-schedule rows are consecutive)
+    int l0 = 0, ln = 0;
     if (STAGED) {
         const int qb0 = q0 + bx * kRowsPerBlock, qb1 = min(qb0 + kRowsPerBlock, q1);
         const int i0 = d.lrows[qb0];
         ap0 = d.prow[i0];
         apn = d.prow[i0 + (qb1 - qb0)] - ap0;
+        l0 = d.lptr[qb0];
+        ln = d.lptr[qb1] - l0;
     }
     const bool stage = STAGED && apn <= kApCap;
+    // On a narrow level every row takes the register path below, so the
+    // workgroup's L blocks all sit in registers once the rows are done: they
+    // go through the same LDS after the copy has left it, and out as one
+    // range, instead of as 24-byte slices spread over 21 rows per store.
+    constexpr bool SL = STAGED && FM == kFactorNarrow;
+    const bool stage_l = SL && stage && ln <= (F32 ? 2 : 1) * kApCap;
+    double lkeep[SL ? FM : 1][3];
+    int le0 = 0, le1 = 0;
     auto ap_store = [&](int pos, const double (&v)[3]) {
         if (stage) {
             double *t = sap + (size_t)(pos - ap0) * 9 + 3 * r;
@@ -533,9 +545,17 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
                     }
                 }
             }
+            le0 = e0;
+            le1 = e1;
 #pragma unroll
             for (int t = 0; t < FM; ++t)
                 if (e0 + t < e1) {
+                    if constexpr (SL) {
+                        if (stage_l) {
+                            lkeep[t][0] = lv[t][0]; lkeep[t][1] = lv[t][1]; lkeep[t][2] = lv[t][2];
+                            continue;
+                        }
+                    }
                     // later levels never read L: with FP32 factors only the FP32 copy is kept
                     if (F32) row3_store(Lf + ((size_t)sys * d.nL + e0 + t) * 9 + 3 * r, lv[t]);
                     else row3_store(Ls + (size_t)(e0 + t) * 9 + 3 * r, lv[t]);
@@ -602,6 +622,33 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
         __syncthreads();
         double *dst = Aps + (size_t)ap0 * 9;
         for (int k = threadIdx.x; k < apn * 9; k += kRowThreads) dst[k] = sap[k];
+    }
+    if constexpr (SL) {
+      if (stage_l) {
+        __syncthreads();   // the copy has been read out of the LDS
+        if (rl.act) {
+#pragma unroll
+            for (int t = 0; t < FM; ++t)
+                if (le0 + t < le1) {
+                    const size_t o = (size_t)(le0 + t - l0) * 9 + 3 * r;
+                    if (F32) {
+                        float *sl = (float *)sap + o;
+                        sl[0] = (float)lkeep[t][0]; sl[1] = (float)lkeep[t][1]; sl[2] = (float)lkeep[t][2];
+                    } else {
+                        sap[o] = lkeep[t][0]; sap[o + 1] = lkeep[t][1]; sap[o + 2] = lkeep[t][2];
+                    }
+                }
+        }
+        __syncthreads();
+        if (F32) {
+            const float *sl = (const float *)sap;
+            float *dst = Lf + ((size_t)sys * d.nL + l0) * 9;
+            for (int k = threadIdx.x; k < ln * 9; k += kRowThreads) dst[k] = sl[k];
+        } else {
+            double *dst = Ls + (size_t)l0 * 9;
+            for (int k = threadIdx.x; k < ln * 9; k += kRowThreads) dst[k] = sap[k];
+        }
+      }
     }
     // gather the three rows of U_ii from the row's lanes
     double a[9];
