@@ -444,7 +444,8 @@ __device__ inline double inv3_row(const double (&a)[9], int r, double (&inv)[3])
 // order, and every block of their reordered rows is written here), a
 // workgroup whose rows hold at most kApCap blocks collects that copy in LDS
 // and writes its contiguous range out with consecutive stores, instead of
-// every lane storing 8-byte pieces spread over 21 rows.
+// every lane storing 8-byte pieces spread over 21 rows.  FM: the register
+// width (kFactorNarrow only for levels whose rows all fit it).
 constexpr int kApCap = 640;
 
 template <bool F32, bool STAGED, int FM>
@@ -478,8 +479,10 @@ __global__ void __launch_bounds__(kRowThreads) k_factor_level(DevSchedule d, con
         ln = d.lptr[qb1] - l0;
     }
     const bool stage = STAGED && apn <= kApCap;
-    // On a narrow level every row takes the register path below, so the
-    // workgroup's L blocks all sit in registers once the rows are done: they
+    // On a narrow level (launch_factor_level is given narrow only when no
+    // row of the level holds more than kFactorNarrow lower or upper blocks)
+    // every row takes the register path below, so the workgroup's L blocks
+    // all sit in registers once the rows are done: they
     // go through the same LDS after the copy has left it, and out as one
     // range, instead of as 24-byte slices spread over 21 rows per store.
     constexpr bool SL = STAGED && FM == kFactorNarrow;
