@@ -167,16 +167,27 @@ def test_apply_parity(solver_of, name, ordering, precision):
         assert np.all(np.abs(z[0][perm] - zp) <= bound)
 
 
-def test_fp32_factors_are_rounded_fp64_factors(solver_of):
-    s = CASES["nnc"]
-    A, M, st, _ = solver_of(s, rs.ORDER_LEVEL_SET, rs.PREC_FP32_FACTORS)
-    _, prow, pcol, _, _, _, lu, dinv = oracle_factors(s, rs.ORDER_LEVEL_SET)
-    glu, gdinv = rs.ilu0_get_factors(M, 0, s.n, s.nnzb)
-    offd = np.array([pcol[p] != i for i in range(s.n) for p in range(prow[i], prow[i + 1])], bool)
-    for g, o in ((glu[offd], lu[offd]), (gdinv, dinv)):
-        o32 = o.astype(np.float32)
-        ulp = np.spacing(np.abs(o32)).astype(np.float64)
-        assert np.all(np.abs(g - o32.astype(np.float64)) <= ulp)
+@pytest.mark.parametrize("case", ["nnc_level_sets", "grid_batch_colour"])
+def test_fp32_factors_are_rounded_fp64_factors(solver_of, case):
+    """FP32 factors within an ulp of the oracle's FP64 factors rounded to
+    FP32: non-neighbour connections under level sets (levels whose rows
+    keep their slices in 8 and in 6 registers), and a batch of two grid
+    systems under colouring (the second colour's L blocks leave through the
+    workgroup's LDS as one range, at a per-system offset)."""
+    if case == "nnc_level_sets":
+        s, ordering = CASES["nnc"], rs.ORDER_LEVEL_SET
+    else:
+        s, ordering = make_ensemble(17, 13, 7, seeds=[41, 42]), rs.ORDER_GRAPH_COLOUR
+    A, M, st, _ = solver_of(s, ordering, rs.PREC_FP32_FACTORS)
+    assert st == rs.OK
+    for k in range(s.vals.shape[0]):
+        _, prow, pcol, _, _, _, lu, dinv = oracle_factors(s, ordering, s.vals[k])
+        glu, gdinv = rs.ilu0_get_factors(M, k, s.n, s.nnzb)
+        offd = np.array([pcol[p] != i for i in range(s.n) for p in range(prow[i], prow[i + 1])], bool)
+        for g, o in ((glu[offd], lu[offd]), (gdinv, dinv)):
+            o32 = o.astype(np.float32)
+            ulp = np.spacing(np.abs(o32)).astype(np.float64)
+            assert np.all(np.abs(g - o32.astype(np.float64)) <= ulp)
 
 
 @pytest.mark.parametrize("ordering", ORDERINGS)
