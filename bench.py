@@ -96,6 +96,9 @@ def parse(argv=None):
     ap.add_argument("--restart", type=int, default=30, help="GMRES restart length (1..32)")
     ap.add_argument("--jacobi", type=int, default=0, metavar="P",
                     help="Block-Jacobi-ILU0 with P transmissibility-weighted partitions (0: plain ILU0)")
+    ap.add_argument("--wells", type=int, default=0, metavar="W",
+                    help="standard wells kept separate (Algorithm 5): W vertical wells on the workload's grid, "
+                         "drawn by synth/wells.py (seed 11); the SpMVs and the true residual subtract them")
     ap.add_argument("--no-extras", action="store_true",
                     help="1M-cell grid: skip the mixed-precision and 1e-6 runs")
     ap.add_argument("--no-serving", action="store_true", help="1M-cell grid: skip the bounded request stream")
@@ -262,6 +265,12 @@ class Problem:
         rs.bcsr_set_values(self.A, hv)
         torch.cuda.synchronize()
         self.upload_ms = (time.perf_counter() - t) * 1e3
+        self.n_perf = 0
+        if args.wells:
+            from synth import make_wells
+            w = make_wells(s, args.wells, seed=11, batch=s.batch)
+            rs.bcsr_set_wells(self.A, w.well_ptr, w.perf_row, w.B, w.C, w.Dinv)
+            self.n_perf = w.n_perf
         self.handles = {}
         t = time.perf_counter()
         self.base = self._analyse()
@@ -466,11 +475,11 @@ def main():
         f"{P.analyse_ms:.1f} ms; value upload from host {P.upload_ms:.2f} ms")
     # key of the committed counter runs (profiles/traffic.json) for this configuration
     key = f"c3_{precision}" if args.workload == "c3" else args.workload
-    if args.jacobi or gmres or args.ordering != "colour":
+    if args.jacobi or gmres or args.ordering != "colour" or args.wells:
         key = None
     head = measure(P, precision, reduction, args.steps, args.warmup, args.roofline, key=key, label=precision)
     extras = args.workload == "c3" and not args.no_extras and not gmres and args.precision is None \
-        and args.reduction is None
+        and args.reduction is None and not args.wells
     mixed = red6 = None
     if extras:
         # the same workload with FP32-stored factors at the same reduction,
@@ -492,7 +501,9 @@ def main():
         serving = serve(args, requests=args.serve_requests, loads=[0.5], burst=100,
                         plain_seeds={10_000: 2, 50_000: 2, 200_000: 1, 1_000_000: 1}, cpu=False)
     cpu = None
-    if not args.no_cpu:
+    if args.wells and not args.no_cpu:
+        log("cpu oracle: not timed with wells (the baseline leg times the plain oracle solve)")
+    elif not args.no_cpu:
         v, nsol, dt = cpu_baseline(s, rhs, ordering, precision, reduction, args.cpu_seconds, part,
                                    args.restart if gmres else 0)
         hc = host_cpu()
@@ -526,6 +537,7 @@ def main():
                    "y_input": args.y_input, "y_input_pattern": P.y_input_pattern,
                    "factor_async": args.factor_async,
                    "jacobi_partitions": args.jacobi or None,
+                   "wells": args.wells or None, "perforations": P.n_perf or None,
                    "mean_half_steps": head["mean_half_steps"],
                    "max_true_rel_residual": head["max_true_rel_residual"], "statuses": head["statuses"],
                    "launch_config": head["launch_config"],
