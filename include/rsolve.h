@@ -131,8 +131,10 @@ enum rs_option {
                                 covers the other rows.  Same z; v and t of those rows add the
                                 diagonal's term last, and the dot products' summation order
                                 changes: the solve agrees with the unfused one to rounding.
-                                Used with per-level sweeps, reduction split 0 and no separate
-                                wells; 0: never */
+                                With separate wells (bcsr_set_wells), the well terms of those
+                                rows, which need the whole product's x, are subtracted after
+                                the SpMV by a small launch that also corrects the dot products.
+                                Used with per-level sweeps and reduction split 0; 0: never */
     RS_OPT_FUSED_ROWS = 10,  /* read only (ilu0_get_option): how many rows the analysed pattern
                                 lets RS_OPT_FUSE_SPMV fuse (0: none) */
     RS_OPT_Y_INPUT = 11,     /* 1 (default): where the analysed pattern allows it (RS_OPT_Y_INPUT_PATTERN),
@@ -161,7 +163,8 @@ enum rs_option {
                                 sum_k A'_ik inv(U_kk) v_k of each row with lower blocks (its lower
                                 blocks are L_ik = A'_ik inv(U_kk) on such a pattern); the
                                 iteration's second application then forms sum_k L_ik s_k as their
-                                combination for s = r - alpha v instead of reading L again.  The
+                                combination for s = r - alpha v instead of reading L again (not
+                                with separate wells).  The
                                 same mathematics (Algorithm 2, equations 3-4), other rounding: the
                                 solves agree with the option off to rounding; 0: off */
 };

@@ -276,7 +276,8 @@ struct rs_ilu0 {
     const rs_bcsr *wells_of = nullptr;
     long long wells_version = -1;
     std::vector<int32_t> h_wperf_x, h_wrow_ptr, h_wrow_perf;
-    DevBuf wperf_x, wrow_ptr, wrow_perf, wt2;
+    DevBuf wperf_x, wrow_ptr, wrow_perf, wt2, wfix;
+    std::vector<int32_t> h_wfix;   // rows below fuse_n0 that a perforation couples
     rs::WellsDev wdev{};
     int split() const { return reduce_split; }
     // a BiCGStab iteration captured as HIP graphs, replayed on the caller's
@@ -940,6 +941,10 @@ static int ensure_wells(ilu0_t M, const rs_bcsr *A, hipStream_t s) {
         HIP_TRY(upload(M->wperf_x, M->h_wperf_x, s));
         HIP_TRY(upload(M->wrow_ptr, M->h_wrow_ptr, s));
         HIP_TRY(upload(M->wrow_perf, M->h_wrow_perf, s));
+        M->h_wfix.clear();
+        for (int i = 0; i < M->an->sch.fuse_n0; ++i)
+            if (M->h_wrow_ptr[i + 1] > M->h_wrow_ptr[i]) M->h_wfix.push_back(i);
+        HIP_TRY(upload(M->wfix, M->h_wfix, s));
         HIP_TRY(M->wt2.alloc((size_t)M->batch * A->nw * 4 * sizeof(double)));
         M->wells_of = A;
         M->wells_version = A->wells_version;
@@ -949,6 +954,8 @@ static int ensure_wells(ilu0_t M, const rs_bcsr *A, hipStream_t s) {
     w.row_ptr = M->wrow_ptr.as<int32_t>();
     w.row_perf = M->wrow_perf.as<int32_t>();
     w.t2 = M->wt2.as<double>();
+    w.nfix = (int)M->h_wfix.size();
+    w.fix_row = M->wfix.as<int32_t>();
     M->wdev = w;
     return RS_OK;
 }
@@ -1125,7 +1132,7 @@ static void lower_levels(ilu0_t M, const T *L, const T *D, const double *in, dou
 // Whether BiCGStab's iterations fuse the upper launch of the rows without
 // lower blocks with their rows of the SpMV that follows (RS_OPT_FUSE_SPMV).
 static bool fused_iteration(const rs_ilu0 *M) {
-    return M->fuse_spmv && M->an->sch.fuse_n0 > 0 && !M->tile_sweeps && M->split() == 0 && M->wdev.nw == 0;
+    return M->fuse_spmv && M->an->sch.fuse_n0 > 0 && !M->tile_sweeps && M->split() == 0;
 }
 
 // Algorithmic bytes of the SpMV rows a fused upper launch forms (their
@@ -1139,7 +1146,8 @@ static double fused_spmv_bytes(ilu0_t M, int nsys) {
 // application inside v = A phat (RS_OPT_LOWER_PARTS): the fused iteration
 // on a two-level pattern with FP64 factors, reading y from the input.
 static bool lower_parts_iteration(const rs_ilu0 *M) {
-    return M->lower_parts && M->precision == RS_PREC_FP64 && fused_iteration(M) && y_from_input(M, true, true);
+    return M->lower_parts && M->precision == RS_PREC_FP64 && fused_iteration(M) && y_from_input(M, true, true) &&
+           M->wdev.nw == 0;
 }
 
 // Its two workspace vectors, allocated on first use (and kept).
@@ -1247,6 +1255,10 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
     const bool yin = y_from_input(M, sizeof(T) == sizeof(double), fz);
     const bool lp = sizeof(T) == sizeof(double) && lower_parts_iteration(M);
     const int r0 = fz ? M->an->sch.fuse_n0 : 0;
+    // wells with the fused iteration: the fused rows' well terms come after
+    // each product, with one more group sum for the vector kernels
+    const bool wfix = fz && M->wdev.nw > 0 && M->wdev.nfix > 0;
+    const int fix_at = wfix ? rs::wells_fix_at(M->an->dev, M->spmv_variant) : 0;
     const double fb = fz ? fused_spmv_bytes(M, B) : 0.0;
     const double spmv_bytes = B * (76 * nnzb + 52 * n) - fb;
     const double apply_bytes = lower_bytes(M, tb, B) + upper_bytes(M, tb, B) + fb;
@@ -1267,10 +1279,12 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
         else
             rs::launch_spmv_v(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), M->wdev,
                               r0, s, ps.start(), ps.stop());
+        // the well terms of the rows the fused upper launch formed
+        if (wfix) rs::launch_wells_fix(M->wdev, k.v, k.rhat, k.vstride, k.fpart, k.fpart_stride, fix_at, k.st, B, s);
     }
     if (parts & P_SUPD) {
         ProfScope ps(PC_VEC, s, B * 72 * n, true);
-        rs::launch_s_update(M->an->dev, k, B, M->spmv_variant, M->split(), fz, s, ps.start(), ps.stop());
+        rs::launch_s_update(M->an->dev, k, B, M->spmv_variant, M->split(), fz, s, ps.start(), ps.stop(), wfix);
     }
     {
         ProfScope pa(PC_APPLY, s, lp ? lp_lower_bytes(M, B) + upper_bytes(M, tb, B) + fb : apply_bytes, false,
@@ -1291,10 +1305,11 @@ static void enqueue_iteration(ilu0_t M, const T *L, const T *U, const T *D, hipS
         ProfScope ps(PC_SPMV_T, s, spmv_bytes, true);
         rs::launch_spmv_t(M->an->dev, M->pvals.as<double>(), per, k, B, M->spmv_variant, M->split(), M->wdev, r0,
                           s, ps.start(), ps.stop());
+        if (wfix) rs::launch_wells_fix(M->wdev, k.t, k.s, k.vstride, k.fpart, k.fpart_stride, fix_at, k.st, B, s);
     }
     if (parts & P_XR) {
         ProfScope ps(PC_VEC, s, B * 192 * n, true);
-        rs::launch_xr_update(M->an->dev, k, B, M->spmv_variant, M->split(), fz, s, ps.start(), ps.stop());
+        rs::launch_xr_update(M->an->dev, k, B, M->spmv_variant, M->split(), fz, s, ps.start(), ps.stop(), wfix);
     }
 }
 

@@ -50,6 +50,10 @@ struct WellsDev {
     const int32_t *perf_well = nullptr;  // np
     const double *B = nullptr, *C = nullptr, *Dinv = nullptr;   // per system: np*12, np*12, nw*16
     double *t2 = nullptr;                // per system: nw*4, D^-1 B x of the current x
+    // rows [0, fuse_n0) that a perforation couples (their rows of v and t,
+    // formed by the fused upper launch, take their well terms afterwards)
+    int nfix = 0;
+    const int32_t *fix_row = nullptr;
 };
 
 // Restarted GMRES: per-system state of the current cycle (Hessenberg matrix
@@ -237,19 +241,30 @@ void launch_setup(const DevSchedule &d, const double *b_orig, const int32_t *bad
 // t2 = D^-1 (B x) for every well and system (x at stride xstride): the
 // first half of the separate well application, run before an SpMV of x.
 void launch_wells_t2(const WellsDev &w, const double *x, size_t xstride, int nsys, hipStream_t s);
+// The well terms of the rows w.fix_row, which the fused upper launch formed
+// without them (t2 of the whole x already computed): y_i -= (C^T t2)_i, and
+// the changes of (w1, y) and (y, y) over those rows stored as one more group
+// sum of the fused launch's partials (position `at` of part, per system
+// part_stride) that the next vector kernel adds.  Systems not iterating are
+// skipped.
+void launch_wells_fix(const WellsDev &w, double *y, const double *w1, size_t vstride, double *part,
+                      size_t part_stride, int at, SysState *st, int nsys, hipStream_t s);
 
 // ev0 / ev1 (optional): events recorded by the dispatch at the kernel's start and end.
 // r0: rows [r0, n) only (the fused upper launch formed rows [0, r0)).
 void launch_spmv_v(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, int split,
                    const WellsDev &w, int r0, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // fused: the product's rows [0, d.fuse_n0) came from the fused upper
-// launch, whose group sums are added after those of the SpMV.
+// launch, whose group sums are added after those of the SpMV; fix: plus the
+// one launch_wells_fix stored after them (at wells_fix_at).
 void launch_s_update(const DevSchedule &d, Krylov &k, int nsys, int spmv_variant, int split, bool fused,
-                     hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                     hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool fix = false);
+// Position in k.fpart (per system) of the group sum launch_wells_fix adds.
+int wells_fix_at(const DevSchedule &d, int spmv_variant);
 void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Krylov &k, int nsys, int variant, int split,
                    const WellsDev &w, int r0, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_xr_update(const DevSchedule &d, Krylov &k, int nsys, int spmv_variant, int split, bool fused,
-                      hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                      hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, bool fix = false);
 
 // Which product the fused upper launch forms.
 enum FuseMode { FUSE_NONE = 0, FUSE_V = 1, FUSE_T = 2 };

@@ -1037,6 +1037,35 @@ __global__ void __launch_bounds__(256) k_wells_t2(WellsDev wl, const double *__r
     for (int i = 0; i < 4; ++i) t2[i] = d[4 * i] * t1[0] + d[4 * i + 1] * t1[1] + d[4 * i + 2] * t1[2] + d[4 * i + 3] * t1[3];
 }
 
+// The well terms of the rows the fused upper launch formed (rows below
+// fuse_n0 that a perforation couples): y_i -= (C^T t2)_i once t2 of the
+// whole x exists, and the changes of the launch's two dot-product sums over
+// those rows, (w1, y_new - y_old) and (y_new, y_new) - (y_old, y_old), as one
+// more group sum.  One workgroup per system.
+__global__ void __launch_bounds__(256) k_wells_fix(WellsDev wl, double *__restrict__ y, const double *__restrict__ w1,
+                                                   size_t vstride, double *__restrict__ part, size_t part_stride,
+                                                   int at, const SysState *__restrict__ st) {
+    __shared__ double lds[4 * 2];
+    const int sys = blockIdx.y;
+    if (st[sys].phase != PH_RUN) return;
+    const size_t vo = (size_t)sys * vstride;
+    double d[2] = {0.0, 0.0};
+    for (int idx = threadIdx.x; idx < 3 * wl.nfix; idx += blockDim.x) {
+        const int i = wl.fix_row[idx / 3], r = idx % 3;
+        const size_t k = vo + 3 * (size_t)i + r;
+        const double yo = y[k], yn = yo - well_terms(wl, sys, i, r);
+        y[k] = yn;
+        d[0] += w1[k] * (yn - yo);
+        d[1] += yn * yn - yo * yo;
+    }
+    block_sum<2>(d, lds);
+    if (threadIdx.x == 0) {
+        double *pp = part + sys * part_stride + at;
+        pp[0] = d[0];
+        pp[1] = d[1];
+    }
+}
+
 // ------------------------------------------------------------------- SpMV
 
 template <int MODE, int W, int STAGE>
@@ -2113,6 +2142,12 @@ static void spmv_any(int variant, int n, const int32_t *ptr, const int32_t *col,
         k_spmv_total<MODE><<<dim3(1, nsys), kTotalThreads, 0, s>>>(part, part_stride, waves, st);
 }
 
+void launch_wells_fix(const WellsDev &w, double *y, const double *w1, size_t vstride, double *part,
+                      size_t part_stride, int at, SysState *st, int nsys, hipStream_t s) {
+    if (w.nw <= 0 || w.nfix <= 0 || nsys <= 0) return;
+    k_wells_fix<<<dim3(1, nsys), 256, 0, s>>>(w, y, w1, vstride, part, part_stride, at, st);
+}
+
 void launch_wells_t2(const WellsDev &w, const double *x, size_t xstride, int nsys, hipStream_t s) {
     if (w.nw <= 0 || nsys <= 0) return;
     k_wells_t2<<<dim3((w.nw + 3) / 4, nsys), 256, 0, s>>>(w, x, xstride);
@@ -2144,10 +2179,16 @@ static SpmvSums fused_sums(const DevSchedule &d, bool fused, int spmv_variant) {
     return SpmvSums{2 * g, (g + 31) / 32};
 }
 
+int wells_fix_at(const DevSchedule &d, int spmv_variant) {
+    const SpmvSums f = fused_sums(d, true, spmv_variant);
+    return f.offset + 2 * f.count;
+}
+
 void launch_s_update(const DevSchedule &d, Krylov &k, int nsys, int spmv_variant, int split, bool fused,
-                     hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                     hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, bool fix) {
     const SpmvSums at = spmv_sums(d.n - (fused ? d.fuse_n0 : 0), variant_waves(spmv_variant), split);
-    const SpmvSums f = fused_sums(d, fused, spmv_variant);
+    SpmvSums f = fused_sums(d, fused, spmv_variant);
+    if (fused && fix) ++f.count;
     launch_ev(k_s_update, dim3(vec_blocks(d.n), nsys), dim3(kVecThreads), s, ev0, ev1, k, at.offset, at.count,
               f.offset, f.count);
 }
@@ -2166,9 +2207,10 @@ void launch_spmv_t(const DevSchedule &d, const double *Ap, size_t a_stride, Kryl
 }
 
 void launch_xr_update(const DevSchedule &d, Krylov &k, int nsys, int spmv_variant, int split, bool fused,
-                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, bool fix) {
     const SpmvSums at = spmv_sums(d.n - (fused ? d.fuse_n0 : 0), variant_waves(spmv_variant), split);
-    const SpmvSums f = fused_sums(d, fused, spmv_variant);
+    SpmvSums f = fused_sums(d, fused, spmv_variant);
+    if (fused && fix) ++f.count;
     launch_ev(k_xr_update, dim3(vec_blocks(d.n), nsys), dim3(kVecThreads), s, ev0, ev1, k, at.offset, at.count,
               f.offset, f.count);
 }
