@@ -1706,6 +1706,12 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
 
 }  // extern "C"
 
+// GMRES steps use the fused upper launch where BiCGStab's iteration would
+// (RS_OPT_FUSE_SPMV), without separate wells.
+static bool gm_fused(const rs_ilu0 *M) {
+    return M->fuse_spmv && M->an->sch.fuse_n0 > 0 && !M->tile_sweeps && M->wdev.nw == 0;
+}
+
 // Queue one Arnoldi step (column j) of every iterating system on `s`.
 // Timed launches record their own dispatch events.
 template <typename T>
@@ -1713,12 +1719,25 @@ static void gm_step(ilu0_t M, const T *L, const T *U, const T *D, const rs::GmWo
     Krylov &k = M->k;
     const int B = M->batch;
     const double n = M->n, nnzb = M->nnzb, vb = (double)B * 24 * n;
-    // z = M^-1 v_j, w = A z
-    apply_levels<T>(M, L, U, D, g.V + (size_t)j * g.colstride, k.phat, false, k, k.st, B, s);
+    // z = M^-1 v_j, w = A z; with the fused upper launch (as in BiCGStab's
+    // iteration) the rows without lower blocks form their rows of w there
+    // (the launch's dot products go unused) and the SpMV covers the others
+    const double *vj = g.V + (size_t)j * g.colstride;
+    const bool fz = gm_fused(M);
+    const double fb = fz ? fused_spmv_bytes(M, B) : 0.0;
+    if (fz) {
+        const bool yin = y_from_input(M, sizeof(T) == sizeof(double), true);
+        ProfScope ps(PC_APPLY, s, lower_bytes(M, sizeof(T), B) + upper_bytes(M, sizeof(T), B) + fb, false, true);
+        lower_levels<T>(M, L, D, vj, k.phat, false, k, k.st, B, s, true, yin);
+        upper_levels<T>(M, U, D, k.phat, false, k, k.st, B, s, true, rs::FUSE_V, k.t, vj, yin ? vj : nullptr);
+    } else {
+        apply_levels<T>(M, L, U, D, vj, k.phat, false, k, k.st, B, s);
+    }
     {
-        ProfScope ps(PC_SPMV_T, s, B * (76 * nnzb + 4 * n + 48 * n), true);
+        ProfScope ps(PC_SPMV_T, s, B * (76 * nnzb + 4 * n + 48 * n) - fb, true);
         rs::launch_spmv_running(M->an->dev, M->pvals.as<double>(), (size_t)M->nnzb * 9, k.phat, k.t, k.vstride, k.st,
-                                B, M->spmv_variant, M->wdev, s, ps.start(), ps.stop());
+                                B, M->spmv_variant, M->wdev, s, ps.start(), ps.stop(),
+                                fz ? M->an->sch.fuse_n0 : 0);
     }
     const int jv = j + 1;
     {

@@ -313,7 +313,7 @@ void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *c
 // order, x and y at stride vstride), minus the separate wells.
 void launch_spmv_running(const DevSchedule &d, const double *Ap, size_t a_stride, const double *x, double *y,
                          size_t vstride, SysState *st, int nsys, int variant, const WellsDev &w, hipStream_t s,
-                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int r0 = 0);
 
 // GMRES workspace as the kernels see it.  Vectors of all systems at stride
 // vstride; Krylov basis column c of system s at V + c * colstride + s * vstride.

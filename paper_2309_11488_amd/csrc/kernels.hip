@@ -2313,10 +2313,10 @@ void launch_finish(const DevSchedule &d, const int32_t *rowptr, const int32_t *c
 
 void launch_spmv_running(const DevSchedule &d, const double *Ap, size_t a_stride, const double *x, double *y,
                          size_t vstride, SysState *st, int nsys, int variant, const WellsDev &w, hipStream_t s,
-                         hipEvent_t ev0, hipEvent_t ev1) {
-    if (d.n <= 0 || nsys <= 0) return;
+                         hipEvent_t ev0, hipEvent_t ev1, int r0) {
+    if (d.n <= r0 || nsys <= 0) return;
     spmv_any<SPMV_RUN>(variant, d.n, d.prow, d.pcol, Ap, a_stride, x, y, vstride, nullptr, nullptr, 0, nullptr, 0,
-                       st, nsys, 0, w, s, ev0, ev1);
+                       st, nsys, 0, w, s, ev0, ev1, r0);
 }
 
 // Workgroups of the GMRES vector kernels: one per 256 * items entries of a
