@@ -1707,9 +1707,9 @@ int bicgstab_solve(ilu0_t M, bcsr_t A, const double *b, double *x, double reduct
 }  // extern "C"
 
 // GMRES steps use the fused upper launch where BiCGStab's iteration would
-// (RS_OPT_FUSE_SPMV), without separate wells.
+// (RS_OPT_FUSE_SPMV).
 static bool gm_fused(const rs_ilu0 *M) {
-    return M->fuse_spmv && M->an->sch.fuse_n0 > 0 && !M->tile_sweeps && M->wdev.nw == 0;
+    return M->fuse_spmv && M->an->sch.fuse_n0 > 0 && !M->tile_sweeps;
 }
 
 // Queue one Arnoldi step (column j) of every iterating system on `s`.
@@ -1738,6 +1738,12 @@ static void gm_step(ilu0_t M, const T *L, const T *U, const T *D, const rs::GmWo
         rs::launch_spmv_running(M->an->dev, M->pvals.as<double>(), (size_t)M->nnzb * 9, k.phat, k.t, k.vstride, k.st,
                                 B, M->spmv_variant, M->wdev, s, ps.start(), ps.stop(),
                                 fz ? M->an->sch.fuse_n0 : 0);
+        // the well terms of the rows the fused launch formed (the dot
+        // products of w come later, from the finished w: the fix-up's sums
+        // go unused)
+        if (fz && M->wdev.nw > 0 && M->wdev.nfix > 0)
+            rs::launch_wells_fix(M->wdev, k.t, vj, k.vstride, k.fpart, k.fpart_stride,
+                                 rs::wells_fix_at(M->an->dev, M->spmv_variant), k.st, B, s);
     }
     const int jv = j + 1;
     {

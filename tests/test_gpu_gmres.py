@@ -181,3 +181,27 @@ def test_gmres_with_wells_matches_oracle(ordering, restart):
     assert abs(info[0]["half_steps"] - oinfo["half_steps"]) <= 1, (info, oinfo)
     assert info[0]["true_rel_residual"] <= 1e-9
     assert info[0]["true_rel_residual"] == pytest.approx(oinfo["true_rel_residual"], rel=0.5, abs=1e-12)
+
+
+def test_fused_gmres_steps_with_wells():
+    """A full grid under graph colouring with wells: GMRES's fused steps
+    (the upper launch forms the first colour's rows of w) take those rows'
+    well terms after the SpMV; the solve matches the oracle, and the
+    unfused steps to rounding."""
+    s = make_grid_system(16, 13, 9, seed=71)
+    w = make_wells(s, 7, seed=72)
+    with rs.Solver(s.rowptr, s.colidx, s.vals, ordering=rs.ORDER_GRAPH_COLOUR) as sol:
+        rs.bcsr_set_wells(sol.A, w.well_ptr, w.perf_row, w.B, w.C, w.Dinv)
+        sol.factor()
+        assert rs.ilu0_get_option(sol.M, rs.OPT_FUSED_ROWS) > 0
+        xf, stf, inf = sol.solve_gmres(s.b[:, 0], restart=30, reduction=1e-10, max_iter=2000)
+        rs.ilu0_set_option(sol.M, rs.OPT_FUSE_SPMV, 0)
+        xu, stu, inu = sol.solve_gmres(s.b[:, 0], restart=30, reduction=1e-10, max_iter=2000)
+    xo, oinfo = oracle.solve_gmres(s.rowptr, s.colidx, s.vals[0], s.b[0, 0], ordering=rs.ORDER_GRAPH_COLOUR,
+                                   restart=30, reduction=1e-10, max_iter=2000,
+                                   wells=(w.well_ptr, w.perf_row, w.B[0], w.C[0], w.Dinv[0]))
+    assert stf == stu == oinfo["status"] == rs.OK
+    assert np.linalg.norm(xf[0] - xo) <= 1e-8 * np.linalg.norm(xo)
+    assert np.linalg.norm(xf[0] - xu[0]) <= 1e-8 * np.linalg.norm(xu[0])
+    assert abs(inf[0]["half_steps"] - oinfo["half_steps"]) <= 1, (inf, oinfo)
+    assert inf[0]["true_rel_residual"] <= 1e-9
